@@ -1,0 +1,213 @@
+#!/usr/bin/env python3
+"""Throughput of third-order semi-Lagrangian advection on one MI355X.
+
+Workload (default): one FP32 scalar on a periodic 512^3 grid (sum of 8
+seeded Gaussians, sigma in [0.05, 0.15] of the box), steady ABC velocity
+(A = B = C = 1) on [0, 2 pi)^3, CFL 0.9, the third-order scheme.  A "step"
+is one full time step of the scheme over the whole grid (all interpolation
+calls of all three axis sweeps).  Inputs are resident in HBM before the
+timed region starts.
+
+Prints one JSON line: Gcell-updates/s over exactly --steps steps, the
+roofline of the dominant kernel (per-launch durations from HIP events
+recorded by the library on its stream during the timed region), the HBM
+traffic from rocprofv3 counters when they were taken on the current kernel
+source, and the FP64 CPU oracle timed on a bounded sample of the same
+workload.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import resource
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+METRIC = "Gcell-updates/s + %HBM peak, 3rd-order 512³ FP32; learned vs plain at equal L2"
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_1606_06117_amd", "csrc", "advect_kernels.hip")
+
+
+def algorithmic_bytes(kind: str, ncells: int, ndim: int) -> int:
+    """Bytes a launch of ``kind`` must move at minimum over ``ncells`` cells.
+
+    A whole step reads phi and the ndim velocity planes and writes phi:
+    (8 + 4 ndim) B per cell.  One axis sweep reads phi and its velocity plane
+    and writes phi: 12 B per cell.  A copy reads and writes 4 B each.
+    """
+    per_cell = {"cir": 8 + 4 * ndim, "fec": 8 + 4 * ndim, "bec": 8 + 4 * ndim,
+                "cec3d": 8 + 4 * ndim, "sweep_x": 12, "sweep_y": 12, "sweep_z": 12,
+                "copy": 8}[kind]
+    return per_cell * ncells
+
+
+def source_hash() -> str:
+    with open(KERNEL_SRC, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def measured_traffic(kind: str, workload: str):
+    """HBM bytes per launch from committed rocprofv3 counters, if still current."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            data = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    entry = data.get(workload, {}).get(kind)
+    if not entry or entry.get("source_sha256_16") != source_hash():
+        return None
+    return entry.get("bytes_per_launch")
+
+
+def cpu_baseline(phi, u, dx, dt, scheme, edge, steps):
+    """The FP64 oracle timed on a periodic sub-box of the same inputs."""
+    import numpy as np
+    import oracle
+    sub = phi[:edge, :edge, :edge].astype(np.float64)
+    usub = np.ascontiguousarray(u[:, :edge, :edge, :edge])
+    c0 = resource.getrusage(resource.RUSAGE_SELF)
+    t0 = time.perf_counter()
+    oracle.advect(sub, usub, dx, dt, scheme, steps)
+    wall = time.perf_counter() - t0
+    c1 = resource.getrusage(resource.RUSAGE_SELF)
+    cpu = (c1.ru_utime - c0.ru_utime) + (c1.ru_stime - c0.ru_stime)
+    cores = max(1, int(round(cpu / wall)))
+    return {
+        "value": edge**3 * steps / wall / 1e9,
+        "unit": "Gcell-updates/s",
+        "cores": cores,
+        "kind": "oracle",
+        "sample": f"FP64 NumPy oracle, {edge}^3 periodic sub-box of the same inputs, "
+                  f"{steps} steps of the same scheme ({wall:.1f} s wall, host has {os.cpu_count()} CPUs)",
+    }
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--size", type=int, default=512)
+    ap.add_argument("--cfl", type=float, default=0.9)
+    ap.add_argument("--scheme", default="cec", choices=["cir", "fec", "bec", "cec"])
+    ap.add_argument("--cpu-edge", type=int, default=128, help="edge of the oracle's sample box")
+    ap.add_argument("--cpu-steps", type=int, default=12, help="oracle steps on the sample box")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args(argv)
+
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(no sharding or collectives); run it with --gpus 1", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    sys.path.insert(0, ROOT)
+    from paper_1606_06117_amd import native
+    from paper_1606_06117_amd import workloads as W
+
+    N = args.size
+    shape = (N, N, N)
+    print(f"[bench] building inputs {N}^3 ...", file=sys.stderr, flush=True)
+    phi0 = W.random_gaussians(shape, 8, seed=2000).astype(np.float32)
+    u = W.abc_velocity(shape)
+    dx = (2 * math.pi / N,) * 3
+    dt = W.abc_dt(shape, args.cfl)
+    scheme = native.SCHEMES[args.scheme]
+
+    dev = torch.device("cuda:0")
+    phi_d = torch.from_numpy(phi0).to(dev)
+    u_d = torch.from_numpy(u).to(dev)
+    ctx = native.Context(0)
+    cmax = ctx.courant_max(u_d, dx, dt)
+
+    for w in range(args.warmup):
+        ctx.advect(phi_d, u_d, dx, dt, scheme, 1, step0=w, courant_max=cmax)
+    ctx.check()
+    torch.cuda.synchronize()
+
+    print(f"[bench] timing {args.steps} steps ...", file=sys.stderr, flush=True)
+    ctx.timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.advect(phi_d, u_d, dx, dt, scheme, args.steps, step0=args.warmup, courant_max=cmax)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    times = ctx.timing_read()
+    ctx.timing(False)
+    ctx.check()
+
+    ncells = N**3
+    value = ncells * args.steps / wall / 1e9
+    ms_per_step = wall * 1e3 / args.steps
+    step_bytes = algorithmic_bytes("cec3d", ncells, 3)  # per cell-update, whole step
+    hbm_frac_step = step_bytes * args.steps / wall / (HBM_PEAK_GBS * 1e9)
+
+    dom = max(times, key=lambda k: times[k][1])
+    launches, total_ms = times[dom]
+    avg_s = total_ms / launches / 1e3
+    alg = algorithmic_bytes(dom, ncells, 3)
+    achieved = alg / avg_s / 1e9
+    workload = f"{args.scheme}-{N}^3-cfl{args.cfl}"
+    traffic = measured_traffic(dom, workload)
+    roofline = {
+        "bound": "hbm",
+        "kernel": dom,
+        "achieved": achieved,
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": achieved / HBM_PEAK_GBS,
+        "traffic": traffic,
+        "algorithmic_bytes_per_launch": alg,
+        "avg_launch_ms": avg_s * 1e3,
+        "launches": launches,
+        "per_kind_ms": {k: round(v[1] / v[0], 4) for k, v in times.items()},
+    }
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "Gcell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{'third-order (CEC)' if args.scheme == 'cec' else args.scheme.upper()} "
+                        f"semi-Lagrangian advection, {N}^3 periodic FP32, 1 scalar (8 Gaussians), "
+                        f"ABC(1,1,1) velocity, CFL {args.cfl}",
+            "grid": [N, N, N],
+            "scheme": args.scheme,
+            "cfl": args.cfl,
+            "scalars": 1,
+            "parallelism": "single GPU",
+        },
+        "hbm_frac_step": hbm_frac_step,
+        "roofline": roofline,
+    }
+
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle sample ...", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(phi0, u, dx, dt, scheme, args.cpu_edge, args.cpu_steps)
+    else:
+        out["cpu_baseline"] = None
+
+    print(json.dumps(out), flush=True)
+    ctx.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,164 @@
+/*
+ * sla.h -- C ABI of the multi-stage semi-Lagrangian advection library (gfx950).
+ *
+ * The library advects passive scalars on periodic Cartesian grids with the
+ * schemes of Cameron, Raynaud & Dormy, "Multi-stage high order semi-Lagrangian
+ * schemes for incompressible flows in Cartesian geometries":
+ *
+ *   CIR  one call of the interpolation operator L_U (section 3, first
+ *        equation; eq. CIR2D for the multilinear 2D/3D form),
+ *   FEC  forward error correction, eq. intro:FEC (two calls),
+ *   BEC  backward error correction, eq. intro:BEC (three calls),
+ *   CEC  the third-order combination A*FEC + B*BEC of eq. intro:CEC with the
+ *        weights of eq. intro:CECcoef, taken from U mod 1 at large Courant
+ *        numbers (eq. intro:CECcoefSL) and applied one axis at a time
+ *        (section 5, eqs. split:1 and split:2).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Pointers named phi, u, a, b, phis[k] are HIP device pointers on the
+ *   context's device; every other pointer is host memory.  The caller owns
+ *   all of them; the library never frees or keeps them past the call.
+ * - A field is FP32, x fastest: cell (x, y, z) sits at x + nx*(y + ny*z).
+ *   A velocity is ndim such planes back to back (u_x, u_y[, u_z]), the
+ *   physical velocity; the Courant number of axis d is c_d = u_d*dt/dx_d,
+ *   formed as one FP32 multiply by fl32(dt/dx_d).
+ * - The departure point of node i along an axis is i - c: it lies between the
+ *   anchor node i - s*n and the far node i - s*(n+1), with s = +1 if c >= 0
+ *   else -1, n = floor(|c|), f = |c| - n.  Interpolation is p + f*(q - p).
+ * - Boundaries are periodic on every axis.
+ * - Calls are asynchronous on the context's stream unless stated; a device
+ *   fault surfaces at a later synchronising call.
+ * - Every function returns an sla_status (0 = success, negative = error) and
+ *   never aborts; sla_last_error() gives the detail of the last failure.
+ * - One context per host thread; calls on one context must not overlap.
+ */
+#ifndef SLA_H
+#define SLA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SLA_CIR = 0, /* L_U only: first order */
+  SLA_FEC = 1, /* eq. intro:FEC, unsplit multilinear: second order */
+  SLA_BEC = 2, /* eq. intro:BEC, unsplit multilinear: second order */
+  SLA_CEC = 3  /* eqs. intro:CEC + intro:CECcoef(SL), split per axis: third order */
+} sla_scheme;
+
+typedef enum {
+  SLA_OK = 0,
+  SLA_EINVAL = -1,   /* bad argument: see sla_last_error() */
+  SLA_ECOURANT = -2, /* floor(max |c|) + 1 exceeds SLA_MAX_REACH, or a kernel
+                        met a Courant number beyond the bound it was given */
+  SLA_EHIP = -3,     /* HIP runtime error */
+  SLA_ENOMEM = -4,   /* device allocation failed */
+  SLA_ENOMODEL = -5  /* learned correction called without usable weights */
+} sla_status;
+
+/* Largest backtrace reach, in cells, the kernels are built for: every
+ * |c_d| must be < SLA_MAX_REACH (so CFL < 4). */
+#define SLA_MAX_REACH 4
+
+/* A periodic grid.  ndim is 1, 2 or 3; n[d] >= 8 cells on each used axis and
+ * n[d] = 1 on unused axes; n[0]*n[1]*n[2] < 2^31; dx[d] > 0 and finite. */
+typedef struct {
+  int32_t ndim;
+  int32_t n[3];
+  double dx[3];
+} sla_grid;
+
+typedef struct sla_ctx sla_ctx; /* opaque */
+
+/* Create a context on HIP device `device` issuing work on `stream`
+ * (a hipStream_t; NULL = the default stream).  *out receives the context. */
+int sla_create(sla_ctx **out, int device, void *stream);
+/* Release a context and the device memory it allocated.  NULL is ignored. */
+void sla_destroy(sla_ctx *ctx);
+/* Change the stream later calls are issued on. */
+int sla_set_stream(sla_ctx *ctx, void *stream);
+/* Static text for a status code. */
+const char *sla_strerror(int status);
+/* Detail of the last failure on this context (empty string if none).  The
+ * pointer stays valid until the next call on the context. */
+const char *sla_last_error(const sla_ctx *ctx);
+
+/* Largest Courant number max_d max_cells |fl32(u_d * fl32(dt/dx_d))| of the
+ * velocity `u` (ndim planes on `grid`), written to host *out.  Synchronises
+ * the stream.  Returns SLA_EINVAL if u holds a NaN or an infinity. */
+int sla_courant_max(sla_ctx *ctx, const sla_grid *grid, const float *u,
+                    double dt, double *out);
+
+/* Advance `phi` in place by `steps` time steps of `scheme` with the steady
+ * velocity `u`, time step `dt` (any finite value; a negative dt advects
+ * backwards).  The velocity is sampled at the arrival node and traced back
+ * one explicit step (section 2: L_U[Phi](x) = Phi~(x - U dt)).
+ *
+ * step0 is the global index of the first step; for SLA_CEC it fixes the sweep
+ * order (x,y,z on even steps, z,y,x on odd steps), so a run split into
+ * several calls matches one call when step0 is carried along.
+ *
+ * courant_max: if > 0, a bound the caller guarantees on every |c_d|; the call
+ * then does not read u to measure it.  If a kernel still meets a larger
+ * Courant number it clamps the offset (the result is then wrong but every
+ * access stays in bounds) and records SLA_ECOURANT for sla_check().
+ * If <= 0 the call measures the bound itself (one extra read of u and one
+ * stream synchronisation).
+ *
+ * steps == 0 is a successful no-op.  Work memory (one field) is allocated on
+ * the context on first use and kept.  The result is in phi when the stream
+ * reaches the end of the call. */
+int sla_advect(sla_ctx *ctx, const sla_grid *grid, float *phi, const float *u,
+               double dt, int32_t scheme, int32_t steps, int64_t step0,
+               double courant_max);
+
+/* Synchronise the context's stream and report a Courant overflow recorded by
+ * a kernel since the previous sla_check() (then SLA_ECOURANT), or a HIP
+ * error.  Clears the record. */
+int sla_check(sla_ctx *ctx);
+
+/* FP64 reductions of two FP32 arrays of `count` elements (section 4 judges
+ * schemes by the norm of their difference to a reference).  Writes to the
+ * host array out[5]:
+ *   out[0] = sum (a-b)^2, out[1] = sum b^2, out[2] = max |a-b|,
+ *   out[3] = sum a,       out[4] = sum b,
+ * all accumulated in FP64 in a fixed order (bitwise reproducible for a given
+ * count).  Synchronises the stream. */
+int sla_norms(sla_ctx *ctx, int64_t count, const float *a, const float *b,
+              double *out);
+
+/* ------------------------------------------------------------------------
+ * Per-kernel timing (for roofline measurements).
+ * While enabled, every kernel launch of later calls on the context is
+ * bracketed by HIP events recorded on the context's stream; durations are
+ * accumulated per kernel kind.  Recording adds two event records per launch.
+ * ---------------------------------------------------------------------- */
+typedef enum {
+  SLA_K_CIR = 0,     /* unsplit CIR step                      */
+  SLA_K_FEC = 1,     /* fused unsplit FEC step                */
+  SLA_K_BEC = 2,     /* fused unsplit BEC step                */
+  SLA_K_SWEEP_X = 3, /* third-order sweep along x             */
+  SLA_K_SWEEP_Y = 4, /* third-order sweep along y             */
+  SLA_K_SWEEP_Z = 5, /* third-order sweep along z             */
+  SLA_K_CEC3D = 6,   /* fused three-axis third-order step     */
+  SLA_K_COPY = 7,    /* device-to-device copy of the result   */
+  SLA_K_COUNT = 8
+} sla_kernel_kind;
+
+/* enable != 0: start recording (totals are cleared); 0: stop recording. */
+int sla_timing(sla_ctx *ctx, int enable);
+/* Synchronise the stream and write, per kernel kind, the number of launches
+ * recorded and their summed duration in milliseconds to the host arrays
+ * launches[SLA_K_COUNT] and ms[SLA_K_COUNT].  Totals keep accumulating until
+ * the next sla_timing(ctx, 1). */
+int sla_timing_read(sla_ctx *ctx, int64_t *launches, double *ms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SLA_H */

@@ -1,0 +1,485 @@
+// Advection kernels for gfx950: CIR, fused unsplit FEC/BEC, and the per-axis
+// third-order sweep.
+//
+// Every kernel decomposes the Courant number of a node the same way
+// (section 3 of the paper defines s_i = sgn(u_i) and U_i = |u_i| dt/dx; at
+// CFL > 1 the stencil moves with the departure point, section 4):
+//   c = u * fl32(dt/dx)          one FP32 multiply
+//   n = floor(|c|), f = |c| - n  (f exact in FP32)
+//   anchor offset oa = -s n, far offset ob = -s (n + 1), s = +1 if c >= 0
+// Offsets stay integers, so a departure point is never formed as an FP32
+// coordinate and index arithmetic stays exact on any grid size.
+// Interpolation is p + f (q - p) with p the anchor: integer Courant numbers
+// and constant fields come out bit-exact.
+
+#include "common.h"
+
+#include "../../include/sla.h"
+
+namespace sla {
+namespace {
+
+constexpr int kThreads = 256;
+
+struct Dep {
+  int oa;  // anchor offset, cells
+  int ob;  // far offset, cells
+  float f; // fraction in [0, 1)
+};
+
+// Departure of a node with Courant number c, for kernels whose halo serves a
+// reach of R cells.  A Courant number needing more is clamped to the reach
+// (every access stays in bounds) and recorded in *flag.
+template <int R>
+__device__ __forceinline__ Dep depart(float c, int* flag) {
+  const float mag = fabsf(c);
+  float nf = floorf(mag);
+  const float f = mag - nf;
+  if (!(nf <= float(R - 1))) {
+    if (nf == nf) *flag = 1;  // NaN is not an overflow: it propagates as NaN
+    nf = float(R - 1);
+  }
+  const int n = int(nf);
+  const bool pos = c >= 0.f;  // -0.0 counts as positive
+  Dep d;
+  d.oa = pos ? -n : n;
+  d.ob = pos ? -(n + 1) : (n + 1);
+  d.f = f;
+  return d;
+}
+
+__device__ __forceinline__ float lerp(float p, float q, float f) { return fmaf(f, q - p, p); }
+
+// v within one period of [0, n)
+__device__ __forceinline__ int wrap1(int v, int n) {
+  v = v < 0 ? v + n : v;
+  return v >= n ? v - n : v;
+}
+// any v (used where a halo may exceed a short axis)
+__device__ __forceinline__ int wrapk(int v, int n) {
+  while (v < 0) v += n;
+  while (v >= n) v -= n;
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// CIR: one multilinear interpolation per node (section 3 first equation;
+// eq. CIR2D; the same tensor product in 3D).  Gathers straight from global
+// memory: the 2^d nodes of a departure cell are near neighbours, served by
+// L1/L2.  Interpolation order x, then y, then z.
+// ---------------------------------------------------------------------------
+template <int NDIM>
+__global__ __launch_bounds__(kThreads) void k_cir(const float* __restrict__ phi,
+                                                  const float* __restrict__ ux,
+                                                  const float* __restrict__ uy,
+                                                  const float* __restrict__ uz,
+                                                  float* __restrict__ out, Geo g, int* flag) {
+  constexpr int R = SLA_MAX_REACH;
+  const int x = blockIdx.x * 64 + threadIdx.x;
+  const int y = blockIdx.y * 4 + threadIdx.y;
+  const int z = blockIdx.z;
+  if (x >= g.nx || y >= g.ny) return;
+  const int plane = g.nx * g.ny;
+  const int idx = x + g.nx * y + plane * z;
+  const Dep dx = depart<R>(ux[idx] * g.lam[0], flag);
+  const int xa = wrap1(x + dx.oa, g.nx), xb = wrap1(x + dx.ob, g.nx);
+  if (NDIM == 1) {
+    out[idx] = lerp(phi[xa], phi[xb], dx.f);
+    return;
+  }
+  const Dep dy = depart<R>(uy[idx] * g.lam[1], flag);
+  const int ya = wrap1(y + dy.oa, g.ny) * g.nx, yb = wrap1(y + dy.ob, g.ny) * g.nx;
+  if (NDIM == 2) {
+    const float v0 = lerp(phi[ya + xa], phi[ya + xb], dx.f);
+    const float v1 = lerp(phi[yb + xa], phi[yb + xb], dx.f);
+    out[idx] = lerp(v0, v1, dy.f);
+    return;
+  }
+  const Dep dz = depart<R>(uz[idx] * g.lam[2], flag);
+  const int za = wrap1(z + dz.oa, g.nz) * plane, zb = wrap1(z + dz.ob, g.nz) * plane;
+  const float v00 = lerp(phi[za + ya + xa], phi[za + ya + xb], dx.f);
+  const float v10 = lerp(phi[za + yb + xa], phi[za + yb + xb], dx.f);
+  const float v01 = lerp(phi[zb + ya + xa], phi[zb + ya + xb], dx.f);
+  const float v11 = lerp(phi[zb + yb + xa], phi[zb + yb + xb], dx.f);
+  out[idx] = lerp(lerp(v00, v10, dy.f), lerp(v01, v11, dy.f), dz.f);
+}
+
+// ---------------------------------------------------------------------------
+// Unsplit FEC / BEC (eqs. intro:FEC, intro:BEC), all calls fused in one pass.
+//
+// A workgroup owns a TX x TY column of cells and marches along z over a chunk
+// of planes.  Each stage keeps a ring of 2*RZ+1 planes in LDS:
+//   stage 0  Phi                 halo K*R   (K = 2 for FEC, 3 for BEC)
+//   stage 1  Phi1 = L_U Phi      halo (K-1)*R
+//   stage 2  psi = Phi + (Phi - L_{-U} Phi1)/2       (BEC only)
+//   output   FEC: Phi1 + (Phi - L_{-U} Phi1)/2 ;  BEC: L_U psi
+// Stage k at plane p reads stage k-1 at planes p-RZ..p+RZ, so a stage lags
+// its input by RZ planes and intermediates never leave LDS.
+// ---------------------------------------------------------------------------
+template <int NDIM, int SCHEME, int R, int TX, int TY>
+struct EcShape {
+  static constexpr int RY = NDIM >= 2 ? R : 0;
+  static constexpr int RZ = NDIM == 3 ? R : 0;
+  static constexpr int K = SCHEME == BEC ? 3 : 2;
+  static constexpr int D = 2 * RZ + 1;
+  static constexpr int HX(int k) { return (K - k) * R; }
+  static constexpr int HY(int k) { return (K - k) * RY; }
+  static constexpr int W(int k) { return TX + 2 * HX(k); }
+  static constexpr int H(int k) { return TY + 2 * HY(k); }
+  static constexpr int PLANE(int k) { return W(k) * H(k); }
+  static constexpr int OFF(int k) { return k == 0 ? 0 : OFF(k - 1) + D * PLANE(k - 1); }
+  static constexpr int FLOATS = OFF(K);
+};
+
+// Interpolate LDS stage array `src` (ring of D planes of W x H) at the
+// departure cell of the point whose centre in src coordinates is (cx, cy) on
+// local plane p.
+template <int NDIM, int W, int PL, int D>
+__device__ __forceinline__ float interp_lds(const float* src, int p, int cx, int cy,
+                                            const Dep& dx, const Dep& dy, const Dep& dz) {
+  const int xa = cx + dx.oa, xb = cx + dx.ob;
+  if (NDIM == 1) {
+    const float* r = src + (p % D) * PL + cy * W;
+    return lerp(r[xa], r[xb], dx.f);
+  }
+  const int ya = (cy + dy.oa) * W, yb = (cy + dy.ob) * W;
+  if (NDIM == 2) {
+    const float* s = src + (p % D) * PL;
+    return lerp(lerp(s[ya + xa], s[ya + xb], dx.f), lerp(s[yb + xa], s[yb + xb], dx.f), dy.f);
+  }
+  const float* sa = src + ((p + dz.oa) % D) * PL;
+  const float* sb = src + ((p + dz.ob) % D) * PL;
+  const float v00 = lerp(sa[ya + xa], sa[ya + xb], dx.f);
+  const float v10 = lerp(sa[yb + xa], sa[yb + xb], dx.f);
+  const float v01 = lerp(sb[ya + xa], sb[ya + xb], dx.f);
+  const float v11 = lerp(sb[yb + xa], sb[yb + xb], dx.f);
+  return lerp(lerp(v00, v10, dy.f), lerp(v01, v11, dy.f), dz.f);
+}
+
+template <int NDIM, int SCHEME, int R, int TX, int TY>
+__global__ __launch_bounds__(kThreads) void k_ec(const float* __restrict__ phi,
+                                                 const float* __restrict__ ux,
+                                                 const float* __restrict__ uy,
+                                                 const float* __restrict__ uz,
+                                                 float* __restrict__ out, Geo g, int zchunk,
+                                                 int* flag) {
+  using S = EcShape<NDIM, SCHEME, R, TX, TY>;
+  constexpr int K = S::K, RZ = S::RZ, RY = S::RY, D = S::D;
+  extern __shared__ float lds[];
+  float* st0 = lds + S::OFF(0);
+  float* st1 = lds + S::OFF(1);
+  float* st2 = lds + S::OFF(K == 3 ? 2 : 1);  // psi (BEC only)
+
+  const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
+  const int zbeg = blockIdx.z * zchunk;
+  const int zend = min(zbeg + zchunk, g.nz);
+  const int first = zbeg - K * RZ;  // global plane of local plane 0
+  const int iters = (zend - zbeg) + 2 * K * RZ;
+  const int plane = g.nx * g.ny;
+
+  // velocity and departures at global (x, y, z) for axis-wise offsets
+  auto deps = [&](int gx, int gy, int gz, bool reverse, Dep& dx, Dep& dy, Dep& dz) {
+    const size_t i = (size_t)gz * plane + (size_t)gy * g.nx + gx;
+    float c = ux[i] * g.lam[0];
+    dx = depart<R>(reverse ? -c : c, flag);
+    if (NDIM >= 2) {
+      c = uy[i] * g.lam[1];
+      dy = depart<R>(reverse ? -c : c, flag);
+    }
+    if (NDIM == 3) {
+      c = uz[i] * g.lam[2];
+      dz = depart<R>(reverse ? -c : c, flag);
+    }
+  };
+
+  for (int t = 0; t < iters; ++t) {
+    // stage 0: load Phi plane (local t) with its halo
+    {
+      const int gz = wrapk(first + t, g.nz);
+      float* dst = st0 + (t % D) * S::PLANE(0);
+      for (int e = threadIdx.x; e < S::PLANE(0); e += kThreads) {
+        const int ly = e / S::W(0), lx = e - ly * S::W(0);
+        const int gx = wrapk(x0 - S::HX(0) + lx, g.nx);
+        const int gy = wrapk(y0 - S::HY(0) + ly, g.ny);
+        dst[e] = phi[(size_t)gz * plane + (size_t)gy * g.nx + gx];
+      }
+    }
+    __syncthreads();
+    // stage 1: Phi1 = L_U Phi at local plane t - RZ
+    if (t >= 2 * RZ) {
+      const int p = t - RZ;
+      const int gz = wrapk(first + p, g.nz);
+      float* dst = st1 + (p % D) * S::PLANE(1);
+      for (int e = threadIdx.x; e < S::PLANE(1); e += kThreads) {
+        const int ly = e / S::W(1), lx = e - ly * S::W(1);
+        const int gx = wrapk(x0 - S::HX(1) + lx, g.nx);
+        const int gy = wrapk(y0 - S::HY(1) + ly, g.ny);
+        Dep dx{}, dy{}, dz{};
+        deps(gx, gy, gz, false, dx, dy, dz);
+        dst[e] = interp_lds<NDIM, S::W(0), S::PLANE(0), D>(st0, p, lx + R, ly + RY, dx, dy, dz);
+      }
+    }
+    __syncthreads();
+    if (K == 3) {
+      // stage 2 (BEC): psi = Phi + (Phi - L_{-U} Phi1)/2 at local plane t - 2RZ
+      if (t >= 4 * RZ) {
+        const int p = t - 2 * RZ;
+        const int gz = wrapk(first + p, g.nz);
+        float* dst = st2 + (p % D) * S::PLANE(2);
+        const float* ph = st0 + (p % D) * S::PLANE(0);
+        for (int e = threadIdx.x; e < S::PLANE(2); e += kThreads) {
+          const int ly = e / S::W(2), lx = e - ly * S::W(2);
+          const int gx = wrapk(x0 - S::HX(2) + lx, g.nx);
+          const int gy = wrapk(y0 - S::HY(2) + ly, g.ny);
+          Dep dx{}, dy{}, dz{};
+          deps(gx, gy, gz, true, dx, dy, dz);
+          const float bar =
+              interp_lds<NDIM, S::W(1), S::PLANE(1), D>(st1, p, lx + R, ly + RY, dx, dy, dz);
+          const float v = ph[(ly + 2 * RY) * S::W(0) + lx + 2 * R];
+          dst[e] = fmaf(0.5f, v - bar, v);
+        }
+      }
+      __syncthreads();
+    }
+    // output at local plane t - K*RZ
+    if (t >= 2 * K * RZ) {
+      const int p = t - K * RZ;
+      const int z = first + p;  // in [zbeg, zend)
+      for (int e = threadIdx.x; e < TX * TY; e += kThreads) {
+        const int ly = e / TX, lx = e - ly * TX;
+        const int gx = x0 + lx, gy = y0 + ly;
+        if (gx >= g.nx || gy >= g.ny) continue;
+        float res;
+        if (K == 2) {
+          Dep dx{}, dy{}, dz{};
+          deps(gx, gy, z, true, dx, dy, dz);
+          const float bar =
+              interp_lds<NDIM, S::W(1), S::PLANE(1), D>(st1, p, lx + R, ly + RY, dx, dy, dz);
+          const float p1 = st1[(p % D) * S::PLANE(1) + (ly + RY) * S::W(1) + lx + R];
+          const float v = st0[(p % D) * S::PLANE(0) + (ly + 2 * RY) * S::W(0) + lx + 2 * R];
+          res = fmaf(0.5f, v - bar, p1);
+        } else {
+          Dep dx{}, dy{}, dz{};
+          deps(gx, gy, z, false, dx, dy, dz);
+          res = interp_lds<NDIM, S::W(2), S::PLANE(2), D>(st2, p, lx + R, ly + RY, dx, dy, dz);
+        }
+        out[(size_t)z * plane + (size_t)gy * g.nx + gx] = res;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Third-order sweep along one axis (eq. intro:CEC with eq. intro:CECcoef
+// weights, large CFL per eq. intro:CECcoefSL; one axis at a time as in
+// eqs. split:1-2).  Per node, with e = Phi - L_{-U} L_U Phi:
+//   out = Phi1 + 1/2 [e_a + (1+f)/3 (e_b - e_a)],   Phi1 = L_U Phi,
+// which for U < 1 is A FEC + B BEC with 3A = 2 - 1/U, B = 1 - A, written
+// without the division.  A tile of TL nodes along the axis plus a halo of 3R
+// (Phi), 2R (Phi1, Courant), R (e) is staged in LDS; the three calls never
+// leave LDS.
+// ---------------------------------------------------------------------------
+
+// Strided axis (y or z): tile = 64 consecutive x (coalesced) x TL along the axis.
+template <int R>
+__global__ __launch_bounds__(kThreads) void k_sweep_s(const float* __restrict__ phi,
+                                                      const float* __restrict__ ud,
+                                                      float* __restrict__ out, int nx, int L,
+                                                      int64_t S, int64_t So, float lam, int* flag) {
+  constexpr int TL = 32, TW = 64;
+  constexpr int NP = TL + 6 * R, NC = TL + 4 * R, NE = TL + 2 * R;
+  __shared__ float P[NP * TW], C[NC * TW], P1[NC * TW], E[NE * TW];
+  const int tx = threadIdx.x & (TW - 1), ty = threadIdx.x / TW;
+  const int x = blockIdx.x * TW + tx;
+  const int l0 = blockIdx.y * TL;
+  const bool xin = x < nx;
+  const size_t base = (size_t)blockIdx.z * So + (xin ? x : 0);
+  for (int r = ty; r < NP; r += kThreads / TW) {
+    const int l = wrapk(l0 - 3 * R + r, L);
+    P[r * TW + tx] = xin ? phi[base + (size_t)l * S] : 0.f;
+  }
+  for (int r = ty; r < NC; r += kThreads / TW) {
+    const int l = wrapk(l0 - 2 * R + r, L);
+    C[r * TW + tx] = xin ? ud[base + (size_t)l * S] * lam : 0.f;
+  }
+  __syncthreads();
+  for (int r = ty; r < NC; r += kThreads / TW) {
+    const Dep d = depart<R>(C[r * TW + tx], flag);
+    P1[r * TW + tx] = lerp(P[(r + R + d.oa) * TW + tx], P[(r + R + d.ob) * TW + tx], d.f);
+  }
+  __syncthreads();
+  for (int r = ty; r < NE; r += kThreads / TW) {
+    const Dep d = depart<R>(-C[(r + R) * TW + tx], flag);
+    const float bar = lerp(P1[(r + R + d.oa) * TW + tx], P1[(r + R + d.ob) * TW + tx], d.f);
+    E[r * TW + tx] = P[(r + 2 * R) * TW + tx] - bar;
+  }
+  __syncthreads();
+  if (!xin) return;
+  for (int r = ty; r < TL; r += kThreads / TW) {
+    const int l = l0 + r;
+    if (l >= L) break;
+    const Dep d = depart<R>(C[(r + 2 * R) * TW + tx], flag);
+    const float ea = E[(r + R + d.oa) * TW + tx], eb = E[(r + R + d.ob) * TW + tx];
+    const float w = fmaf(d.f, 1.f / 3.f, 1.f / 3.f);
+    out[base + (size_t)l * S] = fmaf(0.5f, fmaf(w, eb - ea, ea), P1[(r + 2 * R) * TW + tx]);
+  }
+}
+
+// Contiguous axis (x): tile = TL consecutive x in each of ROWS rows.
+template <int R>
+__global__ __launch_bounds__(kThreads) void k_sweep_x(const float* __restrict__ phi,
+                                                      const float* __restrict__ ud,
+                                                      float* __restrict__ out, int nx, int ny,
+                                                      float lam, int* flag) {
+  constexpr int TL = 256, ROWS = 4;
+  constexpr int NP = TL + 6 * R, NC = TL + 4 * R, NE = TL + 2 * R;
+  __shared__ float P[ROWS * NP], C[ROWS * NC], P1[ROWS * NC], E[ROWS * NE];
+  const int l0 = blockIdx.x * TL;
+  const int y0 = blockIdx.y * ROWS;
+  const size_t zoff = (size_t)blockIdx.z * nx * ny;
+  for (int e = threadIdx.x; e < ROWS * NP; e += kThreads) {
+    const int rr = e / NP, col = e - rr * NP;
+    const int y = y0 + rr;
+    P[e] = y < ny ? phi[zoff + (size_t)y * nx + wrapk(l0 - 3 * R + col, nx)] : 0.f;
+  }
+  for (int e = threadIdx.x; e < ROWS * NC; e += kThreads) {
+    const int rr = e / NC, col = e - rr * NC;
+    const int y = y0 + rr;
+    C[e] = y < ny ? ud[zoff + (size_t)y * nx + wrapk(l0 - 2 * R + col, nx)] * lam : 0.f;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < ROWS * NC; e += kThreads) {
+    const int rr = e / NC, col = e - rr * NC;
+    const Dep d = depart<R>(C[e], flag);
+    const float* p = P + rr * NP + col + R;
+    P1[e] = lerp(p[d.oa], p[d.ob], d.f);
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < ROWS * NE; e += kThreads) {
+    const int rr = e / NE, col = e - rr * NE;
+    const Dep d = depart<R>(-C[rr * NC + col + R], flag);
+    const float* p1 = P1 + rr * NC + col + R;
+    E[e] = P[rr * NP + col + 2 * R] - lerp(p1[d.oa], p1[d.ob], d.f);
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < ROWS * TL; e += kThreads) {
+    const int rr = e / TL, col = e - rr * TL;
+    const int y = y0 + rr, x = l0 + col;
+    if (y >= ny || x >= nx) continue;
+    const Dep d = depart<R>(C[rr * NC + col + 2 * R], flag);
+    const float* ee = E + rr * NE + col + R;
+    const float ea = ee[d.oa], eb = ee[d.ob];
+    const float w = fmaf(d.f, 1.f / 3.f, 1.f / 3.f);
+    out[zoff + (size_t)y * nx + x] = fmaf(0.5f, fmaf(w, eb - ea, ea), P1[rr * NC + col + 2 * R]);
+  }
+}
+
+template <typename F>
+hipError_t set_lds(F kernel, int bytes) {
+  if (bytes <= 64 * 1024) return hipSuccess;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+
+template <int NDIM, int SCHEME, int R>
+hipError_t launch_ec_t(const Geo& g, const float* phi, const float* u, float* out, int* flag,
+                       hipStream_t st) {
+  constexpr int TX = R <= 2 ? 64 : 32;
+  constexpr int TY = NDIM >= 2 ? 8 : 1;
+  using S = EcShape<NDIM, SCHEME, R, TX, TY>;
+  constexpr int bytes = S::FLOATS * 4;
+  static_assert(bytes <= 160 * 1024, "LDS budget");
+  auto kern = k_ec<NDIM, SCHEME, R, TX, TY>;
+  static hipError_t attr = set_lds(kern, bytes);
+  if (attr != hipSuccess) return attr;
+  const size_t n = (size_t)g.ncells;
+  const float* ux = u;
+  const float* uy = NDIM >= 2 ? u + n : u;
+  const float* uz = NDIM == 3 ? u + 2 * n : u;
+  const int zchunk = NDIM == 3 ? 32 : 1;
+  dim3 grid((g.nx + TX - 1) / TX, (g.ny + TY - 1) / TY, (g.nz + zchunk - 1) / zchunk);
+  hipLaunchKernelGGL(kern, grid, dim3(kThreads), bytes, st, phi, ux, uy, uz, out, g, zchunk, flag);
+  return hipGetLastError();
+}
+
+template <int NDIM, int SCHEME>
+hipError_t launch_ec_r(int R, const Geo& g, const float* phi, const float* u, float* out,
+                       int* flag, hipStream_t st) {
+  switch (R) {
+    case 1: return launch_ec_t<NDIM, SCHEME, 1>(g, phi, u, out, flag, st);
+    case 2: return launch_ec_t<NDIM, SCHEME, 2>(g, phi, u, out, flag, st);
+    case 3: return launch_ec_t<NDIM, SCHEME, 3>(g, phi, u, out, flag, st);
+    case 4: return launch_ec_t<NDIM, SCHEME, 4>(g, phi, u, out, flag, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int R>
+hipError_t launch_sweep_t(int d, const Geo& g, const float* phi, const float* ud, float* out,
+                          int* flag, hipStream_t st) {
+  if (d == 0) {
+    dim3 grid((g.nx + 255) / 256, (g.ny + 3) / 4, g.nz);
+    hipLaunchKernelGGL(k_sweep_x<R>, grid, dim3(kThreads), 0, st, phi, ud, out, g.nx, g.ny,
+                       g.lam[0], flag);
+  } else {
+    const int L = d == 1 ? g.ny : g.nz;
+    const int64_t S = d == 1 ? (int64_t)g.nx : (int64_t)g.nx * g.ny;
+    const int other = d == 1 ? g.nz : g.ny;
+    const int64_t So = d == 1 ? (int64_t)g.nx * g.ny : (int64_t)g.nx;
+    dim3 grid((g.nx + 63) / 64, (L + 31) / 32, other);
+    hipLaunchKernelGGL(k_sweep_s<R>, grid, dim3(kThreads), 0, st, phi, ud, out, g.nx, L, S, So,
+                       g.lam[d], flag);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_cir(int ndim, const Geo& g, const float* phi, const float* u, float* out,
+                      int* flag, hipStream_t st) {
+  const size_t n = (size_t)g.ncells;
+  const float* ux = u;
+  const float* uy = ndim >= 2 ? u + n : u;
+  const float* uz = ndim == 3 ? u + 2 * n : u;
+  dim3 block(64, 4);
+  dim3 grid((g.nx + 63) / 64, (g.ny + 3) / 4, g.nz);
+  switch (ndim) {
+    case 1: hipLaunchKernelGGL(k_cir<1>, grid, block, 0, st, phi, ux, uy, uz, out, g, flag); break;
+    case 2: hipLaunchKernelGGL(k_cir<2>, grid, block, 0, st, phi, ux, uy, uz, out, g, flag); break;
+    case 3: hipLaunchKernelGGL(k_cir<3>, grid, block, 0, st, phi, ux, uy, uz, out, g, flag); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_ec(int ndim, int scheme, int R, const Geo& g, const float* phi, const float* u,
+                     float* out, int* flag, hipStream_t st) {
+  if (scheme == FEC) {
+    switch (ndim) {
+      case 1: return launch_ec_r<1, FEC>(R, g, phi, u, out, flag, st);
+      case 2: return launch_ec_r<2, FEC>(R, g, phi, u, out, flag, st);
+      case 3: return launch_ec_r<3, FEC>(R, g, phi, u, out, flag, st);
+    }
+  } else if (scheme == BEC) {
+    switch (ndim) {
+      case 1: return launch_ec_r<1, BEC>(R, g, phi, u, out, flag, st);
+      case 2: return launch_ec_r<2, BEC>(R, g, phi, u, out, flag, st);
+      case 3: return launch_ec_r<3, BEC>(R, g, phi, u, out, flag, st);
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_cec_sweep(int d, int R, const Geo& g, const float* phi, const float* ud,
+                            float* out, int* flag, hipStream_t st) {
+  switch (R) {
+    case 1: return launch_sweep_t<1>(d, g, phi, ud, out, flag, st);
+    case 2: return launch_sweep_t<2>(d, g, phi, ud, out, flag, st);
+    case 3: return launch_sweep_t<3>(d, g, phi, ud, out, flag, st);
+    case 4: return launch_sweep_t<4>(d, g, phi, ud, out, flag, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace sla

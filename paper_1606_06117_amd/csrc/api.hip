@@ -1,0 +1,416 @@
+// C ABI of the library: argument checks, reach selection, work memory,
+// kernel sequencing per scheme.  All compute happens in the kernels.
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/sla.h"
+#include "common.h"
+
+struct sla_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  float* work = nullptr;  // ping-pong field
+  size_t work_cap = 0;    // floats
+  float* fpart = nullptr; // velocity-max partials (3 * kUmaxBlocks) + 3 results
+  double* dpart = nullptr;// norm partials (5 * kNormBlocks) + 5 results
+  int* flag = nullptr;    // set by a kernel that clamped an offset
+  void* host = nullptr;   // pinned staging for small results (256 bytes)
+  std::string err;
+  // per-kernel timing
+  bool timing = false;
+  struct Mark { int kind; hipEvent_t a, b; };
+  std::vector<Mark> marks;        // recorded, not yet read
+  std::vector<hipEvent_t> spare;  // event pool
+  int64_t launches[SLA_K_COUNT] = {};
+  double ms[SLA_K_COUNT] = {};
+};
+
+namespace {
+
+int fail(sla_ctx* ctx, int code, const char* fmt, ...) {
+  if (ctx) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    ctx->err = buf;
+  }
+  return code;
+}
+
+int hip_fail(sla_ctx* ctx, hipError_t e, const char* what) {
+  return fail(ctx, SLA_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+// Makes the context's device current for the duration of a call.
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = true;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+int check_grid(sla_ctx* ctx, const sla_grid* g) {
+  if (!g) return fail(ctx, SLA_EINVAL, "grid is NULL");
+  if (g->ndim < 1 || g->ndim > 3) return fail(ctx, SLA_EINVAL, "ndim must be 1, 2 or 3 (got %d)", g->ndim);
+  int64_t cells = 1;
+  for (int d = 0; d < 3; ++d) {
+    if (d < g->ndim) {
+      if (g->n[d] < 8) return fail(ctx, SLA_EINVAL, "n[%d] = %d: need at least 8 cells", d, g->n[d]);
+      if (!(g->dx[d] > 0.0) || !std::isfinite(g->dx[d]))
+        return fail(ctx, SLA_EINVAL, "dx[%d] must be positive and finite", d);
+    } else if (g->n[d] != 1) {
+      return fail(ctx, SLA_EINVAL, "n[%d] must be 1 on an unused axis", d);
+    }
+    cells *= g->n[d];
+  }
+  if (cells >= (int64_t(1) << 31)) return fail(ctx, SLA_EINVAL, "grid has 2^31 cells or more");
+  return SLA_OK;
+}
+
+sla::Geo make_geo(const sla_grid* g, double dt) {
+  sla::Geo geo;
+  geo.nx = g->n[0];
+  geo.ny = g->n[1];
+  geo.nz = g->n[2];
+  geo.ncells = g->n[0] * g->n[1] * g->n[2];
+  for (int d = 0; d < 3; ++d) geo.lam[d] = d < g->ndim ? float(dt / g->dx[d]) : 0.f;
+  return geo;
+}
+
+// Per-axis max |c_d| measured on the device (synchronises).
+int measure_courant(sla_ctx* ctx, const sla_grid* g, const sla::Geo& geo, const float* u,
+                    float cmax[3]) {
+  float* res = ctx->fpart + 3 * sla::kUmaxBlocks;
+  hipError_t e = sla::launch_umax(g->ndim, geo.ncells, u, ctx->fpart, res, ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "velocity max launch");
+  float* h = static_cast<float*>(ctx->host);
+  e = hipMemcpyAsync(h, res, 3 * sizeof(float), hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "velocity max");
+  for (int d = 0; d < 3; ++d) {
+    if (d >= g->ndim) {
+      cmax[d] = 0.f;
+      continue;
+    }
+    if (!std::isfinite(h[d])) return fail(ctx, SLA_EINVAL, "velocity plane %d holds NaN or Inf", d);
+    cmax[d] = h[d] * std::fabs(geo.lam[d]);  // FP32 product, as the kernels form c
+  }
+  return SLA_OK;
+}
+
+hipEvent_t take_event(sla_ctx* ctx) {
+  if (!ctx->spare.empty()) {
+    hipEvent_t e = ctx->spare.back();
+    ctx->spare.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Run one kernel launch; bracket it with events when timing is on.
+template <typename F>
+hipError_t run(sla_ctx* ctx, int kind, F&& launch) {
+  if (!ctx->timing) return launch();
+  hipEvent_t a = take_event(ctx), b = take_event(ctx);
+  if (!a || !b) return hipErrorOutOfMemory;
+  hipError_t e = hipEventRecord(a, ctx->stream);
+  if (e == hipSuccess) e = launch();
+  if (e == hipSuccess) e = hipEventRecord(b, ctx->stream);
+  if (e != hipSuccess) {
+    ctx->spare.push_back(a);
+    ctx->spare.push_back(b);
+    return e;
+  }
+  ctx->marks.push_back({kind, a, b});
+  return hipSuccess;
+}
+
+// Fold recorded marks into the totals (the stream must be synchronised).
+void fold_marks(sla_ctx* ctx) {
+  for (auto& m : ctx->marks) {
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, m.a, m.b) == hipSuccess) {
+      ctx->launches[m.kind] += 1;
+      ctx->ms[m.kind] += t;
+    }
+    ctx->spare.push_back(m.a);
+    ctx->spare.push_back(m.b);
+  }
+  ctx->marks.clear();
+}
+
+int ensure_work(sla_ctx* ctx, size_t floats) {
+  if (ctx->work_cap >= floats) return SLA_OK;
+  if (ctx->work) {
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "synchronise before growing work memory");
+    (void)hipFree(ctx->work);
+    ctx->work = nullptr;
+    ctx->work_cap = 0;
+  }
+  if (hipMalloc(&ctx->work, floats * sizeof(float)) != hipSuccess) {
+    ctx->work = nullptr;
+    (void)hipGetLastError();
+    return fail(ctx, SLA_ENOMEM, "cannot allocate %zu bytes of work memory", floats * sizeof(float));
+  }
+  ctx->work_cap = floats;
+  return SLA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* sla_strerror(int status) {
+  switch (status) {
+    case SLA_OK: return "success";
+    case SLA_EINVAL: return "invalid argument";
+    case SLA_ECOURANT: return "Courant number beyond the supported reach";
+    case SLA_EHIP: return "HIP runtime error";
+    case SLA_ENOMEM: return "out of device memory";
+    case SLA_ENOMODEL: return "no usable model weights";
+  }
+  return "unknown status";
+}
+
+const char* sla_last_error(const sla_ctx* ctx) { return ctx ? ctx->err.c_str() : ""; }
+
+int sla_create(sla_ctx** out, int device, void* stream) {
+  if (!out) return SLA_EINVAL;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) {
+    (void)hipGetLastError();
+    return SLA_EINVAL;
+  }
+  sla_ctx* ctx = new sla_ctx;
+  ctx->device = device;
+  ctx->stream = static_cast<hipStream_t>(stream);
+  DeviceGuard guard(device);
+  bool ok = guard.ok;
+  ok = ok && hipMalloc(&ctx->fpart, (3 * sla::kUmaxBlocks + 3) * sizeof(float)) == hipSuccess;
+  ok = ok && hipMalloc(&ctx->dpart, (5 * sla::kNormBlocks + 5) * sizeof(double)) == hipSuccess;
+  ok = ok && hipMalloc(&ctx->flag, sizeof(int)) == hipSuccess;
+  ok = ok && hipHostMalloc(&ctx->host, 256, hipHostMallocDefault) == hipSuccess;
+  ok = ok && hipMemset(ctx->flag, 0, sizeof(int)) == hipSuccess;
+  if (!ok) {
+    (void)hipGetLastError();
+    sla_destroy(ctx);
+    return SLA_ENOMEM;
+  }
+  *out = ctx;
+  return SLA_OK;
+}
+
+void sla_destroy(sla_ctx* ctx) {
+  if (!ctx) return;
+  {
+    DeviceGuard guard(ctx->device);
+    if (ctx->stream || ctx->work) (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->work) (void)hipFree(ctx->work);
+    if (ctx->fpart) (void)hipFree(ctx->fpart);
+    if (ctx->dpart) (void)hipFree(ctx->dpart);
+    if (ctx->flag) (void)hipFree(ctx->flag);
+    if (ctx->host) (void)hipHostFree(ctx->host);
+    for (auto& m : ctx->marks) {
+      (void)hipEventDestroy(m.a);
+      (void)hipEventDestroy(m.b);
+    }
+    for (auto e : ctx->spare) (void)hipEventDestroy(e);
+  }
+  delete ctx;
+}
+
+int sla_set_stream(sla_ctx* ctx, void* stream) {
+  if (!ctx) return SLA_EINVAL;
+  ctx->stream = static_cast<hipStream_t>(stream);
+  return SLA_OK;
+}
+
+int sla_courant_max(sla_ctx* ctx, const sla_grid* grid, const float* u, double dt, double* out) {
+  if (!ctx) return SLA_EINVAL;
+  ctx->err.clear();
+  int rc = check_grid(ctx, grid);
+  if (rc) return rc;
+  if (!u || !out) return fail(ctx, SLA_EINVAL, "u and out must not be NULL");
+  if (!std::isfinite(dt)) return fail(ctx, SLA_EINVAL, "dt must be finite");
+  DeviceGuard guard(ctx->device);
+  if (!guard.ok) return fail(ctx, SLA_EHIP, "cannot select device %d", ctx->device);
+  const sla::Geo geo = make_geo(grid, dt);
+  float cm[3];
+  rc = measure_courant(ctx, grid, geo, u, cm);
+  if (rc) return rc;
+  *out = std::fmax(cm[0], std::fmax(cm[1], cm[2]));
+  return SLA_OK;
+}
+
+int sla_advect(sla_ctx* ctx, const sla_grid* grid, float* phi, const float* u, double dt,
+               int32_t scheme, int32_t steps, int64_t step0, double courant_max) {
+  if (!ctx) return SLA_EINVAL;
+  ctx->err.clear();
+  int rc = check_grid(ctx, grid);
+  if (rc) return rc;
+  if (!phi || !u) return fail(ctx, SLA_EINVAL, "phi and u must not be NULL");
+  if (!std::isfinite(dt)) return fail(ctx, SLA_EINVAL, "dt must be finite");
+  if (scheme < SLA_CIR || scheme > SLA_CEC) return fail(ctx, SLA_EINVAL, "unknown scheme %d", scheme);
+  if (steps < 0) return fail(ctx, SLA_EINVAL, "steps must be >= 0");
+  if (std::isnan(courant_max)) return fail(ctx, SLA_EINVAL, "courant_max is NaN");
+  if (steps == 0) return SLA_OK;
+  DeviceGuard guard(ctx->device);
+  if (!guard.ok) return fail(ctx, SLA_EHIP, "cannot select device %d", ctx->device);
+
+  const sla::Geo geo = make_geo(grid, dt);
+  const int ndim = grid->ndim;
+  int reach[3] = {1, 1, 1};
+  if (courant_max > 0.0) {
+    if (!(courant_max < SLA_MAX_REACH))
+      return fail(ctx, SLA_ECOURANT, "courant_max %g: must be below %d", courant_max, SLA_MAX_REACH);
+    const int r = int(std::floor(courant_max)) + 1;
+    reach[0] = reach[1] = reach[2] = r;
+  } else {
+    float cm[3];
+    rc = measure_courant(ctx, grid, geo, u, cm);
+    if (rc) return rc;
+    for (int d = 0; d < ndim; ++d) {
+      if (!(cm[d] < float(SLA_MAX_REACH)))
+        return fail(ctx, SLA_ECOURANT, "max Courant number %g on axis %d: must be below %d",
+                    double(cm[d]), d, SLA_MAX_REACH);
+      reach[d] = int(std::floor(cm[d])) + 1;
+    }
+  }
+  int rmax = 1;
+  for (int d = 0; d < ndim; ++d) rmax = reach[d] > rmax ? reach[d] : rmax;
+
+  const size_t n = size_t(geo.ncells);
+  rc = ensure_work(ctx, n);
+  if (rc) return rc;
+
+  float* cur = phi;
+  float* nxt = ctx->work;
+  hipError_t e = hipSuccess;
+  for (int32_t k = 0; k < steps && e == hipSuccess; ++k) {
+    const int64_t m = step0 + k;
+    switch (scheme) {
+      case SLA_CIR:
+        e = run(ctx, SLA_K_CIR, [&] {
+          return sla::launch_cir(ndim, geo, cur, u, nxt, ctx->flag, ctx->stream);
+        });
+        std::swap(cur, nxt);
+        break;
+      case SLA_FEC:
+      case SLA_BEC:
+        e = run(ctx, scheme == SLA_FEC ? SLA_K_FEC : SLA_K_BEC, [&] {
+          return sla::launch_ec(ndim, scheme, rmax, geo, cur, u, nxt, ctx->flag, ctx->stream);
+        });
+        std::swap(cur, nxt);
+        break;
+      case SLA_CEC:
+        for (int j = 0; j < ndim && e == hipSuccess; ++j) {
+          const int d = (m % 2 == 0) ? j : ndim - 1 - j;
+          e = run(ctx, SLA_K_SWEEP_X + d, [&] {
+            return sla::launch_cec_sweep(d, reach[d], geo, cur, u + size_t(d) * n, nxt,
+                                         ctx->flag, ctx->stream);
+          });
+          std::swap(cur, nxt);
+        }
+        break;
+    }
+  }
+  if (e != hipSuccess) return hip_fail(ctx, e, "advection kernel launch");
+  if (cur != phi) {
+    e = run(ctx, SLA_K_COPY, [&] {
+      return hipMemcpyAsync(phi, cur, n * sizeof(float), hipMemcpyDeviceToDevice, ctx->stream);
+    });
+    if (e != hipSuccess) return hip_fail(ctx, e, "copy of the result");
+  }
+  return SLA_OK;
+}
+
+int sla_check(sla_ctx* ctx) {
+  if (!ctx) return SLA_EINVAL;
+  ctx->err.clear();
+  DeviceGuard guard(ctx->device);
+  int* h = static_cast<int*>(ctx->host);
+  hipError_t e = hipMemcpyAsync(h, ctx->flag, sizeof(int), hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "stream synchronise");
+  if (*h) {
+    e = hipMemsetAsync(ctx->flag, 0, sizeof(int), ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "clear the overflow record");
+    return fail(ctx, SLA_ECOURANT, "a kernel met a Courant number beyond the reach it was built for");
+  }
+  return SLA_OK;
+}
+
+int sla_norms(sla_ctx* ctx, int64_t count, const float* a, const float* b, double* out) {
+  if (!ctx) return SLA_EINVAL;
+  ctx->err.clear();
+  if (count < 0) return fail(ctx, SLA_EINVAL, "count must be >= 0");
+  if (!out) return fail(ctx, SLA_EINVAL, "out must not be NULL");
+  if (count == 0) {
+    for (int k = 0; k < 5; ++k) out[k] = 0.0;
+    return SLA_OK;
+  }
+  if (!a || !b) return fail(ctx, SLA_EINVAL, "a and b must not be NULL");
+  DeviceGuard guard(ctx->device);
+  if (!guard.ok) return fail(ctx, SLA_EHIP, "cannot select device %d", ctx->device);
+  double* res = ctx->dpart + 5 * sla::kNormBlocks;
+  hipError_t e = sla::launch_norms(count, a, b, ctx->dpart, res, ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "norms launch");
+  double* h = static_cast<double*>(ctx->host);
+  e = hipMemcpyAsync(h, res, 5 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "norms");
+  for (int k = 0; k < 5; ++k) out[k] = h[k];
+  return SLA_OK;
+}
+
+int sla_timing(sla_ctx* ctx, int enable) {
+  if (!ctx) return SLA_EINVAL;
+  ctx->err.clear();
+  if (enable) {
+    DeviceGuard guard(ctx->device);
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "stream synchronise");
+    fold_marks(ctx);
+    for (int k = 0; k < SLA_K_COUNT; ++k) {
+      ctx->launches[k] = 0;
+      ctx->ms[k] = 0.0;
+    }
+  }
+  ctx->timing = enable != 0;
+  return SLA_OK;
+}
+
+int sla_timing_read(sla_ctx* ctx, int64_t* launches, double* ms) {
+  if (!ctx) return SLA_EINVAL;
+  ctx->err.clear();
+  if (!launches || !ms) return fail(ctx, SLA_EINVAL, "launches and ms must not be NULL");
+  DeviceGuard guard(ctx->device);
+  hipError_t e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "stream synchronise");
+  fold_marks(ctx);
+  for (int k = 0; k < SLA_K_COUNT; ++k) {
+    launches[k] = ctx->launches[k];
+    ms[k] = ctx->ms[k];
+  }
+  return SLA_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,51 @@
+// Internal declarations shared by the HIP sources of the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sla {
+
+enum { CIR = 0, FEC = 1, BEC = 2, CEC = 3 };
+
+// Grid geometry as the kernels see it.  lam[d] = fl32(dt / dx[d]); unused
+// axes have n = 1 and lam = 0.
+struct Geo {
+  int nx, ny, nz;
+  int ncells;
+  float lam[3];
+};
+
+// Reach (halo in cells) each kernel serves, one per axis: reach[d] =
+// floor(max |c_d|) + 1, at most SLA_MAX_REACH.
+struct Reach {
+  int r[3];
+};
+
+// ---------------------------------------------------------------- launchers
+// All launchers return hipSuccess or the error of the launch.  `flag` is a
+// device int set to 1 by a kernel that had to clamp a backtrace offset.
+
+hipError_t launch_cir(int ndim, const Geo& g, const float* phi, const float* u,
+                      float* out, int* flag, hipStream_t st);
+
+// Unsplit fused FEC or BEC step (scheme = FEC or BEC), reach R (max over axes).
+hipError_t launch_ec(int ndim, int scheme, int R, const Geo& g, const float* phi,
+                     const float* u, float* out, int* flag, hipStream_t st);
+
+// One third-order sweep along axis d with reach R; u_d is that axis' plane.
+hipError_t launch_cec_sweep(int d, int R, const Geo& g, const float* phi,
+                            const float* u_d, float* out, int* flag, hipStream_t st);
+
+// Max |u_d| per axis over the grid (FP32, NaN propagates) into out3 (device).
+hipError_t launch_umax(int ndim, int ncells, const float* u, float* part,
+                       float* out3, hipStream_t st);
+constexpr int kUmaxBlocks = 512;
+
+// FP64 reductions {sum (a-b)^2, sum b^2, max|a-b|, sum a, sum b} into out5
+// (device).  part holds kNormBlocks*5 doubles.
+hipError_t launch_norms(int64_t n, const float* a, const float* b, double* part,
+                        double* out5, hipStream_t st);
+constexpr int kNormBlocks = 1024;
+
+}  // namespace sla

@@ -1,0 +1,136 @@
+// Reductions: FP64 error/mass sums and the FP32 velocity maximum.
+//
+// Both are two-level trees with a fixed number of blocks and a fixed
+// per-thread stride, so a result depends only on the element count, never
+// on the device or on timing: bitwise reproducible.
+
+#include "common.h"
+
+namespace sla {
+namespace {
+
+constexpr int kThreads = 256;
+
+// NaN-propagating maximum.
+__device__ __forceinline__ double max_nan(double m, double v) { return (v > m || v != v) ? v : m; }
+__device__ __forceinline__ float max_nan(float m, float v) { return (v > m || v != v) ? v : m; }
+
+// Per block: partial sums of (a-b)^2, b^2, max|a-b|, a, b over a grid-stride
+// range; the block's 256 partials are combined in a fixed tree.
+__global__ __launch_bounds__(kThreads) void k_norms_part(int64_t n, const float* __restrict__ a,
+                                                         const float* __restrict__ b,
+                                                         double* __restrict__ part) {
+  double s0 = 0.0, s1 = 0.0, mx = 0.0, sa = 0.0, sb = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * kThreads;
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += stride) {
+    const double va = a[i], vb = b[i];
+    const double d = va - vb;
+    s0 = fma(d, d, s0);
+    s1 = fma(vb, vb, s1);
+    mx = max_nan(mx, fabs(d));
+    sa += va;
+    sb += vb;
+  }
+  __shared__ double sh[5][kThreads];
+  sh[0][threadIdx.x] = s0;
+  sh[1][threadIdx.x] = s1;
+  sh[2][threadIdx.x] = mx;
+  sh[3][threadIdx.x] = sa;
+  sh[4][threadIdx.x] = sb;
+  __syncthreads();
+  for (int w = kThreads / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      const int j = threadIdx.x + w;
+      sh[0][threadIdx.x] += sh[0][j];
+      sh[1][threadIdx.x] += sh[1][j];
+      sh[2][threadIdx.x] = max_nan(sh[2][threadIdx.x], sh[2][j]);
+      sh[3][threadIdx.x] += sh[3][j];
+      sh[4][threadIdx.x] += sh[4][j];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < 5) part[blockIdx.x * 5 + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+// One block: combine nblk partials in a fixed order.
+__global__ __launch_bounds__(kThreads) void k_norms_final(int nblk, const double* __restrict__ part,
+                                                          double* __restrict__ out5) {
+  double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int i = threadIdx.x; i < nblk; i += kThreads) {
+    v[0] += part[i * 5 + 0];
+    v[1] += part[i * 5 + 1];
+    v[2] = max_nan(v[2], part[i * 5 + 2]);
+    v[3] += part[i * 5 + 3];
+    v[4] += part[i * 5 + 4];
+  }
+  __shared__ double sh[5][kThreads];
+  for (int k = 0; k < 5; ++k) sh[k][threadIdx.x] = v[k];
+  __syncthreads();
+  for (int w = kThreads / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      const int j = threadIdx.x + w;
+      sh[0][threadIdx.x] += sh[0][j];
+      sh[1][threadIdx.x] += sh[1][j];
+      sh[2][threadIdx.x] = max_nan(sh[2][threadIdx.x], sh[2][j]);
+      sh[3][threadIdx.x] += sh[3][j];
+      sh[4][threadIdx.x] += sh[4][j];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < 5) out5[threadIdx.x] = sh[threadIdx.x][0];
+}
+
+// Max |u_d| over the grid for each of ndim planes: blockIdx.y = axis.
+__global__ __launch_bounds__(kThreads) void k_umax_part(int ncells, const float* __restrict__ u,
+                                                        float* __restrict__ part) {
+  const float* p = u + (size_t)blockIdx.y * ncells;
+  float m = 0.f;
+  const int stride = gridDim.x * kThreads;
+  for (int i = blockIdx.x * kThreads + threadIdx.x; i < ncells; i += stride)
+    m = max_nan(m, fabsf(p[i]));
+  __shared__ float sh[kThreads];
+  sh[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = kThreads / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sh[threadIdx.x] = max_nan(sh[threadIdx.x], sh[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.y * gridDim.x + blockIdx.x] = sh[0];
+}
+
+__global__ __launch_bounds__(kThreads) void k_umax_final(int nblk, const float* __restrict__ part,
+                                                         float* __restrict__ out) {
+  const float* p = part + (size_t)blockIdx.x * nblk;
+  float m = 0.f;
+  for (int i = threadIdx.x; i < nblk; i += kThreads) m = max_nan(m, p[i]);
+  __shared__ float sh[kThreads];
+  sh[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = kThreads / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sh[threadIdx.x] = max_nan(sh[threadIdx.x], sh[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = sh[0];
+}
+
+}  // namespace
+
+hipError_t launch_norms(int64_t n, const float* a, const float* b, double* part, double* out5,
+                        hipStream_t st) {
+  hipLaunchKernelGGL(k_norms_part, dim3(kNormBlocks), dim3(kThreads), 0, st, n, a, b, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_norms_final, dim3(1), dim3(kThreads), 0, st, kNormBlocks, part, out5);
+  return hipGetLastError();
+}
+
+hipError_t launch_umax(int ndim, int ncells, const float* u, float* part, float* out3,
+                       hipStream_t st) {
+  hipLaunchKernelGGL(k_umax_part, dim3(kUmaxBlocks, ndim), dim3(kThreads), 0, st, ncells, u, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_umax_final, dim3(ndim), dim3(kThreads), 0, st, kUmaxBlocks, part, out3);
+  return hipGetLastError();
+}
+
+}  // namespace sla

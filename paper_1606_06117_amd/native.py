@@ -1,0 +1,185 @@
+"""ctypes binding of ``libsla.so`` (argument marshalling only).
+
+Every function here converts torch tensors to device pointers, calls the C
+ABI declared in ``include/sla.h`` and turns a negative status into an
+exception.  No arithmetic of the method happens in Python; if the library is
+missing, loading fails loudly instead of falling back to anything else.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libsla.so")
+
+CIR, FEC, BEC, CEC = 0, 1, 2, 3
+SCHEMES = {"cir": CIR, "fec": FEC, "bec": BEC, "cec": CEC}
+MAX_REACH = 4
+
+OK, EINVAL, ECOURANT, EHIP, ENOMEM, ENOMODEL = 0, -1, -2, -3, -4, -5
+
+# every symbol include/sla.h declares, with (restype, argtypes)
+_c = ctypes
+_vp = _c.c_void_p
+SIGNATURES = {
+    "sla_create": (_c.c_int, [_c.POINTER(_vp), _c.c_int, _vp]),
+    "sla_destroy": (None, [_vp]),
+    "sla_set_stream": (_c.c_int, [_vp, _vp]),
+    "sla_strerror": (_c.c_char_p, [_c.c_int]),
+    "sla_last_error": (_c.c_char_p, [_vp]),
+    "sla_courant_max": (_c.c_int, [_vp, _vp, _vp, _c.c_double, _c.POINTER(_c.c_double)]),
+    "sla_advect": (_c.c_int, [_vp, _vp, _vp, _vp, _c.c_double, _c.c_int32, _c.c_int32,
+                              _c.c_int64, _c.c_double]),
+    "sla_check": (_c.c_int, [_vp]),
+    "sla_norms": (_c.c_int, [_vp, _c.c_int64, _vp, _vp, _c.POINTER(_c.c_double)]),
+    "sla_timing": (_c.c_int, [_vp, _c.c_int]),
+    "sla_timing_read": (_c.c_int, [_vp, _c.POINTER(_c.c_int64), _c.POINTER(_c.c_double)]),
+}
+
+KERNEL_KINDS = ["cir", "fec", "bec", "sweep_x", "sweep_y", "sweep_z", "cec3d", "copy"]
+
+
+class SlaError(RuntimeError):
+    def __init__(self, status, detail):
+        self.status = status
+        super().__init__(f"sla status {status}: {detail}")
+
+
+class Grid(ctypes.Structure):
+    """Mirror of ``sla_grid``."""
+    _fields_ = [("ndim", ctypes.c_int32), ("n", ctypes.c_int32 * 3), ("dx", ctypes.c_double * 3)]
+
+
+_LIB = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the library once and attach the ABI signatures."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(path):
+        raise ImportError(
+            f"{path} is missing: build the HIP library first "
+            "(python -c 'import __graft_entry__ as g; g.build()')")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _LIB = lib
+    return lib
+
+
+def make_grid(shape, dx=None) -> Grid:
+    """``shape`` in NumPy order (z, y, x) / (y, x) / (x,); ``dx`` x first."""
+    ndim = len(shape)
+    n = list(reversed([int(v) for v in shape])) + [1] * (3 - ndim)
+    if dx is None:
+        dx = [1.0 / v for v in n[:ndim]]
+    dx = list(dx) + [1.0] * (3 - ndim)
+    g = Grid()
+    g.ndim = ndim
+    for d in range(3):
+        g.n[d] = n[d]
+        g.dx[d] = float(dx[d])
+    return g
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _check_field(t, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) torch tensor")
+    if t.dtype != torch.float32:
+        raise TypeError(f"{name} must be float32")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+class Context:
+    """One library context bound to a device; calls go to torch's current stream."""
+
+    def __init__(self, device: int = 0):
+        self.lib = load()
+        self.device = device
+        h = ctypes.c_void_p()
+        st = self.lib.sla_create(ctypes.byref(h), device, None)
+        if st != OK:
+            raise SlaError(st, self.lib.sla_strerror(st).decode())
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.sla_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _stream(self):
+        import torch
+        self.lib.sla_set_stream(self.h, ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream))
+
+    def _raise(self, st):
+        if st != OK:
+            raise SlaError(st, self.lib.sla_last_error(self.h).decode() or self.lib.sla_strerror(st).decode())
+
+    def courant_max(self, u, dx, dt) -> float:
+        _check_field(u, "u")
+        g = make_grid(u.shape[1:], dx)
+        out = ctypes.c_double()
+        self._stream()
+        self._raise(self.lib.sla_courant_max(self.h, ctypes.byref(g), _ptr(u), float(dt), ctypes.byref(out)))
+        return out.value
+
+    def advect(self, phi, u, dx, dt, scheme, steps, step0=0, courant_max=0.0):
+        """Advance ``phi`` (float32, (z, y, x)) in place; ``u`` is (ndim, *phi.shape)."""
+        if isinstance(scheme, str):
+            scheme = SCHEMES[scheme]
+        _check_field(phi, "phi")
+        _check_field(u, "u")
+        if tuple(u.shape) != (phi.dim(),) + tuple(phi.shape):
+            raise ValueError(f"u must have shape {(phi.dim(),) + tuple(phi.shape)}, got {tuple(u.shape)}")
+        g = make_grid(phi.shape, dx)
+        self._stream()
+        self._raise(self.lib.sla_advect(self.h, ctypes.byref(g), _ptr(phi), _ptr(u), float(dt),
+                                        int(scheme), int(steps), int(step0), float(courant_max)))
+        return phi
+
+    def check(self):
+        self._stream()
+        self._raise(self.lib.sla_check(self.h))
+
+    def norms(self, a, b):
+        """FP64 ``(sum (a-b)^2, sum b^2, max|a-b|, sum a, sum b)`` computed on the GPU."""
+        _check_field(a, "a")
+        _check_field(b, "b")
+        if a.numel() != b.numel():
+            raise ValueError("a and b must have the same number of elements")
+        out = (ctypes.c_double * 5)()
+        self._stream()
+        self._raise(self.lib.sla_norms(self.h, a.numel(), _ptr(a), _ptr(b), out))
+        return tuple(out)
+
+    def timing(self, enable: bool):
+        """Start (clearing totals) or stop per-kernel event timing."""
+        self._stream()
+        self._raise(self.lib.sla_timing(self.h, 1 if enable else 0))
+
+    def timing_read(self):
+        """``{kind: (launches, total_ms)}`` for kinds with at least one launch."""
+        n = len(KERNEL_KINDS)
+        launches = (ctypes.c_int64 * n)()
+        ms = (ctypes.c_double * n)()
+        self._stream()
+        self._raise(self.lib.sla_timing_read(self.h, launches, ms))
+        return {KERNEL_KINDS[k]: (launches[k], ms[k]) for k in range(n) if launches[k]}

@@ -1,0 +1,156 @@
+"""Seeded synthetic inputs (fields and velocities) for tests and benchmarks.
+
+This module only builds inputs: periodic scalar fields and divergence-free
+velocities on Cartesian grids.  It holds none of the advection arithmetic and
+imports neither the oracle nor the HIP binding, so both can be fed from it.
+Arrays are NumPy, C order with x fastest (``[z, y, x]``), FP64 unless stated;
+callers round to FP32 where the GPU takes FP32.
+
+Recipes (each seeded through ``numpy.random.default_rng``):
+
+* ``gaussians``: a sum of Gaussian blobs on a periodic box, each periodised
+  over the 3**d neighbouring images so the field is smooth across the seam.
+* ``abc_velocity``: the Arnold-Beltrami-Childress flow
+  ``u = A sin z + C cos y, v = B sin x + A cos z, w = C sin y + B cos x`` on
+  ``[0, 2 pi)^3``, divergence free, ``max |u_d| = 2`` for A = B = C = 1.
+* ``fourier_modes``: ``sum_k g_k / (1 + |k|^2) cos(k.x + phi_k)`` over the
+  wave vectors ``k in {0..7}^3 \\ {0}`` (8 modes per axis), Gaussian ``g_k``,
+  uniform phases, rescaled to unit RMS.
+* ``power_law``: an isotropic random field with energy spectrum ``k^-5/3``
+  for ``1 <= |k| <= kmax`` (amplitude ``|k|^-11/6`` per mode in 3D), random
+  phases, unit RMS.
+"""
+
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+TWO_PI = 2.0 * math.pi
+
+
+def node_coords(n: int, length: float) -> np.ndarray:
+    """Node positions ``i * length / n`` of a periodic axis."""
+    return np.arange(n, dtype=np.float64) * (length / n)
+
+
+def _periodic_gauss_1d(x, centre, sigma, length):
+    out = np.zeros_like(x)
+    for img in (-1, 0, 1):
+        out += np.exp(-((x - centre + img * length) ** 2) / (2.0 * sigma * sigma))
+    return out
+
+
+def gaussians(shape, centres, sigmas, length=1.0, amplitude=1.0):
+    """Sum of periodised Gaussians; ``centres[j]`` is x first."""
+    ndim = len(shape)
+    out = np.zeros(shape, dtype=np.float64)
+    for c, s in zip(centres, sigmas):
+        prod = None
+        for d in range(ndim):
+            n = shape[ndim - 1 - d]
+            g = _periodic_gauss_1d(node_coords(n, length), c[d], s, length)
+            view = [1] * ndim
+            view[ndim - 1 - d] = n
+            g = g.reshape(view)
+            prod = g if prod is None else prod * g
+        out += amplitude * prod
+    return out
+
+
+def random_gaussians(shape, count, seed, length=TWO_PI, smin=0.05, smax=0.15):
+    """``count`` Gaussians, centres uniform in the box, sigma = length * U[smin, smax]."""
+    rng = np.random.default_rng(seed)
+    ndim = len(shape)
+    centres = rng.uniform(0.0, length, (count, ndim))
+    sigmas = length * rng.uniform(smin, smax, count)
+    return gaussians(shape, centres, sigmas, length)
+
+
+def abc_velocity(shape, A=1.0, B=1.0, C=1.0, dtype=np.float32):
+    """ABC flow on ``[0, 2 pi)^3`` sampled at the nodes; returns (3, nz, ny, nx)."""
+    nz, ny, nx = shape
+    x = node_coords(nx, TWO_PI)
+    y = node_coords(ny, TWO_PI)
+    z = node_coords(nz, TWO_PI)
+    u = np.empty((3, nz, ny, nx), dtype=dtype)
+    u[0] = (A * np.sin(z)[:, None, None] + C * np.cos(y)[None, :, None]).astype(dtype)
+    u[1] = (B * np.sin(x)[None, None, :] + A * np.cos(z)[:, None, None]).astype(dtype)
+    u[2] = (C * np.sin(y)[None, :, None] + B * np.cos(x)[None, None, :]).astype(dtype)
+    return u
+
+
+def uniform_velocity(shape, vel, dtype=np.float32):
+    """Constant velocity ``vel`` (x first) on every node; (ndim, *shape)."""
+    ndim = len(shape)
+    u = np.empty((ndim,) + tuple(shape), dtype=dtype)
+    for d in range(ndim):
+        u[d] = vel[d]
+    return u
+
+
+def cellular_velocity_2d(shape, amp=1.0, dtype=np.float32):
+    """Divergence-free cellular flow ``u = sin x cos y, v = -cos x sin y`` on [0, 2 pi)^2."""
+    ny, nx = shape
+    x = node_coords(nx, TWO_PI)[None, :]
+    y = node_coords(ny, TWO_PI)[:, None]
+    u = np.empty((2, ny, nx), dtype=dtype)
+    u[0] = (amp * np.sin(x) * np.cos(y)).astype(dtype)
+    u[1] = (-amp * np.cos(x) * np.sin(y)).astype(dtype)
+    return u
+
+
+def fourier_modes(shape, seed, kmax=8, dtype=np.float32):
+    """Smooth random field with ``kmax`` modes per axis (3D), unit RMS."""
+    rng = np.random.default_rng(seed)
+    nz, ny, nx = shape
+    ks = np.arange(kmax)
+    kz, ky, kx = np.meshgrid(ks, ks, ks, indexing="ij")
+    g = rng.standard_normal((kmax, kmax, kmax))
+    ph = rng.uniform(0.0, TWO_PI, (kmax, kmax, kmax))
+    amp = g / (1.0 + kx**2 + ky**2 + kz**2)
+    amp[0, 0, 0] = 0.0
+    a = amp * np.exp(1j * ph)  # field = Re sum_k a_k e^{i k.x}
+    ex = np.exp(1j * np.outer(ks, node_coords(nx, TWO_PI)))  # (kmax, nx)
+    ey = np.exp(1j * np.outer(ks, node_coords(ny, TWO_PI)))
+    ez = np.exp(1j * np.outer(node_coords(nz, TWO_PI), ks))  # (nz, kmax)
+    A = np.einsum("zyk,kx->zyx", a, ex)  # A[kz, ky, x] = sum_kx a e^{i kx x}
+    B = np.einsum("zkx,ky->zyx", A, ey)  # B[kz, y, x] = sum_ky A e^{i ky y}
+    out = np.empty((nz, ny, nx), dtype=np.float64)
+    Bf = B.reshape(kmax, ny * nx)
+    for z0 in range(0, nz, 64):
+        z1 = min(nz, z0 + 64)
+        out[z0:z1] = np.real(ez[z0:z1] @ Bf).reshape(z1 - z0, ny, nx)
+    out /= math.sqrt(np.mean(out * out))
+    return out.astype(dtype)
+
+
+def power_law(shape, seed, kmax=64, dtype=np.float32):
+    """Isotropic random field, E(k) ~ k^-5/3 for 1 <= |k| <= kmax, unit RMS."""
+    rng = np.random.default_rng(seed)
+    nz, ny, nx = shape
+    kz = np.fft.fftfreq(nz, 1.0 / nz)[:, None, None]
+    ky = np.fft.fftfreq(ny, 1.0 / ny)[None, :, None]
+    kx = np.fft.rfftfreq(nx, 1.0 / nx)[None, None, :]
+    kk = np.sqrt(kx * kx + ky * ky + kz * kz)
+    with np.errstate(divide="ignore"):
+        amp = np.where((kk >= 1.0) & (kk <= kmax), kk ** (-11.0 / 6.0), 0.0)
+    ph = rng.uniform(0.0, TWO_PI, amp.shape)
+    spec = amp * np.exp(1j * ph)
+    out = np.fft.irfftn(spec, s=(nz, ny, nx))
+    out /= math.sqrt(np.mean(out * out))
+    return out.astype(dtype)
+
+
+def abc_dt(shape, cfl, length=TWO_PI, umax=2.0):
+    """Time step giving ``max |u_d| dt / dx = cfl`` on a cubic periodic box."""
+    dx = length / shape[-1]
+    return cfl * dx / umax
+
+
+def uneven_grids(count=64, seed_sizes=3100, seed_vel=3101, nmin=32, nmax=192):
+    """Sizes ``N_g ~ U{nmin..nmax}`` and uniform velocities ``U[-1, 1]^3``."""
+    sizes = np.random.default_rng(seed_sizes).integers(nmin, nmax + 1, count)
+    vels = np.random.default_rng(seed_vel).uniform(-1.0, 1.0, (count, 3))
+    return [int(s) for s in sizes], vels

@@ -1,0 +1,286 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Tolerance.  The GPU interpolates in FP32; each output is a short chain of
+FP32 lerps (at most ~20 roundings of relative size 2^-24 per call, three
+calls per axis), so a step's FP32 error is a few 1e-7 of the field scale.
+The bound used is the one the method's target states, 1e-5 relative L2 per
+step, accumulated linearly over K steps (the schemes are L2-stable, so a
+step does not amplify earlier rounding errors): relL2 <= 1e-5 K, and the
+same bound on max |gpu - oracle| / max |phi0|.  Cases whose result is a
+permutation of FP32 inputs (integer Courant numbers) or a constant must be
+bit-exact.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1606_06117_amd import workloads as W
+
+from helpers import box_parity, gpu_advect, oracle_advect, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+SCHEMES = [oracle.CIR, oracle.FEC, oracle.BEC, oracle.CEC]
+NAMES = {0: "cir", 1: "fec", 2: "bec", 3: "cec"}
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_1606_06117_amd import native
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    c = native.Context(0)
+    yield c
+    c.close()
+
+
+def check(got, ref, phi0, steps, label=""):
+    l2 = rel_l2(got, ref)
+    linf = float(np.max(np.abs(got - ref))) / float(np.max(np.abs(phi0)))
+    print(f"{label} relL2={l2:.3e} Linf={linf:.3e}")
+    assert l2 <= TOL * steps, (label, l2)
+    assert linf <= TOL * steps, (label, linf)
+
+
+# ---------------------------------------------------------------------------
+# small configurations: full-grid comparison
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_gaussian_2d_uniform(ctx, scheme):
+    """64x64 Gaussian, uniform U = (1, 0.5), CFL 0.7, 1 and 100 steps."""
+    N = 64
+    phi = W.gaussians((N, N), [(0.5, 0.5)], [0.1]).astype(np.float32)
+    u = W.uniform_velocity((N, N), (1.0, 0.5))
+    dx = (1.0 / N, 1.0 / N)
+    dt = 0.7 / N
+    for steps in (1, 100):
+        got = gpu_advect(ctx, phi, u, dx, dt, scheme, steps)
+        ref = oracle_advect(phi, u, dx, dt, scheme, steps)
+        check(got, ref, phi, steps, f"2d {NAMES[scheme]} steps={steps}")
+
+
+@pytest.mark.parametrize("cfl", [0.9, 1.5, 2.0, 3.5])
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_abc_3d(ctx, scheme, cfl):
+    """ABC flow, 3D, several tiles with ragged tails, reach 1..4."""
+    shape = (36, 40, 72)  # z, y, x: x spans 2 tiles of 64 (ragged), y 5 tiles of 8
+    phi = W.random_gaussians(shape, 8, seed=2000).astype(np.float32)
+    u = W.abc_velocity(shape)
+    dx = tuple(2 * np.pi / n for n in reversed(shape))
+    dt = cfl * dx[0] / 2.0
+    for steps in (1, 3):
+        got = gpu_advect(ctx, phi, u, dx, dt, scheme, steps, step0=1)
+        ref = oracle_advect(phi, u, dx, dt, scheme, steps, step0=1)
+        check(got, ref, phi, steps, f"abc {NAMES[scheme]} cfl={cfl} steps={steps}")
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_cellular_2d_ragged(ctx, scheme):
+    """2D cellular flow on a ragged 37 x 29 grid at CFL 1.3, variable signs."""
+    shape = (29, 37)
+    rng = np.random.default_rng(77)
+    phi = rng.standard_normal(shape).astype(np.float32)
+    u = W.cellular_velocity_2d(shape)
+    dx = (2 * np.pi / 37, 2 * np.pi / 29)
+    dt = 1.3 * dx[1]
+    for steps in (1, 6):
+        got = gpu_advect(ctx, phi, u, dx, dt, scheme, steps)
+        ref = oracle_advect(phi, u, dx, dt, scheme, steps)
+        check(got, ref, phi, steps, f"cell2d {NAMES[scheme]} steps={steps}")
+
+
+@pytest.mark.parametrize("cfl,steps", [(0.75, 40), (3.75, 8)])
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_cosine_1d_paper(ctx, scheme, cfl, steps):
+    """The paper's 1D cosine test: N = 30 at CFL 0.75 and 3.75 (section 4)."""
+    N = 30
+    x = np.arange(N) / N
+    phi = (-np.cos(2 * np.pi * x)).astype(np.float32)
+    u = np.ones((1, N), dtype=np.float32)
+    dx = (1.0 / N,)
+    dt = cfl / N
+    got = gpu_advect(ctx, phi, u, dx, dt, scheme, steps)
+    ref = oracle_advect(phi, u, dx, dt, scheme, steps)
+    check(got, ref, phi, steps, f"1d {NAMES[scheme]} cfl={cfl}")
+
+
+# ---------------------------------------------------------------------------
+# exact cases
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+@pytest.mark.parametrize("ndim", [1, 2, 3])
+def test_integer_shift_bit_exact(ctx, scheme, ndim):
+    shape = (20, 24, 72)[3 - ndim:]
+    rng = np.random.default_rng(100 + ndim)
+    phi = rng.standard_normal(shape).astype(np.float32)
+    shifts = (1, -2, 3)[:ndim]
+    dx = tuple(1.0 for _ in range(ndim))
+    u = W.uniform_velocity(shape, shifts)
+    got = gpu_advect(ctx, phi, u, dx, 1.0, scheme, 3, step0=0)
+    expect = phi.astype(np.float64)
+    for d, k in enumerate(shifts):
+        expect = np.roll(expect, 3 * k, axis=ndim - 1 - d)
+    assert np.array_equal(got, expect)
+    ref = oracle_advect(phi, u, dx, 1.0, scheme, 3)
+    assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_constant_field_bit_exact(ctx, scheme):
+    shape = (24, 20, 40)
+    u = W.abc_velocity(shape)
+    dx = tuple(2 * np.pi / n for n in reversed(shape))
+    for val in (1.0, -2.5, 0.1):
+        phi = np.full(shape, val, dtype=np.float32)
+        got = gpu_advect(ctx, phi, u, dx, 1.7 * dx[0] / 2, scheme, 2)
+        assert np.all(got == np.float64(np.float32(val)))
+
+
+def test_linear_field_cir(ctx):
+    """CIR reproduces a field linear in x away from the periodic seam (FP32)."""
+    ny, nx = 16, 128
+    x = np.arange(nx, dtype=np.float64)
+    phi = np.broadcast_to(0.01 * x + 0.5, (ny, nx)).astype(np.float32)
+    rng = np.random.default_rng(4)
+    u = rng.uniform(-2.5, 2.5, (2, ny, nx)).astype(np.float32)
+    got = gpu_advect(ctx, phi, u, (1.0, 1.0), 1.0, oracle.CIR, 1)
+    c = oracle.courant(u, 1.0, (1.0, 1.0))
+    expect = 0.01 * (x[None, :] - c[0]) + 0.5
+    inner = (x[None, :] - 3 >= 0) & (x[None, :] + 3 < nx)
+    assert np.max(np.abs(got - expect)[inner]) < 4 * 2.0**-24 * 2.0
+
+
+# ---------------------------------------------------------------------------
+# state, determinism, resumption, Courant bound, errors
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_deterministic_and_resumable(ctx, scheme):
+    shape = (24, 32, 40)
+    phi = W.random_gaussians(shape, 4, seed=9).astype(np.float32)
+    u = W.abc_velocity(shape)
+    dx = tuple(2 * np.pi / n for n in reversed(shape))
+    dt = 1.2 * dx[0] / 2
+    a = gpu_advect(ctx, phi, u, dx, dt, scheme, 5, step0=0)
+    b = gpu_advect(ctx, phi, u, dx, dt, scheme, 5, step0=0)
+    assert np.array_equal(a, b)
+    first = gpu_advect(ctx, phi, u, dx, dt, scheme, 3, step0=0).astype(np.float32)
+    rest = gpu_advect(ctx, first, u, dx, dt, scheme, 2, step0=3)
+    assert np.array_equal(a, rest)
+
+
+def test_courant_hint(ctx):
+    import torch
+    from paper_1606_06117_amd import native
+    shape = (24, 24, 32)
+    phi = W.random_gaussians(shape, 4, seed=10).astype(np.float32)
+    u = W.abc_velocity(shape)
+    dx = tuple(2 * np.pi / n for n in reversed(shape))
+    dt = 1.5 * dx[0] / 2
+    ut = torch.from_numpy(u).cuda()
+    assert ctx.courant_max(ut, dx, dt) == pytest.approx(1.5, rel=1e-6)
+    measured = gpu_advect(ctx, phi, u, dx, dt, oracle.CEC, 2)
+    hinted = gpu_advect(ctx, phi, u, dx, dt, oracle.CEC, 2, courant_max=1.5)
+    assert np.array_equal(measured, hinted)
+    ctx.check()
+    # a hint below the true bound: kernels clamp (in bounds) and report it
+    gpu_advect(ctx, phi, u, dx, dt, oracle.CEC, 1, courant_max=0.5)
+    with pytest.raises(native.SlaError) as ei:
+        ctx.check()
+    assert ei.value.status == native.ECOURANT
+    ctx.check()  # the record was cleared
+
+
+def test_errors(ctx):
+    import torch
+    from paper_1606_06117_amd import native
+    shape = (16, 16, 16)
+    phi = torch.zeros(shape, device="cuda")
+    u = torch.zeros((3,) + shape, device="cuda")
+    dx = (1.0, 1.0, 1.0)
+    with pytest.raises(native.SlaError) as ei:
+        ctx.advect(phi, u, dx, float("nan"), "cec", 1)
+    assert ei.value.status == native.EINVAL
+    with pytest.raises(native.SlaError) as ei:
+        ctx.advect(phi, u, dx, 1.0, 7, 1)
+    assert ei.value.status == native.EINVAL
+    with pytest.raises(native.SlaError) as ei:
+        ctx.advect(phi, u, dx, 1.0, "cec", -1)
+    assert ei.value.status == native.EINVAL
+    with pytest.raises(native.SlaError) as ei:
+        ctx.advect(phi, u, (1.0, 0.0, 1.0), 1.0, "cec", 1)
+    assert ei.value.status == native.EINVAL
+    small = torch.zeros((4, 16, 16), device="cuda")
+    with pytest.raises(native.SlaError) as ei:
+        ctx.advect(small, torch.zeros((3, 4, 16, 16), device="cuda"), dx, 1.0, "cec", 1)
+    assert ei.value.status == native.EINVAL
+    # Courant number 4 is beyond the kernels' reach
+    u.fill_(4.0)
+    with pytest.raises(native.SlaError) as ei:
+        ctx.advect(phi, u, dx, 1.0, "cec", 1)
+    assert ei.value.status == native.ECOURANT
+    u.fill_(float("nan"))
+    with pytest.raises(native.SlaError) as ei:
+        ctx.advect(phi, u, dx, 1.0, "cir", 1)
+    assert ei.value.status == native.EINVAL
+    # steps == 0 leaves phi untouched
+    phi.fill_(3.0)
+    ctx.advect(phi, u, dx, 1.0, "cec", 0)
+    assert bool((phi == 3.0).all())
+
+
+def test_norms(ctx):
+    import torch
+    rng = np.random.default_rng(5)
+    for n in (1, 1000, 1 << 20, 3_000_001):
+        a = rng.standard_normal(n).astype(np.float32)
+        b = rng.standard_normal(n).astype(np.float32)
+        got = ctx.norms(torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda())
+        ref = oracle.reductions(a, b)
+        for k in (0, 1, 3, 4):
+            assert got[k] == pytest.approx(ref[k], rel=1e-12, abs=1e-12 * n)
+        assert got[2] == ref[2]
+        again = ctx.norms(torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda())
+        assert again == got  # bitwise reproducible
+
+
+# ---------------------------------------------------------------------------
+# full-size configurations (the benchmark's launch shapes), sampled boxes
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_abc_256_cfl15_boxes(ctx, scheme):
+    """256^3, 8 Gaussians, ABC, CFL 1.5: oracle on sampled boxes (exact halos)."""
+    shape = (256, 256, 256)
+    phi = W.random_gaussians(shape, 8, seed=2000).astype(np.float32)
+    u = W.abc_velocity(shape)
+    dx = tuple(2 * np.pi / n for n in reversed(shape))
+    dt = 1.5 * dx[0] / 2
+    steps = 2
+    got = gpu_advect(ctx, phi, u, dx, dt, scheme, steps)
+    halo = steps * 3 * 2
+    l2, linf = box_parity(got, phi, u, dx, dt, scheme, steps, halo, (24, 24, 24),
+                          np.random.default_rng(1), 3)
+    print(f"256^3 {NAMES[scheme]} boxes relL2={l2:.3e} Linf={linf:.3e}")
+    assert l2 <= TOL * steps and linf <= TOL * steps
+
+
+def test_abc_512_cfl09_cec_boxes(ctx):
+    """The benchmark's workload: 512^3 one scalar, ABC, CFL 0.9, third order."""
+    import torch
+    shape = (512, 512, 512)
+    phi = W.random_gaussians(shape, 8, seed=2000).astype(np.float32)
+    u = W.abc_velocity(shape)
+    dx = tuple(2 * np.pi / n for n in reversed(shape))
+    dt = 0.9 * dx[0] / 2
+    steps = 2
+    got = gpu_advect(ctx, phi, u, dx, dt, oracle.CEC, steps, courant_max=0.9)
+    l2, linf = box_parity(got, phi, u, dx, dt, oracle.CEC, steps, steps * 3, (24, 24, 24),
+                          np.random.default_rng(2), 4)
+    print(f"512^3 cec boxes relL2={l2:.3e} Linf={linf:.3e}")
+    assert l2 <= TOL * steps and linf <= TOL * steps
+    torch.cuda.empty_cache()
