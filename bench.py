@@ -88,6 +88,30 @@ def cpu_baseline(phi, u, dx, dt, scheme, edge, steps):
     }
 
 
+def copy_probe(reps: int, warmup: int) -> int:
+    """Copy a 512 MiB FP32 buffer ``reps`` times (read 512 MiB + write 512 MiB each)."""
+    import torch
+    n = 128 * 1024 * 1024
+    src = torch.ones(n, device="cuda:0", dtype=torch.float32)
+    dst = torch.empty_like(src)
+    for _ in range(max(1, warmup)):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    moved = 2 * 4 * n
+    print(json.dumps({"probe": "copy", "bytes_read_per_copy": 4 * n, "bytes_written_per_copy": 4 * n,
+                      "ms_per_copy": ms, "GBps": moved / (ms / 1e3) / 1e9,
+                      "frac_of_peak": moved / (ms / 1e3) / 1e9 / HBM_PEAK_GBS}), flush=True)
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -99,6 +123,9 @@ def main(argv=None):
     ap.add_argument("--cpu-edge", type=int, default=128, help="edge of the oracle's sample box")
     ap.add_argument("--cpu-steps", type=int, default=12, help="oracle steps on the sample box")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--probe", choices=["copy"], default=None,
+                    help="instead of the benchmark, time a plain device copy of known size "
+                         "(achievable bandwidth; calibrates HBM byte counters)")
     args = ap.parse_args(argv)
 
     if args.gpus != 1:
@@ -108,6 +135,9 @@ def main(argv=None):
 
     import numpy as np
     import torch
+
+    if args.probe == "copy":
+        return copy_probe(args.steps, args.warmup)
 
     sys.path.insert(0, ROOT)
     from paper_1606_06117_amd import native

@@ -300,6 +300,9 @@ int sla_advect(sla_ctx* ctx, const sla_grid* grid, float* phi, const float* u, d
   rc = ensure_work(ctx, n);
   if (rc) return rc;
 
+  // A 3D third-order step whose reach is 1 on every axis runs as one fused
+  // kernel (20 B/cell); other cases run one sweep kernel per axis.
+  const bool fused3d = ndim == 3 && rmax == 1;
   float* cur = phi;
   float* nxt = ctx->work;
   hipError_t e = hipSuccess;
@@ -320,6 +323,13 @@ int sla_advect(sla_ctx* ctx, const sla_grid* grid, float* phi, const float* u, d
         std::swap(cur, nxt);
         break;
       case SLA_CEC:
+        if (fused3d) {
+          e = run(ctx, SLA_K_CEC3D, [&] {
+            return sla::launch_cec3d(1, m % 2 == 0, geo, cur, u, nxt, ctx->flag, ctx->stream);
+          });
+          std::swap(cur, nxt);
+          break;
+        }
         for (int j = 0; j < ndim && e == hipSuccess; ++j) {
           const int d = (m % 2 == 0) ? j : ndim - 1 - j;
           e = run(ctx, SLA_K_SWEEP_X + d, [&] {

@@ -1,0 +1,300 @@
+// Fused third-order 3D step: all three axis sweeps of one time step in one
+// pass over HBM (read phi and u once, write phi once: 20 B per cell).
+//
+// What is computed is the per-axis third-order sweep (eq. intro:CEC with the
+// weights of eq. intro:CECcoef, one axis at a time as in eqs. split:1-2),
+// applied x, y, z on even steps and z, y, x on odd steps.  Per axis and node:
+//   Phi1 = L_U Phi,  e = Phi - L_{-U} Phi1,
+//   out  = Phi1 + 1/2 [e_a + (1+f)/3 (e_b - e_a)].
+//
+// Layout of the work.  A workgroup owns an x-z tile of TX x TZ cells and
+// marches along y over a chunk of planes.  The middle sweep (y) is then a
+// pipeline along the march: each thread keeps, for its columns, rings of the
+// last three planes of its input, Phi1 and e in registers, so the y halo
+// costs a pipeline delay and no recomputation.  The first sweep (x on even
+// steps, z on odd ones) runs in-plane through LDS on the tile grown by the
+// last sweep's halo; the last sweep (z, resp. x) runs in-plane on the y
+// output.  Both orders share this kernel with the roles of x and z swapped.
+//
+// This kernel serves reach 1 (every |c| < 1): the departure interval of a
+// node is (i, i - s) and each call reads one neighbour.
+
+#include <type_traits>
+
+#include "common.h"
+
+namespace sla {
+namespace {
+
+constexpr int kThreads = 256;
+
+__device__ __forceinline__ float lerp(float p, float q, float f) { return fmaf(f, q - p, p); }
+
+__device__ __forceinline__ int wrapk(int v, int n) {
+  while (v < 0) v += n;
+  while (v >= n) v -= n;
+  return v;
+}
+
+// Reach-1 departure: fraction and far-node offset (+-1) for c and for -c.
+struct Dep1 {
+  float f;
+  int ob;   // far node of L_U:    i + ob, ob = -1 if c >= 0 else +1
+  int obr;  // far node of L_{-U}: i + obr, obr = -1 if -c >= 0 else +1
+};
+
+__device__ __forceinline__ Dep1 depart1(float c, int* flag) {
+  const float mag = fabsf(c);
+  float f = mag;
+  if (!(mag < 1.f)) {  // beyond reach 1: keep the fraction, record it
+    if (mag == mag) *flag = 1;
+    f = mag - floorf(mag);
+  }
+  Dep1 d;
+  d.f = f;
+  d.ob = c >= 0.f ? -1 : 1;
+  d.obr = c > 0.f ? 1 : -1;
+  return d;
+}
+
+template <bool EVEN>
+struct Cec3dShape {
+  static constexpr int R = 1;
+  static constexpr int H = 3 * R;      // halo of a sweep's input
+  static constexpr int TX = 64, TZ = 16;
+  static constexpr int W = TX + 2 * H; // padded row length (x)
+  static constexpr int HZ = TZ + 2 * H;
+  static constexpr int NP = W * HZ;    // padded plane
+  // first sweep along A, last along B
+  static constexpr int TA = EVEN ? TX : TZ;
+  static constexpr int TB = EVEN ? TZ : TX;
+  static constexpr int SA = EVEN ? 1 : W;  // LDS stride along A
+  static constexpr int SB = EVEN ? W : 1;  // LDS stride along B
+  // y-pipeline region: A in [0, TA), B in [-H, TB + H)
+  static constexpr int NY = TA * (TB + 2 * H);
+  static constexpr int NC = (NY + kThreads - 1) / kThreads;  // columns per thread
+};
+
+// padded LDS index of tile-relative (a, b)
+template <bool EVEN>
+__device__ __forceinline__ int pidx(int a, int b) {
+  using S = Cec3dShape<EVEN>;
+  const int x = EVEN ? a : b, z = EVEN ? b : a;
+  return (z + S::H) * S::W + (x + S::H);
+}
+
+template <bool EVEN>
+__global__ __launch_bounds__(kThreads) void k_cec3d_r1(const float* __restrict__ phi,
+                                                       const float* __restrict__ ux,
+                                                       const float* __restrict__ uy,
+                                                       const float* __restrict__ uz,
+                                                       float* __restrict__ out, Geo g,
+                                                       int ychunk, int* flag) {
+  using S = Cec3dShape<EVEN>;
+  constexpr int H = S::H, TA = S::TA, TB = S::TB, SA = S::SA, SB = S::SB;
+  __shared__ float P[S::NP];   // phi at the loaded plane, padded
+  __shared__ float CA[S::NP];  // Courant numbers of the first sweep
+  __shared__ float CB[S::NP];  // Courant numbers of the last sweep (output plane)
+  __shared__ float S1[S::NP];  // Phi1 of the first, then of the last sweep
+  __shared__ float SE[S::NP];  // e of the first, then of the last sweep
+  __shared__ float AO[S::NP];  // first-sweep output (y-pipeline input)
+  __shared__ float YO[S::NP];  // y-sweep output (last-sweep input)
+
+  const int tid = threadIdx.x;
+  const int x0 = blockIdx.x * S::TX, z0 = blockIdx.y * S::TZ;
+  const int y0 = blockIdx.z * ychunk;
+  const int y1 = min(y0 + ychunk, g.ny);
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  const unsigned nxy = unsigned(nx) * unsigned(ny);
+  const float* uA = EVEN ? ux : uz;
+  const float* uB = EVEN ? uz : ux;
+  const float lamA = EVEN ? g.lam[0] : g.lam[2];
+  const float lamB = EVEN ? g.lam[2] : g.lam[0];
+  const float lamY = g.lam[1];
+
+  // global x-z offset (without the y term) of tile-relative (a, b)
+  auto xz_off = [&](int a, int b) -> unsigned {
+    const int x = EVEN ? a : b, z = EVEN ? b : a;
+    const int gx = wrapk(x0 + x, nx), gz = wrapk(z0 + z, nz);
+    return unsigned(gx) + nxy * unsigned(gz);
+  };
+
+  // y-pipeline rings, per column: input a, Phi1, e, Courant (3 planes each)
+  float ra[3][S::NC], r1[3][S::NC], re[3][S::NC], rc[3][S::NC];
+  int ycol[S::NC];
+  unsigned ybase[S::NC];
+#pragma unroll
+  for (int j = 0; j < S::NC; ++j) {
+    const int e = tid + j * kThreads;
+    const int ee = e < S::NY ? e : 0;
+    const int b = -H + ee / TA, a = ee % TA;
+    ycol[j] = pidx<EVEN>(a, b);
+    ybase[j] = xz_off(a, b);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) ra[k][j] = r1[k][j] = re[k][j] = rc[k][j] = 0.f;
+  }
+
+  const int iters = (y1 - y0) + 2 * H;
+  // The ring slot of local plane t is t % 3; the loop body is unrolled by 3
+  // so that every slot index is a compile-time constant.
+  auto body = [&](auto phase, int t) {
+    constexpr int p0 = decltype(phase)::value;  // t % 3
+    constexpr int p1 = (p0 + 2) % 3;            // (t - 1) % 3
+    constexpr int p2 = (p0 + 1) % 3;            // (t - 2) % 3
+    constexpr int p3 = p0;                      // (t - 3) % 3
+    const int q = wrapk(y0 - H + t, ny);        // loaded plane
+    const unsigned qoff = unsigned(q) * unsigned(nx);
+
+    // 1. load phi (whole padded plane) and the first sweep's Courant numbers
+    for (int e = tid; e < S::NP; e += kThreads) {
+      const int z = e / S::W - H, x = e % S::W - H;
+      const int a = EVEN ? x : z, b = EVEN ? z : x;
+      P[e] = phi[xz_off(a, b) + qoff];
+    }
+    {
+      constexpr int LA = TA + 4, LB = TB + 2 * H;  // A in [-2, TA+2), B all
+      for (int e = tid; e < LA * LB; e += kThreads) {
+        const int b = -H + e / LA, a = -2 + e % LA;
+        CA[pidx<EVEN>(a, b)] = uA[xz_off(a, b) + qoff] * lamA;
+      }
+    }
+    __syncthreads();
+    // 2. first sweep, Phi1 on A in [-2, TA+2)
+    {
+      constexpr int LA = TA + 4, LB = TB + 2 * H;
+      for (int e = tid; e < LA * LB; e += kThreads) {
+        const int b = -H + e / LA, a = -2 + e % LA;
+        const int i = pidx<EVEN>(a, b);
+        const Dep1 d = depart1(CA[i], flag);
+        S1[i] = lerp(P[i], P[i + d.ob * SA], d.f);
+      }
+    }
+    __syncthreads();
+    // 3. first sweep, e on A in [-1, TA+1)
+    {
+      constexpr int LA = TA + 2, LB = TB + 2 * H;
+      for (int e = tid; e < LA * LB; e += kThreads) {
+        const int b = -H + e / LA, a = -1 + e % LA;
+        const int i = pidx<EVEN>(a, b);
+        const Dep1 d = depart1(CA[i], flag);
+        SE[i] = P[i] - lerp(S1[i], S1[i + d.obr * SA], d.f);
+      }
+    }
+    __syncthreads();
+    // 4. first sweep output on A in [0, TA)
+    {
+      constexpr int LB = TB + 2 * H;
+      for (int e = tid; e < TA * LB; e += kThreads) {
+        const int b = -H + e / TA, a = e % TA;
+        const int i = pidx<EVEN>(a, b);
+        const Dep1 d = depart1(CA[i], flag);
+        const float ea = SE[i], eb = SE[i + d.ob * SA];
+        const float w = fmaf(d.f, 1.f / 3.f, 1.f / 3.f);
+        AO[i] = fmaf(0.5f, fmaf(w, eb - ea, ea), S1[i]);
+      }
+    }
+    __syncthreads();
+    // 5. y sweep as a pipeline along the march (registers), and the last
+    //    sweep's Courant numbers for the output plane t - 6
+    const bool emit = t >= 2 * H;
+    if (emit) {
+      const unsigned ooff = unsigned(wrapk(y0 - H + t - H, ny)) * unsigned(nx);
+      constexpr int LB = TB + 4;  // B in [-2, TB+2)
+      for (int e = tid; e < TA * LB; e += kThreads) {
+        const int b = -2 + e / TA, a = e % TA;
+        CB[pidx<EVEN>(a, b)] = uB[xz_off(a, b) + ooff] * lamB;
+      }
+    }
+    {
+      const unsigned cyoff = unsigned(wrapk(y0 - H + t - 1, ny)) * unsigned(nx);
+#pragma unroll
+      for (int j = 0; j < S::NC; ++j) {
+        if (S::NC * kThreads > S::NY && tid + j * kThreads >= S::NY) continue;
+        const int i = ycol[j];
+        ra[p0][j] = AO[i];                        // input at plane t
+        rc[p1][j] = uy[ybase[j] + cyoff] * lamY;  // Courant at plane t-1
+        // Phi1 at plane t-1
+        Dep1 d = depart1(rc[p1][j], flag);
+        r1[p1][j] = lerp(ra[p1][j], d.ob < 0 ? ra[p2][j] : ra[p0][j], d.f);
+        // e at plane t-2
+        d = depart1(rc[p2][j], flag);
+        re[p2][j] = ra[p2][j] - lerp(r1[p2][j], d.obr > 0 ? r1[p1][j] : r1[p3][j], d.f);
+        // y-sweep output at plane t-3
+        d = depart1(rc[p3][j], flag);
+        const float ea = re[p3][j];
+        const float eb = d.ob < 0 ? re[p1][j] : re[p2][j];  // e at t-4 (slot p1) or t-2
+        const float w = fmaf(d.f, 1.f / 3.f, 1.f / 3.f);
+        YO[i] = fmaf(0.5f, fmaf(w, eb - ea, ea), r1[p3][j]);
+      }
+    }
+    __syncthreads();
+    if (!emit) return;
+    // 6. last sweep, Phi1 on B in [-2, TB+2)
+    {
+      constexpr int LB = TB + 4;
+      for (int e = tid; e < TA * LB; e += kThreads) {
+        const int b = -2 + e / TA, a = e % TA;
+        const int i = pidx<EVEN>(a, b);
+        const Dep1 d = depart1(CB[i], flag);
+        S1[i] = lerp(YO[i], YO[i + d.ob * SB], d.f);
+      }
+    }
+    __syncthreads();
+    // 7. last sweep, e on B in [-1, TB+1)
+    {
+      constexpr int LB = TB + 2;
+      for (int e = tid; e < TA * LB; e += kThreads) {
+        const int b = -1 + e / TA, a = e % TA;
+        const int i = pidx<EVEN>(a, b);
+        const Dep1 d = depart1(CB[i], flag);
+        SE[i] = YO[i] - lerp(S1[i], S1[i + d.obr * SB], d.f);
+      }
+    }
+    __syncthreads();
+    // 8. last sweep output on the tile, stored to HBM at plane t - 6
+    {
+      const int yo = y0 - H + t - H;
+      for (int e = tid; e < TA * TB; e += kThreads) {
+        const int b = e / TA, a = e % TA;
+        const int x = EVEN ? a : b, z = EVEN ? b : a;
+        if (x0 + x >= nx || z0 + z >= nz) continue;
+        const int i = pidx<EVEN>(a, b);
+        const Dep1 d = depart1(CB[i], flag);
+        const float ea = SE[i], eb = SE[i + d.ob * SB];
+        const float w = fmaf(d.f, 1.f / 3.f, 1.f / 3.f);
+        out[unsigned(x0 + x) + unsigned(nx) * unsigned(yo) + nxy * unsigned(z0 + z)] =
+            fmaf(0.5f, fmaf(w, eb - ea, ea), S1[i]);
+      }
+    }
+    // no barrier needed here: the next plane's first writes (P, CA) and
+    // every array the last sweep reads are separated by barriers 1-4
+  };
+
+  for (int t = 0; t < iters; t += 3) {
+    body(std::integral_constant<int, 0>{}, t);
+    if (t + 1 < iters) body(std::integral_constant<int, 1>{}, t + 1);
+    if (t + 2 < iters) body(std::integral_constant<int, 2>{}, t + 2);
+  }
+}
+
+}  // namespace
+
+hipError_t launch_cec3d(int R, bool even, const Geo& g, const float* phi, const float* u,
+                        float* out, int* flag, hipStream_t st) {
+  if (R != 1) return hipErrorInvalidValue;
+  const size_t n = (size_t)g.ncells;
+  const float* ux = u;
+  const float* uy = u + n;
+  const float* uz = u + 2 * n;
+  const int ychunk = g.ny >= 256 ? 128 : 64;
+  dim3 grid((g.nx + 63) / 64, (g.nz + 15) / 16, (g.ny + ychunk - 1) / ychunk);
+  if (even)
+    hipLaunchKernelGGL(k_cec3d_r1<true>, grid, dim3(kThreads), 0, st, phi, ux, uy, uz, out, g,
+                       ychunk, flag);
+  else
+    hipLaunchKernelGGL(k_cec3d_r1<false>, grid, dim3(kThreads), 0, st, phi, ux, uy, uz, out, g,
+                       ychunk, flag);
+  return hipGetLastError();
+}
+
+}  // namespace sla

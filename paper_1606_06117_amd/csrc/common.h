@@ -37,6 +37,11 @@ hipError_t launch_ec(int ndim, int scheme, int R, const Geo& g, const float* phi
 hipError_t launch_cec_sweep(int d, int R, const Geo& g, const float* phi,
                             const float* u_d, float* out, int* flag, hipStream_t st);
 
+// Fused three-axis third-order step (reach 1 only): x,y,z order if even,
+// z,y,x otherwise.  Returns hipErrorInvalidValue for other reaches.
+hipError_t launch_cec3d(int R, bool even, const Geo& g, const float* phi, const float* u,
+                        float* out, int* flag, hipStream_t st);
+
 // Max |u_d| per axis over the grid (FP32, NaN propagates) into out3 (device).
 hipError_t launch_umax(int ndim, int ncells, const float* u, float* part,
                        float* out3, hipStream_t st);
