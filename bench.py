@@ -123,6 +123,8 @@ def main(argv=None):
     ap.add_argument("--cpu-edge", type=int, default=128, help="edge of the oracle's sample box")
     ap.add_argument("--cpu-steps", type=int, default=12, help="oracle steps on the sample box")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--path", choices=["auto", "sweeps"], default="auto",
+                    help="auto: fused step where the library has one; sweeps: one kernel per axis")
     ap.add_argument("--probe", choices=["copy"], default=None,
                     help="instead of the benchmark, time a plain device copy of known size "
                          "(achievable bandwidth; calibrates HBM byte counters)")
@@ -157,6 +159,7 @@ def main(argv=None):
     u_d = torch.from_numpy(u).to(dev)
     ctx = native.Context(0)
     cmax = ctx.courant_max(u_d, dx, dt)
+    ctx.set_option(native.OPT_FUSED, 0 if args.path == "sweeps" else 1)
 
     for w in range(args.warmup):
         ctx.advect(phi_d, u_d, dx, dt, scheme, 1, step0=w, courant_max=cmax)
@@ -222,6 +225,7 @@ def main(argv=None):
             "scheme": args.scheme,
             "cfl": args.cfl,
             "scalars": 1,
+            "path": args.path,
             "parallelism": "single GPU",
         },
         "hbm_frac_step": hbm_frac_step,

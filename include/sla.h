@@ -116,6 +116,18 @@ int sla_advect(sla_ctx *ctx, const sla_grid *grid, float *phi, const float *u,
                double dt, int32_t scheme, int32_t steps, int64_t step0,
                double courant_max);
 
+/* Context options. */
+typedef enum {
+  /* 1 (default): a 3D third-order step whose reach is 1 on every axis runs as
+   * one fused kernel (all three sweeps, 20 B per cell of HBM traffic).
+   * 0: every third-order step runs one sweep kernel per axis.  Both paths
+   * perform the same FP32 operations per node. */
+  SLA_OPT_FUSED = 0
+} sla_option;
+/* Set option `option` to `value`.  Returns SLA_EINVAL for an unknown option
+ * or value. */
+int sla_set_option(sla_ctx *ctx, int option, int64_t value);
+
 /* Synchronise the context's stream and report a Courant overflow recorded by
  * a kernel since the previous sla_check() (then SLA_ECOURANT), or a HIP
  * error.  Clears the record. */

@@ -197,11 +197,20 @@ __global__ __launch_bounds__(kThreads) void k_ec(const float* __restrict__ phi,
     {
       const int gz = wrapk(first + t, g.nz);
       float* dst = st0 + (t % D) * S::PLANE(0);
-      for (int e = threadIdx.x; e < S::PLANE(0); e += kThreads) {
+      constexpr int KL = (S::PLANE(0) + kThreads - 1) / kThreads;
+      float v[KL];
+#pragma unroll
+      for (int k = 0; k < KL; ++k) {
+        const int e = threadIdx.x + k * kThreads;
         const int ly = e / S::W(0), lx = e - ly * S::W(0);
         const int gx = wrapk(x0 - S::HX(0) + lx, g.nx);
         const int gy = wrapk(y0 - S::HY(0) + ly, g.ny);
-        dst[e] = phi[(size_t)gz * plane + (size_t)gy * g.nx + gx];
+        v[k] = e < S::PLANE(0) ? phi[(size_t)gz * plane + (size_t)gy * g.nx + gx] : 0.f;
+      }
+#pragma unroll
+      for (int k = 0; k < KL; ++k) {
+        const int e = threadIdx.x + k * kThreads;
+        if (e < S::PLANE(0)) dst[e] = v[k];
       }
     }
     __syncthreads();
@@ -295,14 +304,28 @@ __global__ __launch_bounds__(kThreads) void k_sweep_s(const float* __restrict__ 
   const int l0 = blockIdx.y * TL;
   const bool xin = x < nx;
   const size_t base = (size_t)blockIdx.z * So + (xin ? x : 0);
-  for (int r = ty; r < NP; r += kThreads / TW) {
+  // issue every load of the tile before the first LDS store
+  constexpr int RS = kThreads / TW;  // rows per pass
+  constexpr int KPr = (NP + RS - 1) / RS, KCr = (NC + RS - 1) / RS;
+  float vp[KPr], vc[KCr];
+#pragma unroll
+  for (int k = 0; k < KPr; ++k) {
+    const int r = ty + k * RS;
     const int l = wrapk(l0 - 3 * R + r, L);
-    P[r * TW + tx] = xin ? phi[base + (size_t)l * S] : 0.f;
+    vp[k] = (xin && r < NP) ? phi[base + (size_t)l * S] : 0.f;
   }
-  for (int r = ty; r < NC; r += kThreads / TW) {
+#pragma unroll
+  for (int k = 0; k < KCr; ++k) {
+    const int r = ty + k * RS;
     const int l = wrapk(l0 - 2 * R + r, L);
-    C[r * TW + tx] = xin ? ud[base + (size_t)l * S] * lam : 0.f;
+    vc[k] = (xin && r < NC) ? ud[base + (size_t)l * S] : 0.f;
   }
+#pragma unroll
+  for (int k = 0; k < KPr; ++k)
+    if (ty + k * RS < NP) P[(ty + k * RS) * TW + tx] = vp[k];
+#pragma unroll
+  for (int k = 0; k < KCr; ++k)
+    if (ty + k * RS < NC) C[(ty + k * RS) * TW + tx] = vc[k] * lam;
   __syncthreads();
   for (int r = ty; r < NC; r += kThreads / TW) {
     const Dep d = depart<R>(C[r * TW + tx], flag);
@@ -338,15 +361,33 @@ __global__ __launch_bounds__(kThreads) void k_sweep_x(const float* __restrict__ 
   const int l0 = blockIdx.x * TL;
   const int y0 = blockIdx.y * ROWS;
   const size_t zoff = (size_t)blockIdx.z * nx * ny;
-  for (int e = threadIdx.x; e < ROWS * NP; e += kThreads) {
+  // issue every load of the tile before the first LDS store
+  constexpr int KPe = (ROWS * NP + kThreads - 1) / kThreads;
+  constexpr int KCe = (ROWS * NC + kThreads - 1) / kThreads;
+  float vp[KPe], vc[KCe];
+#pragma unroll
+  for (int k = 0; k < KPe; ++k) {
+    const int e = threadIdx.x + k * kThreads;
     const int rr = e / NP, col = e - rr * NP;
     const int y = y0 + rr;
-    P[e] = y < ny ? phi[zoff + (size_t)y * nx + wrapk(l0 - 3 * R + col, nx)] : 0.f;
+    vp[k] = (e < ROWS * NP && y < ny) ? phi[zoff + (size_t)y * nx + wrapk(l0 - 3 * R + col, nx)] : 0.f;
   }
-  for (int e = threadIdx.x; e < ROWS * NC; e += kThreads) {
+#pragma unroll
+  for (int k = 0; k < KCe; ++k) {
+    const int e = threadIdx.x + k * kThreads;
     const int rr = e / NC, col = e - rr * NC;
     const int y = y0 + rr;
-    C[e] = y < ny ? ud[zoff + (size_t)y * nx + wrapk(l0 - 2 * R + col, nx)] * lam : 0.f;
+    vc[k] = (e < ROWS * NC && y < ny) ? ud[zoff + (size_t)y * nx + wrapk(l0 - 2 * R + col, nx)] : 0.f;
+  }
+#pragma unroll
+  for (int k = 0; k < KPe; ++k) {
+    const int e = threadIdx.x + k * kThreads;
+    if (e < ROWS * NP) P[e] = vp[k];
+  }
+#pragma unroll
+  for (int k = 0; k < KCe; ++k) {
+    const int e = threadIdx.x + k * kThreads;
+    if (e < ROWS * NC) C[e] = vc[k] * lam;
   }
   __syncthreads();
   for (int e = threadIdx.x; e < ROWS * NC; e += kThreads) {

@@ -21,6 +21,7 @@ struct sla_ctx {
   int* flag = nullptr;    // set by a kernel that clamped an offset
   void* host = nullptr;   // pinned staging for small results (256 bytes)
   std::string err;
+  bool fused = true;  // SLA_OPT_FUSED
   // per-kernel timing
   bool timing = false;
   struct Mark { int kind; hipEvent_t a, b; };
@@ -302,7 +303,7 @@ int sla_advect(sla_ctx* ctx, const sla_grid* grid, float* phi, const float* u, d
 
   // A 3D third-order step whose reach is 1 on every axis runs as one fused
   // kernel (20 B/cell); other cases run one sweep kernel per axis.
-  const bool fused3d = ndim == 3 && rmax == 1;
+  const bool fused3d = ctx->fused && ndim == 3 && rmax == 1;
   float* cur = phi;
   float* nxt = ctx->work;
   hipError_t e = hipSuccess;
@@ -349,6 +350,18 @@ int sla_advect(sla_ctx* ctx, const sla_grid* grid, float* phi, const float* u, d
     if (e != hipSuccess) return hip_fail(ctx, e, "copy of the result");
   }
   return SLA_OK;
+}
+
+int sla_set_option(sla_ctx* ctx, int option, int64_t value) {
+  if (!ctx) return SLA_EINVAL;
+  ctx->err.clear();
+  switch (option) {
+    case SLA_OPT_FUSED:
+      if (value != 0 && value != 1) return fail(ctx, SLA_EINVAL, "SLA_OPT_FUSED takes 0 or 1");
+      ctx->fused = value != 0;
+      return SLA_OK;
+  }
+  return fail(ctx, SLA_EINVAL, "unknown option %d", option);
 }
 
 int sla_check(sla_ctx* ctx) {

@@ -30,12 +30,6 @@ constexpr int kThreads = 256;
 
 __device__ __forceinline__ float lerp(float p, float q, float f) { return fmaf(f, q - p, p); }
 
-__device__ __forceinline__ int wrapk(int v, int n) {
-  while (v < 0) v += n;
-  while (v >= n) v -= n;
-  return v;
-}
-
 // Reach-1 departure: fraction and far-node offset (+-1) for c and for -c.
 struct Dep1 {
   float f;
@@ -65,22 +59,33 @@ struct Cec3dShape {
   static constexpr int W = TX + 2 * H; // padded row length (x)
   static constexpr int HZ = TZ + 2 * H;
   static constexpr int NP = W * HZ;    // padded plane
+  static constexpr int KP = (NP + kThreads - 1) / kThreads;  // padded-plane cells per thread
   // first sweep along A, last along B
   static constexpr int TA = EVEN ? TX : TZ;
   static constexpr int TB = EVEN ? TZ : TX;
   static constexpr int SA = EVEN ? 1 : W;  // LDS stride along A
   static constexpr int SB = EVEN ? W : 1;  // LDS stride along B
-  // y-pipeline region: A in [0, TA), B in [-H, TB + H)
-  static constexpr int NY = TA * (TB + 2 * H);
-  static constexpr int NC = (NY + kThreads - 1) / kThreads;  // columns per thread
+  // y-pipeline region (A in [0, TA), B in [-H, TB + H)) as an x-fastest
+  // rectangle [YX0, YX0 + YW) x [YZ0, YZ0 + YH)
+  static constexpr int YX0 = EVEN ? 0 : -H;
+  static constexpr int YW = EVEN ? TX : TX + 2 * H;
+  static constexpr int YZ0 = EVEN ? -H : 0;
+  static constexpr int YH = EVEN ? TZ + 2 * H : TZ;
+  static constexpr int NY = YW * YH;
+  static constexpr int KY = (NY + kThreads - 1) / kThreads;  // y columns per thread
 };
 
-// padded LDS index of tile-relative (a, b)
+// padded LDS index of tile-relative (x, z)
 template <bool EVEN>
-__device__ __forceinline__ int pidx(int a, int b) {
+__device__ __forceinline__ int lidx(int x, int z) {
   using S = Cec3dShape<EVEN>;
-  const int x = EVEN ? a : b, z = EVEN ? b : a;
   return (z + S::H) * S::W + (x + S::H);
+}
+
+// wrap a coordinate that is at most one period outside [0, n)
+__device__ __forceinline__ int wrap1(int v, int n) {
+  v = v < 0 ? v + n : v;
+  return v >= n ? v - n : v;
 }
 
 template <bool EVEN>
@@ -92,6 +97,7 @@ __global__ __launch_bounds__(kThreads) void k_cec3d_r1(const float* __restrict__
                                                        int ychunk, int* flag) {
   using S = Cec3dShape<EVEN>;
   constexpr int H = S::H, TA = S::TA, TB = S::TB, SA = S::SA, SB = S::SB;
+  constexpr int KP = S::KP, KY = S::KY;
   __shared__ float P[S::NP];   // phi at the loaded plane, padded
   __shared__ float CA[S::NP];  // Courant numbers of the first sweep
   __shared__ float CB[S::NP];  // Courant numbers of the last sweep (output plane)
@@ -112,29 +118,56 @@ __global__ __launch_bounds__(kThreads) void k_cec3d_r1(const float* __restrict__
   const float lamB = EVEN ? g.lam[2] : g.lam[0];
   const float lamY = g.lam[1];
 
-  // global x-z offset (without the y term) of tile-relative (a, b)
-  auto xz_off = [&](int a, int b) -> unsigned {
-    const int x = EVEN ? a : b, z = EVEN ? b : a;
-    const int gx = wrapk(x0 + x, nx), gz = wrapk(z0 + z, nz);
-    return unsigned(gx) + nxy * unsigned(gz);
-  };
+  // Per-thread global x-z offsets (the y term is added per plane), computed
+  // once.  Padded plane: cell e = tid + 256 k; y region: x-fastest rectangle.
+  unsigned poff[KP];
+  unsigned yoff[KY];
+  int ycol[KY];
+#pragma unroll
+  for (int k = 0; k < KP; ++k) {
+    const int e = min(tid + k * kThreads, S::NP - 1);
+    const int z = e / S::W - H, x = e % S::W - H;
+    poff[k] = unsigned(wrap1(x0 + x, nx)) + nxy * unsigned(wrap1(z0 + z, nz));
+  }
+#pragma unroll
+  for (int j = 0; j < KY; ++j) {
+    const int e = min(tid + j * kThreads, S::NY - 1);
+    const int z = S::YZ0 + e / S::YW, x = S::YX0 + e % S::YW;
+    yoff[j] = unsigned(wrap1(x0 + x, nx)) + nxy * unsigned(wrap1(z0 + z, nz));
+    ycol[j] = lidx<EVEN>(x, z);
+  }
+  auto pvalid = [&](int k) { return KP * kThreads == S::NP || tid + k * kThreads < S::NP; };
+  auto yvalid = [&](int j) { return KY * kThreads == S::NY || tid + j * kThreads < S::NY; };
 
   // y-pipeline rings, per column: input a, Phi1, e, Courant (3 planes each)
-  float ra[3][S::NC], r1[3][S::NC], re[3][S::NC], rc[3][S::NC];
-  int ycol[S::NC];
-  unsigned ybase[S::NC];
+  float ra[3][KY], r1[3][KY], re[3][KY], rc[3][KY];
 #pragma unroll
-  for (int j = 0; j < S::NC; ++j) {
-    const int e = tid + j * kThreads;
-    const int ee = e < S::NY ? e : 0;
-    const int b = -H + ee / TA, a = ee % TA;
-    ycol[j] = pidx<EVEN>(a, b);
-    ybase[j] = xz_off(a, b);
+  for (int j = 0; j < KY; ++j)
 #pragma unroll
     for (int k = 0; k < 3; ++k) ra[k][j] = r1[k][j] = re[k][j] = rc[k][j] = 0.f;
-  }
+
+  // Register prefetch of the next plane: phi and the first sweep's velocity
+  // (padded plane), the y velocity one plane back and the last sweep's
+  // velocity at the next output plane (y region).
+  float fp[KP], fa[KP], fy[KY], fb[KY];
+  auto prefetch = [&](int t) {
+    const unsigned qoff = unsigned(wrap1(y0 - H + t, ny)) * unsigned(nx);
+    const unsigned coff = unsigned(wrap1(y0 - H + t - 1, ny)) * unsigned(nx);
+    const unsigned ooff = unsigned(wrap1(y0 + t - 2 * H, ny)) * unsigned(nx);
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+      fp[k] = phi[poff[k] + qoff];
+      fa[k] = uA[poff[k] + qoff];
+    }
+#pragma unroll
+    for (int j = 0; j < KY; ++j) {
+      fy[j] = uy[yoff[j] + coff];
+      fb[j] = uB[yoff[j] + ooff];
+    }
+  };
 
   const int iters = (y1 - y0) + 2 * H;
+  prefetch(0);
   // The ring slot of local plane t is t % 3; the loop body is unrolled by 3
   // so that every slot index is a compile-time constant.
   auto body = [&](auto phase, int t) {
@@ -142,29 +175,29 @@ __global__ __launch_bounds__(kThreads) void k_cec3d_r1(const float* __restrict__
     constexpr int p1 = (p0 + 2) % 3;            // (t - 1) % 3
     constexpr int p2 = (p0 + 1) % 3;            // (t - 2) % 3
     constexpr int p3 = p0;                      // (t - 3) % 3
-    const int q = wrapk(y0 - H + t, ny);        // loaded plane
-    const unsigned qoff = unsigned(q) * unsigned(nx);
+    const bool emit = t >= 2 * H;
 
-    // 1. load phi (whole padded plane) and the first sweep's Courant numbers
-    for (int e = tid; e < S::NP; e += kThreads) {
-      const int z = e / S::W - H, x = e % S::W - H;
-      const int a = EVEN ? x : z, b = EVEN ? z : x;
-      P[e] = phi[xz_off(a, b) + qoff];
+    // 1. publish the prefetched plane, then start fetching the next one
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+      if (!pvalid(k)) continue;
+      P[tid + k * kThreads] = fp[k];
+      CA[tid + k * kThreads] = fa[k] * lamA;
     }
-    {
-      constexpr int LA = TA + 4, LB = TB + 2 * H;  // A in [-2, TA+2), B all
-      for (int e = tid; e < LA * LB; e += kThreads) {
-        const int b = -H + e / LA, a = -2 + e % LA;
-        CA[pidx<EVEN>(a, b)] = uA[xz_off(a, b) + qoff] * lamA;
-      }
+    float cy[KY];
+#pragma unroll
+    for (int j = 0; j < KY; ++j) {
+      cy[j] = fy[j] * lamY;
+      if (emit && yvalid(j)) CB[ycol[j]] = fb[j] * lamB;
     }
+    if (t + 1 < iters) prefetch(t + 1);
     __syncthreads();
     // 2. first sweep, Phi1 on A in [-2, TA+2)
     {
       constexpr int LA = TA + 4, LB = TB + 2 * H;
       for (int e = tid; e < LA * LB; e += kThreads) {
         const int b = -H + e / LA, a = -2 + e % LA;
-        const int i = pidx<EVEN>(a, b);
+        const int i = EVEN ? lidx<EVEN>(a, b) : lidx<EVEN>(b, a);
         const Dep1 d = depart1(CA[i], flag);
         S1[i] = lerp(P[i], P[i + d.ob * SA], d.f);
       }
@@ -175,7 +208,7 @@ __global__ __launch_bounds__(kThreads) void k_cec3d_r1(const float* __restrict__
       constexpr int LA = TA + 2, LB = TB + 2 * H;
       for (int e = tid; e < LA * LB; e += kThreads) {
         const int b = -H + e / LA, a = -1 + e % LA;
-        const int i = pidx<EVEN>(a, b);
+        const int i = EVEN ? lidx<EVEN>(a, b) : lidx<EVEN>(b, a);
         const Dep1 d = depart1(CA[i], flag);
         SE[i] = P[i] - lerp(S1[i], S1[i + d.obr * SA], d.f);
       }
@@ -186,7 +219,7 @@ __global__ __launch_bounds__(kThreads) void k_cec3d_r1(const float* __restrict__
       constexpr int LB = TB + 2 * H;
       for (int e = tid; e < TA * LB; e += kThreads) {
         const int b = -H + e / TA, a = e % TA;
-        const int i = pidx<EVEN>(a, b);
+        const int i = EVEN ? lidx<EVEN>(a, b) : lidx<EVEN>(b, a);
         const Dep1 d = depart1(CA[i], flag);
         const float ea = SE[i], eb = SE[i + d.ob * SA];
         const float w = fmaf(d.f, 1.f / 3.f, 1.f / 3.f);
@@ -194,38 +227,25 @@ __global__ __launch_bounds__(kThreads) void k_cec3d_r1(const float* __restrict__
       }
     }
     __syncthreads();
-    // 5. y sweep as a pipeline along the march (registers), and the last
-    //    sweep's Courant numbers for the output plane t - 6
-    const bool emit = t >= 2 * H;
-    if (emit) {
-      const unsigned ooff = unsigned(wrapk(y0 - H + t - H, ny)) * unsigned(nx);
-      constexpr int LB = TB + 4;  // B in [-2, TB+2)
-      for (int e = tid; e < TA * LB; e += kThreads) {
-        const int b = -2 + e / TA, a = e % TA;
-        CB[pidx<EVEN>(a, b)] = uB[xz_off(a, b) + ooff] * lamB;
-      }
-    }
-    {
-      const unsigned cyoff = unsigned(wrapk(y0 - H + t - 1, ny)) * unsigned(nx);
+    // 5. y sweep as a pipeline along the march (registers)
 #pragma unroll
-      for (int j = 0; j < S::NC; ++j) {
-        if (S::NC * kThreads > S::NY && tid + j * kThreads >= S::NY) continue;
-        const int i = ycol[j];
-        ra[p0][j] = AO[i];                        // input at plane t
-        rc[p1][j] = uy[ybase[j] + cyoff] * lamY;  // Courant at plane t-1
-        // Phi1 at plane t-1
-        Dep1 d = depart1(rc[p1][j], flag);
-        r1[p1][j] = lerp(ra[p1][j], d.ob < 0 ? ra[p2][j] : ra[p0][j], d.f);
-        // e at plane t-2
-        d = depart1(rc[p2][j], flag);
-        re[p2][j] = ra[p2][j] - lerp(r1[p2][j], d.obr > 0 ? r1[p1][j] : r1[p3][j], d.f);
-        // y-sweep output at plane t-3
-        d = depart1(rc[p3][j], flag);
-        const float ea = re[p3][j];
-        const float eb = d.ob < 0 ? re[p1][j] : re[p2][j];  // e at t-4 (slot p1) or t-2
-        const float w = fmaf(d.f, 1.f / 3.f, 1.f / 3.f);
-        YO[i] = fmaf(0.5f, fmaf(w, eb - ea, ea), r1[p3][j]);
-      }
+    for (int j = 0; j < KY; ++j) {
+      if (!yvalid(j)) continue;
+      const int i = ycol[j];
+      ra[p0][j] = AO[i];  // input at plane t
+      rc[p1][j] = cy[j];  // Courant at plane t-1
+      // Phi1 at plane t-1
+      Dep1 d = depart1(rc[p1][j], flag);
+      r1[p1][j] = lerp(ra[p1][j], d.ob < 0 ? ra[p2][j] : ra[p0][j], d.f);
+      // e at plane t-2
+      d = depart1(rc[p2][j], flag);
+      re[p2][j] = ra[p2][j] - lerp(r1[p2][j], d.obr > 0 ? r1[p1][j] : r1[p3][j], d.f);
+      // y-sweep output at plane t-3
+      d = depart1(rc[p3][j], flag);
+      const float ea = re[p3][j];
+      const float eb = d.ob < 0 ? re[p1][j] : re[p2][j];  // e at t-4 (slot p1) or t-2
+      const float w = fmaf(d.f, 1.f / 3.f, 1.f / 3.f);
+      YO[i] = fmaf(0.5f, fmaf(w, eb - ea, ea), r1[p3][j]);
     }
     __syncthreads();
     if (!emit) return;
@@ -234,7 +254,7 @@ __global__ __launch_bounds__(kThreads) void k_cec3d_r1(const float* __restrict__
       constexpr int LB = TB + 4;
       for (int e = tid; e < TA * LB; e += kThreads) {
         const int b = -2 + e / TA, a = e % TA;
-        const int i = pidx<EVEN>(a, b);
+        const int i = EVEN ? lidx<EVEN>(a, b) : lidx<EVEN>(b, a);
         const Dep1 d = depart1(CB[i], flag);
         S1[i] = lerp(YO[i], YO[i + d.ob * SB], d.f);
       }
@@ -245,7 +265,7 @@ __global__ __launch_bounds__(kThreads) void k_cec3d_r1(const float* __restrict__
       constexpr int LB = TB + 2;
       for (int e = tid; e < TA * LB; e += kThreads) {
         const int b = -1 + e / TA, a = e % TA;
-        const int i = pidx<EVEN>(a, b);
+        const int i = EVEN ? lidx<EVEN>(a, b) : lidx<EVEN>(b, a);
         const Dep1 d = depart1(CB[i], flag);
         SE[i] = YO[i] - lerp(S1[i], S1[i + d.obr * SB], d.f);
       }
@@ -253,21 +273,24 @@ __global__ __launch_bounds__(kThreads) void k_cec3d_r1(const float* __restrict__
     __syncthreads();
     // 8. last sweep output on the tile, stored to HBM at plane t - 6
     {
-      const int yo = y0 - H + t - H;
+      const unsigned yo = unsigned(y0 + t - 2 * H) * unsigned(nx);
       for (int e = tid; e < TA * TB; e += kThreads) {
         const int b = e / TA, a = e % TA;
         const int x = EVEN ? a : b, z = EVEN ? b : a;
         if (x0 + x >= nx || z0 + z >= nz) continue;
-        const int i = pidx<EVEN>(a, b);
+        const int i = lidx<EVEN>(x, z);
         const Dep1 d = depart1(CB[i], flag);
         const float ea = SE[i], eb = SE[i + d.ob * SB];
         const float w = fmaf(d.f, 1.f / 3.f, 1.f / 3.f);
-        out[unsigned(x0 + x) + unsigned(nx) * unsigned(yo) + nxy * unsigned(z0 + z)] =
+        out[unsigned(x0 + x) + yo + nxy * unsigned(z0 + z)] =
             fmaf(0.5f, fmaf(w, eb - ea, ea), S1[i]);
       }
     }
-    // no barrier needed here: the next plane's first writes (P, CA) and
-    // every array the last sweep reads are separated by barriers 1-4
+    // No barrier needed here: the next plane's LDS writes (P, CA, CB) are
+    // separated from every read of this plane by barriers 1-5 of the next
+    // iteration, except CB, which the last sweep reads until now: the next
+    // iteration writes CB before its first barrier, so a barrier is needed.
+    __syncthreads();
   };
 
   for (int t = 0; t < iters; t += 3) {

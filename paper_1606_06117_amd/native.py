@@ -19,6 +19,7 @@ SCHEMES = {"cir": CIR, "fec": FEC, "bec": BEC, "cec": CEC}
 MAX_REACH = 4
 
 OK, EINVAL, ECOURANT, EHIP, ENOMEM, ENOMODEL = 0, -1, -2, -3, -4, -5
+OPT_FUSED = 0
 
 # every symbol include/sla.h declares, with (restype, argtypes)
 _c = ctypes
@@ -34,6 +35,7 @@ SIGNATURES = {
                               _c.c_int64, _c.c_double]),
     "sla_check": (_c.c_int, [_vp]),
     "sla_norms": (_c.c_int, [_vp, _c.c_int64, _vp, _vp, _c.POINTER(_c.c_double)]),
+    "sla_set_option": (_c.c_int, [_vp, _c.c_int, _c.c_int64]),
     "sla_timing": (_c.c_int, [_vp, _c.c_int]),
     "sla_timing_read": (_c.c_int, [_vp, _c.POINTER(_c.c_int64), _c.POINTER(_c.c_double)]),
 }
@@ -154,6 +156,9 @@ class Context:
         self._raise(self.lib.sla_advect(self.h, ctypes.byref(g), _ptr(phi), _ptr(u), float(dt),
                                         int(scheme), int(steps), int(step0), float(courant_max)))
         return phi
+
+    def set_option(self, option: int, value: int):
+        self._raise(self.lib.sla_set_option(self.h, int(option), int(value)))
 
     def check(self):
         self._stream()
