@@ -144,6 +144,79 @@ int sla_norms(sla_ctx *ctx, int64_t count, const float *a, const float *b,
               double *out);
 
 /* ------------------------------------------------------------------------
+ * Learned correction (not in the paper; an addition of this library).
+ *
+ * A per-node network predicts the correction that takes the CIR step to the
+ * third-order step (eq. intro:CEC, split per axis as in section 5).  Inputs
+ * of node i (SLA_MLP_INPUTS values, BF16): the 27 differences
+ * Phi1[i+o] - Phi1[i] over the 3x3x3 neighbourhood (o = (dz,dy,dx), z
+ * outermost, x innermost) divided by sigma = sqrt(sum d^2/27 + 1e-30), then
+ * the node's Courant numbers c_x, c_y, c_z, then two zeros; Phi1 is the CIR
+ * step.  Network: h1 = relu(x W1 + b1), h2 = relu(h1 W2 + b2),
+ * y = h2 w3 + b3 (30 -> 64 -> 64 -> 1), run on the matrix cores with BF16
+ * weights and activations and FP32 accumulation.  Corrected value:
+ * Phi1[i] + sigma * y.  Training target: (third-order step - Phi1) / sigma;
+ * loss: mean squared error; optimiser: Adam on FP32 master weights.
+ *
+ * Parameter vector (FP32, SLA_MLP_PARAMS values): W1 (32 x 64 row-major,
+ * [input][hidden]), b1 (64), W2 (64 x 64 row-major, [in][out]), b2 (64),
+ * w3 (64), b3 (1).
+ * ---------------------------------------------------------------------- */
+#define SLA_MLP_INPUTS 32
+#define SLA_MLP_HIDDEN 64
+#define SLA_MLP_PARAMS 6337
+
+typedef struct sla_model sla_model; /* opaque; owns its device memory */
+
+/* Create a model on the context's device with all weights zero and no
+ * trained Courant range (so sla_advect_learned treats it as untrained). */
+int sla_model_create(sla_ctx *ctx, sla_model **out);
+/* Release a model.  NULL is ignored. */
+void sla_model_destroy(sla_model *model);
+/* Load n = SLA_MLP_PARAMS FP32 weights from host memory and reset the
+ * optimiser state.  Synchronises the stream. */
+int sla_model_set_params(sla_ctx *ctx, sla_model *model, const float *params, int64_t n);
+/* Copy the FP32 master weights to host memory.  Synchronises the stream. */
+int sla_model_get_params(sla_ctx *ctx, const sla_model *model, float *params, int64_t n);
+/* Declare the largest |c_d| the weights were trained for (> 0), or 0 for an
+ * untrained model. */
+int sla_model_set_courant_range(sla_model *model, double range);
+
+/* Training pairs on a 3D grid: for each of the m nodes in cells (device,
+ * linear indices x + nx*(y + ny*z)), write its features to feats (device,
+ * m rows of SLA_MLP_INPUTS BF16 values), (phi_next - phi1)/sigma to target
+ * and sigma to sigma (device FP32, m values).  phi1 is the CIR step of the
+ * field, phi_next the step the network should reproduce, u/dt give the
+ * Courant inputs. */
+int sla_make_pairs(sla_ctx *ctx, const sla_grid *grid, const float *phi1,
+                   const float *phi_next, const float *u, double dt,
+                   const int32_t *cells, int64_t m, uint16_t *feats,
+                   float *target, float *sigma);
+/* Network output y for m feature rows (device) into y (device FP32). */
+int sla_model_forward(sla_ctx *ctx, const sla_model *model, const uint16_t *feats,
+                      int64_t m, float *y);
+/* Gradient of the mean squared error over m rows w.r.t. every parameter,
+ * into host grads[SLA_MLP_PARAMS]; the loss into host *loss.  Does not
+ * update the model.  Synchronises the stream. */
+int sla_model_grads(sla_ctx *ctx, sla_model *model, const uint16_t *feats,
+                    const float *target, int64_t m, float *grads, double *loss);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, learning rate lr) on the
+ * mean squared error over m rows.  If loss is not NULL the loss before the
+ * update is written there (and the stream synchronised). */
+int sla_model_train_step(sla_ctx *ctx, sla_model *model, const uint16_t *feats,
+                         const float *target, int64_t m, double lr, double *loss);
+/* Advance a 3D field by `steps` learned steps (a CIR step plus the network's
+ * correction).  The plain third-order scheme is the fallback: when the model
+ * is untrained, or the Courant bound (measured as in sla_advect, or
+ * courant_max if > 0) exceeds the model's trained range, the call runs
+ * sla_advect(..., SLA_CEC, ...) instead if fell_back is not NULL (and sets
+ * *fell_back = 1; otherwise 0), and returns SLA_ENOMODEL or SLA_ECOURANT if
+ * fell_back is NULL. */
+int sla_advect_learned(sla_ctx *ctx, const sla_model *model, const sla_grid *grid,
+                       float *phi, const float *u, double dt, int32_t steps,
+                       int64_t step0, double courant_max, int32_t *fell_back);
+
+/* ------------------------------------------------------------------------
  * Per-kernel timing (for roofline measurements).
  * While enabled, every kernel launch of later calls on the context is
  * bracketed by HIP events recorded on the context's stream; durations are
@@ -158,7 +231,8 @@ typedef enum {
   SLA_K_SWEEP_Z = 5, /* third-order sweep along z             */
   SLA_K_CEC3D = 6,   /* fused three-axis third-order step     */
   SLA_K_COPY = 7,    /* device-to-device copy of the result   */
-  SLA_K_COUNT = 8
+  SLA_K_LEARNED = 8, /* learned correction on top of a CIR step */
+  SLA_K_COUNT = 9
 } sla_kernel_kind;
 
 /* enable != 0: start recording (totals are cleared); 0: stop recording. */

@@ -31,6 +31,21 @@ struct sla_ctx {
   double ms[SLA_K_COUNT] = {};
 };
 
+struct sla_model {
+  int device = 0;
+  float* master = nullptr;  // FP32 weights
+  float* mo = nullptr;      // Adam first moment
+  float* vo = nullptr;      // Adam second moment
+  float* wr = nullptr;      // BF16-rounded weights as FP32
+  void* wpack = nullptr;    // BF16 matrix-core operand layouts
+  float* grad = nullptr;
+  float* gpart = nullptr;   // per-block gradient partials
+  float* lpart = nullptr;   // per-block squared errors
+  double* loss = nullptr;   // device loss sum
+  int64_t adam_t = 0;
+  double range = 0.0;       // trained Courant range (0: untrained)
+};
+
 namespace {
 
 int fail(sla_ctx* ctx, int code, const char* fmt, ...) {
@@ -433,6 +448,241 @@ int sla_timing_read(sla_ctx* ctx, int64_t* launches, double* ms) {
     launches[k] = ctx->launches[k];
     ms[k] = ctx->ms[k];
   }
+  return SLA_OK;
+}
+
+
+// ------------------------------------------------------------------ models
+
+void sla_model_destroy(sla_model* model) {
+  if (!model) return;
+  {
+    DeviceGuard guard(model->device);
+    for (void* p : {(void*)model->master, (void*)model->mo, (void*)model->vo, (void*)model->wr,
+                    model->wpack, (void*)model->grad, (void*)model->gpart, (void*)model->lpart,
+                    (void*)model->loss})
+      if (p) (void)hipFree(p);
+  }
+  delete model;
+}
+
+int sla_model_create(sla_ctx* ctx, sla_model** out) {
+  if (!ctx) return SLA_EINVAL;
+  ctx->err.clear();
+  if (!out) return fail(ctx, SLA_EINVAL, "out must not be NULL");
+  *out = nullptr;
+  DeviceGuard guard(ctx->device);
+  sla_model* m = new sla_model;
+  m->device = ctx->device;
+  const size_t P = sla::kMlpParams * sizeof(float);
+  bool ok = guard.ok;
+  ok = ok && hipMalloc(&m->master, P) == hipSuccess;
+  ok = ok && hipMalloc(&m->mo, P) == hipSuccess;
+  ok = ok && hipMalloc(&m->vo, P) == hipSuccess;
+  ok = ok && hipMalloc(&m->wr, P) == hipSuccess;
+  ok = ok && hipMalloc(&m->wpack, sla::kMlpPackElems * 2) == hipSuccess;
+  ok = ok && hipMalloc(&m->grad, P) == hipSuccess;
+  ok = ok && hipMalloc(&m->gpart, size_t(sla::kMlpMaxBlocks) * P) == hipSuccess;
+  ok = ok && hipMalloc(&m->lpart, sla::kMlpMaxBlocks * sizeof(float)) == hipSuccess;
+  ok = ok && hipMalloc(&m->loss, sizeof(double)) == hipSuccess;
+  if (!ok) {
+    (void)hipGetLastError();
+    sla_model_destroy(m);
+    return fail(ctx, SLA_ENOMEM, "cannot allocate model memory");
+  }
+  hipError_t e = hipMemsetAsync(m->master, 0, P, ctx->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(m->mo, 0, P, ctx->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(m->vo, 0, P, ctx->stream);
+  if (e == hipSuccess) e = sla::launch_pack(m->master, m->wr, m->wpack, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) {
+    sla_model_destroy(m);
+    return hip_fail(ctx, e, "model initialisation");
+  }
+  *out = m;
+  return SLA_OK;
+}
+
+int sla_model_set_params(sla_ctx* ctx, sla_model* model, const float* params, int64_t n) {
+  if (!ctx) return SLA_EINVAL;
+  ctx->err.clear();
+  if (!model || !params) return fail(ctx, SLA_EINVAL, "model and params must not be NULL");
+  if (n != sla::kMlpParams) return fail(ctx, SLA_EINVAL, "need %d parameters", sla::kMlpParams);
+  DeviceGuard guard(ctx->device);
+  const size_t P = sla::kMlpParams * sizeof(float);
+  hipError_t e = hipMemcpyAsync(model->master, params, P, hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(model->mo, 0, P, ctx->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(model->vo, 0, P, ctx->stream);
+  if (e == hipSuccess) e = sla::launch_pack(model->master, model->wr, model->wpack, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "set model parameters");
+  model->adam_t = 0;
+  return SLA_OK;
+}
+
+int sla_model_get_params(sla_ctx* ctx, const sla_model* model, float* params, int64_t n) {
+  if (!ctx) return SLA_EINVAL;
+  ctx->err.clear();
+  if (!model || !params) return fail(ctx, SLA_EINVAL, "model and params must not be NULL");
+  if (n != sla::kMlpParams) return fail(ctx, SLA_EINVAL, "need %d parameters", sla::kMlpParams);
+  DeviceGuard guard(ctx->device);
+  hipError_t e = hipMemcpyAsync(params, model->master, sla::kMlpParams * sizeof(float),
+                                hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "get model parameters");
+  return SLA_OK;
+}
+
+int sla_model_set_courant_range(sla_model* model, double range) {
+  if (!model || !(range >= 0.0) || !std::isfinite(range)) return SLA_EINVAL;
+  model->range = range;
+  return SLA_OK;
+}
+
+int sla_make_pairs(sla_ctx* ctx, const sla_grid* grid, const float* phi1, const float* phi_next,
+                   const float* u, double dt, const int32_t* cells, int64_t m, uint16_t* feats,
+                   float* target, float* sigma) {
+  if (!ctx) return SLA_EINVAL;
+  ctx->err.clear();
+  int rc = check_grid(ctx, grid);
+  if (rc) return rc;
+  if (grid->ndim != 3) return fail(ctx, SLA_EINVAL, "training pairs need a 3D grid");
+  if (!phi1 || !phi_next || !u || !cells || !feats || !target || !sigma)
+    return fail(ctx, SLA_EINVAL, "pointer arguments must not be NULL");
+  if (m < 0 || m > (int64_t(1) << 30)) return fail(ctx, SLA_EINVAL, "bad row count");
+  if (!std::isfinite(dt)) return fail(ctx, SLA_EINVAL, "dt must be finite");
+  if (m == 0) return SLA_OK;
+  DeviceGuard guard(ctx->device);
+  const sla::Geo geo = make_geo(grid, dt);
+  hipError_t e = sla::launch_make_pairs(geo, phi1, phi_next, u, cells, int(m), feats, target, sigma,
+                                        ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "make pairs launch");
+  return SLA_OK;
+}
+
+int sla_model_forward(sla_ctx* ctx, const sla_model* model, const uint16_t* feats, int64_t m,
+                      float* y) {
+  if (!ctx) return SLA_EINVAL;
+  ctx->err.clear();
+  if (!model || !feats || !y) return fail(ctx, SLA_EINVAL, "pointer arguments must not be NULL");
+  if (m < 0 || m > (int64_t(1) << 30)) return fail(ctx, SLA_EINVAL, "bad row count");
+  if (m == 0) return SLA_OK;
+  DeviceGuard guard(ctx->device);
+  hipError_t e = sla::launch_mlp(false, feats, nullptr, int(m), 0.f, model->wpack, model->wr, y,
+                                 nullptr, nullptr, nullptr, ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "network forward launch");
+  return SLA_OK;
+}
+
+namespace {
+int model_gradient(sla_ctx* ctx, sla_model* model, const uint16_t* feats, const float* target,
+                   int64_t m) {
+  if (!model || !feats || !target) return fail(ctx, SLA_EINVAL, "pointer arguments must not be NULL");
+  if (m <= 0 || m > (int64_t(1) << 30)) return fail(ctx, SLA_EINVAL, "bad row count");
+  int nblk = 0;
+  hipError_t e = sla::launch_mlp(true, feats, target, int(m), float(2.0 / double(m)), model->wpack,
+                                 model->wr, nullptr, model->gpart, model->lpart, &nblk, ctx->stream);
+  if (e == hipSuccess)
+    e = sla::launch_grad_reduce(model->gpart, model->lpart, nblk, model->grad, model->loss,
+                                ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "network gradient launch");
+  return SLA_OK;
+}
+
+int read_loss(sla_ctx* ctx, sla_model* model, int64_t m, double* loss) {
+  double* h = static_cast<double*>(ctx->host);
+  hipError_t e = hipMemcpyAsync(h, model->loss, sizeof(double), hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "read loss");
+  *loss = *h / double(m);
+  return SLA_OK;
+}
+}  // namespace
+
+int sla_model_grads(sla_ctx* ctx, sla_model* model, const uint16_t* feats, const float* target,
+                    int64_t m, float* grads, double* loss) {
+  if (!ctx) return SLA_EINVAL;
+  ctx->err.clear();
+  if (!grads || !loss) return fail(ctx, SLA_EINVAL, "grads and loss must not be NULL");
+  DeviceGuard guard(ctx->device);
+  int rc = model_gradient(ctx, model, feats, target, m);
+  if (rc) return rc;
+  hipError_t e = hipMemcpyAsync(grads, model->grad, sla::kMlpParams * sizeof(float),
+                                hipMemcpyDeviceToHost, ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "read gradient");
+  return read_loss(ctx, model, m, loss);
+}
+
+int sla_model_train_step(sla_ctx* ctx, sla_model* model, const uint16_t* feats, const float* target,
+                         int64_t m, double lr, double* loss) {
+  if (!ctx) return SLA_EINVAL;
+  ctx->err.clear();
+  if (!(lr >= 0.0) || !std::isfinite(lr)) return fail(ctx, SLA_EINVAL, "bad learning rate");
+  DeviceGuard guard(ctx->device);
+  int rc = model_gradient(ctx, model, feats, target, m);
+  if (rc) return rc;
+  model->adam_t += 1;
+  const double b1 = 0.9, b2 = 0.999;
+  const float bc1 = float(1.0 - std::pow(b1, double(model->adam_t)));
+  const float bc2 = float(1.0 - std::pow(b2, double(model->adam_t)));
+  hipError_t e = sla::launch_adam(model->master, model->mo, model->vo, model->grad, float(lr),
+                                  float(b1), float(b2), 1e-8f, bc1, bc2, model->wr, model->wpack,
+                                  ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "Adam launch");
+  if (loss) return read_loss(ctx, model, m, loss);
+  return SLA_OK;
+}
+
+int sla_advect_learned(sla_ctx* ctx, const sla_model* model, const sla_grid* grid, float* phi,
+                       const float* u, double dt, int32_t steps, int64_t step0,
+                       double courant_max, int32_t* fell_back) {
+  if (!ctx) return SLA_EINVAL;
+  ctx->err.clear();
+  if (fell_back) *fell_back = 0;
+  int rc = check_grid(ctx, grid);
+  if (rc) return rc;
+  if (!model || !phi || !u) return fail(ctx, SLA_EINVAL, "model, phi and u must not be NULL");
+  if (!std::isfinite(dt)) return fail(ctx, SLA_EINVAL, "dt must be finite");
+  if (steps < 0) return fail(ctx, SLA_EINVAL, "steps must be >= 0");
+  if (std::isnan(courant_max)) return fail(ctx, SLA_EINVAL, "courant_max is NaN");
+  if (steps == 0) return SLA_OK;
+  DeviceGuard guard(ctx->device);
+  const sla::Geo geo = make_geo(grid, dt);
+  double cm = courant_max;
+  if (!(cm > 0.0)) {
+    float c3[3];
+    rc = measure_courant(ctx, grid, geo, u, c3);
+    if (rc) return rc;
+    cm = std::fmax(c3[0], std::fmax(c3[1], c3[2]));
+  }
+  int why = SLA_OK;
+  if (grid->ndim != 3 || model->range <= 0.0) why = SLA_ENOMODEL;
+  else if (cm > model->range) why = SLA_ECOURANT;
+  if (why != SLA_OK) {
+    if (!fell_back)
+      return fail(ctx, why, why == SLA_ENOMODEL ? "model is untrained or the grid is not 3D"
+                                                : "Courant bound %g beyond the model's range %g",
+                  cm, model->range);
+    *fell_back = 1;
+    return sla_advect(ctx, grid, phi, u, dt, SLA_CEC, steps, step0, courant_max);
+  }
+  if (!(cm < SLA_MAX_REACH))
+    return fail(ctx, SLA_ECOURANT, "Courant bound %g: must be below %d", cm, SLA_MAX_REACH);
+  const size_t n = size_t(geo.ncells);
+  rc = ensure_work(ctx, n);
+  if (rc) return rc;
+  hipError_t e = hipSuccess;
+  for (int32_t k = 0; k < steps && e == hipSuccess; ++k) {
+    e = run(ctx, SLA_K_CIR, [&] {
+      return sla::launch_cir(3, geo, phi, u, ctx->work, ctx->flag, ctx->stream);
+    });
+    if (e == hipSuccess)
+      e = run(ctx, SLA_K_LEARNED, [&] {
+        return sla::launch_learned_correct(geo, ctx->work, u, model->wpack, model->wr, phi,
+                                           ctx->stream);
+      });
+  }
+  if (e != hipSuccess) return hip_fail(ctx, e, "learned step launch");
   return SLA_OK;
 }
 

@@ -42,6 +42,32 @@ hipError_t launch_cec_sweep(int d, int R, const Geo& g, const float* phi,
 hipError_t launch_cec3d(int R, bool even, const Geo& g, const float* phi, const float* u,
                         float* out, int* flag, hipStream_t st);
 
+// ---------------------------------------------------------------- network
+constexpr int kMlpInputs = 32;   // 27 differences + 3 Courant numbers + 2 zero
+constexpr int kMlpHidden = 64;
+constexpr int kMlpParams = kMlpInputs * kMlpHidden + kMlpHidden + kMlpHidden * kMlpHidden +
+                           kMlpHidden + kMlpHidden + 1;
+constexpr int kMlpMaxBlocks = 512;  // training blocks (gradient partials)
+constexpr int kMlpPackElems = kMlpHidden * kMlpInputs + 2 * kMlpHidden * kMlpHidden;
+
+size_t mlp_train_lds();
+// Forward (and, if train, backward) over m feature rows; nblk_out receives
+// the number of gradient partials written.
+hipError_t launch_mlp(bool train, const void* X, const float* target, int m, float inv_m2,
+                      const void* wpack, const float* wr, float* yout, float* gpart,
+                      float* lpart, int* nblk_out, hipStream_t st);
+hipError_t launch_grad_reduce(const float* gpart, const float* lpart, int nblk, float* grad,
+                              double* loss_sum, hipStream_t st);
+hipError_t launch_pack(const float* master, float* wr, void* wpack, hipStream_t st);
+hipError_t launch_adam(float* master, float* m, float* v, const float* grad, float lr, float beta1,
+                       float beta2, float eps, float bc1, float bc2, float* wr, void* wpack,
+                       hipStream_t st);
+hipError_t launch_make_pairs(const Geo& g, const float* phi1, const float* phi_next, const float* u,
+                             const int* cells, int m, void* X, float* target, float* sigma,
+                             hipStream_t st);
+hipError_t launch_learned_correct(const Geo& g, const float* phi1, const float* u, const void* wpack,
+                                  const float* wr, float* out, hipStream_t st);
+
 // Max |u_d| per axis over the grid (FP32, NaN propagates) into out3 (device).
 hipError_t launch_umax(int ndim, int ncells, const float* u, float* part,
                        float* out3, hipStream_t st);

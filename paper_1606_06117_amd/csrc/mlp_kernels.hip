@@ -1,0 +1,609 @@
+// Learned per-cell correction: a 30->64->64->1 ReLU network run on the
+// gfx950 matrix cores (v_mfma_f32_16x16x32_bf16: BF16 operands, FP32
+// accumulation), its training (forward, backward, Adam) and the fused
+// inference step.
+//
+// Features of node i (32 inputs, the last two zero): the 27 differences
+// Phi1[i+o] - Phi1[i] over the 3x3x3 neighbourhood (z outermost, x
+// innermost) divided by sigma = sqrt(sum d^2 / 27 + 1e-30), then the node's
+// Courant numbers c_x, c_y, c_z.  The network predicts y; the corrected
+// value is Phi1[i] + sigma * y.  Phi1 is the CIR step (section 3); the
+// training target is (third-order step - Phi1) / sigma.
+//
+// MFMA operand layout (16x16x32, one wave): with g = lane / 16 and
+// c = lane % 16, lane holds A[c][8g..8g+7], B[8g..8g+7][c] and, after the
+// instruction, D[4g..4g+3][c].  Every layer is computed transposed
+// (hidden x cells), so a lane's four results are four consecutive hidden
+// units of one cell and land in a row-major LDS tile as one 8-byte store.
+
+#include "common.h"
+
+namespace sla {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr int kThreads = 256;
+constexpr int NF = kMlpInputs, NH = kMlpHidden;
+constexpr int W1_OFF = 0, B1_OFF = NF * NH, W2_OFF = B1_OFF + NH, B2_OFF = W2_OFF + NH * NH,
+              W3_OFF = B2_OFF + NH, B3_OFF = W3_OFF + NH;
+static_assert(B3_OFF + 1 == kMlpParams, "parameter layout");
+
+__device__ __forceinline__ floatx4 mfma(const bf16x8& a, const bf16x8& b, const floatx4& c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ bf16x8 ld8(const __bf16* p) { return *reinterpret_cast<const bf16x8*>(p); }
+
+__device__ __forceinline__ void st4(__bf16* p, float a, float b, float c, float d) {
+  bf16x4 v;
+  v[0] = (__bf16)a;
+  v[1] = (__bf16)b;
+  v[2] = (__bf16)c;
+  v[3] = (__bf16)d;
+  *reinterpret_cast<bf16x4*>(p) = v;
+}
+
+// sum over the 16 lanes that share g (lane bits 0..3)
+__device__ __forceinline__ float sum16(float v) {
+  v += __shfl_xor(v, 1);
+  v += __shfl_xor(v, 2);
+  v += __shfl_xor(v, 4);
+  v += __shfl_xor(v, 8);
+  return v;
+}
+// sum over the 4 lanes that share c (lane bits 4..5)
+__device__ __forceinline__ float sum4g(float v) {
+  v += __shfl_xor(v, 16);
+  v += __shfl_xor(v, 32);
+  return v;
+}
+
+// Weights in LDS: W1T [n][k] (64 x 32), W2T [n][k] (64 x 64), W2R [k][n]
+// (64 x 64), all BF16; biases and w3 FP32 (already BF16-rounded).
+struct WeightsLds {
+  __bf16 w1t[NH * NF];
+  __bf16 w2t[NH * NH];
+  __bf16 w2r[NH * NH];
+  float b1[NH], b2[NH], w3[NH], b3;
+};
+
+__device__ void load_weights(WeightsLds& W, const __bf16* __restrict__ wpack,
+                             const float* __restrict__ wr, bool need_w2r) {
+  for (int i = threadIdx.x; i < NH * NF; i += kThreads) W.w1t[i] = wpack[i];
+  for (int i = threadIdx.x; i < NH * NH; i += kThreads) W.w2t[i] = wpack[NH * NF + i];
+  if (need_w2r)
+    for (int i = threadIdx.x; i < NH * NH; i += kThreads) W.w2r[i] = wpack[NH * NF + NH * NH + i];
+  for (int i = threadIdx.x; i < NH; i += kThreads) {
+    W.b1[i] = wr[B1_OFF + i];
+    W.b2[i] = wr[B2_OFF + i];
+    W.w3[i] = wr[W3_OFF + i];
+  }
+  if (threadIdx.x == 0) W.b3 = wr[B3_OFF];
+}
+
+// Forward pass of one 32-cell tile held by one wave.  xb[jt] is the B
+// operand of cells 16 jt + c (features 8g..8g+7).  Writes H1 (row-major
+// [cell][hidden], BF16) to h1, returns h2 (transposed tiles, FP32, after the
+// ReLU) in h2 and y of cell 16 jt + c (on every lane of that cell).
+__device__ __forceinline__ void forward_tile(const WeightsLds& W, const bf16x8 xb[2], __bf16* h1,
+                                             floatx4 h2[4][2], float y[2]) {
+  const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
+  // layer 1: H1T[k][j] = sum_i W1T[k][i] X[j][i]
+#pragma unroll
+  for (int it = 0; it < 4; ++it) {
+    const bf16x8 a = ld8(&W.w1t[(16 * it + c) * NF + 8 * g]);
+#pragma unroll
+    for (int jt = 0; jt < 2; ++jt) {
+      floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+      acc = mfma(a, xb[jt], acc);
+      const int k = 16 * it + 4 * g;
+      st4(&h1[(16 * jt + c) * NH + k], fmaxf(acc[0] + W.b1[k], 0.f), fmaxf(acc[1] + W.b1[k + 1], 0.f),
+          fmaxf(acc[2] + W.b1[k + 2], 0.f), fmaxf(acc[3] + W.b1[k + 3], 0.f));
+    }
+  }
+  __syncthreads();
+  // layer 2: H2T[n][j] = sum_k W2T[n][k] H1[j][k], two K steps of 32
+  float s[2] = {0.f, 0.f};
+#pragma unroll
+  for (int it = 0; it < 4; ++it) {
+#pragma unroll
+    for (int jt = 0; jt < 2; ++jt) {
+      floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int kk = 0; kk < 2; ++kk)
+        acc = mfma(ld8(&W.w2t[(16 * it + c) * NH + 32 * kk + 8 * g]),
+                   ld8(&h1[(16 * jt + c) * NH + 32 * kk + 8 * g]), acc);
+      const int n = 16 * it + 4 * g;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        acc[q] = fmaxf(acc[q] + W.b2[n + q], 0.f);
+        s[jt] = fmaf(acc[q], W.w3[n + q], s[jt]);
+      }
+      h2[it][jt] = acc;
+    }
+  }
+  // layer 3: y = h2 . w3 + b3, summed over the 4 lanes holding the cell
+  y[0] = sum4g(s[0]) + W.b3;
+  y[1] = sum4g(s[1]) + W.b3;
+}
+
+// ---------------------------------------------------------------------------
+// Training / evaluation on feature rows.
+// X: m rows of 32 BF16 features.  TRAIN: accumulate the gradient of
+// mean((y - t)^2) (inv_m2 = 2 / m_total) into per-workgroup partials
+// gpart[blockIdx][kMlpParams] and the squared error into lpart[blockIdx].
+// Otherwise write y.  Every wave of a block runs the same number of tiles.
+// ---------------------------------------------------------------------------
+struct TrainLds {
+  WeightsLds W;
+  __bf16 h1[4][32 * NH];   // [cell][hidden]
+  __bf16 h1t[4][NH * 32];  // [hidden][cell]
+  __bf16 dh2[4][32 * NH];  // [cell][n]
+  __bf16 dh2t[4][NH * 32]; // [n][cell]
+  __bf16 dh1t[4][NH * 32]; // [k][cell]
+  __bf16 xt[4][NF * 32];   // [feature][cell]
+};
+
+template <bool TRAIN>
+__global__ __launch_bounds__(kThreads) void k_mlp(const __bf16* __restrict__ X,
+                                                  const float* __restrict__ target, int m,
+                                                  float inv_m2, int tiles_per_wave,
+                                                  const __bf16* __restrict__ wpack,
+                                                  const float* __restrict__ wr,
+                                                  float* __restrict__ yout,
+                                                  float* __restrict__ gpart,
+                                                  float* __restrict__ lpart) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  TrainLds& L = *reinterpret_cast<TrainLds*>(smem);
+  load_weights(L.W, wpack, wr, TRAIN);
+  __syncthreads();
+  const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15, w = threadIdx.x >> 6;
+  __bf16* h1 = L.h1[w];
+
+  floatx4 dw2[4][4], dw1[4][2];
+  float dw3[4][4], db2[4][4], db1[4][4], db3 = 0.f, sq = 0.f;
+  if (TRAIN) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        dw2[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
+        dw3[a][b] = db2[a][b] = db1[a][b] = 0.f;
+      }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) dw1[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
+  }
+
+  for (int tt = 0; tt < tiles_per_wave; ++tt) {
+    const int tile = (blockIdx.x * tiles_per_wave + tt) * 4 + w;
+    const int r0 = tile * 32;
+    bf16x8 xb[2];
+#pragma unroll
+    for (int jt = 0; jt < 2; ++jt) {
+      const int row = r0 + 16 * jt + c;
+      if (row < m) {
+        xb[jt] = ld8(&X[(size_t)row * NF + 8 * g]);
+      } else {
+#pragma unroll
+        for (int v = 0; v < 8; ++v) xb[jt][v] = (__bf16)0.f;
+      }
+      if (TRAIN) {
+#pragma unroll
+        for (int v = 0; v < 8; ++v) L.xt[w][(8 * g + v) * 32 + 16 * jt + c] = xb[jt][v];
+      }
+    }
+    floatx4 h2[4][2];
+    float y[2];
+    forward_tile(L.W, xb, h1, h2, y);
+    if (!TRAIN) {
+#pragma unroll
+      for (int jt = 0; jt < 2; ++jt) {
+        const int row = r0 + 16 * jt + c;
+        if (g == 0 && row < m) yout[row] = y[jt];
+      }
+      __syncthreads();  // h1 is rewritten by the next tile
+      continue;
+    }
+    // ---- backward
+    float dy[2];
+#pragma unroll
+    for (int jt = 0; jt < 2; ++jt) {
+      const int row = r0 + 16 * jt + c;
+      const float err = row < m ? y[jt] - target[row] : 0.f;
+      dy[jt] = err * inv_m2;
+      if (g == 0) {
+        sq = fmaf(err, err, sq);
+        db3 += dy[jt];
+      }
+    }
+    // H1 transposed copy for the W2 gradient (this wave's tile only)
+    for (int e = lane; e < 32 * NH; e += 64) {
+      const int j = e / NH, k = e % NH;
+      L.h1t[w][k * 32 + j] = h1[e];
+    }
+#pragma unroll
+    for (int it = 0; it < 4; ++it) {
+#pragma unroll
+      for (int jt = 0; jt < 2; ++jt) {
+        const int n = 16 * it + 4 * g, j = 16 * jt + c;
+        float d[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          dw3[it][q] = fmaf(h2[it][jt][q], dy[jt], dw3[it][q]);
+          d[q] = h2[it][jt][q] > 0.f ? dy[jt] * L.W.w3[n + q] : 0.f;
+          db2[it][q] += d[q];
+          L.dh2t[w][(n + q) * 32 + j] = (__bf16)d[q];
+        }
+        st4(&L.dh2[w][j * NH + n], d[0], d[1], d[2], d[3]);
+      }
+    }
+    __syncthreads();
+    // dW2T[n][k] += sum_j dH2T[n][j] H1[j][k]
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+      const bf16x8 a = ld8(&L.dh2t[w][(16 * nt + c) * 32 + 8 * g]);
+#pragma unroll
+      for (int kt = 0; kt < 4; ++kt)
+        dw2[nt][kt] = mfma(a, ld8(&L.h1t[w][(16 * kt + c) * 32 + 8 * g]), dw2[nt][kt]);
+    }
+    // dH1T[k][j] = sum_n W2R[k][n] dH2[j][n], masked by H1 > 0
+#pragma unroll
+    for (int kt = 0; kt < 4; ++kt) {
+#pragma unroll
+      for (int jt = 0; jt < 2; ++jt) {
+        floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int nn = 0; nn < 2; ++nn)
+          acc = mfma(ld8(&L.W.w2r[(16 * kt + c) * NH + 32 * nn + 8 * g]),
+                     ld8(&L.dh2[w][(16 * jt + c) * NH + 32 * nn + 8 * g]), acc);
+        const int k = 16 * kt + 4 * g, j = 16 * jt + c;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const float d = (float)h1[j * NH + k + q] > 0.f ? acc[q] : 0.f;
+          db1[kt][q] += d;
+          L.dh1t[w][(k + q) * 32 + j] = (__bf16)d;
+        }
+      }
+    }
+    __syncthreads();
+    // dW1T[k][i] += sum_j dH1T[k][j] X[j][i]
+#pragma unroll
+    for (int kt = 0; kt < 4; ++kt) {
+      const bf16x8 a = ld8(&L.dh1t[w][(16 * kt + c) * 32 + 8 * g]);
+#pragma unroll
+      for (int it = 0; it < 2; ++it)
+        dw1[kt][it] = mfma(a, ld8(&L.xt[w][(16 * it + c) * 32 + 8 * g]), dw1[kt][it]);
+    }
+    __syncthreads();  // tile buffers are rewritten by the next tile
+  }
+  if (!TRAIN) return;
+
+  // ---- per-block gradient: waves add their partials in a fixed order
+  float* acc = reinterpret_cast<float*>(L.h1);  // kMlpParams floats fit in h1..dh2
+  static_assert(sizeof(L.h1) + sizeof(L.h1t) + sizeof(L.dh2) >= kMlpParams * sizeof(float),
+                "gradient staging");
+  // lane-owned entries
+  auto contribute = [&](bool first) {
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+      for (int kt = 0; kt < 4; ++kt)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int n = 16 * nt + 4 * g + q, k = 16 * kt + c;  // dW2T[n][k] -> W2[k][n]
+          float* p = &acc[W2_OFF + k * NH + n];
+          *p = first ? dw2[nt][kt][q] : *p + dw2[nt][kt][q];
+        }
+#pragma unroll
+    for (int kt = 0; kt < 4; ++kt)
+#pragma unroll
+      for (int it = 0; it < 2; ++it)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int k = 16 * kt + 4 * g + q, i = 16 * it + c;  // dW1T[k][i] -> W1[i][k]
+          float* p = &acc[W1_OFF + i * NH + k];
+          *p = first ? dw1[kt][it][q] : *p + dw1[kt][it][q];
+        }
+  };
+  // reduce the lane-local vector partials over the 16 cells of a lane group
+  float rw3[4][4], rb2[4][4], rb1[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      rw3[a][q] = sum16(dw3[a][q]);
+      rb2[a][q] = sum16(db2[a][q]);
+      rb1[a][q] = sum16(db1[a][q]);
+    }
+  const float rb3 = sum16(sum4g(db3));
+  const float rsq = sum16(sum4g(sq));
+  __syncthreads();
+  for (int ww = 0; ww < 4; ++ww) {
+    if (w == ww) {
+      contribute(ww == 0);
+      if (c == 0) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int n = 16 * a + 4 * g + q;
+            acc[W3_OFF + n] = ww == 0 ? rw3[a][q] : acc[W3_OFF + n] + rw3[a][q];
+            acc[B2_OFF + n] = ww == 0 ? rb2[a][q] : acc[B2_OFF + n] + rb2[a][q];
+            acc[B1_OFF + n] = ww == 0 ? rb1[a][q] : acc[B1_OFF + n] + rb1[a][q];
+          }
+      }
+      if (lane == 0) {
+        acc[B3_OFF] = ww == 0 ? rb3 : acc[B3_OFF] + rb3;
+        acc[kMlpParams] = ww == 0 ? rsq : acc[kMlpParams] + rsq;
+      }
+    }
+    __syncthreads();
+  }
+  for (int i = threadIdx.x; i < kMlpParams; i += kThreads)
+    gpart[(size_t)blockIdx.x * kMlpParams + i] = acc[i];
+  if (threadIdx.x == 0) lpart[blockIdx.x] = acc[kMlpParams];
+}
+
+// Sum per-block partials in block order (deterministic).
+__global__ __launch_bounds__(kThreads) void k_grad_reduce(const float* __restrict__ gpart,
+                                                          const float* __restrict__ lpart,
+                                                          int nblk, float* __restrict__ grad,
+                                                          double* __restrict__ loss_sum) {
+  const int p = blockIdx.x * kThreads + threadIdx.x;
+  if (p < kMlpParams) {
+    float s = 0.f;
+    for (int b = 0; b < nblk; ++b) s += gpart[(size_t)b * kMlpParams + p];
+    grad[p] = s;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    double s = 0.0;
+    for (int b = 0; b < nblk; ++b) s += lpart[b];
+    *loss_sum = s;
+  }
+}
+
+// Round the FP32 master weights to BF16 (FP32 copy `wr`) and write the
+// matrix-core operand layouts.
+__device__ __forceinline__ void pack_one(int p, float v, float* __restrict__ wr,
+                                         __bf16* __restrict__ wpack) {
+  const __bf16 b = (__bf16)v;
+  wr[p] = (float)b;
+  if (p < B1_OFF) {
+    const int k = p / NH, n = p % NH;  // W1[k][n]
+    wpack[n * NF + k] = b;
+  } else if (p >= W2_OFF && p < B2_OFF) {
+    const int q = p - W2_OFF, k = q / NH, n = q % NH;  // W2[k][n]
+    wpack[NH * NF + n * NH + k] = b;
+    wpack[NH * NF + NH * NH + k * NH + n] = b;
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_pack(const float* __restrict__ master,
+                                                   float* __restrict__ wr,
+                                                   __bf16* __restrict__ wpack) {
+  const int p = blockIdx.x * kThreads + threadIdx.x;
+  if (p < kMlpParams) pack_one(p, master[p], wr, wpack);
+}
+
+// Adam (Kingma & Ba) on the FP32 master weights; bc1 = 1 - beta1^t,
+// bc2 = 1 - beta2^t.
+__global__ __launch_bounds__(kThreads) void k_adam(float* __restrict__ master, float* __restrict__ mo,
+                                                   float* __restrict__ vo,
+                                                   const float* __restrict__ grad, float lr,
+                                                   float beta1, float beta2, float eps, float bc1,
+                                                   float bc2, float* __restrict__ wr,
+                                                   __bf16* __restrict__ wpack) {
+  const int p = blockIdx.x * kThreads + threadIdx.x;
+  if (p >= kMlpParams) return;
+  const float gr = grad[p];
+  const float m1 = beta1 * mo[p] + (1.f - beta1) * gr;
+  const float v1 = beta2 * vo[p] + (1.f - beta2) * gr * gr;
+  mo[p] = m1;
+  vo[p] = v1;
+  const float w = master[p] - lr * (m1 / bc1) / (sqrtf(v1 / bc2) + eps);
+  master[p] = w;
+  pack_one(p, w, wr, wpack);
+}
+
+// ---------------------------------------------------------------------------
+// Features of one node for the lane that holds inputs 8g..8g+7, and the
+// node's sigma.  Every lane of the node's group computes the same sigma.
+// ---------------------------------------------------------------------------
+struct NodeFeatures {
+  bf16x8 x;
+  float sigma;
+  float centre;
+};
+
+__device__ __forceinline__ NodeFeatures node_features(const float* __restrict__ phi1,
+                                                      const float* __restrict__ ux,
+                                                      const float* __restrict__ uy,
+                                                      const float* __restrict__ uz, const Geo& geo,
+                                                      int x, int y, int z, int g) {
+  const int nx = geo.nx, ny = geo.ny, nz = geo.nz;
+  const size_t plane = (size_t)nx * ny;
+  const size_t ic = (size_t)z * plane + (size_t)y * nx + x;
+  const float centre = phi1[ic];
+  float d[8];
+  float ss = 0.f;
+#pragma unroll
+  for (int v = 0; v < 8; ++v) {
+    const int k = 8 * g + v;
+    d[v] = 0.f;
+    if (k < 27) {
+      const int dz = k / 9 - 1, dy = (k / 3) % 3 - 1, dx = k % 3 - 1;
+      int xx = x + dx, yy = y + dy, zz = z + dz;
+      xx = xx < 0 ? xx + nx : (xx >= nx ? xx - nx : xx);
+      yy = yy < 0 ? yy + ny : (yy >= ny ? yy - ny : yy);
+      zz = zz < 0 ? zz + nz : (zz >= nz ? zz - nz : zz);
+      d[v] = phi1[(size_t)zz * plane + (size_t)yy * nx + xx] - centre;
+      ss = fmaf(d[v], d[v], ss);
+    }
+  }
+  ss = sum4g(ss);
+  NodeFeatures f;
+  f.sigma = sqrtf(ss / 27.f + 1e-30f);
+  f.centre = centre;
+  const float inv = 1.f / f.sigma;
+#pragma unroll
+  for (int v = 0; v < 8; ++v) f.x[v] = (__bf16)(d[v] * inv);
+  if (g == 3) {  // inputs 27..29: Courant numbers, 30..31 zero
+    f.x[3] = (__bf16)(ux[ic] * geo.lam[0]);
+    f.x[4] = (__bf16)(uy[ic] * geo.lam[1]);
+    f.x[5] = (__bf16)(uz[ic] * geo.lam[2]);
+    f.x[6] = (__bf16)0.f;
+    f.x[7] = (__bf16)0.f;
+  }
+  return f;
+}
+
+// Training pairs: features of the listed nodes (linear indices) from the CIR
+// field phi1, and the target (phi_next - phi1) / sigma.  One wave handles 16
+// nodes (4 lanes per node).
+__global__ __launch_bounds__(kThreads) void k_make_pairs(const float* __restrict__ phi1,
+                                                         const float* __restrict__ phi_next,
+                                                         const float* __restrict__ ux,
+                                                         const float* __restrict__ uy,
+                                                         const float* __restrict__ uz, Geo geo,
+                                                         const int* __restrict__ cells, int m,
+                                                         __bf16* __restrict__ X,
+                                                         float* __restrict__ target,
+                                                         float* __restrict__ sigma) {
+  const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15, w = threadIdx.x >> 6;
+  const int row = (blockIdx.x * 4 + w) * 16 + c;
+  const bool ok = row < m;
+  const int id = ok ? cells[row] : 0;
+  const int x = id % geo.nx, y = (id / geo.nx) % geo.ny, z = id / (geo.nx * geo.ny);
+  const NodeFeatures f = node_features(phi1, ux, uy, uz, geo, x, y, z, g);
+  if (!ok) return;
+  *reinterpret_cast<bf16x8*>(&X[(size_t)row * NF + 8 * g]) = f.x;
+  if (g == 0) {
+    target[row] = (phi_next[id] - f.centre) / f.sigma;
+    sigma[row] = f.sigma;
+  }
+}
+
+// Learned step, second half: out = Phi1 + sigma * net(features).  A block
+// covers 32 (x) x 4 (y) nodes of one z plane; wave w takes row y0 + w as two
+// tiles of 16 nodes.
+struct InferLds {
+  WeightsLds W;
+  __bf16 h1[4][32 * NH];
+};
+
+__global__ __launch_bounds__(kThreads) void k_learned_correct(const float* __restrict__ phi1,
+                                                              const float* __restrict__ ux,
+                                                              const float* __restrict__ uy,
+                                                              const float* __restrict__ uz,
+                                                              Geo geo,
+                                                              const __bf16* __restrict__ wpack,
+                                                              const float* __restrict__ wr,
+                                                              float* __restrict__ out) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  InferLds& L = *reinterpret_cast<InferLds*>(smem);
+  load_weights(L.W, wpack, wr, false);
+  __syncthreads();
+  const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15, w = threadIdx.x >> 6;
+  const int y = min(blockIdx.y * 4 + w, geo.ny - 1);  // rows past the end repeat the last one
+  const int z = blockIdx.z;
+  bf16x8 xb[2];
+  float sig[2], cen[2];
+  int xs[2];
+#pragma unroll
+  for (int jt = 0; jt < 2; ++jt) {
+    xs[jt] = blockIdx.x * 32 + 16 * jt + c;
+    const int x = min(xs[jt], geo.nx - 1);
+    const NodeFeatures f = node_features(phi1, ux, uy, uz, geo, x, y, z, g);
+    xb[jt] = f.x;
+    sig[jt] = f.sigma;
+    cen[jt] = f.centre;
+  }
+  floatx4 h2[4][2];
+  float yv[2];
+  forward_tile(L.W, xb, L.h1[w], h2, yv);
+  if (g != 0 || blockIdx.y * 4 + w >= geo.ny) return;
+#pragma unroll
+  for (int jt = 0; jt < 2; ++jt)
+    if (xs[jt] < geo.nx)
+      out[(size_t)z * geo.nx * geo.ny + (size_t)y * geo.nx + xs[jt]] = fmaf(sig[jt], yv[jt], cen[jt]);
+}
+
+}  // namespace
+
+size_t mlp_train_lds() { return sizeof(TrainLds); }
+
+hipError_t launch_mlp(bool train, const void* X, const float* target, int m, float inv_m2,
+                      const void* wpack, const float* wr, float* yout, float* gpart,
+                      float* lpart, int* nblk_out, hipStream_t st) {
+  const int tiles = (m + 31) / 32;
+  const int waves = (tiles + 3) / 4 * 4;
+  // enough blocks to fill the chip, each wave running tiles_per_wave tiles
+  const int tpw = max(1, (waves / 4 + kMlpMaxBlocks - 1) / kMlpMaxBlocks);
+  const int nblk = ((tiles + 4 * tpw - 1) / (4 * tpw));
+  const int bytes = int(sizeof(TrainLds));
+  static hipError_t a1 = hipFuncSetAttribute(reinterpret_cast<const void*>(k_mlp<true>),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  static hipError_t a2 = hipFuncSetAttribute(reinterpret_cast<const void*>(k_mlp<false>),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (a1 != hipSuccess) return a1;
+  if (a2 != hipSuccess) return a2;
+  if (nblk_out) *nblk_out = nblk;
+  if (train)
+    hipLaunchKernelGGL(k_mlp<true>, dim3(nblk), dim3(kThreads), bytes, st,
+                       static_cast<const __bf16*>(X), target, m, inv_m2, tpw,
+                       static_cast<const __bf16*>(wpack), wr, yout, gpart, lpart);
+  else
+    hipLaunchKernelGGL(k_mlp<false>, dim3(nblk), dim3(kThreads), bytes, st,
+                       static_cast<const __bf16*>(X), target, m, inv_m2, tpw,
+                       static_cast<const __bf16*>(wpack), wr, yout, gpart, lpart);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_reduce(const float* gpart, const float* lpart, int nblk, float* grad,
+                              double* loss_sum, hipStream_t st) {
+  hipLaunchKernelGGL(k_grad_reduce, dim3((kMlpParams + kThreads - 1) / kThreads), dim3(kThreads), 0,
+                     st, gpart, lpart, nblk, grad, loss_sum);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack(const float* master, float* wr, void* wpack, hipStream_t st) {
+  hipLaunchKernelGGL(k_pack, dim3((kMlpParams + kThreads - 1) / kThreads), dim3(kThreads), 0, st,
+                     master, wr, static_cast<__bf16*>(wpack));
+  return hipGetLastError();
+}
+
+hipError_t launch_adam(float* master, float* m, float* v, const float* grad, float lr, float beta1,
+                       float beta2, float eps, float bc1, float bc2, float* wr, void* wpack,
+                       hipStream_t st) {
+  hipLaunchKernelGGL(k_adam, dim3((kMlpParams + kThreads - 1) / kThreads), dim3(kThreads), 0, st,
+                     master, m, v, grad, lr, beta1, beta2, eps, bc1, bc2, wr,
+                     static_cast<__bf16*>(wpack));
+  return hipGetLastError();
+}
+
+hipError_t launch_make_pairs(const Geo& g, const float* phi1, const float* phi_next, const float* u,
+                             const int* cells, int m, void* X, float* target, float* sigma,
+                             hipStream_t st) {
+  const size_t n = (size_t)g.ncells;
+  const int nblk = (m + 63) / 64;
+  hipLaunchKernelGGL(k_make_pairs, dim3(nblk), dim3(kThreads), 0, st, phi1, phi_next, u, u + n,
+                     u + 2 * n, g, cells, m, static_cast<__bf16*>(X), target, sigma);
+  return hipGetLastError();
+}
+
+hipError_t launch_learned_correct(const Geo& g, const float* phi1, const float* u, const void* wpack,
+                                  const float* wr, float* out, hipStream_t st) {
+  const size_t n = (size_t)g.ncells;
+  const int bytes = int(sizeof(InferLds));
+  dim3 grid((g.nx + 31) / 32, (g.ny + 3) / 4, g.nz);
+  hipLaunchKernelGGL(k_learned_correct, grid, dim3(kThreads), bytes, st, phi1, u, u + n, u + 2 * n,
+                     g, static_cast<const __bf16*>(wpack), wr, out);
+  return hipGetLastError();
+}
+
+}  // namespace sla

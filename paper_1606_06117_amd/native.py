@@ -36,11 +36,25 @@ SIGNATURES = {
     "sla_check": (_c.c_int, [_vp]),
     "sla_norms": (_c.c_int, [_vp, _c.c_int64, _vp, _vp, _c.POINTER(_c.c_double)]),
     "sla_set_option": (_c.c_int, [_vp, _c.c_int, _c.c_int64]),
+    "sla_model_create": (_c.c_int, [_vp, _c.POINTER(_vp)]),
+    "sla_model_destroy": (None, [_vp]),
+    "sla_model_set_params": (_c.c_int, [_vp, _vp, _vp, _c.c_int64]),
+    "sla_model_get_params": (_c.c_int, [_vp, _vp, _vp, _c.c_int64]),
+    "sla_model_set_courant_range": (_c.c_int, [_vp, _c.c_double]),
+    "sla_make_pairs": (_c.c_int, [_vp, _vp, _vp, _vp, _vp, _c.c_double, _vp, _c.c_int64, _vp,
+                                  _vp, _vp]),
+    "sla_model_forward": (_c.c_int, [_vp, _vp, _vp, _c.c_int64, _vp]),
+    "sla_model_grads": (_c.c_int, [_vp, _vp, _vp, _vp, _c.c_int64, _vp, _c.POINTER(_c.c_double)]),
+    "sla_model_train_step": (_c.c_int, [_vp, _vp, _vp, _vp, _c.c_int64, _c.c_double,
+                                        _c.POINTER(_c.c_double)]),
+    "sla_advect_learned": (_c.c_int, [_vp, _vp, _vp, _vp, _vp, _c.c_double, _c.c_int32,
+                                      _c.c_int64, _c.c_double, _c.POINTER(_c.c_int32)]),
     "sla_timing": (_c.c_int, [_vp, _c.c_int]),
     "sla_timing_read": (_c.c_int, [_vp, _c.POINTER(_c.c_int64), _c.POINTER(_c.c_double)]),
 }
 
-KERNEL_KINDS = ["cir", "fec", "bec", "sweep_x", "sweep_y", "sweep_z", "cec3d", "copy"]
+KERNEL_KINDS = ["cir", "fec", "bec", "sweep_x", "sweep_y", "sweep_z", "cec3d", "copy", "learned"]
+MLP_INPUTS, MLP_HIDDEN, MLP_PARAMS = 32, 64, 6337
 
 
 class SlaError(RuntimeError):
@@ -188,3 +202,92 @@ class Context:
         self._stream()
         self._raise(self.lib.sla_timing_read(self.h, launches, ms))
         return {KERNEL_KINDS[k]: (launches[k], ms[k]) for k in range(n) if launches[k]}
+
+
+class Model:
+    """A learned-correction network living on a context's device."""
+
+    def __init__(self, ctx: Context):
+        self.ctx = ctx
+        self.lib = ctx.lib
+        h = ctypes.c_void_p()
+        ctx._stream()
+        ctx._raise(self.lib.sla_model_create(ctx.h, ctypes.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.sla_model_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, params):
+        import numpy as np
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        if p.size != MLP_PARAMS:
+            raise ValueError(f"need {MLP_PARAMS} parameters")
+        self.ctx._stream()
+        self.ctx._raise(self.lib.sla_model_set_params(self.ctx.h, self.h, p.ctypes.data_as(ctypes.c_void_p),
+                                                      p.size))
+
+    def get_params(self):
+        import numpy as np
+        p = np.empty(MLP_PARAMS, dtype=np.float32)
+        self.ctx._stream()
+        self.ctx._raise(self.lib.sla_model_get_params(self.ctx.h, self.h, p.ctypes.data_as(ctypes.c_void_p),
+                                                      p.size))
+        return p
+
+    def set_courant_range(self, r: float):
+        if self.lib.sla_model_set_courant_range(self.h, float(r)) != OK:
+            raise SlaError(EINVAL, "bad Courant range")
+
+    def forward(self, feats, y):
+        self.ctx._stream()
+        self.ctx._raise(self.lib.sla_model_forward(self.ctx.h, self.h, _ptr(feats), feats.shape[0], _ptr(y)))
+
+    def grads(self, feats, target):
+        import numpy as np
+        g = np.empty(MLP_PARAMS, dtype=np.float32)
+        loss = ctypes.c_double()
+        self.ctx._stream()
+        self.ctx._raise(self.lib.sla_model_grads(self.ctx.h, self.h, _ptr(feats), _ptr(target),
+                                                 feats.shape[0], g.ctypes.data_as(ctypes.c_void_p),
+                                                 ctypes.byref(loss)))
+        return g, loss.value
+
+    def train_step(self, feats, target, lr, want_loss=False, m=None):
+        loss = ctypes.c_double()
+        rows = feats.shape[0] if m is None else int(m)
+        self.ctx._stream()
+        self.ctx._raise(self.lib.sla_model_train_step(self.ctx.h, self.h, _ptr(feats), _ptr(target), rows,
+                                                      float(lr), ctypes.byref(loss) if want_loss else None))
+        return loss.value if want_loss else None
+
+
+def make_pairs(ctx: Context, phi1, phi_next, u, dx, dt, cells, feats, target, sigma):
+    """Features/targets of the nodes ``cells`` (int32 linear indices, device)."""
+    g = make_grid(phi1.shape, dx)
+    ctx._stream()
+    ctx._raise(ctx.lib.sla_make_pairs(ctx.h, ctypes.byref(g), _ptr(phi1), _ptr(phi_next), _ptr(u),
+                                      float(dt), _ptr(cells), cells.numel(), _ptr(feats), _ptr(target),
+                                      _ptr(sigma)))
+
+
+def advect_learned(ctx: Context, model: Model, phi, u, dx, dt, steps, step0=0, courant_max=0.0,
+                   allow_fallback=True):
+    """Learned steps in place; returns True if the call fell back to the plain scheme."""
+    _check_field(phi, "phi")
+    _check_field(u, "u")
+    g = make_grid(phi.shape, dx)
+    fb = ctypes.c_int32(0)
+    ctx._stream()
+    ctx._raise(ctx.lib.sla_advect_learned(ctx.h, model.h, ctypes.byref(g), _ptr(phi), _ptr(u), float(dt),
+                                          int(steps), int(step0), float(courant_max),
+                                          ctypes.byref(fb) if allow_fallback else None))
+    return bool(fb.value)
