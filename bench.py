@@ -31,7 +31,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 METRIC = "Gcell-updates/s + %HBM peak, 3rd-order 512³ FP32; learned vs plain at equal L2"
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_1606_06117_amd", "csrc", "advect_kernels.hip")
+CSRC = os.path.join(ROOT, "paper_1606_06117_amd", "csrc")
+# source file holding each kernel kind (counters are stale once it changes)
+KERNEL_SRC = {"cec3d": "cec3d_kernel.hip", "learned": "mlp_kernels.hip"}
 
 
 def algorithmic_bytes(kind: str, ncells: int, ndim: int) -> int:
@@ -47,8 +49,8 @@ def algorithmic_bytes(kind: str, ncells: int, ndim: int) -> int:
     return per_cell * ncells
 
 
-def source_hash() -> str:
-    with open(KERNEL_SRC, "rb") as fh:
+def source_hash(kind: str) -> str:
+    with open(os.path.join(CSRC, KERNEL_SRC.get(kind, "advect_kernels.hip")), "rb") as fh:
         return hashlib.sha256(fh.read()).hexdigest()[:16]
 
 
@@ -60,7 +62,7 @@ def measured_traffic(kind: str, workload: str):
     except (OSError, ValueError):
         return None
     entry = data.get(workload, {}).get(kind)
-    if not entry or entry.get("source_sha256_16") != source_hash():
+    if not entry or entry.get("source_sha256_16") != source_hash(kind):
         return None
     return entry.get("bytes_per_launch")
 
@@ -112,6 +114,45 @@ def copy_probe(reps: int, warmup: int) -> int:
     return 0
 
 
+def learned_section(ctx, size, fields, steps_per_field, cells, iters, batch, lr):
+    """Learned correction vs the plain third-order scheme on the time-modulated
+    ABC flow (CFL 0.9 at peak amplitude): training on pairs from the GPU
+    third-order scheme, then error against the exact field after whole
+    modulation periods, time per step, and the speedup at equal error."""
+    from paper_1606_06117_amd import learned as Lr
+    shape = (size, size, size)
+    pairs = Lr.generate_pairs(ctx, shape, fields=list(range(4000, 4000 + fields)),
+                              steps_per_field=steps_per_field, cells_per_snapshot=cells,
+                              cfl=0.9, seed_cells=4500)
+    model, hist, train_s = Lr.train(ctx, pairs, iters=iters, batch=batch, lr=lr, seed=4600, cfl=0.9,
+                                    log_every=max(1, iters // 10))
+    ev = Lr.evaluate(ctx, model, shape, seed=4100, periods=2, cfl=0.9)
+    # cost-to-error curve of the plain scheme: a period in 50..200 steps
+    plain = []
+    for spp in (200, 100, 75, 60):
+        err, secs = Lr.error_at_cfl(ctx, shape, 4100, 0.9, spp, 2)
+        plain.append((err, secs, 0.9 * Lr.PERIOD / spp))
+    lerr, lsecs = Lr.error_at_cfl(ctx, shape, 4100, 0.9, Lr.PERIOD, 2, learned_model=model)
+    speed = Lr.equal_error_speedup([(e, t) for e, t, _ in plain], (lerr, lsecs))
+    last = ev["per_step"][-1]
+    out = {
+        "workload": f"{size}^3 FP32, ABC velocity with amplitude sin(2 pi (m+1/2)/100), CFL 0.9 at peak; "
+                    f"{fields} fields x {steps_per_field} steps x {cells} nodes = {pairs.m} training pairs",
+        "pairs_seconds": pairs.seconds,
+        "train_iters": iters, "train_batch": batch, "train_seconds": train_s,
+        "loss_first": hist[0][1] if hist else None, "loss_last": hist[-1][1] if hist else None,
+        "relL2_vs_third_order_after_200_steps": {"learned": last[1], "cir": last[2]},
+        "relL2_vs_exact": ev["vs_exact"],
+        "ms_per_step": ev["ms_per_step"],
+        "fell_back": ev["fell_back"],
+        "plain_error_vs_cost": [{"cfl": c, "relL2_vs_exact": e, "seconds": t} for e, t, c in plain],
+        "learned_error_vs_cost": {"cfl": 0.9, "relL2_vs_exact": lerr, "seconds": lsecs},
+        "speedup_at_equal_L2": speed,
+    }
+    model.close()
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -125,6 +166,13 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--path", choices=["auto", "sweeps"], default="auto",
                     help="auto: fused step where the library has one; sweeps: one kernel per axis")
+    ap.add_argument("--learned", choices=["on", "off"], default="on",
+                    help="also train and evaluate the learned correction (256^3)")
+    ap.add_argument("--learned-size", type=int, default=256)
+    ap.add_argument("--learned-fields", type=int, default=20)
+    ap.add_argument("--learned-steps", type=int, default=100)
+    ap.add_argument("--learned-cells", type=int, default=65536)
+    ap.add_argument("--learned-iters", type=int, default=4000)
     ap.add_argument("--probe", choices=["copy"], default=None,
                     help="instead of the benchmark, time a plain device copy of known size "
                          "(achievable bandwidth; calibrates HBM byte counters)")
@@ -231,6 +279,13 @@ def main(argv=None):
         "hbm_frac_step": hbm_frac_step,
         "roofline": roofline,
     }
+
+    if args.learned == "on":
+        print("[bench] learned correction: pairs, training, evaluation ...", file=sys.stderr, flush=True)
+        del phi_d, u_d
+        torch.cuda.empty_cache()
+        out["learned"] = learned_section(ctx, args.learned_size, args.learned_fields, args.learned_steps,
+                                         args.learned_cells, args.learned_iters, 65536, 2e-3)
 
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle sample ...", file=sys.stderr, flush=True)

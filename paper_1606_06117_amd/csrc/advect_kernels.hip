@@ -62,6 +62,18 @@ __device__ __forceinline__ int wrapk(int v, int n) {
   return v;
 }
 
+// Run f(i) for i = start + STRIDE k < N, unrolled to a compile-time trip
+// count so that a thread's independent LDS reads are all issued before the
+// first result is needed.
+template <int N, int STRIDE, typename F>
+__device__ __forceinline__ void for_strided(int start, F&& f) {
+#pragma unroll
+  for (int k = 0; k < (N + STRIDE - 1) / STRIDE; ++k) {
+    const int i = start + k * STRIDE;
+    if (i < N) f(i);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // CIR: one multilinear interpolation per node (section 3 first equation;
 // eq. CIR2D; the same tensor product in 3D).  Gathers straight from global
@@ -219,14 +231,14 @@ __global__ __launch_bounds__(kThreads) void k_ec(const float* __restrict__ phi,
       const int p = t - RZ;
       const int gz = wrapk(first + p, g.nz);
       float* dst = st1 + (p % D) * S::PLANE(1);
-      for (int e = threadIdx.x; e < S::PLANE(1); e += kThreads) {
+      for_strided<S::PLANE(1), kThreads>(threadIdx.x, [&](int e) {
         const int ly = e / S::W(1), lx = e - ly * S::W(1);
         const int gx = wrapk(x0 - S::HX(1) + lx, g.nx);
         const int gy = wrapk(y0 - S::HY(1) + ly, g.ny);
         Dep dx{}, dy{}, dz{};
         deps(gx, gy, gz, false, dx, dy, dz);
         dst[e] = interp_lds<NDIM, S::W(0), S::PLANE(0), D>(st0, p, lx + R, ly + RY, dx, dy, dz);
-      }
+      });
     }
     __syncthreads();
     if (K == 3) {
@@ -236,7 +248,7 @@ __global__ __launch_bounds__(kThreads) void k_ec(const float* __restrict__ phi,
         const int gz = wrapk(first + p, g.nz);
         float* dst = st2 + (p % D) * S::PLANE(2);
         const float* ph = st0 + (p % D) * S::PLANE(0);
-        for (int e = threadIdx.x; e < S::PLANE(2); e += kThreads) {
+        for_strided<S::PLANE(2), kThreads>(threadIdx.x, [&](int e) {
           const int ly = e / S::W(2), lx = e - ly * S::W(2);
           const int gx = wrapk(x0 - S::HX(2) + lx, g.nx);
           const int gy = wrapk(y0 - S::HY(2) + ly, g.ny);
@@ -246,7 +258,7 @@ __global__ __launch_bounds__(kThreads) void k_ec(const float* __restrict__ phi,
               interp_lds<NDIM, S::W(1), S::PLANE(1), D>(st1, p, lx + R, ly + RY, dx, dy, dz);
           const float v = ph[(ly + 2 * RY) * S::W(0) + lx + 2 * R];
           dst[e] = fmaf(0.5f, v - bar, v);
-        }
+        });
       }
       __syncthreads();
     }
@@ -254,10 +266,10 @@ __global__ __launch_bounds__(kThreads) void k_ec(const float* __restrict__ phi,
     if (t >= 2 * K * RZ) {
       const int p = t - K * RZ;
       const int z = first + p;  // in [zbeg, zend)
-      for (int e = threadIdx.x; e < TX * TY; e += kThreads) {
+      for_strided<TX * TY, kThreads>(threadIdx.x, [&](int e) {
         const int ly = e / TX, lx = e - ly * TX;
         const int gx = x0 + lx, gy = y0 + ly;
-        if (gx >= g.nx || gy >= g.ny) continue;
+        if (gx >= g.nx || gy >= g.ny) return;
         float res;
         if (K == 2) {
           Dep dx{}, dy{}, dz{};
@@ -273,7 +285,7 @@ __global__ __launch_bounds__(kThreads) void k_ec(const float* __restrict__ phi,
           res = interp_lds<NDIM, S::W(2), S::PLANE(2), D>(st2, p, lx + R, ly + RY, dx, dy, dz);
         }
         out[(size_t)z * plane + (size_t)gy * g.nx + gx] = res;
-      }
+      });
     }
     __syncthreads();
   }
@@ -327,26 +339,26 @@ __global__ __launch_bounds__(kThreads) void k_sweep_s(const float* __restrict__ 
   for (int k = 0; k < KCr; ++k)
     if (ty + k * RS < NC) C[(ty + k * RS) * TW + tx] = vc[k] * lam;
   __syncthreads();
-  for (int r = ty; r < NC; r += kThreads / TW) {
+  for_strided<NC, kThreads / TW>(ty, [&](int r) {
     const Dep d = depart<R>(C[r * TW + tx], flag);
     P1[r * TW + tx] = lerp(P[(r + R + d.oa) * TW + tx], P[(r + R + d.ob) * TW + tx], d.f);
-  }
+  });
   __syncthreads();
-  for (int r = ty; r < NE; r += kThreads / TW) {
+  for_strided<NE, kThreads / TW>(ty, [&](int r) {
     const Dep d = depart<R>(-C[(r + R) * TW + tx], flag);
     const float bar = lerp(P1[(r + R + d.oa) * TW + tx], P1[(r + R + d.ob) * TW + tx], d.f);
     E[r * TW + tx] = P[(r + 2 * R) * TW + tx] - bar;
-  }
+  });
   __syncthreads();
   if (!xin) return;
-  for (int r = ty; r < TL; r += kThreads / TW) {
+  for_strided<TL, kThreads / TW>(ty, [&](int r) {
     const int l = l0 + r;
-    if (l >= L) break;
+    if (l >= L) return;
     const Dep d = depart<R>(C[(r + 2 * R) * TW + tx], flag);
     const float ea = E[(r + R + d.oa) * TW + tx], eb = E[(r + R + d.ob) * TW + tx];
     const float w = fmaf(d.f, 1.f / 3.f, 1.f / 3.f);
     out[base + (size_t)l * S] = fmaf(0.5f, fmaf(w, eb - ea, ea), P1[(r + 2 * R) * TW + tx]);
-  }
+  });
 }
 
 // Contiguous axis (x): tile = TL consecutive x in each of ROWS rows.
@@ -390,30 +402,30 @@ __global__ __launch_bounds__(kThreads) void k_sweep_x(const float* __restrict__ 
     if (e < ROWS * NC) C[e] = vc[k] * lam;
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < ROWS * NC; e += kThreads) {
+  for_strided<ROWS * NC, kThreads>(threadIdx.x, [&](int e) {
     const int rr = e / NC, col = e - rr * NC;
     const Dep d = depart<R>(C[e], flag);
     const float* p = P + rr * NP + col + R;
     P1[e] = lerp(p[d.oa], p[d.ob], d.f);
-  }
+  });
   __syncthreads();
-  for (int e = threadIdx.x; e < ROWS * NE; e += kThreads) {
+  for_strided<ROWS * NE, kThreads>(threadIdx.x, [&](int e) {
     const int rr = e / NE, col = e - rr * NE;
     const Dep d = depart<R>(-C[rr * NC + col + R], flag);
     const float* p1 = P1 + rr * NC + col + R;
     E[e] = P[rr * NP + col + 2 * R] - lerp(p1[d.oa], p1[d.ob], d.f);
-  }
+  });
   __syncthreads();
-  for (int e = threadIdx.x; e < ROWS * TL; e += kThreads) {
+  for_strided<ROWS * TL, kThreads>(threadIdx.x, [&](int e) {
     const int rr = e / TL, col = e - rr * TL;
     const int y = y0 + rr, x = l0 + col;
-    if (y >= ny || x >= nx) continue;
+    if (y >= ny || x >= nx) return;
     const Dep d = depart<R>(C[rr * NC + col + 2 * R], flag);
     const float* ee = E + rr * NE + col + R;
     const float ea = ee[d.oa], eb = ee[d.ob];
     const float w = fmaf(d.f, 1.f / 3.f, 1.f / 3.f);
     out[zoff + (size_t)y * nx + x] = fmaf(0.5f, fmaf(w, eb - ea, ea), P1[rr * NC + col + 2 * R]);
-  }
+  });
 }
 
 template <typename F>

@@ -75,6 +75,17 @@ struct Cec3dShape {
   static constexpr int KY = (NY + kThreads - 1) / kThreads;  // y columns per thread
 };
 
+// Run f(e) for e = tid + 256 k < N, unrolled so that the LDS reads of all of
+// a thread's elements are issued before the first result is needed.
+template <int N, typename F>
+__device__ __forceinline__ void for_each_cell(F&& f) {
+#pragma unroll
+  for (int k = 0; k < (N + kThreads - 1) / kThreads; ++k) {
+    const int e = threadIdx.x + k * kThreads;
+    if (N % kThreads == 0 || e < N) f(e);
+  }
+}
+
 // padded LDS index of tile-relative (x, z)
 template <bool EVEN>
 __device__ __forceinline__ int lidx(int x, int z) {
@@ -88,8 +99,13 @@ __device__ __forceinline__ int wrap1(int v, int n) {
   return v >= n ? v - n : v;
 }
 
+// Minimum waves per SIMD the compiler must leave room for (register budget).
+#ifndef SLA_CEC3D_MIN_WAVES
+#define SLA_CEC3D_MIN_WAVES 2
+#endif
+
 template <bool EVEN>
-__global__ __launch_bounds__(kThreads) void k_cec3d_r1(const float* __restrict__ phi,
+__global__ __launch_bounds__(kThreads, SLA_CEC3D_MIN_WAVES) void k_cec3d_r1(const float* __restrict__ phi,
                                                        const float* __restrict__ ux,
                                                        const float* __restrict__ uy,
                                                        const float* __restrict__ uz,
@@ -195,36 +211,36 @@ __global__ __launch_bounds__(kThreads) void k_cec3d_r1(const float* __restrict__
     // 2. first sweep, Phi1 on A in [-2, TA+2)
     {
       constexpr int LA = TA + 4, LB = TB + 2 * H;
-      for (int e = tid; e < LA * LB; e += kThreads) {
+      for_each_cell<LA * LB>([&](int e) {
         const int b = -H + e / LA, a = -2 + e % LA;
         const int i = EVEN ? lidx<EVEN>(a, b) : lidx<EVEN>(b, a);
         const Dep1 d = depart1(CA[i], flag);
         S1[i] = lerp(P[i], P[i + d.ob * SA], d.f);
-      }
+      });
     }
     __syncthreads();
     // 3. first sweep, e on A in [-1, TA+1)
     {
       constexpr int LA = TA + 2, LB = TB + 2 * H;
-      for (int e = tid; e < LA * LB; e += kThreads) {
+      for_each_cell<LA * LB>([&](int e) {
         const int b = -H + e / LA, a = -1 + e % LA;
         const int i = EVEN ? lidx<EVEN>(a, b) : lidx<EVEN>(b, a);
         const Dep1 d = depart1(CA[i], flag);
         SE[i] = P[i] - lerp(S1[i], S1[i + d.obr * SA], d.f);
-      }
+      });
     }
     __syncthreads();
     // 4. first sweep output on A in [0, TA)
     {
       constexpr int LB = TB + 2 * H;
-      for (int e = tid; e < TA * LB; e += kThreads) {
+      for_each_cell<TA * LB>([&](int e) {
         const int b = -H + e / TA, a = e % TA;
         const int i = EVEN ? lidx<EVEN>(a, b) : lidx<EVEN>(b, a);
         const Dep1 d = depart1(CA[i], flag);
         const float ea = SE[i], eb = SE[i + d.ob * SA];
         const float w = fmaf(d.f, 1.f / 3.f, 1.f / 3.f);
         AO[i] = fmaf(0.5f, fmaf(w, eb - ea, ea), S1[i]);
-      }
+      });
     }
     __syncthreads();
     // 5. y sweep as a pipeline along the march (registers)
@@ -252,44 +268,240 @@ __global__ __launch_bounds__(kThreads) void k_cec3d_r1(const float* __restrict__
     // 6. last sweep, Phi1 on B in [-2, TB+2)
     {
       constexpr int LB = TB + 4;
-      for (int e = tid; e < TA * LB; e += kThreads) {
+      for_each_cell<TA * LB>([&](int e) {
         const int b = -2 + e / TA, a = e % TA;
         const int i = EVEN ? lidx<EVEN>(a, b) : lidx<EVEN>(b, a);
         const Dep1 d = depart1(CB[i], flag);
         S1[i] = lerp(YO[i], YO[i + d.ob * SB], d.f);
-      }
+      });
     }
     __syncthreads();
     // 7. last sweep, e on B in [-1, TB+1)
     {
       constexpr int LB = TB + 2;
-      for (int e = tid; e < TA * LB; e += kThreads) {
+      for_each_cell<TA * LB>([&](int e) {
         const int b = -1 + e / TA, a = e % TA;
         const int i = EVEN ? lidx<EVEN>(a, b) : lidx<EVEN>(b, a);
         const Dep1 d = depart1(CB[i], flag);
         SE[i] = YO[i] - lerp(S1[i], S1[i + d.obr * SB], d.f);
-      }
+      });
     }
     __syncthreads();
     // 8. last sweep output on the tile, stored to HBM at plane t - 6
     {
       const unsigned yo = unsigned(y0 + t - 2 * H) * unsigned(nx);
-      for (int e = tid; e < TA * TB; e += kThreads) {
+      for_each_cell<TA * TB>([&](int e) {
         const int b = e / TA, a = e % TA;
         const int x = EVEN ? a : b, z = EVEN ? b : a;
-        if (x0 + x >= nx || z0 + z >= nz) continue;
+        if (x0 + x >= nx || z0 + z >= nz) return;
         const int i = lidx<EVEN>(x, z);
         const Dep1 d = depart1(CB[i], flag);
         const float ea = SE[i], eb = SE[i + d.ob * SB];
         const float w = fmaf(d.f, 1.f / 3.f, 1.f / 3.f);
         out[unsigned(x0 + x) + yo + nxy * unsigned(z0 + z)] =
             fmaf(0.5f, fmaf(w, eb - ea, ea), S1[i]);
+      });
+    }
+    // The next plane stores CB before its first barrier while this plane's
+    // last sweep may still be reading it.
+    __syncthreads();
+  };
+
+  for (int t = 0; t < iters; t += 3) {
+    body(std::integral_constant<int, 0>{}, t);
+    if (t + 1 < iters) body(std::integral_constant<int, 1>{}, t + 1);
+    if (t + 2 < iters) body(std::integral_constant<int, 2>{}, t + 2);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Segment variant: the first and the last sweep of a plane run as per-thread
+// segments of V consecutive nodes along the sweep axis, all three calls in
+// registers (inputs V+6 nodes, Phi1 on V+4, e on V+2, outputs V), so a plane
+// needs four barriers instead of seven.  The y pipeline is the same.
+// ---------------------------------------------------------------------------
+template <bool EVEN>
+struct SegShape : Cec3dShape<EVEN> {
+  using B = Cec3dShape<EVEN>;
+  static constexpr int V = 8;
+  static constexpr int NS1 = B::TA / V, N1 = (B::TB + 2 * B::H) * NS1;  // first sweep items
+  static constexpr int NS2 = B::TB / V, N2 = B::TA * NS2;               // last sweep items
+  static_assert(B::TA % V == 0 && B::TB % V == 0, "segments tile the block");
+  static_assert(N1 <= kThreads && N2 <= kThreads, "one item per thread");
+};
+
+// Third-order sweep of one segment: p holds the V+6 input nodes a0-3..a0+V+2,
+// c the V+4 Courant numbers of a0-2..a0+V+1; out receives a0..a0+V-1.
+template <int V>
+__device__ __forceinline__ void sweep_segment(const float (&p)[V + 6], const float (&c)[V + 4],
+                                              float (&out)[V], int* flag) {
+  float p1[V + 4], e[V + 2];
+#pragma unroll
+  for (int k = 0; k < V + 4; ++k) {  // node a0-2+k
+    const Dep1 d = depart1(c[k], flag);
+    p1[k] = lerp(p[k + 1], d.ob < 0 ? p[k] : p[k + 2], d.f);
+  }
+#pragma unroll
+  for (int k = 0; k < V + 2; ++k) {  // node a0-1+k
+    const Dep1 d = depart1(c[k + 1], flag);
+    e[k] = p[k + 2] - lerp(p1[k + 1], d.obr > 0 ? p1[k + 2] : p1[k], d.f);
+  }
+#pragma unroll
+  for (int k = 0; k < V; ++k) {  // node a0+k
+    const Dep1 d = depart1(c[k + 2], flag);
+    const float ea = e[k + 1], eb = d.ob < 0 ? e[k] : e[k + 2];
+    const float w = fmaf(d.f, 1.f / 3.f, 1.f / 3.f);
+    out[k] = fmaf(0.5f, fmaf(w, eb - ea, ea), p1[k + 2]);
+  }
+}
+
+template <bool EVEN>
+__global__ __launch_bounds__(kThreads, SLA_CEC3D_MIN_WAVES) void k_cec3d_seg(
+    const float* __restrict__ phi, const float* __restrict__ ux, const float* __restrict__ uy,
+    const float* __restrict__ uz, float* __restrict__ out, Geo g, int ychunk, int* flag) {
+  using S = SegShape<EVEN>;
+  constexpr int H = S::H, TA = S::TA, SA = S::SA, SB = S::SB, V = S::V;
+  constexpr int KP = S::KP, KY = S::KY;
+  __shared__ float P[S::NP];   // phi at the loaded plane, padded
+  __shared__ float CA[S::NP];  // Courant numbers of the first sweep
+  __shared__ float CB[S::NP];  // Courant numbers of the last sweep (output plane)
+  __shared__ float AO[S::NP];  // first-sweep output (y-pipeline input)
+  __shared__ float YO[S::NP];  // y-sweep output (last-sweep input)
+
+  const int tid = threadIdx.x;
+  const int x0 = blockIdx.x * S::TX, z0 = blockIdx.y * S::TZ;
+  const int y0 = blockIdx.z * ychunk;
+  const int y1 = min(y0 + ychunk, g.ny);
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  const unsigned nxy = unsigned(nx) * unsigned(ny);
+  const float* uA = EVEN ? ux : uz;
+  const float* uB = EVEN ? uz : ux;
+  const float lamA = EVEN ? g.lam[0] : g.lam[2];
+  const float lamB = EVEN ? g.lam[2] : g.lam[0];
+  const float lamY = g.lam[1];
+
+  unsigned poff[KP];
+  unsigned yoff[KY];
+  int ycol[KY];
+#pragma unroll
+  for (int k = 0; k < KP; ++k) {
+    const int e = min(tid + k * kThreads, S::NP - 1);
+    const int z = e / S::W - H, x = e % S::W - H;
+    poff[k] = unsigned(wrap1(x0 + x, nx)) + nxy * unsigned(wrap1(z0 + z, nz));
+  }
+#pragma unroll
+  for (int j = 0; j < KY; ++j) {
+    const int e = min(tid + j * kThreads, S::NY - 1);
+    const int z = S::YZ0 + e / S::YW, x = S::YX0 + e % S::YW;
+    yoff[j] = unsigned(wrap1(x0 + x, nx)) + nxy * unsigned(wrap1(z0 + z, nz));
+    ycol[j] = lidx<EVEN>(x, z);
+  }
+  auto pvalid = [&](int k) { return KP * kThreads == S::NP || tid + k * kThreads < S::NP; };
+  auto yvalid = [&](int j) { return KY * kThreads == S::NY || tid + j * kThreads < S::NY; };
+
+  // segment items: first sweep (line b, start a0), last sweep (line a, start b0)
+  const bool has1 = tid < S::N1, has2 = tid < S::N2;
+  const int i1 = EVEN ? lidx<EVEN>((tid % S::NS1) * V, tid / S::NS1 - H)
+                      : lidx<EVEN>(tid / S::NS1 - H, (tid % S::NS1) * V);
+  const int la2 = EVEN ? tid % TA : tid / S::NS2;  // last sweep: line (A coordinate)
+  const int sb2 = EVEN ? tid / TA : tid % S::NS2;  // last sweep: segment index along B
+  const int i2 = EVEN ? lidx<EVEN>(la2, sb2 * V) : lidx<EVEN>(sb2 * V, la2);
+  const int ox2 = EVEN ? la2 : sb2 * V, oz2 = EVEN ? sb2 * V : la2;  // tile coords of out[0]
+
+  float ra[3][KY], r1[3][KY], re[3][KY], rc[3][KY];
+#pragma unroll
+  for (int j = 0; j < KY; ++j)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) ra[k][j] = r1[k][j] = re[k][j] = rc[k][j] = 0.f;
+
+  float fp[KP], fa[KP], fy[KY], fb[KY];
+  auto prefetch = [&](int t) {
+    const unsigned qoff = unsigned(wrap1(y0 - H + t, ny)) * unsigned(nx);
+    const unsigned coff = unsigned(wrap1(y0 - H + t - 1, ny)) * unsigned(nx);
+    const unsigned ooff = unsigned(wrap1(y0 + t - 2 * H, ny)) * unsigned(nx);
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+      fp[k] = phi[poff[k] + qoff];
+      fa[k] = uA[poff[k] + qoff];
+    }
+#pragma unroll
+    for (int j = 0; j < KY; ++j) {
+      fy[j] = uy[yoff[j] + coff];
+      fb[j] = uB[yoff[j] + ooff];
+    }
+  };
+
+  const int iters = (y1 - y0) + 2 * H;
+  prefetch(0);
+  auto body = [&](auto phase, int t) {
+    constexpr int p0 = decltype(phase)::value;  // t % 3
+    constexpr int p1 = (p0 + 2) % 3;            // (t - 1) % 3
+    constexpr int p2 = (p0 + 1) % 3;            // (t - 2) % 3
+    constexpr int p3 = p0;                      // (t - 3) % 3
+    const bool emit = t >= 2 * H;
+
+    // 1. publish the prefetched plane, then start fetching the next one
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+      if (!pvalid(k)) continue;
+      P[tid + k * kThreads] = fp[k];
+      CA[tid + k * kThreads] = fa[k] * lamA;
+    }
+    float cy[KY];
+#pragma unroll
+    for (int j = 0; j < KY; ++j) {
+      cy[j] = fy[j] * lamY;
+      if (emit && yvalid(j)) CB[ycol[j]] = fb[j] * lamB;
+    }
+    if (t + 1 < iters) prefetch(t + 1);
+    __syncthreads();
+    // 2. first sweep, one segment per thread
+    if (has1) {
+      float p[V + 6], c[V + 4], o[V];
+#pragma unroll
+      for (int k = 0; k < V + 6; ++k) p[k] = P[i1 + (k - 3) * SA];
+#pragma unroll
+      for (int k = 0; k < V + 4; ++k) c[k] = CA[i1 + (k - 2) * SA];
+      sweep_segment<V>(p, c, o, flag);
+#pragma unroll
+      for (int k = 0; k < V; ++k) AO[i1 + k * SA] = o[k];
+    }
+    __syncthreads();
+    // 3. y sweep as a pipeline along the march (registers)
+#pragma unroll
+    for (int j = 0; j < KY; ++j) {
+      if (!yvalid(j)) continue;
+      const int i = ycol[j];
+      ra[p0][j] = AO[i];
+      rc[p1][j] = cy[j];
+      Dep1 d = depart1(rc[p1][j], flag);
+      r1[p1][j] = lerp(ra[p1][j], d.ob < 0 ? ra[p2][j] : ra[p0][j], d.f);
+      d = depart1(rc[p2][j], flag);
+      re[p2][j] = ra[p2][j] - lerp(r1[p2][j], d.obr > 0 ? r1[p1][j] : r1[p3][j], d.f);
+      d = depart1(rc[p3][j], flag);
+      const float ea = re[p3][j];
+      const float eb = d.ob < 0 ? re[p1][j] : re[p2][j];
+      const float w = fmaf(d.f, 1.f / 3.f, 1.f / 3.f);
+      YO[i] = fmaf(0.5f, fmaf(w, eb - ea, ea), r1[p3][j]);
+    }
+    __syncthreads();
+    if (!emit) return;
+    // 4. last sweep, one segment per thread, stored to HBM at plane t - 6
+    if (has2) {
+      float p[V + 6], c[V + 4], o[V];
+#pragma unroll
+      for (int k = 0; k < V + 6; ++k) p[k] = YO[i2 + (k - 3) * SB];
+#pragma unroll
+      for (int k = 0; k < V + 4; ++k) c[k] = CB[i2 + (k - 2) * SB];
+      sweep_segment<V>(p, c, o, flag);
+      const unsigned yo = unsigned(y0 + t - 2 * H) * unsigned(nx);
+#pragma unroll
+      for (int k = 0; k < V; ++k) {
+        const int x = x0 + ox2 + (EVEN ? 0 : k), z = z0 + oz2 + (EVEN ? k : 0);
+        if (x < nx && z < nz) out[unsigned(x) + yo + nxy * unsigned(z)] = o[k];
       }
     }
-    // No barrier needed here: the next plane's LDS writes (P, CA, CB) are
-    // separated from every read of this plane by barriers 1-5 of the next
-    // iteration, except CB, which the last sweep reads until now: the next
-    // iteration writes CB before its first barrier, so a barrier is needed.
+    // the next plane stores CB before its first barrier
     __syncthreads();
   };
 
@@ -301,6 +513,20 @@ __global__ __launch_bounds__(kThreads) void k_cec3d_r1(const float* __restrict__
 }
 
 }  // namespace
+
+hipError_t launch_cec3d_seg(bool even, const Geo& g, const float* phi, const float* u, float* out,
+                            int* flag, hipStream_t st) {
+  const size_t n = (size_t)g.ncells;
+  const int ychunk = g.ny >= 256 ? 128 : 64;
+  dim3 grid((g.nx + 63) / 64, (g.nz + 15) / 16, (g.ny + ychunk - 1) / ychunk);
+  if (even)
+    hipLaunchKernelGGL(k_cec3d_seg<true>, grid, dim3(kThreads), 0, st, phi, u, u + n, u + 2 * n,
+                       out, g, ychunk, flag);
+  else
+    hipLaunchKernelGGL(k_cec3d_seg<false>, grid, dim3(kThreads), 0, st, phi, u, u + n, u + 2 * n,
+                       out, g, ychunk, flag);
+  return hipGetLastError();
+}
 
 hipError_t launch_cec3d(int R, bool even, const Geo& g, const float* phi, const float* u,
                         float* out, int* flag, hipStream_t st) {

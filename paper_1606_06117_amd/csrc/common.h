@@ -68,6 +68,10 @@ hipError_t launch_make_pairs(const Geo& g, const float* phi1, const float* phi_n
 hipError_t launch_learned_correct(const Geo& g, const float* phi1, const float* u, const void* wpack,
                                   const float* wr, float* out, hipStream_t st);
 
+// Segment variant of the same step (identical arithmetic per node).
+hipError_t launch_cec3d_seg(bool even, const Geo& g, const float* phi, const float* u, float* out,
+                            int* flag, hipStream_t st);
+
 // Max |u_d| per axis over the grid (FP32, NaN propagates) into out3 (device).
 hipError_t launch_umax(int ndim, int ncells, const float* u, float* part,
                        float* out3, hipStream_t st);
