@@ -122,7 +122,11 @@ typedef enum {
    * one fused kernel (all three sweeps, 20 B per cell of HBM traffic).
    * 0: every third-order step runs one sweep kernel per axis.  Both paths
    * perform the same FP32 operations per node. */
-  SLA_OPT_FUSED = 0
+  SLA_OPT_FUSED = 0,
+  /* Which implementation runs the fused step (same FP32 operations, same
+   * results): 0 LDS stages, 1 register segments, 2 streaming (direct
+   * global-to-LDS loads, default). */
+  SLA_OPT_CEC3D_KERNEL = 1
 } sla_option;
 /* Set option `option` to `value`.  Returns SLA_EINVAL for an unknown option
  * or value. */
@@ -142,6 +146,50 @@ int sla_check(sla_ctx *ctx);
  * count).  Synchronises the stream. */
 int sla_norms(sla_ctx *ctx, int64_t count, const float *a, const float *b,
               double *out);
+
+/* ------------------------------------------------------------------------
+ * Batched third-order steps in one captured graph.
+ *
+ * A plan advances many independent problems by the same number of
+ * third-order steps (eq. intro:CEC, split per axis as in section 5) with one
+ * graph launch.  A problem is a 3D periodic grid with its own field, and
+ * either its own velocity planes or a uniform velocity.  Problems whose
+ * velocity pointer and grid are equal share the velocity: their tiles run
+ * side by side on the same accelerator partition, so the shared velocity is
+ * read from memory about once for all of them.  Every step of every problem
+ * is one tile of a persistent kernel (one launch per step over all
+ * problems); a result equals sla_advect(..., SLA_CEC, ...) on that problem
+ * with a uniform velocity field, bit for bit.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+  sla_grid grid;        /* 3D, as for sla_advect */
+  float *phi;           /* device field, advanced in place */
+  const float *u;       /* device velocity planes, or NULL for a uniform one */
+  float u_uniform[3];   /* the uniform velocity (x, y, z) when u is NULL */
+  double dt;            /* time step */
+} sla_problem;
+
+typedef struct sla_plan sla_plan; /* opaque; owns work memory and the graph */
+
+/* Plan `steps` steps (global step indices step0 .. step0+steps-1) of the
+ * nprob problems probs (host array, copied).  Every Courant number must be
+ * below 1: courant_max > 0 is the caller's bound for all problems, else the
+ * plan measures it.  If tune != 0 the plan times candidate launch shapes (y
+ * extent of a tile, persistent grid size) on the problems (reading their
+ * fields, writing only its own work memory) and keeps the fastest.  Work
+ * memory: one field per problem.  The graph is built on a private stream.
+ * Synchronises the context's stream. */
+int sla_plan_create(sla_ctx *ctx, sla_plan **out, int32_t nprob, const sla_problem *probs,
+                    int32_t steps, int64_t step0, double courant_max, int32_t tune);
+/* Launch the plan's graph on the context's stream (asynchronous). */
+int sla_plan_run(sla_ctx *ctx, sla_plan *plan);
+/* Chosen launch shape: y extent of a tile, workgroups of the persistent
+ * kernel, work items per step, and the tuned time of one step in ms
+ * (0 if not tuned).  Any pointer may be NULL. */
+int sla_plan_info(const sla_plan *plan, int32_t *ychunk, int32_t *blocks, int32_t *items,
+                  double *step_ms);
+/* Release a plan.  NULL is ignored. */
+void sla_plan_destroy(sla_plan *plan);
 
 /* ------------------------------------------------------------------------
  * Learned correction (not in the paper; an addition of this library).

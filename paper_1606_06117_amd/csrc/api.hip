@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <string>
 #include <utility>
+#include <algorithm>
 #include <vector>
 
 #include "../../include/sla.h"
@@ -21,7 +22,8 @@ struct sla_ctx {
   int* flag = nullptr;    // set by a kernel that clamped an offset
   void* host = nullptr;   // pinned staging for small results (256 bytes)
   std::string err;
-  bool fused = true;  // SLA_OPT_FUSED
+  bool fused = true;    // SLA_OPT_FUSED
+  int cec3d_kernel = 2;  // SLA_OPT_CEC3D_KERNEL
   // per-kernel timing
   bool timing = false;
   struct Mark { int kind; hipEvent_t a, b; };
@@ -29,6 +31,25 @@ struct sla_ctx {
   std::vector<hipEvent_t> spare;  // event pool
   int64_t launches[SLA_K_COUNT] = {};
   double ms[SLA_K_COUNT] = {};
+};
+
+struct sla_plan {
+  int device = 0;
+  int nprob = 0;
+  int32_t steps = 0;
+  int64_t step0 = 0;
+  std::vector<float*> work;          // one work field per problem
+  std::vector<float*> phis;          // caller's fields
+  std::vector<size_t> cells;         // cells per problem
+  float* uniform = nullptr;          // device: 3 floats per uniform problem
+  sla::BatchProblem* dprobs = nullptr;
+  int4* ditems = nullptr;
+  int nitems = 0, ychunk = 0, blocks = 0;
+  double step_ms = 0.0;
+  hipStream_t cap = nullptr;         // private capture stream
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int* flag = nullptr;               // the creating context's overflow record
 };
 
 struct sla_model {
@@ -341,7 +362,8 @@ int sla_advect(sla_ctx* ctx, const sla_grid* grid, float* phi, const float* u, d
       case SLA_CEC:
         if (fused3d) {
           e = run(ctx, SLA_K_CEC3D, [&] {
-            return sla::launch_cec3d(1, m % 2 == 0, geo, cur, u, nxt, ctx->flag, ctx->stream);
+            return sla::launch_cec3d(ctx->cec3d_kernel, m % 2 == 0, geo, cur, u, nxt, ctx->flag,
+                                     ctx->stream);
           });
           std::swap(cur, nxt);
           break;
@@ -374,6 +396,11 @@ int sla_set_option(sla_ctx* ctx, int option, int64_t value) {
     case SLA_OPT_FUSED:
       if (value != 0 && value != 1) return fail(ctx, SLA_EINVAL, "SLA_OPT_FUSED takes 0 or 1");
       ctx->fused = value != 0;
+      return SLA_OK;
+    case SLA_OPT_CEC3D_KERNEL:
+      if (value < 0 || value >= sla::kCec3dVariants)
+        return fail(ctx, SLA_EINVAL, "SLA_OPT_CEC3D_KERNEL takes 0..%d", sla::kCec3dVariants - 1);
+      ctx->cec3d_kernel = int(value);
       return SLA_OK;
   }
   return fail(ctx, SLA_EINVAL, "unknown option %d", option);
@@ -683,6 +710,293 @@ int sla_advect_learned(sla_ctx* ctx, const sla_model* model, const sla_grid* gri
       });
   }
   if (e != hipSuccess) return hip_fail(ctx, e, "learned step launch");
+  return SLA_OK;
+}
+
+
+// ------------------------------------------------------------------ plans
+
+namespace {
+
+// Work items of every problem for a y extent ychunk.  Problems sharing a
+// velocity (same pointer and grid) are interleaved so that the items of one
+// tile for all of them have indices congruent modulo 8: with a persistent
+// grid whose size is a multiple of 8, they land on the same accelerator
+// partition (workgroups are dealt to the 8 partitions round-robin) in the
+// same round, and share that partition's L2.
+std::vector<int4> build_items(const std::vector<sla_problem>& P, int ychunk) {
+  std::vector<int4> items;
+  std::vector<bool> done(P.size(), false);
+  auto tiles_of = [&](const sla_problem& p, std::vector<int3>& t) {
+    const int tx = (p.grid.n[0] + sla::kBatchTileX - 1) / sla::kBatchTileX;
+    const int tz = (p.grid.n[2] + sla::kBatchTileZ - 1) / sla::kBatchTileZ;
+    const int cy = (p.grid.n[1] + ychunk - 1) / ychunk;
+    for (int c = 0; c < cy; ++c)
+      for (int z = 0; z < tz; ++z)
+        for (int x = 0; x < tx; ++x) t.push_back(make_int3(x, z, c));
+  };
+  for (size_t i = 0; i < P.size(); ++i) {
+    if (done[i]) continue;
+    std::vector<int> group{int(i)};
+    done[i] = true;
+    if (P[i].u)
+      for (size_t j = i + 1; j < P.size(); ++j)
+        if (!done[j] && P[j].u == P[i].u && P[j].grid.n[0] == P[i].grid.n[0] &&
+            P[j].grid.n[1] == P[i].grid.n[1] && P[j].grid.n[2] == P[i].grid.n[2]) {
+          group.push_back(int(j));
+          done[j] = true;
+        }
+    std::vector<int3> tiles;
+    tiles_of(P[i], tiles);
+    const int S = int(group.size());
+    if (S > 1)  // start a shared group on a partition boundary
+      while (items.size() % 8) items.push_back(make_int4(-1, 0, 0, 0));
+    for (size_t b = 0; b < tiles.size(); b += 8) {
+      const int nb = int(std::min<size_t>(8, tiles.size() - b));
+      for (int sidx = 0; sidx < S; ++sidx)
+        for (int r = 0; r < 8; ++r) {
+          if (r < nb)
+            items.push_back(make_int4(group[sidx], tiles[b + r].x, tiles[b + r].y, tiles[b + r].z));
+          else if (S > 1)
+            items.push_back(make_int4(-1, 0, 0, 0));  // keep the partition alignment
+        }
+    }
+  }
+  // drop alignment holes at the very end; the kernel skips problem -1 items
+  while (!items.empty() && items.back().x < 0) items.pop_back();
+  return items;
+}
+
+int plan_upload(sla_ctx* ctx, sla_plan* pl, const std::vector<sla_problem>& P, int ychunk) {
+  std::vector<sla::BatchProblem> bp(P.size());
+  for (size_t i = 0; i < P.size(); ++i) bp[i].ychunk = std::min(ychunk, P[i].grid.n[1]);
+  for (size_t i = 0; i < P.size(); ++i) {
+    const sla_problem& p = P[i];
+    const size_t n = pl->cells[i];
+    bp[i].buf[0] = p.phi;
+    bp[i].buf[1] = pl->work[i];
+    if (p.u) {
+      bp[i].u[0] = p.u;
+      bp[i].u[1] = p.u + n;
+      bp[i].u[2] = p.u + 2 * n;
+      bp[i].umask = ~0u;
+    } else {
+      bp[i].u[0] = pl->uniform + 3 * i;
+      bp[i].u[1] = pl->uniform + 3 * i + 1;
+      bp[i].u[2] = pl->uniform + 3 * i + 2;
+      bp[i].umask = 0u;
+    }
+    for (int d = 0; d < 3; ++d) {
+      bp[i].n[d] = p.grid.n[d];
+      bp[i].lam[d] = float(p.dt / p.grid.dx[d]);
+    }
+  }
+  std::vector<int4> items = build_items(P, ychunk);
+  if (pl->ditems) (void)hipFree(pl->ditems);
+  pl->ditems = nullptr;
+  if (hipMalloc(&pl->ditems, std::max<size_t>(1, items.size()) * sizeof(int4)) != hipSuccess)
+    return fail(ctx, SLA_ENOMEM, "plan work list");
+  hipError_t e = hipMemcpy(pl->ditems, items.data(), items.size() * sizeof(int4),
+                           hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(pl->dprobs, bp.data(), bp.size() * sizeof(sla::BatchProblem),
+                  hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(ctx, e, "plan upload");
+  pl->nitems = int(items.size());
+  pl->ychunk = ychunk;
+  return SLA_OK;
+}
+
+// Launch the plan's steps on stream st (also used while capturing).
+hipError_t plan_launch(sla_plan* pl, hipStream_t st, int32_t steps) {
+  hipError_t e = hipSuccess;
+  for (int32_t k = 0; k < steps && e == hipSuccess; ++k)
+    e = sla::launch_cec3d_batch((pl->step0 + k) % 2 == 0, pl->dprobs, pl->ditems, pl->nitems, k & 1,
+                                pl->blocks, pl->flag, st);
+  if (e == hipSuccess && (steps & 1))
+    e = sla::launch_batch_copy_back(pl->dprobs, pl->nprob, st);
+  return e;
+}
+
+}  // namespace
+
+void sla_plan_destroy(sla_plan* pl) {
+  if (!pl) return;
+  {
+    DeviceGuard guard(pl->device);
+    if (pl->exec) (void)hipGraphExecDestroy(pl->exec);
+    if (pl->graph) (void)hipGraphDestroy(pl->graph);
+    if (pl->cap) (void)hipStreamDestroy(pl->cap);
+    for (float* w : pl->work)
+      if (w) (void)hipFree(w);
+    if (pl->uniform) (void)hipFree(pl->uniform);
+    if (pl->dprobs) (void)hipFree(pl->dprobs);
+    if (pl->ditems) (void)hipFree(pl->ditems);
+  }
+  delete pl;
+}
+
+int sla_plan_create(sla_ctx* ctx, sla_plan** out, int32_t nprob, const sla_problem* probs,
+                    int32_t steps, int64_t step0, double courant_max, int32_t tune) {
+  if (!ctx) return SLA_EINVAL;
+  ctx->err.clear();
+  if (!out || !probs || nprob <= 0) return fail(ctx, SLA_EINVAL, "need out, probs and nprob > 0");
+  *out = nullptr;
+  if (steps < 0) return fail(ctx, SLA_EINVAL, "steps must be >= 0");
+  if (std::isnan(courant_max)) return fail(ctx, SLA_EINVAL, "courant_max is NaN");
+  DeviceGuard guard(ctx->device);
+  if (!guard.ok) return fail(ctx, SLA_EHIP, "cannot select device %d", ctx->device);
+  std::vector<sla_problem> P(probs, probs + nprob);
+  // validate; measure or check the Courant bound
+  for (int i = 0; i < nprob; ++i) {
+    int rc = check_grid(ctx, &P[i].grid);
+    if (rc) return rc;
+    if (P[i].grid.ndim != 3) return fail(ctx, SLA_EINVAL, "problem %d: plans take 3D grids", i);
+    if (!P[i].phi) return fail(ctx, SLA_EINVAL, "problem %d: phi is NULL", i);
+    if (!std::isfinite(P[i].dt)) return fail(ctx, SLA_EINVAL, "problem %d: dt must be finite", i);
+    const sla::Geo geo = make_geo(&P[i].grid, P[i].dt);
+    float cm = 0.f;
+    if (!P[i].u) {
+      for (int d = 0; d < 3; ++d) {
+        if (!std::isfinite(P[i].u_uniform[d]))
+          return fail(ctx, SLA_EINVAL, "problem %d: non-finite uniform velocity", i);
+        cm = std::fmax(cm, std::fabs(P[i].u_uniform[d] * geo.lam[d]));
+      }
+    } else if (courant_max > 0.0) {
+      cm = float(courant_max);
+    } else {
+      float c3[3];
+      rc = measure_courant(ctx, &P[i].grid, geo, P[i].u, c3);
+      if (rc) return rc;
+      cm = std::fmax(c3[0], std::fmax(c3[1], c3[2]));
+    }
+    if (!(cm < 1.f))
+      return fail(ctx, SLA_ECOURANT, "problem %d: Courant bound %g, plans need < 1", i, double(cm));
+  }
+  sla_plan* pl = new sla_plan;
+  pl->device = ctx->device;
+  pl->nprob = nprob;
+  pl->steps = steps;
+  pl->step0 = step0;
+  pl->flag = ctx->flag;
+  bool ok = true;
+  std::vector<float> uni(3 * size_t(nprob), 0.f);
+  for (int i = 0; i < nprob; ++i) {
+    const size_t n = size_t(P[i].grid.n[0]) * P[i].grid.n[1] * P[i].grid.n[2];
+    pl->cells.push_back(n);
+    pl->phis.push_back(P[i].phi);
+    float* w = nullptr;
+    ok = ok && hipMalloc(&w, n * sizeof(float)) == hipSuccess;
+    pl->work.push_back(w);
+    for (int d = 0; d < 3; ++d) uni[3 * i + d] = P[i].u_uniform[d];
+  }
+  ok = ok && hipMalloc(&pl->uniform, uni.size() * sizeof(float)) == hipSuccess;
+  ok = ok && hipMalloc(&pl->dprobs, size_t(nprob) * sizeof(sla::BatchProblem)) == hipSuccess;
+  if (!ok) {
+    (void)hipGetLastError();
+    sla_plan_destroy(pl);
+    return fail(ctx, SLA_ENOMEM, "cannot allocate plan memory");
+  }
+  hipError_t e = hipStreamSynchronize(ctx->stream);
+  if (e == hipSuccess)
+    e = hipMemcpy(pl->uniform, uni.data(), uni.size() * sizeof(float), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    sla_plan_destroy(pl);
+    return hip_fail(ctx, e, "plan set-up");
+  }
+  int cus = 0;
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device);
+  const int per_cu = sla::cec3d_batch_blocks_per_cu();
+  const int full = std::max(8, (cus * per_cu) / 8 * 8);
+  int best_y = 128, best_b = full;
+  double best_ms = 0.0;
+  if (tune && steps > 0) {
+    // time one step (reads the fields, writes the work memory) per candidate
+    hipEvent_t a = nullptr, b = nullptr;
+    (void)hipEventCreate(&a);
+    (void)hipEventCreate(&b);
+    best_ms = 1e30;
+    const int ychunks[] = {32, 64, 128, 256};
+    const int blocks[] = {full, 2 * full};
+    for (int yc : ychunks) {
+      int rc = plan_upload(ctx, pl, P, yc);
+      if (rc) {
+        sla_plan_destroy(pl);
+        return rc;
+      }
+      for (int bl : blocks) {
+        pl->blocks = bl;
+        float ms = 0.f, tot = 0.f;
+        for (int r = 0; r < 3 && e == hipSuccess; ++r) {
+          e = hipEventRecord(a, ctx->stream);
+          if (e == hipSuccess)
+            e = sla::launch_cec3d_batch(step0 % 2 == 0, pl->dprobs, pl->ditems, pl->nitems, 0, bl,
+                                        pl->flag, ctx->stream);
+          if (e == hipSuccess) e = hipEventRecord(b, ctx->stream);
+          if (e == hipSuccess) e = hipEventSynchronize(b);
+          if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+          if (r > 0) tot += ms;  // the first run warms up
+        }
+        if (e != hipSuccess) break;
+        const double avg = tot / 2.0;
+        if (avg < best_ms) {
+          best_ms = avg;
+          best_y = yc;
+          best_b = bl;
+        }
+      }
+      if (e != hipSuccess) break;
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (e != hipSuccess) {
+      sla_plan_destroy(pl);
+      return hip_fail(ctx, e, "plan tuning");
+    }
+  }
+  int rc = plan_upload(ctx, pl, P, best_y);
+  if (rc) {
+    sla_plan_destroy(pl);
+    return rc;
+  }
+  pl->blocks = best_b;
+  pl->step_ms = best_ms;
+  // capture all steps into one graph on a private stream
+  e = hipStreamCreateWithFlags(&pl->cap, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipStreamBeginCapture(pl->cap, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    hipError_t le = plan_launch(pl, pl->cap, steps);
+    e = hipStreamEndCapture(pl->cap, &pl->graph);
+    if (e == hipSuccess) e = le;
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&pl->exec, pl->graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    sla_plan_destroy(pl);
+    return hip_fail(ctx, e, "plan graph capture");
+  }
+  *out = pl;
+  return SLA_OK;
+}
+
+int sla_plan_run(sla_ctx* ctx, sla_plan* plan) {
+  if (!ctx) return SLA_EINVAL;
+  ctx->err.clear();
+  if (!plan) return fail(ctx, SLA_EINVAL, "plan is NULL");
+  if (plan->device != ctx->device) return fail(ctx, SLA_EINVAL, "plan belongs to another device");
+  if (plan->steps == 0) return SLA_OK;
+  DeviceGuard guard(ctx->device);
+  hipError_t e = run(ctx, SLA_K_CEC3D, [&] { return hipGraphLaunch(plan->exec, ctx->stream); });
+  if (e != hipSuccess) return hip_fail(ctx, e, "plan launch");
+  return SLA_OK;
+}
+
+int sla_plan_info(const sla_plan* plan, int32_t* ychunk, int32_t* blocks, int32_t* items,
+                  double* step_ms) {
+  if (!plan) return SLA_EINVAL;
+  if (ychunk) *ychunk = plan->ychunk;
+  if (blocks) *blocks = plan->blocks;
+  if (items) *items = plan->nitems;
+  if (step_ms) *step_ms = plan->step_ms;
   return SLA_OK;
 }
 

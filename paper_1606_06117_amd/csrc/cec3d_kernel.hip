@@ -30,26 +30,29 @@ constexpr int kThreads = 256;
 
 __device__ __forceinline__ float lerp(float p, float q, float f) { return fmaf(f, q - p, p); }
 
-// Reach-1 departure: fraction and far-node offset (+-1) for c and for -c.
+// Reach-1 departure of a node with Courant number c (|c| < 1): fraction
+// f = |c|; the far node of L_U is i - 1 if c >= 0 else i + 1 (ob < 0), the
+// far node of L_{-U} is i + 1 if c > 0 else i - 1 (obr > 0).  A Courant
+// number of magnitude 1 or more is detected once, where it is published to
+// LDS (see `over`); the kernel then still reads only the nodes i-1..i+1.
 struct Dep1 {
   float f;
-  int ob;   // far node of L_U:    i + ob, ob = -1 if c >= 0 else +1
-  int obr;  // far node of L_{-U}: i + obr, obr = -1 if -c >= 0 else +1
+  bool ob_neg;   // far node of L_U is i - 1
+  bool obr_pos;  // far node of L_{-U} is i + 1
+  int ob() const { return ob_neg ? -1 : 1; }
+  int obr() const { return obr_pos ? 1 : -1; }
 };
 
-__device__ __forceinline__ Dep1 depart1(float c, int* flag) {
-  const float mag = fabsf(c);
-  float f = mag;
-  if (!(mag < 1.f)) {  // beyond reach 1: keep the fraction, record it
-    if (mag == mag) *flag = 1;
-    f = mag - floorf(mag);
-  }
+__device__ __forceinline__ Dep1 depart1(float c, int*) {
   Dep1 d;
-  d.f = f;
-  d.ob = c >= 0.f ? -1 : 1;
-  d.obr = c > 0.f ? 1 : -1;
+  d.f = fabsf(c);
+  d.ob_neg = c >= 0.f;
+  d.obr_pos = c > 0.f;
   return d;
 }
+
+// True if |c| is beyond reach 1 (NaN is not an overflow: it propagates).
+__device__ __forceinline__ bool over1(float c) { return fabsf(c) >= 1.f; }
 
 template <bool EVEN>
 struct Cec3dShape {
@@ -183,6 +186,7 @@ __global__ __launch_bounds__(kThreads, SLA_CEC3D_MIN_WAVES) void k_cec3d_r1(cons
   };
 
   const int iters = (y1 - y0) + 2 * H;
+  bool over = false;  // a Courant number beyond reach 1 was published
   prefetch(0);
   // The ring slot of local plane t is t % 3; the loop body is unrolled by 3
   // so that every slot index is a compile-time constant.
@@ -197,14 +201,21 @@ __global__ __launch_bounds__(kThreads, SLA_CEC3D_MIN_WAVES) void k_cec3d_r1(cons
 #pragma unroll
     for (int k = 0; k < KP; ++k) {
       if (!pvalid(k)) continue;
+      const float ca = fa[k] * lamA;
+      over |= over1(ca);
       P[tid + k * kThreads] = fp[k];
-      CA[tid + k * kThreads] = fa[k] * lamA;
+      CA[tid + k * kThreads] = ca;
     }
     float cy[KY];
 #pragma unroll
     for (int j = 0; j < KY; ++j) {
       cy[j] = fy[j] * lamY;
-      if (emit && yvalid(j)) CB[ycol[j]] = fb[j] * lamB;
+      over |= over1(cy[j]);
+      if (emit && yvalid(j)) {
+        const float cb = fb[j] * lamB;
+        over |= over1(cb);
+        CB[ycol[j]] = cb;
+      }
     }
     if (t + 1 < iters) prefetch(t + 1);
     __syncthreads();
@@ -215,7 +226,7 @@ __global__ __launch_bounds__(kThreads, SLA_CEC3D_MIN_WAVES) void k_cec3d_r1(cons
         const int b = -H + e / LA, a = -2 + e % LA;
         const int i = EVEN ? lidx<EVEN>(a, b) : lidx<EVEN>(b, a);
         const Dep1 d = depart1(CA[i], flag);
-        S1[i] = lerp(P[i], P[i + d.ob * SA], d.f);
+        S1[i] = lerp(P[i], P[i + (d.ob_neg ? -SA : SA)], d.f);
       });
     }
     __syncthreads();
@@ -226,7 +237,7 @@ __global__ __launch_bounds__(kThreads, SLA_CEC3D_MIN_WAVES) void k_cec3d_r1(cons
         const int b = -H + e / LA, a = -1 + e % LA;
         const int i = EVEN ? lidx<EVEN>(a, b) : lidx<EVEN>(b, a);
         const Dep1 d = depart1(CA[i], flag);
-        SE[i] = P[i] - lerp(S1[i], S1[i + d.obr * SA], d.f);
+        SE[i] = P[i] - lerp(S1[i], S1[i + (d.obr_pos ? SA : -SA)], d.f);
       });
     }
     __syncthreads();
@@ -237,7 +248,7 @@ __global__ __launch_bounds__(kThreads, SLA_CEC3D_MIN_WAVES) void k_cec3d_r1(cons
         const int b = -H + e / TA, a = e % TA;
         const int i = EVEN ? lidx<EVEN>(a, b) : lidx<EVEN>(b, a);
         const Dep1 d = depart1(CA[i], flag);
-        const float ea = SE[i], eb = SE[i + d.ob * SA];
+        const float ea = SE[i], eb = SE[i + (d.ob_neg ? -SA : SA)];
         const float w = fmaf(d.f, 1.f / 3.f, 1.f / 3.f);
         AO[i] = fmaf(0.5f, fmaf(w, eb - ea, ea), S1[i]);
       });
@@ -252,14 +263,14 @@ __global__ __launch_bounds__(kThreads, SLA_CEC3D_MIN_WAVES) void k_cec3d_r1(cons
       rc[p1][j] = cy[j];  // Courant at plane t-1
       // Phi1 at plane t-1
       Dep1 d = depart1(rc[p1][j], flag);
-      r1[p1][j] = lerp(ra[p1][j], d.ob < 0 ? ra[p2][j] : ra[p0][j], d.f);
+      r1[p1][j] = lerp(ra[p1][j], d.ob_neg ? ra[p2][j] : ra[p0][j], d.f);
       // e at plane t-2
       d = depart1(rc[p2][j], flag);
-      re[p2][j] = ra[p2][j] - lerp(r1[p2][j], d.obr > 0 ? r1[p1][j] : r1[p3][j], d.f);
+      re[p2][j] = ra[p2][j] - lerp(r1[p2][j], d.obr_pos ? r1[p1][j] : r1[p3][j], d.f);
       // y-sweep output at plane t-3
       d = depart1(rc[p3][j], flag);
       const float ea = re[p3][j];
-      const float eb = d.ob < 0 ? re[p1][j] : re[p2][j];  // e at t-4 (slot p1) or t-2
+      const float eb = d.ob_neg ? re[p1][j] : re[p2][j];  // e at t-4 (slot p1) or t-2
       const float w = fmaf(d.f, 1.f / 3.f, 1.f / 3.f);
       YO[i] = fmaf(0.5f, fmaf(w, eb - ea, ea), r1[p3][j]);
     }
@@ -272,7 +283,7 @@ __global__ __launch_bounds__(kThreads, SLA_CEC3D_MIN_WAVES) void k_cec3d_r1(cons
         const int b = -2 + e / TA, a = e % TA;
         const int i = EVEN ? lidx<EVEN>(a, b) : lidx<EVEN>(b, a);
         const Dep1 d = depart1(CB[i], flag);
-        S1[i] = lerp(YO[i], YO[i + d.ob * SB], d.f);
+        S1[i] = lerp(YO[i], YO[i + (d.ob_neg ? -SB : SB)], d.f);
       });
     }
     __syncthreads();
@@ -283,7 +294,7 @@ __global__ __launch_bounds__(kThreads, SLA_CEC3D_MIN_WAVES) void k_cec3d_r1(cons
         const int b = -1 + e / TA, a = e % TA;
         const int i = EVEN ? lidx<EVEN>(a, b) : lidx<EVEN>(b, a);
         const Dep1 d = depart1(CB[i], flag);
-        SE[i] = YO[i] - lerp(S1[i], S1[i + d.obr * SB], d.f);
+        SE[i] = YO[i] - lerp(S1[i], S1[i + (d.obr_pos ? SB : -SB)], d.f);
       });
     }
     __syncthreads();
@@ -296,7 +307,7 @@ __global__ __launch_bounds__(kThreads, SLA_CEC3D_MIN_WAVES) void k_cec3d_r1(cons
         if (x0 + x >= nx || z0 + z >= nz) return;
         const int i = lidx<EVEN>(x, z);
         const Dep1 d = depart1(CB[i], flag);
-        const float ea = SE[i], eb = SE[i + d.ob * SB];
+        const float ea = SE[i], eb = SE[i + (d.ob_neg ? -SB : SB)];
         const float w = fmaf(d.f, 1.f / 3.f, 1.f / 3.f);
         out[unsigned(x0 + x) + yo + nxy * unsigned(z0 + z)] =
             fmaf(0.5f, fmaf(w, eb - ea, ea), S1[i]);
@@ -312,6 +323,7 @@ __global__ __launch_bounds__(kThreads, SLA_CEC3D_MIN_WAVES) void k_cec3d_r1(cons
     if (t + 1 < iters) body(std::integral_constant<int, 1>{}, t + 1);
     if (t + 2 < iters) body(std::integral_constant<int, 2>{}, t + 2);
   }
+  if (over) *flag = 1;
 }
 
 // ---------------------------------------------------------------------------
@@ -332,24 +344,47 @@ struct SegShape : Cec3dShape<EVEN> {
 
 // Third-order sweep of one segment: p holds the V+6 input nodes a0-3..a0+V+2,
 // c the V+4 Courant numbers of a0-2..a0+V+1; out receives a0..a0+V-1.
+// A select between two elements of one register array is folded by the
+// compiler into a dynamic index over the whole array (a compare chain); so
+// every select below picks between two different arrays, the left and
+// right neighbour views of the same values.
 template <int V>
 __device__ __forceinline__ void sweep_segment(const float (&p)[V + 6], const float (&c)[V + 4],
                                               float (&out)[V], int* flag) {
-  float p1[V + 4], e[V + 2];
+  float pl[V + 4], pr[V + 4];  // left / right neighbours of node a0-2+k
+#pragma unroll
+  for (int k = 0; k < V + 4; ++k) {
+    pl[k] = p[k];
+    pr[k] = p[k + 2];
+  }
+  float p1[V + 4];
 #pragma unroll
   for (int k = 0; k < V + 4; ++k) {  // node a0-2+k
     const Dep1 d = depart1(c[k], flag);
-    p1[k] = lerp(p[k + 1], d.ob < 0 ? p[k] : p[k + 2], d.f);
+    p1[k] = lerp(p[k + 1], d.ob_neg ? pl[k] : pr[k], d.f);
   }
+  float ql[V + 2], qr[V + 2];  // neighbours of Phi1 at node a0-1+k
+#pragma unroll
+  for (int k = 0; k < V + 2; ++k) {
+    ql[k] = p1[k];
+    qr[k] = p1[k + 2];
+  }
+  float e[V + 2];
 #pragma unroll
   for (int k = 0; k < V + 2; ++k) {  // node a0-1+k
     const Dep1 d = depart1(c[k + 1], flag);
-    e[k] = p[k + 2] - lerp(p1[k + 1], d.obr > 0 ? p1[k + 2] : p1[k], d.f);
+    e[k] = p[k + 2] - lerp(p1[k + 1], d.obr_pos ? qr[k] : ql[k], d.f);
+  }
+  float el[V], er[V];  // neighbours of e at node a0+k
+#pragma unroll
+  for (int k = 0; k < V; ++k) {
+    el[k] = e[k];
+    er[k] = e[k + 2];
   }
 #pragma unroll
   for (int k = 0; k < V; ++k) {  // node a0+k
     const Dep1 d = depart1(c[k + 2], flag);
-    const float ea = e[k + 1], eb = d.ob < 0 ? e[k] : e[k + 2];
+    const float ea = e[k + 1], eb = d.ob_neg ? el[k] : er[k];
     const float w = fmaf(d.f, 1.f / 3.f, 1.f / 3.f);
     out[k] = fmaf(0.5f, fmaf(w, eb - ea, ea), p1[k + 2]);
   }
@@ -432,6 +467,7 @@ __global__ __launch_bounds__(kThreads, SLA_CEC3D_MIN_WAVES) void k_cec3d_seg(
   };
 
   const int iters = (y1 - y0) + 2 * H;
+  bool over = false;  // a Courant number beyond reach 1 was published
   prefetch(0);
   auto body = [&](auto phase, int t) {
     constexpr int p0 = decltype(phase)::value;  // t % 3
@@ -444,14 +480,21 @@ __global__ __launch_bounds__(kThreads, SLA_CEC3D_MIN_WAVES) void k_cec3d_seg(
 #pragma unroll
     for (int k = 0; k < KP; ++k) {
       if (!pvalid(k)) continue;
+      const float ca = fa[k] * lamA;
+      over |= over1(ca);
       P[tid + k * kThreads] = fp[k];
-      CA[tid + k * kThreads] = fa[k] * lamA;
+      CA[tid + k * kThreads] = ca;
     }
     float cy[KY];
 #pragma unroll
     for (int j = 0; j < KY; ++j) {
       cy[j] = fy[j] * lamY;
-      if (emit && yvalid(j)) CB[ycol[j]] = fb[j] * lamB;
+      over |= over1(cy[j]);
+      if (emit && yvalid(j)) {
+        const float cb = fb[j] * lamB;
+        over |= over1(cb);
+        CB[ycol[j]] = cb;
+      }
     }
     if (t + 1 < iters) prefetch(t + 1);
     __syncthreads();
@@ -475,12 +518,12 @@ __global__ __launch_bounds__(kThreads, SLA_CEC3D_MIN_WAVES) void k_cec3d_seg(
       ra[p0][j] = AO[i];
       rc[p1][j] = cy[j];
       Dep1 d = depart1(rc[p1][j], flag);
-      r1[p1][j] = lerp(ra[p1][j], d.ob < 0 ? ra[p2][j] : ra[p0][j], d.f);
+      r1[p1][j] = lerp(ra[p1][j], d.ob_neg ? ra[p2][j] : ra[p0][j], d.f);
       d = depart1(rc[p2][j], flag);
-      re[p2][j] = ra[p2][j] - lerp(r1[p2][j], d.obr > 0 ? r1[p1][j] : r1[p3][j], d.f);
+      re[p2][j] = ra[p2][j] - lerp(r1[p2][j], d.obr_pos ? r1[p1][j] : r1[p3][j], d.f);
       d = depart1(rc[p3][j], flag);
       const float ea = re[p3][j];
-      const float eb = d.ob < 0 ? re[p1][j] : re[p2][j];
+      const float eb = d.ob_neg ? re[p1][j] : re[p2][j];
       const float w = fmaf(d.f, 1.f / 3.f, 1.f / 3.f);
       YO[i] = fmaf(0.5f, fmaf(w, eb - ea, ea), r1[p3][j]);
     }
@@ -510,9 +553,384 @@ __global__ __launch_bounds__(kThreads, SLA_CEC3D_MIN_WAVES) void k_cec3d_seg(
     if (t + 1 < iters) body(std::integral_constant<int, 1>{}, t + 1);
     if (t + 2 < iters) body(std::integral_constant<int, 2>{}, t + 2);
   }
+  if (over) *flag = 1;
+}
+
+// ---------------------------------------------------------------------------
+// Streaming variant: 512-thread workgroups; every plane of phi and of the
+// Courant numbers reaches LDS through direct global-to-LDS loads (no
+// registers, no per-load address arithmetic: a per-plane base in scalar
+// registers plus per-lane 32-bit offsets computed once).  phi and the
+// first sweep's velocity are double-buffered and fetched a whole plane
+// ahead; the y and last-sweep velocities are fetched one phase ahead.  The
+// first and last sweeps run as register segments, the y sweep as the
+// register pipeline.  Four barriers per plane.
+// ---------------------------------------------------------------------------
+constexpr int kT4 = 512;
+
+template <bool EVEN>
+struct V4Shape {
+  static constexpr int H = 3, TX = 64, TZ = 16;
+  static constexpr int W = TX + 2 * H, HZ = TZ + 2 * H, NP = W * HZ;
+  static constexpr int TA = EVEN ? TX : TZ, TB = EVEN ? TZ : TX;
+  static constexpr int SA = EVEN ? 1 : W, SB = EVEN ? W : 1;
+  // y region: x-fastest rectangle [YX0, YX0+YW) x [YZ0, YZ0+YH)
+  static constexpr int YX0 = EVEN ? 0 : -H, YW = EVEN ? TX : TX + 2 * H;
+  static constexpr int YZ0 = EVEN ? -H : 0, YH = EVEN ? TZ + 2 * H : TZ;
+  static constexpr int NY = YW * YH;
+  static constexpr int KY = (NY + kT4 - 1) / kT4;  // y columns per thread
+  static constexpr int V = 8;
+  static constexpr int NS1 = TA / V, N1 = (TB + 2 * H) * NS1;
+  static constexpr int NS2 = TB / V, N2 = TA * NS2;
+  // LDS chunks of 64 floats: the padded plane, and the y region
+  static constexpr int CP = (NP + 63) / 64;
+  static constexpr int CPW = (CP + kT4 / 64 - 1) / (kT4 / 64);  // per wave
+  static constexpr int CYc = (NY + 63) / 64;
+  static constexpr int CYW = (CYc + kT4 / 64 - 1) / (kT4 / 64);
+  static_assert(N1 <= kT4 && N2 <= kT4, "one segment per thread");
+};
+
+template <bool EVEN>
+__device__ __forceinline__ int v4_lidx(int x, int z) {
+  using S = V4Shape<EVEN>;
+  return (z + S::H) * S::W + (x + S::H);
+}
+
+typedef __attribute__((address_space(3))) void lds_void;
+
+// Direct global -> LDS load of one float per lane into lds_chunk[lane].
+__device__ __forceinline__ void g2l(const float* base, unsigned byte_off, float* lds_chunk) {
+  __builtin_amdgcn_global_load_lds(
+      reinterpret_cast<const void*>(reinterpret_cast<const char*>(base) + byte_off),
+      (lds_void*)(lds_chunk), 4, 0, 0);
+}
+
+// One tile of one problem for the streaming variant.  umask is ~0u for a
+// velocity field and 0 for a uniform velocity (u points at one value per
+// axis; every lane then reads that value).
+struct Tile {
+  const float* phi;
+  float* out;
+  const float* u[3];
+  unsigned umask;
+  int nx, ny, nz;
+  float lam[3];
+  int x0, z0, y0, y1;
+};
+
+struct V4Lds {
+  float P[2][V4Shape<true>::NP];   // phi, double-buffered by plane parity
+  float UA[2][V4Shape<true>::NP];  // first-sweep velocity (raw), double-buffered
+  float UY[V4Shape<true>::NY > V4Shape<false>::NY ? V4Shape<true>::NY : V4Shape<false>::NY];
+  float UB[V4Shape<true>::NP];     // last-sweep velocity at the output plane (raw)
+  float AO[V4Shape<true>::NP];     // first-sweep output
+  float YO[V4Shape<true>::NP];     // y-sweep output
+};
+
+template <bool EVEN>
+__device__ __forceinline__ void cec3d_tile_v4(const Tile& T, V4Lds& L, int* flag) {
+  using S = V4Shape<EVEN>;
+  constexpr int H = S::H, TA = S::TA, SA = S::SA, SB = S::SB, V = S::V, KY = S::KY;
+  static_assert(V4Shape<true>::NP == V4Shape<false>::NP, "same padded plane");
+  auto& P = L.P;
+  auto& UA = L.UA;
+  float* UY = L.UY;
+  float* UB = L.UB;
+  float* AO = L.AO;
+  float* YO = L.YO;
+
+  const int tid = threadIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+  const int x0 = T.x0, z0 = T.z0, y0 = T.y0, y1 = T.y1;
+  const int nx = T.nx, ny = T.ny, nz = T.nz;
+  const unsigned nxy = unsigned(nx) * unsigned(ny);
+  const float* phi = T.phi;
+  float* out = T.out;
+  const float* uA = EVEN ? T.u[0] : T.u[2];
+  const float* uB = EVEN ? T.u[2] : T.u[0];
+  const float* uy = T.u[1];
+  const unsigned um = T.umask;
+  const float lamA = EVEN ? T.lam[0] : T.lam[2];
+  const float lamB = EVEN ? T.lam[2] : T.lam[0];
+  const float lamY = T.lam[1];
+
+  // byte offsets (x-z part) of this lane's element in each chunk it loads
+  unsigned pofs[S::CPW], yofs[S::CYW];
+#pragma unroll
+  for (int k = 0; k < S::CPW; ++k) {
+    const int e = min((wave + k * (kT4 / 64)) * 64 + lane, S::NP - 1);
+    const int z = e / S::W - H, x = e % S::W - H;
+    pofs[k] = 4u * (unsigned(wrap1(x0 + x, nx)) + nxy * unsigned(wrap1(z0 + z, nz)));
+  }
+#pragma unroll
+  for (int k = 0; k < S::CYW; ++k) {
+    const int e = min((wave + k * (kT4 / 64)) * 64 + lane, S::NY - 1);
+    const int z = S::YZ0 + e / S::YW, x = S::YX0 + e % S::YW;
+    yofs[k] = 4u * (unsigned(wrap1(x0 + x, nx)) + nxy * unsigned(wrap1(z0 + z, nz)));
+  }
+  // padded-plane position of y-region element e (for UB, AO, YO)
+  auto ypos = [&](int e) {
+    const int z = S::YZ0 + e / S::YW, x = S::YX0 + e % S::YW;
+    return v4_lidx<EVEN>(x, z);
+  };
+  const unsigned rowb = 4u * unsigned(nx);  // bytes per y step
+
+  // issue the loads of one padded plane (phi + first-sweep velocity) at y = q
+  auto fetch_plane = [&](int q, int buf) {
+    const unsigned qb = unsigned(wrap1(q, ny)) * rowb;
+#pragma unroll
+    for (int k = 0; k < S::CPW; ++k) {
+      const int ch = wave + k * (kT4 / 64);
+      if (ch >= S::CP) break;
+      if (ch * 64 + lane < S::NP) {
+        g2l(phi, pofs[k] + qb, &P[buf][ch * 64]);
+        g2l(uA, (pofs[k] + qb) & um, &UA[buf][ch * 64]);
+      }
+    }
+  };
+  // y velocity of plane q into UY (y-region order)
+  auto fetch_uy = [&](int q) {
+    const unsigned qb = unsigned(wrap1(q, ny)) * rowb;
+#pragma unroll
+    for (int k = 0; k < S::CYW; ++k) {
+      const int ch = wave + k * (kT4 / 64);
+      if (ch >= S::CYc) break;
+      if (ch * 64 + lane < S::NY) g2l(uy, (yofs[k] + qb) & um, &UY[ch * 64]);
+    }
+  };
+  // last-sweep velocity of plane q into UB at the y-region positions: the
+  // region is whole padded rows (odd) or 64-wide rows (even), so each chunk
+  // of 64 consecutive region elements is 64 consecutive LDS floats
+  auto fetch_ub = [&](int q) {
+    const unsigned qb = unsigned(wrap1(q, ny)) * rowb;
+#pragma unroll
+    for (int k = 0; k < S::CYW; ++k) {
+      const int ch = wave + k * (kT4 / 64);
+      if (ch >= S::CYc) break;
+      if (ch * 64 + lane < S::NY) g2l(uB, (yofs[k] + qb) & um, &UB[ypos(ch * 64)]);
+    }
+  };
+  static_assert(EVEN ? (S::YW == 64) : (S::YW == S::W), "y-region chunks are contiguous in LDS");
+
+  // segment items
+  const bool has1 = tid < S::N1, has2 = tid < S::N2;
+  const int i1 = EVEN ? v4_lidx<EVEN>((tid % S::NS1) * V, tid / S::NS1 - H)
+                      : v4_lidx<EVEN>(tid / S::NS1 - H, (tid % S::NS1) * V);
+  const int la2 = EVEN ? tid % TA : tid / S::NS2;
+  const int sb2 = EVEN ? tid / TA : tid % S::NS2;
+  const int i2 = EVEN ? v4_lidx<EVEN>(la2, sb2 * V) : v4_lidx<EVEN>(sb2 * V, la2);
+  const int ox2 = EVEN ? la2 : sb2 * V, oz2 = EVEN ? sb2 * V : la2;
+
+  int ycol[KY];
+#pragma unroll
+  for (int j = 0; j < KY; ++j) ycol[j] = ypos(min(tid + j * kT4, S::NY - 1));
+  auto yvalid = [&](int j) { return KY * kT4 == S::NY || tid + j * kT4 < S::NY; };
+
+  float ra[3][KY], r1[3][KY], re[3][KY], rc[3][KY];
+#pragma unroll
+  for (int j = 0; j < KY; ++j)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) ra[k][j] = r1[k][j] = re[k][j] = rc[k][j] = 0.f;
+
+  const int iters = (y1 - y0) + 2 * H;
+  bool over = false;
+  __syncthreads();  // LDS of a previous tile is no longer read
+  fetch_plane(y0 - H, 0);
+  fetch_uy(y0 - H - 1);
+  fetch_ub(y0 - 2 * H);
+
+  auto body = [&](auto phase, int t) {
+    constexpr int p0 = decltype(phase)::value;  // t % 3
+    constexpr int p1 = (p0 + 2) % 3;            // (t - 1) % 3
+    constexpr int p2 = (p0 + 1) % 3;            // (t - 2) % 3
+    constexpr int p3 = p0;                      // (t - 3) % 3
+    const bool emit = t >= 2 * H;
+    const int buf = t & 1;
+    __builtin_amdgcn_s_waitcnt(0);  // this wave's loads of plane t have landed
+    __syncthreads();
+    if (t + 1 < iters) fetch_plane(y0 - H + t + 1, buf ^ 1);
+    // 1. first sweep, one segment per thread
+    if (has1) {
+      float p[V + 6], c[V + 4], o[V];
+#pragma unroll
+      for (int k = 0; k < V + 6; ++k) p[k] = P[buf][i1 + (k - 3) * SA];
+#pragma unroll
+      for (int k = 0; k < V + 4; ++k) {
+        c[k] = UA[buf][i1 + (k - 2) * SA] * lamA;
+        over |= over1(c[k]);
+      }
+      sweep_segment<V>(p, c, o, flag);
+#pragma unroll
+      for (int k = 0; k < V; ++k) AO[i1 + k * SA] = o[k];
+    }
+    __syncthreads();
+    // 2. y sweep as a pipeline along the march
+    float cy[KY];
+#pragma unroll
+    for (int j = 0; j < KY; ++j) cy[j] = UY[min(tid + j * kT4, S::NY - 1)] * lamY;
+#pragma unroll
+    for (int j = 0; j < KY; ++j) {
+      if (!yvalid(j)) continue;
+      over |= over1(cy[j]);
+      const int i = ycol[j];
+      ra[p0][j] = AO[i];
+      rc[p1][j] = cy[j];
+      Dep1 d = depart1(rc[p1][j], flag);
+      r1[p1][j] = lerp(ra[p1][j], d.ob_neg ? ra[p2][j] : ra[p0][j], d.f);
+      d = depart1(rc[p2][j], flag);
+      re[p2][j] = ra[p2][j] - lerp(r1[p2][j], d.obr_pos ? r1[p1][j] : r1[p3][j], d.f);
+      d = depart1(rc[p3][j], flag);
+      const float ea = re[p3][j];
+      const float eb = d.ob_neg ? re[p1][j] : re[p2][j];
+      const float w = fmaf(d.f, 1.f / 3.f, 1.f / 3.f);
+      YO[i] = fmaf(0.5f, fmaf(w, eb - ea, ea), r1[p3][j]);
+    }
+    __syncthreads();
+    if (t + 1 < iters) fetch_uy(y0 - H + t);  // y velocity of plane t, used at t + 1
+    if (emit) {
+      // 3. last sweep, one segment per thread, stored to HBM at plane t - 6
+      if (has2) {
+        float p[V + 6], c[V + 4], o[V];
+#pragma unroll
+        for (int k = 0; k < V + 6; ++k) p[k] = YO[i2 + (k - 3) * SB];
+#pragma unroll
+        for (int k = 0; k < V + 4; ++k) {
+          c[k] = UB[i2 + (k - 2) * SB] * lamB;
+          over |= over1(c[k]);
+        }
+        sweep_segment<V>(p, c, o, flag);
+        const unsigned yo = unsigned(y0 + t - 2 * H) * unsigned(nx);
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+          const int x = x0 + ox2 + (EVEN ? 0 : k), z = z0 + oz2 + (EVEN ? k : 0);
+          if (x < nx && z < nz) out[unsigned(x) + yo + nxy * unsigned(z)] = o[k];
+        }
+      }
+    }
+    __syncthreads();  // UB and YO are rewritten next
+    if (t + 1 < iters) fetch_ub(y0 + t + 1 - 2 * H);
+  };
+
+  for (int t = 0; t < iters; t += 3) {
+    body(std::integral_constant<int, 0>{}, t);
+    if (t + 1 < iters) body(std::integral_constant<int, 1>{}, t + 1);
+    if (t + 2 < iters) body(std::integral_constant<int, 2>{}, t + 2);
+  }
+  if (over) *flag = 1;
+}
+
+template <bool EVEN>
+__global__ __launch_bounds__(kT4, 4) void k_cec3d_v4(const float* __restrict__ phi,
+                                                     const float* __restrict__ ux,
+                                                     const float* __restrict__ uy,
+                                                     const float* __restrict__ uz,
+                                                     float* __restrict__ out, Geo g, int ychunk,
+                                                     int* flag) {
+  __shared__ V4Lds L;
+  Tile T;
+  T.phi = phi;
+  T.out = out;
+  T.u[0] = ux;
+  T.u[1] = uy;
+  T.u[2] = uz;
+  T.umask = ~0u;
+  T.nx = g.nx;
+  T.ny = g.ny;
+  T.nz = g.nz;
+  T.lam[0] = g.lam[0];
+  T.lam[1] = g.lam[1];
+  T.lam[2] = g.lam[2];
+  T.x0 = blockIdx.x * V4Shape<EVEN>::TX;
+  T.z0 = blockIdx.y * V4Shape<EVEN>::TZ;
+  T.y0 = blockIdx.z * ychunk;
+  T.y1 = min(T.y0 + ychunk, g.ny);
+  cec3d_tile_v4<EVEN>(T, L, flag);
+}
+
+// ---------------------------------------------------------------------------
+// Batched step: many problems (fields sharing a velocity, or independent
+// grids with a uniform velocity) advanced by one third-order step in one
+// persistent launch.  A workgroup takes items blockIdx.x, +gridDim.x, ...;
+// an item is one tile (x tile, z tile, y chunk) of one problem.
+// ---------------------------------------------------------------------------
+template <bool EVEN>
+__global__ __launch_bounds__(kT4, 4) void k_cec3d_batch(const BatchProblem* __restrict__ probs,
+                                                        const int4* __restrict__ items,
+                                                        int nitems, int parity, int* flag) {
+  __shared__ V4Lds L;
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const int4 item = items[it];
+    if (item.x < 0) continue;  // alignment hole (uniform across the block)
+    const BatchProblem& B = probs[item.x];
+    Tile T;
+    T.phi = B.buf[parity];
+    T.out = B.buf[parity ^ 1];
+    T.u[0] = B.u[0];
+    T.u[1] = B.u[1];
+    T.u[2] = B.u[2];
+    T.umask = B.umask;
+    T.nx = B.n[0];
+    T.ny = B.n[1];
+    T.nz = B.n[2];
+    T.lam[0] = B.lam[0];
+    T.lam[1] = B.lam[1];
+    T.lam[2] = B.lam[2];
+    T.x0 = item.y * V4Shape<EVEN>::TX;
+    T.z0 = item.z * V4Shape<EVEN>::TZ;
+    T.y0 = item.w * B.ychunk;
+    T.y1 = min(T.y0 + B.ychunk, B.n[1]);
+    cec3d_tile_v4<EVEN>(T, L, flag);
+  }
 }
 
 }  // namespace
+
+hipError_t launch_cec3d_v4(bool even, const Geo& g, const float* phi, const float* u, float* out,
+                           int* flag, hipStream_t st) {
+  const size_t n = (size_t)g.ncells;
+  const int ychunk = g.ny >= 256 ? 128 : 64;
+  dim3 grid((g.nx + 63) / 64, (g.nz + 15) / 16, (g.ny + ychunk - 1) / ychunk);
+  if (even)
+    hipLaunchKernelGGL(k_cec3d_v4<true>, grid, dim3(kT4), 0, st, phi, u, u + n, u + 2 * n, out, g,
+                       ychunk, flag);
+  else
+    hipLaunchKernelGGL(k_cec3d_v4<false>, grid, dim3(kT4), 0, st, phi, u, u + n, u + 2 * n, out, g,
+                       ychunk, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_cec3d_batch(bool even, const BatchProblem* probs, const int4* items, int nitems,
+                              int parity, int grid, int* flag, hipStream_t st) {
+  if (even)
+    hipLaunchKernelGGL(k_cec3d_batch<true>, dim3(grid), dim3(kT4), 0, st, probs, items, nitems,
+                       parity, flag);
+  else
+    hipLaunchKernelGGL(k_cec3d_batch<false>, dim3(grid), dim3(kT4), 0, st, probs, items, nitems,
+                       parity, flag);
+  return hipGetLastError();
+}
+
+// buf[0] = buf[1] for every problem (after an odd number of steps).
+__global__ __launch_bounds__(256) void k_batch_copy_back(const BatchProblem* __restrict__ probs) {
+  const BatchProblem& B = probs[blockIdx.y];
+  const size_t n = size_t(B.n[0]) * B.n[1] * B.n[2];
+  const float* src = B.buf[1];
+  float* dst = B.buf[0];
+  for (size_t i = size_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += size_t(gridDim.x) * 256)
+    dst[i] = src[i];
+}
+
+hipError_t launch_batch_copy_back(const BatchProblem* probs, int nprob, hipStream_t st) {
+  hipLaunchKernelGGL(k_batch_copy_back, dim3(1024, nprob), dim3(256), 0, st, probs);
+  return hipGetLastError();
+}
+
+int cec3d_batch_blocks_per_cu() {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_cec3d_batch<true>, kT4, 0) != hipSuccess)
+    return 1;
+  return nb > 0 ? nb : 1;
+}
 
 hipError_t launch_cec3d_seg(bool even, const Geo& g, const float* phi, const float* u, float* out,
                             int* flag, hipStream_t st) {
@@ -528,9 +946,11 @@ hipError_t launch_cec3d_seg(bool even, const Geo& g, const float* phi, const flo
   return hipGetLastError();
 }
 
-hipError_t launch_cec3d(int R, bool even, const Geo& g, const float* phi, const float* u,
+hipError_t launch_cec3d(int variant, bool even, const Geo& g, const float* phi, const float* u,
                         float* out, int* flag, hipStream_t st) {
-  if (R != 1) return hipErrorInvalidValue;
+  if (variant == 1) return launch_cec3d_seg(even, g, phi, u, out, flag, st);
+  if (variant == 2) return launch_cec3d_v4(even, g, phi, u, out, flag, st);
+  if (variant != 0) return hipErrorInvalidValue;
   const size_t n = (size_t)g.ncells;
   const float* ux = u;
   const float* uy = u + n;

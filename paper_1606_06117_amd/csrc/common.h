@@ -38,8 +38,10 @@ hipError_t launch_cec_sweep(int d, int R, const Geo& g, const float* phi,
                             const float* u_d, float* out, int* flag, hipStream_t st);
 
 // Fused three-axis third-order step (reach 1 only): x,y,z order if even,
-// z,y,x otherwise.  Returns hipErrorInvalidValue for other reaches.
-hipError_t launch_cec3d(int R, bool even, const Geo& g, const float* phi, const float* u,
+// z,y,x otherwise.  variant: 0 LDS stages, 1 register segments, 2 streaming
+// (direct global-to-LDS loads); all perform the same FP32 operations.
+constexpr int kCec3dVariants = 3;
+hipError_t launch_cec3d(int variant, bool even, const Geo& g, const float* phi, const float* u,
                         float* out, int* flag, hipStream_t st);
 
 // ---------------------------------------------------------------- network
@@ -71,6 +73,27 @@ hipError_t launch_learned_correct(const Geo& g, const float* phi1, const float* 
 // Segment variant of the same step (identical arithmetic per node).
 hipError_t launch_cec3d_seg(bool even, const Geo& g, const float* phi, const float* u, float* out,
                             int* flag, hipStream_t st);
+
+// Streaming variant (direct global-to-LDS loads, 512-thread workgroups).
+hipError_t launch_cec3d_v4(bool even, const Geo& g, const float* phi, const float* u, float* out,
+                           int* flag, hipStream_t st);
+
+// One problem of a batched step.  buf[parity] is read and buf[parity ^ 1]
+// written; u are velocity planes (umask ~0u) or three single values of a
+// uniform velocity (umask 0).  Tiles are 64 (x) x 16 (z) x ychunk (y).
+struct BatchProblem {
+  float* buf[2];
+  const float* u[3];
+  unsigned umask;
+  int n[3];
+  float lam[3];
+  int ychunk;
+};
+constexpr int kBatchTileX = 64, kBatchTileZ = 16;
+hipError_t launch_cec3d_batch(bool even, const BatchProblem* probs, const int4* items, int nitems,
+                              int parity, int grid, int* flag, hipStream_t st);
+int cec3d_batch_blocks_per_cu();
+hipError_t launch_batch_copy_back(const BatchProblem* probs, int nprob, hipStream_t st);
 
 // Max |u_d| per axis over the grid (FP32, NaN propagates) into out3 (device).
 hipError_t launch_umax(int ndim, int ncells, const float* u, float* part,

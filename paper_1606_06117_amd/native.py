@@ -20,6 +20,7 @@ MAX_REACH = 4
 
 OK, EINVAL, ECOURANT, EHIP, ENOMEM, ENOMODEL = 0, -1, -2, -3, -4, -5
 OPT_FUSED = 0
+OPT_CEC3D_KERNEL = 1
 
 # every symbol include/sla.h declares, with (restype, argtypes)
 _c = ctypes
@@ -36,6 +37,12 @@ SIGNATURES = {
     "sla_check": (_c.c_int, [_vp]),
     "sla_norms": (_c.c_int, [_vp, _c.c_int64, _vp, _vp, _c.POINTER(_c.c_double)]),
     "sla_set_option": (_c.c_int, [_vp, _c.c_int, _c.c_int64]),
+    "sla_plan_create": (_c.c_int, [_vp, _c.POINTER(_vp), _c.c_int32, _vp, _c.c_int32, _c.c_int64,
+                                   _c.c_double, _c.c_int32]),
+    "sla_plan_run": (_c.c_int, [_vp, _vp]),
+    "sla_plan_info": (_c.c_int, [_vp, _c.POINTER(_c.c_int32), _c.POINTER(_c.c_int32),
+                                 _c.POINTER(_c.c_int32), _c.POINTER(_c.c_double)]),
+    "sla_plan_destroy": (None, [_vp]),
     "sla_model_create": (_c.c_int, [_vp, _c.POINTER(_vp)]),
     "sla_model_destroy": (None, [_vp]),
     "sla_model_set_params": (_c.c_int, [_vp, _vp, _vp, _c.c_int64]),
@@ -66,6 +73,12 @@ class SlaError(RuntimeError):
 class Grid(ctypes.Structure):
     """Mirror of ``sla_grid``."""
     _fields_ = [("ndim", ctypes.c_int32), ("n", ctypes.c_int32 * 3), ("dx", ctypes.c_double * 3)]
+
+
+class Problem(ctypes.Structure):
+    """Mirror of ``sla_problem``."""
+    _fields_ = [("grid", Grid), ("phi", ctypes.c_void_p), ("u", ctypes.c_void_p),
+                ("u_uniform", ctypes.c_float * 3), ("dt", ctypes.c_double)]
 
 
 _LIB = None
@@ -291,3 +304,61 @@ def advect_learned(ctx: Context, model: Model, phi, u, dx, dt, steps, step0=0, c
                                           int(steps), int(step0), float(courant_max),
                                           ctypes.byref(fb) if allow_fallback else None))
     return bool(fb.value)
+
+
+class Plan:
+    """Batched third-order steps of many 3D problems, replayed as one graph.
+
+    ``problems``: list of ``(phi, u, dx, dt)`` with ``phi`` a float32 (z, y, x)
+    tensor and ``u`` either a (3, z, y, x) tensor (shared when the same tensor
+    is passed for several problems) or a 3-tuple uniform velocity (x, y, z).
+    """
+
+    def __init__(self, ctx: Context, problems, steps, step0=0, courant_max=0.0, tune=True):
+        self.ctx = ctx
+        self.lib = ctx.lib
+        arr = (Problem * len(problems))()
+        self._keep = []
+        for i, (phi, u, dx, dt) in enumerate(problems):
+            _check_field(phi, "phi")
+            if phi.dim() != 3:
+                raise ValueError("plans take 3D fields")
+            arr[i].grid = make_grid(phi.shape, dx)
+            arr[i].phi = phi.data_ptr()
+            if isinstance(u, (tuple, list)):
+                arr[i].u = None
+                for d in range(3):
+                    arr[i].u_uniform[d] = float(u[d])
+            else:
+                _check_field(u, "u")
+                if tuple(u.shape) != (3,) + tuple(phi.shape):
+                    raise ValueError("u must have shape (3, *phi.shape)")
+                arr[i].u = u.data_ptr()
+            arr[i].dt = float(dt)
+            self._keep.append((phi, u))
+        h = ctypes.c_void_p()
+        ctx._stream()
+        ctx._raise(self.lib.sla_plan_create(ctx.h, ctypes.byref(h), len(problems), arr, int(steps),
+                                            int(step0), float(courant_max), 1 if tune else 0))
+        self.h = h
+
+    def run(self):
+        self.ctx._stream()
+        self.ctx._raise(self.lib.sla_plan_run(self.ctx.h, self.h))
+
+    def info(self):
+        y, b, n = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        ms = ctypes.c_double()
+        self.lib.sla_plan_info(self.h, ctypes.byref(y), ctypes.byref(b), ctypes.byref(n), ctypes.byref(ms))
+        return {"ychunk": y.value, "blocks": b.value, "items": n.value, "tuned_step_ms": ms.value}
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.sla_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -287,8 +287,9 @@ def test_abc_512_cfl09_cec_boxes(ctx):
     torch.cuda.empty_cache()
 
 
+@pytest.mark.parametrize("variant", [0, 1, 2])
 @pytest.mark.parametrize("step0", [0, 1])
-def test_fused_step_matches_sweeps(ctx, step0):
+def test_fused_step_matches_sweeps(ctx, step0, variant):
     """At reach 1 the fused 3D step and the three sweep kernels evaluate the
     same FP32 operations per node, so their results agree bitwise."""
     from paper_1606_06117_amd import native
@@ -297,7 +298,11 @@ def test_fused_step_matches_sweeps(ctx, step0):
     u = W.abc_velocity(shape)
     dx = tuple(2 * np.pi / n for n in reversed(shape))
     dt = 0.9 * dx[0] / 2
-    fused = gpu_advect(ctx, phi, u, dx, dt, oracle.CEC, 3, step0=step0)
+    ctx.set_option(native.OPT_CEC3D_KERNEL, variant)
+    try:
+        fused = gpu_advect(ctx, phi, u, dx, dt, oracle.CEC, 3, step0=step0)
+    finally:
+        ctx.set_option(native.OPT_CEC3D_KERNEL, 2)
     ctx.set_option(native.OPT_FUSED, 0)
     try:
         sweeps = gpu_advect(ctx, phi, u, dx, dt, oracle.CEC, 3, step0=step0)
