@@ -64,6 +64,10 @@ def measured_traffic(kind: str, workload: str):
     entry = data.get(workload, {}).get(kind)
     if not entry or entry.get("source_sha256_16") != source_hash(kind):
         return None
+    if kind == "cec3d":
+        from paper_1606_06117_amd import native
+        if entry.get("variant") != native.CEC3D_DEFAULT:
+            return None  # counters of another implementation of the fused step
     return entry.get("bytes_per_launch")
 
 
@@ -153,6 +157,60 @@ def learned_section(ctx, size, fields, steps_per_field, cells, iters, batch, lr)
     return out
 
 
+def batch_section(ctx, size, scalars, ngrids, steps):
+    """Batched workload: ``scalars`` fields on a size^3 grid sharing one ABC
+    velocity, plus ``ngrids`` cubic grids of uneven sizes 32^3..192^3 with
+    their own uniform velocities, all at CFL 0.9, advanced by ``steps``
+    third-order steps as one tuned plan (one graph launch)."""
+    import torch
+    from paper_1606_06117_amd import native
+    from paper_1606_06117_amd import workloads as W
+    dev = torch.device("cuda:0")
+    shape = (size,) * 3
+    dx = (2 * math.pi / size,) * 3
+    dt = W.abc_dt(shape, 0.9)
+    u = torch.from_numpy(W.abc_velocity(shape)).to(dev)
+    probs = [(W.fourier_modes_torch(shape, 3000 + s, dev), u, dx, dt) for s in range(scalars)]
+    sizes, vels = W.uneven_grids(count=ngrids)
+    for gi, (n, v) in enumerate(zip(sizes, vels)):
+        dxg = (2 * math.pi / n,) * 3
+        dtg = 0.9 * dxg[0] / float(max(abs(v)))
+        probs.append((W.fourier_modes_torch((n, n, n), 3200 + gi, dev), tuple(float(a) for a in v), dxg, dtg))
+    cells_shared = scalars * size**3
+    cells_uniform = sum(n**3 for n in sizes)
+    t0 = time.perf_counter()
+    plan = native.Plan(ctx, probs, steps, step0=0, courant_max=0.9, tune=True)
+    setup = time.perf_counter() - t0
+    plan.run()  # warm-up replay
+    torch.cuda.synchronize()
+    ctx.timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.run()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ctx.timing(False)
+    ctx.check()
+    updates = (cells_shared + cells_uniform) * steps
+    # algorithmic bytes: shared fields read/write phi (8 B) and share one
+    # read of the velocity (12 B per grid cell); uniform grids move phi only
+    alg = steps * (cells_shared * 8 + size**3 * 12 + cells_uniform * 8)
+    info = plan.info()
+    plan.close()
+    return {
+        "workload": f"{scalars} scalars on {size}^3 sharing one ABC velocity + {ngrids} uniform-velocity "
+                    f"grids of {min(sizes)}^3..{max(sizes)}^3 ({cells_uniform / 1e6:.0f} M cells), CFL 0.9, "
+                    f"{steps} third-order steps in one graph launch",
+        "value": updates / wall / 1e9,
+        "unit": "Gcell-updates/s",
+        "seconds": wall,
+        "hbm_frac": alg / wall / (HBM_PEAK_GBS * 1e9),
+        "algorithmic_bytes_per_cell_update": alg / updates,
+        "plan": info,
+        "plan_setup_seconds": setup,
+    }
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -166,6 +224,10 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--path", choices=["auto", "sweeps"], default="auto",
                     help="auto: fused step where the library has one; sweeps: one kernel per axis")
+    ap.add_argument("--batch", choices=["on", "off"], default="on",
+                    help="also run the batched workload (16 x 512^3 + 64 uneven grids)")
+    ap.add_argument("--batch-scalars", type=int, default=16)
+    ap.add_argument("--batch-grids", type=int, default=64)
     ap.add_argument("--learned", choices=["on", "off"], default="on",
                     help="also train and evaluate the learned correction (256^3)")
     ap.add_argument("--learned-size", type=int, default=256)
@@ -280,10 +342,14 @@ def main(argv=None):
         "roofline": roofline,
     }
 
+    del phi_d, u_d
+    torch.cuda.empty_cache()
+    if args.batch == "on":
+        print("[bench] batched workload ...", file=sys.stderr, flush=True)
+        out["batch"] = batch_section(ctx, args.size, args.batch_scalars, args.batch_grids, args.steps)
+        torch.cuda.empty_cache()
     if args.learned == "on":
         print("[bench] learned correction: pairs, training, evaluation ...", file=sys.stderr, flush=True)
-        del phi_d, u_d
-        torch.cuda.empty_cache()
         out["learned"] = learned_section(ctx, args.learned_size, args.learned_fields, args.learned_steps,
                                          args.learned_cells, args.learned_iters, 65536, 2e-3)
 

@@ -124,8 +124,8 @@ typedef enum {
    * perform the same FP32 operations per node. */
   SLA_OPT_FUSED = 0,
   /* Which implementation runs the fused step (same FP32 operations, same
-   * results): 0 LDS stages, 1 register segments, 2 streaming (direct
-   * global-to-LDS loads, default). */
+   * results): 0 LDS stages, 1 register segments (default), 2 streaming
+   * (direct global-to-LDS loads).  The batched plans always use 2. */
   SLA_OPT_CEC3D_KERNEL = 1
 } sla_option;
 /* Set option `option` to `value`.  Returns SLA_EINVAL for an unknown option
@@ -203,7 +203,9 @@ void sla_plan_destroy(sla_plan *plan);
  * step.  Network: h1 = relu(x W1 + b1), h2 = relu(h1 W2 + b2),
  * y = h2 w3 + b3 (30 -> 64 -> 64 -> 1), run on the matrix cores with BF16
  * weights and activations and FP32 accumulation.  Corrected value:
- * Phi1[i] + sigma * y.  Training target: (third-order step - Phi1) / sigma;
+ * Phi1[i] + sigma * y, limited to [min, max] of the 27 values Phi1[i+o]
+ * (the step cannot raise the maximum norm of the field, whatever the
+ * network outputs).  Training target: (third-order step - Phi1) / sigma;
  * loss: mean squared error; optimiser: Adam on FP32 master weights.
  *
  * Parameter vector (FP32, SLA_MLP_PARAMS values): W1 (32 x 64 row-major,

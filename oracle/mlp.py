@@ -10,8 +10,11 @@ Features of node i (30 used, padded to 32):
                                        z outermost, x innermost (d_13 = 0)
     sigma = sqrt(sum_k d_k^2 / 27 + 1e-30)
     x_k = d_k / sigma (k < 27),  x_27..29 = c_x, c_y, c_z,  x_30 = x_31 = 0
-The network predicts y; the corrected value is Phi1[i] + sigma * y.  The
-training target is (Phi_third_order[i] - Phi1[i]) / sigma.  Differences make
+The network predicts y; the corrected value is Phi1[i] + sigma * y, limited
+to [min, max] of the 27 values Phi1[i + o_k] (so a step never leaves the
+range of the CIR field around the node, and the maximum norm of the field
+cannot grow whatever the network outputs).  The training target is
+(Phi_third_order[i] - Phi1[i]) / sigma (not limited).  Differences make
 the prediction invariant to adding a constant to Phi, and the sigma scaling
 makes it linear in the scale of Phi, as the true correction is.
 
@@ -137,4 +140,16 @@ def learned_step(phi, c, flat_params):
     X, sigma = features(phi1, c, cells)
     X = bf16_round(X.astype(np.float32)).astype(np.float64)
     y, _ = forward(params, X)
-    return (phi1.ravel() + sigma * y).reshape(phi1.shape)
+    lo, hi = neighbourhood_range(phi1)
+    return np.clip(phi1.ravel() + sigma * y, lo.ravel(), hi.ravel()).reshape(phi1.shape)
+
+
+def neighbourhood_range(phi1):
+    """Minimum and maximum of the 27 values around every node (periodic)."""
+    lo = np.asarray(phi1, dtype=np.float64).copy()
+    hi = lo.copy()
+    for dz, dy, dx in offsets27():
+        v = np.roll(phi1, (-dz, -dy, -dx), axis=(0, 1, 2))
+        lo = np.minimum(lo, v)
+        hi = np.maximum(hi, v)
+    return lo, hi

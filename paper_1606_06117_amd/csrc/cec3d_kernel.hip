@@ -102,6 +102,21 @@ __device__ __forceinline__ int wrap1(int v, int n) {
   return v >= n ? v - n : v;
 }
 
+// Tile (x tile, z tile, y chunk) of this workgroup.  Workgroups are handed
+// to the 8 XCDs round robin in launch order; with swz set, XCD k takes a
+// contiguous range of the tile space instead (x fastest, then z, then the y
+// chunk), so the tiles whose halos overlap run on the same XCD and share
+// its L2.
+__device__ __forceinline__ int3 block_tile(int swz) {
+  if (!swz) return make_int3(blockIdx.x, blockIdx.y, blockIdx.z);
+  const unsigned gx = gridDim.x, gy = gridDim.y;
+  const unsigned n = gx * gy * gridDim.z;
+  const unsigned L = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+  const unsigned xcd = L % 8u, q = n / 8u, r = n % 8u;
+  const unsigned lg = xcd * q + min(xcd, r) + L / 8u;
+  return make_int3(int(lg % gx), int((lg / gx) % gy), int(lg / (gx * gy)));
+}
+
 // Minimum waves per SIMD the compiler must leave room for (register budget).
 #ifndef SLA_CEC3D_MIN_WAVES
 #define SLA_CEC3D_MIN_WAVES 2
@@ -113,7 +128,7 @@ __global__ __launch_bounds__(kThreads, SLA_CEC3D_MIN_WAVES) void k_cec3d_r1(cons
                                                        const float* __restrict__ uy,
                                                        const float* __restrict__ uz,
                                                        float* __restrict__ out, Geo g,
-                                                       int ychunk, int* flag) {
+                                                       int ychunk, int swz, int* flag) {
   using S = Cec3dShape<EVEN>;
   constexpr int H = S::H, TA = S::TA, TB = S::TB, SA = S::SA, SB = S::SB;
   constexpr int KP = S::KP, KY = S::KY;
@@ -126,8 +141,9 @@ __global__ __launch_bounds__(kThreads, SLA_CEC3D_MIN_WAVES) void k_cec3d_r1(cons
   __shared__ float YO[S::NP];  // y-sweep output (last-sweep input)
 
   const int tid = threadIdx.x;
-  const int x0 = blockIdx.x * S::TX, z0 = blockIdx.y * S::TZ;
-  const int y0 = blockIdx.z * ychunk;
+  const int3 bt = block_tile(swz);
+  const int x0 = bt.x * S::TX, z0 = bt.y * S::TZ;
+  const int y0 = bt.z * ychunk;
   const int y1 = min(y0 + ychunk, g.ny);
   const int nx = g.nx, ny = g.ny, nz = g.nz;
   const unsigned nxy = unsigned(nx) * unsigned(ny);
@@ -393,7 +409,7 @@ __device__ __forceinline__ void sweep_segment(const float (&p)[V + 6], const flo
 template <bool EVEN>
 __global__ __launch_bounds__(kThreads, SLA_CEC3D_MIN_WAVES) void k_cec3d_seg(
     const float* __restrict__ phi, const float* __restrict__ ux, const float* __restrict__ uy,
-    const float* __restrict__ uz, float* __restrict__ out, Geo g, int ychunk, int* flag) {
+    const float* __restrict__ uz, float* __restrict__ out, Geo g, int ychunk, int swz, int* flag) {
   using S = SegShape<EVEN>;
   constexpr int H = S::H, TA = S::TA, SA = S::SA, SB = S::SB, V = S::V;
   constexpr int KP = S::KP, KY = S::KY;
@@ -404,8 +420,9 @@ __global__ __launch_bounds__(kThreads, SLA_CEC3D_MIN_WAVES) void k_cec3d_seg(
   __shared__ float YO[S::NP];  // y-sweep output (last-sweep input)
 
   const int tid = threadIdx.x;
-  const int x0 = blockIdx.x * S::TX, z0 = blockIdx.y * S::TZ;
-  const int y0 = blockIdx.z * ychunk;
+  const int3 bt = block_tile(swz);
+  const int x0 = bt.x * S::TX, z0 = bt.y * S::TZ;
+  const int y0 = bt.z * ychunk;
   const int y1 = min(y0 + ychunk, g.ny);
   const int nx = g.nx, ny = g.ny, nz = g.nz;
   const unsigned nxy = unsigned(nx) * unsigned(ny);
@@ -824,7 +841,7 @@ __global__ __launch_bounds__(kT4, 4) void k_cec3d_v4(const float* __restrict__ p
                                                      const float* __restrict__ ux,
                                                      const float* __restrict__ uy,
                                                      const float* __restrict__ uz,
-                                                     float* __restrict__ out, Geo g, int ychunk,
+                                                     float* __restrict__ out, Geo g, int ychunk, int swz,
                                                      int* flag) {
   __shared__ V4Lds L;
   Tile T;
@@ -840,9 +857,10 @@ __global__ __launch_bounds__(kT4, 4) void k_cec3d_v4(const float* __restrict__ p
   T.lam[0] = g.lam[0];
   T.lam[1] = g.lam[1];
   T.lam[2] = g.lam[2];
-  T.x0 = blockIdx.x * V4Shape<EVEN>::TX;
-  T.z0 = blockIdx.y * V4Shape<EVEN>::TZ;
-  T.y0 = blockIdx.z * ychunk;
+  const int3 bt = block_tile(swz);
+  T.x0 = bt.x * V4Shape<EVEN>::TX;
+  T.z0 = bt.y * V4Shape<EVEN>::TZ;
+  T.y0 = bt.z * ychunk;
   T.y1 = min(T.y0 + ychunk, g.ny);
   cec3d_tile_v4<EVEN>(T, L, flag);
 }
@@ -886,16 +904,16 @@ __global__ __launch_bounds__(kT4, 4) void k_cec3d_batch(const BatchProblem* __re
 }  // namespace
 
 hipError_t launch_cec3d_v4(bool even, const Geo& g, const float* phi, const float* u, float* out,
-                           int* flag, hipStream_t st) {
+                           int* flag, hipStream_t st, Cec3dLaunch lc) {
   const size_t n = (size_t)g.ncells;
-  const int ychunk = g.ny >= 256 ? 128 : 64;
+  const int ychunk = lc.ychunk > 0 ? lc.ychunk : cec3d_default_ychunk(g);
   dim3 grid((g.nx + 63) / 64, (g.nz + 15) / 16, (g.ny + ychunk - 1) / ychunk);
   if (even)
     hipLaunchKernelGGL(k_cec3d_v4<true>, grid, dim3(kT4), 0, st, phi, u, u + n, u + 2 * n, out, g,
-                       ychunk, flag);
+                       ychunk, lc.swizzle, flag);
   else
     hipLaunchKernelGGL(k_cec3d_v4<false>, grid, dim3(kT4), 0, st, phi, u, u + n, u + 2 * n, out, g,
-                       ychunk, flag);
+                       ychunk, lc.swizzle, flag);
   return hipGetLastError();
 }
 
@@ -933,36 +951,43 @@ int cec3d_batch_blocks_per_cu() {
 }
 
 hipError_t launch_cec3d_seg(bool even, const Geo& g, const float* phi, const float* u, float* out,
-                            int* flag, hipStream_t st) {
+                            int* flag, hipStream_t st, Cec3dLaunch lc) {
   const size_t n = (size_t)g.ncells;
-  const int ychunk = g.ny >= 256 ? 128 : 64;
+  const int ychunk = lc.ychunk > 0 ? lc.ychunk : cec3d_default_ychunk(g);
   dim3 grid((g.nx + 63) / 64, (g.nz + 15) / 16, (g.ny + ychunk - 1) / ychunk);
   if (even)
     hipLaunchKernelGGL(k_cec3d_seg<true>, grid, dim3(kThreads), 0, st, phi, u, u + n, u + 2 * n,
-                       out, g, ychunk, flag);
+                       out, g, ychunk, lc.swizzle, flag);
   else
     hipLaunchKernelGGL(k_cec3d_seg<false>, grid, dim3(kThreads), 0, st, phi, u, u + n, u + 2 * n,
-                       out, g, ychunk, flag);
+                       out, g, ychunk, lc.swizzle, flag);
   return hipGetLastError();
 }
 
+// 64 planes per workgroup unless that leaves fewer than 1024 workgroups
+// (four per CU), then 32.
+int cec3d_default_ychunk(const Geo& g) {
+  const long long tiles = (long long)((g.nx + 63) / 64) * ((g.nz + 15) / 16);
+  return tiles * ((g.ny + 63) / 64) >= 1024 ? 64 : 32;
+}
+
 hipError_t launch_cec3d(int variant, bool even, const Geo& g, const float* phi, const float* u,
-                        float* out, int* flag, hipStream_t st) {
-  if (variant == 1) return launch_cec3d_seg(even, g, phi, u, out, flag, st);
-  if (variant == 2) return launch_cec3d_v4(even, g, phi, u, out, flag, st);
+                        float* out, int* flag, hipStream_t st, Cec3dLaunch lc) {
+  if (variant == 1) return launch_cec3d_seg(even, g, phi, u, out, flag, st, lc);
+  if (variant == 2) return launch_cec3d_v4(even, g, phi, u, out, flag, st, lc);
   if (variant != 0) return hipErrorInvalidValue;
   const size_t n = (size_t)g.ncells;
   const float* ux = u;
   const float* uy = u + n;
   const float* uz = u + 2 * n;
-  const int ychunk = g.ny >= 256 ? 128 : 64;
+  const int ychunk = lc.ychunk > 0 ? lc.ychunk : cec3d_default_ychunk(g);
   dim3 grid((g.nx + 63) / 64, (g.nz + 15) / 16, (g.ny + ychunk - 1) / ychunk);
   if (even)
     hipLaunchKernelGGL(k_cec3d_r1<true>, grid, dim3(kThreads), 0, st, phi, ux, uy, uz, out, g,
-                       ychunk, flag);
+                       ychunk, lc.swizzle, flag);
   else
     hipLaunchKernelGGL(k_cec3d_r1<false>, grid, dim3(kThreads), 0, st, phi, ux, uy, uz, out, g,
-                       ychunk, flag);
+                       ychunk, lc.swizzle, flag);
   return hipGetLastError();
 }
 

@@ -41,8 +41,15 @@ hipError_t launch_cec_sweep(int d, int R, const Geo& g, const float* phi,
 // z,y,x otherwise.  variant: 0 LDS stages, 1 register segments, 2 streaming
 // (direct global-to-LDS loads); all perform the same FP32 operations.
 constexpr int kCec3dVariants = 3;
+// Launch shape: y planes per workgroup (0: the default for the grid) and
+// whether tiles are mapped to XCDs in contiguous ranges (1) or round robin.
+struct Cec3dLaunch {
+  int ychunk = 0;
+  int swizzle = 1;
+};
+int cec3d_default_ychunk(const Geo& g);
 hipError_t launch_cec3d(int variant, bool even, const Geo& g, const float* phi, const float* u,
-                        float* out, int* flag, hipStream_t st);
+                        float* out, int* flag, hipStream_t st, Cec3dLaunch lc = Cec3dLaunch());
 
 // ---------------------------------------------------------------- network
 constexpr int kMlpInputs = 32;   // 27 differences + 3 Courant numbers + 2 zero
@@ -50,6 +57,7 @@ constexpr int kMlpHidden = 64;
 constexpr int kMlpParams = kMlpInputs * kMlpHidden + kMlpHidden + kMlpHidden * kMlpHidden +
                            kMlpHidden + kMlpHidden + 1;
 constexpr int kMlpMaxBlocks = 512;  // training blocks (gradient partials)
+constexpr int kLearnedBlocks = 1024;  // workgroups of a learned-step launch (each loads the weights once)
 constexpr int kMlpPackElems = kMlpHidden * kMlpInputs + 2 * kMlpHidden * kMlpHidden;
 
 size_t mlp_train_lds();
@@ -72,11 +80,11 @@ hipError_t launch_learned_correct(const Geo& g, const float* phi1, const float* 
 
 // Segment variant of the same step (identical arithmetic per node).
 hipError_t launch_cec3d_seg(bool even, const Geo& g, const float* phi, const float* u, float* out,
-                            int* flag, hipStream_t st);
+                            int* flag, hipStream_t st, Cec3dLaunch lc = Cec3dLaunch());
 
 // Streaming variant (direct global-to-LDS loads, 512-thread workgroups).
 hipError_t launch_cec3d_v4(bool even, const Geo& g, const float* phi, const float* u, float* out,
-                           int* flag, hipStream_t st);
+                           int* flag, hipStream_t st, Cec3dLaunch lc = Cec3dLaunch());
 
 // One problem of a batched step.  buf[parity] is read and buf[parity ^ 1]
 // written; u are velocity planes (umask ~0u) or three single values of a

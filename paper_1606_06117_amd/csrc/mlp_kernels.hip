@@ -16,6 +16,8 @@
 // (hidden x cells), so a lane's four results are four consecutive hidden
 // units of one cell and land in a row-major LDS tile as one 8-byte store.
 
+#include <algorithm>
+
 #include "common.h"
 
 namespace sla {
@@ -59,6 +61,14 @@ __device__ __forceinline__ float sum4g(float v) {
   v += __shfl_xor(v, 16);
   v += __shfl_xor(v, 32);
   return v;
+}
+__device__ __forceinline__ float min4g(float v) {
+  v = fminf(v, __shfl_xor(v, 16));
+  return fminf(v, __shfl_xor(v, 32));
+}
+__device__ __forceinline__ float max4g(float v) {
+  v = fmaxf(v, __shfl_xor(v, 16));
+  return fmaxf(v, __shfl_xor(v, 32));
 }
 
 // Weights in LDS: W1T [n][k] (64 x 32), W2T [n][k] (64 x 64), W2R [k][n]
@@ -418,6 +428,7 @@ struct NodeFeatures {
   bf16x8 x;
   float sigma;
   float centre;
+  float lo, hi;  // range of the 27 values around the node
 };
 
 __device__ __forceinline__ NodeFeatures node_features(const float* __restrict__ phi1,
@@ -430,7 +441,7 @@ __device__ __forceinline__ NodeFeatures node_features(const float* __restrict__ 
   const size_t ic = (size_t)z * plane + (size_t)y * nx + x;
   const float centre = phi1[ic];
   float d[8];
-  float ss = 0.f;
+  float ss = 0.f, lo = centre, hi = centre;
 #pragma unroll
   for (int v = 0; v < 8; ++v) {
     const int k = 8 * g + v;
@@ -441,7 +452,10 @@ __device__ __forceinline__ NodeFeatures node_features(const float* __restrict__ 
       xx = xx < 0 ? xx + nx : (xx >= nx ? xx - nx : xx);
       yy = yy < 0 ? yy + ny : (yy >= ny ? yy - ny : yy);
       zz = zz < 0 ? zz + nz : (zz >= nz ? zz - nz : zz);
-      d[v] = phi1[(size_t)zz * plane + (size_t)yy * nx + xx] - centre;
+      const float val = phi1[(size_t)zz * plane + (size_t)yy * nx + xx];
+      lo = fminf(lo, val);
+      hi = fmaxf(hi, val);
+      d[v] = val - centre;
       ss = fmaf(d[v], d[v], ss);
     }
   }
@@ -449,6 +463,8 @@ __device__ __forceinline__ NodeFeatures node_features(const float* __restrict__ 
   NodeFeatures f;
   f.sigma = sqrtf(ss / 27.f + 1e-30f);
   f.centre = centre;
+  f.lo = min4g(lo);
+  f.hi = max4g(hi);
   const float inv = 1.f / f.sigma;
 #pragma unroll
   for (int v = 0; v < 8; ++v) f.x[v] = (__bf16)(d[v] * inv);
@@ -488,9 +504,11 @@ __global__ __launch_bounds__(kThreads) void k_make_pairs(const float* __restrict
   }
 }
 
-// Learned step, second half: out = Phi1 + sigma * net(features).  A block
-// covers 32 (x) x 4 (y) nodes of one z plane; wave w takes row y0 + w as two
-// tiles of 16 nodes.
+// Learned step, second half: out = Phi1 + sigma * net(features), limited to
+// the range of the 27 values around the node.  A wave tile is 32 nodes of
+// one x row (two MFMA tiles of 16); the waves of the grid take the tiles
+// w, w + W, ... (W waves in all), so every workgroup loads the weights into
+// LDS once.
 struct InferLds {
   WeightsLds W;
   __bf16 h1[4][32 * NH];
@@ -509,28 +527,38 @@ __global__ __launch_bounds__(kThreads) void k_learned_correct(const float* __res
   load_weights(L.W, wpack, wr, false);
   __syncthreads();
   const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15, w = threadIdx.x >> 6;
-  const int y = min(blockIdx.y * 4 + w, geo.ny - 1);  // rows past the end repeat the last one
-  const int z = blockIdx.z;
-  bf16x8 xb[2];
-  float sig[2], cen[2];
-  int xs[2];
+  const int nxb = (geo.nx + 31) / 32;
+  const int tiles = nxb * geo.ny * geo.nz;
+  const int nwaves = gridDim.x * (kThreads / 64);
+  for (int t = blockIdx.x * (kThreads / 64) + w; t < tiles; t += nwaves) {
+    const int xb0 = (t % nxb) * 32;
+    const int row = t / nxb;
+    const int y = row % geo.ny, z = row / geo.ny;
+    bf16x8 xb[2];
+    float sig[2], cen[2], lo[2], hi[2];
+    int xs[2];
 #pragma unroll
-  for (int jt = 0; jt < 2; ++jt) {
-    xs[jt] = blockIdx.x * 32 + 16 * jt + c;
-    const int x = min(xs[jt], geo.nx - 1);
-    const NodeFeatures f = node_features(phi1, ux, uy, uz, geo, x, y, z, g);
-    xb[jt] = f.x;
-    sig[jt] = f.sigma;
-    cen[jt] = f.centre;
+    for (int jt = 0; jt < 2; ++jt) {
+      xs[jt] = xb0 + 16 * jt + c;
+      const int x = min(xs[jt], geo.nx - 1);  // lanes past the end repeat the last node
+      const NodeFeatures f = node_features(phi1, ux, uy, uz, geo, x, y, z, g);
+      xb[jt] = f.x;
+      sig[jt] = f.sigma;
+      cen[jt] = f.centre;
+      lo[jt] = f.lo;
+      hi[jt] = f.hi;
+    }
+    floatx4 h2[4][2];
+    float yv[2];
+    forward_tile(L.W, xb, L.h1[w], h2, yv);
+    if (g == 0) {
+#pragma unroll
+      for (int jt = 0; jt < 2; ++jt)
+        if (xs[jt] < geo.nx)
+          out[(size_t)z * geo.nx * geo.ny + (size_t)y * geo.nx + xs[jt]] =
+              fminf(fmaxf(fmaf(sig[jt], yv[jt], cen[jt]), lo[jt]), hi[jt]);
+    }
   }
-  floatx4 h2[4][2];
-  float yv[2];
-  forward_tile(L.W, xb, L.h1[w], h2, yv);
-  if (g != 0 || blockIdx.y * 4 + w >= geo.ny) return;
-#pragma unroll
-  for (int jt = 0; jt < 2; ++jt)
-    if (xs[jt] < geo.nx)
-      out[(size_t)z * geo.nx * geo.ny + (size_t)y * geo.nx + xs[jt]] = fmaf(sig[jt], yv[jt], cen[jt]);
 }
 
 }  // namespace
@@ -600,8 +628,9 @@ hipError_t launch_learned_correct(const Geo& g, const float* phi1, const float* 
                                   const float* wr, float* out, hipStream_t st) {
   const size_t n = (size_t)g.ncells;
   const int bytes = int(sizeof(InferLds));
-  dim3 grid((g.nx + 31) / 32, (g.ny + 3) / 4, g.nz);
-  hipLaunchKernelGGL(k_learned_correct, grid, dim3(kThreads), bytes, st, phi1, u, u + n, u + 2 * n,
+  const long long wave_tiles = (long long)((g.nx + 31) / 32) * g.ny * g.nz;
+  const int blocks = int(std::min<long long>((wave_tiles + 3) / 4, kLearnedBlocks));
+  hipLaunchKernelGGL(k_learned_correct, dim3(blocks), dim3(kThreads), bytes, st, phi1, u, u + n, u + 2 * n,
                      g, static_cast<const __bf16*>(wpack), wr, out);
   return hipGetLastError();
 }

@@ -101,6 +101,39 @@ def cellular_velocity_2d(shape, amp=1.0, dtype=np.float32):
     return u
 
 
+def _fourier_parts(shape, seed, kmax):
+    rng = np.random.default_rng(seed)
+    nz, ny, nx = shape
+    ks = np.arange(kmax)
+    kz, ky, kx = np.meshgrid(ks, ks, ks, indexing="ij")
+    g = rng.standard_normal((kmax, kmax, kmax))
+    ph = rng.uniform(0.0, TWO_PI, (kmax, kmax, kmax))
+    amp = g / (1.0 + kx**2 + ky**2 + kz**2)
+    amp[0, 0, 0] = 0.0
+    a = amp * np.exp(1j * ph)
+    ex = np.exp(1j * np.outer(ks, node_coords(nx, TWO_PI)))
+    ey = np.exp(1j * np.outer(ks, node_coords(ny, TWO_PI)))
+    ez = np.exp(1j * np.outer(node_coords(nz, TWO_PI), ks))
+    A = np.einsum("zyk,kx->zyx", a, ex)
+    B = np.einsum("zkx,ky->zyx", A, ey)
+    return ez, B.reshape(kmax, ny * nx)
+
+
+def fourier_modes_torch(shape, seed, device, kmax=8):
+    """``fourier_modes`` with its final mode sum done in FP64 by torch on
+    ``device``; returns an FP32 torch tensor (same recipe and seed)."""
+    import torch
+    nz, ny, nx = shape
+    ez, Bf = _fourier_parts(shape, seed, kmax)
+    er = torch.from_numpy(np.ascontiguousarray(ez.real)).to(device)
+    ei = torch.from_numpy(np.ascontiguousarray(ez.imag)).to(device)
+    br = torch.from_numpy(np.ascontiguousarray(Bf.real)).to(device)
+    bi = torch.from_numpy(np.ascontiguousarray(Bf.imag)).to(device)
+    out = (er @ br - ei @ bi).reshape(nz, ny, nx)
+    out /= torch.sqrt(torch.mean(out * out))
+    return out.to(torch.float32).contiguous()
+
+
 def fourier_modes(shape, seed, kmax=8, dtype=np.float32):
     """Smooth random field with ``kmax`` modes per axis (3D), unit RMS."""
     rng = np.random.default_rng(seed)

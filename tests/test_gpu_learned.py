@@ -240,3 +240,51 @@ def test_training_reduces_loss(ctx):
     print(f"training loss {first:.4e} -> {last:.4e}")
     assert last < 0.5 * first
     model.close()
+
+
+@pytest.mark.parametrize("b3", [1.0e3, -1.0e3])
+def test_learned_step_limited_to_neighbourhood(ctx, b3):
+    """A network with a huge output gives exactly the maximum (minimum) of the
+    27 CIR values around each node: the limiter, checked on the GPU's own
+    CIR field (a max/min of FP32 values is exact)."""
+    from paper_1606_06117_amd import native
+    shape = (12, 20, 40)
+    phi = W.random_gaussians(shape, 4, seed=16).astype(np.float32)
+    u = W.abc_velocity(shape)
+    dx = tuple(2 * np.pi / n for n in reversed(shape))
+    dt = 0.9 * dx[0] / 2
+    p = {name: np.zeros(s) for name, s in mlp.SHAPES}
+    p["b3"][0] = b3
+    model = native.Model(ctx)
+    model.set_params(mlp.pack(p).astype(np.float32))
+    model.set_courant_range(1.0)
+    d = device(phi)
+    assert not native.advect_learned(ctx, model, d, device(u), dx, dt, 1)
+    got = d.cpu().numpy()
+    phi1 = gpu_advect(ctx, phi, u, dx, dt, oracle.CIR, 1).astype(np.float32)
+    lo, hi = mlp.neighbourhood_range(phi1)
+    assert np.array_equal(got, (hi if b3 > 0 else lo).astype(np.float32))
+    model.close()
+
+
+def test_learned_steps_keep_the_maximum_norm(ctx):
+    """Untrained random weights, 30 learned steps: max|phi| never grows."""
+    import torch
+    from paper_1606_06117_amd import native
+    shape = (16, 24, 32)
+    phi = W.random_gaussians(shape, 4, seed=17).astype(np.float32)
+    phi += 0.05 * np.random.default_rng(18).normal(size=shape).astype(np.float32)
+    u = W.abc_velocity(shape)
+    dx = tuple(2 * np.pi / n for n in reversed(shape))
+    dt = 0.9 * dx[0] / 2
+    model = native.Model(ctx)
+    model.set_params(he_params(19, scale=3.0))
+    model.set_courant_range(1.0)
+    d = device(phi)
+    m = float(np.max(np.abs(phi)))
+    for step in range(30):
+        native.advect_learned(ctx, model, d, device(u), dx, dt, 1, step0=step)
+        mm = float(torch.max(torch.abs(d)).item())
+        assert mm <= m
+        m = mm
+    model.close()

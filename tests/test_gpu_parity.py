@@ -302,7 +302,7 @@ def test_fused_step_matches_sweeps(ctx, step0, variant):
     try:
         fused = gpu_advect(ctx, phi, u, dx, dt, oracle.CEC, 3, step0=step0)
     finally:
-        ctx.set_option(native.OPT_CEC3D_KERNEL, 2)
+        ctx.set_option(native.OPT_CEC3D_KERNEL, native.CEC3D_DEFAULT)
     ctx.set_option(native.OPT_FUSED, 0)
     try:
         sweeps = gpu_advect(ctx, phi, u, dx, dt, oracle.CEC, 3, step0=step0)

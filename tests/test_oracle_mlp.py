@@ -112,3 +112,41 @@ def test_zero_network_is_cir():
     c = rng.uniform(-0.9, 0.9, (3,) + shape)
     out = mlp.learned_step(phi, c, np.zeros(mlp.NPARAMS))
     assert np.allclose(out, oracle.cir(phi, c), atol=1e-15)
+
+
+def _range_brute(phi1, z, y, x):
+    nz, ny, nx = phi1.shape
+    vals = [phi1[(z + a) % nz, (y + b) % ny, (x + c) % nx]
+            for a in (-1, 0, 1) for b in (-1, 0, 1) for c in (-1, 0, 1)]
+    return min(vals), max(vals)
+
+
+@pytest.mark.parametrize("b3", [1.0e3, -1.0e3])
+def test_learned_step_limited_to_neighbourhood(b3):
+    """A network whose output is huge gives, at every node, the maximum
+    (resp. minimum) of the 27 CIR values around it (checked by brute force)."""
+    rng = np.random.default_rng(6)
+    shape = (5, 6, 7)
+    phi = rng.normal(size=shape)
+    c = rng.uniform(-0.9, 0.9, (3,) + shape)
+    p = {name: np.zeros(s) for name, s in mlp.SHAPES}
+    p["b3"][0] = b3
+    out = mlp.learned_step(phi, c, mlp.pack(p))
+    phi1 = oracle.cir(phi, c)
+    for z, y, x in np.ndindex(*shape):
+        lo, hi = _range_brute(phi1, z, y, x)
+        assert out[z, y, x] == (hi if b3 > 0 else lo)
+
+
+def test_learned_steps_keep_the_maximum_norm():
+    """Random (untrained) weights: repeated learned steps never raise max|phi|."""
+    rng = np.random.default_rng(7)
+    shape = (6, 6, 8)
+    phi = rng.normal(size=shape)
+    c = rng.uniform(-0.9, 0.9, (3,) + shape)
+    flat = mlp.pack(rand_params(rng, scale=2.0))
+    m = np.max(np.abs(phi))
+    for _ in range(5):
+        phi = mlp.learned_step(phi, c, flat)
+        assert np.max(np.abs(phi)) <= m
+        m = np.max(np.abs(phi))
