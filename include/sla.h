@@ -178,6 +178,7 @@ typedef struct sla_plan sla_plan; /* opaque; owns work memory and the graph */
  * extent of a tile, persistent grid size) on the problems (reading their
  * fields, writing only its own work memory) and keeps the fastest.  Work
  * memory: one field per problem.  The graph is built on a private stream.
+ * Grids are 3D with at most 2^30 cells each (else SLA_EINVAL).
  * Synchronises the context's stream. */
 int sla_plan_create(sla_ctx *ctx, sla_plan **out, int32_t nprob, const sla_problem *probs,
                     int32_t steps, int64_t step0, double courant_max, int32_t tune);

@@ -338,8 +338,9 @@ int sla_advect(sla_ctx* ctx, const sla_grid* grid, float* phi, const float* u, d
   if (rc) return rc;
 
   // A 3D third-order step whose reach is 1 on every axis runs as one fused
-  // kernel (20 B/cell); other cases run one sweep kernel per axis.
-  const bool fused3d = ctx->fused && ndim == 3 && rmax == 1;
+  // kernel (20 B/cell); other cases run one sweep kernel per axis.  The
+  // fused kernels address a field with 32-bit byte offsets: up to 2^30 cells.
+  const bool fused3d = ctx->fused && ndim == 3 && rmax == 1 && geo.ncells <= (1 << 30);
   float* cur = phi;
   float* nxt = ctx->work;
   hipError_t e = hipSuccess;
@@ -852,6 +853,8 @@ int sla_plan_create(sla_ctx* ctx, sla_plan** out, int32_t nprob, const sla_probl
     int rc = check_grid(ctx, &P[i].grid);
     if (rc) return rc;
     if (P[i].grid.ndim != 3) return fail(ctx, SLA_EINVAL, "problem %d: plans take 3D grids", i);
+    if (int64_t(P[i].grid.n[0]) * P[i].grid.n[1] * P[i].grid.n[2] > (int64_t(1) << 30))
+      return fail(ctx, SLA_EINVAL, "problem %d: plans take grids of at most 2^30 cells", i);
     if (!P[i].phi) return fail(ctx, SLA_EINVAL, "problem %d: phi is NULL", i);
     if (!std::isfinite(P[i].dt)) return fail(ctx, SLA_EINVAL, "problem %d: dt must be finite", i);
     const sla::Geo geo = make_geo(&P[i].grid, P[i].dt);

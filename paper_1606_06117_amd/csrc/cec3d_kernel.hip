@@ -117,9 +117,31 @@ __device__ __forceinline__ int3 block_tile(int swz) {
   return make_int3(int(lg % gx), int((lg / gx) % gy), int(lg / (gx * gy)));
 }
 
+// Buffer accesses relative to a plane's start: the base lives in a scalar
+// buffer descriptor built once per plane and each access is a 32-bit byte
+// offset, so loads and stores need no per-access address arithmetic.
+// Offsets stay below 2^32 because fused-step grids hold at most 2^30
+// cells; the descriptor's size is the rest of the field (accesses beyond it
+// read zero and write nothing).
+typedef __amdgpu_buffer_rsrc_t Rsrc;
+constexpr int kRsrcWord3 = 0x00020000;  // raw 32-bit buffer, gfx9 family
+__device__ __forceinline__ Rsrc plane_rsrc(const float* base, size_t elems_left) {
+  const unsigned bytes = elems_left >= (size_t(1) << 30) ? 0xFFFFFFFFu : unsigned(elems_left) * 4u;
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(base), short(0), int(bytes), kRsrcWord3);
+}
+__device__ __forceinline__ float ld_at(Rsrc r, unsigned byte_off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, byte_off, 0, 0));
+}
+__device__ __forceinline__ void st_at(Rsrc r, unsigned byte_off, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, byte_off, 0, 0);
+}
+
 // Minimum waves per SIMD the compiler must leave room for (register budget).
 #ifndef SLA_CEC3D_MIN_WAVES
 #define SLA_CEC3D_MIN_WAVES 2
+#endif
+#ifndef SLA_SEG_MIN_WAVES
+#define SLA_SEG_MIN_WAVES 2
 #endif
 
 template <bool EVEN>
@@ -407,7 +429,7 @@ __device__ __forceinline__ void sweep_segment(const float (&p)[V + 6], const flo
 }
 
 template <bool EVEN>
-__global__ __launch_bounds__(kThreads, SLA_CEC3D_MIN_WAVES) void k_cec3d_seg(
+__global__ __launch_bounds__(kThreads, SLA_SEG_MIN_WAVES) void k_cec3d_seg(
     const float* __restrict__ phi, const float* __restrict__ ux, const float* __restrict__ uy,
     const float* __restrict__ uz, float* __restrict__ out, Geo g, int ychunk, int swz, int* flag) {
   using S = SegShape<EVEN>;
@@ -432,22 +454,28 @@ __global__ __launch_bounds__(kThreads, SLA_CEC3D_MIN_WAVES) void k_cec3d_seg(
   const float lamB = EVEN ? g.lam[2] : g.lam[0];
   const float lamY = g.lam[1];
 
+  // byte offsets (x-z part) of this thread's cells within a y plane
   unsigned poff[KP];
   unsigned yoff[KY];
-  int ycol[KY];
 #pragma unroll
   for (int k = 0; k < KP; ++k) {
     const int e = min(tid + k * kThreads, S::NP - 1);
     const int z = e / S::W - H, x = e % S::W - H;
-    poff[k] = unsigned(wrap1(x0 + x, nx)) + nxy * unsigned(wrap1(z0 + z, nz));
+    poff[k] = 4u * (unsigned(wrap1(x0 + x, nx)) + nxy * unsigned(wrap1(z0 + z, nz)));
   }
 #pragma unroll
   for (int j = 0; j < KY; ++j) {
     const int e = min(tid + j * kThreads, S::NY - 1);
     const int z = S::YZ0 + e / S::YW, x = S::YX0 + e % S::YW;
-    yoff[j] = unsigned(wrap1(x0 + x, nx)) + nxy * unsigned(wrap1(z0 + z, nz));
-    ycol[j] = lidx<EVEN>(x, z);
+    yoff[j] = 4u * (unsigned(wrap1(x0 + x, nx)) + nxy * unsigned(wrap1(z0 + z, nz)));
   }
+  // LDS index of y column j (region element tid + 256 j): the region is
+  // 64-wide rows (even) or whole padded rows (odd), so consecutive j are a
+  // fixed stride apart and only the first index is kept in a register
+  static_assert(EVEN ? (kThreads % S::YW == 0) : (S::YW == S::W), "y columns a fixed stride apart");
+  const int ycol0 = lidx<EVEN>(S::YX0 + tid % S::YW, S::YZ0 + tid / S::YW);
+  constexpr int YCS = EVEN ? (kThreads / S::YW) * S::W : kThreads;
+  auto ycol = [&](int j) { return ycol0 + j * YCS; };
   auto pvalid = [&](int k) { return KP * kThreads == S::NP || tid + k * kThreads < S::NP; };
   auto yvalid = [&](int j) { return KY * kThreads == S::NY || tid + j * kThreads < S::NY; };
 
@@ -459,6 +487,12 @@ __global__ __launch_bounds__(kThreads, SLA_CEC3D_MIN_WAVES) void k_cec3d_seg(
   const int sb2 = EVEN ? tid / TA : tid % S::NS2;  // last sweep: segment index along B
   const int i2 = EVEN ? lidx<EVEN>(la2, sb2 * V) : lidx<EVEN>(sb2 * V, la2);
   const int ox2 = EVEN ? la2 : sb2 * V, oz2 = EVEN ? sb2 * V : la2;  // tile coords of out[0]
+  // byte offset of out[0] within a y plane, the step between outputs, and
+  // how many of the V outputs are inside the grid
+  const unsigned ostep2 = EVEN ? 4u * nxy : 4u;
+  const unsigned obase2 = 4u * (unsigned(min(x0 + ox2, nx - 1)) + nxy * unsigned(min(z0 + oz2, nz - 1)));
+  const int nvalid2 = EVEN ? (x0 + ox2 < nx ? min(V, nz - (z0 + oz2)) : 0)
+                           : (z0 + oz2 < nz ? min(V, nx - (x0 + ox2)) : 0);
 
   float ra[3][KY], r1[3][KY], re[3][KY], rc[3][KY];
 #pragma unroll
@@ -468,18 +502,23 @@ __global__ __launch_bounds__(kThreads, SLA_CEC3D_MIN_WAVES) void k_cec3d_seg(
 
   float fp[KP], fa[KP], fy[KY], fb[KY];
   auto prefetch = [&](int t) {
-    const unsigned qoff = unsigned(wrap1(y0 - H + t, ny)) * unsigned(nx);
-    const unsigned coff = unsigned(wrap1(y0 - H + t - 1, ny)) * unsigned(nx);
-    const unsigned ooff = unsigned(wrap1(y0 + t - 2 * H, ny)) * unsigned(nx);
+    const size_t qoff = size_t(wrap1(y0 - H + t, ny)) * size_t(nx);
+    const size_t coff = size_t(wrap1(y0 - H + t - 1, ny)) * size_t(nx);
+    const size_t ooff = size_t(wrap1(y0 + t - 2 * H, ny)) * size_t(nx);
+    const size_t ncells = size_t(nxy) * size_t(nz);
+    const Rsrc pq = plane_rsrc(phi + qoff, ncells - qoff);
+    const Rsrc aq = plane_rsrc(uA + qoff, ncells - qoff);
+    const Rsrc yq = plane_rsrc(uy + coff, ncells - coff);
+    const Rsrc bq = plane_rsrc(uB + ooff, ncells - ooff);
 #pragma unroll
     for (int k = 0; k < KP; ++k) {
-      fp[k] = phi[poff[k] + qoff];
-      fa[k] = uA[poff[k] + qoff];
+      fp[k] = ld_at(pq, poff[k]);
+      fa[k] = ld_at(aq, poff[k]);
     }
 #pragma unroll
     for (int j = 0; j < KY; ++j) {
-      fy[j] = uy[yoff[j] + coff];
-      fb[j] = uB[yoff[j] + ooff];
+      fy[j] = ld_at(yq, yoff[j]);
+      fb[j] = ld_at(bq, yoff[j]);
     }
   };
 
@@ -510,7 +549,7 @@ __global__ __launch_bounds__(kThreads, SLA_CEC3D_MIN_WAVES) void k_cec3d_seg(
       if (emit && yvalid(j)) {
         const float cb = fb[j] * lamB;
         over |= over1(cb);
-        CB[ycol[j]] = cb;
+        CB[ycol(j)] = cb;
       }
     }
     if (t + 1 < iters) prefetch(t + 1);
@@ -531,7 +570,7 @@ __global__ __launch_bounds__(kThreads, SLA_CEC3D_MIN_WAVES) void k_cec3d_seg(
 #pragma unroll
     for (int j = 0; j < KY; ++j) {
       if (!yvalid(j)) continue;
-      const int i = ycol[j];
+      const int i = ycol(j);
       ra[p0][j] = AO[i];
       rc[p1][j] = cy[j];
       Dep1 d = depart1(rc[p1][j], flag);
@@ -554,12 +593,11 @@ __global__ __launch_bounds__(kThreads, SLA_CEC3D_MIN_WAVES) void k_cec3d_seg(
 #pragma unroll
       for (int k = 0; k < V + 4; ++k) c[k] = CB[i2 + (k - 2) * SB];
       sweep_segment<V>(p, c, o, flag);
-      const unsigned yo = unsigned(y0 + t - 2 * H) * unsigned(nx);
+      const size_t orow = size_t(y0 + t - 2 * H) * size_t(nx);
+      const Rsrc oq = plane_rsrc(out + orow, size_t(nxy) * size_t(nz) - orow);
 #pragma unroll
-      for (int k = 0; k < V; ++k) {
-        const int x = x0 + ox2 + (EVEN ? 0 : k), z = z0 + oz2 + (EVEN ? k : 0);
-        if (x < nx && z < nz) out[unsigned(x) + yo + nxy * unsigned(z)] = o[k];
-      }
+      for (int k = 0; k < V; ++k)
+        if (k < nvalid2) st_at(oq, obase2 + k * ostep2, o[k]);
     }
     // the next plane stores CB before its first barrier
     __syncthreads();
