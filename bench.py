@@ -118,18 +118,18 @@ def copy_probe(reps: int, warmup: int) -> int:
     return 0
 
 
-def learned_section(ctx, size, fields, steps_per_field, cells, iters, batch, lr):
+def learned_section(ctx, size, fields, steps_per_field, cells, iters, batch, lr, rounds):
     """Learned correction vs the plain third-order scheme on the time-modulated
     ABC flow (CFL 0.9 at peak amplitude): training on pairs from the GPU
     third-order scheme, then error against the exact field after whole
     modulation periods, time per step, and the speedup at equal error."""
     from paper_1606_06117_amd import learned as Lr
     shape = (size, size, size)
-    pairs = Lr.generate_pairs(ctx, shape, fields=list(range(4000, 4000 + fields)),
-                              steps_per_field=steps_per_field, cells_per_snapshot=cells,
-                              cfl=0.9, seed_cells=4500)
-    model, hist, train_s = Lr.train(ctx, pairs, iters=iters, batch=batch, lr=lr, seed=4600, cfl=0.9,
-                                    log_every=max(1, iters // 10))
+    model, pairs, hists, pairs_s, train_s = Lr.train_rollout(
+        ctx, shape, fields=list(range(4000, 4000 + fields)), steps_per_field=steps_per_field,
+        cells_per_snapshot=cells, cfl=0.9, seed=4500, rounds=rounds, iters=iters, batch=batch, lr=lr,
+        log_every=max(1, iters // 10))
+    hist = [h for hh in hists for h in hh]
     ev = Lr.evaluate(ctx, model, shape, seed=4100, periods=2, cfl=0.9)
     # cost-to-error curve of the plain scheme: a period in 50..200 steps
     plain = []
@@ -141,10 +141,12 @@ def learned_section(ctx, size, fields, steps_per_field, cells, iters, batch, lr)
     last = ev["per_step"][-1]
     out = {
         "workload": f"{size}^3 FP32, ABC velocity with amplitude sin(2 pi (m+1/2)/100), CFL 0.9 at peak; "
-                    f"{fields} fields x {steps_per_field} steps x {cells} nodes = {pairs.m} training pairs",
-        "pairs_seconds": pairs.seconds,
-        "train_iters": iters, "train_batch": batch, "train_seconds": train_s,
+                    f"{fields} fields x {steps_per_field} steps x {cells} nodes per round, "
+                    f"{rounds} rounds of pairs from the model's own rollouts: {pairs.m} training pairs",
+        "pairs_seconds": pairs_s,
+        "train_iters": iters * (rounds + 1), "train_batch": batch, "train_seconds": train_s,
         "loss_first": hist[0][1] if hist else None, "loss_last": hist[-1][1] if hist else None,
+        "loss_per_round": [[h[0][1], h[-1][1]] for h in hists if h],
         "relL2_vs_third_order_after_200_steps": {"learned": last[1], "cir": last[2]},
         "relL2_vs_exact": ev["vs_exact"],
         "ms_per_step": ev["ms_per_step"],
@@ -234,7 +236,9 @@ def main(argv=None):
     ap.add_argument("--learned-fields", type=int, default=20)
     ap.add_argument("--learned-steps", type=int, default=100)
     ap.add_argument("--learned-cells", type=int, default=65536)
-    ap.add_argument("--learned-iters", type=int, default=4000)
+    ap.add_argument("--learned-iters", type=int, default=4000, help="Adam steps per training round")
+    ap.add_argument("--learned-rounds", type=int, default=2,
+                    help="rounds of pairs from the model's own rollouts after the first training")
     ap.add_argument("--probe", choices=["copy"], default=None,
                     help="instead of the benchmark, time a plain device copy of known size "
                          "(achievable bandwidth; calibrates HBM byte counters)")
@@ -351,7 +355,8 @@ def main(argv=None):
     if args.learned == "on":
         print("[bench] learned correction: pairs, training, evaluation ...", file=sys.stderr, flush=True)
         out["learned"] = learned_section(ctx, args.learned_size, args.learned_fields, args.learned_steps,
-                                         args.learned_cells, args.learned_iters, 65536, 2e-3)
+                                         args.learned_cells, args.learned_iters, 65536, 2e-3,
+                                         args.learned_rounds)
 
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle sample ...", file=sys.stderr, flush=True)

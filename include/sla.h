@@ -125,7 +125,9 @@ typedef enum {
   SLA_OPT_FUSED = 0,
   /* Which implementation runs the fused step (same FP32 operations, same
    * results): 0 LDS stages, 1 register segments (default), 2 streaming
-   * (direct global-to-LDS loads).  The batched plans always use 2. */
+   * (direct global-to-LDS loads), 3 overlapped (first and last sweeps of
+   * neighbouring planes run at once on different waves).  The batched plans
+   * always use 2. */
   SLA_OPT_CEC3D_KERNEL = 1
 } sla_option;
 /* Set option `option` to `value`.  Returns SLA_EINVAL for an unknown option

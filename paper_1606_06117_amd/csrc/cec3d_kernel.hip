@@ -612,6 +612,243 @@ __global__ __launch_bounds__(kThreads, SLA_SEG_MIN_WAVES) void k_cec3d_seg(
 }
 
 // ---------------------------------------------------------------------------
+// Overlapped variant: 320-thread workgroups (5 waves) and two barriers per
+// plane.  Phase A: every wave runs the y pipeline on the first-sweep output
+// of the previous plane, then publishes the prefetched inputs of the next
+// plane to LDS and issues the loads of the one after.  Phase B: waves 0-2
+// run the first sweep of the new plane while waves 3-4 run the last sweep
+// of the y output and store it.  The two sweeps of phase B touch different
+// LDS arrays, so they need no barrier between them.
+// ---------------------------------------------------------------------------
+constexpr int kTO = 320;
+constexpr int kTO1 = 192;  // threads of the first sweep (waves 0-2)
+
+template <bool EVEN>
+struct OvlShape : Cec3dShape<EVEN> {
+  using B = Cec3dShape<EVEN>;
+  static constexpr int V = 8;
+  static constexpr int NS1 = B::TA / V, N1 = (B::TB + 2 * B::H) * NS1;  // first sweep items
+  static constexpr int NS2 = B::TB / V, N2 = B::TA * NS2;               // last sweep items
+  static constexpr int KP = (B::NP + kTO - 1) / kTO;  // padded-plane cells per thread
+  static constexpr int KY = (B::NY + kTO - 1) / kTO;  // y columns per thread
+  static_assert(N1 <= kTO1 && N2 <= kTO - kTO1, "one item per thread of each group");
+  static_assert(B::TA % V == 0 && B::TB % V == 0, "segments tile the block");
+};
+
+template <bool EVEN>
+__global__ __launch_bounds__(kTO, 2) void k_cec3d_ovl(
+    const float* __restrict__ phi, const float* __restrict__ ux, const float* __restrict__ uy,
+    const float* __restrict__ uz, float* __restrict__ out, Geo g, int ychunk, int swz, int* flag) {
+  using S = OvlShape<EVEN>;
+  constexpr int H = S::H, TA = S::TA, SA = S::SA, SB = S::SB, V = S::V;
+  constexpr int KP = S::KP, KY = S::KY;
+  __shared__ float P[S::NP];   // phi at the loaded plane, padded
+  __shared__ float CA[S::NP];  // Courant numbers of the first sweep
+  __shared__ float CB[S::NP];  // Courant numbers of the last sweep (output plane)
+  __shared__ float AO[S::NP];  // first-sweep output (y-pipeline input)
+  __shared__ float YO[S::NP];  // y-sweep output (last-sweep input)
+
+  const int tid = threadIdx.x;
+  const int3 bt = block_tile(swz);
+  const int x0 = bt.x * S::TX, z0 = bt.y * S::TZ;
+  const int y0 = bt.z * ychunk;
+  const int y1 = min(y0 + ychunk, g.ny);
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  const unsigned nxy = unsigned(nx) * unsigned(ny);
+  const size_t ncells = size_t(nxy) * size_t(nz);
+  const float* uA = EVEN ? ux : uz;
+  const float* uB = EVEN ? uz : ux;
+  const float lamA = EVEN ? g.lam[0] : g.lam[2];
+  const float lamB = EVEN ? g.lam[2] : g.lam[0];
+  const float lamY = g.lam[1];
+
+  // byte offsets (x-z part) of this thread's cells within a y plane
+  unsigned poff[KP];
+  unsigned yoff[KY];
+#pragma unroll
+  for (int k = 0; k < KP; ++k) {
+    const int e = min(tid + k * kTO, S::NP - 1);
+    const int z = e / S::W - H, x = e % S::W - H;
+    poff[k] = 4u * (unsigned(wrap1(x0 + x, nx)) + nxy * unsigned(wrap1(z0 + z, nz)));
+  }
+#pragma unroll
+  for (int j = 0; j < KY; ++j) {
+    const int e = min(tid + j * kTO, S::NY - 1);
+    const int z = S::YZ0 + e / S::YW, x = S::YX0 + e % S::YW;
+    yoff[j] = 4u * (unsigned(wrap1(x0 + x, nx)) + nxy * unsigned(wrap1(z0 + z, nz)));
+  }
+  // LDS index of y column j (region element tid + 320 j), a fixed stride apart
+  static_assert(EVEN ? (kTO % S::YW == 0) : (S::YW == S::W), "y columns a fixed stride apart");
+  const int ycol0 = lidx<EVEN>(S::YX0 + tid % S::YW, S::YZ0 + tid / S::YW);
+  constexpr int YCS = EVEN ? (kTO / S::YW) * S::W : kTO;
+  auto ycol = [&](int j) { return ycol0 + j * YCS; };
+  auto pvalid = [&](int k) { return KP * kTO == S::NP || tid + k * kTO < S::NP; };
+  auto yvalid = [&](int j) { return KY * kTO == S::NY || tid + j * kTO < S::NY; };
+
+  // phase-B roles: first-sweep segment (threads < N1) or last-sweep segment
+  // (threads kTO1 .. kTO1 + N2 - 1)
+  const bool has1 = tid < S::N1;
+  const int i1 = EVEN ? lidx<EVEN>((tid % S::NS1) * V, tid / S::NS1 - H)
+                      : lidx<EVEN>(tid / S::NS1 - H, (tid % S::NS1) * V);
+  const int k2 = tid >= kTO1 ? tid - kTO1 : 0;
+  const bool has2 = tid >= kTO1 && k2 < S::N2;
+  const int la2 = EVEN ? k2 % TA : k2 / S::NS2;  // last sweep: line (A coordinate)
+  const int sb2 = EVEN ? k2 / TA : k2 % S::NS2;  // last sweep: segment index along B
+  const int i2 = EVEN ? lidx<EVEN>(la2, sb2 * V) : lidx<EVEN>(sb2 * V, la2);
+  const int ox2 = EVEN ? la2 : sb2 * V, oz2 = EVEN ? sb2 * V : la2;
+  const unsigned ostep2 = EVEN ? 4u * nxy : 4u;
+  const unsigned obase2 = 4u * (unsigned(min(x0 + ox2, nx - 1)) + nxy * unsigned(min(z0 + oz2, nz - 1)));
+  const int nvalid2 = EVEN ? (x0 + ox2 < nx ? min(V, nz - (z0 + oz2)) : 0)
+                           : (z0 + oz2 < nz ? min(V, nx - (x0 + ox2)) : 0);
+
+  float ra[3][KY], r1[3][KY], re[3][KY], rc[3][KY];
+#pragma unroll
+  for (int j = 0; j < KY; ++j)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) ra[k][j] = r1[k][j] = re[k][j] = rc[k][j] = 0.f;
+
+  // Iteration t publishes input plane q_t = y0 - H + t (t < iters), runs the
+  // y pipeline on q_{t-1} (t >= 1) and stores output plane y0 + t - 1 - 2H
+  // (t >= 1 + 2H).  prefetch(t) loads what iteration t publishes: phi and
+  // the first-sweep velocity of q_t, the y velocity of q_{t-2} (the plane
+  // whose y sweep completes when q_{t-1} enters) and the last-sweep
+  // velocity of the output plane.
+  const int iters = (y1 - y0) + 2 * H;
+  float fp[KP], fa[KP], fy[KY], fb[KY];
+  auto prefetch = [&](int t) {
+    const size_t qoff = size_t(wrap1(y0 - H + t, ny)) * size_t(nx);
+    const size_t coff = size_t(wrap1(y0 - H + t - 2, ny)) * size_t(nx);
+    const size_t ooff = size_t(wrap1(y0 + t - 1 - 2 * H, ny)) * size_t(nx);
+    const Rsrc pq = plane_rsrc(phi + qoff, ncells - qoff);
+    const Rsrc aq = plane_rsrc(uA + qoff, ncells - qoff);
+    const Rsrc yq = plane_rsrc(uy + coff, ncells - coff);
+    const Rsrc bq = plane_rsrc(uB + ooff, ncells - ooff);
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+      fp[k] = ld_at(pq, poff[k]);
+      fa[k] = ld_at(aq, poff[k]);
+    }
+#pragma unroll
+    for (int j = 0; j < KY; ++j) {
+      fy[j] = ld_at(yq, yoff[j]);
+      fb[j] = ld_at(bq, yoff[j]);
+    }
+  };
+
+  bool over = false;  // a Courant number beyond reach 1 was published
+  auto publish = [&](int t) {
+    if (t < iters) {
+#pragma unroll
+      for (int k = 0; k < KP; ++k) {
+        if (!pvalid(k)) continue;
+        const float ca = fa[k] * lamA;
+        over |= over1(ca);
+        P[tid + k * kTO] = fp[k];
+        CA[tid + k * kTO] = ca;
+      }
+    }
+    if (t >= 1 + 2 * H) {
+#pragma unroll
+      for (int j = 0; j < KY; ++j) {
+        if (!yvalid(j)) continue;
+        const float cb = fb[j] * lamB;
+        over |= over1(cb);
+        CB[ycol(j)] = cb;
+      }
+    }
+  };
+  auto phase_b = [&](int t) {
+    if (t < iters && has1) {  // first sweep of q_t
+      float p[V + 6], c[V + 4], o[V];
+#pragma unroll
+      for (int k = 0; k < V + 6; ++k) p[k] = P[i1 + (k - 3) * SA];
+#pragma unroll
+      for (int k = 0; k < V + 4; ++k) c[k] = CA[i1 + (k - 2) * SA];
+      sweep_segment<V>(p, c, o, flag);
+#pragma unroll
+      for (int k = 0; k < V; ++k) AO[i1 + k * SA] = o[k];
+    }
+    if (t >= 1 + 2 * H && has2) {  // last sweep of output plane y0 + t - 1 - 2H
+      float p[V + 6], c[V + 4], o[V];
+#pragma unroll
+      for (int k = 0; k < V + 6; ++k) p[k] = YO[i2 + (k - 3) * SB];
+#pragma unroll
+      for (int k = 0; k < V + 4; ++k) c[k] = CB[i2 + (k - 2) * SB];
+      sweep_segment<V>(p, c, o, flag);
+      const size_t orow = size_t(y0 + t - 1 - 2 * H) * size_t(nx);
+      const Rsrc oq = plane_rsrc(out + orow, ncells - orow);
+#pragma unroll
+      for (int k = 0; k < V; ++k)
+        if (k < nvalid2) st_at(oq, obase2 + k * ostep2, o[k]);
+    }
+  };
+
+  // t = 0: nothing in the y pipeline yet
+  prefetch(0);
+  publish(0);
+  prefetch(1);
+  __syncthreads();
+  phase_b(0);
+  __syncthreads();
+
+  // iterations t = s + 1 for s = 0 .. iters - 1; the y pipeline takes AO of
+  // plane q_s, so its ring slot is s % 3
+  auto body = [&](auto phase, int s) {
+    constexpr int p0 = decltype(phase)::value;  // s % 3
+    constexpr int p1 = (p0 + 2) % 3;            // (s - 1) % 3
+    constexpr int p2 = (p0 + 1) % 3;            // (s - 2) % 3
+    constexpr int p3 = p0;                      // (s - 3) % 3
+    const int t = s + 1;
+    // A. y sweep as a pipeline along the march (registers)
+#pragma unroll
+    for (int j = 0; j < KY; ++j) {
+      const float cy = fy[j] * lamY;
+      over |= over1(cy);
+      if (!yvalid(j)) continue;
+      const int i = ycol(j);
+      ra[p0][j] = AO[i];
+      rc[p1][j] = cy;
+      Dep1 d = depart1(rc[p1][j], flag);
+      r1[p1][j] = lerp(ra[p1][j], d.ob_neg ? ra[p2][j] : ra[p0][j], d.f);
+      d = depart1(rc[p2][j], flag);
+      re[p2][j] = ra[p2][j] - lerp(r1[p2][j], d.obr_pos ? r1[p1][j] : r1[p3][j], d.f);
+      d = depart1(rc[p3][j], flag);
+      const float ea = re[p3][j];
+      const float eb = d.ob_neg ? re[p1][j] : re[p2][j];
+      const float w = fmaf(d.f, 1.f / 3.f, 1.f / 3.f);
+      YO[i] = fmaf(0.5f, fmaf(w, eb - ea, ea), r1[p3][j]);
+    }
+    publish(t);
+    if (t + 1 <= iters) prefetch(t + 1);
+    __syncthreads();
+    // B. first sweep of q_t (waves 0-2) and last sweep of the y output (waves 3-4)
+    phase_b(t);
+    __syncthreads();
+  };
+
+  for (int s = 0; s < iters; s += 3) {
+    body(std::integral_constant<int, 0>{}, s);
+    if (s + 1 < iters) body(std::integral_constant<int, 1>{}, s + 1);
+    if (s + 2 < iters) body(std::integral_constant<int, 2>{}, s + 2);
+  }
+  if (over) *flag = 1;
+}
+
+hipError_t launch_cec3d_ovl(bool even, const Geo& g, const float* phi, const float* u, float* out,
+                            int* flag, hipStream_t st, Cec3dLaunch lc) {
+  const size_t n = (size_t)g.ncells;
+  const int ychunk = lc.ychunk > 0 ? lc.ychunk : cec3d_default_ychunk(g);
+  dim3 grid((g.nx + 63) / 64, (g.nz + 15) / 16, (g.ny + ychunk - 1) / ychunk);
+  if (even)
+    hipLaunchKernelGGL(k_cec3d_ovl<true>, grid, dim3(kTO), 0, st, phi, u, u + n, u + 2 * n, out, g,
+                       ychunk, lc.swizzle, flag);
+  else
+    hipLaunchKernelGGL(k_cec3d_ovl<false>, grid, dim3(kTO), 0, st, phi, u, u + n, u + 2 * n, out, g,
+                       ychunk, lc.swizzle, flag);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Streaming variant: 512-thread workgroups; every plane of phi and of the
 // Courant numbers reaches LDS through direct global-to-LDS loads (no
 // registers, no per-load address arithmetic: a per-plane base in scalar
@@ -1012,6 +1249,7 @@ int cec3d_default_ychunk(const Geo& g) {
 hipError_t launch_cec3d(int variant, bool even, const Geo& g, const float* phi, const float* u,
                         float* out, int* flag, hipStream_t st, Cec3dLaunch lc) {
   if (variant == 1) return launch_cec3d_seg(even, g, phi, u, out, flag, st, lc);
+  if (variant == 3) return launch_cec3d_ovl(even, g, phi, u, out, flag, st, lc);
   if (variant == 2) return launch_cec3d_v4(even, g, phi, u, out, flag, st, lc);
   if (variant != 0) return hipErrorInvalidValue;
   const size_t n = (size_t)g.ncells;

@@ -506,9 +506,10 @@ __global__ __launch_bounds__(kThreads) void k_make_pairs(const float* __restrict
 
 // Learned step, second half: out = Phi1 + sigma * net(features), limited to
 // the range of the 27 values around the node.  A wave tile is 32 nodes of
-// one x row (two MFMA tiles of 16); the waves of the grid take the tiles
-// w, w + W, ... (W waves in all), so every workgroup loads the weights into
-// LDS once.
+// one x row (two MFMA tiles of 16).  Workgroup b takes the groups of four
+// consecutive tiles 4b, 4b + 4G, ... (G workgroups), one tile per wave, so
+// every workgroup loads the weights into LDS once and all its waves run the
+// same number of iterations (forward_tile synchronises the workgroup).
 struct InferLds {
   WeightsLds W;
   __bf16 h1[4][32 * NH];
@@ -529,8 +530,10 @@ __global__ __launch_bounds__(kThreads) void k_learned_correct(const float* __res
   const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15, w = threadIdx.x >> 6;
   const int nxb = (geo.nx + 31) / 32;
   const int tiles = nxb * geo.ny * geo.nz;
-  const int nwaves = gridDim.x * (kThreads / 64);
-  for (int t = blockIdx.x * (kThreads / 64) + w; t < tiles; t += nwaves) {
+  constexpr int WPB = kThreads / 64;
+  for (int t0 = blockIdx.x * WPB; t0 < tiles; t0 += gridDim.x * WPB) {
+    const bool valid = t0 + w < tiles;
+    const int t = valid ? t0 + w : tiles - 1;  // idle waves repeat the last tile, unstored
     const int xb0 = (t % nxb) * 32;
     const int row = t / nxb;
     const int y = row % geo.ny, z = row / geo.ny;
@@ -551,7 +554,7 @@ __global__ __launch_bounds__(kThreads) void k_learned_correct(const float* __res
     floatx4 h2[4][2];
     float yv[2];
     forward_tile(L.W, xb, L.h1[w], h2, yv);
-    if (g == 0) {
+    if (valid && g == 0) {
 #pragma unroll
       for (int jt = 0; jt < 2; ++jt)
         if (xs[jt] < geo.nx)

@@ -12,9 +12,15 @@ exact solution returns to the initial field after every period.
 * ``generate_pairs``: for each initial field (8 random Gaussians) and each
   step, the CIR step and the third-order step of the current field; training
   pairs are sampled at random nodes (features of the CIR field, target the
-  third-order correction); the trajectory continues with the third-order
-  field.
+  third-order correction).  The trajectory continues with the third-order
+  field, or, given a model, with the learned step, so that the pairs cover
+  the states the learned scheme itself visits.
 * ``train``: Adam on minibatches of the pairs.
+* ``train_rollout``: ``train``, then rounds of pairs from the current
+  model's own trajectories added to the set and training continued
+  (dataset aggregation: a network trained only on third-order trajectories
+  meets states it never saw once its own small errors accumulate, and its
+  rollout drifts).
 * ``evaluate``: learned, third-order and CIR runs from the same field; per
   step the relative L2 distance of learned and CIR to the third-order run,
   the error against the exact field after whole periods, time per step.
@@ -67,7 +73,7 @@ def _hint(cfl: float, a: float) -> float:
 
 
 def generate_pairs(ctx, shape, fields, steps_per_field, cells_per_snapshot, cfl, seed_cells,
-                   period=PERIOD) -> Pairs:
+                   period=PERIOD, model=None) -> Pairs:
     import torch
     N = shape[-1]
     dx = (2 * math.pi / N,) * 3
@@ -95,18 +101,30 @@ def generate_pairs(ctx, shape, fields, steps_per_field, cells_per_snapshot, cfl,
             native.make_pairs(ctx, phi1, nxt, u, dx, a * dt, cells, feats[o:o + k], target[o:o + k],
                               sigma[o:o + k])
             o += k
-            phi = nxt
+            if model is None:
+                phi = nxt
+            else:
+                native.advect_learned(ctx, model, phi, u, dx, a * dt, 1, step0=m,
+                                      courant_max=_hint(cfl, a), allow_fallback=False)
     torch.cuda.synchronize()
     ctx.check()
     return Pairs(feats, target, sigma, total, time.perf_counter() - t0)
 
 
-def train(ctx, pairs: Pairs, iters: int, batch: int, lr: float, seed: int, cfl: float,
-          log_every: int = 0):
-    """Adam over shuffled minibatches; returns (model, loss history, seconds)."""
+def concat(a: Pairs, b: Pairs) -> Pairs:
     import torch
-    model = native.Model(ctx)
-    model.set_params(init_params(seed))
+    return Pairs(torch.cat([a.feats, b.feats]), torch.cat([a.target, b.target]),
+                 torch.cat([a.sigma, b.sigma]), a.m + b.m, a.seconds + b.seconds)
+
+
+def train(ctx, pairs: Pairs, iters: int, batch: int, lr: float, seed: int, cfl: float,
+          log_every: int = 0, model=None):
+    """Adam over shuffled minibatches; returns (model, loss history, seconds).
+    A given model is trained further (its Adam state continues)."""
+    import torch
+    if model is None:
+        model = native.Model(ctx)
+        model.set_params(init_params(seed))
     gen = torch.Generator(device="cuda")
     gen.manual_seed(seed)
     perm = torch.randperm(pairs.m, device="cuda", generator=gen)
@@ -129,6 +147,29 @@ def train(ctx, pairs: Pairs, iters: int, batch: int, lr: float, seed: int, cfl: 
     secs = time.perf_counter() - t0
     model.set_courant_range(cfl * (1.0 + 1e-4))
     return model, hist, secs
+
+
+def train_rollout(ctx, shape, fields, steps_per_field, cells_per_snapshot, cfl, seed, rounds,
+                  iters, batch, lr, log_every=0):
+    """``train`` on third-order pairs, then ``rounds`` rounds that add pairs
+    from the model's own trajectories (new initial fields each round) and
+    continue training.  Returns (model, pairs, loss history per round,
+    seconds spent making pairs, seconds spent training)."""
+    pairs = generate_pairs(ctx, shape, fields, steps_per_field, cells_per_snapshot, cfl,
+                           seed_cells=seed)
+    model, hist, tsec = train(ctx, pairs, iters, batch, lr, seed + 1, cfl, log_every)
+    hists = [hist]
+    psec = pairs.seconds
+    for r in range(rounds):
+        new_fields = [f + 1000 * (r + 1) for f in fields]
+        more = generate_pairs(ctx, shape, new_fields, steps_per_field, cells_per_snapshot, cfl,
+                              seed_cells=seed + 10 * (r + 1), model=model)
+        psec += more.seconds
+        pairs = concat(pairs, more)
+        model, hist, t = train(ctx, pairs, iters, batch, lr, seed + 2 + r, cfl, log_every, model=model)
+        hists.append(hist)
+        tsec += t
+    return model, pairs, hists, psec, tsec
 
 
 def evaluate(ctx, model, shape, seed, periods, cfl, period=PERIOD):
