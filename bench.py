@@ -159,6 +159,78 @@ def learned_section(ctx, size, fields, steps_per_field, cells, iters, batch, lr,
     return out
 
 
+def timed_steps(ctx, phi, u, dx, dt, steps, warmup):
+    """Third-order steps with the library's per-kernel timing; returns
+    (wall seconds, per-kind (launches, ms))."""
+    import torch
+    from paper_1606_06117_amd import native
+    cmax = ctx.courant_max(u, dx, dt)
+    for w in range(warmup):
+        ctx.advect(phi, u, dx, dt, native.CEC, 1, step0=w, courant_max=cmax)
+    ctx.check()
+    torch.cuda.synchronize()
+    ctx.timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.advect(phi, u, dx, dt, native.CEC, steps, step0=warmup, courant_max=cmax)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    times = ctx.timing_read()
+    ctx.timing(False)
+    ctx.check()
+    return wall, times, cmax
+
+
+def cfl_section(ctx, size, cfls, steps):
+    """The headline workload (8 Gaussians, ABC velocity) at larger Courant
+    numbers: reach 2 and 3 take the three-sweep path (36 B per cell-update
+    moved; 20 B algorithmic)."""
+    import torch
+    from paper_1606_06117_amd import workloads as W
+    shape = (size,) * 3
+    dev = torch.device("cuda:0")
+    phi = torch.from_numpy(W.random_gaussians(shape, 8, seed=2000).astype(np.float32)).to(dev)
+    u = W.abc_velocity_torch(shape, dev)
+    dx = (2 * math.pi / size,) * 3
+    rows = []
+    for cfl in cfls:
+        wall, times, cmax = timed_steps(ctx, phi, u, dx, W.abc_dt(shape, cfl), steps, 2)
+        upd = size**3 * steps
+        rows.append({"cfl": cfl, "courant_max": cmax, "value": upd / wall / 1e9, "unit": "Gcell-updates/s",
+                     "ms_per_step": wall * 1e3 / steps,
+                     "hbm_frac_step": 20 * upd / wall / (HBM_PEAK_GBS * 1e9),
+                     "per_kind_ms": {k: round(v[1] / v[0], 4) for k, v in times.items()}})
+    del phi, u
+    torch.cuda.empty_cache()
+    return {"workload": f"third order, {size}^3, 8 Gaussians, ABC velocity, {steps} steps per CFL",
+            "runs": rows}
+
+
+def large_section(ctx, size, cfl, steps):
+    """One large problem: a k^-5/3 field (|k| <= 64) on size^3 with the ABC
+    velocity at CFL ``cfl``, built on the GPU."""
+    import torch
+    from paper_1606_06117_amd import workloads as W
+    shape = (size,) * 3
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    phi = W.power_law_torch(shape, 5000, dev)
+    u = W.abc_velocity_torch(shape, dev)
+    torch.cuda.synchronize()
+    build = time.perf_counter() - t0
+    dx = (2 * math.pi / size,) * 3
+    wall, times, cmax = timed_steps(ctx, phi, u, dx, W.abc_dt(shape, cfl), steps, 1)
+    upd = size**3 * steps
+    del phi, u
+    torch.cuda.empty_cache()
+    return {"workload": f"third order, {size}^3 FP32, k^-5/3 field (|k| <= 64), ABC velocity, CFL {cfl}, "
+                        f"{steps} steps", "value": upd / wall / 1e9, "unit": "Gcell-updates/s",
+            "ms_per_step": wall * 1e3 / steps, "courant_max": cmax,
+            "hbm_frac_step": 20 * upd / wall / (HBM_PEAK_GBS * 1e9),
+            "per_kind_ms": {k: round(v[1] / v[0], 4) for k, v in times.items()},
+            "input_build_seconds": build}
+
+
 def batch_section(ctx, size, scalars, ngrids, steps):
     """Batched workload: ``scalars`` fields on a size^3 grid sharing one ABC
     velocity, plus ``ngrids`` cubic grids of uneven sizes 32^3..192^3 with
@@ -226,6 +298,10 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--path", choices=["auto", "sweeps"], default="auto",
                     help="auto: fused step where the library has one; sweeps: one kernel per axis")
+    ap.add_argument("--other-cfl", choices=["on", "off"], default="on",
+                    help="also time the headline workload at CFL 1.5 and 2.0 (10 steps each)")
+    ap.add_argument("--large", choices=["on", "off"], default="on",
+                    help="also time one 1024^3 problem at CFL 2.0 (10 steps)")
     ap.add_argument("--batch", choices=["on", "off"], default="on",
                     help="also run the batched workload (16 x 512^3 + 64 uneven grids)")
     ap.add_argument("--batch-scalars", type=int, default=16)
@@ -348,6 +424,12 @@ def main(argv=None):
 
     del phi_d, u_d
     torch.cuda.empty_cache()
+    if args.other_cfl == "on":
+        print("[bench] CFL 1.5 and 2.0 ...", file=sys.stderr, flush=True)
+        out["other_cfl"] = cfl_section(ctx, args.size, (1.5, 2.0), 10)
+    if args.large == "on":
+        print("[bench] 1024^3 at CFL 2.0 ...", file=sys.stderr, flush=True)
+        out["large"] = large_section(ctx, 1024, 2.0, 10)
     if args.batch == "on":
         print("[bench] batched workload ...", file=sys.stderr, flush=True)
         out["batch"] = batch_section(ctx, args.size, args.batch_scalars, args.batch_grids, args.steps)

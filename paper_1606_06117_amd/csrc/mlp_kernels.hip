@@ -71,21 +71,31 @@ __device__ __forceinline__ float max4g(float v) {
   return fmaxf(v, __shfl_xor(v, 32));
 }
 
-// Weights in LDS: W1T [n][k] (64 x 32), W2T [n][k] (64 x 64), W2R [k][n]
-// (64 x 64), all BF16; biases and w3 FP32 (already BF16-rounded).
+// LDS row strides (BF16 elements), padded by 16 bytes: a matrix-core
+// operand read takes 16 bytes from each of 16 rows, and with rows 64 or 128
+// bytes apart those rows would share banks; 80 and 144 bytes spread every 8
+// consecutive rows over all 32 banks.
+constexpr int SF = NF + 8;  // rows of 32 (W1T rows; [feature|hidden][cell] tiles)
+constexpr int SH = NH + 8;  // rows of 64 (W2T, W2R, [cell][hidden] tiles)
+constexpr int SC = 32 + 8;  // rows of 32 cells
+
+// Weights in LDS: W1T [n][k] (64 x 32), W2T [n][k] (64 x 64), all BF16 with
+// padded rows; biases and w3 FP32 (already BF16-rounded).  Training also
+// keeps W2R [k][n] (64 x 64).
 struct WeightsLds {
-  __bf16 w1t[NH * NF];
-  __bf16 w2t[NH * NH];
-  __bf16 w2r[NH * NH];
+  __bf16 w1t[NH * SF];
+  __bf16 w2t[NH * SH];
   float b1[NH], b2[NH], w3[NH], b3;
 };
 
-__device__ void load_weights(WeightsLds& W, const __bf16* __restrict__ wpack,
-                             const float* __restrict__ wr, bool need_w2r) {
-  for (int i = threadIdx.x; i < NH * NF; i += kThreads) W.w1t[i] = wpack[i];
-  for (int i = threadIdx.x; i < NH * NH; i += kThreads) W.w2t[i] = wpack[NH * NF + i];
-  if (need_w2r)
-    for (int i = threadIdx.x; i < NH * NH; i += kThreads) W.w2r[i] = wpack[NH * NF + NH * NH + i];
+__device__ void load_weights(WeightsLds& W, __bf16* w2r, const __bf16* __restrict__ wpack,
+                             const float* __restrict__ wr) {
+  for (int i = threadIdx.x; i < NH * NF; i += kThreads) W.w1t[(i / NF) * SF + i % NF] = wpack[i];
+  for (int i = threadIdx.x; i < NH * NH; i += kThreads)
+    W.w2t[(i / NH) * SH + i % NH] = wpack[NH * NF + i];
+  if (w2r)
+    for (int i = threadIdx.x; i < NH * NH; i += kThreads)
+      w2r[(i / NH) * SH + i % NH] = wpack[NH * NF + NH * NH + i];
   for (int i = threadIdx.x; i < NH; i += kThreads) {
     W.b1[i] = wr[B1_OFF + i];
     W.b2[i] = wr[B2_OFF + i];
@@ -104,13 +114,13 @@ __device__ __forceinline__ void forward_tile(const WeightsLds& W, const bf16x8 x
   // layer 1: H1T[k][j] = sum_i W1T[k][i] X[j][i]
 #pragma unroll
   for (int it = 0; it < 4; ++it) {
-    const bf16x8 a = ld8(&W.w1t[(16 * it + c) * NF + 8 * g]);
+    const bf16x8 a = ld8(&W.w1t[(16 * it + c) * SF + 8 * g]);
 #pragma unroll
     for (int jt = 0; jt < 2; ++jt) {
       floatx4 acc = {0.f, 0.f, 0.f, 0.f};
       acc = mfma(a, xb[jt], acc);
       const int k = 16 * it + 4 * g;
-      st4(&h1[(16 * jt + c) * NH + k], fmaxf(acc[0] + W.b1[k], 0.f), fmaxf(acc[1] + W.b1[k + 1], 0.f),
+      st4(&h1[(16 * jt + c) * SH + k], fmaxf(acc[0] + W.b1[k], 0.f), fmaxf(acc[1] + W.b1[k + 1], 0.f),
           fmaxf(acc[2] + W.b1[k + 2], 0.f), fmaxf(acc[3] + W.b1[k + 3], 0.f));
     }
   }
@@ -124,8 +134,8 @@ __device__ __forceinline__ void forward_tile(const WeightsLds& W, const bf16x8 x
       floatx4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int kk = 0; kk < 2; ++kk)
-        acc = mfma(ld8(&W.w2t[(16 * it + c) * NH + 32 * kk + 8 * g]),
-                   ld8(&h1[(16 * jt + c) * NH + 32 * kk + 8 * g]), acc);
+        acc = mfma(ld8(&W.w2t[(16 * it + c) * SH + 32 * kk + 8 * g]),
+                   ld8(&h1[(16 * jt + c) * SH + 32 * kk + 8 * g]), acc);
       const int n = 16 * it + 4 * g;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
@@ -149,12 +159,13 @@ __device__ __forceinline__ void forward_tile(const WeightsLds& W, const bf16x8 x
 // ---------------------------------------------------------------------------
 struct TrainLds {
   WeightsLds W;
-  __bf16 h1[4][32 * NH];   // [cell][hidden]
-  __bf16 h1t[4][NH * 32];  // [hidden][cell]
-  __bf16 dh2[4][32 * NH];  // [cell][n]
-  __bf16 dh2t[4][NH * 32]; // [n][cell]
-  __bf16 dh1t[4][NH * 32]; // [k][cell]
-  __bf16 xt[4][NF * 32];   // [feature][cell]
+  __bf16 w2r[NH * SH];     // W2R [k][n]
+  __bf16 h1[4][32 * SH];   // [cell][hidden]
+  __bf16 h1t[4][NH * SC];  // [hidden][cell]
+  __bf16 dh2[4][32 * SH];  // [cell][n]
+  __bf16 dh2t[4][NH * SC]; // [n][cell]
+  __bf16 dh1t[4][NH * SC]; // [k][cell]
+  __bf16 xt[4][NF * SC];   // [feature][cell]
 };
 
 template <bool TRAIN>
@@ -168,7 +179,7 @@ __global__ __launch_bounds__(kThreads) void k_mlp(const __bf16* __restrict__ X,
                                                   float* __restrict__ lpart) {
   extern __shared__ __align__(16) unsigned char smem[];
   TrainLds& L = *reinterpret_cast<TrainLds*>(smem);
-  load_weights(L.W, wpack, wr, TRAIN);
+  load_weights(L.W, TRAIN ? L.w2r : nullptr, wpack, wr);
   __syncthreads();
   const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15, w = threadIdx.x >> 6;
   __bf16* h1 = L.h1[w];
@@ -204,7 +215,7 @@ __global__ __launch_bounds__(kThreads) void k_mlp(const __bf16* __restrict__ X,
       }
       if (TRAIN) {
 #pragma unroll
-        for (int v = 0; v < 8; ++v) L.xt[w][(8 * g + v) * 32 + 16 * jt + c] = xb[jt][v];
+        for (int v = 0; v < 8; ++v) L.xt[w][(8 * g + v) * SC + 16 * jt + c] = xb[jt][v];
       }
     }
     floatx4 h2[4][2];
@@ -234,7 +245,7 @@ __global__ __launch_bounds__(kThreads) void k_mlp(const __bf16* __restrict__ X,
     // H1 transposed copy for the W2 gradient (this wave's tile only)
     for (int e = lane; e < 32 * NH; e += 64) {
       const int j = e / NH, k = e % NH;
-      L.h1t[w][k * 32 + j] = h1[e];
+      L.h1t[w][k * SC + j] = h1[j * SH + k];
     }
 #pragma unroll
     for (int it = 0; it < 4; ++it) {
@@ -247,19 +258,19 @@ __global__ __launch_bounds__(kThreads) void k_mlp(const __bf16* __restrict__ X,
           dw3[it][q] = fmaf(h2[it][jt][q], dy[jt], dw3[it][q]);
           d[q] = h2[it][jt][q] > 0.f ? dy[jt] * L.W.w3[n + q] : 0.f;
           db2[it][q] += d[q];
-          L.dh2t[w][(n + q) * 32 + j] = (__bf16)d[q];
+          L.dh2t[w][(n + q) * SC + j] = (__bf16)d[q];
         }
-        st4(&L.dh2[w][j * NH + n], d[0], d[1], d[2], d[3]);
+        st4(&L.dh2[w][j * SH + n], d[0], d[1], d[2], d[3]);
       }
     }
     __syncthreads();
     // dW2T[n][k] += sum_j dH2T[n][j] H1[j][k]
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
-      const bf16x8 a = ld8(&L.dh2t[w][(16 * nt + c) * 32 + 8 * g]);
+      const bf16x8 a = ld8(&L.dh2t[w][(16 * nt + c) * SC + 8 * g]);
 #pragma unroll
       for (int kt = 0; kt < 4; ++kt)
-        dw2[nt][kt] = mfma(a, ld8(&L.h1t[w][(16 * kt + c) * 32 + 8 * g]), dw2[nt][kt]);
+        dw2[nt][kt] = mfma(a, ld8(&L.h1t[w][(16 * kt + c) * SC + 8 * g]), dw2[nt][kt]);
     }
     // dH1T[k][j] = sum_n W2R[k][n] dH2[j][n], masked by H1 > 0
 #pragma unroll
@@ -269,14 +280,14 @@ __global__ __launch_bounds__(kThreads) void k_mlp(const __bf16* __restrict__ X,
         floatx4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int nn = 0; nn < 2; ++nn)
-          acc = mfma(ld8(&L.W.w2r[(16 * kt + c) * NH + 32 * nn + 8 * g]),
-                     ld8(&L.dh2[w][(16 * jt + c) * NH + 32 * nn + 8 * g]), acc);
+          acc = mfma(ld8(&L.w2r[(16 * kt + c) * SH + 32 * nn + 8 * g]),
+                     ld8(&L.dh2[w][(16 * jt + c) * SH + 32 * nn + 8 * g]), acc);
         const int k = 16 * kt + 4 * g, j = 16 * jt + c;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          const float d = (float)h1[j * NH + k + q] > 0.f ? acc[q] : 0.f;
+          const float d = (float)h1[j * SH + k + q] > 0.f ? acc[q] : 0.f;
           db1[kt][q] += d;
-          L.dh1t[w][(k + q) * 32 + j] = (__bf16)d;
+          L.dh1t[w][(k + q) * SC + j] = (__bf16)d;
         }
       }
     }
@@ -284,10 +295,10 @@ __global__ __launch_bounds__(kThreads) void k_mlp(const __bf16* __restrict__ X,
     // dW1T[k][i] += sum_j dH1T[k][j] X[j][i]
 #pragma unroll
     for (int kt = 0; kt < 4; ++kt) {
-      const bf16x8 a = ld8(&L.dh1t[w][(16 * kt + c) * 32 + 8 * g]);
+      const bf16x8 a = ld8(&L.dh1t[w][(16 * kt + c) * SC + 8 * g]);
 #pragma unroll
       for (int it = 0; it < 2; ++it)
-        dw1[kt][it] = mfma(a, ld8(&L.xt[w][(16 * it + c) * 32 + 8 * g]), dw1[kt][it]);
+        dw1[kt][it] = mfma(a, ld8(&L.xt[w][(16 * it + c) * SC + 8 * g]), dw1[kt][it]);
     }
     __syncthreads();  // tile buffers are rewritten by the next tile
   }
@@ -359,21 +370,50 @@ __global__ __launch_bounds__(kThreads) void k_mlp(const __bf16* __restrict__ X,
   if (threadIdx.x == 0) lpart[blockIdx.x] = acc[kMlpParams];
 }
 
-// Sum per-block partials in block order (deterministic).
+// Sum per-block partials in a fixed order (deterministic).  A workgroup
+// takes 32 parameters; its 8 row groups each sum every 8th partial in
+// block order, and the 8 sums are added in group order.  Workgroup 0 also
+// sums the loss partials: 256 fixed strided sums, then a fixed tree.
+constexpr int kRedParams = 32, kRedParts = kThreads / kRedParams;
 __global__ __launch_bounds__(kThreads) void k_grad_reduce(const float* __restrict__ gpart,
                                                           const float* __restrict__ lpart,
                                                           int nblk, float* __restrict__ grad,
                                                           double* __restrict__ loss_sum) {
-  const int p = blockIdx.x * kThreads + threadIdx.x;
+  __shared__ float part[kRedParts][kRedParams];
+  __shared__ double lsum[kThreads];
+  const int pl = threadIdx.x % kRedParams, grp = threadIdx.x / kRedParams;
+  const int p = blockIdx.x * kRedParams + pl;
+  float s = 0.f;
   if (p < kMlpParams) {
-    float s = 0.f;
-    for (int b = 0; b < nblk; ++b) s += gpart[(size_t)b * kMlpParams + p];
-    grad[p] = s;
+    int b = grp;
+    for (; b + 3 * kRedParts < nblk; b += 4 * kRedParts) {  // four loads in flight
+      const float v0 = gpart[(size_t)b * kMlpParams + p];
+      const float v1 = gpart[(size_t)(b + kRedParts) * kMlpParams + p];
+      const float v2 = gpart[(size_t)(b + 2 * kRedParts) * kMlpParams + p];
+      const float v3 = gpart[(size_t)(b + 3 * kRedParts) * kMlpParams + p];
+      s = (((s + v0) + v1) + v2) + v3;
+    }
+    for (; b < nblk; b += kRedParts) s += gpart[(size_t)b * kMlpParams + p];
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    double s = 0.0;
-    for (int b = 0; b < nblk; ++b) s += lpart[b];
-    *loss_sum = s;
+  part[grp][pl] = s;
+  if (blockIdx.x == 0) {
+    double l = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += kThreads) l += lpart[b];
+    lsum[threadIdx.x] = l;
+  }
+  __syncthreads();
+  if (grp == 0 && p < kMlpParams) {
+    float t = part[0][pl];
+#pragma unroll
+    for (int q = 1; q < kRedParts; ++q) t += part[q][pl];
+    grad[p] = t;
+  }
+  if (blockIdx.x == 0) {
+    for (int h = kThreads / 2; h > 0; h /= 2) {
+      if (threadIdx.x < h) lsum[threadIdx.x] += lsum[threadIdx.x + h];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) *loss_sum = lsum[0];
   }
 }
 
@@ -431,31 +471,20 @@ struct NodeFeatures {
   float lo, hi;  // range of the 27 values around the node
 };
 
-__device__ __forceinline__ NodeFeatures node_features(const float* __restrict__ phi1,
-                                                      const float* __restrict__ ux,
-                                                      const float* __restrict__ uy,
-                                                      const float* __restrict__ uz, const Geo& geo,
-                                                      int x, int y, int z, int g) {
-  const int nx = geo.nx, ny = geo.ny, nz = geo.nz;
-  const size_t plane = (size_t)nx * ny;
-  const size_t ic = (size_t)z * plane + (size_t)y * nx + x;
-  const float centre = phi1[ic];
+// Features of a node from its gathered values: val[v] is the neighbour
+// k = 8g + v (k < 27) of this lane's group, c3 the node's three Courant
+// numbers (used by group 3).
+__device__ __forceinline__ NodeFeatures features_from(const float (&val)[8], float centre, int g,
+                                                      float cx, float cy, float cz) {
   float d[8];
   float ss = 0.f, lo = centre, hi = centre;
 #pragma unroll
   for (int v = 0; v < 8; ++v) {
-    const int k = 8 * g + v;
     d[v] = 0.f;
-    if (k < 27) {
-      const int dz = k / 9 - 1, dy = (k / 3) % 3 - 1, dx = k % 3 - 1;
-      int xx = x + dx, yy = y + dy, zz = z + dz;
-      xx = xx < 0 ? xx + nx : (xx >= nx ? xx - nx : xx);
-      yy = yy < 0 ? yy + ny : (yy >= ny ? yy - ny : yy);
-      zz = zz < 0 ? zz + nz : (zz >= nz ? zz - nz : zz);
-      const float val = phi1[(size_t)zz * plane + (size_t)yy * nx + xx];
-      lo = fminf(lo, val);
-      hi = fmaxf(hi, val);
-      d[v] = val - centre;
+    if (8 * g + v < 27) {
+      lo = fminf(lo, val[v]);
+      hi = fmaxf(hi, val[v]);
+      d[v] = val[v] - centre;
       ss = fmaf(d[v], d[v], ss);
     }
   }
@@ -469,13 +498,51 @@ __device__ __forceinline__ NodeFeatures node_features(const float* __restrict__ 
 #pragma unroll
   for (int v = 0; v < 8; ++v) f.x[v] = (__bf16)(d[v] * inv);
   if (g == 3) {  // inputs 27..29: Courant numbers, 30..31 zero
-    f.x[3] = (__bf16)(ux[ic] * geo.lam[0]);
-    f.x[4] = (__bf16)(uy[ic] * geo.lam[1]);
-    f.x[5] = (__bf16)(uz[ic] * geo.lam[2]);
+    f.x[3] = (__bf16)cx;
+    f.x[4] = (__bf16)cy;
+    f.x[5] = (__bf16)cz;
     f.x[6] = (__bf16)0.f;
     f.x[7] = (__bf16)0.f;
   }
   return f;
+}
+
+// Gather with periodic wrap on every axis (any node).
+__device__ __forceinline__ NodeFeatures node_features(const float* __restrict__ phi1,
+                                                      const float* __restrict__ ux,
+                                                      const float* __restrict__ uy,
+                                                      const float* __restrict__ uz, const Geo& geo,
+                                                      int x, int y, int z, int g) {
+  const int nx = geo.nx, ny = geo.ny, nz = geo.nz;
+  const size_t plane = (size_t)nx * ny;
+  const size_t ic = (size_t)z * plane + (size_t)y * nx + x;
+  float val[8];
+#pragma unroll
+  for (int v = 0; v < 8; ++v) {
+    const int k = 8 * g + v;
+    val[v] = 0.f;
+    if (k < 27) {
+      const int dz = k / 9 - 1, dy = (k / 3) % 3 - 1, dx = k % 3 - 1;
+      int xx = x + dx, yy = y + dy, zz = z + dz;
+      xx = xx < 0 ? xx + nx : (xx >= nx ? xx - nx : xx);
+      yy = yy < 0 ? yy + ny : (yy >= ny ? yy - ny : yy);
+      zz = zz < 0 ? zz + nz : (zz >= nz ? zz - nz : zz);
+      val[v] = phi1[(size_t)zz * plane + (size_t)yy * nx + xx];
+    }
+  }
+  return features_from(val, phi1[ic], g, ux[ic] * geo.lam[0], uy[ic] * geo.lam[1],
+                       uz[ic] * geo.lam[2]);
+}
+
+// Buffer access with a 32-bit byte offset from a descriptor in scalar
+// registers (fields of at most 2^30 cells), for the interior gather.
+typedef __amdgpu_buffer_rsrc_t Rsrc;
+__device__ __forceinline__ Rsrc field_rsrc(const float* base, size_t n) {
+  const unsigned bytes = n >= (size_t(1) << 30) ? 0xFFFFFFFFu : unsigned(n) * 4u;
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(base), short(0), int(bytes), 0x00020000);
+}
+__device__ __forceinline__ float ld_at(Rsrc r, unsigned byte_off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, byte_off, 0, 0));
 }
 
 // Training pairs: features of the listed nodes (linear indices) from the CIR
@@ -512,7 +579,7 @@ __global__ __launch_bounds__(kThreads) void k_make_pairs(const float* __restrict
 // same number of iterations (forward_tile synchronises the workgroup).
 struct InferLds {
   WeightsLds W;
-  __bf16 h1[4][32 * NH];
+  __bf16 h1[4][32 * SH];
 };
 
 __global__ __launch_bounds__(kThreads) void k_learned_correct(const float* __restrict__ phi1,
@@ -522,15 +589,26 @@ __global__ __launch_bounds__(kThreads) void k_learned_correct(const float* __res
                                                               Geo geo,
                                                               const __bf16* __restrict__ wpack,
                                                               const float* __restrict__ wr,
-                                                              float* __restrict__ out) {
+                                                              float* __restrict__ out, bool fast) {
   extern __shared__ __align__(16) unsigned char smem[];
   InferLds& L = *reinterpret_cast<InferLds*>(smem);
-  load_weights(L.W, wpack, wr, false);
+  load_weights(L.W, nullptr, wpack, wr);
   __syncthreads();
   const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15, w = threadIdx.x >> 6;
   const int nxb = (geo.nx + 31) / 32;
   const int tiles = nxb * geo.ny * geo.nz;
   constexpr int WPB = kThreads / 64;
+  // interior rows: byte offsets of this lane's neighbours, computed once
+  const size_t ncells = (size_t)geo.nx * geo.ny * geo.nz;
+  const unsigned plane = unsigned(geo.nx) * unsigned(geo.ny);
+  const Rsrc rp = field_rsrc(phi1, ncells), rx = field_rsrc(ux, ncells);
+  const Rsrc ry = field_rsrc(uy, ncells), rz = field_rsrc(uz, ncells);
+  int noff[8];
+#pragma unroll
+  for (int v = 0; v < 8; ++v) {
+    const int k = min(8 * g + v, 26);
+    noff[v] = 4 * ((k / 9 - 1) * int(plane) + ((k / 3) % 3 - 1) * geo.nx + (k % 3 - 1));
+  }
   for (int t0 = blockIdx.x * WPB; t0 < tiles; t0 += gridDim.x * WPB) {
     const bool valid = t0 + w < tiles;
     const int t = valid ? t0 + w : tiles - 1;  // idle waves repeat the last tile, unstored
@@ -540,11 +618,24 @@ __global__ __launch_bounds__(kThreads) void k_learned_correct(const float* __res
     bf16x8 xb[2];
     float sig[2], cen[2], lo[2], hi[2];
     int xs[2];
+    // all 27 neighbours of the tile's 32 nodes inside the grid: no wrap
+    const bool interior = fast && xb0 >= 1 && xb0 + 32 <= geo.nx - 1 && y >= 1 && y <= geo.ny - 2 &&
+                          z >= 1 && z <= geo.nz - 2;
 #pragma unroll
     for (int jt = 0; jt < 2; ++jt) {
       xs[jt] = xb0 + 16 * jt + c;
       const int x = min(xs[jt], geo.nx - 1);  // lanes past the end repeat the last node
-      const NodeFeatures f = node_features(phi1, ux, uy, uz, geo, x, y, z, g);
+      NodeFeatures f;
+      if (interior) {
+        const unsigned ic4 = 4u * (unsigned(z) * plane + unsigned(y) * unsigned(geo.nx) + unsigned(x));
+        float val[8];
+#pragma unroll
+        for (int v = 0; v < 8; ++v) val[v] = ld_at(rp, ic4 + unsigned(noff[v]));
+        f = features_from(val, ld_at(rp, ic4), g, ld_at(rx, ic4) * geo.lam[0],
+                          ld_at(ry, ic4) * geo.lam[1], ld_at(rz, ic4) * geo.lam[2]);
+      } else {
+        f = node_features(phi1, ux, uy, uz, geo, x, y, z, g);
+      }
       xb[jt] = f.x;
       sig[jt] = f.sigma;
       cen[jt] = f.centre;
@@ -597,7 +688,7 @@ hipError_t launch_mlp(bool train, const void* X, const float* target, int m, flo
 
 hipError_t launch_grad_reduce(const float* gpart, const float* lpart, int nblk, float* grad,
                               double* loss_sum, hipStream_t st) {
-  hipLaunchKernelGGL(k_grad_reduce, dim3((kMlpParams + kThreads - 1) / kThreads), dim3(kThreads), 0,
+  hipLaunchKernelGGL(k_grad_reduce, dim3((kMlpParams + kRedParams - 1) / kRedParams), dim3(kThreads), 0,
                      st, gpart, lpart, nblk, grad, loss_sum);
   return hipGetLastError();
 }
@@ -634,7 +725,7 @@ hipError_t launch_learned_correct(const Geo& g, const float* phi1, const float* 
   const long long wave_tiles = (long long)((g.nx + 31) / 32) * g.ny * g.nz;
   const int blocks = int(std::min<long long>((wave_tiles + 3) / 4, kLearnedBlocks));
   hipLaunchKernelGGL(k_learned_correct, dim3(blocks), dim3(kThreads), bytes, st, phi1, u, u + n, u + 2 * n,
-                     g, static_cast<const __bf16*>(wpack), wr, out);
+                     g, static_cast<const __bf16*>(wpack), wr, out, n <= (size_t(1) << 30));
   return hipGetLastError();
 }
 

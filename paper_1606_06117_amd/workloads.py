@@ -176,6 +176,48 @@ def power_law(shape, seed, kmax=64, dtype=np.float32):
     return out.astype(dtype)
 
 
+def abc_velocity_torch(shape, device, A=1.0, B=1.0, C=1.0):
+    """``abc_velocity`` evaluated in FP64 by torch on ``device`` (for grids
+    too large to build on the host); FP32 (3, nz, ny, nx) tensor."""
+    import torch
+    nz, ny, nx = shape
+    f64 = dict(dtype=torch.float64, device=device)
+    x = torch.arange(nx, **f64) * (TWO_PI / nx)
+    y = torch.arange(ny, **f64) * (TWO_PI / ny)
+    z = torch.arange(nz, **f64) * (TWO_PI / nz)
+    u = torch.empty((3, nz, ny, nx), dtype=torch.float32, device=device)
+    u[0] = (A * torch.sin(z)[:, None, None] + C * torch.cos(y)[None, :, None]).float()
+    u[1] = (B * torch.sin(x)[None, None, :] + A * torch.cos(z)[:, None, None]).float()
+    u[2] = (C * torch.sin(y)[None, :, None] + B * torch.cos(x)[None, None, :]).float()
+    return u
+
+
+def power_law_torch(shape, seed, device, kmax=64):
+    """Isotropic random field with E(k) ~ k^-5/3 for 1 <= |k| <= kmax at unit
+    RMS, like ``power_law``, but with phases drawn (seeded) only for the
+    modes inside the box |k_d| <= kmax and the inverse FFT done by torch on
+    ``device`` in FP64; FP32 tensor."""
+    import torch
+    nz, ny, nx = shape
+    rng = np.random.default_rng(seed)
+    kb = np.arange(-kmax, kmax + 1)
+    kxb = np.arange(0, kmax + 1)
+    KZ, KY, KX = np.meshgrid(kb, kb, kxb, indexing="ij")
+    kk = np.sqrt(KX * KX + KY * KY + KZ * KZ)
+    with np.errstate(divide="ignore"):
+        amp = np.where((kk >= 1.0) & (kk <= kmax), kk ** (-11.0 / 6.0), 0.0)
+    ph = rng.uniform(0.0, TWO_PI, amp.shape)
+    block = torch.from_numpy(amp * np.exp(1j * ph)).to(device)
+    spec = torch.zeros((nz, ny, nx // 2 + 1), dtype=torch.complex128, device=device)
+    iz = torch.from_numpy(kb % nz).to(device)
+    iy = torch.from_numpy(kb % ny).to(device)
+    spec[iz[:, None, None], iy[None, :, None], torch.arange(kmax + 1, device=device)[None, None, :]] = block
+    out = torch.fft.irfftn(spec, s=(nz, ny, nx))
+    del spec
+    out /= torch.sqrt(torch.mean(out * out))
+    return out.float().contiguous()
+
+
 def abc_dt(shape, cfl, length=TWO_PI, umax=2.0):
     """Time step giving ``max |u_d| dt / dx = cfl`` on a cubic periodic box."""
     dx = length / shape[-1]

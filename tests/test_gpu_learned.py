@@ -164,9 +164,11 @@ def test_make_pairs_match_oracle_features(ctx):
     assert np.allclose(target.cpu().numpy(), tr, rtol=1e-4, atol=1e-6 * np.max(np.abs(tr)))
 
 
-@pytest.mark.parametrize("shape", [(16, 20, 36), (9, 11, 40)])
+@pytest.mark.parametrize("shape", [(16, 20, 36), (9, 11, 40), (12, 14, 100)])
 def test_learned_step_matches_oracle(ctx, shape):
-    """(9, 11, 40) has 198 row tiles: the last group of four leaves idle waves."""
+    """(9, 11, 40) has 198 row tiles: the last group of four leaves idle
+    waves.  (12, 14, 100) has interior row tiles (no neighbour wraps), which
+    take the gather without periodic wrap."""
     import torch
     from paper_1606_06117_amd import native
     phi = W.random_gaussians(shape, 4, seed=13).astype(np.float32)
