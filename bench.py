@@ -185,6 +185,7 @@ def cfl_section(ctx, size, cfls, steps):
     """The headline workload (8 Gaussians, ABC velocity) at larger Courant
     numbers: reach 2 and 3 take the three-sweep path (36 B per cell-update
     moved; 20 B algorithmic)."""
+    import numpy as np
     import torch
     from paper_1606_06117_amd import workloads as W
     shape = (size,) * 3
