@@ -128,7 +128,12 @@ typedef enum {
    * (direct global-to-LDS loads), 3 overlapped (first and last sweeps of
    * neighbouring planes run at once on different waves).  The batched plans
    * always use 2. */
-  SLA_OPT_CEC3D_KERNEL = 1
+  SLA_OPT_CEC3D_KERNEL = 1,
+  /* How the y and z sweeps of the third-order scheme run (same FP32
+   * operations, same results): 1 (default) each thread walks one column
+   * along the axis with its stencil in registers (grids of at most 2^30
+   * cells), 0 LDS tiles with the halo re-read per tile. */
+  SLA_OPT_SWEEP_KERNEL = 2
 } sla_option;
 /* Set option `option` to `value`.  Returns SLA_EINVAL for an unknown option
  * or value. */

@@ -12,6 +12,9 @@
 // Interpolation is p + f (q - p) with p the anchor: integer Courant numbers
 // and constant fields come out bit-exact.
 
+#include <algorithm>
+#include <utility>
+
 #include "common.h"
 
 #include "../../include/sla.h"
@@ -428,6 +431,173 @@ __global__ __launch_bounds__(kThreads) void k_sweep_x(const float* __restrict__ 
   });
 }
 
+// ---------------------------------------------------------------------------
+// Marching sweep along a strided axis (y or z), any reach R.  A thread owns
+// one column (x from the lane, the other strided coordinate from the
+// workgroup) and walks along the sweep axis over positions m = l0 - 3R ..
+// l1 - 1 + 3R, loading phi and the velocity once per node.  At step m:
+//   Phi1 of node m - R  (needs phi of m - 2R .. m),
+//   e    of node m - 2R (needs Phi1 of m - 3R .. m - R),
+//   out  of node m - 3R (needs e of m - 4R .. m - 2R).
+// Rings of K = 3R + 1 registers hold phi, Phi1, e and the Courant numbers,
+// node n at index (n - l0 + 3R) mod K; the walk is unrolled by K so that
+// every ring index is a compile-time constant.  Loads run K steps ahead
+// into a second register set.  Addresses are a per-thread byte offset plus
+// a row offset that is the same for the whole wave (a scalar register), so
+// a load or store needs no vector instruction.  No LDS and no barriers.
+// The arithmetic per node is that of k_sweep_s.  Fields of at most 2^30
+// cells (32-bit byte offsets).
+// ---------------------------------------------------------------------------
+typedef __amdgpu_buffer_rsrc_t Rsrc;
+__device__ __forceinline__ Rsrc field_rsrc(const float* base, size_t n) {
+  const unsigned bytes = n >= (size_t(1) << 30) ? 0xFFFFFFFFu : unsigned(n) * 4u;
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(base), short(0), int(bytes), 0x00020000);
+}
+__device__ __forceinline__ float ld_row(Rsrc r, unsigned voff, unsigned soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+__device__ __forceinline__ void st_row(Rsrc r, unsigned voff, unsigned soff, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
+}
+
+template <typename F, int... Is>
+__device__ __forceinline__ void static_for_impl(F& f, std::integer_sequence<int, Is...>) {
+  (f(std::integral_constant<int, Is>{}), ...);
+}
+// f(integral_constant<int, i>) for i = 0 .. N-1, unrolled
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+constexpr int pmod(int a, int k) { return ((a % k) + k) % k; }
+
+// Departure of a node as anchor direction and distance (the decomposition
+// of depart<R>, same clamp and flag): anchor = node - n if pos, node + n
+// otherwise; far = one further.
+struct DepN {
+  float f;
+  int n;
+  bool pos;
+};
+template <int R>
+__device__ __forceinline__ DepN depart_n(float c, int* flag) {
+  const float mag = fabsf(c);
+  float nf = floorf(mag);
+  const float f = mag - nf;
+  if (!(nf <= float(R - 1))) {
+    if (nf == nf) *flag = 1;
+    nf = float(R - 1);
+  }
+  return DepN{f, int(nf), c >= 0.f};
+}
+
+// A value passed through an empty asm statement: selects between such values
+// stay selects (the compiler otherwise turns selects between elements of one
+// register array into a dynamically indexed array in scratch memory).
+__device__ __forceinline__ float opaque(float v) {
+  asm("" : "+v"(v));
+  return v;
+}
+
+// Anchor and far values of a call at ring index BASE: the candidates
+// ring[BASE -+ k], k = 0 .. R, chosen by distance n, then by direction.
+template <int R, int K, int BASE>
+__device__ __forceinline__ void ring_pair(const float (&ring)[K], const DepN& d, float& a, float& b) {
+  const float c0 = opaque(ring[pmod(BASE, K)]);
+  float an_l = c0, an_r = c0;
+  float fa_l = opaque(ring[pmod(BASE - 1, K)]), fa_r = opaque(ring[pmod(BASE + 1, K)]);
+  float pl = fa_l, pr = fa_r;  // candidates at distance k
+#pragma unroll
+  for (int k = 1; k < R; ++k) {
+    const float nl = opaque(ring[pmod(BASE - k - 1, K)]), nr = opaque(ring[pmod(BASE + k + 1, K)]);
+    const bool hit = d.n == k;
+    an_l = hit ? pl : an_l;
+    an_r = hit ? pr : an_r;
+    fa_l = hit ? nl : fa_l;
+    fa_r = hit ? nr : fa_r;
+    pl = nl;
+    pr = nr;
+  }
+  a = d.pos ? an_l : an_r;
+  b = d.pos ? fa_l : fa_r;
+}
+
+template <int R>
+__global__ __launch_bounds__(kThreads) void k_sweep_m(const float* __restrict__ phi,
+                                                      const float* __restrict__ ud,
+                                                      float* __restrict__ out, int nx, int L,
+                                                      unsigned S4, unsigned So4, int nother,
+                                                      int chunk, unsigned ncells, float lam,
+                                                      int* flag) {
+  constexpr int K = 3 * R + 1;
+  const int x = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int other = blockIdx.y * (kThreads / 64) + (threadIdx.x >> 6);
+  if (x >= nx || other >= nother) return;
+  const int l0 = blockIdx.z * chunk;
+  const int l1 = min(l0 + chunk, L);
+  const unsigned voff = 4u * unsigned(x) + unsigned(other) * So4;
+  const Rsrc rp = field_rsrc(phi, ncells), ru = field_rsrc(ud, ncells), ro = field_rsrc(out, ncells);
+  auto wrapped = [&](int m) {
+    m %= L;
+    return m < 0 ? m + L : m;
+  };
+  const int m0 = l0 - 3 * R, m1 = l1 + 3 * R;  // steps m0 .. m1 - 1
+  float pr[K], p1[K], er[K], cr[K];  // rings
+  float np[K], nc[K];                // loads of the next K steps
+  int lrow = wrapped(m0);            // wrapped axis position of the next load
+#pragma unroll
+  for (int i = 0; i < K; ++i) {
+    pr[i] = p1[i] = er[i] = cr[i] = 0.f;
+    const unsigned ro_i = unsigned(lrow) * S4;
+    np[i] = ld_row(rp, voff, ro_i);
+    nc[i] = ld_row(ru, voff, ro_i);
+    lrow = lrow + 1 == L ? 0 : lrow + 1;
+  }
+  int srow = wrapped(m0 - 3 * R);  // wrapped axis position of node m - 3R
+  for (int mb = m0; mb < m1; mb += K) {
+    static_for<K>([&](auto ic) {
+      constexpr int i = decltype(ic)::value;
+      const int m = mb + i;
+      if (m >= m1) return;
+      pr[i] = np[i];
+      cr[i] = nc[i] * lam;
+      if (m + K < m1) {
+        const unsigned rn = unsigned(lrow) * S4;
+        np[i] = ld_row(rp, voff, rn);
+        nc[i] = ld_row(ru, voff, rn);
+      }
+      lrow = lrow + 1 == L ? 0 : lrow + 1;
+      // Phi1 of node m - R
+      constexpr int j1 = pmod(i - R, K);
+      {
+        const DepN d = depart_n<R>(cr[j1], flag);
+        float a, b;
+        ring_pair<R, K, j1>(pr, d, a, b);
+        p1[j1] = lerp(a, b, d.f);
+      }
+      // e of node m - 2R
+      constexpr int j2 = pmod(i - 2 * R, K);
+      {
+        const DepN d = depart_n<R>(-cr[j2], flag);
+        float a, b;
+        ring_pair<R, K, j2>(p1, d, a, b);
+        er[j2] = pr[j2] - lerp(a, b, d.f);
+      }
+      // out of node m - 3R
+      constexpr int j3 = pmod(i - 3 * R, K);
+      if (m - 3 * R >= l0) {
+        const DepN d = depart_n<R>(cr[j3], flag);
+        float ea, eb;
+        ring_pair<R, K, j3>(er, d, ea, eb);
+        const float w = fmaf(d.f, 1.f / 3.f, 1.f / 3.f);
+        st_row(ro, voff, unsigned(srow) * S4, fmaf(0.5f, fmaf(w, eb - ea, ea), p1[j3]));
+      }
+      srow = srow + 1 == L ? 0 : srow + 1;
+    });
+  }
+}
+
 template <typename F>
 hipError_t set_lds(F kernel, int bytes) {
   if (bytes <= 64 * 1024) return hipSuccess;
@@ -470,7 +640,21 @@ hipError_t launch_ec_r(int R, const Geo& g, const float* phi, const float* u, fl
 
 template <int R>
 hipError_t launch_sweep_t(int d, const Geo& g, const float* phi, const float* ud, float* out,
-                          int* flag, hipStream_t st) {
+                          int* flag, hipStream_t st, bool march) {
+  if (d != 0 && march && (size_t)g.ncells <= (size_t(1) << 30)) {
+    const int L = d == 1 ? g.ny : g.nz;
+    const int other = d == 1 ? g.nz : g.ny;
+    const unsigned S4 = 4u * unsigned(d == 1 ? g.nx : g.nx * g.ny);
+    const unsigned So4 = 4u * unsigned(d == 1 ? g.nx * g.ny : g.nx);
+    // enough waves to fill the chip (about 8 per CU), chunks of >= 16R nodes
+    const long long waves = (long long)((g.nx + 63) / 64) * other;
+    const int want = int(std::min<long long>((2048 + waves - 1) / waves, std::max(1, L / (16 * R))));
+    const int chunk = (L + want - 1) / want;
+    dim3 grid((g.nx + 63) / 64, (other + 3) / 4, (L + chunk - 1) / chunk);
+    hipLaunchKernelGGL(k_sweep_m<R>, grid, dim3(kThreads), 0, st, phi, ud, out, g.nx, L, S4, So4,
+                       other, chunk, unsigned(g.ncells), g.lam[d], flag);
+    return hipGetLastError();
+  }
   if (d == 0) {
     dim3 grid((g.nx + 255) / 256, (g.ny + 3) / 4, g.nz);
     hipLaunchKernelGGL(k_sweep_x<R>, grid, dim3(kThreads), 0, st, phi, ud, out, g.nx, g.ny,
@@ -525,12 +709,12 @@ hipError_t launch_ec(int ndim, int scheme, int R, const Geo& g, const float* phi
 }
 
 hipError_t launch_cec_sweep(int d, int R, const Geo& g, const float* phi, const float* ud,
-                            float* out, int* flag, hipStream_t st) {
+                            float* out, int* flag, hipStream_t st, bool march) {
   switch (R) {
-    case 1: return launch_sweep_t<1>(d, g, phi, ud, out, flag, st);
-    case 2: return launch_sweep_t<2>(d, g, phi, ud, out, flag, st);
-    case 3: return launch_sweep_t<3>(d, g, phi, ud, out, flag, st);
-    case 4: return launch_sweep_t<4>(d, g, phi, ud, out, flag, st);
+    case 1: return launch_sweep_t<1>(d, g, phi, ud, out, flag, st, march);
+    case 2: return launch_sweep_t<2>(d, g, phi, ud, out, flag, st, march);
+    case 3: return launch_sweep_t<3>(d, g, phi, ud, out, flag, st, march);
+    case 4: return launch_sweep_t<4>(d, g, phi, ud, out, flag, st, march);
   }
   return hipErrorInvalidValue;
 }

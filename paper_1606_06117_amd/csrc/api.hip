@@ -24,6 +24,7 @@ struct sla_ctx {
   std::string err;
   bool fused = true;    // SLA_OPT_FUSED
   int cec3d_kernel = 1;  // SLA_OPT_CEC3D_KERNEL
+  bool sweep_march = true;  // SLA_OPT_SWEEP_KERNEL
   // per-kernel timing
   bool timing = false;
   struct Mark { int kind; hipEvent_t a, b; };
@@ -373,7 +374,7 @@ int sla_advect(sla_ctx* ctx, const sla_grid* grid, float* phi, const float* u, d
           const int d = (m % 2 == 0) ? j : ndim - 1 - j;
           e = run(ctx, SLA_K_SWEEP_X + d, [&] {
             return sla::launch_cec_sweep(d, reach[d], geo, cur, u + size_t(d) * n, nxt,
-                                         ctx->flag, ctx->stream);
+                                         ctx->flag, ctx->stream, ctx->sweep_march);
           });
           std::swap(cur, nxt);
         }
@@ -402,6 +403,10 @@ int sla_set_option(sla_ctx* ctx, int option, int64_t value) {
       if (value < 0 || value >= sla::kCec3dVariants)
         return fail(ctx, SLA_EINVAL, "SLA_OPT_CEC3D_KERNEL takes 0..%d", sla::kCec3dVariants - 1);
       ctx->cec3d_kernel = int(value);
+      return SLA_OK;
+    case SLA_OPT_SWEEP_KERNEL:
+      if (value != 0 && value != 1) return fail(ctx, SLA_EINVAL, "SLA_OPT_SWEEP_KERNEL takes 0 or 1");
+      ctx->sweep_march = value != 0;
       return SLA_OK;
   }
   return fail(ctx, SLA_EINVAL, "unknown option %d", option);

@@ -34,8 +34,11 @@ hipError_t launch_ec(int ndim, int scheme, int R, const Geo& g, const float* phi
                      const float* u, float* out, int* flag, hipStream_t st);
 
 // One third-order sweep along axis d with reach R; u_d is that axis' plane.
+// march: y and z sweeps of grids of at most 2^30 cells walk columns through
+// registers (k_sweep_m); otherwise LDS tiles (k_sweep_s).  Same results.
 hipError_t launch_cec_sweep(int d, int R, const Geo& g, const float* phi,
-                            const float* u_d, float* out, int* flag, hipStream_t st);
+                            const float* u_d, float* out, int* flag, hipStream_t st,
+                            bool march = true);
 
 // Fused three-axis third-order step (reach 1 only): x,y,z order if even,
 // z,y,x otherwise.  variant: 0 LDS stages, 1 register segments, 2 streaming

@@ -22,6 +22,7 @@ OK, EINVAL, ECOURANT, EHIP, ENOMEM, ENOMODEL = 0, -1, -2, -3, -4, -5
 OPT_FUSED = 0
 OPT_CEC3D_KERNEL = 1
 CEC3D_DEFAULT = 1  # the library's default fused-step implementation
+OPT_SWEEP_KERNEL = 2
 
 # every symbol include/sla.h declares, with (restype, argtypes)
 _c = ctypes

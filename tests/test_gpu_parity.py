@@ -311,3 +311,36 @@ def test_fused_step_matches_sweeps(ctx, step0, variant):
     assert np.array_equal(fused, sweeps)
     ref = oracle_advect(phi, u, dx, dt, oracle.CEC, 3, step0=step0)
     check(fused, ref, phi, 3, f"fused step0={step0}")
+
+
+@pytest.mark.parametrize("shape,cfl,steps", [
+    ((40, 96, 24), 0.9, 2),    # reach 1, y axis chunked
+    ((40, 96, 24), 1.5, 3),    # reach 2
+    ((12, 33, 70), 2.5, 2),    # reach 3, ragged
+    ((8, 9, 70), 3.5, 2),      # reach 4: halo 12 > axis length 8 and 9
+    ((1, 50, 66), 3.5, 2),     # 2D (y sweep only)
+])
+def test_marching_sweeps_match_tiles(ctx, shape, cfl, steps):
+    """The y and z sweeps walking columns through registers give the same
+    bits as the LDS-tile sweeps (same FP32 operations per node)."""
+    from paper_1606_06117_amd import native
+    if shape[0] == 1:
+        shp = shape[1:]
+        phi = W.random_gaussians(shp, 5, seed=41).astype(np.float32)
+        u = W.cellular_velocity_2d(shp)
+    else:
+        shp = shape
+        phi = W.random_gaussians(shp, 5, seed=41).astype(np.float32)
+        u = W.abc_velocity(shp)
+    dx = tuple(2 * np.pi / n for n in reversed(shp))
+    umax = float(np.max(np.abs(u)))
+    dt = cfl * min(dx) / umax
+    ctx.set_option(native.OPT_FUSED, 0)
+    try:
+        march = gpu_advect(ctx, phi, u, dx, dt, oracle.CEC, steps, step0=1)
+        ctx.set_option(native.OPT_SWEEP_KERNEL, 0)
+        tiles = gpu_advect(ctx, phi, u, dx, dt, oracle.CEC, steps, step0=1)
+    finally:
+        ctx.set_option(native.OPT_SWEEP_KERNEL, 1)
+        ctx.set_option(native.OPT_FUSED, 1)
+    assert np.array_equal(march, tiles)
