@@ -318,7 +318,8 @@ def test_fused_step_matches_sweeps(ctx, step0, variant):
     ((40, 96, 24), 1.5, 3),    # reach 2
     ((12, 33, 70), 2.5, 2),    # reach 3, ragged
     ((8, 9, 70), 3.5, 2),      # reach 4: halo 12 > axis length 8 and 9
-    ((1, 50, 66), 3.5, 2),     # 2D (y sweep only)
+    ((1, 50, 66), 3.5, 2),     # 2D
+    ((64, 8, 16), 0.9, 2),     # z columns walked in 2 chunks
 ])
 def test_marching_sweeps_match_tiles(ctx, shape, cfl, steps):
     """The y and z sweeps walking columns through registers give the same
