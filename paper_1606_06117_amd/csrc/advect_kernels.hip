@@ -598,6 +598,59 @@ __global__ __launch_bounds__(kThreads) void k_sweep_m(const float* __restrict__ 
   }
 }
 
+// ---------------------------------------------------------------------------
+// Window sweep along x, any reach R.  A window is 64 consecutive x of one
+// row, x0 - 3R .. x0 + 60 - 3R (wrapped), one node per lane; a wave loads 4
+// consecutive windows of its row together.  A window
+// produces the 64 - 6R outputs x0 .. x0 + 63 - 6R; the anchor and far
+// values of each call are read from the lanes at the departure offsets
+// (__shfl, a cross-lane read): Phi1 is valid on lanes R .. 63 - R, e on
+// 2R .. 63 - 2R, the output on 3R .. 63 - 3R.  No LDS memory, no barriers.
+// The arithmetic per node is that of k_sweep_x.
+// ---------------------------------------------------------------------------
+template <int R>
+__global__ __launch_bounds__(kThreads) void k_sweep_xw(const float* __restrict__ phi,
+                                                       const float* __restrict__ ud,
+                                                       float* __restrict__ out, int nx, int nrows,
+                                                       int nwin, unsigned ncells, float lam,
+                                                       int* flag) {
+  constexpr int USE = 64 - 6 * R;  // outputs per window
+  constexpr int WPW = 4;           // windows per wave, loaded together
+  const int lane = threadIdx.x & 63;
+  const int wid = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
+  const int ngrp = (nwin + WPW - 1) / WPW;
+  const int row = wid / ngrp;
+  if (row >= nrows) return;
+  const int w0 = (wid - row * ngrp) * WPW;
+  const Rsrc rp = field_rsrc(phi, ncells), ru = field_rsrc(ud, ncells), ro = field_rsrc(out, ncells);
+  unsigned off[WPW];
+  float p[WPW], c[WPW];
+#pragma unroll
+  for (int k = 0; k < WPW; ++k) {
+    const int x = wrapk((w0 + k) * USE - 3 * R + lane, nx);
+    off[k] = 4u * (unsigned(row) * unsigned(nx) + unsigned(x));
+    p[k] = c[k] = 0.f;
+    if (w0 + k < nwin) {  // the same for the whole wave
+      p[k] = ld_row(rp, off[k], 0);
+      c[k] = ld_row(ru, off[k], 0);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < WPW; ++k) {
+    if (w0 + k >= nwin) break;
+    const float ck = c[k] * lam;
+    const Dep d = depart<R>(ck, flag);
+    const float p1 = lerp(__shfl(p[k], lane + d.oa), __shfl(p[k], lane + d.ob), d.f);
+    const Dep dr = depart<R>(-ck, flag);
+    const float e = p[k] - lerp(__shfl(p1, lane + dr.oa), __shfl(p1, lane + dr.ob), dr.f);
+    const float ea = __shfl(e, lane + d.oa), eb = __shfl(e, lane + d.ob);
+    const float w = fmaf(d.f, 1.f / 3.f, 1.f / 3.f);
+    const float o = fmaf(0.5f, fmaf(w, eb - ea, ea), p1);
+    const int xo = (w0 + k) * USE + lane - 3 * R;  // output node of this lane
+    if (lane >= 3 * R && lane < 64 - 3 * R && xo < nx) st_row(ro, off[k], 0, o);
+  }
+}
+
 template <typename F>
 hipError_t set_lds(F kernel, int bytes) {
   if (bytes <= 64 * 1024) return hipSuccess;
@@ -653,6 +706,14 @@ hipError_t launch_sweep_t(int d, const Geo& g, const float* phi, const float* ud
     dim3 grid((g.nx + 63) / 64, (other + 3) / 4, (L + chunk - 1) / chunk);
     hipLaunchKernelGGL(k_sweep_m<R>, grid, dim3(kThreads), 0, st, phi, ud, out, g.nx, L, S4, So4,
                        other, chunk, unsigned(g.ncells), g.lam[d], flag);
+    return hipGetLastError();
+  }
+  if (d == 0 && march && (size_t)g.ncells <= (size_t(1) << 30)) {
+    const int nrows = g.ny * g.nz;
+    const int nwin = (g.nx + 64 - 6 * R - 1) / (64 - 6 * R);
+    const long long waves = (long long)nrows * ((nwin + 3) / 4);
+    hipLaunchKernelGGL(k_sweep_xw<R>, dim3(unsigned((waves + 3) / 4)), dim3(kThreads), 0, st, phi, ud,
+                       out, g.nx, nrows, nwin, unsigned(g.ncells), g.lam[0], flag);
     return hipGetLastError();
   }
   if (d == 0) {
