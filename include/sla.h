@@ -124,10 +124,12 @@ typedef enum {
    * perform the same FP32 operations per node. */
   SLA_OPT_FUSED = 0,
   /* Which implementation runs the fused step (same FP32 operations, same
-   * results): 0 LDS stages, 1 register segments (default), 2 streaming
-   * (direct global-to-LDS loads), 3 overlapped (first and last sweeps of
-   * neighbouring planes run at once on different waves).  The batched plans
-   * always use 2. */
+   * results): 0 LDS stages, 1 register segments, 2 streaming (direct
+   * global-to-LDS loads), 3 overlapped (first and last sweeps of
+   * neighbouring planes run at once on different waves), 4 window march (no
+   * LDS: x across lanes, one axis in registers, one along the march),
+   * 5 (default) 1 on even steps and 4 on odd steps.  The batched plans always
+   * use 2. */
   SLA_OPT_CEC3D_KERNEL = 1,
   /* How the y and z sweeps of the third-order scheme run (same FP32
    * operations, same results): 1 (default) each thread walks one column

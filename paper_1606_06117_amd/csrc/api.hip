@@ -23,7 +23,7 @@ struct sla_ctx {
   void* host = nullptr;   // pinned staging for small results (256 bytes)
   std::string err;
   bool fused = true;    // SLA_OPT_FUSED
-  int cec3d_kernel = 1;  // SLA_OPT_CEC3D_KERNEL
+  int cec3d_kernel = 5;  // SLA_OPT_CEC3D_KERNEL
   bool sweep_march = true;  // SLA_OPT_SWEEP_KERNEL
   // per-kernel timing
   bool timing = false;

@@ -19,6 +19,7 @@
 // This kernel serves reach 1 (every |c| < 1): the departure interval of a
 // node is (i, i - s) and each call reads one neighbour.
 
+#include <algorithm>
 #include <type_traits>
 
 #include "common.h"
@@ -100,6 +101,11 @@ __device__ __forceinline__ int lidx(int x, int z) {
 __device__ __forceinline__ int wrap1(int v, int n) {
   v = v < 0 ? v + n : v;
   return v >= n ? v - n : v;
+}
+// wrap any coordinate into [0, n)
+__device__ __forceinline__ int wrapk(int v, int n) {
+  v %= n;
+  return v < 0 ? v + n : v;
 }
 
 // Tile (x tile, z tile, y chunk) of this workgroup.  Workgroups are handed
@@ -609,6 +615,200 @@ __global__ __launch_bounds__(kThreads, SLA_SEG_MIN_WAVES) void k_cec3d_seg(
     if (t + 2 < iters) body(std::integral_constant<int, 2>{}, t + 2);
   }
   if (over) *flag = 1;
+}
+
+// ---------------------------------------------------------------------------
+// Window-march variant (4): no LDS and no barriers; every wave works alone.
+// A wave covers a window of 64 consecutive x (one node per lane, the 58
+// middle lanes produce outputs) and a segment of V rows of a second axis,
+// and marches along the third.  The sweep along x reads the neighbour
+// values from the adjacent lanes; the sweep along the segment axis runs
+// in each thread's registers (sweep_segment, the segment grown by the 3-row
+// halo); the sweep along the march axis is the register pipeline.
+//   even step (x, y, z): x across lanes, y in the segment, z along the march;
+//   odd step  (z, y, x): z in the segment, y along the march, x across lanes.
+// Loads and stores use a per-lane byte offset (x) plus a row/plane offset
+// that is the same for the whole wave (scalar registers).
+// ---------------------------------------------------------------------------
+constexpr int kWmUse = 58;  // outputs per 64-lane window (reach 1: 3 halo lanes a side)
+
+// Third-order sweep along x of one node per lane (lanes are consecutive x);
+// the values of lanes 0 and 63 are not valid (their neighbours are outside).
+__device__ __forceinline__ float xsweep_lanes(float p, float c) {
+  const Dep1 d = depart1(c, nullptr);
+  const float pm = __shfl_up(p, 1), pp = __shfl_down(p, 1);
+  const float p1 = lerp(p, d.ob_neg ? pm : pp, d.f);
+  const float qm = __shfl_up(p1, 1), qp = __shfl_down(p1, 1);
+  const float e = p - lerp(p1, d.obr_pos ? qp : qm, d.f);
+  const float em = __shfl_up(e, 1), ep = __shfl_down(e, 1);
+  const float eb = d.ob_neg ? em : ep;
+  const float w = fmaf(d.f, 1.f / 3.f, 1.f / 3.f);
+  return fmaf(0.5f, fmaf(w, eb - e, e), p1);
+}
+
+// One step of the register pipeline along the march for V columns: a (the
+// new plane's input) enters at ring slot p0, cprev is the Courant number of
+// the previous plane; returns in out the output of the plane three back.
+template <int V, int P0>
+__device__ __forceinline__ void march_step(float (&ra)[3][V], float (&r1)[3][V], float (&re)[3][V],
+                                           float (&rc)[3][V], const float (&a)[V],
+                                           const float (&cprev)[V], float (&out)[V]) {
+  constexpr int p0 = P0, p1 = (P0 + 2) % 3, p2 = (P0 + 1) % 3, p3 = P0;
+#pragma unroll
+  for (int j = 0; j < V; ++j) {
+    ra[p0][j] = a[j];
+    rc[p1][j] = cprev[j];
+    Dep1 d = depart1(rc[p1][j], nullptr);
+    r1[p1][j] = lerp(ra[p1][j], d.ob_neg ? ra[p2][j] : ra[p0][j], d.f);
+    d = depart1(rc[p2][j], nullptr);
+    re[p2][j] = ra[p2][j] - lerp(r1[p2][j], d.obr_pos ? r1[p1][j] : r1[p3][j], d.f);
+    d = depart1(rc[p3][j], nullptr);
+    const float ea = re[p3][j];
+    const float eb = d.ob_neg ? re[p1][j] : re[p2][j];
+    const float w = fmaf(d.f, 1.f / 3.f, 1.f / 3.f);
+    out[j] = fmaf(0.5f, fmaf(w, eb - ea, ea), r1[p3][j]);
+  }
+}
+
+template <bool EVEN, int V>
+__global__ __launch_bounds__(kThreads) void k_cec3d_wm(const float* __restrict__ phi,
+                                                       const float* __restrict__ ux,
+                                                       const float* __restrict__ uy,
+                                                       const float* __restrict__ uz,
+                                                       float* __restrict__ out, Geo g, int chunk,
+                                                       int swz, int* flag) {
+  const int lane = threadIdx.x & 63;
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  // segment axis: y (even) or z (odd); march axis: z (even) or y (odd)
+  const int ns = EVEN ? ny : nz, nm = EVEN ? nz : ny;
+  const int nwx = (nx + kWmUse - 1) / kWmUse, nseg = (ns + V - 1) / V;
+  const int nch = (nm + chunk - 1) / chunk;
+  const int3 bt = block_tile(swz);  // 1D grid: bt.x is the (XCD-mapped) block
+  const int wid = bt.x * (kThreads / 64) + (threadIdx.x >> 6);
+  if (wid >= nwx * nseg * nch) return;  // the whole wave
+  const int wx = wid % nwx, sg = (wid / nwx) % nseg, ch = wid / (nwx * nseg);
+  const int xw = wx * kWmUse - 3 + lane;  // this lane's x (before wrap)
+  const unsigned vx = 4u * unsigned(wrapk(xw, nx));
+  const size_t ncells = size_t(nx) * ny * nz;
+  const unsigned rowb = 4u * unsigned(nx), plb = 4u * unsigned(nx) * unsigned(ny);
+  const unsigned sstr = EVEN ? rowb : plb;  // bytes per segment-axis step
+  const unsigned mstr = EVEN ? plb : rowb;  // bytes per march-axis step
+  const int s0 = sg * V, m0 = ch * chunk, m1 = min(m0 + chunk, nm);
+  // wave-uniform byte offsets of the segment rows s0 - 3 .. s0 + V + 2
+  unsigned soff[V + 6];
+#pragma unroll
+  for (int k = 0; k < V + 6; ++k)
+    soff[k] = unsigned(__builtin_amdgcn_readfirstlane(wrapk(s0 - 3 + k, ns))) * sstr;
+  const Rsrc rp = plane_rsrc(phi, ncells), rx = plane_rsrc(ux, ncells);
+  const Rsrc ry = plane_rsrc(uy, ncells), rz = plane_rsrc(uz, ncells), ro = plane_rsrc(out, ncells);
+  // first sweep's velocity (along x if even, along the segment if odd)
+  const Rsrc rA = EVEN ? rx : rz;
+  const Rsrc rS = EVEN ? ry : rz;  // segment-axis velocity
+  const Rsrc rM = EVEN ? rz : ry;  // march-axis velocity
+  const float lamX = g.lam[0], lamS = EVEN ? g.lam[1] : g.lam[2], lamM = EVEN ? g.lam[2] : g.lam[1];
+  auto moff = [&](int q) { return unsigned(__builtin_amdgcn_readfirstlane(wrapk(q, nm))) * mstr; };
+
+  // prefetched inputs of iteration t (march plane q_t = m0 - 3 + t)
+  float fp[V + 6];  // phi on the segment rows (+halo)
+  float fa[V + 6];  // even: x velocity on the same rows; odd: unused
+  float fs[V + 4];  // segment-axis velocity on rows s0 - 2 .. s0 + V + 1
+  float fm[V];      // march-axis velocity of plane q_{t-1}, rows s0 .. s0 + V - 1
+  float fx[V];      // odd: x velocity of the output plane q_{t-3}
+  auto prefetch = [&](int t) {
+    const unsigned q = moff(m0 - 3 + t), qm1 = moff(m0 - 4 + t), qo = moff(m0 - 6 + t);
+#pragma unroll
+    for (int k = 0; k < V + 6; ++k) {
+      fp[k] = ld_at(rp, vx + soff[k] + q);
+      if (EVEN) fa[k] = ld_at(rA, vx + soff[k] + q);
+    }
+#pragma unroll
+    for (int k = 0; k < V + 4; ++k) fs[k] = ld_at(rS, vx + soff[k + 1] + q);
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+      fm[j] = ld_at(rM, vx + soff[j + 3] + qm1);
+      if (!EVEN) fx[j] = ld_at(rx, vx + soff[j + 3] + qo);
+    }
+  };
+
+  float ra[3][V], r1[3][V], re[3][V], rc[3][V];
+#pragma unroll
+  for (int j = 0; j < V; ++j)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) ra[k][j] = r1[k][j] = re[k][j] = rc[k][j] = 0.f;
+
+  const int iters = (m1 - m0) + 6;
+  const bool lane_out = lane >= 3 && lane < 61 && wx * kWmUse + lane - 3 < nx;
+  bool over = false;
+  prefetch(0);
+  auto body = [&](auto phase, int t) {
+    constexpr int P0 = decltype(phase)::value;
+    float p[V + 6], cs[V + 4], cm[V], a[V], o[V];
+    float cxo[V];
+#pragma unroll
+    for (int k = 0; k < V + 6; ++k) {
+      p[k] = fp[k];
+      if (EVEN) {
+        const float c = fa[k] * lamX;
+        over |= over1(c);
+        p[k] = xsweep_lanes(p[k], c);  // first sweep (x) of this row
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < V + 4; ++k) {
+      cs[k] = fs[k] * lamS;
+      over |= over1(cs[k]);
+    }
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+      cm[j] = fm[j] * lamM;
+      over |= over1(cm[j]);
+      cxo[j] = EVEN ? 0.f : fx[j] * lamX;
+      if (!EVEN) over |= over1(cxo[j]);
+    }
+    if (t + 1 < iters) prefetch(t + 1);
+    // sweep along the segment axis (second for even, first for odd)
+    sweep_segment<V>(p, cs, a, flag);
+    // sweep along the march axis (even: last; odd: second)
+    march_step<V, P0>(ra, r1, re, rc, a, cm, o);
+    if (t >= 6) {
+      const unsigned qo = moff(m0 + t - 6);
+#pragma unroll
+      for (int j = 0; j < V; ++j) {
+        float v = o[j];
+        if (!EVEN) v = xsweep_lanes(v, cxo[j]);  // last sweep (x) of this row
+        if (lane_out && s0 + j < ns) st_at(ro, vx + soff[j + 3] + qo, v);
+      }
+    }
+  };
+  for (int t = 0; t < iters; t += 3) {
+    body(std::integral_constant<int, 0>{}, t);
+    if (t + 1 < iters) body(std::integral_constant<int, 1>{}, t + 1);
+    if (t + 2 < iters) body(std::integral_constant<int, 2>{}, t + 2);
+  }
+  if (over) *flag = 1;
+}
+
+template <int V>
+hipError_t launch_cec3d_wm(bool even, const Geo& g, const float* phi, const float* u, float* out,
+                           int* flag, hipStream_t st, Cec3dLaunch lc) {
+  const size_t n = (size_t)g.ncells;
+  const int ns = even ? g.ny : g.nz, nm = even ? g.nz : g.ny;
+  const long long layer = (long long)((g.nx + kWmUse - 1) / kWmUse) * ((ns + V - 1) / V);
+  // march chunks: enough waves for the chip (about 16 per CU), chunks >= 32
+  int chunk = lc.ychunk;
+  if (chunk <= 0) {
+    const long long want = std::max(1LL, std::min<long long>((4096 + layer - 1) / layer, nm / 32));
+    chunk = int((nm + want - 1) / want);
+  }
+  const long long waves = layer * ((nm + chunk - 1) / chunk);
+  dim3 grid(unsigned((waves + 3) / 4));
+  if (even)
+    hipLaunchKernelGGL((k_cec3d_wm<true, V>), grid, dim3(kThreads), 0, st, phi, u, u + n, u + 2 * n,
+                       out, g, chunk, lc.swizzle, flag);
+  else
+    hipLaunchKernelGGL((k_cec3d_wm<false, V>), grid, dim3(kThreads), 0, st, phi, u, u + n, u + 2 * n,
+                       out, g, chunk, lc.swizzle, flag);
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -1250,6 +1450,15 @@ hipError_t launch_cec3d(int variant, bool even, const Geo& g, const float* phi, 
                         float* out, int* flag, hipStream_t st, Cec3dLaunch lc) {
   if (variant == 1) return launch_cec3d_seg(even, g, phi, u, out, flag, st, lc);
   if (variant == 3) return launch_cec3d_ovl(even, g, phi, u, out, flag, st, lc);
+  if (variant == 4) return launch_cec3d_wm<4>(even, g, phi, u, out, flag, st, lc);
+  if (variant == 5) {
+    // the faster implementation of each parity at 512^3: segments with 128
+    // planes per workgroup for even steps, window march with 64 for odd
+    Cec3dLaunch l = lc;
+    if (l.ychunk <= 0) l.ychunk = even ? (g.ny >= 512 ? 128 : cec3d_default_ychunk(g)) : 64;
+    return even ? launch_cec3d_seg(true, g, phi, u, out, flag, st, l)
+                : launch_cec3d_wm<4>(false, g, phi, u, out, flag, st, l);
+  }
   if (variant == 2) return launch_cec3d_v4(even, g, phi, u, out, flag, st, lc);
   if (variant != 0) return hipErrorInvalidValue;
   const size_t n = (size_t)g.ncells;

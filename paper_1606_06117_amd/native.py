@@ -21,7 +21,7 @@ MAX_REACH = 4
 OK, EINVAL, ECOURANT, EHIP, ENOMEM, ENOMODEL = 0, -1, -2, -3, -4, -5
 OPT_FUSED = 0
 OPT_CEC3D_KERNEL = 1
-CEC3D_DEFAULT = 1  # the library's default fused-step implementation
+CEC3D_DEFAULT = 5  # the library's default fused-step implementation
 OPT_SWEEP_KERNEL = 2
 
 # every symbol include/sla.h declares, with (restype, argtypes)

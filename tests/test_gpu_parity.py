@@ -287,7 +287,7 @@ def test_abc_512_cfl09_cec_boxes(ctx):
     torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5])
 @pytest.mark.parametrize("step0", [0, 1])
 def test_fused_step_matches_sweeps(ctx, step0, variant):
     """At reach 1 the fused 3D step and the three sweep kernels evaluate the
