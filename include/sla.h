@@ -127,9 +127,10 @@ typedef enum {
    * results): 0 LDS stages, 1 register segments, 2 streaming (direct
    * global-to-LDS loads), 3 overlapped (first and last sweeps of
    * neighbouring planes run at once on different waves), 4 window march (no
-   * LDS: x across lanes, one axis in registers, one along the march),
-   * 5 (default) 1 on even steps and 4 on odd steps.  The batched plans always
-   * use 2. */
+   * LDS: x across lanes, 4-row segments of one axis in registers, the third
+   * axis along the march), 6 window march with 8-row segments, 5 (default)
+   * the fastest of 1, 4 and 6 for each parity and grid size (measured from
+   * 256^3 to 1024^3).  The batched plans always use 2. */
   SLA_OPT_CEC3D_KERNEL = 1,
   /* How the y and z sweeps of the third-order scheme run (same FP32
    * operations, same results): 1 (default) each thread walks one column

@@ -618,7 +618,8 @@ __global__ __launch_bounds__(kThreads, SLA_SEG_MIN_WAVES) void k_cec3d_seg(
 }
 
 // ---------------------------------------------------------------------------
-// Window-march variant (4): no LDS and no barriers; every wave works alone.
+// Window-march variants (4: V = 4, 6: V = 8): no LDS and no barriers; every
+// wave works alone.
 // A wave covers a window of 64 consecutive x (one node per lane, the 58
 // middle lanes produce outputs) and a segment of V rows of a second axis,
 // and marches along the third.  The sweep along x reads the neighbour
@@ -628,19 +629,33 @@ __global__ __launch_bounds__(kThreads, SLA_SEG_MIN_WAVES) void k_cec3d_seg(
 //   even step (x, y, z): x across lanes, y in the segment, z along the march;
 //   odd step  (z, y, x): z in the segment, y along the march, x across lanes.
 // Loads and stores use a per-lane byte offset (x) plus a row/plane offset
-// that is the same for the whole wave (scalar registers).
+// that is the same for the whole wave (scalar registers).  Each segment
+// reads V + 6 rows of phi for V rows of output, so longer segments read
+// less (V = 8: 1.45x the algorithmic loads issued against 1.79x for V = 4)
+// but hold twice the registers.
 // ---------------------------------------------------------------------------
 constexpr int kWmUse = 58;  // outputs per 64-lane window (reach 1: 3 halo lanes a side)
+
+// Value of the lane below (lane - 1) and above (lane + 1): DPP wave shifts
+// (one vector move each); lanes 0 and 63 receive their own value.
+__device__ __forceinline__ float from_below(float v) {
+  const int i = __builtin_bit_cast(int, v);
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(i, i, 0x138, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float from_above(float v) {
+  const int i = __builtin_bit_cast(int, v);
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(i, i, 0x130, 0xf, 0xf, false));
+}
 
 // Third-order sweep along x of one node per lane (lanes are consecutive x);
 // the values of lanes 0 and 63 are not valid (their neighbours are outside).
 __device__ __forceinline__ float xsweep_lanes(float p, float c) {
   const Dep1 d = depart1(c, nullptr);
-  const float pm = __shfl_up(p, 1), pp = __shfl_down(p, 1);
+  const float pm = from_below(p), pp = from_above(p);
   const float p1 = lerp(p, d.ob_neg ? pm : pp, d.f);
-  const float qm = __shfl_up(p1, 1), qp = __shfl_down(p1, 1);
+  const float qm = from_below(p1), qp = from_above(p1);
   const float e = p - lerp(p1, d.obr_pos ? qp : qm, d.f);
-  const float em = __shfl_up(e, 1), ep = __shfl_down(e, 1);
+  const float em = from_below(e), ep = from_above(e);
   const float eb = d.ob_neg ? em : ep;
   const float w = fmaf(d.f, 1.f / 3.f, 1.f / 3.f);
   return fmaf(0.5f, fmaf(w, eb - e, e), p1);
@@ -788,20 +803,42 @@ __global__ __launch_bounds__(kThreads) void k_cec3d_wm(const float* __restrict__
   if (over) *flag = 1;
 }
 
+// Window-march launch geometry: waves per march layer and the wave count
+// for a march chunk of c planes.
+struct WmShape {
+  long long layer;  // x windows x segments
+  int nm;           // march-axis length
+  long long waves(int c) const { return layer * ((nm + c - 1) / c); }
+};
+WmShape wm_shape(bool even, const Geo& g, int V) {
+  const int ns = even ? g.ny : g.nz, nm = even ? g.nz : g.ny;
+  return {(long long)((g.nx + kWmUse - 1) / kWmUse) * ((ns + V - 1) / V), nm};
+}
+// With 8-row segments a wave needs about 200 registers: 2 waves per SIMD,
+// 2048 on the chip (256 CUs).  Such long waves run best when the launch is
+// one nearly full pass over the chip or at least four (the last partial
+// pass then costs little).
+constexpr long long kWm8Resident = 2048;
+bool wm8_fills(long long waves) {
+  return (waves >= kWm8Resident * 9 / 10 && waves <= kWm8Resident) || waves >= 4 * kWm8Resident;
+}
+// March chunk (planes per wave), measured best at 256^3 .. 1024^3:
+// 4-row segments take 64 unless that leaves fewer than 3840 waves (15 per
+// CU), then 32, then 16; 8-row segments take the largest of 64, 32 that
+// fills the chip (above), else 16.
+int wm_default_chunk(const WmShape& s, int V) {
+  for (int c : {64, 32})
+    if (V >= 8 ? wm8_fills(s.waves(c)) : s.waves(c) >= 3840) return c;
+  return 16;
+}
+
 template <int V>
 hipError_t launch_cec3d_wm(bool even, const Geo& g, const float* phi, const float* u, float* out,
                            int* flag, hipStream_t st, Cec3dLaunch lc) {
   const size_t n = (size_t)g.ncells;
-  const int ns = even ? g.ny : g.nz, nm = even ? g.nz : g.ny;
-  const long long layer = (long long)((g.nx + kWmUse - 1) / kWmUse) * ((ns + V - 1) / V);
-  // march chunks: enough waves for the chip (about 16 per CU), chunks >= 32
-  int chunk = lc.ychunk;
-  if (chunk <= 0) {
-    const long long want = std::max(1LL, std::min<long long>((4096 + layer - 1) / layer, nm / 32));
-    chunk = int((nm + want - 1) / want);
-  }
-  const long long waves = layer * ((nm + chunk - 1) / chunk);
-  dim3 grid(unsigned((waves + 3) / 4));
+  const WmShape s = wm_shape(even, g, V);
+  const int chunk = lc.ychunk > 0 ? lc.ychunk : wm_default_chunk(s, V);
+  dim3 grid(unsigned((s.waves(chunk) + 3) / 4));
   if (even)
     hipLaunchKernelGGL((k_cec3d_wm<true, V>), grid, dim3(kThreads), 0, st, phi, u, u + n, u + 2 * n,
                        out, g, chunk, lc.swizzle, flag);
@@ -1451,13 +1488,21 @@ hipError_t launch_cec3d(int variant, bool even, const Geo& g, const float* phi, 
   if (variant == 1) return launch_cec3d_seg(even, g, phi, u, out, flag, st, lc);
   if (variant == 3) return launch_cec3d_ovl(even, g, phi, u, out, flag, st, lc);
   if (variant == 4) return launch_cec3d_wm<4>(even, g, phi, u, out, flag, st, lc);
+  if (variant == 6) return launch_cec3d_wm<8>(even, g, phi, u, out, flag, st, lc);
   if (variant == 5) {
-    // the faster implementation of each parity at 512^3: segments with 128
-    // planes per workgroup for even steps, window march with 64 for odd
-    Cec3dLaunch l = lc;
-    if (l.ychunk <= 0) l.ychunk = even ? (g.ny >= 512 ? 128 : cec3d_default_ychunk(g)) : 64;
-    return even ? launch_cec3d_seg(true, g, phi, u, out, flag, st, l)
-                : launch_cec3d_wm<4>(false, g, phi, u, out, flag, st, l);
+    // the fastest implementation of each parity as measured from 256^3 to
+    // 1024^3: up to 2^24 cells, register segments for even steps and the
+    // 4-row window march for odd ones; above, the 8-row window march, except
+    // on odd steps whose 8-row launch would not fill the chip (see wm8_fills)
+    if (g.ncells <= (1 << 24)) {
+      if (!even) return launch_cec3d_wm<4>(false, g, phi, u, out, flag, st, lc);
+      Cec3dLaunch l = lc;
+      if (l.ychunk <= 0) l.ychunk = g.ny >= 512 ? 128 : cec3d_default_ychunk(g);
+      return launch_cec3d_seg(true, g, phi, u, out, flag, st, l);
+    }
+    if (!even && !wm8_fills(wm_shape(false, g, 8).waves(64)))
+      return launch_cec3d_wm<4>(false, g, phi, u, out, flag, st, lc);
+    return launch_cec3d_wm<8>(even, g, phi, u, out, flag, st, lc);
   }
   if (variant == 2) return launch_cec3d_v4(even, g, phi, u, out, flag, st, lc);
   if (variant != 0) return hipErrorInvalidValue;

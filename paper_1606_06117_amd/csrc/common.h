@@ -43,9 +43,10 @@ hipError_t launch_cec_sweep(int d, int R, const Geo& g, const float* phi,
 // Fused three-axis third-order step (reach 1 only): x,y,z order if even,
 // z,y,x otherwise.  variant: 0 LDS stages, 1 register segments, 2 streaming
 // (direct global-to-LDS loads), 3 overlapped first/last sweeps, 4 window
-// march (no LDS), 5 segments for even steps and window march for odd ones;
-// all perform the same FP32 operations.
-constexpr int kCec3dVariants = 6;
+// march with 4-row segments (no LDS), 5 the fastest of these per parity
+// and grid size, 6 window march with 8-row segments; all perform the same
+// FP32 operations.
+constexpr int kCec3dVariants = 7;
 // Launch shape: y planes per workgroup (0: the default for the grid) and
 // whether tiles are mapped to XCDs in contiguous ranges (1) or round robin.
 struct Cec3dLaunch {

@@ -287,13 +287,14 @@ def test_abc_512_cfl09_cec_boxes(ctx):
     torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6])
 @pytest.mark.parametrize("step0", [0, 1])
-def test_fused_step_matches_sweeps(ctx, step0, variant):
+@pytest.mark.parametrize("shape", [(40, 48, 72), (37, 45, 130)])
+def test_fused_step_matches_sweeps(ctx, step0, variant, shape):
     """At reach 1 the fused 3D step and the three sweep kernels evaluate the
-    same FP32 operations per node, so their results agree bitwise."""
+    same FP32 operations per node, so their results agree bitwise.  The
+    second shape leaves partial x windows, row segments and march chunks."""
     from paper_1606_06117_amd import native
-    shape = (40, 48, 72)
     phi = W.random_gaussians(shape, 6, seed=31).astype(np.float32)
     u = W.abc_velocity(shape)
     dx = tuple(2 * np.pi / n for n in reversed(shape))
