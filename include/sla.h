@@ -119,23 +119,27 @@ int sla_advect(sla_ctx *ctx, const sla_grid *grid, float *phi, const float *u,
 /* Context options. */
 typedef enum {
   /* 1 (default): a 3D third-order step whose reach is 1 on every axis runs as
-   * one fused kernel (all three sweeps, 20 B per cell of HBM traffic).
-   * 0: every third-order step runs one sweep kernel per axis.  Both paths
-   * perform the same FP32 operations per node. */
+   * one fused kernel (all three sweeps, 20 B per cell of HBM traffic), on
+   * grids of fewer than 2^30 cells or of 2^30 cells with ny >= 2 (others
+   * run the sweeps).  0: every third-order step runs one sweep kernel per
+   * axis.  Both paths perform the same FP32 operations per node. */
   SLA_OPT_FUSED = 0,
   /* Which implementation runs the fused step (same FP32 operations, same
    * results): 0 LDS stages, 1 register segments, 2 streaming (direct
    * global-to-LDS loads), 3 overlapped (first and last sweeps of
    * neighbouring planes run at once on different waves), 4 window march (no
    * LDS: x across lanes, 4-row segments of one axis in registers, the third
-   * axis along the march), 6 window march with 8-row segments, 5 (default)
-   * the fastest of 1, 4 and 6 for each parity and grid size (measured from
-   * 256^3 to 1024^3).  The batched plans always use 2. */
+   * axis along the march), 6 window march with 8-row segments, 7 window
+   * march whose workgroups (2 or 3 windows, 2 waves each) share the segment
+   * halo rows through LDS, 5 (default) the fastest of 1, 4, 6 and 7 for each
+   * parity and grid size (measured from 256^3 to 1024^3).  The batched plans
+   * always use 2. */
   SLA_OPT_CEC3D_KERNEL = 1,
   /* How the y and z sweeps of the third-order scheme run (same FP32
    * operations, same results): 1 (default) each thread walks one column
-   * along the axis with its stencil in registers (grids of at most 2^30
-   * cells), 0 LDS tiles with the halo re-read per tile. */
+   * along the axis with its stencil in registers (grids of fewer than 2^30
+   * cells, or of 2^30 cells with ny >= 2), 0 LDS tiles with the halo re-read
+   * per tile. */
   SLA_OPT_SWEEP_KERNEL = 2
 } sla_option;
 /* Set option `option` to `value`.  Returns SLA_EINVAL for an unknown option
@@ -188,7 +192,8 @@ typedef struct sla_plan sla_plan; /* opaque; owns work memory and the graph */
  * extent of a tile, persistent grid size) on the problems (reading their
  * fields, writing only its own work memory) and keeps the fastest.  Work
  * memory: one field per problem.  The graph is built on a private stream.
- * Grids are 3D with at most 2^30 cells each (else SLA_EINVAL).
+ * Grids are 3D with at most 2^30 cells each, and ny >= 2 at 2^30 cells
+ * (else SLA_EINVAL).
  * Synchronises the context's stream. */
 int sla_plan_create(sla_ctx *ctx, sla_plan **out, int32_t nprob, const sla_problem *probs,
                     int32_t steps, int64_t step0, double courant_max, int32_t tune);

@@ -448,16 +448,28 @@ __global__ __launch_bounds__(kThreads) void k_sweep_x(const float* __restrict__ 
 // The arithmetic per node is that of k_sweep_s.  Fields of at most 2^30
 // cells (32-bit byte offsets).
 // ---------------------------------------------------------------------------
+// Access at a per-thread byte offset voff from the row or plane that starts
+// soff bytes into the field (soff the same for the whole wave): a buffer
+// descriptor rebased on that row or plane (two scalar adds), with the
+// largest size a descriptor holds, so only voff is range-checked.  A
+// descriptor on the field's start cannot cover a field of 2^30 cells (its
+// size tops out one byte short of 2^32 and would clip the last element).
+// voff + 4 stays below 2^32 when ny >= 2 or the field holds fewer than 2^30
+// cells (the launchers check that).
 typedef __amdgpu_buffer_rsrc_t Rsrc;
-__device__ __forceinline__ Rsrc field_rsrc(const float* base, size_t n) {
-  const unsigned bytes = n >= (size_t(1) << 30) ? 0xFFFFFFFFu : unsigned(n) * 4u;
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(base), short(0), int(bytes), 0x00020000);
+__device__ __forceinline__ Rsrc based_rsrc(const float* field, unsigned soff) {
+  // readfirstlane returns a signed int: widen the byte offset as unsigned
+  const size_t off = unsigned(__builtin_amdgcn_readfirstlane(int(soff)));
+  const char* b = reinterpret_cast<const char*>(field) + off;
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(b), short(0), int(0xFFFFFFFFu), 0x00020000);
 }
-__device__ __forceinline__ float ld_row(Rsrc r, unsigned voff, unsigned soff) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+__device__ __forceinline__ float ld_row(const float* field, unsigned voff, unsigned soff) {
+  return __builtin_bit_cast(float,
+                            __builtin_amdgcn_raw_buffer_load_b32(based_rsrc(field, soff), voff, 0, 0));
 }
-__device__ __forceinline__ void st_row(Rsrc r, unsigned voff, unsigned soff, float v) {
-  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
+__device__ __forceinline__ void st_row(float* field, unsigned voff, unsigned soff, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), based_rsrc(field, soff), voff,
+                                        0, 0);
 }
 
 template <typename F, int... Is>
@@ -537,7 +549,8 @@ __global__ __launch_bounds__(kThreads) void k_sweep_m(const float* __restrict__ 
   const int l0 = blockIdx.z * chunk;
   const int l1 = min(l0 + chunk, L);
   const unsigned voff = 4u * unsigned(x) + unsigned(other) * So4;
-  const Rsrc rp = field_rsrc(phi, ncells), ru = field_rsrc(ud, ncells), ro = field_rsrc(out, ncells);
+  const float *rp = phi, *ru = ud;
+  float* ro = out;
   auto wrapped = [&](int m) {
     m %= L;
     return m < 0 ? m + L : m;
@@ -622,17 +635,17 @@ __global__ __launch_bounds__(kThreads) void k_sweep_xw(const float* __restrict__
   const int row = wid / ngrp;
   if (row >= nrows) return;
   const int w0 = (wid - row * ngrp) * WPW;
-  const Rsrc rp = field_rsrc(phi, ncells), ru = field_rsrc(ud, ncells), ro = field_rsrc(out, ncells);
+  const unsigned rowoff = 4u * unsigned(row) * unsigned(nx);  // the same for the whole wave
   unsigned off[WPW];
   float p[WPW], c[WPW];
 #pragma unroll
   for (int k = 0; k < WPW; ++k) {
     const int x = wrapk((w0 + k) * USE - 3 * R + lane, nx);
-    off[k] = 4u * (unsigned(row) * unsigned(nx) + unsigned(x));
+    off[k] = 4u * unsigned(x);
     p[k] = c[k] = 0.f;
     if (w0 + k < nwin) {  // the same for the whole wave
-      p[k] = ld_row(rp, off[k], 0);
-      c[k] = ld_row(ru, off[k], 0);
+      p[k] = ld_row(phi, off[k], rowoff);
+      c[k] = ld_row(ud, off[k], rowoff);
     }
   }
 #pragma unroll
@@ -647,7 +660,7 @@ __global__ __launch_bounds__(kThreads) void k_sweep_xw(const float* __restrict__
     const float w = fmaf(d.f, 1.f / 3.f, 1.f / 3.f);
     const float o = fmaf(0.5f, fmaf(w, eb - ea, ea), p1);
     const int xo = (w0 + k) * USE + lane - 3 * R;  // output node of this lane
-    if (lane >= 3 * R && lane < 64 - 3 * R && xo < nx) st_row(ro, off[k], 0, o);
+    if (lane >= 3 * R && lane < 64 - 3 * R && xo < nx) st_row(out, off[k], rowoff, o);
   }
 }
 
@@ -694,7 +707,7 @@ hipError_t launch_ec_r(int R, const Geo& g, const float* phi, const float* u, fl
 template <int R>
 hipError_t launch_sweep_t(int d, const Geo& g, const float* phi, const float* ud, float* out,
                           int* flag, hipStream_t st, bool march) {
-  if (d != 0 && march && (size_t)g.ncells <= (size_t(1) << 30)) {
+  if (d != 0 && march && offsets32_ok(g)) {
     const int L = d == 1 ? g.ny : g.nz;
     const int other = d == 1 ? g.nz : g.ny;
     const unsigned S4 = 4u * unsigned(d == 1 ? g.nx : g.nx * g.ny);
@@ -708,7 +721,7 @@ hipError_t launch_sweep_t(int d, const Geo& g, const float* phi, const float* ud
                        other, chunk, unsigned(g.ncells), g.lam[d], flag);
     return hipGetLastError();
   }
-  if (d == 0 && march && (size_t)g.ncells <= (size_t(1) << 30)) {
+  if (d == 0 && march && offsets32_ok(g)) {
     const int nrows = g.ny * g.nz;
     const int nwin = (g.nx + 64 - 6 * R - 1) / (64 - 6 * R);
     const long long waves = (long long)nrows * ((nwin + 3) / 4);

@@ -341,7 +341,7 @@ int sla_advect(sla_ctx* ctx, const sla_grid* grid, float* phi, const float* u, d
   // A 3D third-order step whose reach is 1 on every axis runs as one fused
   // kernel (20 B/cell); other cases run one sweep kernel per axis.  The
   // fused kernels address a field with 32-bit byte offsets: up to 2^30 cells.
-  const bool fused3d = ctx->fused && ndim == 3 && rmax == 1 && geo.ncells <= (1 << 30);
+  const bool fused3d = ctx->fused && ndim == 3 && rmax == 1 && sla::offsets32_ok(geo);
   float* cur = phi;
   float* nxt = ctx->work;
   hipError_t e = hipSuccess;
@@ -863,6 +863,8 @@ int sla_plan_create(sla_ctx* ctx, sla_plan** out, int32_t nprob, const sla_probl
     if (!P[i].phi) return fail(ctx, SLA_EINVAL, "problem %d: phi is NULL", i);
     if (!std::isfinite(P[i].dt)) return fail(ctx, SLA_EINVAL, "problem %d: dt must be finite", i);
     const sla::Geo geo = make_geo(&P[i].grid, P[i].dt);
+    if (!sla::offsets32_ok(geo))
+      return fail(ctx, SLA_EINVAL, "problem %d: a plan's grid of 2^30 cells needs ny >= 2", i);
     float cm = 0.f;
     if (!P[i].u) {
       for (int d = 0; d < 3; ++d) {

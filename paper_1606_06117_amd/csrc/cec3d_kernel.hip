@@ -141,6 +141,29 @@ __device__ __forceinline__ float ld_at(Rsrc r, unsigned byte_off) {
 __device__ __forceinline__ void st_at(Rsrc r, unsigned byte_off, float v) {
   __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, byte_off, 0, 0);
 }
+// Access at a per-lane byte offset voff from the row or plane that starts
+// soff bytes into the field (soff the same for the whole wave).  The
+// descriptor is rebased on that row or plane (two scalar adds) and has the
+// largest size a descriptor holds, so voff alone is range-checked.  A
+// descriptor on the field's start cannot cover a field of 2^30 cells: its
+// size tops out one byte short of 2^32, which would clip the last element.
+// Callers keep voff + 4 <= 2^32 - 1: plane offsets go in soff whenever a
+// plane is the march unit, and a row offset otherwise (then voff spans at
+// most the field minus one row of planes: fine when ny >= 2 or the field
+// holds fewer than 2^30 cells; the launchers check that).
+__device__ __forceinline__ Rsrc based_rsrc(const float* field, unsigned soff) {
+  // readfirstlane returns a signed int: widen the byte offset as unsigned
+  const size_t off = unsigned(__builtin_amdgcn_readfirstlane(int(soff)));
+  const char* b = reinterpret_cast<const char*>(field) + off;
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(b), short(0), int(0xFFFFFFFFu), kRsrcWord3);
+}
+__device__ __forceinline__ float ld_vs(const float* field, unsigned voff, unsigned soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(based_rsrc(field, soff), voff, 0, 0));
+}
+__device__ __forceinline__ void st_vs(float* field, unsigned voff, unsigned soff, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), based_rsrc(field, soff), voff,
+                                        0, 0);
+}
 
 // Minimum waves per SIMD the compiler must leave room for (register budget).
 #ifndef SLA_CEC3D_MIN_WAVES
@@ -636,15 +659,50 @@ __global__ __launch_bounds__(kThreads, SLA_SEG_MIN_WAVES) void k_cec3d_seg(
 // ---------------------------------------------------------------------------
 constexpr int kWmUse = 58;  // outputs per 64-lane window (reach 1: 3 halo lanes a side)
 
+// Wrapped indices of five consecutive march planes, advanced by one plane at
+// a time without a division (the values are the same for the whole wave).
+struct PlaneWin {
+  int p[5];
+  int n;
+  __device__ PlaneWin(int first, int n_) : n(n_) {
+#pragma unroll
+    for (int k = 0; k < 5; ++k) p[k] = __builtin_amdgcn_readfirstlane(wrapk(first + k, n));
+  }
+  __device__ void advance() {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) p[k] = p[k + 1];
+    p[4] = p[4] + 1 < n ? p[4] + 1 : 0;
+  }
+};
+
+// Store V output rows of one plane: rows j < rows_left only (a uniform
+// test per row), lanes with lane_out only (one exec-mask region).
+// roff: per-lane byte offsets of the rows within a plane; q: the plane's.
+template <int V>
+__device__ __forceinline__ void store_rows(float* ro, const unsigned* roff, unsigned q,
+                                           const float (&o)[V], bool lane_out, int rows_left) {
+  if (!lane_out) return;
+  if (rows_left >= V) {
+#pragma unroll
+    for (int j = 0; j < V; ++j) st_vs(ro, roff[j], q, o[j]);
+  } else {
+#pragma unroll
+    for (int j = 0; j < V; ++j)
+      if (j < rows_left) st_vs(ro, roff[j], q, o[j]);
+  }
+}
+
 // Value of the lane below (lane - 1) and above (lane + 1): DPP wave shifts
-// (one vector move each); lanes 0 and 63 receive their own value.
+// (one vector move each, which the compiler can fold into the instruction
+// that uses it); lanes 0 and 63 receive 0.  Only halo lanes see those
+// zeros: a sweep's output is valid three lanes in from the window's edges.
 __device__ __forceinline__ float from_below(float v) {
   const int i = __builtin_bit_cast(int, v);
-  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(i, i, 0x138, 0xf, 0xf, false));
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, i, 0x138, 0xf, 0xf, true));
 }
 __device__ __forceinline__ float from_above(float v) {
   const int i = __builtin_bit_cast(int, v);
-  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(i, i, 0x130, 0xf, 0xf, false));
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, i, 0x130, 0xf, 0xf, true));
 }
 
 // Third-order sweep along x of one node per lane (lanes are consecutive x);
@@ -709,19 +767,22 @@ __global__ __launch_bounds__(kThreads) void k_cec3d_wm(const float* __restrict__
   const unsigned sstr = EVEN ? rowb : plb;  // bytes per segment-axis step
   const unsigned mstr = EVEN ? plb : rowb;  // bytes per march-axis step
   const int s0 = sg * V, m0 = ch * chunk, m1 = min(m0 + chunk, nm);
-  // wave-uniform byte offsets of the segment rows s0 - 3 .. s0 + V + 2
-  unsigned soff[V + 6];
+  // per-lane byte offsets of the segment rows s0 - 3 .. s0 + V + 2 within a
+  // march plane (the plane's offset goes in the instructions' scalar part)
+  unsigned vrow[V + 6];
 #pragma unroll
   for (int k = 0; k < V + 6; ++k)
-    soff[k] = unsigned(__builtin_amdgcn_readfirstlane(wrapk(s0 - 3 + k, ns))) * sstr;
-  const Rsrc rp = plane_rsrc(phi, ncells), rx = plane_rsrc(ux, ncells);
-  const Rsrc ry = plane_rsrc(uy, ncells), rz = plane_rsrc(uz, ncells), ro = plane_rsrc(out, ncells);
+    vrow[k] = vx + unsigned(__builtin_amdgcn_readfirstlane(wrapk(s0 - 3 + k, ns))) * sstr;
+  const float *rp = phi, *rx = ux;
+  float* ro = out;
   // first sweep's velocity (along x if even, along the segment if odd)
-  const Rsrc rA = EVEN ? rx : rz;
-  const Rsrc rS = EVEN ? ry : rz;  // segment-axis velocity
-  const Rsrc rM = EVEN ? rz : ry;  // march-axis velocity
+  const float* rA = EVEN ? ux : uz;
+  const float* rS = EVEN ? uy : uz;  // segment-axis velocity
+  const float* rM = EVEN ? uz : uy;  // march-axis velocity
   const float lamX = g.lam[0], lamS = EVEN ? g.lam[1] : g.lam[2], lamM = EVEN ? g.lam[2] : g.lam[1];
-  auto moff = [&](int q) { return unsigned(__builtin_amdgcn_readfirstlane(wrapk(q, nm))) * mstr; };
+  // wrapped march-plane indices of planes m0 - 6 + t .. m0 - 2 + t at
+  // iteration t, advanced by one plane per iteration (uniform, scalar)
+  PlaneWin pw(m0 - 6, nm);
 
   // prefetched inputs of iteration t (march plane q_t = m0 - 3 + t)
   float fp[V + 6];  // phi on the segment rows (+halo)
@@ -729,19 +790,22 @@ __global__ __launch_bounds__(kThreads) void k_cec3d_wm(const float* __restrict__
   float fs[V + 4];  // segment-axis velocity on rows s0 - 2 .. s0 + V + 1
   float fm[V];      // march-axis velocity of plane q_{t-1}, rows s0 .. s0 + V - 1
   float fx[V];      // odd: x velocity of the output plane q_{t-3}
-  auto prefetch = [&](int t) {
-    const unsigned q = moff(m0 - 3 + t), qm1 = moff(m0 - 4 + t), qo = moff(m0 - 6 + t);
+  // planes q_t, q_{t-1}, q_{t-3} of the iteration being prefetched (ahead =
+  // 0 for iteration t, 1 for t + 1)
+  auto prefetch = [&](int ahead) {
+    const unsigned q = unsigned(pw.p[3 + ahead]) * mstr, qm1 = unsigned(pw.p[2 + ahead]) * mstr,
+                   qo = unsigned(pw.p[ahead]) * mstr;
 #pragma unroll
     for (int k = 0; k < V + 6; ++k) {
-      fp[k] = ld_at(rp, vx + soff[k] + q);
-      if (EVEN) fa[k] = ld_at(rA, vx + soff[k] + q);
+      fp[k] = ld_vs(rp, vrow[k], q);
+      if (EVEN) fa[k] = ld_vs(rA, vrow[k], q);
     }
 #pragma unroll
-    for (int k = 0; k < V + 4; ++k) fs[k] = ld_at(rS, vx + soff[k + 1] + q);
+    for (int k = 0; k < V + 4; ++k) fs[k] = ld_vs(rS, vrow[k + 1], q);
 #pragma unroll
     for (int j = 0; j < V; ++j) {
-      fm[j] = ld_at(rM, vx + soff[j + 3] + qm1);
-      if (!EVEN) fx[j] = ld_at(rx, vx + soff[j + 3] + qo);
+      fm[j] = ld_vs(rM, vrow[j + 3], qm1);
+      if (!EVEN) fx[j] = ld_vs(rx, vrow[j + 3], qo);
     }
   };
 
@@ -780,20 +844,19 @@ __global__ __launch_bounds__(kThreads) void k_cec3d_wm(const float* __restrict__
       cxo[j] = EVEN ? 0.f : fx[j] * lamX;
       if (!EVEN) over |= over1(cxo[j]);
     }
-    if (t + 1 < iters) prefetch(t + 1);
+    if (t + 1 < iters) prefetch(1);
     // sweep along the segment axis (second for even, first for odd)
     sweep_segment<V>(p, cs, a, flag);
     // sweep along the march axis (even: last; odd: second)
     march_step<V, P0>(ra, r1, re, rc, a, cm, o);
     if (t >= 6) {
-      const unsigned qo = moff(m0 + t - 6);
+      const unsigned qo = unsigned(pw.p[0]) * mstr;
+      if (!EVEN)
 #pragma unroll
-      for (int j = 0; j < V; ++j) {
-        float v = o[j];
-        if (!EVEN) v = xsweep_lanes(v, cxo[j]);  // last sweep (x) of this row
-        if (lane_out && s0 + j < ns) st_at(ro, vx + soff[j + 3] + qo, v);
-      }
+        for (int j = 0; j < V; ++j) o[j] = xsweep_lanes(o[j], cxo[j]);  // last sweep (x)
+      store_rows<V>(ro, vrow + 3, qo, o, lane_out, ns - s0);
     }
+    pw.advance();
   };
   for (int t = 0; t < iters; t += 3) {
     body(std::integral_constant<int, 0>{}, t);
@@ -846,6 +909,190 @@ hipError_t launch_cec3d_wm(bool even, const Geo& g, const float* phi, const floa
     hipLaunchKernelGGL((k_cec3d_wm<false, V>), grid, dim3(kThreads), 0, st, phi, u, u + n, u + 2 * n,
                        out, g, chunk, lc.swizzle, flag);
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Window march with shared segment halos (variant 7).  A workgroup of WX x W
+// waves takes WX consecutive 64-lane x windows and, in each, W consecutive
+// V-row segments (S = W*V rows), and marches them together along the third
+// axis.  The S + 6 rows the segment-axis sweep reads are loaded once per
+// window instead of V + 6 per wave: wave w of a window loads the
+// R = V + 6/W rows w*R .. w*R + R - 1 of the grown segment, stores what the
+// segment sweep needs in LDS (even: the x-swept phi and the y Courant
+// numbers; odd: phi and the z Courant numbers), and after one barrier per
+// march plane every wave reads its V + 6 rows back.  The neighbouring
+// windows of one workgroup share the 128-byte lines their 3-lane x halos
+// straddle.  The LDS is double-buffered, so a wave writing plane t+1 never
+// meets one still reading plane t.  The march-axis velocity (and on odd
+// steps the x velocity of the output plane) is read for the wave's own
+// rows only.  Windows past the row's end (when WX does not divide the
+// window count) only take part in the barriers.  Same FP32 operations per
+// node as the other variants.
+// ---------------------------------------------------------------------------
+template <bool EVEN, int V, int W, int WX>
+__global__ __launch_bounds__(64 * W * WX) void k_cec3d_wl(const float* __restrict__ phi,
+                                                          const float* __restrict__ ux,
+                                                          const float* __restrict__ uy,
+                                                          const float* __restrict__ uz,
+                                                          float* __restrict__ out, Geo g, int chunk,
+                                                          int swz, int* flag) {
+  static_assert(6 % W == 0, "the 6 halo rows must split evenly over the waves");
+  constexpr int S = V * W, R = V + 6 / W, NR = S + 6;
+  __shared__ float lp[2][WX][NR][64];  // segment sweep input (phi, x-swept if even)
+  __shared__ float lc[2][WX][NR][64];  // segment-axis Courant numbers
+  const int lane = threadIdx.x & 63, xi = (threadIdx.x >> 6) % WX, w = (threadIdx.x >> 6) / WX;
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  const int ns = EVEN ? ny : nz, nm = EVEN ? nz : ny;
+  const int nwx = (nx + kWmUse - 1) / kWmUse, ngx = (nwx + WX - 1) / WX, ngs = (ns + S - 1) / S;
+  const int nch = (nm + chunk - 1) / chunk;
+  const int blk = block_tile(swz).x;  // 1D grid, XCD-mapped
+  if (blk >= ngx * ngs * nch) return;  // the whole workgroup
+  const int wx0 = (blk % ngx) * WX, gs = (blk / ngx) % ngs, ch = blk / (ngx * ngs);
+  const bool wx_ok = wx0 + xi < nwx;  // the same for the whole wave
+  const int wx = min(wx0 + xi, nwx - 1);
+  const int xw = wx * kWmUse - 3 + lane;
+  const unsigned vx = 4u * unsigned(wrapk(xw, nx));
+  const size_t ncells = size_t(nx) * ny * nz;
+  const unsigned rowb = 4u * unsigned(nx), plb = 4u * unsigned(nx) * unsigned(ny);
+  const unsigned sstr = EVEN ? rowb : plb, mstr = EVEN ? plb : rowb;
+  const int g0 = gs * S, s0 = g0 + w * V, m0 = ch * chunk, m1 = min(m0 + chunk, nm);
+  // per-lane byte offsets within a march plane of the rows this wave loads
+  // (grown-segment rows w*R + k) and of its output rows
+  unsigned loff[R], ooff[V];
+#pragma unroll
+  for (int k = 0; k < R; ++k)
+    loff[k] = vx + unsigned(__builtin_amdgcn_readfirstlane(wrapk(g0 - 3 + w * R + k, ns))) * sstr;
+#pragma unroll
+  for (int j = 0; j < V; ++j)
+    ooff[j] = vx + unsigned(__builtin_amdgcn_readfirstlane(wrapk(s0 + j, ns))) * sstr;
+  const float *rp = phi, *rx = ux;
+  float* ro = out;
+  const float* rS = EVEN ? uy : uz;  // segment-axis velocity
+  const float* rM = EVEN ? uz : uy;  // march-axis velocity
+  const float lamX = g.lam[0], lamS = EVEN ? g.lam[1] : g.lam[2], lamM = EVEN ? g.lam[2] : g.lam[1];
+  PlaneWin pw(m0 - 6, nm);  // planes m0 - 6 + t .. m0 - 2 + t at iteration t
+
+  float fp[R], fa[R], fs[R];  // phi, x velocity (even), segment velocity on the loaded rows
+  float fm[V], fx[V];         // march velocity of plane q-1; odd: x velocity of the output plane
+  auto prefetch = [&](int ahead) {  // 0: iteration t; 1: iteration t + 1
+    const unsigned q = unsigned(pw.p[3 + ahead]) * mstr, qm1 = unsigned(pw.p[2 + ahead]) * mstr,
+                   qo = unsigned(pw.p[ahead]) * mstr;
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      fp[k] = ld_vs(rp, loff[k], q);
+      if (EVEN) fa[k] = ld_vs(rx, loff[k], q);
+      fs[k] = ld_vs(rS, loff[k], q);
+    }
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+      fm[j] = ld_vs(rM, ooff[j], qm1);
+      if (!EVEN) fx[j] = ld_vs(rx, ooff[j], qo);
+    }
+  };
+
+  float ra[3][V], r1[3][V], re[3][V], rc[3][V];
+#pragma unroll
+  for (int j = 0; j < V; ++j)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) ra[k][j] = r1[k][j] = re[k][j] = rc[k][j] = 0.f;
+
+  const int iters = (m1 - m0) + 6;
+  const bool lane_out = lane >= 3 && lane < 61 && wx * kWmUse + lane - 3 < nx;
+  bool over = false;
+  if (wx_ok) prefetch(0);
+  auto body = [&](auto phase, int t) {
+    constexpr int P0 = decltype(phase)::value;
+    const int b = t & 1;
+    if (!wx_ok) {  // a window past the row's end: barriers only
+      __syncthreads();
+      return;
+    }
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      float v = fp[k];
+      if (EVEN) {
+        const float c = fa[k] * lamX;
+        over |= over1(c);
+        v = xsweep_lanes(v, c);  // first sweep (x) of this row
+      }
+      const float c = fs[k] * lamS;
+      over |= over1(c);
+      lp[b][xi][w * R + k][lane] = v;
+      lc[b][xi][w * R + k][lane] = c;
+    }
+    float cm[V], cxo[V];
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+      cm[j] = fm[j] * lamM;
+      over |= over1(cm[j]);
+      cxo[j] = EVEN ? 0.f : fx[j] * lamX;
+      if (!EVEN) over |= over1(cxo[j]);
+    }
+    if (t + 1 < iters) prefetch(1);
+    __syncthreads();
+    float p[V + 6], cs[V + 4], a[V], o[V];
+#pragma unroll
+    for (int k = 0; k < V + 6; ++k) p[k] = lp[b][xi][w * V + k][lane];
+#pragma unroll
+    for (int k = 0; k < V + 4; ++k) cs[k] = lc[b][xi][w * V + 1 + k][lane];
+    // sweep along the segment axis (second for even, first for odd)
+    sweep_segment<V>(p, cs, a, flag);
+    // sweep along the march axis (even: last; odd: second)
+    march_step<V, P0>(ra, r1, re, rc, a, cm, o);
+    if (t >= 6) {
+      const unsigned qo = unsigned(pw.p[0]) * mstr;
+      if (!EVEN)
+#pragma unroll
+        for (int j = 0; j < V; ++j) o[j] = xsweep_lanes(o[j], cxo[j]);  // last sweep (x)
+      store_rows<V>(ro, ooff, qo, o, lane_out, ns - s0);
+    }
+    pw.advance();
+  };
+  for (int t = 0; t < iters; t += 3) {
+    body(std::integral_constant<int, 0>{}, t);
+    if (t + 1 < iters) body(std::integral_constant<int, 1>{}, t + 1);
+    if (t + 2 < iters) body(std::integral_constant<int, 2>{}, t + 2);
+  }
+  if (over) *flag = 1;
+}
+
+// x windows per workgroup of the shared-halo march: 3 or 2 when that divides
+// the window count (no surplus windows), else 0 (no such choice).
+int wl_windows(const Geo& g) {
+  const int nwx = (g.nx + kWmUse - 1) / kWmUse;
+  return nwx % 3 == 0 ? 3 : nwx % 2 == 0 ? 2 : 0;
+}
+
+// V = 8 rows per wave, W = 2 waves per window, WX windows per workgroup
+// (3 if that divides the window count, else 2).  March chunk: 64 planes
+// unless that leaves fewer than 512 workgroups (two per CU), then 32, then 16.
+template <int WX>
+hipError_t launch_cec3d_wl_x(bool even, const Geo& g, const float* phi, const float* u, float* out,
+                             int* flag, hipStream_t st, Cec3dLaunch lc) {
+  constexpr int V = 8, W = 2;
+  const size_t n = (size_t)g.ncells;
+  const int ns = even ? g.ny : g.nz, nm = even ? g.nz : g.ny;
+  const long long groups =
+      (long long)(((g.nx + kWmUse - 1) / kWmUse + WX - 1) / WX) * ((ns + V * W - 1) / (V * W));
+  int chunk = lc.ychunk;
+  if (chunk <= 0) {
+    chunk = 16;
+    for (int c : {64, 32})
+      if (groups * ((nm + c - 1) / c) >= 512) { chunk = c; break; }
+  }
+  dim3 grid(unsigned(groups * ((nm + chunk - 1) / chunk)));
+  if (even)
+    hipLaunchKernelGGL((k_cec3d_wl<true, V, W, WX>), grid, dim3(64 * W * WX), 0, st, phi, u, u + n,
+                       u + 2 * n, out, g, chunk, lc.swizzle, flag);
+  else
+    hipLaunchKernelGGL((k_cec3d_wl<false, V, W, WX>), grid, dim3(64 * W * WX), 0, st, phi, u, u + n,
+                       u + 2 * n, out, g, chunk, lc.swizzle, flag);
+  return hipGetLastError();
+}
+hipError_t launch_cec3d_wl(bool even, const Geo& g, const float* phi, const float* u, float* out,
+                           int* flag, hipStream_t st, Cec3dLaunch lc) {
+  return wl_windows(g) == 3 ? launch_cec3d_wl_x<3>(even, g, phi, u, out, flag, st, lc)
+                            : launch_cec3d_wl_x<2>(even, g, phi, u, out, flag, st, lc);
 }
 
 // ---------------------------------------------------------------------------
@@ -1489,17 +1736,20 @@ hipError_t launch_cec3d(int variant, bool even, const Geo& g, const float* phi, 
   if (variant == 3) return launch_cec3d_ovl(even, g, phi, u, out, flag, st, lc);
   if (variant == 4) return launch_cec3d_wm<4>(even, g, phi, u, out, flag, st, lc);
   if (variant == 6) return launch_cec3d_wm<8>(even, g, phi, u, out, flag, st, lc);
+  if (variant == 7) return launch_cec3d_wl(even, g, phi, u, out, flag, st, lc);
   if (variant == 5) {
     // the fastest implementation of each parity as measured from 256^3 to
     // 1024^3: up to 2^24 cells, register segments for even steps and the
-    // 4-row window march for odd ones; above, the 8-row window march, except
-    // on odd steps whose 8-row launch would not fill the chip (see wm8_fills)
+    // 4-row window march for odd ones; above, the shared-halo march when 2
+    // or 3 divides the window count, else the 8-row window march, except on
+    // odd steps whose 8-row launch would not fill the chip (see wm8_fills)
     if (g.ncells <= (1 << 24)) {
       if (!even) return launch_cec3d_wm<4>(false, g, phi, u, out, flag, st, lc);
       Cec3dLaunch l = lc;
       if (l.ychunk <= 0) l.ychunk = g.ny >= 512 ? 128 : cec3d_default_ychunk(g);
       return launch_cec3d_seg(true, g, phi, u, out, flag, st, l);
     }
+    if (wl_windows(g) > 0) return launch_cec3d_wl(even, g, phi, u, out, flag, st, lc);
     if (!even && !wm8_fills(wm_shape(false, g, 8).waves(64)))
       return launch_cec3d_wm<4>(false, g, phi, u, out, flag, st, lc);
     return launch_cec3d_wm<8>(even, g, phi, u, out, flag, st, lc);

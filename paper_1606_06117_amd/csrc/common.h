@@ -16,6 +16,15 @@ struct Geo {
   float lam[3];
 };
 
+// Kernels that address a field by 32-bit byte offsets from a row or plane
+// start (the fused step, the marching sweeps): every offset + 4 stays below
+// 2^32 for fields of fewer than 2^30 cells, and of exactly 2^30 cells when
+// ny >= 2 (an offset then spans at most the field minus one row).
+inline bool offsets32_ok(const Geo& g) {
+  const size_t n = (size_t)g.ncells, lim = size_t(1) << 30;
+  return n < lim || (n == lim && g.ny >= 2);
+}
+
 // Reach (halo in cells) each kernel serves, one per axis: reach[d] =
 // floor(max |c_d|) + 1, at most SLA_MAX_REACH.
 struct Reach {
@@ -44,9 +53,10 @@ hipError_t launch_cec_sweep(int d, int R, const Geo& g, const float* phi,
 // z,y,x otherwise.  variant: 0 LDS stages, 1 register segments, 2 streaming
 // (direct global-to-LDS loads), 3 overlapped first/last sweeps, 4 window
 // march with 4-row segments (no LDS), 5 the fastest of these per parity
-// and grid size, 6 window march with 8-row segments; all perform the same
-// FP32 operations.
-constexpr int kCec3dVariants = 7;
+// and grid size, 6 window march with 8-row segments, 7 window march whose
+// workgroups share segment halos through LDS; all perform the same FP32
+// operations.
+constexpr int kCec3dVariants = 8;
 // Launch shape: y planes per workgroup (0: the default for the grid) and
 // whether tiles are mapped to XCDs in contiguous ranges (1) or round robin.
 struct Cec3dLaunch {

@@ -535,7 +535,9 @@ __device__ __forceinline__ NodeFeatures node_features(const float* __restrict__ 
 }
 
 // Buffer access with a 32-bit byte offset from a descriptor in scalar
-// registers (fields of at most 2^30 cells), for the interior gather.
+// registers, for the interior gather: fields of fewer than 2^30 cells (a
+// descriptor's size tops out one byte short of 2^32, so at 2^30 cells it
+// would clip the field's last element; such fields take the wrapping path).
 typedef __amdgpu_buffer_rsrc_t Rsrc;
 __device__ __forceinline__ Rsrc field_rsrc(const float* base, size_t n) {
   const unsigned bytes = n >= (size_t(1) << 30) ? 0xFFFFFFFFu : unsigned(n) * 4u;
@@ -725,7 +727,7 @@ hipError_t launch_learned_correct(const Geo& g, const float* phi1, const float* 
   const long long wave_tiles = (long long)((g.nx + 31) / 32) * g.ny * g.nz;
   const int blocks = int(std::min<long long>((wave_tiles + 3) / 4, kLearnedBlocks));
   hipLaunchKernelGGL(k_learned_correct, dim3(blocks), dim3(kThreads), bytes, st, phi1, u, u + n, u + 2 * n,
-                     g, static_cast<const __bf16*>(wpack), wr, out, n <= (size_t(1) << 30));
+                     g, static_cast<const __bf16*>(wpack), wr, out, n < (size_t(1) << 30));
   return hipGetLastError();
 }
 

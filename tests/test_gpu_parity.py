@@ -287,13 +287,15 @@ def test_abc_512_cfl09_cec_boxes(ctx):
     torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6, 7])
 @pytest.mark.parametrize("step0", [0, 1])
-@pytest.mark.parametrize("shape", [(40, 48, 72), (37, 45, 130)])
+@pytest.mark.parametrize("shape", [(40, 48, 72), (37, 45, 130), (13, 11, 250)])
 def test_fused_step_matches_sweeps(ctx, step0, variant, shape):
     """At reach 1 the fused 3D step and the three sweep kernels evaluate the
     same FP32 operations per node, so their results agree bitwise.  The
-    second shape leaves partial x windows, row segments and march chunks."""
+    second shape leaves partial x windows, row segments and march chunks;
+    the third has 5 x windows (a workgroup of 2 windows past the row's end)
+    and fewer rows than one shared-halo workgroup holds."""
     from paper_1606_06117_amd import native
     phi = W.random_gaussians(shape, 6, seed=31).astype(np.float32)
     u = W.abc_velocity(shape)
@@ -346,6 +348,52 @@ def test_marching_sweeps_match_tiles(ctx, shape, cfl, steps):
         ctx.set_option(native.OPT_SWEEP_KERNEL, 1)
         ctx.set_option(native.OPT_FUSED, 1)
     assert np.array_equal(march, tiles)
+
+
+def test_fused_1024_matches_sweeps_and_last_cell(ctx):
+    """2^30 cells, the largest grid the fused kernels take, at CFL 0.9 (the
+    fused path, default implementation): two steps agree bitwise with the
+    three sweeps over the whole grid, and 16^3 boxes, one wrapping around
+    the grid's last cell and one inside, match the FP64 oracle.  A buffer
+    descriptor's size tops out one byte short of 2^32, so a descriptor on
+    the field's start would clip the last element of such a field; the
+    kernels rebase theirs on each row or plane."""
+    import torch
+    from paper_1606_06117_amd import native
+    N, steps, inner = 1024, 2, 16
+    halo = 3 * steps  # three calls of reach 1 per axis and step
+    shape = (N, N, N)
+    dev = torch.device("cuda:0")
+    phi0 = W.fourier_modes_torch(shape, 11, dev)
+    u = W.abc_velocity_torch(shape, dev)
+    dx = (2 * np.pi / N,) * 3
+    dt = W.abc_dt(shape, 0.9)
+    big = inner + 2 * halo
+    boxes = {"last cell": (np.arange(big) + N - inner // 2 - halo) % N, "interior": np.arange(big) + 500}
+    idx = {k: torch.from_numpy(v).to(dev) for k, v in boxes.items()}
+    sub = lambda a, i: a[..., i[:, None, None], i[None, :, None], i[None, None, :]]
+    inputs = {k: (sub(phi0, i).cpu().numpy(), torch.stack([sub(u[d], i) for d in range(3)]).cpu().numpy())
+              for k, i in idx.items()}
+    fused = phi0.clone()
+    ctx.advect(fused, u, dx, dt, native.CEC, steps, 0, 0.0)
+    ctx.set_option(native.OPT_FUSED, 0)
+    try:
+        sweeps = phi0.clone()
+        ctx.advect(sweeps, u, dx, dt, native.CEC, steps, 0, 0.0)
+    finally:
+        ctx.set_option(native.OPT_FUSED, 1)
+    torch.cuda.synchronize()
+    diff = (fused != sweeps).reshape(-1)
+    ndiff = int(diff.sum())
+    first = torch.nonzero(diff)[:4].reshape(-1).tolist() if ndiff else []
+    inner_sl = (slice(halo, halo + inner),) * 3
+    got = {k: sub(fused, i).cpu().numpy()[inner_sl] for k, i in idx.items()}
+    del phi0, u, fused, sweeps, diff
+    torch.cuda.empty_cache()
+    assert ndiff == 0, f"{ndiff} cells differ, first flat indices {first}"
+    for k, (p0, u0) in inputs.items():
+        ref = oracle.advect(p0.astype(np.float64), u0, dx, dt, oracle.CEC, steps, 0)[inner_sl]
+        check(got[k].astype(np.float64), ref, p0, steps, f"1024^3 fused, {k} box")
 
 
 def test_large_1024_cfl2_cec_box(ctx):
