@@ -295,7 +295,7 @@ def main(argv=None):
     ap.add_argument("--cfl", type=float, default=0.9)
     ap.add_argument("--scheme", default="cec", choices=["cir", "fec", "bec", "cec"])
     ap.add_argument("--cpu-edge", type=int, default=128, help="edge of the oracle's sample box")
-    ap.add_argument("--cpu-steps", type=int, default=12, help="oracle steps on the sample box")
+    ap.add_argument("--cpu-steps", type=int, default=60, help="oracle steps on the sample box (about 13 s)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--path", choices=["auto", "sweeps"], default="auto",
                     help="auto: fused step where the library has one; sweeps: one kernel per axis")
