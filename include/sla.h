@@ -170,10 +170,13 @@ int sla_norms(sla_ctx *ctx, int64_t count, const float *a, const float *b,
  * either its own velocity planes or a uniform velocity.  Problems whose
  * velocity pointer and grid are equal share the velocity: their tiles run
  * side by side on the same accelerator partition, so the shared velocity is
- * read from memory about once for all of them.  Every step of every problem
- * is one tile of a persistent kernel (one launch per step over all
- * problems); a result equals sla_advect(..., SLA_CEC, ...) on that problem
- * with a uniform velocity field, bit for bit.
+ * read from memory about once for all of them.  Each step launches one
+ * persistent kernel over the tiles of all problems, except problems with
+ * their own velocity planes and at least 2^24 cells: those fill the GPU
+ * alone and take one launch of the fused third-order step each (the
+ * creating context's SLA_OPT_CEC3D_KERNEL choice).  A result equals
+ * sla_advect(..., SLA_CEC, ...) on that problem (with a uniform velocity
+ * field for a uniform problem), bit for bit.
  * ---------------------------------------------------------------------- */
 typedef struct {
   sla_grid grid;        /* 3D, as for sla_advect */
@@ -200,8 +203,9 @@ int sla_plan_create(sla_ctx *ctx, sla_plan **out, int32_t nprob, const sla_probl
 /* Launch the plan's graph on the context's stream (asynchronous). */
 int sla_plan_run(sla_ctx *ctx, sla_plan *plan);
 /* Chosen launch shape: y extent of a tile, workgroups of the persistent
- * kernel, work items per step, and the tuned time of one step in ms
- * (0 if not tuned).  Any pointer may be NULL. */
+ * kernel, its work items per step (problems launched on their own have
+ * none), and the tuned time of one whole step in ms (0 if not tuned).  Any
+ * pointer may be NULL. */
 int sla_plan_info(const sla_plan *plan, int32_t *ychunk, int32_t *blocks, int32_t *items,
                   double *step_ms);
 /* Release a plan.  NULL is ignored. */

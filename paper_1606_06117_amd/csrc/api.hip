@@ -47,6 +47,11 @@ struct sla_plan {
   int4* ditems = nullptr;
   int nitems = 0, ychunk = 0, blocks = 0;
   double step_ms = 0.0;
+  // problems run by their own launches of the fused step (see plan_direct)
+  std::vector<int> direct;
+  std::vector<sla::Geo> geo;         // per problem
+  std::vector<const float*> u;       // per problem (NULL: uniform velocity)
+  int cec3d_kernel = 5;              // the creating context's fused-step choice
   hipStream_t cap = nullptr;         // private capture stream
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -730,9 +735,20 @@ namespace {
 // grid whose size is a multiple of 8, they land on the same accelerator
 // partition (workgroups are dealt to the 8 partitions round-robin) in the
 // same round, and share that partition's L2.
-std::vector<int4> build_items(const std::vector<sla_problem>& P, int ychunk) {
+// Problems with their own velocity planes and at least 2^24 cells fill the
+// GPU alone: they run one launch of the context's fused step per step (the
+// same FP32 operations as the tiles of the persistent kernel), which is
+// faster than their tiles in the work list.  The persistent kernel takes the
+// rest, where many small problems share its launch.
+constexpr size_t kPlanDirectCells = size_t(1) << 24;
+bool plan_direct(const sla_problem& p) {
+  return p.u && size_t(p.grid.n[0]) * p.grid.n[1] * p.grid.n[2] >= kPlanDirectCells;
+}
+
+std::vector<int4> build_items(const std::vector<sla_problem>& P, int ychunk,
+                              const std::vector<bool>& skip) {
   std::vector<int4> items;
-  std::vector<bool> done(P.size(), false);
+  std::vector<bool> done(skip);  // problems outside the work list count as done
   auto tiles_of = [&](const sla_problem& p, std::vector<int3>& t) {
     const int tx = (p.grid.n[0] + sla::kBatchTileX - 1) / sla::kBatchTileX;
     const int tz = (p.grid.n[2] + sla::kBatchTileZ - 1) / sla::kBatchTileZ;
@@ -797,7 +813,9 @@ int plan_upload(sla_ctx* ctx, sla_plan* pl, const std::vector<sla_problem>& P, i
       bp[i].lam[d] = float(p.dt / p.grid.dx[d]);
     }
   }
-  std::vector<int4> items = build_items(P, ychunk);
+  std::vector<bool> skip(P.size(), false);
+  for (int i : pl->direct) skip[size_t(i)] = true;
+  std::vector<int4> items = build_items(P, ychunk, skip);
   if (pl->ditems) (void)hipFree(pl->ditems);
   pl->ditems = nullptr;
   if (hipMalloc(&pl->ditems, std::max<size_t>(1, items.size()) * sizeof(int4)) != hipSuccess)
@@ -814,11 +832,28 @@ int plan_upload(sla_ctx* ctx, sla_plan* pl, const std::vector<sla_problem>& P, i
 }
 
 // Launch the plan's steps on stream st (also used while capturing).
+// Step k of a plan: the persistent kernel over the work list, then one
+// fused-step launch per direct problem.  Even k reads the caller's fields
+// and writes the work fields, odd k the reverse.
+hipError_t plan_step(sla_plan* pl, hipStream_t st, int32_t k) {
+  const bool even = (pl->step0 + k) % 2 == 0;
+  hipError_t e = hipSuccess;
+  if (pl->nitems > 0)
+    e = sla::launch_cec3d_batch(even, pl->dprobs, pl->ditems, pl->nitems, k & 1, pl->blocks,
+                                pl->flag, st);
+  for (size_t j = 0; j < pl->direct.size() && e == hipSuccess; ++j) {
+    const int i = pl->direct[j];
+    float* a = pl->phis[size_t(i)];
+    float* b = pl->work[size_t(i)];
+    e = sla::launch_cec3d(pl->cec3d_kernel, even, pl->geo[size_t(i)], (k & 1) ? b : a,
+                          pl->u[size_t(i)], (k & 1) ? a : b, pl->flag, st);
+  }
+  return e;
+}
+
 hipError_t plan_launch(sla_plan* pl, hipStream_t st, int32_t steps) {
   hipError_t e = hipSuccess;
-  for (int32_t k = 0; k < steps && e == hipSuccess; ++k)
-    e = sla::launch_cec3d_batch((pl->step0 + k) % 2 == 0, pl->dprobs, pl->ditems, pl->nitems, k & 1,
-                                pl->blocks, pl->flag, st);
+  for (int32_t k = 0; k < steps && e == hipSuccess; ++k) e = plan_step(pl, st, k);
   if (e == hipSuccess && (steps & 1))
     e = sla::launch_batch_copy_back(pl->dprobs, pl->nprob, st);
   return e;
@@ -889,6 +924,12 @@ int sla_plan_create(sla_ctx* ctx, sla_plan** out, int32_t nprob, const sla_probl
   pl->steps = steps;
   pl->step0 = step0;
   pl->flag = ctx->flag;
+  pl->cec3d_kernel = ctx->cec3d_kernel;
+  for (int i = 0; i < nprob; ++i) {
+    pl->geo.push_back(make_geo(&P[i].grid, P[i].dt));
+    pl->u.push_back(P[i].u);
+    if (plan_direct(P[i])) pl->direct.push_back(i);
+  }
   bool ok = true;
   std::vector<float> uni(3 * size_t(nprob), 0.f);
   for (int i = 0; i < nprob; ++i) {
@@ -939,9 +980,7 @@ int sla_plan_create(sla_ctx* ctx, sla_plan** out, int32_t nprob, const sla_probl
         float ms = 0.f, tot = 0.f;
         for (int r = 0; r < 3 && e == hipSuccess; ++r) {
           e = hipEventRecord(a, ctx->stream);
-          if (e == hipSuccess)
-            e = sla::launch_cec3d_batch(step0 % 2 == 0, pl->dprobs, pl->ditems, pl->nitems, 0, bl,
-                                        pl->flag, ctx->stream);
+          if (e == hipSuccess) e = plan_step(pl, ctx->stream, 0);  // writes work fields only
           if (e == hipSuccess) e = hipEventRecord(b, ctx->stream);
           if (e == hipSuccess) e = hipEventSynchronize(b);
           if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);

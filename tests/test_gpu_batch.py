@@ -93,3 +93,45 @@ def test_plan_rejects_large_courant(ctx):
     with pytest.raises(native.SlaError) as ei:
         native.Plan(ctx, [(phi, (1.5, 0.0, 0.0), (1.0, 1.0, 1.0), 1.0)], 2)
     assert ei.value.status == native.ECOURANT
+
+
+def test_plan_with_large_problems(ctx):
+    """Problems of at least 2^24 cells with their own velocity run their own
+    fused-step launches inside the plan's graph, next to the persistent
+    kernel's tiles of the small ones; every result still equals its
+    standalone run bit for bit (odd step count: the copy back included)."""
+    import torch
+    from paper_1606_06117_amd import native
+    shape = (256, 256, 256)
+    dev = torch.device("cuda:0")
+    u = W.abc_velocity_torch(shape, dev)
+    dx = (2 * np.pi / 256,) * 3
+    dt = W.abc_dt(shape, 0.9)
+    big = [W.fourier_modes_torch(shape, 40 + k, dev) for k in range(2)]
+    probs, small = [], []
+    for f in big:
+        probs.append((f.clone(), u, dx, dt))
+    rng = np.random.default_rng(3)
+    for sh in [(20, 24, 33), (32, 32, 32)]:
+        vel = rng.uniform(-1.0, 1.0, 3).astype(np.float32)
+        dxs = tuple(2 * np.pi / n for n in reversed(sh))
+        dts = 0.9 * min(dxs) / float(np.max(np.abs(vel)))
+        f = rng.standard_normal(sh).astype(np.float32)
+        small.append((f, W.uniform_velocity(sh, vel), dxs, dts))
+        probs.append((torch.from_numpy(f).cuda(), tuple(float(v) for v in vel), dxs, dts))
+    steps = 3
+    plan = native.Plan(ctx, probs, steps, step0=0, tune=True)
+    info = plan.info()
+    print("plan", info)
+    plan.run()
+    torch.cuda.synchronize()
+    ctx.check()
+    for k, f in enumerate(big):
+        ref = f.clone()
+        ctx.advect(ref, u, dx, dt, native.CEC, steps, 0, 0.0)
+        torch.cuda.synchronize()
+        assert torch.equal(probs[k][0], ref), k
+    for (phi_d, _, dxs, dts), (f, uu, _, _) in zip(probs[2:], small):
+        ref = gpu_advect(ctx, f, uu, dxs, dts, oracle.CEC, steps, step0=0)
+        assert np.array_equal(phi_d.cpu().numpy().astype(np.float64), ref)
+    plan.close()
