@@ -122,7 +122,10 @@ def learned_section(ctx, size, fields, steps_per_field, cells, iters, batch, lr,
     """Learned correction vs the plain third-order scheme on the time-modulated
     ABC flow (CFL 0.9 at peak amplitude): training on pairs from the GPU
     third-order scheme, then error against the exact field after whole
-    modulation periods, time per step, and the speedup at equal error."""
+    modulation periods, time per step, and the speedup at equal error: the
+    learned run's cost against the plain scheme's cost interpolated at the
+    same error, over plain runs at several time steps on the same grid and on
+    coarser grids of the same physical problem."""
     from paper_1606_06117_amd import learned as Lr
     shape = (size, size, size)
     model, pairs, hists, pairs_s, train_s = Lr.train_rollout(
@@ -136,8 +139,14 @@ def learned_section(ctx, size, fields, steps_per_field, cells, iters, batch, lr,
     for spp in (200, 100, 75, 60):
         err, secs = Lr.error_at_cfl(ctx, shape, 4100, 0.9, spp, 2)
         plain.append((err, secs, 0.9 * Lr.PERIOD / spp))
+    # and of the same physical problem on coarser grids (same time step)
+    coarse = []
+    for n in (32, 48, 64, 96, 128):
+        if n < size:
+            err, secs = Lr.error_at_resolution(ctx, n, size, 4100, 0.9, 2)
+            coarse.append((err, secs, n))
     lerr, lsecs = Lr.error_at_cfl(ctx, shape, 4100, 0.9, Lr.PERIOD, 2, learned_model=model)
-    speed = Lr.equal_error_speedup([(e, t) for e, t, _ in plain], (lerr, lsecs))
+    speed = Lr.equal_error_speedup([(e, t) for e, t, _ in plain + coarse], (lerr, lsecs))
     last = ev["per_step"][-1]
     out = {
         "workload": f"{size}^3 FP32, ABC velocity with amplitude sin(2 pi (m+1/2)/100), CFL 0.9 at peak; "
@@ -152,6 +161,7 @@ def learned_section(ctx, size, fields, steps_per_field, cells, iters, batch, lr,
         "ms_per_step": ev["ms_per_step"],
         "fell_back": ev["fell_back"],
         "plain_error_vs_cost": [{"cfl": c, "relL2_vs_exact": e, "seconds": t} for e, t, c in plain],
+        "plain_error_vs_resolution": [{"n": n, "relL2_vs_exact": e, "seconds": t} for e, t, n in coarse],
         "learned_error_vs_cost": {"cfl": 0.9, "relL2_vs_exact": lerr, "seconds": lsecs},
         "speedup_at_equal_L2": speed,
     }

@@ -244,6 +244,30 @@ def error_at_cfl(ctx, shape, seed, cfl, steps_per_period, periods, learned_model
     return math.sqrt(s[0] / s[1]), secs
 
 
+def error_at_resolution(ctx, n, ref_n, seed, cfl, periods, period=PERIOD):
+    """Plain third-order error against the exact field after ``periods``
+    periods on an n^3 grid, with the physical time step of the ref_n^3 run at
+    ``cfl`` at peak amplitude: the same physical problem (field, flow, time
+    step) resolved with fewer or more cells.  Returns (error, seconds)."""
+    import torch
+    shape = (n, n, n)
+    dx = (2 * math.pi / n,) * 3
+    dt = W.abc_dt((ref_n,) * 3, cfl)
+    c = cfl * n / ref_n  # the Courant number on this grid
+    u = torch.from_numpy(W.abc_velocity(shape)).cuda()
+    phi0 = torch.from_numpy(W.random_gaussians(shape, 8, seed=seed).astype(np.float32)).cuda()
+    phi = phi0.clone()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for m in range(periods * period):
+        a = modulation(m, period)
+        ctx.advect(phi, u, dx, a * dt, native.CEC, 1, step0=m, courant_max=_hint(c, a))
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    s = ctx.norms(phi, phi0)
+    return math.sqrt(s[0] / s[1]), secs
+
+
 def equal_error_speedup(points_plain, point_learned):
     """Cost of the plain scheme at the learned error, by log-log interpolation
     of its (error, seconds) points; None when the learned error is outside
