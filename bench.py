@@ -41,11 +41,12 @@ def algorithmic_bytes(kind: str, ncells: int, ndim: int) -> int:
 
     A whole step reads phi and the ndim velocity planes and writes phi:
     (8 + 4 ndim) B per cell.  One axis sweep reads phi and its velocity plane
-    and writes phi: 12 B per cell.  A copy reads and writes 4 B each.
+    and writes phi: 12 B per cell; the fused x and y sweeps read phi and two
+    planes: 16 B.  A copy reads and writes 4 B each.
     """
     per_cell = {"cir": 8 + 4 * ndim, "fec": 8 + 4 * ndim, "bec": 8 + 4 * ndim,
                 "cec3d": 8 + 4 * ndim, "sweep_x": 12, "sweep_y": 12, "sweep_z": 12,
-                "copy": 8}[kind]
+                "sweep_xy": 16, "copy": 8}[kind]
     return per_cell * ncells
 
 

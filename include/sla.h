@@ -135,11 +135,15 @@ typedef enum {
    * parity and grid size (measured from 256^3 to 1024^3).  The batched plans
    * always use 2. */
   SLA_OPT_CEC3D_KERNEL = 1,
-  /* How the y and z sweeps of the third-order scheme run (same FP32
-   * operations, same results): 1 (default) each thread walks one column
-   * along the axis with its stencil in registers (grids of fewer than 2^30
-   * cells, or of 2^30 cells with ny >= 2), 0 LDS tiles with the halo re-read
-   * per tile. */
+  /* How the sweeps of a third-order step that is not fused run (same FP32
+   * operations, same results): 2 (default) the x and y sweeps in one kernel
+   * when their reach is at most 2 (x then y on even steps, y then x on odd
+   * ones: 64-lane x windows marching along y) and z by column walks, else
+   * as 1; 1 one kernel per axis, x in
+   * 64-lane windows, y and z by each thread walking one column with its
+   * stencil in registers; 0 one kernel per axis with LDS tiles.  2 and 1
+   * need grids of fewer than 2^30 cells, or of 2^30 cells with ny >= 2
+   * (others run 0). */
   SLA_OPT_SWEEP_KERNEL = 2
 } sla_option;
 /* Set option `option` to `value`.  Returns SLA_EINVAL for an unknown option
@@ -302,7 +306,8 @@ typedef enum {
   SLA_K_CEC3D = 6,   /* fused three-axis third-order step     */
   SLA_K_COPY = 7,    /* device-to-device copy of the result   */
   SLA_K_LEARNED = 8, /* learned correction on top of a CIR step */
-  SLA_K_COUNT = 9
+  SLA_K_SWEEP_XY = 9, /* fused x and y third-order sweeps       */
+  SLA_K_COUNT = 10
 } sla_kernel_kind;
 
 /* enable != 0: start recording (totals are cleared); 0: stop recording. */

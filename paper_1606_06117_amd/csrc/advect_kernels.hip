@@ -621,6 +621,20 @@ __global__ __launch_bounds__(kThreads) void k_sweep_m(const float* __restrict__ 
 // 2R .. 63 - 2R, the output on 3R .. 63 - 3R.  No LDS memory, no barriers.
 // The arithmetic per node is that of k_sweep_x.
 // ---------------------------------------------------------------------------
+// Third-order sweep along x of one value per lane (lanes are consecutive
+// x): the anchor and far values of each call are read from the lanes at the
+// departure offsets (__shfl).  Exact on lanes 3R .. 63 - 3R.
+template <int R>
+__device__ __forceinline__ float xsweep_lanes(float p, float c, int lane, int* flag) {
+  const Dep d = depart<R>(c, flag);
+  const float p1 = lerp(__shfl(p, lane + d.oa), __shfl(p, lane + d.ob), d.f);
+  const Dep dr = depart<R>(-c, flag);
+  const float e = p - lerp(__shfl(p1, lane + dr.oa), __shfl(p1, lane + dr.ob), dr.f);
+  const float ea = __shfl(e, lane + d.oa), eb = __shfl(e, lane + d.ob);
+  const float w = fmaf(d.f, 1.f / 3.f, 1.f / 3.f);
+  return fmaf(0.5f, fmaf(w, eb - ea, ea), p1);
+}
+
 template <int R>
 __global__ __launch_bounds__(kThreads) void k_sweep_xw(const float* __restrict__ phi,
                                                        const float* __restrict__ ud,
@@ -651,16 +665,114 @@ __global__ __launch_bounds__(kThreads) void k_sweep_xw(const float* __restrict__
 #pragma unroll
   for (int k = 0; k < WPW; ++k) {
     if (w0 + k >= nwin) break;
-    const float ck = c[k] * lam;
-    const Dep d = depart<R>(ck, flag);
-    const float p1 = lerp(__shfl(p[k], lane + d.oa), __shfl(p[k], lane + d.ob), d.f);
-    const Dep dr = depart<R>(-ck, flag);
-    const float e = p[k] - lerp(__shfl(p1, lane + dr.oa), __shfl(p1, lane + dr.ob), dr.f);
-    const float ea = __shfl(e, lane + d.oa), eb = __shfl(e, lane + d.ob);
-    const float w = fmaf(d.f, 1.f / 3.f, 1.f / 3.f);
-    const float o = fmaf(0.5f, fmaf(w, eb - ea, ea), p1);
+    const float o = xsweep_lanes<R>(p[k], c[k] * lam, lane, flag);
     const int xo = (w0 + k) * USE + lane - 3 * R;  // output node of this lane
     if (lane >= 3 * R && lane < 64 - 3 * R && xo < nx) st_row(out, off[k], rowoff, o);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Fused x and y sweeps, any reach R: the first two sweeps of an x,y,z step
+// (XFIRST: x then y) or the last two of a z,y,x step (y then x).  A wave
+// takes one 64-lane x window of one z plane, x0 - 3R .. x0 + 60 - 3R
+// (wrapped, one node per lane; lanes 3R .. 63 - 3R are its 64 - 6R
+// outputs), and marches along y through a chunk of rows with the y sweep's
+// stencil in rings of K = 3R + 1 registers, as k_sweep_m does.  XFIRST:
+// every loaded row is swept along x across the lanes (xsweep_lanes) before
+// it enters the rings.  Otherwise every output row of the y sweep is swept
+// along x.  The y sweep works lane by lane, so the lanes whose x sweep is
+// exact give exact results.  The four waves of a workgroup take four
+// neighbouring windows of one row, which share the lines their lane halos
+// straddle.  Loads and stores address a row through a descriptor rebased
+// on it, with the lane's x offset.  The same FP32 operations per node as
+// k_sweep_xw followed by k_sweep_m (or the reverse).  Phi and the two
+// velocity planes are read once and Phi written once: 16 B per node
+// instead of 24 for the two sweeps.
+// ---------------------------------------------------------------------------
+template <int R, bool XFIRST>
+__global__ __launch_bounds__(kThreads) void k_sweep_xym(const float* __restrict__ phi,
+                                                        const float* __restrict__ ux,
+                                                        const float* __restrict__ uy,
+                                                        float* __restrict__ out, int nx, int ny,
+                                                        int nz, int nwin, int chunk, float lamx,
+                                                        float lamy, int* flag) {
+  constexpr int K = 3 * R + 1;
+  constexpr int USE = 64 - 6 * R;  // outputs per window
+  const int lane = threadIdx.x & 63;
+  const int wid = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
+  const int win = wid % nwin, z = (wid / nwin) % nz, ch = wid / (nwin * nz);
+  const int l0 = ch * chunk;
+  if (l0 >= ny) return;  // the whole wave
+  const int l1 = min(l0 + chunk, ny);
+  const unsigned vx = 4u * unsigned(wrapk(win * USE - 3 * R + lane, nx));
+  const unsigned rowb = 4u * unsigned(nx);
+  const unsigned zoff = unsigned(z) * unsigned(ny) * rowb;  // the plane's byte offset
+  const bool lane_out = lane >= 3 * R && lane < 64 - 3 * R && win * USE + lane - 3 * R < nx;
+  auto wrapped = [&](int m) {
+    m %= ny;
+    return m < 0 ? m + ny : m;
+  };
+  const int m0 = l0 - 3 * R, m1 = l1 + 3 * R;  // steps m0 .. m1 - 1
+  float pr[K], p1[K], er[K], cr[K];  // rings
+  float np[K], nc[K], nx_[K];        // loads of the next K steps (nx_: x velocity)
+  int lrow = wrapped(m0);            // row of the next phi / y-velocity load
+  int xrow = XFIRST ? lrow : wrapped(m0 - 3 * R);  // row of the next x-velocity load
+#pragma unroll
+  for (int i = 0; i < K; ++i) {
+    pr[i] = p1[i] = er[i] = cr[i] = 0.f;
+    const unsigned ro = zoff + unsigned(lrow) * rowb;
+    np[i] = ld_row(phi, vx, ro);
+    nc[i] = ld_row(uy, vx, ro);
+    nx_[i] = ld_row(ux, vx, zoff + unsigned(xrow) * rowb);
+    lrow = lrow + 1 == ny ? 0 : lrow + 1;
+    xrow = xrow + 1 == ny ? 0 : xrow + 1;
+  }
+  int srow = wrapped(m0 - 3 * R);  // row of node m - 3R
+  for (int mb = m0; mb < m1; mb += K) {
+    static_for<K>([&](auto ic) {
+      constexpr int i = decltype(ic)::value;
+      const int m = mb + i;
+      if (m >= m1) return;
+      const float cx = nx_[i] * lamx;  // x Courant number of row m (XFIRST) or of row m - 3R
+      pr[i] = XFIRST ? xsweep_lanes<R>(np[i], cx, lane, flag) : np[i];
+      cr[i] = nc[i] * lamy;
+      if (m + K < m1) {
+        const unsigned rn = zoff + unsigned(lrow) * rowb;
+        np[i] = ld_row(phi, vx, rn);
+        nc[i] = ld_row(uy, vx, rn);
+        nx_[i] = ld_row(ux, vx, zoff + unsigned(xrow) * rowb);
+      }
+      lrow = lrow + 1 == ny ? 0 : lrow + 1;
+      xrow = xrow + 1 == ny ? 0 : xrow + 1;
+      // Phi1 of node m - R
+      constexpr int j1 = pmod(i - R, K);
+      {
+        const DepN d = depart_n<R>(cr[j1], flag);
+        float a, b;
+        ring_pair<R, K, j1>(pr, d, a, b);
+        p1[j1] = lerp(a, b, d.f);
+      }
+      // e of node m - 2R
+      constexpr int j2 = pmod(i - 2 * R, K);
+      {
+        const DepN d = depart_n<R>(-cr[j2], flag);
+        float a, b;
+        ring_pair<R, K, j2>(p1, d, a, b);
+        er[j2] = pr[j2] - lerp(a, b, d.f);
+      }
+      // out of node m - 3R
+      constexpr int j3 = pmod(i - 3 * R, K);
+      if (m - 3 * R >= l0) {
+        const DepN d = depart_n<R>(cr[j3], flag);
+        float ea, eb;
+        ring_pair<R, K, j3>(er, d, ea, eb);
+        const float w = fmaf(d.f, 1.f / 3.f, 1.f / 3.f);
+        float o = fmaf(0.5f, fmaf(w, eb - ea, ea), p1[j3]);
+        if (!XFIRST) o = xsweep_lanes<R>(o, cx, lane, flag);
+        if (lane_out) st_row(out, vx, zoff + unsigned(srow) * rowb, o);
+      }
+      srow = srow + 1 == ny ? 0 : srow + 1;
+    });
   }
 }
 
@@ -778,6 +890,37 @@ hipError_t launch_ec(int ndim, int scheme, int R, const Geo& g, const float* phi
       case 2: return launch_ec_r<2, BEC>(R, g, phi, u, out, flag, st);
       case 3: return launch_ec_r<3, BEC>(R, g, phi, u, out, flag, st);
     }
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int R>
+hipError_t launch_sweep_xy_t(bool xfirst, const Geo& g, const float* phi, const float* u,
+                             float* out, int* flag, hipStream_t st) {
+  constexpr int USE = 64 - 6 * R;
+  const size_t n = (size_t)g.ncells;
+  const int nwin = (g.nx + USE - 1) / USE;
+  // chunks along y: about 8192 waves for the chip, chunks of >= 16R rows
+  const long long per = (long long)nwin * g.nz;
+  const int want = int(std::min<long long>((8192 + per - 1) / per, std::max(1, g.ny / (16 * R))));
+  const int chunk = (g.ny + want - 1) / want;
+  const long long waves = per * ((g.ny + chunk - 1) / chunk);
+  const dim3 grid(unsigned((waves + 3) / 4));
+  if (xfirst)
+    hipLaunchKernelGGL((k_sweep_xym<R, true>), grid, dim3(kThreads), 0, st, phi, u, u + n, out, g.nx,
+                       g.ny, g.nz, nwin, chunk, g.lam[0], g.lam[1], flag);
+  else
+    hipLaunchKernelGGL((k_sweep_xym<R, false>), grid, dim3(kThreads), 0, st, phi, u, u + n, out,
+                       g.nx, g.ny, g.nz, nwin, chunk, g.lam[0], g.lam[1], flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_cec_sweep_xy(int R, bool xfirst, const Geo& g, const float* phi, const float* u,
+                               float* out, int* flag, hipStream_t st) {
+  if (!offsets32_ok(g)) return hipErrorInvalidValue;
+  switch (R) {  // reach 3 and more run one sweep per axis (see the caller)
+    case 1: return launch_sweep_xy_t<1>(xfirst, g, phi, u, out, flag, st);
+    case 2: return launch_sweep_xy_t<2>(xfirst, g, phi, u, out, flag, st);
   }
   return hipErrorInvalidValue;
 }

@@ -24,7 +24,7 @@ struct sla_ctx {
   std::string err;
   bool fused = true;    // SLA_OPT_FUSED
   int cec3d_kernel = 5;  // SLA_OPT_CEC3D_KERNEL
-  bool sweep_march = true;  // SLA_OPT_SWEEP_KERNEL
+  int sweep_kernel = 2;  // SLA_OPT_SWEEP_KERNEL
   // per-kernel timing
   bool timing = false;
   struct Mark { int kind; hipEvent_t a, b; };
@@ -375,11 +375,35 @@ int sla_advect(sla_ctx* ctx, const sla_grid* grid, float* phi, const float* u, d
           std::swap(cur, nxt);
           break;
         }
+        const int rxy = reach[0] > reach[1] ? reach[0] : reach[1];
+        if (ctx->sweep_kernel == 2 && rxy <= 2 && sla::offsets32_ok(geo)) {
+          // x and y in one kernel: x,y then z on even steps, z then y,x on
+          // odd.  Up to reach 2: a 64-lane window then yields 52 or more
+          // outputs; at reach 3 (46) the y sweep's work on the halo lanes
+          // outweighs the saved traffic, and the sweeps run one per axis.
+          const bool even = m % 2 == 0;
+          for (int part = 0; part < 2 && e == hipSuccess; ++part) {
+            const bool xy = (part == 0) == even;
+            if (xy) {
+              e = run(ctx, SLA_K_SWEEP_XY, [&] {
+                return sla::launch_cec_sweep_xy(rxy, even, geo, cur, u, nxt, ctx->flag, ctx->stream);
+              });
+            } else {
+              if (ndim < 3) continue;
+              e = run(ctx, SLA_K_SWEEP_Z, [&] {
+                return sla::launch_cec_sweep(2, reach[2], geo, cur, u + 2 * n, nxt, ctx->flag,
+                                             ctx->stream, true);
+              });
+            }
+            std::swap(cur, nxt);
+          }
+          break;
+        }
         for (int j = 0; j < ndim && e == hipSuccess; ++j) {
           const int d = (m % 2 == 0) ? j : ndim - 1 - j;
           e = run(ctx, SLA_K_SWEEP_X + d, [&] {
             return sla::launch_cec_sweep(d, reach[d], geo, cur, u + size_t(d) * n, nxt,
-                                         ctx->flag, ctx->stream, ctx->sweep_march);
+                                         ctx->flag, ctx->stream, ctx->sweep_kernel != 0);
           });
           std::swap(cur, nxt);
         }
@@ -410,8 +434,8 @@ int sla_set_option(sla_ctx* ctx, int option, int64_t value) {
       ctx->cec3d_kernel = int(value);
       return SLA_OK;
     case SLA_OPT_SWEEP_KERNEL:
-      if (value != 0 && value != 1) return fail(ctx, SLA_EINVAL, "SLA_OPT_SWEEP_KERNEL takes 0 or 1");
-      ctx->sweep_march = value != 0;
+      if (value < 0 || value > 2) return fail(ctx, SLA_EINVAL, "SLA_OPT_SWEEP_KERNEL takes 0, 1 or 2");
+      ctx->sweep_kernel = int(value);
       return SLA_OK;
   }
   return fail(ctx, SLA_EINVAL, "unknown option %d", option);

@@ -48,6 +48,11 @@ hipError_t launch_ec(int ndim, int scheme, int R, const Geo& g, const float* phi
 hipError_t launch_cec_sweep(int d, int R, const Geo& g, const float* phi,
                             const float* u_d, float* out, int* flag, hipStream_t st,
                             bool march = true);
+// The x and y sweeps of a third-order step in one kernel (reach R <= 2 on
+// both axes): x then y if xfirst, else y then x; u holds the x and y
+// planes.  Same results as the two sweeps.  Needs offsets32_ok(g).
+hipError_t launch_cec_sweep_xy(int R, bool xfirst, const Geo& g, const float* phi, const float* u,
+                               float* out, int* flag, hipStream_t st);
 
 // Fused three-axis third-order step (reach 1 only): x,y,z order if even,
 // z,y,x otherwise.  variant: 0 LDS stages, 1 register segments, 2 streaming

@@ -62,7 +62,8 @@ SIGNATURES = {
     "sla_timing_read": (_c.c_int, [_vp, _c.POINTER(_c.c_int64), _c.POINTER(_c.c_double)]),
 }
 
-KERNEL_KINDS = ["cir", "fec", "bec", "sweep_x", "sweep_y", "sweep_z", "cec3d", "copy", "learned"]
+KERNEL_KINDS = ["cir", "fec", "bec", "sweep_x", "sweep_y", "sweep_z", "cec3d", "copy", "learned",
+                "sweep_xy"]
 MLP_INPUTS, MLP_HIDDEN, MLP_PARAMS = 32, 64, 6337
 
 

@@ -319,14 +319,19 @@ def test_fused_step_matches_sweeps(ctx, step0, variant, shape):
 @pytest.mark.parametrize("shape,cfl,steps", [
     ((40, 96, 24), 0.9, 2),    # reach 1, y axis chunked
     ((40, 96, 24), 1.5, 3),    # reach 2
+    ((12, 33, 70), 1.8, 3),    # reach 2, ragged (x windows, y chunks)
+    ((1, 50, 66), 1.5, 2),     # 2D, reach 2
     ((12, 33, 70), 2.5, 2),    # reach 3, ragged
     ((8, 9, 70), 3.5, 2),      # reach 4: halo 12 > axis length 8 and 9
     ((1, 50, 66), 3.5, 2),     # 2D
     ((64, 8, 16), 0.9, 2),     # z columns walked in 2 chunks
 ])
 def test_marching_sweeps_match_tiles(ctx, shape, cfl, steps):
-    """The y and z sweeps walking columns through registers give the same
-    bits as the LDS-tile sweeps (same FP32 operations per node)."""
+    """The three ways the sweeps run give the same bits (same FP32 operations
+    per node): the fused x+y kernel with z walking columns (default), one
+    kernel per axis with x in lane windows and y, z walking columns, and the
+    LDS-tile sweeps.  Odd then even steps, so both orders of the x+y kernel
+    run."""
     from paper_1606_06117_amd import native
     if shape[0] == 1:
         shp = shape[1:]
@@ -341,13 +346,16 @@ def test_marching_sweeps_match_tiles(ctx, shape, cfl, steps):
     dt = cfl * min(dx) / umax
     ctx.set_option(native.OPT_FUSED, 0)
     try:
+        fused_xy = gpu_advect(ctx, phi, u, dx, dt, oracle.CEC, steps, step0=1)
+        ctx.set_option(native.OPT_SWEEP_KERNEL, 1)
         march = gpu_advect(ctx, phi, u, dx, dt, oracle.CEC, steps, step0=1)
         ctx.set_option(native.OPT_SWEEP_KERNEL, 0)
         tiles = gpu_advect(ctx, phi, u, dx, dt, oracle.CEC, steps, step0=1)
     finally:
-        ctx.set_option(native.OPT_SWEEP_KERNEL, 1)
+        ctx.set_option(native.OPT_SWEEP_KERNEL, 2)
         ctx.set_option(native.OPT_FUSED, 1)
     assert np.array_equal(march, tiles)
+    assert np.array_equal(fused_xy, tiles)
 
 
 def test_fused_1024_matches_sweeps_and_last_cell(ctx):
