@@ -540,8 +540,7 @@ __global__ __launch_bounds__(kThreads) void k_sweep_m(const float* __restrict__ 
                                                       const float* __restrict__ ud,
                                                       float* __restrict__ out, int nx, int L,
                                                       unsigned S4, unsigned So4, int nother,
-                                                      int chunk, unsigned ncells, float lam,
-                                                      int* flag) {
+                                                      int chunk, float lam, int* flag) {
   constexpr int K = 3 * R + 1;
   const int x = blockIdx.x * 64 + (threadIdx.x & 63);
   const int other = blockIdx.y * (kThreads / 64) + (threadIdx.x >> 6);
@@ -639,8 +638,7 @@ template <int R>
 __global__ __launch_bounds__(kThreads) void k_sweep_xw(const float* __restrict__ phi,
                                                        const float* __restrict__ ud,
                                                        float* __restrict__ out, int nx, int nrows,
-                                                       int nwin, unsigned ncells, float lam,
-                                                       int* flag) {
+                                                       int nwin, float lam, int* flag) {
   constexpr int USE = 64 - 6 * R;  // outputs per window
   constexpr int WPW = 4;           // windows per wave, loaded together
   const int lane = threadIdx.x & 63;
@@ -830,7 +828,7 @@ hipError_t launch_sweep_t(int d, const Geo& g, const float* phi, const float* ud
     const int chunk = (L + want - 1) / want;
     dim3 grid((g.nx + 63) / 64, (other + 3) / 4, (L + chunk - 1) / chunk);
     hipLaunchKernelGGL(k_sweep_m<R>, grid, dim3(kThreads), 0, st, phi, ud, out, g.nx, L, S4, So4,
-                       other, chunk, unsigned(g.ncells), g.lam[d], flag);
+                       other, chunk, g.lam[d], flag);
     return hipGetLastError();
   }
   if (d == 0 && march && offsets32_ok(g)) {
@@ -838,7 +836,7 @@ hipError_t launch_sweep_t(int d, const Geo& g, const float* phi, const float* ud
     const int nwin = (g.nx + 64 - 6 * R - 1) / (64 - 6 * R);
     const long long waves = (long long)nrows * ((nwin + 3) / 4);
     hipLaunchKernelGGL(k_sweep_xw<R>, dim3(unsigned((waves + 3) / 4)), dim3(kThreads), 0, st, phi, ud,
-                       out, g.nx, nrows, nwin, unsigned(g.ncells), g.lam[0], flag);
+                       out, g.nx, nrows, nwin, g.lam[0], flag);
     return hipGetLastError();
   }
   if (d == 0) {

@@ -636,6 +636,8 @@ int sla_model_forward(sla_ctx* ctx, const sla_model* model, const uint16_t* feat
   return SLA_OK;
 }
 
+}  // extern "C"
+
 namespace {
 int model_gradient(sla_ctx* ctx, sla_model* model, const uint16_t* feats, const float* target,
                    int64_t m) {
@@ -660,6 +662,8 @@ int read_loss(sla_ctx* ctx, sla_model* model, int64_t m, double* loss) {
   return SLA_OK;
 }
 }  // namespace
+
+extern "C" {
 
 int sla_model_grads(sla_ctx* ctx, sla_model* model, const uint16_t* feats, const float* target,
                     int64_t m, float* grads, double* loss) {
@@ -750,6 +754,8 @@ int sla_advect_learned(sla_ctx* ctx, const sla_model* model, const sla_grid* gri
 
 
 // ------------------------------------------------------------------ plans
+
+}  // extern "C"
 
 namespace {
 
@@ -884,6 +890,8 @@ hipError_t plan_launch(sla_plan* pl, hipStream_t st, int32_t steps) {
 }
 
 }  // namespace
+
+extern "C" {
 
 void sla_plan_destroy(sla_plan* pl) {
   if (!pl) return;

@@ -762,7 +762,6 @@ __global__ __launch_bounds__(kThreads) void k_cec3d_wm(const float* __restrict__
   const int wx = wid % nwx, sg = (wid / nwx) % nseg, ch = wid / (nwx * nseg);
   const int xw = wx * kWmUse - 3 + lane;  // this lane's x (before wrap)
   const unsigned vx = 4u * unsigned(wrapk(xw, nx));
-  const size_t ncells = size_t(nx) * ny * nz;
   const unsigned rowb = 4u * unsigned(nx), plb = 4u * unsigned(nx) * unsigned(ny);
   const unsigned sstr = EVEN ? rowb : plb;  // bytes per segment-axis step
   const unsigned mstr = EVEN ? plb : rowb;  // bytes per march-axis step
@@ -952,7 +951,6 @@ __global__ __launch_bounds__(64 * W * WX) void k_cec3d_wl(const float* __restric
   const int wx = min(wx0 + xi, nwx - 1);
   const int xw = wx * kWmUse - 3 + lane;
   const unsigned vx = 4u * unsigned(wrapk(xw, nx));
-  const size_t ncells = size_t(nx) * ny * nz;
   const unsigned rowb = 4u * unsigned(nx), plb = 4u * unsigned(nx) * unsigned(ny);
   const unsigned sstr = EVEN ? rowb : plb, mstr = EVEN ? plb : rowb;
   const int g0 = gs * S, s0 = g0 + w * V, m0 = ch * chunk, m1 = min(m0 + chunk, nm);

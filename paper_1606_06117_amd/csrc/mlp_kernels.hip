@@ -410,7 +410,7 @@ __global__ __launch_bounds__(kThreads) void k_grad_reduce(const float* __restric
   }
   if (blockIdx.x == 0) {
     for (int h = kThreads / 2; h > 0; h /= 2) {
-      if (threadIdx.x < h) lsum[threadIdx.x] += lsum[threadIdx.x + h];
+      if (int(threadIdx.x) < h) lsum[threadIdx.x] += lsum[threadIdx.x + h];
       __syncthreads();
     }
     if (threadIdx.x == 0) *loss_sum = lsum[0];

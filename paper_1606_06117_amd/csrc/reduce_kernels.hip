@@ -39,7 +39,7 @@ __global__ __launch_bounds__(kThreads) void k_norms_part(int64_t n, const float*
   sh[4][threadIdx.x] = sb;
   __syncthreads();
   for (int w = kThreads / 2; w > 0; w >>= 1) {
-    if (threadIdx.x < w) {
+    if (int(threadIdx.x) < w) {
       const int j = threadIdx.x + w;
       sh[0][threadIdx.x] += sh[0][j];
       sh[1][threadIdx.x] += sh[1][j];
@@ -67,7 +67,7 @@ __global__ __launch_bounds__(kThreads) void k_norms_final(int nblk, const double
   for (int k = 0; k < 5; ++k) sh[k][threadIdx.x] = v[k];
   __syncthreads();
   for (int w = kThreads / 2; w > 0; w >>= 1) {
-    if (threadIdx.x < w) {
+    if (int(threadIdx.x) < w) {
       const int j = threadIdx.x + w;
       sh[0][threadIdx.x] += sh[0][j];
       sh[1][threadIdx.x] += sh[1][j];
@@ -92,7 +92,7 @@ __global__ __launch_bounds__(kThreads) void k_umax_part(int ncells, const float*
   sh[threadIdx.x] = m;
   __syncthreads();
   for (int w = kThreads / 2; w > 0; w >>= 1) {
-    if (threadIdx.x < w) sh[threadIdx.x] = max_nan(sh[threadIdx.x], sh[threadIdx.x + w]);
+    if (int(threadIdx.x) < w) sh[threadIdx.x] = max_nan(sh[threadIdx.x], sh[threadIdx.x + w]);
     __syncthreads();
   }
   if (threadIdx.x == 0) part[blockIdx.y * gridDim.x + blockIdx.x] = sh[0];
@@ -107,7 +107,7 @@ __global__ __launch_bounds__(kThreads) void k_umax_final(int nblk, const float* 
   sh[threadIdx.x] = m;
   __syncthreads();
   for (int w = kThreads / 2; w > 0; w >>= 1) {
-    if (threadIdx.x < w) sh[threadIdx.x] = max_nan(sh[threadIdx.x], sh[threadIdx.x + w]);
+    if (int(threadIdx.x) < w) sh[threadIdx.x] = max_nan(sh[threadIdx.x], sh[threadIdx.x + w]);
     __syncthreads();
   }
   if (threadIdx.x == 0) out[blockIdx.x] = sh[0];
