@@ -333,7 +333,7 @@ def main(argv=None):
     args = ap.parse_args(argv)
 
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(no sharding or collectives); run it with --gpus 1", file=sys.stderr)
         return 2
 
