@@ -289,13 +289,14 @@ def test_abc_512_cfl09_cec_boxes(ctx):
 
 @pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6, 7])
 @pytest.mark.parametrize("step0", [0, 1])
-@pytest.mark.parametrize("shape", [(40, 48, 72), (37, 45, 130), (13, 11, 250)])
+@pytest.mark.parametrize("shape", [(40, 48, 72), (37, 45, 130), (13, 11, 250), (11, 13, 9)])
 def test_fused_step_matches_sweeps(ctx, step0, variant, shape):
     """At reach 1 the fused 3D step and the three sweep kernels evaluate the
     same FP32 operations per node, so their results agree bitwise.  The
     second shape leaves partial x windows, row segments and march chunks;
     the third has 5 x windows (a workgroup of 2 windows past the row's end)
-    and fewer rows than one shared-halo workgroup holds."""
+    and fewer rows than one shared-halo workgroup holds; in the fourth a row
+    is narrower than a window (its lanes wrap around the row)."""
     from paper_1606_06117_amd import native
     phi = W.random_gaussians(shape, 6, seed=31).astype(np.float32)
     u = W.abc_velocity(shape)
