@@ -110,11 +110,37 @@ int sla_courant_max(sla_ctx *ctx, const sla_grid *grid, const float *u,
  * stream synchronisation).
  *
  * steps == 0 is a successful no-op.  Work memory (one field) is allocated on
- * the context on first use and kept.  The result is in phi when the stream
+ * the context on first use and kept, unless the caller gave the context a
+ * workspace (sla_set_workspace).  The result is in phi when the stream
  * reaches the end of the call. */
 int sla_advect(sla_ctx *ctx, const sla_grid *grid, float *phi, const float *u,
                double dt, int32_t scheme, int32_t steps, int64_t step0,
                double courant_max);
+
+/* sla_advect on nscalars fields that share the velocity u: phis is a host
+ * array of nscalars device fields, each advanced in place with the same
+ * grid, dt, scheme and steps.  The Courant bound is measured (or taken from
+ * courant_max) once for all of them; the fields run one after another
+ * through the same work memory.  Every field's result equals sla_advect on
+ * it, bit for bit. */
+int sla_advect_multi(sla_ctx *ctx, const sla_grid *grid, int32_t nscalars, float *const *phis,
+                     const float *u, double dt, int32_t scheme, int32_t steps, int64_t step0,
+                     double courant_max);
+
+/* Device bytes of work memory sla_advect and sla_advect_multi need on grid
+ * (one FP32 field whatever the scheme; nscalars does not change it, the
+ * fields run one after another).  0 for an invalid grid or scheme. */
+size_t sla_workspace_size(const sla_grid *grid, int32_t scheme, int32_t nscalars);
+
+/* Make the context use `bytes` of caller-owned device memory at dev_ptr as
+ * its work memory instead of memory it allocates.  Later sla_advect and
+ * sla_advect_multi calls then never allocate work memory: a call that needs
+ * more than `bytes` (see sla_workspace_size) fails with SLA_EINVAL.  The
+ * caller keeps the memory valid until it sets another workspace or destroys
+ * the context; the library never frees it.  dev_ptr == NULL returns to
+ * library-allocated work memory.  Synchronises the stream (earlier calls may
+ * still use the old work memory). */
+int sla_set_workspace(sla_ctx *ctx, void *dev_ptr, size_t bytes);
 
 /* Context options. */
 typedef enum {
@@ -215,6 +241,18 @@ int sla_plan_info(const sla_plan *plan, int32_t *ychunk, int32_t *blocks, int32_
 /* Release a plan.  NULL is ignored. */
 void sla_plan_destroy(sla_plan *plan);
 
+/* Advance nprob independent problems (host array) by `steps` steps of any
+ * scheme; a problem with u == NULL has the uniform velocity u_uniform.
+ * Third-order runs of 3D problems whose Courant numbers are all below 1 go
+ * through a plan (sla_plan_create, no tuning) run once.  Otherwise each
+ * problem runs as sla_advect would (courant_max as there); a uniform
+ * velocity is first written into a temporary field of ndim planes that the
+ * call allocates and frees.  Every result equals sla_advect on that problem
+ * (with a uniform velocity field for a uniform problem), bit for bit.
+ * Synchronises the stream when it used a plan or a temporary field. */
+int sla_advect_batch(sla_ctx *ctx, int32_t nprob, const sla_problem *probs, int32_t scheme,
+                     int32_t steps, int64_t step0, double courant_max);
+
 /* ------------------------------------------------------------------------
  * Learned correction (not in the paper; an addition of this library).
  *
@@ -252,6 +290,9 @@ void sla_model_destroy(sla_model *model);
 int sla_model_set_params(sla_ctx *ctx, sla_model *model, const float *params, int64_t n);
 /* Copy the FP32 master weights to host memory.  Synchronises the stream. */
 int sla_model_get_params(sla_ctx *ctx, const sla_model *model, float *params, int64_t n);
+/* The same two calls under the names of a weight file's load and save. */
+int sla_model_load(sla_ctx *ctx, sla_model *model, const float *params, int64_t n);
+int sla_model_save(sla_ctx *ctx, const sla_model *model, float *params, int64_t n);
 /* Declare the largest |c_d| the weights were trained for (> 0), or 0 for an
  * untrained model. */
 int sla_model_set_courant_range(sla_model *model, double range);

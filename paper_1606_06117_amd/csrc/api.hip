@@ -17,6 +17,7 @@ struct sla_ctx {
   hipStream_t stream = nullptr;
   float* work = nullptr;  // ping-pong field
   size_t work_cap = 0;    // floats
+  bool work_borrowed = false;  // work is the caller's (sla_set_workspace): never allocate
   float* fpart = nullptr; // velocity-max partials (3 * kUmaxBlocks) + 3 results
   double* dpart = nullptr;// norm partials (5 * kNormBlocks) + 5 results
   int* flag = nullptr;    // set by a kernel that clamped an offset
@@ -199,6 +200,9 @@ void fold_marks(sla_ctx* ctx) {
 
 int ensure_work(sla_ctx* ctx, size_t floats) {
   if (ctx->work_cap >= floats) return SLA_OK;
+  if (ctx->work_borrowed)
+    return fail(ctx, SLA_EINVAL, "the workspace holds %zu bytes, the call needs %zu",
+                ctx->work_cap * sizeof(float), floats * sizeof(float));
   if (ctx->work) {
     hipError_t e = hipStreamSynchronize(ctx->stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "synchronise before growing work memory");
@@ -265,7 +269,7 @@ void sla_destroy(sla_ctx* ctx) {
   {
     DeviceGuard guard(ctx->device);
     if (ctx->stream || ctx->work) (void)hipStreamSynchronize(ctx->stream);
-    if (ctx->work) (void)hipFree(ctx->work);
+    if (ctx->work && !ctx->work_borrowed) (void)hipFree(ctx->work);
     if (ctx->fpart) (void)hipFree(ctx->fpart);
     if (ctx->dpart) (void)hipFree(ctx->dpart);
     if (ctx->flag) (void)hipFree(ctx->flag);
@@ -302,10 +306,14 @@ int sla_courant_max(sla_ctx* ctx, const sla_grid* grid, const float* u, double d
   return SLA_OK;
 }
 
-int sla_advect(sla_ctx* ctx, const sla_grid* grid, float* phi, const float* u, double dt,
-               int32_t scheme, int32_t steps, int64_t step0, double courant_max) {
-  if (!ctx) return SLA_EINVAL;
-  ctx->err.clear();
+}  // extern "C"
+
+namespace {
+
+// Arguments of sla_advect (and of each scalar or problem of the multi and
+// batch calls) other than the Courant bound.
+int check_advect(sla_ctx* ctx, const sla_grid* grid, const float* phi, const float* u, double dt,
+                 int32_t scheme, int32_t steps, double courant_max) {
   int rc = check_grid(ctx, grid);
   if (rc) return rc;
   if (!phi || !u) return fail(ctx, SLA_EINVAL, "phi and u must not be NULL");
@@ -313,29 +321,216 @@ int sla_advect(sla_ctx* ctx, const sla_grid* grid, float* phi, const float* u, d
   if (scheme < SLA_CIR || scheme > SLA_CEC) return fail(ctx, SLA_EINVAL, "unknown scheme %d", scheme);
   if (steps < 0) return fail(ctx, SLA_EINVAL, "steps must be >= 0");
   if (std::isnan(courant_max)) return fail(ctx, SLA_EINVAL, "courant_max is NaN");
-  if (steps == 0) return SLA_OK;
-  DeviceGuard guard(ctx->device);
-  if (!guard.ok) return fail(ctx, SLA_EHIP, "cannot select device %d", ctx->device);
+  return SLA_OK;
+}
 
-  const sla::Geo geo = make_geo(grid, dt);
-  const int ndim = grid->ndim;
-  int reach[3] = {1, 1, 1};
+// Reach per axis: from the caller's bound on every axis, else measured.
+int advect_reach(sla_ctx* ctx, const sla_grid* grid, const sla::Geo& geo, const float* u,
+                 double courant_max, int reach[3]) {
+  reach[0] = reach[1] = reach[2] = 1;
   if (courant_max > 0.0) {
     if (!(courant_max < SLA_MAX_REACH))
       return fail(ctx, SLA_ECOURANT, "courant_max %g: must be below %d", courant_max, SLA_MAX_REACH);
     const int r = int(std::floor(courant_max)) + 1;
     reach[0] = reach[1] = reach[2] = r;
-  } else {
-    float cm[3];
-    rc = measure_courant(ctx, grid, geo, u, cm);
-    if (rc) return rc;
-    for (int d = 0; d < ndim; ++d) {
-      if (!(cm[d] < float(SLA_MAX_REACH)))
-        return fail(ctx, SLA_ECOURANT, "max Courant number %g on axis %d: must be below %d",
-                    double(cm[d]), d, SLA_MAX_REACH);
-      reach[d] = int(std::floor(cm[d])) + 1;
-    }
+    return SLA_OK;
   }
+  float cm[3];
+  const int rc = measure_courant(ctx, grid, geo, u, cm);
+  if (rc) return rc;
+  for (int d = 0; d < grid->ndim; ++d) {
+    if (!(cm[d] < float(SLA_MAX_REACH)))
+      return fail(ctx, SLA_ECOURANT, "max Courant number %g on axis %d: must be below %d",
+                  double(cm[d]), d, SLA_MAX_REACH);
+    reach[d] = int(std::floor(cm[d])) + 1;
+  }
+  return SLA_OK;
+}
+
+int advect_steps(sla_ctx* ctx, const sla_grid* grid, float* phi, const float* u, double dt,
+                 int32_t scheme, int32_t steps, int64_t step0, const int reach[3]);
+
+}  // namespace
+
+extern "C" {
+
+int sla_advect(sla_ctx* ctx, const sla_grid* grid, float* phi, const float* u, double dt,
+               int32_t scheme, int32_t steps, int64_t step0, double courant_max) {
+  if (!ctx) return SLA_EINVAL;
+  ctx->err.clear();
+  int rc = check_advect(ctx, grid, phi, u, dt, scheme, steps, courant_max);
+  if (rc) return rc;
+  if (steps == 0) return SLA_OK;
+  DeviceGuard guard(ctx->device);
+  if (!guard.ok) return fail(ctx, SLA_EHIP, "cannot select device %d", ctx->device);
+  int reach[3];
+  rc = advect_reach(ctx, grid, make_geo(grid, dt), u, courant_max, reach);
+  if (rc) return rc;
+  return advect_steps(ctx, grid, phi, u, dt, scheme, steps, step0, reach);
+}
+
+size_t sla_workspace_size(const sla_grid* grid, int32_t scheme, int32_t nscalars) {
+  if (!grid || grid->ndim < 1 || grid->ndim > 3 || scheme < SLA_CIR || scheme > SLA_CEC ||
+      nscalars < 0)
+    return 0;
+  size_t cells = 1;
+  for (int d = 0; d < 3; ++d) {
+    if (grid->n[d] < 1) return 0;
+    cells *= size_t(grid->n[d]);
+  }
+  return cells * sizeof(float);  // one ping-pong field; scalars run one after another
+}
+
+int sla_set_workspace(sla_ctx* ctx, void* dev_ptr, size_t bytes) {
+  if (!ctx) return SLA_EINVAL;
+  ctx->err.clear();
+  if (dev_ptr && bytes < sizeof(float)) return fail(ctx, SLA_EINVAL, "workspace of %zu bytes", bytes);
+  DeviceGuard guard(ctx->device);
+  if (!guard.ok) return fail(ctx, SLA_EHIP, "cannot select device %d", ctx->device);
+  const hipError_t e = hipStreamSynchronize(ctx->stream);  // earlier calls may still use it
+  if (e != hipSuccess) return hip_fail(ctx, e, "synchronise before changing the workspace");
+  if (ctx->work && !ctx->work_borrowed) (void)hipFree(ctx->work);
+  ctx->work = static_cast<float*>(dev_ptr);
+  ctx->work_cap = dev_ptr ? bytes / sizeof(float) : 0;
+  ctx->work_borrowed = dev_ptr != nullptr;
+  return SLA_OK;
+}
+
+int sla_advect_multi(sla_ctx* ctx, const sla_grid* grid, int32_t nscalars, float* const* phis,
+                     const float* u, double dt, int32_t scheme, int32_t steps, int64_t step0,
+                     double courant_max) {
+  if (!ctx) return SLA_EINVAL;
+  ctx->err.clear();
+  if (nscalars < 0 || (nscalars > 0 && !phis))
+    return fail(ctx, SLA_EINVAL, "need nscalars >= 0 and the array of fields");
+  for (int32_t k = 0; k < nscalars; ++k)
+    if (!phis[k]) return fail(ctx, SLA_EINVAL, "field %d is NULL", k);
+  int rc = check_advect(ctx, grid, nscalars > 0 ? phis[0] : u, u, dt, scheme, steps, courant_max);
+  if (rc) return rc;
+  if (steps == 0 || nscalars == 0) return SLA_OK;
+  DeviceGuard guard(ctx->device);
+  if (!guard.ok) return fail(ctx, SLA_EHIP, "cannot select device %d", ctx->device);
+  int reach[3];  // one Courant bound for all the fields
+  rc = advect_reach(ctx, grid, make_geo(grid, dt), u, courant_max, reach);
+  for (int32_t k = 0; k < nscalars && rc == SLA_OK; ++k)
+    rc = advect_steps(ctx, grid, phis[k], u, dt, scheme, steps, step0, reach);
+  return rc;
+}
+
+}  // extern "C"
+
+namespace {
+
+__global__ __launch_bounds__(256) void k_fill_velocity(float* __restrict__ u, size_t n, int ndim,
+                                                       float ux, float uy, float uz) {
+  for (size_t i = size_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += size_t(gridDim.x) * 256) {
+    u[i] = ux;
+    if (ndim > 1) u[n + i] = uy;
+    if (ndim > 2) u[2 * n + i] = uz;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int sla_advect_batch(sla_ctx* ctx, int32_t nprob, const sla_problem* probs, int32_t scheme,
+                     int32_t steps, int64_t step0, double courant_max) {
+  if (!ctx) return SLA_EINVAL;
+  ctx->err.clear();
+  if (nprob < 0 || (nprob > 0 && !probs)) return fail(ctx, SLA_EINVAL, "need nprob >= 0 and probs");
+  bool all3d = true;
+  for (int32_t i = 0; i < nprob; ++i) {
+    const sla_problem& p = probs[i];
+    const float* any_u = p.u ? p.u : p.u_uniform;  // a uniform problem passes the pointer check
+    int rc = check_advect(ctx, &p.grid, p.phi, any_u, p.dt, scheme, steps, courant_max);
+    if (rc) return rc;
+    if (!p.u)
+      for (int d = 0; d < p.grid.ndim; ++d)
+        if (!std::isfinite(p.u_uniform[d]))
+          return fail(ctx, SLA_EINVAL, "problem %d: non-finite uniform velocity", i);
+    all3d = all3d && p.grid.ndim == 3;
+  }
+  if (steps == 0 || nprob == 0) return SLA_OK;
+  DeviceGuard guard(ctx->device);
+  if (!guard.ok) return fail(ctx, SLA_EHIP, "cannot select device %d", ctx->device);
+  if (scheme == SLA_CEC && all3d) {
+    // every Courant number below 1: one plan (a graph of all steps), run once
+    sla_plan* plan = nullptr;
+    int rc = sla_plan_create(ctx, &plan, nprob, probs, steps, step0, courant_max, 0);
+    if (rc == SLA_OK) {
+      rc = sla_plan_run(ctx, plan);
+      const hipError_t e = hipStreamSynchronize(ctx->stream);  // before the plan's memory goes
+      sla_plan_destroy(plan);
+      if (rc == SLA_OK && e != hipSuccess) rc = hip_fail(ctx, e, "batched run");
+      return rc;
+    }
+    if (rc != SLA_ECOURANT) return rc;
+    ctx->err.clear();  // larger Courant numbers: problem by problem
+  }
+  // problem by problem; a uniform velocity is written into a temporary field
+  float* tmp = nullptr;
+  size_t tmp_cap = 0;
+  int rc = SLA_OK;
+  for (int32_t i = 0; i < nprob && rc == SLA_OK; ++i) {
+    const sla_problem& p = probs[i];
+    const float* u = p.u;
+    if (!u) {
+      const size_t n = size_t(p.grid.n[0]) * p.grid.n[1] * p.grid.n[2];
+      const size_t need = size_t(p.grid.ndim) * n;
+      if (need > tmp_cap) {
+        hipError_t e = hipStreamSynchronize(ctx->stream);
+        if (e == hipSuccess && tmp) e = hipFree(tmp);
+        tmp = nullptr;
+        tmp_cap = 0;
+        if (e == hipSuccess) e = hipMalloc(&tmp, need * sizeof(float));
+        if (e != hipSuccess) {
+          tmp = nullptr;
+          rc = hip_fail(ctx, e, "temporary velocity field");
+          break;
+        }
+        tmp_cap = need;
+      }
+      hipLaunchKernelGGL(k_fill_velocity, dim3(1024), dim3(256), 0, ctx->stream, tmp, n, p.grid.ndim,
+                         p.u_uniform[0], p.u_uniform[1], p.u_uniform[2]);
+      const hipError_t e = hipGetLastError();
+      if (e != hipSuccess) {
+        rc = hip_fail(ctx, e, "velocity fill");
+        break;
+      }
+      u = tmp;
+    }
+    int reach[3];
+    rc = advect_reach(ctx, &p.grid, make_geo(&p.grid, p.dt), u, courant_max, reach);
+    if (rc == SLA_OK) rc = advect_steps(ctx, &p.grid, p.phi, u, p.dt, scheme, steps, step0, reach);
+  }
+  if (tmp) {
+    const hipError_t e = hipStreamSynchronize(ctx->stream);
+    (void)hipFree(tmp);
+    if (rc == SLA_OK && e != hipSuccess) rc = hip_fail(ctx, e, "batched run");
+  }
+  return rc;
+}
+
+int sla_model_load(sla_ctx* ctx, sla_model* model, const float* params, int64_t n) {
+  return sla_model_set_params(ctx, model, params, n);
+}
+
+int sla_model_save(sla_ctx* ctx, const sla_model* model, float* params, int64_t n) {
+  return sla_model_get_params(ctx, model, params, n);
+}
+
+}  // extern "C"
+
+namespace {
+
+// The steps of sla_advect once the arguments are checked and the reach per
+// axis is known (the device is selected).
+int advect_steps(sla_ctx* ctx, const sla_grid* grid, float* phi, const float* u, double dt,
+                 int32_t scheme, int32_t steps, int64_t step0, const int reach[3]) {
+  const sla::Geo geo = make_geo(grid, dt);
+  const int ndim = grid->ndim;
+  int rc;
   int rmax = 1;
   for (int d = 0; d < ndim; ++d) rmax = reach[d] > rmax ? reach[d] : rmax;
 
@@ -419,6 +614,10 @@ int sla_advect(sla_ctx* ctx, const sla_grid* grid, float* phi, const float* u, d
   }
   return SLA_OK;
 }
+
+}  // namespace
+
+extern "C" {
 
 int sla_set_option(sla_ctx* ctx, int option, int64_t value) {
   if (!ctx) return SLA_EINVAL;

@@ -36,6 +36,12 @@ SIGNATURES = {
     "sla_courant_max": (_c.c_int, [_vp, _vp, _vp, _c.c_double, _c.POINTER(_c.c_double)]),
     "sla_advect": (_c.c_int, [_vp, _vp, _vp, _vp, _c.c_double, _c.c_int32, _c.c_int32,
                               _c.c_int64, _c.c_double]),
+    "sla_advect_multi": (_c.c_int, [_vp, _vp, _c.c_int32, _vp, _vp, _c.c_double, _c.c_int32,
+                                    _c.c_int32, _c.c_int64, _c.c_double]),
+    "sla_workspace_size": (_c.c_size_t, [_vp, _c.c_int32, _c.c_int32]),
+    "sla_set_workspace": (_c.c_int, [_vp, _vp, _c.c_size_t]),
+    "sla_advect_batch": (_c.c_int, [_vp, _c.c_int32, _vp, _c.c_int32, _c.c_int32, _c.c_int64,
+                                    _c.c_double]),
     "sla_check": (_c.c_int, [_vp]),
     "sla_norms": (_c.c_int, [_vp, _c.c_int64, _vp, _vp, _c.POINTER(_c.c_double)]),
     "sla_set_option": (_c.c_int, [_vp, _c.c_int, _c.c_int64]),
@@ -49,6 +55,8 @@ SIGNATURES = {
     "sla_model_destroy": (None, [_vp]),
     "sla_model_set_params": (_c.c_int, [_vp, _vp, _vp, _c.c_int64]),
     "sla_model_get_params": (_c.c_int, [_vp, _vp, _vp, _c.c_int64]),
+    "sla_model_load": (_c.c_int, [_vp, _vp, _vp, _c.c_int64]),
+    "sla_model_save": (_c.c_int, [_vp, _vp, _vp, _c.c_int64]),
     "sla_model_set_courant_range": (_c.c_int, [_vp, _c.c_double]),
     "sla_make_pairs": (_c.c_int, [_vp, _vp, _vp, _vp, _vp, _c.c_double, _vp, _c.c_int64, _vp,
                                   _vp, _vp]),
@@ -187,6 +195,53 @@ class Context:
                                         int(scheme), int(steps), int(step0), float(courant_max)))
         return phi
 
+    def advect_multi(self, phis, u, dx, dt, scheme, steps, step0=0, courant_max=0.0):
+        """Advance every field of ``phis`` (same shape) in place; they share ``u``."""
+        if isinstance(scheme, str):
+            scheme = SCHEMES[scheme]
+        for f in phis:
+            _check_field(f, "phi")
+            if f.shape != phis[0].shape:
+                raise ValueError("the fields must have one shape")
+        _check_field(u, "u")
+        if phis and tuple(u.shape) != (phis[0].dim(),) + tuple(phis[0].shape):
+            raise ValueError("u must have shape (ndim, *phi.shape)")
+        g = make_grid(phis[0].shape if phis else u.shape[1:], dx)
+        arr = (ctypes.c_void_p * max(1, len(phis)))(*[f.data_ptr() for f in phis])
+        self._stream()
+        self._raise(self.lib.sla_advect_multi(self.h, ctypes.byref(g), len(phis), arr, _ptr(u),
+                                              float(dt), int(scheme), int(steps), int(step0),
+                                              float(courant_max)))
+
+    def advect_batch(self, problems, scheme, steps, step0=0, courant_max=0.0):
+        """Advance independent problems in place: a list of ``(phi, u, dx, dt)``
+        with ``u`` a (ndim, *phi.shape) tensor or an ndim-tuple uniform velocity."""
+        if isinstance(scheme, str):
+            scheme = SCHEMES[scheme]
+        arr, keep = problem_array(problems)
+        self._stream()
+        self._raise(self.lib.sla_advect_batch(self.h, len(problems), arr, int(scheme), int(steps),
+                                              int(step0), float(courant_max)))
+        del keep
+
+    def workspace_size(self, shape, dx, scheme, nscalars=1):
+        """Device bytes of work memory ``advect`` needs on a grid of ``shape``."""
+        if isinstance(scheme, str):
+            scheme = SCHEMES[scheme]
+        g = make_grid(shape, dx)
+        return int(self.lib.sla_workspace_size(ctypes.byref(g), int(scheme), int(nscalars)))
+
+    def set_workspace(self, buf):
+        """Use the device tensor ``buf`` as the work memory (None: back to the
+        library's own).  The caller keeps ``buf`` alive while it is set."""
+        if buf is None:
+            self._raise(self.lib.sla_set_workspace(self.h, None, 0))
+        else:
+            if not buf.is_cuda or not buf.is_contiguous():
+                raise TypeError("the workspace must be a contiguous device tensor")
+            self._raise(self.lib.sla_set_workspace(self.h, _ptr(buf),
+                                                   buf.numel() * buf.element_size()))
+
     def set_option(self, option: int, value: int):
         self._raise(self.lib.sla_set_option(self.h, int(option), int(value)))
 
@@ -309,6 +364,32 @@ def advect_learned(ctx: Context, model: Model, phi, u, dx, dt, steps, step0=0, c
     return bool(fb.value)
 
 
+def problem_array(problems):
+    """``sla_problem`` array of ``(phi, u, dx, dt)`` problems, ``u`` a
+    (ndim, *phi.shape) tensor or an ndim-tuple uniform velocity; returns the
+    array and the objects it points into."""
+    arr = (Problem * max(1, len(problems)))()
+    keep = []
+    for i, (phi, u, dx, dt) in enumerate(problems):
+        _check_field(phi, "phi")
+        arr[i].grid = make_grid(phi.shape, dx)
+        arr[i].phi = phi.data_ptr()
+        if isinstance(u, (tuple, list)):
+            if len(u) != phi.dim():
+                raise ValueError("a uniform velocity has one component per axis")
+            arr[i].u = None
+            for d in range(len(u)):
+                arr[i].u_uniform[d] = float(u[d])
+        else:
+            _check_field(u, "u")
+            if tuple(u.shape) != (phi.dim(),) + tuple(phi.shape):
+                raise ValueError("u must have shape (ndim, *phi.shape)")
+            arr[i].u = u.data_ptr()
+        arr[i].dt = float(dt)
+        keep.append((phi, u))
+    return arr, keep
+
+
 class Plan:
     """Batched third-order steps of many 3D problems, replayed as one graph.
 
@@ -320,25 +401,9 @@ class Plan:
     def __init__(self, ctx: Context, problems, steps, step0=0, courant_max=0.0, tune=True):
         self.ctx = ctx
         self.lib = ctx.lib
-        arr = (Problem * len(problems))()
-        self._keep = []
-        for i, (phi, u, dx, dt) in enumerate(problems):
-            _check_field(phi, "phi")
-            if phi.dim() != 3:
-                raise ValueError("plans take 3D fields")
-            arr[i].grid = make_grid(phi.shape, dx)
-            arr[i].phi = phi.data_ptr()
-            if isinstance(u, (tuple, list)):
-                arr[i].u = None
-                for d in range(3):
-                    arr[i].u_uniform[d] = float(u[d])
-            else:
-                _check_field(u, "u")
-                if tuple(u.shape) != (3,) + tuple(phi.shape):
-                    raise ValueError("u must have shape (3, *phi.shape)")
-                arr[i].u = u.data_ptr()
-            arr[i].dt = float(dt)
-            self._keep.append((phi, u))
+        if any(phi.dim() != 3 for phi, _, _, _ in problems):
+            raise ValueError("plans take 3D fields")
+        arr, self._keep = problem_array(problems)
         h = ctypes.c_void_p()
         ctx._stream()
         ctx._raise(self.lib.sla_plan_create(ctx.h, ctypes.byref(h), len(problems), arr, int(steps),

@@ -40,7 +40,25 @@ def test_strerror_and_null_handling():
     assert lib.sla_advect(None, None, None, None, 0.0, 0, 0, 0, 0.0) == native.EINVAL
     assert lib.sla_norms(None, 0, None, None, None) == native.EINVAL
     assert lib.sla_check(None) == native.EINVAL
+    assert lib.sla_advect_multi(None, None, 0, None, None, 0.0, 0, 0, 0, 0.0) == native.EINVAL
+    assert lib.sla_advect_batch(None, 0, None, 0, 0, 0, 0.0) == native.EINVAL
+    assert lib.sla_set_workspace(None, None, 0) == native.EINVAL
+    assert lib.sla_workspace_size(None, 3, 1) == 0
     lib.sla_destroy(None)
+
+
+def test_workspace_size():
+    """One FP32 field of the grid, whatever the scheme and the number of
+    scalars; 0 for an invalid grid or scheme."""
+    import ctypes
+    from paper_1606_06117_amd import native
+    lib = native.load()
+    g = native.make_grid((12, 34, 56), (0.1, 0.1, 0.1))
+    for scheme in range(4):
+        for ns in (1, 16):
+            assert lib.sla_workspace_size(ctypes.byref(g), scheme, ns) == 4 * 12 * 34 * 56
+    assert lib.sla_workspace_size(ctypes.byref(g), 7, 1) == 0
+    assert lib.sla_workspace_size(ctypes.byref(g), 3, -1) == 0
 
 
 def test_create_without_device_is_an_error():
