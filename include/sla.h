@@ -57,7 +57,9 @@ typedef enum {
                         met a Courant number beyond the bound it was given */
   SLA_EHIP = -3,     /* HIP runtime error */
   SLA_ENOMEM = -4,   /* device allocation failed */
-  SLA_ENOMODEL = -5  /* learned correction called without usable weights */
+  SLA_ENOMODEL = -5, /* learned correction called without usable weights */
+  SLA_ECAPTURE = -6  /* the call would synchronise the stream or allocate while
+                        the stream is being captured into a graph */
 } sla_status;
 
 /* Largest backtrace reach, in cells, the kernels are built for: every
@@ -112,7 +114,12 @@ int sla_courant_max(sla_ctx *ctx, const sla_grid *grid, const float *u,
  * steps == 0 is a successful no-op.  Work memory (one field) is allocated on
  * the context on first use and kept, unless the caller gave the context a
  * workspace (sla_set_workspace).  The result is in phi when the stream
- * reaches the end of the call. */
+ * reaches the end of the call.
+ *
+ * Graph capture: the call only launches kernels (and at most one device
+ * copy) when courant_max > 0 and the work memory is large enough, so it can
+ * be captured into a graph; while the stream is captured it returns
+ * SLA_ECAPTURE instead of measuring the bound or allocating. */
 int sla_advect(sla_ctx *ctx, const sla_grid *grid, float *phi, const float *u,
                double dt, int32_t scheme, int32_t steps, int64_t step0,
                double courant_max);

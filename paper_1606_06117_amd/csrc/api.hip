@@ -198,8 +198,18 @@ void fold_marks(sla_ctx* ctx) {
   ctx->marks.clear();
 }
 
+// True while the context's stream is being captured into a graph: a call
+// must then neither synchronise nor allocate.
+bool capturing(sla_ctx* ctx) {
+  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+  return hipStreamIsCapturing(ctx->stream, &st) == hipSuccess && st != hipStreamCaptureStatusNone;
+}
+
 int ensure_work(sla_ctx* ctx, size_t floats) {
   if (ctx->work_cap >= floats) return SLA_OK;
+  if (capturing(ctx))
+    return fail(ctx, SLA_ECAPTURE, "work memory would be allocated while the stream is captured: "
+                "run the call once before capturing, or set a workspace");
   if (ctx->work_borrowed)
     return fail(ctx, SLA_EINVAL, "the workspace holds %zu bytes, the call needs %zu",
                 ctx->work_cap * sizeof(float), floats * sizeof(float));
@@ -231,6 +241,7 @@ const char* sla_strerror(int status) {
     case SLA_EHIP: return "HIP runtime error";
     case SLA_ENOMEM: return "out of device memory";
     case SLA_ENOMODEL: return "no usable model weights";
+    case SLA_ECAPTURE: return "not allowed while the stream is captured into a graph";
   }
   return "unknown status";
 }
@@ -292,6 +303,7 @@ int sla_set_stream(sla_ctx* ctx, void* stream) {
 int sla_courant_max(sla_ctx* ctx, const sla_grid* grid, const float* u, double dt, double* out) {
   if (!ctx) return SLA_EINVAL;
   ctx->err.clear();
+  if (capturing(ctx)) return fail(ctx, SLA_ECAPTURE, "this call synchronises the stream");
   int rc = check_grid(ctx, grid);
   if (rc) return rc;
   if (!u || !out) return fail(ctx, SLA_EINVAL, "u and out must not be NULL");
@@ -335,6 +347,9 @@ int advect_reach(sla_ctx* ctx, const sla_grid* grid, const sla::Geo& geo, const 
     reach[0] = reach[1] = reach[2] = r;
     return SLA_OK;
   }
+  if (capturing(ctx))
+    return fail(ctx, SLA_ECAPTURE, "measuring the Courant bound synchronises the stream: "
+                "pass courant_max > 0 while capturing");
   float cm[3];
   const int rc = measure_courant(ctx, grid, geo, u, cm);
   if (rc) return rc;
@@ -384,6 +399,7 @@ size_t sla_workspace_size(const sla_grid* grid, int32_t scheme, int32_t nscalars
 int sla_set_workspace(sla_ctx* ctx, void* dev_ptr, size_t bytes) {
   if (!ctx) return SLA_EINVAL;
   ctx->err.clear();
+  if (capturing(ctx)) return fail(ctx, SLA_ECAPTURE, "this call synchronises the stream");
   if (dev_ptr && bytes < sizeof(float)) return fail(ctx, SLA_EINVAL, "workspace of %zu bytes", bytes);
   DeviceGuard guard(ctx->device);
   if (!guard.ok) return fail(ctx, SLA_EHIP, "cannot select device %d", ctx->device);
@@ -439,6 +455,7 @@ int sla_advect_batch(sla_ctx* ctx, int32_t nprob, const sla_problem* probs, int3
   if (!ctx) return SLA_EINVAL;
   ctx->err.clear();
   if (nprob < 0 || (nprob > 0 && !probs)) return fail(ctx, SLA_EINVAL, "need nprob >= 0 and probs");
+  if (capturing(ctx)) return fail(ctx, SLA_ECAPTURE, "batches synchronise the stream");
   bool all3d = true;
   for (int32_t i = 0; i < nprob; ++i) {
     const sla_problem& p = probs[i];
@@ -643,6 +660,7 @@ int sla_set_option(sla_ctx* ctx, int option, int64_t value) {
 int sla_check(sla_ctx* ctx) {
   if (!ctx) return SLA_EINVAL;
   ctx->err.clear();
+  if (capturing(ctx)) return fail(ctx, SLA_ECAPTURE, "this call synchronises the stream");
   DeviceGuard guard(ctx->device);
   int* h = static_cast<int*>(ctx->host);
   hipError_t e = hipMemcpyAsync(h, ctx->flag, sizeof(int), hipMemcpyDeviceToHost, ctx->stream);
@@ -660,6 +678,7 @@ int sla_check(sla_ctx* ctx) {
 int sla_norms(sla_ctx* ctx, int64_t count, const float* a, const float* b, double* out) {
   if (!ctx) return SLA_EINVAL;
   ctx->err.clear();
+  if (capturing(ctx)) return fail(ctx, SLA_ECAPTURE, "this call synchronises the stream");
   if (count < 0) return fail(ctx, SLA_EINVAL, "count must be >= 0");
   if (!out) return fail(ctx, SLA_EINVAL, "out must not be NULL");
   if (count == 0) {

@@ -18,7 +18,7 @@ CIR, FEC, BEC, CEC = 0, 1, 2, 3
 SCHEMES = {"cir": CIR, "fec": FEC, "bec": BEC, "cec": CEC}
 MAX_REACH = 4
 
-OK, EINVAL, ECOURANT, EHIP, ENOMEM, ENOMODEL = 0, -1, -2, -3, -4, -5
+OK, EINVAL, ECOURANT, EHIP, ENOMEM, ENOMODEL, ECAPTURE = 0, -1, -2, -3, -4, -5, -6
 OPT_FUSED = 0
 OPT_CEC3D_KERNEL = 1
 CEC3D_DEFAULT = 5  # the library's default fused-step implementation

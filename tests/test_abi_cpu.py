@@ -36,6 +36,7 @@ def test_strerror_and_null_handling():
     assert lib.sla_strerror(0) == b"success"
     assert lib.sla_strerror(-2).startswith(b"Courant")
     assert lib.sla_strerror(12345) == b"unknown status"
+    assert b"captured" in lib.sla_strerror(native.ECAPTURE)
     assert lib.sla_last_error(None) == b""
     assert lib.sla_advect(None, None, None, None, 0.0, 0, 0, 0, 0.0) == native.EINVAL
     assert lib.sla_norms(None, 0, None, None, None) == native.EINVAL

@@ -2,6 +2,8 @@
 of independent problems of any scheme, and a caller-owned workspace.  Every
 result equals the standalone sla_advect run bit for bit."""
 
+import warnings
+
 import numpy as np
 import pytest
 
@@ -111,3 +113,41 @@ def test_caller_workspace(ctx):
     ctx.advect(p, ud, dx, dt, native.CEC, 3)
     torch.cuda.synchronize()
     assert np.array_equal(p.cpu().numpy().astype(np.float64), ref)
+
+
+def test_graph_capture_and_replays(ctx):
+    """Two third-order steps (courant_max given, work memory already there)
+    captured into a graph: every replay, with eager runs and synchronisations
+    between replays, equals the eager result bitwise.  A call that would
+    measure the Courant bound while the stream is captured is refused."""
+    import torch
+    from paper_1606_06117_amd import native
+    shape = (24, 40, 72)
+    u = torch.from_numpy(W.abc_velocity(shape)).cuda()
+    dx = tuple(2 * np.pi / n for n in reversed(shape))
+    dt = 0.9 * dx[0] / 2
+    phi0 = torch.from_numpy(W.random_gaussians(shape, 4, seed=80).astype(np.float32)).cuda()
+    warm = phi0.clone()
+    ctx.advect(warm, u, dx, dt, native.CEC, 2, 0, 0.9)  # allocates the work memory
+    torch.cuda.synchronize()
+    static = phi0.clone()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        ctx.advect(static, u, dx, dt, native.CEC, 2, 0, 0.9)
+    torch.cuda.synchronize()
+    assert torch.equal(static, phi0)  # capturing ran nothing
+    expected = phi0.clone()
+    for rep in range(3):
+        g.replay()
+        ctx.advect(expected, u, dx, dt, native.CEC, 2, 0, 0.9)  # eager, between replays
+        torch.cuda.synchronize()
+        assert torch.equal(static, expected), rep
+    g2 = torch.cuda.CUDAGraph()
+    other = phi0.clone()
+    with pytest.raises(native.SlaError) as ei, warnings.catch_warnings():
+        warnings.simplefilter("ignore")  # the refused capture leaves an empty graph
+        with torch.cuda.graph(g2):
+            ctx.advect(other, u, dx, dt, native.CEC, 1)  # would measure the bound
+    assert ei.value.status == native.ECAPTURE
+    torch.cuda.synchronize()
+    ctx.check()
