@@ -95,6 +95,38 @@ def cpu_baseline(phi, u, dx, dt, scheme, edge, steps):
     }
 
 
+def cpu_all_cores(phi, u, dx, dt, scheme, edge, zedge, steps, workers):
+    """The same oracle over z-slabs with halos in ``workers`` processes.
+
+    The sample is a periodic ``zedge x edge x edge`` sub-box of the same
+    inputs; each step every worker advances one slab plus the planes one step
+    can read, so the result is the one-process result bit for bit.
+    """
+    import numpy as np
+    from oracle import slabs
+    sub = phi[:zedge, :edge, :edge].astype(np.float64)
+    usub = np.ascontiguousarray(u[:, :zedge, :edge, :edge])
+    p0 = resource.getrusage(resource.RUSAGE_SELF)
+    c0 = resource.getrusage(resource.RUSAGE_CHILDREN)
+    with slabs.SlabPool(usub, dx, dt, scheme, workers) as pool:
+        t0 = time.perf_counter()
+        pool.advect(sub, steps)
+        wall = time.perf_counter() - t0
+        used, halo = pool.workers, pool.halo
+    p1 = resource.getrusage(resource.RUSAGE_SELF)
+    c1 = resource.getrusage(resource.RUSAGE_CHILDREN)
+    cpu = sum(b.ru_utime - a.ru_utime + b.ru_stime - a.ru_stime for a, b in ((p0, p1), (c0, c1)))
+    return {
+        "value": zedge * edge * edge * steps / wall / 1e9,
+        "unit": "Gcell-updates/s",
+        "cores": used,
+        "busy_cores": round(cpu / wall, 1),
+        "sample": f"FP64 NumPy oracle over {used} z-slabs (+{halo} halo planes each side) in "
+                  f"{used} processes, {zedge}x{edge}x{edge} periodic sub-box of the same inputs, "
+                  f"{steps} steps ({wall:.1f} s wall; busy cores include pool start-up)",
+    }
+
+
 def copy_probe(reps: int, warmup: int) -> int:
     """Copy a 512 MiB FP32 buffer ``reps`` times (read 512 MiB + write 512 MiB each)."""
     import torch
@@ -308,6 +340,10 @@ def main(argv=None):
     ap.add_argument("--cpu-edge", type=int, default=128, help="edge of the oracle's sample box")
     ap.add_argument("--cpu-steps", type=int, default=60, help="oracle steps on the sample box (about 13 s)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-workers", type=int, default=min(len(os.sched_getaffinity(0)), 16),
+                    help="processes of the all-core oracle figure (0: skip it)")
+    ap.add_argument("--cpu-all-steps", type=int, default=20,
+                    help="oracle steps of the all-core figure on a --size x edge x edge box")
     ap.add_argument("--path", choices=["auto", "sweeps"], default="auto",
                     help="auto: fused step where the library has one; sweeps: one kernel per axis")
     ap.add_argument("--other-cfl", choices=["on", "off"], default="on",
@@ -455,6 +491,11 @@ def main(argv=None):
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle sample ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(phi0, u, dx, dt, scheme, args.cpu_edge, args.cpu_steps)
+        if args.cpu_workers > 0:
+            print(f"[bench] timing the CPU oracle on {args.cpu_workers} processes ...",
+                  file=sys.stderr, flush=True)
+            out["cpu_baseline"]["all_cores"] = cpu_all_cores(
+                phi0, u, dx, dt, scheme, args.cpu_edge, args.size, args.cpu_all_steps, args.cpu_workers)
     else:
         out["cpu_baseline"] = None
 

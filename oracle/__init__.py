@@ -14,6 +14,8 @@ schemes  departure decomposition, interpolation operator L_U, CIR, FEC, BEC and
 norms    FP64 error and mass reductions.
 mlp      FP64 forward/backward of the learned per-cell correction network
          (not in the paper; the network shape is the library's).
+slabs    the same advection run over slabs in worker processes, bit for bit
+         the one-process result (for timing the oracle on every core).
 
 Every function is pinned by CPU tests against closed forms the paper prints
 (constant-velocity stencils, amplification factors, modified equations),
