@@ -16,6 +16,10 @@ mlp      FP64 forward/backward of the learned per-cell correction network
          (not in the paper; the network shape is the library's).
 slabs    the same advection run over slabs in worker processes, bit for bit
          the one-process result (for timing the oracle on every core).
+characteristics
+         exact solutions under a variable velocity: the initial field at the
+         foot of each node's characteristic (RK4 in FP64), the fully
+         Lagrangian reference of section 6.
 
 Every function is pinned by CPU tests against closed forms the paper prints
 (constant-velocity stencils, amplification factors, modified equations),

@@ -68,6 +68,31 @@ def random_gaussians(shape, count, seed, length=TWO_PI, smin=0.05, smax=0.15):
     return gaussians(shape, centres, sigmas, length)
 
 
+def gaussians_at(points, centres, sigmas, length=1.0, amplitude=1.0):
+    """``gaussians`` evaluated at arbitrary ``points`` (rows, x first), FP64.
+
+    Points are wrapped into the box first, so the value is that of the
+    periodic field ``gaussians`` samples at the nodes.
+    """
+    p = np.mod(np.asarray(points, dtype=np.float64), length)
+    out = np.zeros(p.shape[0], dtype=np.float64)
+    for c, s in zip(centres, sigmas):
+        prod = np.ones(p.shape[0], dtype=np.float64)
+        for d in range(p.shape[1]):
+            prod *= _periodic_gauss_1d(p[:, d], c[d], s, length)
+        out += amplitude * prod
+    return out
+
+
+def random_gaussians_at(points, count, seed, length=TWO_PI, smin=0.05, smax=0.15):
+    """The field of ``random_gaussians`` (same seed) at arbitrary ``points``."""
+    rng = np.random.default_rng(seed)
+    ndim = np.asarray(points).shape[1]
+    centres = rng.uniform(0.0, length, (count, ndim))
+    sigmas = length * rng.uniform(smin, smax, count)
+    return gaussians_at(points, centres, sigmas, length)
+
+
 def abc_velocity(shape, A=1.0, B=1.0, C=1.0, dtype=np.float32):
     """ABC flow on ``[0, 2 pi)^3`` sampled at the nodes; returns (3, nz, ny, nx)."""
     nz, ny, nx = shape
@@ -199,15 +224,8 @@ def power_law_torch(shape, seed, device, kmax=64):
     ``device`` in FP64; FP32 tensor."""
     import torch
     nz, ny, nx = shape
-    rng = np.random.default_rng(seed)
-    kb = np.arange(-kmax, kmax + 1)
-    kxb = np.arange(0, kmax + 1)
-    KZ, KY, KX = np.meshgrid(kb, kb, kxb, indexing="ij")
-    kk = np.sqrt(KX * KX + KY * KY + KZ * KZ)
-    with np.errstate(divide="ignore"):
-        amp = np.where((kk >= 1.0) & (kk <= kmax), kk ** (-11.0 / 6.0), 0.0)
-    ph = rng.uniform(0.0, TWO_PI, amp.shape)
-    block = torch.from_numpy(amp * np.exp(1j * ph)).to(device)
+    kb, _, coef = _power_law_block(seed, kmax)
+    block = torch.from_numpy(coef).to(device)
     spec = torch.zeros((nz, ny, nx // 2 + 1), dtype=torch.complex128, device=device)
     iz = torch.from_numpy(kb % nz).to(device)
     iy = torch.from_numpy(kb % ny).to(device)
@@ -216,6 +234,59 @@ def power_law_torch(shape, seed, device, kmax=64):
     del spec
     out /= torch.sqrt(torch.mean(out * out))
     return out.float().contiguous()
+
+
+def _power_law_block(seed, kmax):
+    """The seeded spectral block of ``power_law_torch``: (kz, ky, kx) with
+    ``|kz|, |ky| <= kmax`` and ``0 <= kx <= kmax``; the wave numbers and the
+    complex coefficients."""
+    rng = np.random.default_rng(seed)
+    kb = np.arange(-kmax, kmax + 1)
+    kxb = np.arange(0, kmax + 1)
+    KZ, KY, KX = np.meshgrid(kb, kb, kxb, indexing="ij")
+    kk = np.sqrt(KX * KX + KY * KY + KZ * KZ)
+    with np.errstate(divide="ignore"):
+        amp = np.where((kk >= 1.0) & (kk <= kmax), kk ** (-11.0 / 6.0), 0.0)
+    ph = rng.uniform(0.0, TWO_PI, amp.shape)
+    return kb, kxb, amp * np.exp(1j * ph)
+
+
+def power_law_at(points, seed, kmax=64, chunk=256):
+    """The field of ``power_law_torch`` (same seed) at arbitrary ``points``
+    (rows x, y, z on [0, 2 pi)^3), FP64.
+
+    The inverse real FFT of the block is, on any grid finer than 2 kmax + 1
+    nodes per axis, the samples of one trigonometric polynomial: each
+    coefficient of the kx = 0 plane contributes the real part of its wave,
+    each of kx > 0 twice that (the conjugate half of the spectrum).  Its mean
+    square follows from Parseval's identity, so the unit-RMS field does not
+    depend on the grid.
+    """
+    kb, kxb, c = _power_law_block(seed, kmax)
+    w = np.where(kxb == 0, 1.0, 2.0)
+    cw = (c * w[None, None, :]).reshape(-1, kxb.size)
+    # mean square: Hermitian-completed coefficients G_k, sum of |G_k|^2
+    n = 2 * kmax + 1
+    G = np.zeros((n, n, n), dtype=np.complex128)
+    iz = (kb % n)[:, None, None]
+    iy = (kb % n)[None, :, None]
+    ix = kxb[None, None, :]
+    half = np.where(kxb == 0, 0.5, 1.0)[None, None, :]
+    np.add.at(G, (iz, iy, ix % n), c * half)
+    np.add.at(G, (((-kb) % n)[:, None, None], ((-kb) % n)[None, :, None], (-kxb) % n),
+              np.conj(c) * half)
+    rms = math.sqrt(float(np.sum(np.abs(G) ** 2)))
+    p = np.asarray(points, dtype=np.float64)
+    out = np.empty(p.shape[0], dtype=np.float64)
+    for s in range(0, p.shape[0], chunk):
+        q = p[s:s + chunk]
+        ex = np.exp(1j * q[:, 0:1] * kxb[None, :])        # (P, Kx)
+        ey = np.exp(1j * q[:, 1:2] * kb[None, :])         # (P, K)
+        ez = np.exp(1j * q[:, 2:3] * kb[None, :])
+        t1 = (cw @ ex.T).reshape(kb.size, kb.size, -1)    # (Kz, Ky, P)
+        t2 = np.einsum("zyp,py->zp", t1, ey)
+        out[s:s + chunk] = np.einsum("zp,pz->p", t2, ez).real
+    return out / rms
 
 
 def abc_dt(shape, cfl, length=TWO_PI, umax=2.0):

@@ -1,0 +1,113 @@
+"""The characteristics reference, and the schemes' orders under a variable velocity.
+
+The exact solution of a variable-velocity problem is the initial field at the
+foot of each node's characteristic.  The foot finder is pinned here to closed
+forms (a uniform velocity; the ABC flow with B = C = 0, whose characteristics
+are straight lines; the conserved stream function of the cellular flow) and to
+its own fourth order; the point evaluation of the initial fields is pinned to
+the grid samples.  With that reference, the oracle's schemes converge at
+first order (CIR) and second order (FEC, BEC and the third-order scheme) under
+the 2D cellular flow: the one-step backtrace from the arrival node and the
+splitting cap the order at 2 once the velocity varies (the paper's order-3
+analysis is for a uniform velocity, sections 3-4).
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import characteristics as ch
+from paper_1606_06117_amd import workloads as W
+
+L = 2 * math.pi
+
+
+def test_uniform_foot_is_exact():
+    rng = np.random.default_rng(0)
+    p = rng.uniform(0, L, (50, 3))
+    u = (0.3, -1.7, 2.2)
+    got = ch.foot(p, ch.uniform(u), 0.8, 3)
+    assert np.allclose(got, p - 0.8 * np.asarray(u), rtol=0, atol=1e-14)
+
+
+def test_abc_a_only_closed_form():
+    """A = 1, B = C = 0: u = sin z, v = cos z, w = 0, so z is constant and the
+    characteristics are straight lines."""
+    rng = np.random.default_rng(1)
+    p = rng.uniform(0, L, (200, 3))
+    T = 1.3
+    got = ch.foot(p, ch.abc(1.0, 0.0, 0.0), T, 40)
+    x, y, z = p.T
+    want = np.stack([x - T * np.sin(z), y - T * np.cos(z), z], axis=1)
+    assert np.max(np.abs(got - want)) < 1e-13
+
+
+def test_cellular_stream_function_conserved():
+    rng = np.random.default_rng(2)
+    p = rng.uniform(0, L, (500, 2))
+    f = ch.foot(p, ch.cellular(), 2.0, 400)
+    psi = lambda q: np.sin(q[:, 0]) * np.sin(q[:, 1])  # noqa: E731
+    assert np.max(np.abs(psi(f) - psi(p))) < 1e-10
+    assert np.max(np.abs(f - p)) > 0.1   # the points did move
+
+
+def test_rk4_is_fourth_order():
+    rng = np.random.default_rng(3)
+    p = rng.uniform(0, L, (100, 3))
+    vel = ch.abc()
+    ref = ch.foot(p, vel, 1.0, 640)
+    e1 = np.max(np.abs(ch.foot(p, vel, 1.0, 10) - ref))
+    e2 = np.max(np.abs(ch.foot(p, vel, 1.0, 20) - ref))
+    assert 12.0 < e1 / e2 < 20.0
+
+
+@pytest.mark.parametrize("shape", [(20, 24), (10, 12, 14)])
+def test_gaussians_at_nodes_match_grid(shape):
+    pts = ch.node_points(shape, L)
+    grid = W.random_gaussians(shape, 5, seed=9)
+    at = W.random_gaussians_at(pts, 5, seed=9).reshape(shape)
+    assert np.max(np.abs(grid - at)) < 1e-14
+    # wrapped points give the periodic field's values
+    shifted = W.random_gaussians_at(pts + L * np.array([1.0, -2.0, 3.0][:len(shape)]), 5, seed=9)
+    assert np.max(np.abs(shifted.reshape(shape) - grid)) < 1e-13
+
+
+@pytest.mark.parametrize("N,kmax", [(24, 8), (40, 12)])
+def test_power_law_at_nodes_matches_grid(N, kmax):
+    """The grid the power-law generator builds (inverse FFT in FP64, rounded to
+    FP32) holds the point evaluation's values at its nodes, on grids of two
+    sizes: one continuous field, the same on every grid finer than 2 kmax + 1."""
+    torch = pytest.importorskip("torch")
+    shape = (N, N + 2, N + 4)
+    grid = W.power_law_torch(shape, 5, torch.device("cpu"), kmax=kmax).double().numpy()
+    at = W.power_law_at(ch.node_points(shape, L), 5, kmax).reshape(shape)
+    assert np.sqrt(np.mean(at * at)) == pytest.approx(1.0, abs=1e-12)
+    assert np.max(np.abs(grid - at)) <= 2.0 ** -23 * np.max(np.abs(at))
+
+
+def _variable_u_errors(scheme, Ns, T=1.0, cfl=0.8):
+    errs = []
+    for N in Ns:
+        shape = (N, N)
+        phi = W.random_gaussians(shape, 4, seed=11)
+        u = W.cellular_velocity_2d(shape)
+        dx = (L / N, L / N)
+        steps = int(round(T / (cfl * dx[0])))       # max |u| = 1
+        out = oracle.advect(phi, u, dx, T / steps, scheme, steps)
+        exact = W.random_gaussians_at(ch.foot(ch.node_points(shape, L), ch.cellular(), T, 200),
+                                      4, seed=11).reshape(shape)
+        errs.append(oracle.rel_l2(out, exact))
+    return errs
+
+
+@pytest.mark.parametrize("scheme,order", [("cir", 1), ("fec", 2), ("bec", 2), ("cec", 2)])
+def test_variable_velocity_orders(scheme, order):
+    """Cellular flow, 4 Gaussians, T = 1 at CFL 0.8, N = 32, 64, 128.  Measured
+    slopes at the finest pair: 0.94 / 1.97 / 1.89 / 1.83 (the third-order
+    scheme's slope still rising: 1.78, 1.83, 1.92 up to N = 256)."""
+    errs = _variable_u_errors(scheme, (32, 64, 128))
+    assert errs[0] > errs[1] > errs[2]
+    slope = math.log2(errs[1] / errs[2])
+    assert abs(slope - order) < 0.25, (errs, slope)
