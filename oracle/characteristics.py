@@ -38,6 +38,19 @@ def cellular(amp=1.0):
     return vel
 
 
+def swirl(length=1.0):
+    """The 2D patch test's flow (section 5): ``u = P(y/l)``, ``v = -P(x/l)``,
+    ``P(e) = e (1 - e) (1/2 - e) [cos(2 pi e (1 - e)) + 1] / (2 pi^2)``."""
+    def prof(e):
+        s = e * (1.0 - e)
+        return s * (0.5 - e) * (np.cos(2.0 * np.pi * s) + 1.0) / (2.0 * np.pi ** 2)
+
+    def vel(p, t):
+        q = np.mod(p, length) / length
+        return np.stack([prof(q[:, 1]), -prof(q[:, 0])], axis=1)
+    return vel
+
+
 def uniform(u):
     """Constant velocity ``u`` (x first)."""
     u = np.asarray(u, dtype=np.float64)

@@ -126,6 +126,40 @@ def cellular_velocity_2d(shape, amp=1.0, dtype=np.float32):
     return u
 
 
+def _swirl_profile(eta):
+    """``eta (1 - eta) (1/2 - eta) [cos(2 pi eta (1 - eta)) + 1] / (2 pi^2)``."""
+    s = eta * (1.0 - eta)
+    return s * (0.5 - eta) * (np.cos(TWO_PI * s) + 1.0) / (2.0 * math.pi ** 2)
+
+
+def swirl_velocity_2d(shape, length=1.0, dtype=np.float32):
+    """The swirling flow of the paper's 2D patch test (section 5) on
+    ``[0, length)^2``: ``u = P(y / length)``, ``v = -P(x / length)`` with
+    ``P(eta) = eta (1 - eta) (1/2 - eta) [cos(2 pi eta (1 - eta)) + 1] / (2 pi^2)``.
+    Zero on the box edges, divergence free; (2, ny, nx)."""
+    ny, nx = shape
+    x = node_coords(nx, length) / length
+    y = node_coords(ny, length) / length
+    u = np.empty((2, ny, nx), dtype=dtype)
+    u[0] = np.broadcast_to(_swirl_profile(y)[:, None], shape).astype(dtype)
+    u[1] = np.broadcast_to(-_swirl_profile(x)[None, :], shape).astype(dtype)
+    return u
+
+
+def square_patch_at(points, lo, hi):
+    """1 inside the square ``[lo, hi)`` (per axis, x first), 0 outside."""
+    p = np.asarray(points, dtype=np.float64)
+    inside = np.all((p >= np.asarray(lo)) & (p < np.asarray(hi)), axis=1)
+    return inside.astype(np.float64)
+
+
+def square_patch(shape, lo, hi, length=1.0):
+    """``square_patch_at`` at the nodes of a periodic 2D grid."""
+    ny, nx = shape
+    X, Y = np.meshgrid(node_coords(nx, length), node_coords(ny, length))
+    return square_patch_at(np.stack([X.ravel(), Y.ravel()], axis=1), lo, hi).reshape(shape)
+
+
 def _fourier_parts(shape, seed, kmax):
     rng = np.random.default_rng(seed)
     nz, ny, nx = shape

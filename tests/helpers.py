@@ -7,6 +7,8 @@ import math
 import numpy as np
 
 import oracle
+from oracle import characteristics as ch
+from paper_1606_06117_amd import workloads as W
 
 
 def gpu_advect(ctx, phi, u, dx, dt, scheme, steps, step0=0, courant_max=0.0):
@@ -67,3 +69,18 @@ def box_parity(gpu_out, phi0, u, dx, dt, scheme, steps, halo, inner, rng, nboxes
 
 def reach(cfl):
     return int(math.floor(cfl)) + 1
+
+
+PATCH_LO, PATCH_HI, PATCH_T, SWIRL_UMAX = (0.15, 0.55), (0.40, 0.80), 200.0, 0.0038538656
+
+
+def patch_case(N, cfl=0.75):
+    """The 2D patch test: a unit square patch, the swirl flow, T = 200, CFL
+    0.75 (u_max = 0.00385); the exact field at the nodes by characteristics."""
+    shape = (N, N)
+    phi = W.square_patch(shape, PATCH_LO, PATCH_HI)
+    u = W.swirl_velocity_2d(shape)
+    steps = int(math.ceil(PATCH_T / (cfl / N / SWIRL_UMAX)))
+    feet = np.mod(ch.foot(ch.node_points(shape, 1.0), ch.swirl(), PATCH_T, 200), 1.0)
+    exact = W.square_patch_at(feet, PATCH_LO, PATCH_HI).reshape(shape)
+    return phi, u, (1.0 / N, 1.0 / N), PATCH_T / steps, steps, exact

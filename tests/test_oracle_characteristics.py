@@ -21,6 +21,8 @@ import oracle
 from oracle import characteristics as ch
 from paper_1606_06117_amd import workloads as W
 
+from helpers import patch_case
+
 L = 2 * math.pi
 
 
@@ -85,6 +87,57 @@ def test_power_law_at_nodes_matches_grid(N, kmax):
     at = W.power_law_at(ch.node_points(shape, L), 5, kmax).reshape(shape)
     assert np.sqrt(np.mean(at * at)) == pytest.approx(1.0, abs=1e-12)
     assert np.max(np.abs(grid - at)) <= 2.0 ** -23 * np.max(np.abs(at))
+
+
+def _swirl_primitive(e):
+    """F(s(e)) with s = e (1 - e): dF/de is the swirl profile P(e) (the
+    substitution ds = 2 (1/2 - e) de turns P de into s (cos 2 pi s + 1) ds / 2)."""
+    s = e * (1 - e)
+    return (0.5 * (s * np.sin(2 * np.pi * s) / (2 * np.pi) + np.cos(2 * np.pi * s) / (4 * np.pi ** 2)
+                   + s * s / 2) / (2 * np.pi ** 2))
+
+
+def test_swirl_velocity():
+    """The 2D patch flow: the grid sampler and the point formula agree, the
+    velocity is zero on the box edges, and H = F(x) + F(y) (with F' the
+    profile) is conserved along the characteristics, since x' = P(y) and
+    y' = -P(x) make dH/dt = P(x) P(y) - P(y) P(x) = 0."""
+    shape = (24, 40)
+    grid = W.swirl_velocity_2d(shape)
+    pts = ch.node_points(shape, 1.0)
+    at = ch.swirl()(pts, 0.0)
+    assert np.max(np.abs(grid[0].ravel() - at[:, 0])) < 1e-9
+    assert np.max(np.abs(grid[1].ravel() - at[:, 1])) < 1e-9
+    assert np.all(grid[0][0] == 0.0) and np.all(grid[1][:, 0] == 0.0)
+    edge = ch.swirl()(np.array([[0.3, 1.0], [1.0, 0.7]]), 0.0)
+    assert abs(edge[0, 0]) < 1e-17 and abs(edge[1, 1]) < 1e-17
+    e = np.linspace(0.01, 0.99, 97)
+    d = (_swirl_primitive(e + 1e-6) - _swirl_primitive(e - 1e-6)) / 2e-6
+    assert np.max(np.abs(d - ch.swirl()(np.stack([np.zeros_like(e), e], 1), 0.0)[:, 0])) < 1e-10
+    rng = np.random.default_rng(4)
+    p = rng.uniform(0, 1, (300, 2))
+    f = ch.foot(p, ch.swirl(), 200.0, 400)
+    # the flow is periodic: H is evaluated at the wrapped position.  The
+    # profile's second derivative jumps at the box edges, so RK4 is less
+    # accurate on paths across them (5e-11 here, 8e-13 at 1600 sub-steps).
+    H = lambda q: _swirl_primitive(q[:, 0] % 1.0) + _swirl_primitive(q[:, 1] % 1.0)  # noqa: E731
+    assert np.max(np.abs(H(f) - H(p))) < 1e-10
+    assert np.max(np.abs(f - p)) > 0.1
+
+
+def test_patch2d_oracle_ranking():
+    """Section 5's observations, at N = 64: CIR is furthest from the
+    Lagrangian reference and the third-order scheme nearest; FEC and BEC
+    ring (dispersion) more than the third order does."""
+    phi, u, dx, dt, steps, exact = patch_case(64)
+    l1, over = {}, {}
+    for s in ("cir", "fec", "bec", "cec"):
+        out = oracle.advect(phi, u, dx, dt, s, steps)
+        l1[s] = float(np.mean(np.abs(out - exact)))
+        over[s] = float(max(out.max() - 1.0, -out.min()))
+    assert l1["cir"] > l1["fec"] > l1["bec"] > l1["cec"], l1
+    assert over["cir"] < 1e-12            # CIR is monotone
+    assert over["cec"] < over["bec"] < over["fec"], over
 
 
 def _variable_u_errors(scheme, Ns, T=1.0, cfl=0.8):
