@@ -202,20 +202,21 @@ def learned_section(ctx, size, fields, steps_per_field, cells, iters, batch, lr,
     return out
 
 
-def timed_steps(ctx, phi, u, dx, dt, steps, warmup):
-    """Third-order steps with the library's per-kernel timing; returns
-    (wall seconds, per-kind (launches, ms))."""
+def timed_steps(ctx, phi, u, dx, dt, steps, warmup, scheme=None):
+    """Third-order steps (or ``scheme``'s) with the library's per-kernel
+    timing; returns (wall seconds, per-kind (launches, ms))."""
     import torch
     from paper_1606_06117_amd import native
+    scheme = native.CEC if scheme is None else scheme
     cmax = ctx.courant_max(u, dx, dt)
     for w in range(warmup):
-        ctx.advect(phi, u, dx, dt, native.CEC, 1, step0=w, courant_max=cmax)
+        ctx.advect(phi, u, dx, dt, scheme, 1, step0=w, courant_max=cmax)
     ctx.check()
     torch.cuda.synchronize()
     ctx.timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ctx.advect(phi, u, dx, dt, native.CEC, steps, step0=warmup, courant_max=cmax)
+    ctx.advect(phi, u, dx, dt, scheme, steps, step0=warmup, courant_max=cmax)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     times = ctx.timing_read()
@@ -224,10 +225,11 @@ def timed_steps(ctx, phi, u, dx, dt, steps, warmup):
     return wall, times, cmax
 
 
-def cfl_section(ctx, size, cfls, steps):
-    """The headline workload (8 Gaussians, ABC velocity) at larger Courant
-    numbers: reach 2 and 3 take the three-sweep path (36 B per cell-update
-    moved; 20 B algorithmic)."""
+def cfl_section(ctx, size, cfls, steps, scheme=None, name="third order"):
+    """The headline workload (8 Gaussians, ABC velocity) at other Courant
+    numbers: reach 2 takes the fused x+y sweep and the z sweep (28 B per
+    cell-update moved), reach 3 three sweeps (36 B); 20 B algorithmic.  With
+    ``scheme`` = Strang splitting: x/2 y/2 in one kernel, z, y/2 x/2 (44 B)."""
     import numpy as np
     import torch
     from paper_1606_06117_amd import workloads as W
@@ -238,7 +240,7 @@ def cfl_section(ctx, size, cfls, steps):
     dx = (2 * math.pi / size,) * 3
     rows = []
     for cfl in cfls:
-        wall, times, cmax = timed_steps(ctx, phi, u, dx, W.abc_dt(shape, cfl), steps, 2)
+        wall, times, cmax = timed_steps(ctx, phi, u, dx, W.abc_dt(shape, cfl), steps, 2, scheme)
         upd = size**3 * steps
         rows.append({"cfl": cfl, "courant_max": cmax, "value": upd / wall / 1e9, "unit": "Gcell-updates/s",
                      "ms_per_step": wall * 1e3 / steps,
@@ -246,7 +248,7 @@ def cfl_section(ctx, size, cfls, steps):
                      "per_kind_ms": {k: round(v[1] / v[0], 4) for k, v in times.items()}})
     del phi, u
     torch.cuda.empty_cache()
-    return {"workload": f"third order, {size}^3, 8 Gaussians, ABC velocity, {steps} steps per CFL",
+    return {"workload": f"{name}, {size}^3, 8 Gaussians, ABC velocity, {steps} steps per CFL",
             "runs": rows}
 
 
@@ -475,6 +477,9 @@ def main(argv=None):
     if args.other_cfl == "on":
         print("[bench] CFL 1.5 and 2.0 ...", file=sys.stderr, flush=True)
         out["other_cfl"] = cfl_section(ctx, args.size, (1.5, 2.0), 10)
+        print("[bench] Strang splitting at CFL 0.9 and 1.5 ...", file=sys.stderr, flush=True)
+        out["strang"] = cfl_section(ctx, args.size, (0.9, 1.5), 10, native.CEC_STRANG,
+                                    "third order with Strang splitting")
     if args.large == "on":
         print("[bench] 1024^3 at CFL 2.0 ...", file=sys.stderr, flush=True)
         out["large"] = large_section(ctx, 1024, 2.0, 10)

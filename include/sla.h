@@ -47,7 +47,11 @@ typedef enum {
   SLA_CIR = 0, /* L_U only: first order */
   SLA_FEC = 1, /* eq. intro:FEC, unsplit multilinear: second order */
   SLA_BEC = 2, /* eq. intro:BEC, unsplit multilinear: second order */
-  SLA_CEC = 3  /* eqs. intro:CEC + intro:CECcoef(SL), split per axis: third order */
+  SLA_CEC = 3, /* eqs. intro:CEC + intro:CECcoef(SL), split per axis: third order */
+  /* the same sweeps under Strang's symmetric splitting (section 5): half a
+     step along x (and y in 3D), a whole step along the last axis, then the
+     half steps in reverse order; every step the same (no step0 dependence) */
+  SLA_CEC_STRANG = 4
 } sla_scheme;
 
 typedef enum {
@@ -102,7 +106,11 @@ int sla_courant_max(sla_ctx *ctx, const sla_grid *grid, const float *u,
  *
  * step0 is the global index of the first step; for SLA_CEC it fixes the sweep
  * order (x,y,z on even steps, z,y,x on odd steps), so a run split into
- * several calls matches one call when step0 is carried along.
+ * several calls matches one call when step0 is carried along.  SLA_CEC_STRANG
+ * runs x/2, y/2, z, y/2, x/2 (2D: x/2, y, x/2; 1D: x) every step, each a
+ * third-order sweep kernel (the x and y half steps in one kernel where the
+ * fused x+y sweep applies); the half steps use the Courant number u * fl32(dt
+ * / dx) / 2, exactly half the whole step's.
  *
  * courant_max: if > 0, a bound the caller guarantees on every |c_d|; the call
  * then does not read u to measure it.  If a kernel still meets a larger

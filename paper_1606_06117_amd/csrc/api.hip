@@ -330,7 +330,8 @@ int check_advect(sla_ctx* ctx, const sla_grid* grid, const float* phi, const flo
   if (rc) return rc;
   if (!phi || !u) return fail(ctx, SLA_EINVAL, "phi and u must not be NULL");
   if (!std::isfinite(dt)) return fail(ctx, SLA_EINVAL, "dt must be finite");
-  if (scheme < SLA_CIR || scheme > SLA_CEC) return fail(ctx, SLA_EINVAL, "unknown scheme %d", scheme);
+  if (scheme < SLA_CIR || scheme > SLA_CEC_STRANG)
+    return fail(ctx, SLA_EINVAL, "unknown scheme %d", scheme);
   if (steps < 0) return fail(ctx, SLA_EINVAL, "steps must be >= 0");
   if (std::isnan(courant_max)) return fail(ctx, SLA_EINVAL, "courant_max is NaN");
   return SLA_OK;
@@ -385,7 +386,7 @@ int sla_advect(sla_ctx* ctx, const sla_grid* grid, float* phi, const float* u, d
 }
 
 size_t sla_workspace_size(const sla_grid* grid, int32_t scheme, int32_t nscalars) {
-  if (!grid || grid->ndim < 1 || grid->ndim > 3 || scheme < SLA_CIR || scheme > SLA_CEC ||
+  if (!grid || grid->ndim < 1 || grid->ndim > 3 || scheme < SLA_CIR || scheme > SLA_CEC_STRANG ||
       nscalars < 0)
     return 0;
   size_t cells = 1;
@@ -578,7 +579,7 @@ int advect_steps(sla_ctx* ctx, const sla_grid* grid, float* phi, const float* u,
         });
         std::swap(cur, nxt);
         break;
-      case SLA_CEC:
+      case SLA_CEC: {
         if (fused3d) {
           e = run(ctx, SLA_K_CEC3D, [&] {
             return sla::launch_cec3d(ctx->cec3d_kernel, m % 2 == 0, geo, cur, u, nxt, ctx->flag,
@@ -620,6 +621,44 @@ int advect_steps(sla_ctx* ctx, const sla_grid* grid, float* phi, const float* u,
           std::swap(cur, nxt);
         }
         break;
+      }
+      case SLA_CEC_STRANG: {
+        // half steps: lambda = fl32(dt/2/dx) = fl32(dt/dx)/2 exactly, so
+        // every half-step Courant number is half the whole step's; their
+        // reach is floor(max|c|/2) + 1 <= (reach - 1)/2 + 1
+        const sla::Geo half = make_geo(grid, 0.5 * dt);
+        int rh[3];
+        for (int d = 0; d < 3; ++d) rh[d] = (reach[d] - 1) / 2 + 1;
+        auto sweep = [&](int d, bool whole) {
+          if (e != hipSuccess) return;
+          e = run(ctx, SLA_K_SWEEP_X + d, [&] {
+            return sla::launch_cec_sweep(d, whole ? reach[d] : rh[d], whole ? geo : half, cur,
+                                         u + size_t(d) * n, nxt, ctx->flag, ctx->stream,
+                                         ctx->sweep_kernel != 0);
+          });
+          std::swap(cur, nxt);
+        };
+        const int rxy = rh[0] > rh[1] ? rh[0] : rh[1];
+        if (ndim == 3 && ctx->sweep_kernel == 2 && rxy <= 2 && sla::offsets32_ok(geo)) {
+          // x/2 then y/2 in one kernel, z, then y/2 then x/2 in one kernel
+          for (int part = 0; part < 3 && e == hipSuccess; ++part) {
+            if (part == 1) {
+              sweep(2, true);
+              continue;
+            }
+            e = run(ctx, SLA_K_SWEEP_XY, [&] {
+              return sla::launch_cec_sweep_xy(rxy, part == 0, half, cur, u, nxt, ctx->flag,
+                                              ctx->stream);
+            });
+            std::swap(cur, nxt);
+          }
+          break;
+        }
+        for (int d = 0; d < ndim - 1; ++d) sweep(d, false);
+        sweep(ndim - 1, true);
+        for (int d = ndim - 2; d >= 0; --d) sweep(d, false);
+        break;
+      }
     }
   }
   if (e != hipSuccess) return hip_fail(ctx, e, "advection kernel launch");

@@ -14,8 +14,8 @@ import os
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libsla.so")
 
-CIR, FEC, BEC, CEC = 0, 1, 2, 3
-SCHEMES = {"cir": CIR, "fec": FEC, "bec": BEC, "cec": CEC}
+CIR, FEC, BEC, CEC, CEC_STRANG = 0, 1, 2, 3, 4
+SCHEMES = {"cir": CIR, "fec": FEC, "bec": BEC, "cec": CEC, "cec_strang": CEC_STRANG}
 MAX_REACH = 4
 
 OK, EINVAL, ECOURANT, EHIP, ENOMEM, ENOMODEL, ECAPTURE = 0, -1, -2, -3, -4, -5, -6

@@ -1,0 +1,123 @@
+"""GPU parity of the third-order scheme under Strang splitting (SLA_CEC_STRANG).
+
+The step is x/2, y/2, z, y/2, x/2 (2D: x/2, y, x/2; 1D: x), built from the
+same third-order sweep kernels as the default scheme, with the x and y half
+steps in one kernel where the fused x+y sweep applies.  Held to the oracle
+with the per-step bound of the other parity tests; the three sweep-kernel
+families must agree bitwise; whole-cell half steps must be exact shifts.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1606_06117_amd import workloads as W
+
+from helpers import box_parity, gpu_advect, oracle_advect, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+STRANG = oracle.CEC_STRANG
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_1606_06117_amd import native
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    c = native.Context(0)
+    yield c
+    c.close()
+
+
+def check(got, ref, phi0, steps, label):
+    l2 = rel_l2(got, ref)
+    linf = float(np.max(np.abs(got - ref))) / float(np.max(np.abs(phi0)))
+    print(f"{label}: relL2={l2:.2e} Linf={linf:.2e}")
+    assert l2 <= TOL * steps and linf <= TOL * steps, label
+
+
+@pytest.mark.parametrize("cfl", [0.9, 1.5, 2.0, 3.5])
+def test_abc_3d(ctx, cfl):
+    shape = (36, 40, 72)
+    phi = W.random_gaussians(shape, 8, seed=2000).astype(np.float32)
+    u = W.abc_velocity(shape)
+    dx = tuple(2 * np.pi / n for n in reversed(shape))
+    dt = cfl * dx[0] / 2.0
+    for steps in (1, 3):
+        got = gpu_advect(ctx, phi, u, dx, dt, STRANG, steps, step0=1)
+        ref = oracle_advect(phi, u, dx, dt, STRANG, steps, step0=1)
+        check(got, ref, phi, steps, f"strang abc cfl={cfl} steps={steps}")
+
+
+@pytest.mark.parametrize("cfl", [1.3, 3.2])
+def test_cellular_2d(ctx, cfl):
+    shape = (29, 37)
+    phi = np.random.default_rng(77).standard_normal(shape).astype(np.float32)
+    u = W.cellular_velocity_2d(shape)
+    dx = (2 * np.pi / 37, 2 * np.pi / 29)
+    dt = cfl * min(dx)   # max |u| = 1: the largest Courant number is cfl (on x)
+    got = gpu_advect(ctx, phi, u, dx, dt, STRANG, 4)
+    ref = oracle_advect(phi, u, dx, dt, STRANG, 4)
+    check(got, ref, phi, 4, f"strang cellular2d cfl={cfl}")
+
+
+def test_cosine_1d(ctx):
+    N = 30
+    phi = (-np.cos(2 * np.pi * np.arange(N) / N)).astype(np.float32)
+    u = np.ones((1, N), dtype=np.float32)
+    got = gpu_advect(ctx, phi, u, (1.0 / N,), 0.75 / N, STRANG, 40)
+    ref = oracle_advect(phi, u, (1.0 / N,), 0.75 / N, STRANG, 40)
+    check(got, ref, phi, 40, "strang 1d")
+    plain = gpu_advect(ctx, phi, u, (1.0 / N,), 0.75 / N, oracle.CEC, 40)
+    assert np.array_equal(got, plain)   # one axis: the plain sweep
+
+
+@pytest.mark.parametrize("shape,cfl", [((40, 96, 24), 0.9), ((12, 33, 70), 2.5), ((8, 9, 70), 3.5),
+                                       ((50, 66), 1.5)])
+def test_sweep_kernels_agree(ctx, shape, cfl):
+    """Tile sweeps (0), marching and window sweeps (1), fused x+y (2); the 2D
+    case under the cellular flow."""
+    from paper_1606_06117_amd import native
+    phi = W.random_gaussians(shape, 5, seed=41).astype(np.float32)
+    u = W.abc_velocity(shape) if len(shape) == 3 else W.cellular_velocity_2d(shape)
+    dx = tuple(2 * np.pi / n for n in reversed(shape))
+    dt = cfl * min(dx) / (2.0 if len(shape) == 3 else 1.0)
+    outs = []
+    for kern in (0, 1, 2):
+        ctx.set_option(native.OPT_SWEEP_KERNEL, kern)
+        try:
+            outs.append(gpu_advect(ctx, phi, u, dx, dt, STRANG, 2))
+        finally:
+            ctx.set_option(native.OPT_SWEEP_KERNEL, 2)
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[1], outs[2])
+    ref = oracle_advect(phi, u, dx, dt, STRANG, 2)
+    check(outs[2], ref, phi, 2, f"strang kernels {shape} cfl={cfl}")
+
+
+def test_whole_cell_half_steps_are_exact(ctx):
+    shape = (20, 24, 72)
+    phi = np.random.default_rng(9).standard_normal(shape).astype(np.float32)
+    u = W.uniform_velocity(shape, (2.0, -2.0, 3.0))   # half steps move 1 and -1 cells
+    got = gpu_advect(ctx, phi, u, (1.0, 1.0, 1.0), 1.0, STRANG, 3)
+    want = np.roll(np.roll(np.roll(phi.astype(np.float64), 6, axis=2), -6, axis=1), 9, axis=0)
+    assert np.array_equal(got, want)
+
+
+def test_abc_512_boxes(ctx):
+    """The benchmark's workload under Strang splitting: 512^3, CFL 0.9."""
+    import torch
+    shape = (512, 512, 512)
+    phi = W.random_gaussians(shape, 8, seed=2000).astype(np.float32)
+    u = W.abc_velocity(shape)
+    dx = tuple(2 * np.pi / n for n in reversed(shape))
+    dt = 0.9 * dx[0] / 2
+    steps = 2
+    got = gpu_advect(ctx, phi, u, dx, dt, STRANG, steps, courant_max=0.9)
+    # a step reads 6 cells along x and y (two half steps of three calls), 3 along z
+    l2, linf = box_parity(got, phi, u, dx, dt, STRANG, steps, steps * 6, (24, 24, 24),
+                          np.random.default_rng(3), 3)
+    print(f"512^3 strang boxes relL2={l2:.3e} Linf={linf:.3e}")
+    assert l2 <= TOL * steps and linf <= TOL * steps
+    torch.cuda.empty_cache()
