@@ -51,7 +51,12 @@ typedef enum {
   /* the same sweeps under Strang's symmetric splitting (section 5): half a
      step along x (and y in 3D), a whole step along the last axis, then the
      half steps in reverse order; every step the same (no step0 dependence) */
-  SLA_CEC_STRANG = 4
+  SLA_CEC_STRANG = 4,
+  /* FEC and BEC split per axis (eqs. split:1-2 applied to eqs. intro:FEC and
+     intro:BEC): one one-dimensional FEC or BEC sweep per axis, the order
+     alternating like SLA_CEC's */
+  SLA_FEC_SPLIT = 5,
+  SLA_BEC_SPLIT = 6
 } sla_scheme;
 
 typedef enum {
@@ -104,7 +109,8 @@ int sla_courant_max(sla_ctx *ctx, const sla_grid *grid, const float *u,
  * backwards).  The velocity is sampled at the arrival node and traced back
  * one explicit step (section 2: L_U[Phi](x) = Phi~(x - U dt)).
  *
- * step0 is the global index of the first step; for SLA_CEC it fixes the sweep
+ * step0 is the global index of the first step; for SLA_CEC (and the split
+ * FEC and BEC) it fixes the sweep
  * order (x,y,z on even steps, z,y,x on odd steps), so a run split into
  * several calls matches one call when step0 is carried along.  SLA_CEC_STRANG
  * runs x/2, y/2, z, y/2, x/2 (2D: x/2, y, x/2; 1D: x) every step, each a

@@ -28,8 +28,8 @@ measured convergence orders.
 """
 
 from .schemes import (  # noqa: F401
-    CIR, FEC, BEC, CEC, CEC_STRANG, SCHEMES,
-    courant, departure, interp, cir, fec, bec, cec_sweep, cec_split, cec_strang,
+    CIR, FEC, BEC, CEC, CEC_STRANG, FEC_SPLIT, BEC_SPLIT, SCHEMES,
+    courant, departure, interp, cir, fec, bec, cec_sweep, cec_split, cec_strang, ec_split,
     step, run, advect, sweep_order,
 )
 from .norms import reductions, rel_l2, linf, mass_error  # noqa: F401

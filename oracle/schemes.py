@@ -54,8 +54,9 @@ import itertools
 
 import numpy as np
 
-CIR, FEC, BEC, CEC, CEC_STRANG = 0, 1, 2, 3, 4
-SCHEMES = {"cir": CIR, "fec": FEC, "bec": BEC, "cec": CEC, "cec_strang": CEC_STRANG}
+CIR, FEC, BEC, CEC, CEC_STRANG, FEC_SPLIT, BEC_SPLIT = 0, 1, 2, 3, 4, 5, 6
+SCHEMES = {"cir": CIR, "fec": FEC, "bec": BEC, "cec": CEC, "cec_strang": CEC_STRANG,
+           "fec_split": FEC_SPLIT, "bec_split": BEC_SPLIT}
 
 
 # ---------------------------------------------------------------------------
@@ -244,9 +245,23 @@ def cec_strang(phi, c):
     return out
 
 
+def ec_split(phi, c, scheme, m=0):
+    """FEC or BEC split per axis (eqs. split:1-2 applied to eqs. intro:FEC
+    and intro:BEC): the scheme applied along one axis at a time, with the
+    Courant numbers of the other axes set to zero (L_U then moves nothing
+    along them), in the order of ``sweep_order``."""
+    out = np.asarray(phi, dtype=np.float64)
+    one = fec if scheme == FEC else bec
+    for d in sweep_order(m, out.ndim):
+        cd = np.zeros_like(c)
+        cd[d] = c[d]
+        out = one(out, cd)
+    return out
+
+
 def step(phi, c, scheme, m=0):
-    """One time step of ``scheme`` (CIR, FEC, BEC, CEC or CEC_STRANG) at
-    global step ``m``."""
+    """One time step of ``scheme`` (CIR, FEC, BEC, CEC, CEC_STRANG, FEC_SPLIT
+    or BEC_SPLIT) at global step ``m``."""
     if scheme == CIR:
         return cir(phi, c)
     if scheme == FEC:
@@ -257,6 +272,10 @@ def step(phi, c, scheme, m=0):
         return cec_split(phi, c, m)
     if scheme == CEC_STRANG:
         return cec_strang(phi, c)
+    if scheme == FEC_SPLIT:
+        return ec_split(phi, c, FEC, m)
+    if scheme == BEC_SPLIT:
+        return ec_split(phi, c, BEC, m)
     raise ValueError(f"unknown scheme {scheme!r}")
 
 

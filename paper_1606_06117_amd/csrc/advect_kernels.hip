@@ -305,8 +305,21 @@ __global__ __launch_bounds__(kThreads) void k_ec(const float* __restrict__ phi,
 // leave LDS.
 // ---------------------------------------------------------------------------
 
+// The last stage of a sweep, from Phi1 and e at the arrival node (ei) and at
+// the anchor and far nodes of the departure interval (ea, eb).  COMB selects
+// the scheme the sweep applies along its axis: the third order (lerp form of
+// A FEC + B BEC), FEC (eq. intro:FEC: Phi1 + e/2 at the arrival node) or BEC
+// (eq. intro:BEC: L_U[Phi + e/2] = Phi1 + 1/2 [e_a + f (e_b - e_a)]).
+constexpr int kCombCec = 0, kCombFec = 1, kCombBec = 2;
+template <int COMB>
+__device__ __forceinline__ float sweep_combine(float p1, float ei, float ea, float eb, float f) {
+  if (COMB == kCombFec) return fmaf(0.5f, ei, p1);
+  const float w = COMB == kCombBec ? f : fmaf(f, 1.f / 3.f, 1.f / 3.f);
+  return fmaf(0.5f, fmaf(w, eb - ea, ea), p1);
+}
+
 // Strided axis (y or z): tile = 64 consecutive x (coalesced) x TL along the axis.
-template <int R>
+template <int R, int COMB = kCombCec>
 __global__ __launch_bounds__(kThreads) void k_sweep_s(const float* __restrict__ phi,
                                                       const float* __restrict__ ud,
                                                       float* __restrict__ out, int nx, int L,
@@ -359,13 +372,13 @@ __global__ __launch_bounds__(kThreads) void k_sweep_s(const float* __restrict__ 
     if (l >= L) return;
     const Dep d = depart<R>(C[(r + 2 * R) * TW + tx], flag);
     const float ea = E[(r + R + d.oa) * TW + tx], eb = E[(r + R + d.ob) * TW + tx];
-    const float w = fmaf(d.f, 1.f / 3.f, 1.f / 3.f);
-    out[base + (size_t)l * S] = fmaf(0.5f, fmaf(w, eb - ea, ea), P1[(r + 2 * R) * TW + tx]);
+    out[base + (size_t)l * S] =
+        sweep_combine<COMB>(P1[(r + 2 * R) * TW + tx], E[(r + R) * TW + tx], ea, eb, d.f);
   });
 }
 
 // Contiguous axis (x): tile = TL consecutive x in each of ROWS rows.
-template <int R>
+template <int R, int COMB = kCombCec>
 __global__ __launch_bounds__(kThreads) void k_sweep_x(const float* __restrict__ phi,
                                                       const float* __restrict__ ud,
                                                       float* __restrict__ out, int nx, int ny,
@@ -425,9 +438,8 @@ __global__ __launch_bounds__(kThreads) void k_sweep_x(const float* __restrict__ 
     if (y >= ny || x >= nx) return;
     const Dep d = depart<R>(C[rr * NC + col + 2 * R], flag);
     const float* ee = E + rr * NE + col + R;
-    const float ea = ee[d.oa], eb = ee[d.ob];
-    const float w = fmaf(d.f, 1.f / 3.f, 1.f / 3.f);
-    out[zoff + (size_t)y * nx + x] = fmaf(0.5f, fmaf(w, eb - ea, ea), P1[rr * NC + col + 2 * R]);
+    out[zoff + (size_t)y * nx + x] =
+        sweep_combine<COMB>(P1[rr * NC + col + 2 * R], ee[0], ee[d.oa], ee[d.ob], d.f);
   });
 }
 
@@ -920,6 +932,45 @@ hipError_t launch_cec_sweep_xy(int R, bool xfirst, const Geo& g, const float* ph
     case 1: return launch_sweep_xy_t<1>(xfirst, g, phi, u, out, flag, st);
     case 2: return launch_sweep_xy_t<2>(xfirst, g, phi, u, out, flag, st);
   }
+  return hipErrorInvalidValue;
+}
+
+namespace {
+template <int R, int COMB>
+hipError_t launch_split_t(int d, const Geo& g, const float* phi, const float* ud, float* out,
+                          int* flag, hipStream_t st) {
+  if (d == 0) {
+    dim3 grid((g.nx + 255) / 256, (g.ny + 3) / 4, g.nz);
+    hipLaunchKernelGGL((k_sweep_x<R, COMB>), grid, dim3(kThreads), 0, st, phi, ud, out, g.nx, g.ny,
+                       g.lam[0], flag);
+  } else {
+    const int L = d == 1 ? g.ny : g.nz;
+    const int64_t S = d == 1 ? (int64_t)g.nx : (int64_t)g.nx * g.ny;
+    const int other = d == 1 ? g.nz : g.ny;
+    const int64_t So = d == 1 ? (int64_t)g.nx * g.ny : (int64_t)g.nx;
+    dim3 grid((g.nx + 63) / 64, (L + 31) / 32, other);
+    hipLaunchKernelGGL((k_sweep_s<R, COMB>), grid, dim3(kThreads), 0, st, phi, ud, out, g.nx, L, S,
+                       So, g.lam[d], flag);
+  }
+  return hipGetLastError();
+}
+template <int COMB>
+hipError_t launch_split_r(int d, int R, const Geo& g, const float* phi, const float* ud, float* out,
+                          int* flag, hipStream_t st) {
+  switch (R) {
+    case 1: return launch_split_t<1, COMB>(d, g, phi, ud, out, flag, st);
+    case 2: return launch_split_t<2, COMB>(d, g, phi, ud, out, flag, st);
+    case 3: return launch_split_t<3, COMB>(d, g, phi, ud, out, flag, st);
+    case 4: return launch_split_t<4, COMB>(d, g, phi, ud, out, flag, st);
+  }
+  return hipErrorInvalidValue;
+}
+}  // namespace
+
+hipError_t launch_ec_sweep(int scheme, int d, int R, const Geo& g, const float* phi,
+                           const float* ud, float* out, int* flag, hipStream_t st) {
+  if (scheme == FEC) return launch_split_r<kCombFec>(d, R, g, phi, ud, out, flag, st);
+  if (scheme == BEC) return launch_split_r<kCombBec>(d, R, g, phi, ud, out, flag, st);
   return hipErrorInvalidValue;
 }
 

@@ -330,7 +330,7 @@ int check_advect(sla_ctx* ctx, const sla_grid* grid, const float* phi, const flo
   if (rc) return rc;
   if (!phi || !u) return fail(ctx, SLA_EINVAL, "phi and u must not be NULL");
   if (!std::isfinite(dt)) return fail(ctx, SLA_EINVAL, "dt must be finite");
-  if (scheme < SLA_CIR || scheme > SLA_CEC_STRANG)
+  if (scheme < SLA_CIR || scheme > SLA_BEC_SPLIT)
     return fail(ctx, SLA_EINVAL, "unknown scheme %d", scheme);
   if (steps < 0) return fail(ctx, SLA_EINVAL, "steps must be >= 0");
   if (std::isnan(courant_max)) return fail(ctx, SLA_EINVAL, "courant_max is NaN");
@@ -386,7 +386,7 @@ int sla_advect(sla_ctx* ctx, const sla_grid* grid, float* phi, const float* u, d
 }
 
 size_t sla_workspace_size(const sla_grid* grid, int32_t scheme, int32_t nscalars) {
-  if (!grid || grid->ndim < 1 || grid->ndim > 3 || scheme < SLA_CIR || scheme > SLA_CEC_STRANG ||
+  if (!grid || grid->ndim < 1 || grid->ndim > 3 || scheme < SLA_CIR || scheme > SLA_BEC_SPLIT ||
       nscalars < 0)
     return 0;
   size_t cells = 1;
@@ -622,6 +622,18 @@ int advect_steps(sla_ctx* ctx, const sla_grid* grid, float* phi, const float* u,
         }
         break;
       }
+      case SLA_FEC_SPLIT:
+      case SLA_BEC_SPLIT:
+        // one 1D FEC or BEC sweep per axis, x,y,z on even steps, z,y,x on odd
+        for (int j = 0; j < ndim && e == hipSuccess; ++j) {
+          const int d = (m % 2 == 0) ? j : ndim - 1 - j;
+          e = run(ctx, SLA_K_SWEEP_X + d, [&] {
+            return sla::launch_ec_sweep(scheme == SLA_FEC_SPLIT ? sla::FEC : sla::BEC, d, reach[d],
+                                        geo, cur, u + size_t(d) * n, nxt, ctx->flag, ctx->stream);
+          });
+          std::swap(cur, nxt);
+        }
+        break;
       case SLA_CEC_STRANG: {
         // half steps: lambda = fl32(dt/2/dx) = fl32(dt/dx)/2 exactly, so
         // every half-step Courant number is half the whole step's; their

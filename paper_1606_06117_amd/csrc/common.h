@@ -45,6 +45,10 @@ hipError_t launch_ec(int ndim, int scheme, int R, const Geo& g, const float* phi
 // One third-order sweep along axis d with reach R; u_d is that axis' plane.
 // march: y and z sweeps of grids of at most 2^30 cells walk columns through
 // registers (k_sweep_m); otherwise LDS tiles (k_sweep_s).  Same results.
+// One FEC (scheme FEC) or BEC (scheme BEC) sweep along axis d: the
+// one-dimensional scheme applied along one axis (tile kernels, reach 1-4).
+hipError_t launch_ec_sweep(int scheme, int d, int R, const Geo& g, const float* phi,
+                           const float* ud, float* out, int* flag, hipStream_t st);
 hipError_t launch_cec_sweep(int d, int R, const Geo& g, const float* phi,
                             const float* u_d, float* out, int* flag, hipStream_t st,
                             bool march = true);
