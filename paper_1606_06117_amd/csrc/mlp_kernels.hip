@@ -104,6 +104,16 @@ __device__ void load_weights(WeightsLds& W, __bf16* w2r, const __bf16* __restric
   if (threadIdx.x == 0) W.b3 = wr[B3_OFF];
 }
 
+// Order a wave's LDS writes before its later LDS reads of what other lanes of
+// the same wave wrote (and reads before later rewrites).  The tiles in LDS
+// belong to one wave each, so no workgroup barrier is needed: the waves of a
+// workgroup run their tiles independently.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Forward pass of one 32-cell tile held by one wave.  xb[jt] is the B
 // operand of cells 16 jt + c (features 8g..8g+7).  Writes H1 (row-major
 // [cell][hidden], BF16) to h1, returns h2 (transposed tiles, FP32, after the
@@ -124,7 +134,7 @@ __device__ __forceinline__ void forward_tile(const WeightsLds& W, const bf16x8 x
           fmaxf(acc[2] + W.b1[k + 2], 0.f), fmaxf(acc[3] + W.b1[k + 3], 0.f));
     }
   }
-  __syncthreads();
+  wave_lds_sync();
   // layer 2: H2T[n][j] = sum_k W2T[n][k] H1[j][k], two K steps of 32
   float s[2] = {0.f, 0.f};
 #pragma unroll
@@ -145,6 +155,7 @@ __device__ __forceinline__ void forward_tile(const WeightsLds& W, const bf16x8 x
       h2[it][jt] = acc;
     }
   }
+  wave_lds_sync();  // h1 is rewritten by the wave's next tile
   // layer 3: y = h2 . w3 + b3, summed over the 4 lanes holding the cell
   y[0] = sum4g(s[0]) + W.b3;
   y[1] = sum4g(s[1]) + W.b3;
@@ -227,7 +238,6 @@ __global__ __launch_bounds__(kThreads) void k_mlp(const __bf16* __restrict__ X,
         const int row = r0 + 16 * jt + c;
         if (g == 0 && row < m) yout[row] = y[jt];
       }
-      __syncthreads();  // h1 is rewritten by the next tile
       continue;
     }
     // ---- backward
@@ -575,10 +585,9 @@ __global__ __launch_bounds__(kThreads) void k_make_pairs(const float* __restrict
 
 // Learned step, second half: out = Phi1 + sigma * net(features), limited to
 // the range of the 27 values around the node.  A wave tile is 32 nodes of
-// one x row (two MFMA tiles of 16).  Workgroup b takes the groups of four
-// consecutive tiles 4b, 4b + 4G, ... (G workgroups), one tile per wave, so
-// every workgroup loads the weights into LDS once and all its waves run the
-// same number of iterations (forward_tile synchronises the workgroup).
+// one x row (two MFMA tiles of 16).  Wave w of workgroup b takes the tiles
+// 4b + w, 4b + w + 4G, ... (G workgroups); every workgroup loads the weights
+// into LDS once, after which its waves run independently.
 struct InferLds {
   WeightsLds W;
   __bf16 h1[4][32 * SH];
@@ -611,9 +620,7 @@ __global__ __launch_bounds__(kThreads) void k_learned_correct(const float* __res
     const int k = min(8 * g + v, 26);
     noff[v] = 4 * ((k / 9 - 1) * int(plane) + ((k / 3) % 3 - 1) * geo.nx + (k % 3 - 1));
   }
-  for (int t0 = blockIdx.x * WPB; t0 < tiles; t0 += gridDim.x * WPB) {
-    const bool valid = t0 + w < tiles;
-    const int t = valid ? t0 + w : tiles - 1;  // idle waves repeat the last tile, unstored
+  for (int t = blockIdx.x * WPB + w; t < tiles; t += gridDim.x * WPB) {
     const int xb0 = (t % nxb) * 32;
     const int row = t / nxb;
     const int y = row % geo.ny, z = row / geo.ny;
@@ -647,7 +654,7 @@ __global__ __launch_bounds__(kThreads) void k_learned_correct(const float* __res
     floatx4 h2[4][2];
     float yv[2];
     forward_tile(L.W, xb, L.h1[w], h2, yv);
-    if (valid && g == 0) {
+    if (g == 0) {
 #pragma unroll
       for (int jt = 0; jt < 2; ++jt)
         if (xs[jt] < geo.nx)
