@@ -545,9 +545,9 @@ __device__ __forceinline__ NodeFeatures node_features(const float* __restrict__ 
 }
 
 // Buffer access with a 32-bit byte offset from a descriptor in scalar
-// registers, for the interior gather: fields of fewer than 2^30 cells (a
-// descriptor's size tops out one byte short of 2^32, so at 2^30 cells it
-// would clip the field's last element; such fields take the wrapping path).
+// registers, for the learned step's gather: fields of fewer than 2^30 cells
+// (a descriptor's size tops out one byte short of 2^32, so at 2^30 cells it
+// would clip the field's last element; such fields take node_features).
 typedef __amdgpu_buffer_rsrc_t Rsrc;
 __device__ __forceinline__ Rsrc field_rsrc(const float* base, size_t n) {
   const unsigned bytes = n >= (size_t(1) << 30) ? 0xFFFFFFFFu : unsigned(n) * 4u;
@@ -609,37 +609,60 @@ __global__ __launch_bounds__(kThreads) void k_learned_correct(const float* __res
   const int nxb = (geo.nx + 31) / 32;
   const int tiles = nxb * geo.ny * geo.nz;
   constexpr int WPB = kThreads / 64;
-  // interior rows: byte offsets of this lane's neighbours, computed once
+  // byte offsets of this lane's neighbours from the node, computed once, and
+  // which of them step across the low (m) or high (p) face of each axis
   const size_t ncells = (size_t)geo.nx * geo.ny * geo.nz;
   const unsigned plane = unsigned(geo.nx) * unsigned(geo.ny);
   const Rsrc rp = field_rsrc(phi1, ncells), rx = field_rsrc(ux, ncells);
   const Rsrc ry = field_rsrc(uy, ncells), rz = field_rsrc(uz, ncells);
   int noff[8];
+  unsigned xm = 0, xp = 0, ym = 0, yp = 0, zm = 0, zp = 0;
 #pragma unroll
   for (int v = 0; v < 8; ++v) {
     const int k = min(8 * g + v, 26);
-    noff[v] = 4 * ((k / 9 - 1) * int(plane) + ((k / 3) % 3 - 1) * geo.nx + (k % 3 - 1));
+    const int dz = k / 9 - 1, dy = (k / 3) % 3 - 1, dx = k % 3 - 1;
+    noff[v] = 4 * (dz * int(plane) + dy * geo.nx + dx);
+    xm |= unsigned(dx < 0) << v;
+    xp |= unsigned(dx > 0) << v;
+    ym |= unsigned(dy < 0) << v;
+    yp |= unsigned(dy > 0) << v;
+    zm |= unsigned(dz < 0) << v;
+    zp |= unsigned(dz > 0) << v;
   }
+  // a neighbour across a face is the node on the opposite face (periodic):
+  // one axis length further along that axis
+  const unsigned wx4 = 4u * unsigned(geo.nx), wy4 = 4u * plane, wz4 = 4u * unsigned(ncells);
   for (int t = blockIdx.x * WPB + w; t < tiles; t += gridDim.x * WPB) {
-    const int xb0 = (t % nxb) * 32;
-    const int row = t / nxb;
+    const int tu = __builtin_amdgcn_readfirstlane(t);  // the same for the whole wave
+    const int xb0 = (tu % nxb) * 32;
+    const int row = tu / nxb;
     const int y = row % geo.ny, z = row / geo.ny;
     bf16x8 xb[2];
     float sig[2], cen[2], lo[2], hi[2];
     int xs[2];
-    // all 27 neighbours of the tile's 32 nodes inside the grid: no wrap
-    const bool interior = fast && xb0 >= 1 && xb0 + 32 <= geo.nx - 1 && y >= 1 && y <= geo.ny - 2 &&
-                          z >= 1 && z <= geo.nz - 2;
+    // wrap corrections of the tile's row (the same for every node of the row)
+    const unsigned ysel = y == 0 ? ym : (y == geo.ny - 1 ? yp : 0u);
+    const unsigned ydel = y == 0 ? wy4 : 0u - wy4;
+    const unsigned zsel = z == 0 ? zm : (z == geo.nz - 1 ? zp : 0u);
+    const unsigned zdel = z == 0 ? wz4 : 0u - wz4;
 #pragma unroll
     for (int jt = 0; jt < 2; ++jt) {
       xs[jt] = xb0 + 16 * jt + c;
       const int x = min(xs[jt], geo.nx - 1);  // lanes past the end repeat the last node
       NodeFeatures f;
-      if (interior) {
+      if (fast) {
         const unsigned ic4 = 4u * (unsigned(z) * plane + unsigned(y) * unsigned(geo.nx) + unsigned(x));
+        const unsigned xsel = x == 0 ? xm : (x == geo.nx - 1 ? xp : 0u);
+        const unsigned xdel = x == 0 ? wx4 : 0u - wx4;
         float val[8];
 #pragma unroll
-        for (int v = 0; v < 8; ++v) val[v] = ld_at(rp, ic4 + unsigned(noff[v]));
+        for (int v = 0; v < 8; ++v) {
+          unsigned o = ic4 + unsigned(noff[v]);
+          o += (xsel >> v & 1u) ? xdel : 0u;
+          o += (ysel >> v & 1u) ? ydel : 0u;
+          o += (zsel >> v & 1u) ? zdel : 0u;
+          val[v] = ld_at(rp, o);
+        }
         f = features_from(val, ld_at(rp, ic4), g, ld_at(rx, ic4) * geo.lam[0],
                           ld_at(ry, ic4) * geo.lam[1], ld_at(rz, ic4) * geo.lam[2]);
       } else {
