@@ -178,7 +178,15 @@ def learned_section(ctx, size, fields, steps_per_field, cells, iters, batch, lr,
         if n < size:
             err, secs = Lr.error_at_resolution(ctx, n, size, 4100, 0.9, 2)
             coarse.append((err, secs, n))
-    lerr, lsecs = Lr.error_at_cfl(ctx, shape, 4100, 0.9, Lr.PERIOD, 2, learned_model=model)
+    # the learned model at its training Courant number, below it, and above
+    # the range it was trained on (there it must fall back to the plain scheme)
+    learned_pts = []
+    for spp in (200, Lr.PERIOD, 67):
+        fb = []
+        err, secs = Lr.error_at_cfl(ctx, shape, 4100, 0.9, spp, 2, learned_model=model, fallbacks=fb)
+        learned_pts.append({"cfl": round(0.9 * Lr.PERIOD / spp, 4), "relL2_vs_exact": err,
+                            "seconds": secs, "fell_back_steps": fb[0], "steps": 2 * spp})
+    lerr, lsecs = learned_pts[1]["relL2_vs_exact"], learned_pts[1]["seconds"]
     speed = Lr.equal_error_speedup([(e, t) for e, t, _ in plain + coarse], (lerr, lsecs))
     last = ev["per_step"][-1]
     out = {
@@ -195,7 +203,7 @@ def learned_section(ctx, size, fields, steps_per_field, cells, iters, batch, lr,
         "fell_back": ev["fell_back"],
         "plain_error_vs_cost": [{"cfl": c, "relL2_vs_exact": e, "seconds": t} for e, t, c in plain],
         "plain_error_vs_resolution": [{"n": n, "relL2_vs_exact": e, "seconds": t} for e, t, n in coarse],
-        "learned_error_vs_cost": {"cfl": 0.9, "relL2_vs_exact": lerr, "seconds": lsecs},
+        "learned_error_vs_cost": learned_pts,
         "speedup_at_equal_L2": speed,
     }
     model.close()

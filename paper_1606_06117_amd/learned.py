@@ -218,9 +218,12 @@ def evaluate(ctx, model, shape, seed, periods, cfl, period=PERIOD):
     }
 
 
-def error_at_cfl(ctx, shape, seed, cfl, steps_per_period, periods, learned_model=None):
+def error_at_cfl(ctx, shape, seed, cfl, steps_per_period, periods, learned_model=None,
+                 fallbacks=None):
     """Error vs the exact field after ``periods`` periods when a period takes
-    ``steps_per_period`` steps (so the Courant number is cfl*100/steps_per_period)."""
+    ``steps_per_period`` steps (so the Courant number is cfl*100/steps_per_period).
+    With a learned model, the number of steps that fell back to the plain
+    scheme is appended to ``fallbacks`` (a list) when one is given."""
     import torch
     N = shape[-1]
     dx = (2 * math.pi / N,) * 3
@@ -231,15 +234,18 @@ def error_at_cfl(ctx, shape, seed, cfl, steps_per_period, periods, learned_model
     phi = phi0.clone()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    fell = 0
     for m in range(periods * steps_per_period):
         a = modulation(m, steps_per_period)
         if learned_model is not None:
-            native.advect_learned(ctx, learned_model, phi, u, dx, a * dt, 1, step0=m,
-                                  courant_max=_hint(c, a))
+            fell += native.advect_learned(ctx, learned_model, phi, u, dx, a * dt, 1, step0=m,
+                                          courant_max=_hint(c, a))
         else:
             ctx.advect(phi, u, dx, a * dt, native.CEC, 1, step0=m, courant_max=_hint(c, a))
     torch.cuda.synchronize()
     secs = time.perf_counter() - t0
+    if fallbacks is not None:
+        fallbacks.append(fell)
     s = ctx.norms(phi, phi0)
     return math.sqrt(s[0] / s[1]), secs
 
