@@ -260,6 +260,32 @@ def cfl_section(ctx, size, cfls, steps, scheme=None, name="third order"):
             "runs": rows}
 
 
+def schemes_section(ctx, size, cfl, steps):
+    """Every scheme on one workload (8 Gaussians, ABC velocity): the unsplit
+    CIR, FEC and BEC steps, the third order, and the split options."""
+    import numpy as np
+    import torch
+    from paper_1606_06117_amd import native
+    from paper_1606_06117_amd import workloads as W
+    shape = (size,) * 3
+    dev = torch.device("cuda:0")
+    phi = torch.from_numpy(W.random_gaussians(shape, 8, seed=2000).astype(np.float32)).to(dev)
+    u = W.abc_velocity_torch(shape, dev)
+    dx = (2 * math.pi / size,) * 3
+    rows = []
+    for name in ("cir", "fec", "bec", "cec", "cec_strang", "fec_split", "bec_split"):
+        wall, times, _ = timed_steps(ctx, phi, u, dx, W.abc_dt(shape, cfl), steps, 2, native.SCHEMES[name])
+        upd = size**3 * steps
+        rows.append({"scheme": name, "value": upd / wall / 1e9, "unit": "Gcell-updates/s",
+                     "ms_per_step": wall * 1e3 / steps,
+                     "hbm_frac_step": 20 * upd / wall / (HBM_PEAK_GBS * 1e9),
+                     "per_kind_ms": {k: round(v[1] / v[0], 4) for k, v in times.items()}})
+    del phi, u
+    torch.cuda.empty_cache()
+    return {"workload": f"every scheme, {size}^3, 8 Gaussians, ABC velocity, CFL {cfl}, {steps} steps each",
+            "runs": rows}
+
+
 def large_section(ctx, size, cfl, steps):
     """One large problem: a k^-5/3 field (|k| <= 64) on size^3 with the ABC
     velocity at CFL ``cfl``, built on the GPU."""
@@ -488,6 +514,8 @@ def main(argv=None):
         print("[bench] Strang splitting at CFL 0.9 and 1.5 ...", file=sys.stderr, flush=True)
         out["strang"] = cfl_section(ctx, args.size, (0.9, 1.5), 10, native.CEC_STRANG,
                                     "third order with Strang splitting")
+        print("[bench] every scheme at 256^3, CFL 1.5 ...", file=sys.stderr, flush=True)
+        out["schemes_256"] = schemes_section(ctx, 256, 1.5, 10)
     if args.large == "on":
         print("[bench] 1024^3 at CFL 2.0 ...", file=sys.stderr, flush=True)
         out["large"] = large_section(ctx, 1024, 2.0, 10)
