@@ -386,14 +386,12 @@ int sla_advect(sla_ctx* ctx, const sla_grid* grid, float* phi, const float* u, d
 }
 
 size_t sla_workspace_size(const sla_grid* grid, int32_t scheme, int32_t nscalars) {
-  if (!grid || grid->ndim < 1 || grid->ndim > 3 || scheme < SLA_CIR || scheme > SLA_BEC_SPLIT ||
+  // the grid rules of sla_advect (check_grid records no message without a context)
+  if (check_grid(nullptr, grid) != SLA_OK || scheme < SLA_CIR || scheme > SLA_BEC_SPLIT ||
       nscalars < 0)
     return 0;
   size_t cells = 1;
-  for (int d = 0; d < 3; ++d) {
-    if (grid->n[d] < 1) return 0;
-    cells *= size_t(grid->n[d]);
-  }
+  for (int d = 0; d < 3; ++d) cells *= size_t(grid->n[d]);
   return cells * sizeof(float);  // one ping-pong field; scalars run one after another
 }
 
