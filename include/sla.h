@@ -191,7 +191,14 @@ typedef enum {
    * stencil in registers; 0 one kernel per axis with LDS tiles.  2 and 1
    * need grids of fewer than 2^30 cells, or of 2^30 cells with ny >= 2
    * (others run 0). */
-  SLA_OPT_SWEEP_KERNEL = 2
+  SLA_OPT_SWEEP_KERNEL = 2,
+  /* How unsplit FEC and BEC steps run (same FP32 operations, same results):
+   * 0 all calls of a step in one kernel, with the intermediate fields in
+   * LDS; 1 one gather kernel per call (FEC: 2, BEC: 3), the intermediates
+   * through the work field (44 and 64 B per cell moved); 2 (default) 1,
+   * except FEC with every Courant number below 1 on grids of more than 2^24
+   * cells, which runs 0 (the faster of the two where measured). */
+  SLA_OPT_EC_KERNEL = 3
 } sla_option;
 /* Set option `option` to `value`.  Returns SLA_EINVAL for an unknown option
  * or value. */

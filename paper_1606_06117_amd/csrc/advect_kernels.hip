@@ -120,6 +120,52 @@ __global__ __launch_bounds__(kThreads) void k_cir(const float* __restrict__ phi,
 }
 
 // ---------------------------------------------------------------------------
+// Unsplit FEC / BEC as a chain of gathers like k_cir, one interpolation call
+// per kernel (the same FP32 operations as the fused k_ec below, so the same
+// results).  MODE 1, FEC's last call: out = a + (b - L_{-U}[a])/2 with
+// a = Phi1 and b = Phi; MODE 2, BEC's middle call: out = b + (b - L_{-U}[a])/2
+// (psi).  out may be b: a thread reads b only at its own node, before it
+// writes there.  FEC = k_cir, MODE 1; BEC = k_cir, MODE 2, k_cir.
+// ---------------------------------------------------------------------------
+template <int NDIM, int MODE>
+__global__ __launch_bounds__(kThreads) void k_ec_gather(const float* __restrict__ a, const float* b,
+                                                        const float* __restrict__ ux,
+                                                        const float* __restrict__ uy,
+                                                        const float* __restrict__ uz, float* out,
+                                                        Geo g, int* flag) {
+  constexpr int R = SLA_MAX_REACH;
+  const int x = blockIdx.x * 64 + threadIdx.x;
+  const int y = blockIdx.y * 4 + threadIdx.y;
+  const int z = blockIdx.z;
+  if (x >= g.nx || y >= g.ny) return;
+  const int plane = g.nx * g.ny;
+  const int idx = x + g.nx * y + plane * z;
+  // the reverse call: departure with -c
+  const Dep dx = depart<R>(-(ux[idx] * g.lam[0]), flag);
+  const int xa = wrap1(x + dx.oa, g.nx), xb = wrap1(x + dx.ob, g.nx);
+  float bar;
+  if (NDIM == 1) {
+    bar = lerp(a[xa], a[xb], dx.f);
+  } else {
+    const Dep dy = depart<R>(-(uy[idx] * g.lam[1]), flag);
+    const int ya = wrap1(y + dy.oa, g.ny) * g.nx, yb = wrap1(y + dy.ob, g.ny) * g.nx;
+    if (NDIM == 2) {
+      bar = lerp(lerp(a[ya + xa], a[ya + xb], dx.f), lerp(a[yb + xa], a[yb + xb], dx.f), dy.f);
+    } else {
+      const Dep dz = depart<R>(-(uz[idx] * g.lam[2]), flag);
+      const int za = wrap1(z + dz.oa, g.nz) * plane, zb = wrap1(z + dz.ob, g.nz) * plane;
+      const float v00 = lerp(a[za + ya + xa], a[za + ya + xb], dx.f);
+      const float v10 = lerp(a[za + yb + xa], a[za + yb + xb], dx.f);
+      const float v01 = lerp(a[zb + ya + xa], a[zb + ya + xb], dx.f);
+      const float v11 = lerp(a[zb + yb + xa], a[zb + yb + xb], dx.f);
+      bar = lerp(lerp(v00, v10, dy.f), lerp(v01, v11, dy.f), dz.f);
+    }
+  }
+  const float v = b[idx];
+  out[idx] = fmaf(0.5f, v - bar, MODE == 1 ? a[idx] : v);
+}
+
+// ---------------------------------------------------------------------------
 // Unsplit FEC / BEC (eqs. intro:FEC, intro:BEC), all calls fused in one pass.
 //
 // A workgroup owns a TX x TY column of cells and marches along z over a chunk
@@ -883,6 +929,31 @@ hipError_t launch_cir(int ndim, const Geo& g, const float* phi, const float* u, 
     case 3: hipLaunchKernelGGL(k_cir<3>, grid, block, 0, st, phi, ux, uy, uz, out, g, flag); break;
     default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_ec_gather(int ndim, int mode, const Geo& g, const float* a, const float* b,
+                            const float* u, float* out, int* flag, hipStream_t st) {
+  const size_t n = (size_t)g.ncells;
+  const float* ux = u;
+  const float* uy = ndim >= 2 ? u + n : u;
+  const float* uz = ndim == 3 ? u + 2 * n : u;
+  dim3 block(64, 4);
+  dim3 grid((g.nx + 63) / 64, (g.ny + 3) / 4, g.nz);
+#define SLA_EC_GATHER(D, M)                                                                    \
+  hipLaunchKernelGGL((k_ec_gather<D, M>), grid, block, 0, st, a, b, ux, uy, uz, out, g, flag)
+  if (mode == 1) {
+    if (ndim == 1) SLA_EC_GATHER(1, 1);
+    else if (ndim == 2) SLA_EC_GATHER(2, 1);
+    else SLA_EC_GATHER(3, 1);
+  } else if (mode == 2) {
+    if (ndim == 1) SLA_EC_GATHER(1, 2);
+    else if (ndim == 2) SLA_EC_GATHER(2, 2);
+    else SLA_EC_GATHER(3, 2);
+  } else {
+    return hipErrorInvalidValue;
+  }
+#undef SLA_EC_GATHER
   return hipGetLastError();
 }
 

@@ -26,6 +26,7 @@ struct sla_ctx {
   bool fused = true;    // SLA_OPT_FUSED
   int cec3d_kernel = 5;  // SLA_OPT_CEC3D_KERNEL
   int sweep_kernel = 2;  // SLA_OPT_SWEEP_KERNEL
+  int ec_kernel = 2;     // SLA_OPT_EC_KERNEL
   // per-kernel timing
   bool timing = false;
   struct Mark { int kind; hipEvent_t a, b; };
@@ -571,12 +572,39 @@ int advect_steps(sla_ctx* ctx, const sla_grid* grid, float* phi, const float* u,
         std::swap(cur, nxt);
         break;
       case SLA_FEC:
-      case SLA_BEC:
-        e = run(ctx, scheme == SLA_FEC ? SLA_K_FEC : SLA_K_BEC, [&] {
-          return sla::launch_ec(ndim, scheme, rmax, geo, cur, u, nxt, ctx->flag, ctx->stream);
+      case SLA_BEC: {
+        const int kind = scheme == SLA_FEC ? SLA_K_FEC : SLA_K_BEC;
+        // default: the gather chain, except FEC at reach 1 on grids above
+        // 2^24 cells, where the fused kernel is faster (1.53 against 1.75 ms
+        // at 512^3; the chain wins everywhere else that was measured)
+        const bool fused_ec = ctx->ec_kernel == 0 ||
+                              (ctx->ec_kernel == 2 && scheme == SLA_FEC && rmax == 1 &&
+                               geo.ncells > (int64_t(1) << 24));
+        if (fused_ec) {
+          e = run(ctx, kind, [&] {
+            return sla::launch_ec(ndim, scheme, rmax, geo, cur, u, nxt, ctx->flag, ctx->stream);
+          });
+          std::swap(cur, nxt);
+          break;
+        }
+        // one gather kernel per call: Phi1 = L_U Phi into the work field, then
+        // FEC's result (or BEC's psi) in place of Phi, then BEC's L_U psi
+        e = run(ctx, kind, [&] {
+          return sla::launch_cir(ndim, geo, cur, u, nxt, ctx->flag, ctx->stream);
         });
-        std::swap(cur, nxt);
+        if (e == hipSuccess)
+          e = run(ctx, kind, [&] {
+            return sla::launch_ec_gather(ndim, scheme == SLA_FEC ? 1 : 2, geo, nxt, cur, u, cur,
+                                         ctx->flag, ctx->stream);
+          });
+        if (scheme == SLA_BEC && e == hipSuccess) {
+          e = run(ctx, kind, [&] {
+            return sla::launch_cir(ndim, geo, cur, u, nxt, ctx->flag, ctx->stream);
+          });
+          std::swap(cur, nxt);
+        }
         break;
+      }
       case SLA_CEC: {
         if (fused3d) {
           e = run(ctx, SLA_K_CEC3D, [&] {
@@ -701,6 +729,10 @@ int sla_set_option(sla_ctx* ctx, int option, int64_t value) {
     case SLA_OPT_SWEEP_KERNEL:
       if (value < 0 || value > 2) return fail(ctx, SLA_EINVAL, "SLA_OPT_SWEEP_KERNEL takes 0, 1 or 2");
       ctx->sweep_kernel = int(value);
+      return SLA_OK;
+    case SLA_OPT_EC_KERNEL:
+      if (value < 0 || value > 2) return fail(ctx, SLA_EINVAL, "SLA_OPT_EC_KERNEL takes 0, 1 or 2");
+      ctx->ec_kernel = int(value);
       return SLA_OK;
   }
   return fail(ctx, SLA_EINVAL, "unknown option %d", option);

@@ -45,6 +45,11 @@ hipError_t launch_ec(int ndim, int scheme, int R, const Geo& g, const float* phi
 // One third-order sweep along axis d with reach R; u_d is that axis' plane.
 // march: y and z sweeps of grids of at most 2^30 cells walk columns through
 // registers (k_sweep_m); otherwise LDS tiles (k_sweep_s).  Same results.
+// One gather call of the chained unsplit FEC / BEC: mode 1 writes
+// a + (b - L_{-U}[a])/2 (FEC's result, a = Phi1, b = Phi), mode 2
+// b + (b - L_{-U}[a])/2 (BEC's psi).  out may equal b.
+hipError_t launch_ec_gather(int ndim, int mode, const Geo& g, const float* a, const float* b,
+                            const float* u, float* out, int* flag, hipStream_t st);
 // One FEC (scheme FEC) or BEC (scheme BEC) sweep along axis d: the
 // one-dimensional scheme applied along one axis (tile kernels, reach 1-4).
 hipError_t launch_ec_sweep(int scheme, int d, int R, const Geo& g, const float* phi,

@@ -24,6 +24,7 @@ OPT_FUSED = 0
 OPT_CEC3D_KERNEL = 1
 CEC3D_DEFAULT = 5  # the library's default fused-step implementation
 OPT_SWEEP_KERNEL = 2
+OPT_EC_KERNEL = 3
 
 # every symbol include/sla.h declares, with (restype, argtypes)
 _c = ctypes
