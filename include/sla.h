@@ -195,9 +195,8 @@ typedef enum {
   /* How unsplit FEC and BEC steps run (same FP32 operations, same results):
    * 0 all calls of a step in one kernel, with the intermediate fields in
    * LDS; 1 one gather kernel per call (FEC: 2, BEC: 3), the intermediates
-   * through the work field (44 and 64 B per cell moved); 2 (default) 1,
-   * except FEC with every Courant number below 1 on grids of more than 2^24
-   * cells, which runs 0 (the faster of the two where measured). */
+   * through the work field (44 and 64 B per cell moved); 2 (default) as 1,
+   * the faster of the two at every size and Courant number measured. */
   SLA_OPT_EC_KERNEL = 3
 } sla_option;
 /* Set option `option` to `value`.  Returns SLA_EINVAL for an unknown option

@@ -78,91 +78,96 @@ __device__ __forceinline__ void for_strided(int start, F&& f) {
 }
 
 // ---------------------------------------------------------------------------
-// CIR: one multilinear interpolation per node (section 3 first equation;
-// eq. CIR2D; the same tensor product in 3D).  Gathers straight from global
-// memory: the 2^d nodes of a departure cell are near neighbours, served by
-// L1/L2.  Interpolation order x, then y, then z.
+// One interpolation call per node, gathered from global memory (served by
+// L1/L2), CPT nodes per thread: the CPT rows y0 + 4j + threadIdx.y of a
+// 64-wide x window, so a thread issues all its velocity loads, then all its
+// gathers, before it needs the first of them.  MODE 0, CIR: out = L_U[a]
+// (section 3 first equation; eq. CIR2D; the same tensor product in 3D).
+// The chained unsplit FEC / BEC use the reverse call: MODE 1, FEC's last
+// call: out = a + (b - L_{-U}[a])/2 with a = Phi1 and b = Phi; MODE 2, BEC's
+// middle call: out = b + (b - L_{-U}[a])/2 (psi).  out may be b: a thread
+// reads b only at its own nodes, before it writes there.  Interpolation
+// order x, then y, then z, as in every kernel here: FEC = MODE 0, MODE 1;
+// BEC = MODE 0, MODE 2, MODE 0 give the fused k_ec's results bit for bit.
 // ---------------------------------------------------------------------------
-template <int NDIM>
-__global__ __launch_bounds__(kThreads) void k_cir(const float* __restrict__ phi,
-                                                  const float* __restrict__ ux,
-                                                  const float* __restrict__ uy,
-                                                  const float* __restrict__ uz,
-                                                  float* __restrict__ out, Geo g, int* flag) {
+template <int NDIM, int MODE, int CPT>
+__global__ __launch_bounds__(kThreads) void k_gather(const float* __restrict__ a, const float* b,
+                                                     const float* __restrict__ ux,
+                                                     const float* __restrict__ uy,
+                                                     const float* __restrict__ uz, float* out,
+                                                     Geo g, int* flag) {
   constexpr int R = SLA_MAX_REACH;
   const int x = blockIdx.x * 64 + threadIdx.x;
-  const int y = blockIdx.y * 4 + threadIdx.y;
   const int z = blockIdx.z;
-  if (x >= g.nx || y >= g.ny) return;
+  if (x >= g.nx) return;
   const int plane = g.nx * g.ny;
-  const int idx = x + g.nx * y + plane * z;
-  const Dep dx = depart<R>(ux[idx] * g.lam[0], flag);
-  const int xa = wrap1(x + dx.oa, g.nx), xb = wrap1(x + dx.ob, g.nx);
-  if (NDIM == 1) {
-    out[idx] = lerp(phi[xa], phi[xb], dx.f);
-    return;
+  const float sgn = MODE == 0 ? 1.f : -1.f;  // MODE 1, 2: the reverse call
+  int idx[CPT];
+  Dep dx[CPT], dy[CPT], dz[CPT];
+  bool ok[CPT];
+#pragma unroll
+  for (int j = 0; j < CPT; ++j) {
+    const int y = blockIdx.y * (4 * CPT) + 4 * j + threadIdx.y;
+    ok[j] = y < g.ny;
+    idx[j] = x + g.nx * min(y, g.ny - 1) + plane * z;
   }
-  const Dep dy = depart<R>(uy[idx] * g.lam[1], flag);
-  const int ya = wrap1(y + dy.oa, g.ny) * g.nx, yb = wrap1(y + dy.ob, g.ny) * g.nx;
-  if (NDIM == 2) {
-    const float v0 = lerp(phi[ya + xa], phi[ya + xb], dx.f);
-    const float v1 = lerp(phi[yb + xa], phi[yb + xb], dx.f);
-    out[idx] = lerp(v0, v1, dy.f);
-    return;
+  float cx[CPT], cy[CPT], cz[CPT];
+#pragma unroll
+  for (int j = 0; j < CPT; ++j) {
+    cx[j] = ux[idx[j]];
+    if (NDIM >= 2) cy[j] = uy[idx[j]];
+    if (NDIM == 3) cz[j] = uz[idx[j]];
   }
-  const Dep dz = depart<R>(uz[idx] * g.lam[2], flag);
-  const int za = wrap1(z + dz.oa, g.nz) * plane, zb = wrap1(z + dz.ob, g.nz) * plane;
-  const float v00 = lerp(phi[za + ya + xa], phi[za + ya + xb], dx.f);
-  const float v10 = lerp(phi[za + yb + xa], phi[za + yb + xb], dx.f);
-  const float v01 = lerp(phi[zb + ya + xa], phi[zb + ya + xb], dx.f);
-  const float v11 = lerp(phi[zb + yb + xa], phi[zb + yb + xb], dx.f);
-  out[idx] = lerp(lerp(v00, v10, dy.f), lerp(v01, v11, dy.f), dz.f);
-}
-
-// ---------------------------------------------------------------------------
-// Unsplit FEC / BEC as a chain of gathers like k_cir, one interpolation call
-// per kernel (the same FP32 operations as the fused k_ec below, so the same
-// results).  MODE 1, FEC's last call: out = a + (b - L_{-U}[a])/2 with
-// a = Phi1 and b = Phi; MODE 2, BEC's middle call: out = b + (b - L_{-U}[a])/2
-// (psi).  out may be b: a thread reads b only at its own node, before it
-// writes there.  FEC = k_cir, MODE 1; BEC = k_cir, MODE 2, k_cir.
-// ---------------------------------------------------------------------------
-template <int NDIM, int MODE>
-__global__ __launch_bounds__(kThreads) void k_ec_gather(const float* __restrict__ a, const float* b,
-                                                        const float* __restrict__ ux,
-                                                        const float* __restrict__ uy,
-                                                        const float* __restrict__ uz, float* out,
-                                                        Geo g, int* flag) {
-  constexpr int R = SLA_MAX_REACH;
-  const int x = blockIdx.x * 64 + threadIdx.x;
-  const int y = blockIdx.y * 4 + threadIdx.y;
-  const int z = blockIdx.z;
-  if (x >= g.nx || y >= g.ny) return;
-  const int plane = g.nx * g.ny;
-  const int idx = x + g.nx * y + plane * z;
-  // the reverse call: departure with -c
-  const Dep dx = depart<R>(-(ux[idx] * g.lam[0]), flag);
-  const int xa = wrap1(x + dx.oa, g.nx), xb = wrap1(x + dx.ob, g.nx);
-  float bar;
-  if (NDIM == 1) {
-    bar = lerp(a[xa], a[xb], dx.f);
-  } else {
-    const Dep dy = depart<R>(-(uy[idx] * g.lam[1]), flag);
-    const int ya = wrap1(y + dy.oa, g.ny) * g.nx, yb = wrap1(y + dy.ob, g.ny) * g.nx;
-    if (NDIM == 2) {
-      bar = lerp(lerp(a[ya + xa], a[ya + xb], dx.f), lerp(a[yb + xa], a[yb + xb], dx.f), dy.f);
-    } else {
-      const Dep dz = depart<R>(-(uz[idx] * g.lam[2]), flag);
-      const int za = wrap1(z + dz.oa, g.nz) * plane, zb = wrap1(z + dz.ob, g.nz) * plane;
-      const float v00 = lerp(a[za + ya + xa], a[za + ya + xb], dx.f);
-      const float v10 = lerp(a[za + yb + xa], a[za + yb + xb], dx.f);
-      const float v01 = lerp(a[zb + ya + xa], a[zb + ya + xb], dx.f);
-      const float v11 = lerp(a[zb + yb + xa], a[zb + yb + xb], dx.f);
-      bar = lerp(lerp(v00, v10, dy.f), lerp(v01, v11, dy.f), dz.f);
+  float v[CPT][8];
+#pragma unroll
+  for (int j = 0; j < CPT; ++j) {
+    const int y = min(blockIdx.y * (4 * CPT) + 4 * j + threadIdx.y, g.ny - 1);
+    dx[j] = depart<R>(sgn * (cx[j] * g.lam[0]), flag);
+    const int xa = wrap1(x + dx[j].oa, g.nx), xb = wrap1(x + dx[j].ob, g.nx);
+    if (NDIM == 1) {
+      v[j][0] = a[xa];
+      v[j][1] = a[xb];
+      continue;
+    }
+    dy[j] = depart<R>(sgn * (cy[j] * g.lam[1]), flag);
+    const int ya = wrap1(y + dy[j].oa, g.ny) * g.nx, yb = wrap1(y + dy[j].ob, g.ny) * g.nx;
+    int za = z * plane, zb = za;
+    if (NDIM == 3) {
+      dz[j] = depart<R>(sgn * (cz[j] * g.lam[2]), flag);
+      za = wrap1(z + dz[j].oa, g.nz) * plane;
+      zb = wrap1(z + dz[j].ob, g.nz) * plane;
+    }
+    v[j][0] = a[za + ya + xa];
+    v[j][1] = a[za + ya + xb];
+    v[j][2] = a[za + yb + xa];
+    v[j][3] = a[za + yb + xb];
+    if (NDIM == 3) {
+      v[j][4] = a[zb + ya + xa];
+      v[j][5] = a[zb + ya + xb];
+      v[j][6] = a[zb + yb + xa];
+      v[j][7] = a[zb + yb + xb];
     }
   }
-  const float v = b[idx];
-  out[idx] = fmaf(0.5f, v - bar, MODE == 1 ? a[idx] : v);
+#pragma unroll
+  for (int j = 0; j < CPT; ++j) {
+    float r;
+    if (NDIM == 1) {
+      r = lerp(v[j][0], v[j][1], dx[j].f);
+    } else if (NDIM == 2) {
+      r = lerp(lerp(v[j][0], v[j][1], dx[j].f), lerp(v[j][2], v[j][3], dx[j].f), dy[j].f);
+    } else {
+      const float v00 = lerp(v[j][0], v[j][1], dx[j].f);
+      const float v10 = lerp(v[j][2], v[j][3], dx[j].f);
+      const float v01 = lerp(v[j][4], v[j][5], dx[j].f);
+      const float v11 = lerp(v[j][6], v[j][7], dx[j].f);
+      r = lerp(lerp(v00, v10, dy[j].f), lerp(v01, v11, dy[j].f), dz[j].f);
+    }
+    if (MODE != 0) {
+      const float bv = b[idx[j]];
+      r = fmaf(0.5f, bv - r, MODE == 1 ? a[idx[j]] : bv);
+    }
+    if (ok[j]) out[idx[j]] = r;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -915,46 +920,44 @@ hipError_t launch_sweep_t(int d, const Geo& g, const float* phi, const float* ud
 
 }  // namespace
 
-hipError_t launch_cir(int ndim, const Geo& g, const float* phi, const float* u, float* out,
-                      int* flag, hipStream_t st) {
+namespace {
+constexpr int kGatherCpt = 4;  // nodes per thread of the gather kernels
+template <int MODE>
+hipError_t launch_gather_m(int ndim, const Geo& g, const float* a, const float* b, const float* u,
+                           float* out, int* flag, hipStream_t st) {
   const size_t n = (size_t)g.ncells;
   const float* ux = u;
   const float* uy = ndim >= 2 ? u + n : u;
   const float* uz = ndim == 3 ? u + 2 * n : u;
   dim3 block(64, 4);
-  dim3 grid((g.nx + 63) / 64, (g.ny + 3) / 4, g.nz);
+  dim3 grid((g.nx + 63) / 64, (g.ny + 4 * kGatherCpt - 1) / (4 * kGatherCpt), g.nz);
   switch (ndim) {
-    case 1: hipLaunchKernelGGL(k_cir<1>, grid, block, 0, st, phi, ux, uy, uz, out, g, flag); break;
-    case 2: hipLaunchKernelGGL(k_cir<2>, grid, block, 0, st, phi, ux, uy, uz, out, g, flag); break;
-    case 3: hipLaunchKernelGGL(k_cir<3>, grid, block, 0, st, phi, ux, uy, uz, out, g, flag); break;
-    default: return hipErrorInvalidValue;
+    case 1:
+      hipLaunchKernelGGL((k_gather<1, MODE, kGatherCpt>), grid, block, 0, st, a, b, ux, uy, uz, out, g, flag);
+      break;
+    case 2:
+      hipLaunchKernelGGL((k_gather<2, MODE, kGatherCpt>), grid, block, 0, st, a, b, ux, uy, uz, out, g, flag);
+      break;
+    case 3:
+      hipLaunchKernelGGL((k_gather<3, MODE, kGatherCpt>), grid, block, 0, st, a, b, ux, uy, uz, out, g, flag);
+      break;
+    default:
+      return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_cir(int ndim, const Geo& g, const float* phi, const float* u, float* out,
+                      int* flag, hipStream_t st) {
+  return launch_gather_m<0>(ndim, g, phi, phi, u, out, flag, st);
 }
 
 hipError_t launch_ec_gather(int ndim, int mode, const Geo& g, const float* a, const float* b,
                             const float* u, float* out, int* flag, hipStream_t st) {
-  const size_t n = (size_t)g.ncells;
-  const float* ux = u;
-  const float* uy = ndim >= 2 ? u + n : u;
-  const float* uz = ndim == 3 ? u + 2 * n : u;
-  dim3 block(64, 4);
-  dim3 grid((g.nx + 63) / 64, (g.ny + 3) / 4, g.nz);
-#define SLA_EC_GATHER(D, M)                                                                    \
-  hipLaunchKernelGGL((k_ec_gather<D, M>), grid, block, 0, st, a, b, ux, uy, uz, out, g, flag)
-  if (mode == 1) {
-    if (ndim == 1) SLA_EC_GATHER(1, 1);
-    else if (ndim == 2) SLA_EC_GATHER(2, 1);
-    else SLA_EC_GATHER(3, 1);
-  } else if (mode == 2) {
-    if (ndim == 1) SLA_EC_GATHER(1, 2);
-    else if (ndim == 2) SLA_EC_GATHER(2, 2);
-    else SLA_EC_GATHER(3, 2);
-  } else {
-    return hipErrorInvalidValue;
-  }
-#undef SLA_EC_GATHER
-  return hipGetLastError();
+  if (mode == 1) return launch_gather_m<1>(ndim, g, a, b, u, out, flag, st);
+  if (mode == 2) return launch_gather_m<2>(ndim, g, a, b, u, out, flag, st);
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_ec(int ndim, int scheme, int R, const Geo& g, const float* phi, const float* u,

@@ -574,13 +574,10 @@ int advect_steps(sla_ctx* ctx, const sla_grid* grid, float* phi, const float* u,
       case SLA_FEC:
       case SLA_BEC: {
         const int kind = scheme == SLA_FEC ? SLA_K_FEC : SLA_K_BEC;
-        // default: the gather chain, except FEC at reach 1 on grids above
-        // 2^24 cells, where the fused kernel is faster (1.53 against 1.75 ms
-        // at 512^3; the chain wins everywhere else that was measured)
-        const bool fused_ec = ctx->ec_kernel == 0 ||
-                              (ctx->ec_kernel == 2 && scheme == SLA_FEC && rmax == 1 &&
-                               geo.ncells > (int64_t(1) << 24));
-        if (fused_ec) {
+        // default (2): the gather chain, faster than the fused kernel at
+        // every grid and Courant number measured (256^3 and 512^3, CFL 0.9
+        // to 2.5)
+        if (ctx->ec_kernel == 0) {
           e = run(ctx, kind, [&] {
             return sla::launch_ec(ndim, scheme, rmax, geo, cur, u, nxt, ctx->flag, ctx->stream);
           });
