@@ -208,7 +208,7 @@ int sla_set_option(sla_ctx *ctx, int option, int64_t value);
  * error.  Clears the record. */
 int sla_check(sla_ctx *ctx);
 
-/* FP64 reductions of two FP32 arrays of `count` elements (section 4 judges
+/* FP64 reductions of two FP32 arrays of `count` elements (section 4 rates
  * schemes by the norm of their difference to a reference).  Writes to the
  * host array out[5]:
  *   out[0] = sum (a-b)^2, out[1] = sum b^2, out[2] = max |a-b|,

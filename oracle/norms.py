@@ -1,6 +1,6 @@
 """FP64 error and mass reductions (test infrastructure only).
 
-The paper judges a scheme by the norm of its difference to a reference
+The paper rates a scheme by the norm of its difference to a reference
 profile (section 4, cosine test); the library reports the relative L2
 error, the maximum error and the mass drift.  These are their plain
 definitions.
