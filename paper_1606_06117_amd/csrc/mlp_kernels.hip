@@ -17,6 +17,7 @@
 // units of one cell and land in a row-major LDS tile as one 8-byte store.
 
 #include <algorithm>
+#include <cstddef>
 
 #include "common.h"
 
@@ -87,6 +88,9 @@ struct WeightsLds {
   __bf16 w2t[NH * SH];
   float b1[NH], b2[NH], w3[NH], b3;
 };
+// the biases are read four at a time as MFMA accumulator seeds
+static_assert(offsetof(WeightsLds, b1) % 16 == 0 && offsetof(WeightsLds, b2) % 16 == 0,
+              "bias rows must be 16-byte aligned");
 
 __device__ void load_weights(WeightsLds& W, __bf16* w2r, const __bf16* __restrict__ wpack,
                              const float* __restrict__ wr) {
@@ -125,13 +129,14 @@ __device__ __forceinline__ void forward_tile(const WeightsLds& W, const bf16x8 x
 #pragma unroll
   for (int it = 0; it < 4; ++it) {
     const bf16x8 a = ld8(&W.w1t[(16 * it + c) * SF + 8 * g]);
+    const int k = 16 * it + 4 * g;
+    const floatx4 bias = *reinterpret_cast<const floatx4*>(&W.b1[k]);
 #pragma unroll
     for (int jt = 0; jt < 2; ++jt) {
-      floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-      acc = mfma(a, xb[jt], acc);
-      const int k = 16 * it + 4 * g;
-      st4(&h1[(16 * jt + c) * SH + k], fmaxf(acc[0] + W.b1[k], 0.f), fmaxf(acc[1] + W.b1[k + 1], 0.f),
-          fmaxf(acc[2] + W.b1[k + 2], 0.f), fmaxf(acc[3] + W.b1[k + 3], 0.f));
+      // the bias starts the accumulation (one vector add fewer per output)
+      const floatx4 acc = mfma(a, xb[jt], bias);
+      st4(&h1[(16 * jt + c) * SH + k], fmaxf(acc[0], 0.f), fmaxf(acc[1], 0.f), fmaxf(acc[2], 0.f),
+          fmaxf(acc[3], 0.f));
     }
   }
   wave_lds_sync();
@@ -141,15 +146,15 @@ __device__ __forceinline__ void forward_tile(const WeightsLds& W, const bf16x8 x
   for (int it = 0; it < 4; ++it) {
 #pragma unroll
     for (int jt = 0; jt < 2; ++jt) {
-      floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+      const int n = 16 * it + 4 * g;
+      floatx4 acc = *reinterpret_cast<const floatx4*>(&W.b2[n]);
 #pragma unroll
       for (int kk = 0; kk < 2; ++kk)
         acc = mfma(ld8(&W.w2t[(16 * it + c) * SH + 32 * kk + 8 * g]),
                    ld8(&h1[(16 * jt + c) * SH + 32 * kk + 8 * g]), acc);
-      const int n = 16 * it + 4 * g;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        acc[q] = fmaxf(acc[q] + W.b2[n + q], 0.f);
+        acc[q] = fmaxf(acc[q], 0.f);
         s[jt] = fmaf(acc[q], W.w3[n + q], s[jt]);
       }
       h2[it][jt] = acc;
