@@ -26,6 +26,7 @@ import os
 import resource
 import sys
 import time
+import traceback
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 METRIC = "Gcell-updates/s + %HBM peak, 3rd-order 512³ FP32; learned vs plain at equal L2"
@@ -508,35 +509,45 @@ def main(argv=None):
 
     del phi_d, u_d
     torch.cuda.empty_cache()
+    # secondary sections: a failure in one is recorded in its place (and its
+    # traceback printed) so that the measured headline is still reported
+    def section(key, msg, fn, *a):
+        print(f"[bench] {msg} ...", file=sys.stderr, flush=True)
+        try:
+            out[key] = fn(*a)
+        except Exception as exc:  # noqa: BLE001 - reported, not swallowed
+            traceback.print_exc()
+            out[key] = {"error": f"{type(exc).__name__}: {exc}"}
+
     if args.other_cfl == "on":
-        print("[bench] CFL 1.5 and 2.0 ...", file=sys.stderr, flush=True)
-        out["other_cfl"] = cfl_section(ctx, args.size, (1.5, 2.0), 10)
-        print("[bench] Strang splitting at CFL 0.9 and 1.5 ...", file=sys.stderr, flush=True)
-        out["strang"] = cfl_section(ctx, args.size, (0.9, 1.5), 10, native.CEC_STRANG,
-                                    "third order with Strang splitting")
-        print("[bench] every scheme at 256^3, CFL 1.5 ...", file=sys.stderr, flush=True)
-        out["schemes_256"] = schemes_section(ctx, 256, 1.5, 10)
+        section("other_cfl", "CFL 1.5 and 2.0", cfl_section, ctx, args.size, (1.5, 2.0), 10)
+        section("strang", "Strang splitting at CFL 0.9 and 1.5", cfl_section, ctx, args.size,
+                (0.9, 1.5), 10, native.CEC_STRANG, "third order with Strang splitting")
+        section("schemes_256", "every scheme at 256^3, CFL 1.5", schemes_section, ctx, 256, 1.5, 10)
     if args.large == "on":
-        print("[bench] 1024^3 at CFL 2.0 ...", file=sys.stderr, flush=True)
-        out["large"] = large_section(ctx, 1024, 2.0, 10)
+        section("large", "1024^3 at CFL 2.0", large_section, ctx, 1024, 2.0, 10)
     if args.batch == "on":
-        print("[bench] batched workload ...", file=sys.stderr, flush=True)
-        out["batch"] = batch_section(ctx, args.size, args.batch_scalars, args.batch_grids, args.steps)
+        section("batch", "batched workload", batch_section, ctx, args.size, args.batch_scalars,
+                args.batch_grids, args.steps)
         torch.cuda.empty_cache()
     if args.learned == "on":
-        print("[bench] learned correction: pairs, training, evaluation ...", file=sys.stderr, flush=True)
-        out["learned"] = learned_section(ctx, args.learned_size, args.learned_fields, args.learned_steps,
-                                         args.learned_cells, args.learned_iters, 65536, 2e-3,
-                                         args.learned_rounds)
+        section("learned", "learned correction: pairs, training, evaluation", learned_section, ctx,
+                args.learned_size, args.learned_fields, args.learned_steps, args.learned_cells,
+                args.learned_iters, 65536, 2e-3, args.learned_rounds)
 
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle sample ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(phi0, u, dx, dt, scheme, args.cpu_edge, args.cpu_steps)
         if args.cpu_workers > 0:
-            print(f"[bench] timing the CPU oracle on {args.cpu_workers} processes ...",
-                  file=sys.stderr, flush=True)
-            out["cpu_baseline"]["all_cores"] = cpu_all_cores(
-                phi0, u, dx, dt, scheme, args.cpu_edge, args.size, args.cpu_all_steps, args.cpu_workers)
+            try:
+                print(f"[bench] timing the CPU oracle on {args.cpu_workers} processes ...",
+                      file=sys.stderr, flush=True)
+                out["cpu_baseline"]["all_cores"] = cpu_all_cores(
+                    phi0, u, dx, dt, scheme, args.cpu_edge, args.size, args.cpu_all_steps,
+                    args.cpu_workers)
+            except Exception as exc:  # noqa: BLE001 - reported, not swallowed
+                traceback.print_exc()
+                out["cpu_baseline"]["all_cores"] = {"error": f"{type(exc).__name__}: {exc}"}
     else:
         out["cpu_baseline"] = None
 
