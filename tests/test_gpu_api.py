@@ -151,3 +151,24 @@ def test_graph_capture_and_replays(ctx):
     assert ei.value.status == native.ECAPTURE
     torch.cuda.synchronize()
     ctx.check()
+
+
+def test_empty_calls_are_no_ops(ctx):
+    """Zero fields, zero problems and zero steps succeed without touching memory."""
+    import ctypes
+    import torch
+    from paper_1606_06117_amd import native
+    lib = native.load()
+    shape = (16, 16, 16)
+    g = native.make_grid(shape, (0.1, 0.1, 0.1))
+    u = torch.zeros((3,) + shape, device="cuda")
+    phi = torch.full(shape, 2.5, device="cuda")
+    assert lib.sla_advect_multi(ctx.h, ctypes.byref(g), 0, None, ctypes.c_void_p(u.data_ptr()), 0.01,
+                                native.CEC, 3, 0, 0.0) == native.OK
+    assert lib.sla_advect_batch(ctx.h, 0, None, native.CEC, 3, 0, 0.0) == native.OK
+    assert lib.sla_advect_batch(ctx.h, -1, None, native.CEC, 3, 0, 0.0) == native.EINVAL
+    for scheme in range(7):
+        ctx.advect(phi, u, (0.1, 0.1, 0.1), 0.01, scheme, 0)
+    torch.cuda.synchronize()
+    assert bool((phi == 2.5).all())
+    ctx.check()
