@@ -12,7 +12,11 @@
  *   CEC  the third-order combination A*FEC + B*BEC of eq. intro:CEC with the
  *        weights of eq. intro:CECcoef, taken from U mod 1 at large Courant
  *        numbers (eq. intro:CECcoefSL) and applied one axis at a time
- *        (section 5, eqs. split:1 and split:2).
+ *        (section 5, eqs. split:1 and split:2),
+ *
+ * and, as options, the third order under Strang's symmetric splitting
+ * (SLA_CEC_STRANG) and FEC and BEC one axis at a time (SLA_FEC_SPLIT,
+ * SLA_BEC_SPLIT).
  *
  * Conventions shared by every entry point
  * ---------------------------------------
