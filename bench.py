@@ -287,6 +287,29 @@ def schemes_section(ctx, size, cfl, steps):
             "runs": rows}
 
 
+def norms_section(ctx, size, reps):
+    """The FP64 reductions (relative L2, max error, sums) of two FP32 fields
+    of size^3: 8 B per element pair read; each call ends with the five
+    results copied to the host."""
+    import numpy as np
+    import torch
+    from paper_1606_06117_amd import workloads as W
+    shape = (size,) * 3
+    dev = torch.device("cuda:0")
+    a = torch.from_numpy(W.random_gaussians(shape, 8, seed=2000).astype(np.float32)).to(dev)
+    b = a * 1.0001
+    ctx.norms(a, b)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ctx.norms(a, b)
+    wall = (time.perf_counter() - t0) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return {"workload": f"sla_norms on two FP32 {size}^3 fields, {reps} calls", "ms_per_call": wall * 1e3,
+            "GB_per_s": 8 * size**3 / wall / 1e9, "hbm_frac": 8 * size**3 / wall / (HBM_PEAK_GBS * 1e9)}
+
+
 def large_section(ctx, size, cfl, steps):
     """One large problem: a k^-5/3 field (|k| <= 64) on size^3 with the ABC
     velocity at CFL ``cfl``, built on the GPU."""
@@ -524,6 +547,7 @@ def main(argv=None):
         section("strang", "Strang splitting at CFL 0.9 and 1.5", cfl_section, ctx, args.size,
                 (0.9, 1.5), 10, native.CEC_STRANG, "third order with Strang splitting")
         section("schemes_256", "every scheme at 256^3, CFL 1.5", schemes_section, ctx, 256, 1.5, 10)
+        section("norms_512", "FP64 reductions at 512^3", norms_section, ctx, 512, 20)
     if args.large == "on":
         section("large", "1024^3 at CFL 2.0", large_section, ctx, 1024, 2.0, 10)
     if args.batch == "on":

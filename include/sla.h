@@ -370,8 +370,8 @@ int sla_advect_learned(sla_ctx *ctx, const sla_model *model, const sla_grid *gri
  * ---------------------------------------------------------------------- */
 typedef enum {
   SLA_K_CIR = 0,     /* unsplit CIR step                      */
-  SLA_K_FEC = 1,     /* fused unsplit FEC step                */
-  SLA_K_BEC = 2,     /* fused unsplit BEC step                */
+  SLA_K_FEC = 1,     /* unsplit FEC step (each of its launches) */
+  SLA_K_BEC = 2,     /* unsplit BEC step (each of its launches) */
   SLA_K_SWEEP_X = 3, /* third-order sweep along x             */
   SLA_K_SWEEP_Y = 4, /* third-order sweep along y             */
   SLA_K_SWEEP_Z = 5, /* third-order sweep along z             */

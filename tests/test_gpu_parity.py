@@ -247,6 +247,14 @@ def test_norms(ctx):
         assert got[2] == ref[2]
         again = ctx.norms(torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda())
         assert again == got  # bitwise reproducible
+        if n > 1:
+            # fields that do not start on a 16-byte boundary take the scalar loads
+            da, db = torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()
+            got1 = ctx.norms(da[1:], db[1:])
+            ref1 = oracle.reductions(a[1:], b[1:])
+            for k in (0, 1, 3, 4):
+                assert got1[k] == pytest.approx(ref1[k], rel=1e-12, abs=1e-12 * n)
+            assert got1[2] == ref1[2]
 
 
 # ---------------------------------------------------------------------------
