@@ -119,9 +119,11 @@ int check_grid(sla_ctx* ctx, const sla_grid* g) {
     } else if (g->n[d] != 1) {
       return fail(ctx, SLA_EINVAL, "n[%d] must be 1 on an unused axis", d);
     }
+    // each extent is below 2^31 and the running product stays below 2^31,
+    // so the product cannot overflow before it is checked
     cells *= g->n[d];
+    if (cells >= (int64_t(1) << 31)) return fail(ctx, SLA_EINVAL, "grid has 2^31 cells or more");
   }
-  if (cells >= (int64_t(1) << 31)) return fail(ctx, SLA_EINVAL, "grid has 2^31 cells or more");
   return SLA_OK;
 }
 
@@ -612,7 +614,7 @@ int advect_steps(sla_ctx* ctx, const sla_grid* grid, float* phi, const float* u,
           break;
         }
         const int rxy = reach[0] > reach[1] ? reach[0] : reach[1];
-        if (ctx->sweep_kernel == 2 && rxy <= 2 && sla::offsets32_ok(geo)) {
+        if (ndim >= 2 && ctx->sweep_kernel == 2 && rxy <= 2 && sla::offsets32_ok(geo)) {
           // x and y in one kernel: x,y then z on even steps, z then y,x on
           // odd.  Up to reach 2: a 64-lane window then yields 52 or more
           // outputs; at reach 3 (46) the y sweep's work on the halo lanes
@@ -1012,6 +1014,9 @@ int sla_advect_learned(sla_ctx* ctx, const sla_model* model, const sla_grid* gri
   const sla::Geo geo = make_geo(grid, dt);
   double cm = courant_max;
   if (!(cm > 0.0)) {
+    if (capturing(ctx))
+      return fail(ctx, SLA_ECAPTURE, "measuring the Courant bound synchronises the stream: "
+                  "pass courant_max > 0 while capturing");
     float c3[3];
     rc = measure_courant(ctx, grid, geo, u, c3);
     if (rc) return rc;
@@ -1213,6 +1218,8 @@ int sla_plan_create(sla_ctx* ctx, sla_plan** out, int32_t nprob, const sla_probl
   *out = nullptr;
   if (steps < 0) return fail(ctx, SLA_EINVAL, "steps must be >= 0");
   if (std::isnan(courant_max)) return fail(ctx, SLA_EINVAL, "courant_max is NaN");
+  if (capturing(ctx))
+    return fail(ctx, SLA_ECAPTURE, "creating a plan allocates and synchronises the stream");
   DeviceGuard guard(ctx->device);
   if (!guard.ok) return fail(ctx, SLA_EHIP, "cannot select device %d", ctx->device);
   std::vector<sla_problem> P(probs, probs + nprob);

@@ -2,7 +2,8 @@
 //
 // Both are two-level trees with a fixed number of blocks and a fixed
 // per-thread stride, so a result depends only on the element count, never
-// on the device or on timing: bitwise reproducible.
+// on the device, on timing or on the alignment of the inputs: bitwise
+// reproducible.
 
 #include "common.h"
 
@@ -16,9 +17,10 @@ __device__ __forceinline__ double max_nan(double m, double v) { return (v > m ||
 __device__ __forceinline__ float max_nan(float m, float v) { return (v > m || v != v) ? v : m; }
 
 // Per block: partial sums of (a-b)^2, b^2, max|a-b|, a, b over a grid-stride
-// range; the block's 256 partials are combined in a fixed tree.  VEC: both
-// arrays 16-byte aligned, read four elements per load (a thread keeps four
-// loads in flight), the n % 4 tail elements by the first threads.
+// range of groups of four elements; the block's 256 partials are combined
+// in a fixed tree.  VEC: both arrays 16-byte aligned, a group is one load
+// per array; otherwise four.  The n % 4 tail elements go to the first
+// threads.
 template <bool VEC>
 __global__ __launch_bounds__(kThreads) void k_norms_part(int64_t n, const float* __restrict__ a,
                                                          const float* __restrict__ b,
@@ -34,21 +36,25 @@ __global__ __launch_bounds__(kThreads) void k_norms_part(int64_t n, const float*
   };
   const int64_t stride = (int64_t)gridDim.x * kThreads;
   const int64_t gid = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (VEC) {
-    const int64_t n4 = n / 4;
-    const float4* a4 = reinterpret_cast<const float4*>(a);
-    const float4* b4 = reinterpret_cast<const float4*>(b);
-    for (int64_t i = gid; i < n4; i += stride) {
-      const float4 va = a4[i], vb = b4[i];
-      add(va.x, vb.x);
-      add(va.y, vb.y);
-      add(va.z, vb.z);
-      add(va.w, vb.w);
+  // Both forms give every thread the same groups of four consecutive
+  // elements in the same order, so the result does not depend on the
+  // alignment of a and b.
+  const int64_t n4 = n / 4;
+  for (int64_t i = gid; i < n4; i += stride) {
+    float4 va, vb;
+    if (VEC) {
+      va = reinterpret_cast<const float4*>(a)[i];
+      vb = reinterpret_cast<const float4*>(b)[i];
+    } else {
+      va = make_float4(a[4 * i], a[4 * i + 1], a[4 * i + 2], a[4 * i + 3]);
+      vb = make_float4(b[4 * i], b[4 * i + 1], b[4 * i + 2], b[4 * i + 3]);
     }
-    if (gid < n - 4 * n4) add(a[4 * n4 + gid], b[4 * n4 + gid]);
-  } else {
-    for (int64_t i = gid; i < n; i += stride) add(a[i], b[i]);
+    add(va.x, vb.x);
+    add(va.y, vb.y);
+    add(va.z, vb.z);
+    add(va.w, vb.w);
   }
+  if (gid < n - 4 * n4) add(a[4 * n4 + gid], b[4 * n4 + gid]);
   __shared__ double sh[5][kThreads];
   sh[0][threadIdx.x] = s0;
   sh[1][threadIdx.x] = s1;

@@ -96,6 +96,13 @@ int main(int argc, char **argv) {
   CHECK(sla_workspace_size(&bad, SLA_CEC, 1) == 0);
   bad = grid3(2048, 2048, 1024, 0.1); /* 2^32 cells: beyond the limit */
   CHECK(sla_workspace_size(&bad, SLA_CEC, 1) == 0);
+  /* extents whose product wraps a signed 64-bit integer: 2^63 */
+  bad = grid3(1 << 21, 1 << 21, 1 << 21, 0.1);
+  CHECK(sla_workspace_size(&bad, SLA_CEC, 1) == 0);
+  bad = grid3(2147483647, 2147483647, 2147483647, 0.1);
+  CHECK(sla_workspace_size(&bad, SLA_CEC, 1) == 0);
+  bad = grid3(1 << 16, 1 << 15, 8, 0.1); /* 2^34 cells, no wrap */
+  CHECK(sla_workspace_size(&bad, SLA_CEC, 1) == 0);
 
   /* a context on a machine without a usable device fails and leaves *out NULL */
   if (expect_no_device) {

@@ -60,6 +60,13 @@ def test_workspace_size():
             assert lib.sla_workspace_size(ctypes.byref(g), scheme, ns) == 4 * 12 * 34 * 56
     assert lib.sla_workspace_size(ctypes.byref(g), 7, 1) == 0
     assert lib.sla_workspace_size(ctypes.byref(g), 3, -1) == 0
+    # grids of 2^31 cells or more, including extents whose product would
+    # wrap a 64-bit integer, are invalid
+    for shape in [(1 << 21,) * 3, (2**31 - 1,) * 3, (8, 1 << 15, 1 << 16), (1 << 10, 1 << 11, 1 << 10)]:
+        big = native.make_grid(shape, (0.1, 0.1, 0.1))
+        assert lib.sla_workspace_size(ctypes.byref(big), 3, 1) == 0, shape
+    ok = native.make_grid((8, 1 << 12, 1 << 15), (0.1, 0.1, 0.1))  # 2^30 cells
+    assert lib.sla_workspace_size(ctypes.byref(ok), 3, 1) == 4 << 30
 
 
 def test_create_without_device_is_an_error():

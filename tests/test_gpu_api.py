@@ -150,6 +150,22 @@ def test_graph_capture_and_replays(ctx):
             ctx.advect(other, u, dx, dt, native.CEC, 1)  # would measure the bound
     assert ei.value.status == native.ECAPTURE
     torch.cuda.synchronize()
+    # the learned step would measure the bound; a plan allocates and synchronises
+    model = native.Model(ctx)
+    refused = [
+        lambda: native.advect_learned(ctx, model, other, u, dx, dt, 1),
+        lambda: native.Plan(ctx, [(other, u, dx, dt)], 1, tune=False),
+    ]
+    for call in refused:
+        g3 = torch.cuda.CUDAGraph()
+        with pytest.raises(native.SlaError) as ei, warnings.catch_warnings():
+            warnings.simplefilter("ignore")
+            with torch.cuda.graph(g3):
+                call()
+        assert ei.value.status == native.ECAPTURE
+        torch.cuda.synchronize()
+    model.close()
+    assert torch.equal(other, phi0)
     ctx.check()
 
 

@@ -255,6 +255,40 @@ def test_norms(ctx):
             for k in (0, 1, 3, 4):
                 assert got1[k] == pytest.approx(ref1[k], rel=1e-12, abs=1e-12 * n)
             assert got1[2] == ref1[2]
+            # the same values in aligned memory give the same bits
+            assert ctx.norms(da[1:].clone(), db[1:].clone()) == got1
+
+
+def test_cec_1d_reads_only_its_plane(ctx):
+    """A 1D third-order step reads the one velocity plane it is given: NaN in
+    the memory after it does not reach the result, which equals the one
+    kernel per axis path bit for bit."""
+    import torch
+    from paper_1606_06117_amd import native
+    n = 30
+    x = np.arange(n) / n
+    phi = (-np.cos(2 * np.pi * x)).astype(np.float32)
+    big = torch.full((2 * n,), float("nan"), device="cuda")
+    big[:n] = 1.0
+    u = big[:n].view(1, n)
+    dx = (1.0 / n,)
+    dt = 0.75 * dx[0]
+    p = torch.from_numpy(phi).cuda()
+    ctx.advect(p, u, dx, dt, native.CEC, 4)
+    torch.cuda.synchronize()
+    got = p.cpu().numpy()
+    assert np.isfinite(got).all()
+    ctx.set_option(native.OPT_SWEEP_KERNEL, 1)
+    try:
+        q = torch.from_numpy(phi).cuda()
+        ctx.advect(q, u, dx, dt, native.CEC, 4)
+        torch.cuda.synchronize()
+    finally:
+        ctx.set_option(native.OPT_SWEEP_KERNEL, 2)
+    assert np.array_equal(got, q.cpu().numpy())
+    ref = oracle_advect(phi, u.cpu().numpy(), dx, dt, oracle.CEC, 4)
+    check(got.astype(np.float64), ref, phi, 4, "1d cec, NaN after u")
+    ctx.check()
 
 
 # ---------------------------------------------------------------------------
