@@ -142,6 +142,29 @@ int sla_advect(sla_ctx *ctx, const sla_grid *grid, float *phi, const float *u,
                double dt, int32_t scheme, int32_t steps, int64_t step0,
                double courant_max);
 
+/* Largest grid, in cells, that sla_advect_noalloc takes (2^23: 32 MiB of
+ * static device memory per device). */
+#define SLA_NOALLOC_MAX_CELLS 8388608
+
+/* sla_advect for callers that cannot allocate device memory: code being
+ * captured into a graph, tight serving loops, hosts that forbid allocation.
+ * Same arguments, checks and result (bit for bit) as sla_advect, but the work
+ * field is a static device array of SLA_NOALLOC_MAX_CELLS FP32 values that
+ * each device holds from the library's load to the end of the process; the
+ * call never allocates, frees or creates anything, and ignores the context's
+ * workspace and its timing (its launches are not timed).  A grid of more than
+ * SLA_NOALLOC_MAX_CELLS cells returns SLA_EINVAL before any work.  With
+ * courant_max > 0 the call only launches kernels (and at most one device
+ * copy); with courant_max <= 0 it measures the bound (one stream
+ * synchronisation; SLA_ECAPTURE while the stream is captured).
+ * Every context on a device shares that device's array, and nothing of it
+ * carries over between calls: calls on one device whose work overlaps in time
+ * (other streams, other contexts, other host threads) race on it and must be
+ * ordered by the caller. */
+int sla_advect_noalloc(sla_ctx *ctx, const sla_grid *grid, float *phi, const float *u,
+                       double dt, int32_t scheme, int32_t steps, int64_t step0,
+                       double courant_max);
+
 /* sla_advect on nscalars fields that share the velocity u: phis is a host
  * array of nscalars device fields, each advanced in place with the same
  * grid, dt, scheme and steps.  The Courant bound is measured (or taken from

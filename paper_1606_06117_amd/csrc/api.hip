@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <algorithm>
@@ -22,6 +23,7 @@ struct sla_ctx {
   double* dpart = nullptr;// norm partials (5 * kNormBlocks) + 5 results
   int* flag = nullptr;    // set by a kernel that clamped an offset
   void* host = nullptr;   // pinned staging for small results (256 bytes)
+  float* scratch = nullptr;  // this device's static work field (sla_advect_noalloc)
   std::string err;
   bool fused = true;    // SLA_OPT_FUSED
   int cec3d_kernel = 5;  // SLA_OPT_CEC3D_KERNEL
@@ -232,6 +234,33 @@ int ensure_work(sla_ctx* ctx, size_t floats) {
   return SLA_OK;
 }
 
+// Work memory of sla_advect_noalloc: one field of at most
+// SLA_NOALLOC_MAX_CELLS cells per device, held from the library's load to the
+// end of the process.  Host code must not use the array's name as an
+// address: each device's copy is reached through the pointer that
+// hipGetSymbolAddress returned on that device (scratch_on).
+static __device__ __align__(256) float scratch[SLA_NOALLOC_MAX_CELLS];
+
+constexpr int kScratchDevices = 64;
+std::mutex scratch_mu;
+float* scratch_dev[kScratchDevices] = {};
+
+// The device address of `scratch` on `device` (which must be current),
+// looked up once per device.
+hipError_t scratch_on(int device, float** out) {
+  *out = nullptr;
+  if (device < 0 || device >= kScratchDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (!scratch_dev[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    scratch_dev[device] = static_cast<float*>(p);
+  }
+  *out = scratch_dev[device];
+  return hipSuccess;
+}
+
 }  // namespace
 
 extern "C" {
@@ -269,6 +298,8 @@ int sla_create(sla_ctx** out, int device, void* stream) {
   ok = ok && hipMalloc(&ctx->flag, sizeof(int)) == hipSuccess;
   ok = ok && hipHostMalloc(&ctx->host, 256, hipHostMallocDefault) == hipSuccess;
   ok = ok && hipMemset(ctx->flag, 0, sizeof(int)) == hipSuccess;
+  // the static work field of sla_advect_noalloc (that call fails without it)
+  if (ok && scratch_on(device, &ctx->scratch) != hipSuccess) (void)hipGetLastError();
   if (!ok) {
     (void)hipGetLastError();
     sla_destroy(ctx);
@@ -366,8 +397,11 @@ int advect_reach(sla_ctx* ctx, const sla_grid* grid, const sla::Geo& geo, const 
   return SLA_OK;
 }
 
+// work: the ping-pong field to use, or NULL for the context's work memory
+// (allocated on first use).
 int advect_steps(sla_ctx* ctx, const sla_grid* grid, float* phi, const float* u, double dt,
-                 int32_t scheme, int32_t steps, int64_t step0, const int reach[3]);
+                 int32_t scheme, int32_t steps, int64_t step0, const int reach[3],
+                 float* work = nullptr);
 
 }  // namespace
 
@@ -386,6 +420,31 @@ int sla_advect(sla_ctx* ctx, const sla_grid* grid, float* phi, const float* u, d
   rc = advect_reach(ctx, grid, make_geo(grid, dt), u, courant_max, reach);
   if (rc) return rc;
   return advect_steps(ctx, grid, phi, u, dt, scheme, steps, step0, reach);
+}
+
+int sla_advect_noalloc(sla_ctx* ctx, const sla_grid* grid, float* phi, const float* u, double dt,
+                       int32_t scheme, int32_t steps, int64_t step0, double courant_max) {
+  if (!ctx) return SLA_EINVAL;
+  ctx->err.clear();
+  int rc = check_advect(ctx, grid, phi, u, dt, scheme, steps, courant_max);
+  if (rc) return rc;
+  const int64_t cells = int64_t(grid->n[0]) * grid->n[1] * grid->n[2];
+  if (cells > SLA_NOALLOC_MAX_CELLS)
+    return fail(ctx, SLA_EINVAL, "grid of %lld cells: sla_advect_noalloc takes at most %d",
+                (long long)cells, SLA_NOALLOC_MAX_CELLS);
+  if (!ctx->scratch) return fail(ctx, SLA_EHIP, "no static work memory on device %d", ctx->device);
+  if (steps == 0) return SLA_OK;
+  DeviceGuard guard(ctx->device);
+  if (!guard.ok) return fail(ctx, SLA_EHIP, "cannot select device %d", ctx->device);
+  int reach[3];
+  rc = advect_reach(ctx, grid, make_geo(grid, dt), u, courant_max, reach);
+  if (rc) return rc;
+  // per-launch timing would create events: this call's launches are not timed
+  const bool timing = ctx->timing;
+  ctx->timing = false;
+  rc = advect_steps(ctx, grid, phi, u, dt, scheme, steps, step0, reach, ctx->scratch);
+  ctx->timing = timing;
+  return rc;
 }
 
 size_t sla_workspace_size(const sla_grid* grid, int32_t scheme, int32_t nscalars) {
@@ -546,23 +605,25 @@ namespace {
 // The steps of sla_advect once the arguments are checked and the reach per
 // axis is known (the device is selected).
 int advect_steps(sla_ctx* ctx, const sla_grid* grid, float* phi, const float* u, double dt,
-                 int32_t scheme, int32_t steps, int64_t step0, const int reach[3]) {
+                 int32_t scheme, int32_t steps, int64_t step0, const int reach[3], float* work) {
   const sla::Geo geo = make_geo(grid, dt);
   const int ndim = grid->ndim;
-  int rc;
   int rmax = 1;
   for (int d = 0; d < ndim; ++d) rmax = reach[d] > rmax ? reach[d] : rmax;
 
   const size_t n = size_t(geo.ncells);
-  rc = ensure_work(ctx, n);
-  if (rc) return rc;
+  if (!work) {
+    const int rc = ensure_work(ctx, n);
+    if (rc) return rc;
+    work = ctx->work;
+  }
 
   // A 3D third-order step whose reach is 1 on every axis runs as one fused
   // kernel (20 B/cell); other cases run one sweep kernel per axis.  The
   // fused kernels address a field with 32-bit byte offsets: up to 2^30 cells.
   const bool fused3d = ctx->fused && ndim == 3 && rmax == 1 && sla::offsets32_ok(geo);
   float* cur = phi;
-  float* nxt = ctx->work;
+  float* nxt = work;
   hipError_t e = hipSuccess;
   for (int32_t k = 0; k < steps && e == hipSuccess; ++k) {
     const int64_t m = step0 + k;

@@ -18,6 +18,7 @@ CIR, FEC, BEC, CEC, CEC_STRANG, FEC_SPLIT, BEC_SPLIT = 0, 1, 2, 3, 4, 5, 6
 SCHEMES = {"cir": CIR, "fec": FEC, "bec": BEC, "cec": CEC, "cec_strang": CEC_STRANG,
            "fec_split": FEC_SPLIT, "bec_split": BEC_SPLIT}
 MAX_REACH = 4
+NOALLOC_MAX_CELLS = 1 << 23
 
 OK, EINVAL, ECOURANT, EHIP, ENOMEM, ENOMODEL, ECAPTURE = 0, -1, -2, -3, -4, -5, -6
 OPT_FUSED = 0
@@ -38,6 +39,8 @@ SIGNATURES = {
     "sla_courant_max": (_c.c_int, [_vp, _vp, _vp, _c.c_double, _c.POINTER(_c.c_double)]),
     "sla_advect": (_c.c_int, [_vp, _vp, _vp, _vp, _c.c_double, _c.c_int32, _c.c_int32,
                               _c.c_int64, _c.c_double]),
+    "sla_advect_noalloc": (_c.c_int, [_vp, _vp, _vp, _vp, _c.c_double, _c.c_int32, _c.c_int32,
+                                      _c.c_int64, _c.c_double]),
     "sla_advect_multi": (_c.c_int, [_vp, _vp, _c.c_int32, _vp, _vp, _c.c_double, _c.c_int32,
                                     _c.c_int32, _c.c_int64, _c.c_double]),
     "sla_workspace_size": (_c.c_size_t, [_vp, _c.c_int32, _c.c_int32]),
@@ -195,6 +198,20 @@ class Context:
         self._stream()
         self._raise(self.lib.sla_advect(self.h, ctypes.byref(g), _ptr(phi), _ptr(u), float(dt),
                                         int(scheme), int(steps), int(step0), float(courant_max)))
+        return phi
+
+    def advect_noalloc(self, phi, u, dx, dt, scheme, steps, step0=0, courant_max=0.0):
+        """``advect`` through ``sla_advect_noalloc`` (static work memory, no allocation)."""
+        if isinstance(scheme, str):
+            scheme = SCHEMES[scheme]
+        _check_field(phi, "phi")
+        _check_field(u, "u")
+        if tuple(u.shape) != (phi.dim(),) + tuple(phi.shape):
+            raise ValueError(f"u must have shape {(phi.dim(),) + tuple(phi.shape)}, got {tuple(u.shape)}")
+        g = make_grid(phi.shape, dx)
+        self._stream()
+        self._raise(self.lib.sla_advect_noalloc(self.h, ctypes.byref(g), _ptr(phi), _ptr(u), float(dt),
+                                                int(scheme), int(steps), int(step0), float(courant_max)))
         return phi
 
     def advect_multi(self, phis, u, dx, dt, scheme, steps, step0=0, courant_max=0.0):
