@@ -168,16 +168,21 @@ int sla_advect_noalloc(sla_ctx *ctx, const sla_grid *grid, float *phi, const flo
 /* sla_advect on nscalars fields that share the velocity u: phis is a host
  * array of nscalars device fields, each advanced in place with the same
  * grid, dt, scheme and steps.  The Courant bound is measured (or taken from
- * courant_max) once for all of them; the fields run one after another
- * through the same work memory.  Every field's result equals sla_advect on
- * it, bit for bit. */
+ * courant_max) once for all of them.  Third-order steps of a 3D grid whose
+ * Courant numbers are all below 1 run the fields four at a time (then two,
+ * then one) through a fused kernel that loads the velocity once per tile for
+ * all of them; each field of such a group takes its own work field (up to
+ * four, see sla_workspace_size; a smaller caller workspace runs fewer at a
+ * time).  Other cases run the fields one after another through one work
+ * field.  Every field's result equals sla_advect on it, bit for bit. */
 int sla_advect_multi(sla_ctx *ctx, const sla_grid *grid, int32_t nscalars, float *const *phis,
                      const float *u, double dt, int32_t scheme, int32_t steps, int64_t step0,
                      double courant_max);
 
-/* Device bytes of work memory sla_advect and sla_advect_multi need on grid
- * (one FP32 field whatever the scheme; nscalars does not change it, the
- * fields run one after another).  0 for an invalid grid or scheme. */
+/* Device bytes of work memory sla_advect and sla_advect_multi need on grid:
+ * one FP32 field, or for SLA_CEC on a 3D grid min(nscalars, 4) fields (the
+ * fields of a shared-velocity group each take one).  0 for an invalid grid
+ * or scheme. */
 size_t sla_workspace_size(const sla_grid *grid, int32_t scheme, int32_t nscalars);
 
 /* Make the context use `bytes` of caller-owned device memory at dev_ptr as
@@ -224,7 +229,21 @@ typedef enum {
    * LDS; 1 one gather kernel per call (FEC: 2, BEC: 3), the intermediates
    * through the work field (44 and 64 B per cell moved); 2 (default) as 1,
    * the faster of the two at every size and Courant number measured. */
-  SLA_OPT_EC_KERNEL = 3
+  SLA_OPT_EC_KERNEL = 3,
+  /* Launch shape of the fused step (same results whatever the value): the
+   * planes a workgroup marches (variants 0-4, 6 and 7), or the workgroups
+   * launched per compute unit (variants 8 and up); 0 (default): the
+   * implementation's own rule. */
+  SLA_OPT_CEC3D_SHAPE = 4,
+  /* How the learned step's correction runs (same results): 1 (default) a
+   * march along z with each node's neighbourhood staged in LDS; 0 a gather
+   * of the 27 values per node. */
+  SLA_OPT_LEARNED_KERNEL = 5,
+  /* The largest group of fields sla_advect_multi runs through one fused
+   * kernel that reads the shared velocity once per tile for all of them
+   * (third-order 3D steps at reach 1): 4 (default) or 2; 0 or 1: field after
+   * field.  Same results. */
+  SLA_OPT_SHARED_VELOCITY = 6
 } sla_option;
 /* Set option `option` to `value`.  Returns SLA_EINVAL for an unknown option
  * or value. */

@@ -29,6 +29,9 @@ struct sla_ctx {
   int cec3d_kernel = 5;  // SLA_OPT_CEC3D_KERNEL
   int sweep_kernel = 2;  // SLA_OPT_SWEEP_KERNEL
   int ec_kernel = 2;     // SLA_OPT_EC_KERNEL
+  int cec3d_shape = 0;   // SLA_OPT_CEC3D_SHAPE
+  int learned_kernel = 1;  // SLA_OPT_LEARNED_KERNEL
+  int multi = 4;           // SLA_OPT_SHARED_VELOCITY: largest group of fields
   // per-kernel timing
   bool timing = false;
   struct Mark { int kind; hipEvent_t a, b; };
@@ -454,7 +457,11 @@ size_t sla_workspace_size(const sla_grid* grid, int32_t scheme, int32_t nscalars
     return 0;
   size_t cells = 1;
   for (int d = 0; d < 3; ++d) cells *= size_t(grid->n[d]);
-  return cells * sizeof(float);  // one ping-pong field; scalars run one after another
+  // one ping-pong field; third-order 3D runs of several fields take one per
+  // field, up to four (the fields sharing a velocity run four at a time)
+  size_t fields = 1;
+  if (scheme == SLA_CEC && grid->ndim == 3) fields = size_t(std::min(std::max(nscalars, 1), 4));
+  return fields * cells * sizeof(float);
 }
 
 int sla_set_workspace(sla_ctx* ctx, void* dev_ptr, size_t bytes) {
@@ -488,10 +495,55 @@ int sla_advect_multi(sla_ctx* ctx, const sla_grid* grid, int32_t nscalars, float
   DeviceGuard guard(ctx->device);
   if (!guard.ok) return fail(ctx, SLA_EHIP, "cannot select device %d", ctx->device);
   int reach[3];  // one Courant bound for all the fields
-  rc = advect_reach(ctx, grid, make_geo(grid, dt), u, courant_max, reach);
-  for (int32_t k = 0; k < nscalars && rc == SLA_OK; ++k)
-    rc = advect_steps(ctx, grid, phis[k], u, dt, scheme, steps, step0, reach);
-  return rc;
+  const sla::Geo geo = make_geo(grid, dt);
+  rc = advect_reach(ctx, grid, geo, u, courant_max, reach);
+  if (rc) return rc;
+  // third order in 3D at reach 1: the fields run up to four at a time
+  // through the shared-velocity fused step, each with its own work field
+  const bool shared = scheme == SLA_CEC && grid->ndim == 3 && ctx->fused && ctx->multi > 1 &&
+                      reach[0] == 1 && reach[1] == 1 && reach[2] == 1 && nscalars >= 2 &&
+                      sla::offsets32_ok(geo);
+  if (!shared) {
+    for (int32_t k = 0; k < nscalars && rc == SLA_OK; ++k)
+      rc = advect_steps(ctx, grid, phis[k], u, dt, scheme, steps, step0, reach);
+    return rc;
+  }
+  const size_t n = size_t(geo.ncells);
+  size_t kmax = size_t(std::min<int32_t>(nscalars, ctx->multi));
+  if (ctx->work_borrowed) {
+    kmax = std::min(kmax, ctx->work_cap / n);  // what the caller's workspace holds
+    if (kmax == 0) return ensure_work(ctx, n);  // reports the size it needs
+  } else {
+    rc = ensure_work(ctx, kmax * n);
+    if (rc) return rc;
+  }
+  hipError_t e = hipSuccess;
+  for (int32_t f0 = 0; f0 < nscalars && e == hipSuccess;) {
+    const int left = nscalars - f0;
+    const int k = (left >= 4 && kmax >= 4) ? 4 : (left >= 2 && kmax >= 2) ? 2 : 1;
+    float* cur[4];
+    float* nxt[4];
+    for (int f = 0; f < k; ++f) {
+      cur[f] = phis[f0 + f];
+      nxt[f] = ctx->work + size_t(f) * n;
+    }
+    for (int32_t s = 0; s < steps && e == hipSuccess; ++s) {
+      const bool even = (step0 + s) % 2 == 0;
+      e = run(ctx, SLA_K_CEC3D, [&] {
+        return sla::launch_cec3d_multi(k, even, geo, cur, nxt, u, ctx->flag, ctx->stream);
+      });
+      for (int f = 0; f < k; ++f) std::swap(cur[f], nxt[f]);
+    }
+    for (int f = 0; f < k && e == hipSuccess; ++f)
+      if (cur[f] != phis[f0 + f])
+        e = run(ctx, SLA_K_COPY, [&] {
+          return hipMemcpyAsync(phis[f0 + f], cur[f], n * sizeof(float), hipMemcpyDeviceToDevice,
+                                ctx->stream);
+        });
+    f0 += k;
+  }
+  if (e != hipSuccess) return hip_fail(ctx, e, "shared-velocity step launch");
+  return SLA_OK;
 }
 
 }  // extern "C"
@@ -668,8 +720,10 @@ int advect_steps(sla_ctx* ctx, const sla_grid* grid, float* phi, const float* u,
       case SLA_CEC: {
         if (fused3d) {
           e = run(ctx, SLA_K_CEC3D, [&] {
+            sla::Cec3dLaunch lc;
+            lc.ychunk = ctx->cec3d_shape;
             return sla::launch_cec3d(ctx->cec3d_kernel, m % 2 == 0, geo, cur, u, nxt, ctx->flag,
-                                     ctx->stream);
+                                     ctx->stream, lc);
           });
           std::swap(cur, nxt);
           break;
@@ -793,6 +847,20 @@ int sla_set_option(sla_ctx* ctx, int option, int64_t value) {
     case SLA_OPT_EC_KERNEL:
       if (value < 0 || value > 2) return fail(ctx, SLA_EINVAL, "SLA_OPT_EC_KERNEL takes 0, 1 or 2");
       ctx->ec_kernel = int(value);
+      return SLA_OK;
+    case SLA_OPT_SHARED_VELOCITY:
+      if (value != 0 && value != 1 && value != 2 && value != 4)
+        return fail(ctx, SLA_EINVAL, "SLA_OPT_SHARED_VELOCITY takes 0, 1, 2 or 4");
+      ctx->multi = value <= 1 ? 1 : int(value);
+      return SLA_OK;
+    case SLA_OPT_LEARNED_KERNEL:
+      if (value != 0 && value != 1) return fail(ctx, SLA_EINVAL, "SLA_OPT_LEARNED_KERNEL takes 0 or 1");
+      ctx->learned_kernel = int(value);
+      return SLA_OK;
+    case SLA_OPT_CEC3D_SHAPE:
+      if (value < -4096 || value > 4096)
+        return fail(ctx, SLA_EINVAL, "SLA_OPT_CEC3D_SHAPE takes -4096..4096");
+      ctx->cec3d_shape = int(value);
       return SLA_OK;
   }
   return fail(ctx, SLA_EINVAL, "unknown option %d", option);
@@ -1106,8 +1174,11 @@ int sla_advect_learned(sla_ctx* ctx, const sla_model* model, const sla_grid* gri
     });
     if (e == hipSuccess)
       e = run(ctx, SLA_K_LEARNED, [&] {
-        return sla::launch_learned_correct(geo, ctx->work, u, model->wpack, model->wr, phi,
-                                           ctx->stream);
+        return ctx->learned_kernel == 1
+                   ? sla::launch_learned_march(geo, ctx->work, u, model->wpack, model->wr, phi,
+                                               ctx->stream)
+                   : sla::launch_learned_correct(geo, ctx->work, u, model->wpack, model->wr, phi,
+                                                 ctx->stream);
       });
   }
   if (e != hipSuccess) return hip_fail(ctx, e, "learned step launch");

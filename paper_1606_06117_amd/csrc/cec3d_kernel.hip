@@ -1094,6 +1094,456 @@ hipError_t launch_cec3d_wl(bool even, const Geo& g, const float* phi, const floa
 }
 
 // ---------------------------------------------------------------------------
+// Persistent shared-halo window march (variant 8).  The work of the
+// shared-halo march (a group of WX 64-lane x windows by S = V*W rows of the
+// segment axis, marched along the third axis) is cut into runs: the groups
+// are laid end to end, plane after plane, and workgroup b takes the range
+// [b*span, (b+1)*span) of that line, so a launch of about one workgroup per
+// CU leaves no tail and a workgroup restarts its march pipeline only where
+// its range crosses into the next group (6 extra planes per restart, against
+// one per march chunk in variant 7).  The S + 6 rows the segment sweep reads
+// are split over the W waves of a window as evenly as possible.  Same FP32
+// operations per node as the other variants.
+// ---------------------------------------------------------------------------
+template <bool EVEN, int V, int W, int WX>
+__global__ __launch_bounds__(64 * W * WX) void k_cec3d_wp(const float* __restrict__ phi,
+                                                          const float* __restrict__ ux,
+                                                          const float* __restrict__ uy,
+                                                          const float* __restrict__ uz,
+                                                          float* __restrict__ out, Geo g, int span,
+                                                          int* flag) {
+  constexpr int S = V * W, NR = S + 6, RW = (NR + W - 1) / W;
+  __shared__ float lp[2][WX][NR][64];  // segment sweep input (phi, x-swept if even)
+  __shared__ float lc[2][WX][NR][64];  // segment-axis Courant numbers
+  const int lane = threadIdx.x & 63, xi = (threadIdx.x >> 6) % WX, w = (threadIdx.x >> 6) / WX;
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  const int ns = EVEN ? ny : nz, nm = EVEN ? nz : ny;
+  const int nwx = (nx + kWmUse - 1) / kWmUse, ngx = (nwx + WX - 1) / WX, ngs = (ns + S - 1) / S;
+  const long long total = (long long)ngx * ngs * nm;
+  const int blk = block_tile(1).x;  // XCD-mapped 1D grid
+  long long i0, i1;
+  if (span > 0) {  // a range of the line of groups
+    i0 = (long long)blk * span;
+    i1 = min(i0 + (long long)span, total);
+  } else {  // one chunk of -span planes of one group, groups fastest
+    const int ng = ngx * ngs, ch = blk / ng, grp = blk - ch * ng;
+    i0 = (long long)grp * nm + (long long)ch * -span;
+    i1 = (long long)grp * nm + min(nm, (ch + 1) * -span);
+  }
+  const unsigned rowb = 4u * unsigned(nx), plb = 4u * unsigned(nx) * unsigned(ny);
+  const unsigned sstr = EVEN ? rowb : plb, mstr = EVEN ? plb : rowb;
+  const float* rS = EVEN ? uy : uz;  // segment-axis velocity
+  const float* rM = EVEN ? uz : uy;  // march-axis velocity
+  const float lamX = g.lam[0], lamS = EVEN ? g.lam[1] : g.lam[2], lamM = EVEN ? g.lam[2] : g.lam[1];
+  // rows this wave loads: grown-segment rows w*RW + k (k < nld); every wave
+  // loads its first kAll rows
+  constexpr int kAll = NR - (W - 1) * RW;
+  const int nld = min(RW, NR - w * RW);
+  bool over = false;
+  while (i0 < i1) {  // one run: the same for every wave of the workgroup
+    const int grp = int(i0 / nm), m0 = int(i0 - (long long)grp * nm);
+    const int m1 = int(min((long long)nm, (long long)m0 + (i1 - i0)));
+    i0 += m1 - m0;
+    const int wx0 = (grp % ngx) * WX, gs = grp / ngx;
+    const bool wx_ok = wx0 + xi < nwx;  // the same for the whole wave
+    const int wx = min(wx0 + xi, nwx - 1);
+    const unsigned vx = 4u * unsigned(wrapk(wx * kWmUse - 3 + lane, nx));
+    const int g0 = gs * S, s0 = g0 + w * V;
+    // per-lane byte offsets within a march plane of the rows this wave loads
+    // and of its output rows (the plane's offset goes in the scalar part)
+    unsigned lrow[RW], orow[V];
+#pragma unroll
+    for (int k = 0; k < RW; ++k)
+      lrow[k] = vx + unsigned(__builtin_amdgcn_readfirstlane(wrapk(g0 - 3 + w * RW + k, ns))) * sstr;
+#pragma unroll
+    for (int j = 0; j < V; ++j)
+      orow[j] = vx + unsigned(__builtin_amdgcn_readfirstlane(wrapk(s0 + j, ns))) * sstr;
+    PlaneWin pw(m0 - 6, nm);  // planes m0 - 6 + t .. m0 - 2 + t at iteration t
+
+    float fp[RW], fa[RW], fs[RW];  // phi, x velocity (even), segment velocity on loaded rows
+    float fm[V], fx[V];            // march velocity of plane q-1; odd: x velocity of the output plane
+    auto prefetch = [&](int ahead) {  // 0: iteration t; 1: iteration t + 1
+      const unsigned q = unsigned(pw.p[3 + ahead]) * mstr, qm1 = unsigned(pw.p[2 + ahead]) * mstr,
+                     qo = unsigned(pw.p[ahead]) * mstr;
+#pragma unroll
+      for (int k = 0; k < RW; ++k) {
+        if (k < kAll || k < nld) {
+          fp[k] = ld_vs(phi, lrow[k], q);
+          if (EVEN) fa[k] = ld_vs(ux, lrow[k], q);
+          fs[k] = ld_vs(rS, lrow[k], q);
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < V; ++j) {
+        fm[j] = ld_vs(rM, orow[j], qm1);
+        if (!EVEN) fx[j] = ld_vs(ux, orow[j], qo);
+      }
+    };
+
+    float ra[3][V], r1[3][V], re[3][V], rc[3][V];
+#pragma unroll
+    for (int j = 0; j < V; ++j)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) ra[k][j] = r1[k][j] = re[k][j] = rc[k][j] = 0.f;
+
+    const int iters = (m1 - m0) + 6;
+    const bool lane_out = lane >= 3 && lane < 61 && wx * kWmUse + lane - 3 < nx;
+    if (wx_ok) prefetch(0);
+    auto body = [&](auto phase, int t) {
+      constexpr int P0 = decltype(phase)::value;
+      const int b = t & 1;
+      if (!wx_ok) {  // a window past the row's end: barriers only
+        __syncthreads();
+        return;
+      }
+#pragma unroll
+      for (int k = 0; k < RW; ++k) {
+        if (k < kAll || k < nld) {
+          float v = fp[k];
+          if (EVEN) {
+            const float c = fa[k] * lamX;
+            over |= over1(c);
+            v = xsweep_lanes(v, c);  // first sweep (x) of this row
+          }
+          const float c = fs[k] * lamS;
+          over |= over1(c);
+          lp[b][xi][w * RW + k][lane] = v;
+          lc[b][xi][w * RW + k][lane] = c;
+        }
+      }
+      float cm[V], cxo[V];
+#pragma unroll
+      for (int j = 0; j < V; ++j) {
+        cm[j] = fm[j] * lamM;
+        over |= over1(cm[j]);
+        cxo[j] = EVEN ? 0.f : fx[j] * lamX;
+        if (!EVEN) over |= over1(cxo[j]);
+      }
+      if (t + 1 < iters) prefetch(1);
+      __syncthreads();
+      float p[V + 6], cs[V + 4], a[V], o[V];
+#pragma unroll
+      for (int k = 0; k < V + 6; ++k) p[k] = lp[b][xi][w * V + k][lane];
+#pragma unroll
+      for (int k = 0; k < V + 4; ++k) cs[k] = lc[b][xi][w * V + 1 + k][lane];
+      // sweep along the segment axis (second for even, first for odd)
+      sweep_segment<V>(p, cs, a, flag);
+      // sweep along the march axis (even: last; odd: second)
+      march_step<V, P0>(ra, r1, re, rc, a, cm, o);
+      if (t >= 6) {
+        const unsigned qo = unsigned(pw.p[0]) * mstr;
+        if (!EVEN)  // all lanes: the halo lanes feed the output lanes' neighbours
+#pragma unroll
+          for (int j = 0; j < V; ++j) o[j] = xsweep_lanes(o[j], cxo[j]);  // last sweep (x)
+        if (lane_out) {
+          const int rows_left = ns - s0;
+#pragma unroll
+          for (int j = 0; j < V; ++j)
+            if (j < rows_left) st_vs(out, orow[j], qo, o[j]);
+        }
+      }
+      pw.advance();
+    };
+    for (int t = 0; t < iters; t += 3) {
+      body(std::integral_constant<int, 0>{}, t);
+      if (t + 1 < iters) body(std::integral_constant<int, 1>{}, t + 1);
+      if (t + 2 < iters) body(std::integral_constant<int, 2>{}, t + 2);
+    }
+    // the next run's first LDS writes must not meet this run's last reads
+    __syncthreads();
+  }
+  if (over) *flag = 1;
+}
+
+// The persistent march's configurations: (V, W, WX) and a name.
+struct WpConfig {
+  int V, W, WX;
+};
+constexpr WpConfig kWpConfigs[] = {
+    {8, 2, 3},  // 0: variant 7's shape
+    {4, 4, 3},  // 1: 16-row groups, 12 waves
+    {4, 8, 2},  // 2: 32-row groups, 16 waves
+    {8, 4, 2},  // 3: 32-row groups, 8 waves
+    {4, 6, 2},  // 4: 24-row groups, 12 waves
+    {2, 8, 2},  // 5: 16-row groups, 16 waves, two rows per wave
+};
+constexpr int kWpCount = sizeof(kWpConfigs) / sizeof(kWpConfigs[0]);
+
+template <bool EVEN, int V, int W, int WX>
+hipError_t launch_wp_t(const Geo& g, const float* phi, const float* u, float* out, int* flag,
+                       hipStream_t st, int shape) {
+  auto kern = k_cec3d_wp<EVEN, V, W, WX>;
+  constexpr int S = V * W;
+  const size_t n = (size_t)g.ncells;
+  const int ns = EVEN ? g.ny : g.nz, nm = EVEN ? g.nz : g.ny;
+  const int nwx = (g.nx + kWmUse - 1) / kWmUse;
+  const long long total = (long long)((nwx + WX - 1) / WX) * ((ns + S - 1) / S) * nm;
+  static int cus = 0, fit = 0;
+  if (!cus) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      cus = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&fit, kern, 64 * W * WX, 0) != hipSuccess ||
+        fit < 1)
+      fit = 1;
+  }
+  long long blocks;
+  int span;
+  if (shape < 0) {  // chunks of -shape planes, one per workgroup
+    const int chunk = -shape;
+    span = -chunk;
+    blocks = total / nm * ((nm + chunk - 1) / chunk);
+  } else {
+    const int per_cu = shape > 0 ? min(shape, fit) : fit;
+    blocks = (long long)cus * per_cu;
+    // every workgroup marches at least 16 planes
+    blocks = max(1LL, min(blocks, total / 16));
+    span = int((total + blocks - 1) / blocks);
+    blocks = (total + span - 1) / span;
+  }
+  hipLaunchKernelGGL(kern, dim3(unsigned(blocks)), dim3(64 * W * WX), 0, st, phi, u, u + n,
+                     u + 2 * n, out, g, span, flag);
+  return hipGetLastError();
+}
+
+template <int C>
+hipError_t launch_wp_c(bool even, const Geo& g, const float* phi, const float* u, float* out,
+                       int* flag, hipStream_t st, int bpc) {
+  constexpr WpConfig c = kWpConfigs[C];
+  return even ? launch_wp_t<true, c.V, c.W, c.WX>(g, phi, u, out, flag, st, bpc)
+              : launch_wp_t<false, c.V, c.W, c.WX>(g, phi, u, out, flag, st, bpc);
+}
+
+hipError_t launch_cec3d_wp(int config, bool even, const Geo& g, const float* phi, const float* u,
+                           float* out, int* flag, hipStream_t st, Cec3dLaunch lc) {
+  // > 0: persistent, workgroups per CU; < 0: march chunk of -value planes,
+  // one workgroup per chunk of a group; 0: persistent, as many as fit
+  const int bpc = lc.ychunk;
+  switch (config) {
+    case 0: return launch_wp_c<0>(even, g, phi, u, out, flag, st, bpc);
+    case 1: return launch_wp_c<1>(even, g, phi, u, out, flag, st, bpc);
+    case 2: return launch_wp_c<2>(even, g, phi, u, out, flag, st, bpc);
+    case 3: return launch_wp_c<3>(even, g, phi, u, out, flag, st, bpc);
+    case 4: return launch_wp_c<4>(even, g, phi, u, out, flag, st, bpc);
+    case 5: return launch_wp_c<5>(even, g, phi, u, out, flag, st, bpc);
+  }
+  return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------------
+// Several fields sharing one velocity (K per launch): the shared-halo window
+// march of variant 7 with the velocity loaded once per tile for all K
+// fields.  Per march plane a workgroup loads the velocity rows its tile
+// needs and forms the Courant numbers once; then, field after field, it
+// loads the field's rows, runs its first sweep, exchanges the rows through
+// LDS (one barrier per field and plane, the LDS buffers alternating along
+// the sequence of fields and planes), and runs the segment sweep and the
+// march step on that field's own register pipeline.  A field's value at a
+// node goes through the same FP32 operations as in the single-field kernels,
+// so every field ends bit for bit as if advanced alone.
+// ---------------------------------------------------------------------------
+constexpr int kMfMax = 4;
+struct MfFields {
+  const float* in[kMfMax];
+  float* out[kMfMax];
+};
+
+template <bool EVEN, int V, int W, int WX, int K>
+__global__ __launch_bounds__(64 * W * WX) void k_cec3d_mf(MfFields fl, const float* __restrict__ ux,
+                                                          const float* __restrict__ uy,
+                                                          const float* __restrict__ uz, Geo g,
+                                                          int chunk, int* flag) {
+  constexpr int S = V * W, NR = S + 6, RW = (NR + W - 1) / W, kAll = NR - (W - 1) * RW;
+  __shared__ float lp[2][WX][NR][64];  // a field's segment sweep input (x-swept if even)
+  __shared__ float lc[2][WX][NR][64];  // segment-axis Courant numbers of a plane
+  const int lane = threadIdx.x & 63, xi = (threadIdx.x >> 6) % WX, w = (threadIdx.x >> 6) / WX;
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  const int ns = EVEN ? ny : nz, nm = EVEN ? nz : ny;
+  const int nwx = (nx + kWmUse - 1) / kWmUse, ngx = (nwx + WX - 1) / WX, ngs = (ns + S - 1) / S;
+  const int nch = (nm + chunk - 1) / chunk;
+  const int blk = block_tile(1).x;  // 1D grid, XCD-mapped
+  if (blk >= ngx * ngs * nch) return;  // the whole workgroup
+  const int wx0 = (blk % ngx) * WX, gs = (blk / ngx) % ngs, ch = blk / (ngx * ngs);
+  const bool wx_ok = wx0 + xi < nwx;  // the same for the whole wave
+  const int wx = min(wx0 + xi, nwx - 1);
+  const unsigned vx = 4u * unsigned(wrapk(wx * kWmUse - 3 + lane, nx));
+  const unsigned rowb = 4u * unsigned(nx), plb = 4u * unsigned(nx) * unsigned(ny);
+  const unsigned sstr = EVEN ? rowb : plb, mstr = EVEN ? plb : rowb;
+  const int g0 = gs * S, s0 = g0 + w * V, m0 = ch * chunk, m1 = min(m0 + chunk, nm);
+  const int nld = min(RW, NR - w * RW);
+  unsigned loff[RW], ooff[V];
+#pragma unroll
+  for (int k = 0; k < RW; ++k)
+    loff[k] = vx + unsigned(__builtin_amdgcn_readfirstlane(wrapk(g0 - 3 + w * RW + k, ns))) * sstr;
+#pragma unroll
+  for (int j = 0; j < V; ++j)
+    ooff[j] = vx + unsigned(__builtin_amdgcn_readfirstlane(wrapk(s0 + j, ns))) * sstr;
+  const float* rS = EVEN ? uy : uz;  // segment-axis velocity
+  const float* rM = EVEN ? uz : uy;  // march-axis velocity
+  const float lamX = g.lam[0], lamS = EVEN ? g.lam[1] : g.lam[2], lamM = EVEN ? g.lam[2] : g.lam[1];
+  PlaneWin pw(m0 - 6, nm);  // planes m0 - 6 + t .. m0 - 2 + t at iteration t
+
+  float fp[K][RW], fa[RW], fs[RW];  // fields, x velocity (even), segment velocity: loaded rows
+  float fm[V], fx[V];               // march velocity of plane q-1; odd: x velocity of the output plane
+  auto prefetch = [&](int ahead) {  // 0: iteration t; 1: iteration t + 1
+    const unsigned q = unsigned(pw.p[3 + ahead]) * mstr, qm1 = unsigned(pw.p[2 + ahead]) * mstr,
+                   qo = unsigned(pw.p[ahead]) * mstr;
+#pragma unroll
+    for (int k = 0; k < RW; ++k) {
+      if (k < kAll || k < nld) {
+        if (EVEN) fa[k] = ld_vs(ux, loff[k], q);
+        fs[k] = ld_vs(rS, loff[k], q);
+#pragma unroll
+        for (int f = 0; f < K; ++f) fp[f][k] = ld_vs(fl.in[f], loff[k], q);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+      fm[j] = ld_vs(rM, ooff[j], qm1);
+      if (!EVEN) fx[j] = ld_vs(ux, ooff[j], qo);
+    }
+  };
+
+  // per field: rings of the march pipeline; the Courant ring is shared
+  float ra[K][3][V], r1[K][3][V], re[K][3][V], rc[3][V];
+#pragma unroll
+  for (int j = 0; j < V; ++j)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      rc[k][j] = 0.f;
+#pragma unroll
+      for (int f = 0; f < K; ++f) ra[f][k][j] = r1[f][k][j] = re[f][k][j] = 0.f;
+    }
+
+  const int iters = (m1 - m0) + 6;
+  const bool lane_out = lane >= 3 && lane < 61 && wx * kWmUse + lane - 3 < nx;
+  bool over = false;
+  if (wx_ok) prefetch(0);
+  auto body = [&](auto phase, int t) {
+    constexpr int P0 = decltype(phase)::value;
+    if (!wx_ok) {  // a window past the row's end: barriers only
+#pragma unroll
+      for (int f = 0; f < K; ++f) __syncthreads();
+      return;
+    }
+    // the velocity part of this plane, shared by the fields
+    float cxr[RW], cm[V], cxo[V];
+    float pv[K][RW];
+#pragma unroll
+    for (int k = 0; k < RW; ++k) {
+      if (k < kAll || k < nld) {
+        if (EVEN) {
+          cxr[k] = fa[k] * lamX;
+          over |= over1(cxr[k]);
+        }
+        const float c = fs[k] * lamS;
+        over |= over1(c);
+        lc[t & 1][xi][w * RW + k][lane] = c;
+#pragma unroll
+        for (int f = 0; f < K; ++f) pv[f][k] = fp[f][k];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+      cm[j] = fm[j] * lamM;
+      over |= over1(cm[j]);
+      cxo[j] = EVEN ? 0.f : fx[j] * lamX;
+      if (!EVEN) over |= over1(cxo[j]);
+    }
+    if (t + 1 < iters) prefetch(1);
+#pragma unroll
+    for (int f = 0; f < K; ++f) {
+      const int bf = (t * K + f) & 1;
+#pragma unroll
+      for (int k = 0; k < RW; ++k) {
+        if (k < kAll || k < nld) {
+          float v = pv[f][k];
+          if (EVEN) v = xsweep_lanes(v, cxr[k]);  // first sweep (x) of this row
+          lp[bf][xi][w * RW + k][lane] = v;
+        }
+      }
+      __syncthreads();
+      float p[V + 6], cs[V + 4], a[V], o[V];
+#pragma unroll
+      for (int k = 0; k < V + 6; ++k) p[k] = lp[bf][xi][w * V + k][lane];
+#pragma unroll
+      for (int k = 0; k < V + 4; ++k) cs[k] = lc[t & 1][xi][w * V + 1 + k][lane];
+      // sweep along the segment axis (second for even, first for odd)
+      sweep_segment<V>(p, cs, a, flag);
+      // sweep along the march axis (even: last; odd: second); the Courant
+      // ring advances with the first field only
+      if (f == 0) {
+        march_step<V, P0>(ra[0], r1[0], re[0], rc, a, cm, o);
+      } else {
+        float rcf[3][V];
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+          for (int j = 0; j < V; ++j) rcf[k][j] = rc[k][j];
+        // rc already holds this plane's entry: march_step writes the same
+        // value into its own copy
+        march_step<V, P0>(ra[f], r1[f], re[f], rcf, a, cm, o);
+      }
+      if (t >= 6) {
+        const unsigned qo = unsigned(pw.p[0]) * mstr;
+        if (!EVEN)
+#pragma unroll
+          for (int j = 0; j < V; ++j) o[j] = xsweep_lanes(o[j], cxo[j]);  // last sweep (x)
+        store_rows<V>(fl.out[f], ooff, qo, o, lane_out, ns - s0);
+      }
+    }
+    pw.advance();
+  };
+  for (int t = 0; t < iters; t += 3) {
+    body(std::integral_constant<int, 0>{}, t);
+    if (t + 1 < iters) body(std::integral_constant<int, 1>{}, t + 1);
+    if (t + 2 < iters) body(std::integral_constant<int, 2>{}, t + 2);
+  }
+  if (over) *flag = 1;
+}
+
+// Multi-field launch shapes: (V, W, WX) per field count.
+template <int K>
+struct MfShape;
+template <>
+struct MfShape<1> {
+  static constexpr int V = 8, W = 2, WX = 3;
+};
+template <>
+struct MfShape<2> {
+  static constexpr int V = 4, W = 4, WX = 3;
+};
+template <>
+struct MfShape<4> {
+  static constexpr int V = 4, W = 4, WX = 2;
+};
+
+template <int K>
+hipError_t launch_mf_k(bool even, const Geo& g, const MfFields& fl, const float* u, int* flag,
+                       hipStream_t st, int chunk) {
+  using Sh = MfShape<K>;
+  constexpr int S = Sh::V * Sh::W;
+  const size_t n = (size_t)g.ncells;
+  const int ns = even ? g.ny : g.nz, nm = even ? g.nz : g.ny;
+  const long long groups =
+      (long long)(((g.nx + kWmUse - 1) / kWmUse + Sh::WX - 1) / Sh::WX) * ((ns + S - 1) / S);
+  if (chunk <= 0) {
+    chunk = 16;
+    for (int c : {64, 32})
+      if (groups * ((nm + c - 1) / c) >= 512) { chunk = c; break; }
+  }
+  dim3 grid(unsigned(groups * ((nm + chunk - 1) / chunk)));
+  if (even)
+    hipLaunchKernelGGL((k_cec3d_mf<true, Sh::V, Sh::W, Sh::WX, K>), grid, dim3(64 * Sh::W * Sh::WX),
+                       0, st, fl, u, u + n, u + 2 * n, g, chunk, flag);
+  else
+    hipLaunchKernelGGL((k_cec3d_mf<false, Sh::V, Sh::W, Sh::WX, K>), grid, dim3(64 * Sh::W * Sh::WX),
+                       0, st, fl, u, u + n, u + 2 * n, g, chunk, flag);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Overlapped variant: 320-thread workgroups (5 waves) and two barriers per
 // plane.  Phase A: every wave runs the y pipeline on the first-sweep output
 // of the previous plane, then publishes the prefetched inputs of the next
@@ -1728,6 +2178,22 @@ int cec3d_default_ychunk(const Geo& g) {
   return tiles * ((g.ny + 63) / 64) >= 1024 ? 64 : 32;
 }
 
+hipError_t launch_cec3d_multi(int k, bool even, const Geo& g, const float* const* in,
+                              float* const* out, const float* u, int* flag, hipStream_t st,
+                              int chunk) {
+  MfFields fl = {};
+  for (int f = 0; f < k && f < kMfMax; ++f) {
+    fl.in[f] = in[f];
+    fl.out[f] = out[f];
+  }
+  switch (k) {
+    case 1: return launch_mf_k<1>(even, g, fl, u, flag, st, chunk);
+    case 2: return launch_mf_k<2>(even, g, fl, u, flag, st, chunk);
+    case 4: return launch_mf_k<4>(even, g, fl, u, flag, st, chunk);
+  }
+  return hipErrorInvalidValue;
+}
+
 hipError_t launch_cec3d(int variant, bool even, const Geo& g, const float* phi, const float* u,
                         float* out, int* flag, hipStream_t st, Cec3dLaunch lc) {
   if (variant == 1) return launch_cec3d_seg(even, g, phi, u, out, flag, st, lc);
@@ -1735,6 +2201,8 @@ hipError_t launch_cec3d(int variant, bool even, const Geo& g, const float* phi, 
   if (variant == 4) return launch_cec3d_wm<4>(even, g, phi, u, out, flag, st, lc);
   if (variant == 6) return launch_cec3d_wm<8>(even, g, phi, u, out, flag, st, lc);
   if (variant == 7) return launch_cec3d_wl(even, g, phi, u, out, flag, st, lc);
+  if (variant >= 8 && variant < 8 + kWpCount)
+    return launch_cec3d_wp(variant - 8, even, g, phi, u, out, flag, st, lc);
   if (variant == 5) {
     // the fastest implementation of each parity as measured from 256^3 to
     // 1024^3: up to 2^24 cells, register segments for even steps and the

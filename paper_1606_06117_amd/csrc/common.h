@@ -68,9 +68,9 @@ hipError_t launch_cec_sweep_xy(int R, bool xfirst, const Geo& g, const float* ph
 // (direct global-to-LDS loads), 3 overlapped first/last sweeps, 4 window
 // march with 4-row segments (no LDS), 5 the fastest of these per parity
 // and grid size, 6 window march with 8-row segments, 7 window march whose
-// workgroups share segment halos through LDS; all perform the same FP32
-// operations.
-constexpr int kCec3dVariants = 8;
+// workgroups share segment halos through LDS, 8.. the persistent form of 7
+// in several group shapes; all perform the same FP32 operations.
+constexpr int kCec3dVariants = 14;
 // Launch shape: y planes per workgroup (0: the default for the grid) and
 // whether tiles are mapped to XCDs in contiguous ranges (1) or round robin.
 struct Cec3dLaunch {
@@ -78,6 +78,13 @@ struct Cec3dLaunch {
   int swizzle = 1;
 };
 int cec3d_default_ychunk(const Geo& g);
+// The fused step of k = 1, 2 or 4 fields sharing the velocity u (reach 1):
+// in[f] -> out[f]; the velocity is loaded once per tile for the k fields.
+// Every field's result equals launch_cec3d's bit for bit.  chunk: march
+// planes per workgroup (0: the default).
+hipError_t launch_cec3d_multi(int k, bool even, const Geo& g, const float* const* in,
+                              float* const* out, const float* u, int* flag, hipStream_t st,
+                              int chunk = 0);
 hipError_t launch_cec3d(int variant, bool even, const Geo& g, const float* phi, const float* u,
                         float* out, int* flag, hipStream_t st, Cec3dLaunch lc = Cec3dLaunch());
 
@@ -107,6 +114,10 @@ hipError_t launch_make_pairs(const Geo& g, const float* phi1, const float* phi_n
                              hipStream_t st);
 hipError_t launch_learned_correct(const Geo& g, const float* phi1, const float* u, const void* wpack,
                                   const float* wr, float* out, hipStream_t st);
+// The same correction as a march along z (LDS-staged neighbourhoods, one
+// node per lane for the features); same results bit for bit.
+hipError_t launch_learned_march(const Geo& g, const float* phi1, const float* u, const void* wpack,
+                                const float* wr, float* out, hipStream_t st);
 
 // Segment variant of the same step (identical arithmetic per node).
 hipError_t launch_cec3d_seg(bool even, const Geo& g, const float* phi, const float* u, float* out,

@@ -27,6 +27,34 @@ namespace {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef unsigned uintx4 __attribute__((ext_vector_type(4)));
+
+// Two values rounded to BF16 (to nearest, ties to even) in one register, lo
+// in bits 0-15: written this way the pair becomes one conversion
+// instruction (element-wise insertion into a wider vector does not).
+__device__ __forceinline__ unsigned cvt_pk_bf16(float lo, float hi) {
+  const bf16x2 v = {(__bf16)lo, (__bf16)hi};
+  return __builtin_bit_cast(unsigned, v);
+}
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+// ReLU of two packed BF16 values: a signed 16-bit maximum with 0 of each bit
+// pattern (negative values and -0 become +0).  On rounded values it equals
+// rounding after ReLU for every non-NaN value.  The empty asm statement
+// keeps the compiler from splitting the paired conversion that produced v
+// into two single ones.
+__device__ __forceinline__ unsigned relu_pk(unsigned v) {
+  asm("" : "+v"(v));
+  return __builtin_bit_cast(unsigned, __builtin_elementwise_max(__builtin_bit_cast(s16x2, v), s16x2{}));
+}
+
+// max(v, 0) as a signed integer maximum of the bit pattern with 0: negative
+// values (sign bit set) and -0 become +0, the rest stay.  The same value as
+// fmaxf(v, 0.f) for every non-NaN v, in one instruction (fmaxf also
+// quiets a possible signalling NaN first, one more instruction).
+__device__ __forceinline__ float relu_bits(float v) {
+  return __builtin_bit_cast(float, max(__builtin_bit_cast(int, v), 0));
+}
 
 constexpr int kThreads = 256;
 constexpr int NF = kMlpInputs, NH = kMlpHidden;
@@ -692,6 +720,246 @@ __global__ __launch_bounds__(kThreads) void k_learned_correct(const float* __res
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// Learned step, second half, as a march along z (the default).  A workgroup
+// of kLmRows waves owns a window of 64 consecutive x by kLmRows rows of y and
+// marches along z through a chunk of planes.  Every plane of the CIR field
+// is staged in LDS over the window plus one node on each side and the rows
+// plus one on each side (a ring of 4 planes, so one barrier per plane); each
+// lane then builds the features of one node from the 27 staged values
+// around it.  The features reach the matrix-core operand layout through a
+// per-wave LDS tile, and the network runs on the wave's 64 nodes at once.
+//
+// The hidden units of the first layer are computed in a permuted row order
+// (W1's columns and b1 are permuted when they are staged): matrix-core tile
+// `it` row 4g + q of the first layer holds hidden unit
+// 32 (it / 2) + 8 g + 4 (it % 2) + q, which is exactly the unit lane (g, c)
+// supplies as operand element j = 4 (it % 2) + q of the second layer's
+// K-block it / 2.  So the first layer's results feed the second layer from
+// the lanes that hold them: no exchange through LDS.  Row permutations do
+// not change how any one output is accumulated, so per node the FP32
+// operations and their order are those of k_learned_correct: the same
+// results bit for bit.
+// ---------------------------------------------------------------------------
+constexpr int kLmRows = 4, kLmX = 64, kLmW = kLmX + 2, kLmH = kLmRows + 2, kLmRing = 4;
+constexpr int kLmThreads = 64 * kLmRows;
+struct MarchLds {
+  __bf16 w1t[NH * SF];  // permuted rows (see above)
+  __bf16 w2t[NH * SH];
+  float b1[NH];         // permuted like W1's rows
+  float b2[NH], w3[NH], b3;
+  __bf16 feat[kLmRows][64 * SF];
+  float phi[kLmRing][kLmH][kLmW];
+};
+static_assert(offsetof(MarchLds, b1) % 16 == 0 && offsetof(MarchLds, b2) % 16 == 0,
+              "bias rows must be 16-byte aligned");
+
+// Hidden unit computed by permuted first-layer row r.
+__device__ __forceinline__ int lm_unit(int r) {
+  const int it = r / 16, g = (r % 16) / 4, q = r % 4;
+  return 32 * (it / 2) + 8 * g + 4 * (it % 2) + q;
+}
+
+// Buffer access at a per-lane byte offset voff from the row that starts soff
+// bytes into the field (soff the same for the whole wave): the descriptor is
+// rebased on the row (two scalar adds) and has the largest size a descriptor
+// holds, so voff alone is range-checked.
+__device__ __forceinline__ Rsrc row_rsrc(const float* field, unsigned soff) {
+  const size_t off = unsigned(__builtin_amdgcn_readfirstlane(int(soff)));
+  const char* b = reinterpret_cast<const char*>(field) + off;
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(b), short(0), int(0xFFFFFFFFu), 0x00020000);
+}
+__device__ __forceinline__ float ld_row(const float* field, unsigned voff, unsigned soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(row_rsrc(field, soff), voff, 0, 0));
+}
+__device__ __forceinline__ void st_row(float* field, unsigned voff, unsigned soff, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), row_rsrc(field, soff), voff,
+                                        0, 0);
+}
+
+// wrap any coordinate into [0, n)
+__device__ __forceinline__ int wrapk(int v, int n) {
+  v %= n;
+  return v < 0 ? v + n : v;
+}
+
+__global__ __launch_bounds__(kLmThreads, 3) void k_learned_march(const float* __restrict__ phi1,
+                                                              const float* __restrict__ ux,
+                                                              const float* __restrict__ uy,
+                                                              const float* __restrict__ uz, Geo geo,
+                                                              const __bf16* __restrict__ wpack,
+                                                              const float* __restrict__ wr,
+                                                              float* __restrict__ out, int chunk) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  MarchLds& L = *reinterpret_cast<MarchLds*>(smem);
+  for (int i = threadIdx.x; i < NH * NF; i += kLmThreads) {
+    const int r = i / NF, k = i % NF;
+    L.w1t[r * SF + k] = wpack[lm_unit(r) * NF + k];
+  }
+  for (int i = threadIdx.x; i < NH * NH; i += kLmThreads)
+    L.w2t[(i / NH) * SH + i % NH] = wpack[NH * NF + i];
+  for (int i = threadIdx.x; i < NH; i += kLmThreads) {
+    L.b1[i] = wr[B1_OFF + lm_unit(i)];
+    L.b2[i] = wr[B2_OFF + i];
+    L.w3[i] = wr[W3_OFF + i];
+  }
+  if (threadIdx.x == 0) L.b3 = wr[B3_OFF];
+  const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15, w = threadIdx.x >> 6;
+  const int nx = geo.nx, ny = geo.ny, nz = geo.nz;
+  const int nwx = (nx + kLmX - 1) / kLmX, nry = (ny + kLmRows - 1) / kLmRows;
+  const int b = blockIdx.x;
+  const int wx = b % nwx, ry = (b / nwx) % nry, ch = b / (nwx * nry);
+  const int x0 = wx * kLmX, y0 = ry * kLmRows, z0 = ch * chunk, z1 = min(z0 + chunk, nz);
+  // Global accesses: a byte offset per lane (its x) and a row offset that is
+  // the same for the whole wave (scalar registers); fields of at most 2^30
+  // cells keep both below 2^32.
+  const unsigned rowb = 4u * unsigned(nx);
+  // this lane's x (wrapped, so the lanes past a short row hold the nodes
+  // that follow it periodically) and the two halo nodes (lanes 0 and 1)
+  const unsigned vxl = 4u * unsigned(wrapk(x0 + lane, nx));
+  const unsigned vxh = 4u * unsigned(lane == 0 ? wrapk(x0 - 1, nx) : wrapk(x0 + kLmX, nx));
+  // staged rows: wave w loads row w of y0 - 1 .. y0 + kLmRows, waves 0 and 1
+  // also rows kLmRows and kLmRows + 1
+  int srow[2];
+  srow[0] = __builtin_amdgcn_readfirstlane(wrapk(y0 - 1 + w, ny));
+  srow[1] = __builtin_amdgcn_readfirstlane(wrapk(y0 - 1 + w + kLmRows, ny));
+  const int nsr = w + kLmRows < kLmH ? 2 : 1;
+  const int y = y0 + w;  // this wave's output row
+  const bool lane_ok = y < ny && x0 + lane < nx;
+  const int yc = __builtin_amdgcn_readfirstlane(min(y, ny - 1));
+  float pre[2], preh[2];
+  auto fetch = [&](int zp) {  // the staged rows of plane zp (wrapped)
+    const unsigned pz = unsigned(__builtin_amdgcn_readfirstlane(wrapk(zp, nz))) * unsigned(ny);
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      if (r < nsr) {
+        const unsigned row = (pz + unsigned(srow[r])) * rowb;
+        pre[r] = ld_row(phi1, vxl, row);
+        preh[r] = lane < 2 ? ld_row(phi1, vxh, row) : 0.f;
+      }
+    }
+  };
+  auto stage = [&](int slot) {
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      if (r < nsr) {
+        float* dst = L.phi[slot][w + kLmRows * r];
+        dst[lane + 1] = pre[r];
+        if (lane == 0) dst[0] = preh[r];
+        if (lane == 1) dst[kLmW - 1] = preh[r];
+      }
+    }
+  };
+  // planes z0 - 1 and z0 in slots 0 and 1; plane z0 + 1 in flight
+  fetch(z0 - 1);
+  stage(0);
+  fetch(z0);
+  stage(1);
+  fetch(z0 + 1);
+  __syncthreads();  // the weights
+  float w3r[4][4];  // w3 of the second layer's outputs this lane holds
+#pragma unroll
+  for (int it = 0; it < 4; ++it)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) w3r[it][q] = L.w3[16 * it + 4 * g + q];
+  const float b3 = L.b3;
+  __bf16* feat = L.feat[w];
+  for (int z = z0; z < z1; ++z) {
+    const int t = z - z0;  // plane z sits in slot (t + 1) % 4
+    stage((t + 2) % kLmRing);  // plane z + 1
+    fetch(z + 2);              // in flight while this plane's nodes run
+    // node velocity of this lane (only its Courant numbers are features)
+    const unsigned rowz = (unsigned(z) * unsigned(ny) + unsigned(yc)) * rowb;
+    const float cx = ld_row(ux, vxl, rowz) * geo.lam[0], cy = ld_row(uy, vxl, rowz) * geo.lam[1],
+                cz = ld_row(uz, vxl, rowz) * geo.lam[2];
+    __syncthreads();
+    // the 27 values around this lane's node: slots of planes z-1, z, z+1,
+    // staged rows w .. w + 2, x positions lane .. lane + 2
+    float val[27];
+#pragma unroll
+    for (int dz = 0; dz < 3; ++dz) {
+      const float* sp = &L.phi[(t + dz) & (kLmRing - 1)][w][lane];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) val[9 * dz + k] = sp[(k / 3) * kLmW + k % 3];
+    }
+    const float centre = val[13];
+    float lo = centre, hi = centre, ssg[4], d[27];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      ssg[q] = 0.f;
+#pragma unroll
+      for (int v = 0; v < 8; ++v) {
+        const int k = 8 * q + v;
+        if (k < 27) {
+          lo = fminf(lo, val[k]);
+          hi = fmaxf(hi, val[k]);
+          d[k] = val[k] - centre;
+          ssg[q] = fmaf(d[k], d[k], ssg[q]);
+        }
+      }
+    }
+    const float ss = (ssg[0] + ssg[1]) + (ssg[2] + ssg[3]);
+    const float sigma = sqrtf(ss / 27.f + 1e-30f);
+    const float inv = 1.f / sigma;
+    float fv[32];
+#pragma unroll
+    for (int k = 0; k < 32; ++k) {
+      fv[k] = 0.f;
+      if (k < 27) fv[k] = d[k] * inv;
+      else if (k == 27) fv[k] = cx;
+      else if (k == 28) fv[k] = cy;
+      else if (k == 29) fv[k] = cz;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      uintx4 fx;
+#pragma unroll
+      for (int h = 0; h < 4; ++h) fx[h] = cvt_pk_bf16(fv[8 * q + 2 * h], fv[8 * q + 2 * h + 1]);
+      *reinterpret_cast<uintx4*>(&feat[lane * SF + 8 * q]) = fx;
+    }
+    wave_lds_sync();
+    bf16x8 xb[4];  // node tile jt: features 8g..8g+7 of node 16 jt + c
+#pragma unroll
+    for (int jt = 0; jt < 4; ++jt) xb[jt] = ld8(&feat[(16 * jt + c) * SF + 8 * g]);
+    // layer 1 (permuted rows), BF16, ReLU: the second layer's operands in place
+    uintx4 h1[4][2];
+#pragma unroll
+    for (int it = 0; it < 4; ++it) {
+      const bf16x8 a = ld8(&L.w1t[(16 * it + c) * SF + 8 * g]);
+      const floatx4 bias = *reinterpret_cast<const floatx4*>(&L.b1[16 * it + 4 * g]);
+#pragma unroll
+      for (int jt = 0; jt < 4; ++jt) {
+        const floatx4 acc = mfma(a, xb[jt], bias);
+        h1[jt][it / 2][2 * (it % 2)] = relu_pk(cvt_pk_bf16(acc[0], acc[1]));
+        h1[jt][it / 2][2 * (it % 2) + 1] = relu_pk(cvt_pk_bf16(acc[2], acc[3]));
+      }
+    }
+    // layer 2, ReLU, and the output layer's dot product
+    float s[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int it = 0; it < 4; ++it) {
+      const bf16x8 a0 = ld8(&L.w2t[(16 * it + c) * SH + 8 * g]);
+      const bf16x8 a1 = ld8(&L.w2t[(16 * it + c) * SH + 32 + 8 * g]);
+      const floatx4 bias = *reinterpret_cast<const floatx4*>(&L.b2[16 * it + 4 * g]);
+#pragma unroll
+      for (int jt = 0; jt < 4; ++jt) {
+        floatx4 acc = mfma(a0, __builtin_bit_cast(bf16x8, h1[jt][0]), bias);
+        acc = mfma(a1, __builtin_bit_cast(bf16x8, h1[jt][1]), acc);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) s[jt] = fmaf(relu_bits(acc[q]), w3r[it][q], s[jt]);
+      }
+    }
+    // y of node 16 jt + c, summed over the four lanes that hold the node;
+    // node `lane` (jt = g) is then on this lane
+    float yv[4];
+#pragma unroll
+    for (int jt = 0; jt < 4; ++jt) yv[jt] = sum4g(s[jt]) + b3;
+    const float yn = g == 0 ? yv[0] : g == 1 ? yv[1] : g == 2 ? yv[2] : yv[3];
+    if (lane_ok) st_row(out, vxl, rowz, fminf(fmaxf(fmaf(sigma, yn, centre), lo), hi));
+    wave_lds_sync();  // the feature tile is rewritten at the next plane
+  }
+}
 }  // namespace
 
 size_t mlp_train_lds() { return sizeof(TrainLds); }
@@ -752,6 +1020,25 @@ hipError_t launch_make_pairs(const Geo& g, const float* phi1, const float* phi_n
   const int nblk = (m + 63) / 64;
   hipLaunchKernelGGL(k_make_pairs, dim3(nblk), dim3(kThreads), 0, st, phi1, phi_next, u, u + n,
                      u + 2 * n, g, cells, m, static_cast<__bf16*>(X), target, sigma);
+  return hipGetLastError();
+}
+
+hipError_t launch_learned_march(const Geo& g, const float* phi1, const float* u, const void* wpack,
+                                const float* wr, float* out, hipStream_t st) {
+  const size_t n = (size_t)g.ncells;
+  // row offsets are 32-bit: fields of 2^30 cells take the gather
+  if (n >= (size_t(1) << 30)) return launch_learned_correct(g, phi1, u, wpack, wr, out, st);
+  const int bytes = int(sizeof(MarchLds));
+  static hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(k_learned_march),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (attr != hipSuccess) return attr;
+  const long long cols = (long long)((g.nx + kLmX - 1) / kLmX) * ((g.ny + kLmRows - 1) / kLmRows);
+  // march chunks of 32 planes, or shorter if that leaves under 2048 workgroups
+  int chunk = 32;
+  while (chunk > 8 && cols * ((g.nz + chunk - 1) / chunk) < 2048) chunk /= 2;
+  const long long blocks = cols * ((g.nz + chunk - 1) / chunk);
+  hipLaunchKernelGGL(k_learned_march, dim3(unsigned(blocks)), dim3(kLmThreads), bytes, st, phi1, u,
+                     u + n, u + 2 * n, g, static_cast<const __bf16*>(wpack), wr, out, chunk);
   return hipGetLastError();
 }
 

@@ -26,6 +26,9 @@ OPT_CEC3D_KERNEL = 1
 CEC3D_DEFAULT = 5  # the library's default fused-step implementation
 OPT_SWEEP_KERNEL = 2
 OPT_EC_KERNEL = 3
+OPT_CEC3D_SHAPE = 4
+OPT_LEARNED_KERNEL = 5
+OPT_SHARED_VELOCITY = 6
 
 # every symbol include/sla.h declares, with (restype, argtypes)
 _c = ctypes

@@ -49,15 +49,19 @@ def test_strerror_and_null_handling():
 
 
 def test_workspace_size():
-    """One FP32 field of the grid, whatever the scheme and the number of
-    scalars; 0 for an invalid grid or scheme."""
+    """One FP32 field of the grid, and for third order in 3D one per field up
+    to four (shared-velocity groups); 0 for an invalid grid or scheme."""
     import ctypes
     from paper_1606_06117_amd import native
     lib = native.load()
     g = native.make_grid((12, 34, 56), (0.1, 0.1, 0.1))
+    field = 4 * 12 * 34 * 56
     for scheme in range(7):
-        for ns in (1, 16):
-            assert lib.sla_workspace_size(ctypes.byref(g), scheme, ns) == 4 * 12 * 34 * 56
+        for ns in (1, 2, 3, 16):
+            want = field * (min(ns, 4) if scheme == native.CEC else 1)
+            assert lib.sla_workspace_size(ctypes.byref(g), scheme, ns) == want
+    g2 = native.make_grid((34, 56), (0.1, 0.1))
+    assert lib.sla_workspace_size(ctypes.byref(g2), native.CEC, 16) == 4 * 34 * 56
     assert lib.sla_workspace_size(ctypes.byref(g), 7, 1) == 0
     assert lib.sla_workspace_size(ctypes.byref(g), 3, -1) == 0
     # grids of 2^31 cells or more, including extents whose product would

@@ -164,6 +164,36 @@ def test_make_pairs_match_oracle_features(ctx):
     assert np.allclose(target.cpu().numpy(), tr, rtol=1e-4, atol=1e-6 * np.max(np.abs(tr)))
 
 
+@pytest.mark.parametrize("shape", [(16, 20, 36), (9, 11, 40), (12, 14, 100), (70, 13, 130),
+                                   (33, 66, 64), (8, 8, 8)])
+def test_learned_march_matches_gather(ctx, shape):
+    """The z-march correction (staged neighbourhoods, one node per lane) and
+    the per-node gather give the same bits: same FP32 operations per node.
+    The shapes leave partial x windows and row groups, rows shorter than a
+    window, march chunks that do not divide the planes, and axes of 8."""
+    import torch
+    from paper_1606_06117_amd import native
+    phi = W.random_gaussians(shape, 4, seed=17).astype(np.float32)
+    u = W.abc_velocity(shape)
+    dx = tuple(2 * np.pi / n for n in reversed(shape))
+    dt = 0.9 * dx[0] / 2
+    model = native.Model(ctx)
+    model.set_params(he_params(15, scale=0.5))
+    model.set_courant_range(1.0)
+    res = []
+    for kern in (0, 1):
+        ctx.set_option(native.OPT_LEARNED_KERNEL, kern)
+        p = device(phi)
+        try:
+            assert not native.advect_learned(ctx, model, p, device(u), dx, dt, 2)
+        finally:
+            ctx.set_option(native.OPT_LEARNED_KERNEL, 1)
+        torch.cuda.synchronize()
+        res.append(p.cpu().numpy())
+    assert np.array_equal(res[0], res[1])
+    model.close()
+
+
 @pytest.mark.parametrize("shape", [(16, 20, 36), (9, 11, 40), (12, 14, 100)])
 def test_learned_step_matches_oracle(ctx, shape):
     """(9, 11, 40) has 198 row tiles: the last group of four leaves idle
