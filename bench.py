@@ -128,6 +128,54 @@ def cpu_all_cores(phi, u, dx, dt, scheme, edge, zedge, steps, workers):
     }
 
 
+def cpu_scheme_parity(ctx, size, cfl, steps, workers):
+    """Every scheme's error against the FP64 oracle on a whole workload.
+
+    The 3D problem of 8 Gaussians under the ABC flow at ``size``^3 and CFL
+    ``cfl``: each scheme runs ``steps`` steps on the GPU and in the oracle
+    (over z-slabs in ``workers`` processes, the one-process result bit for
+    bit), and the two results are compared on every cell: relative L2, and
+    max |gpu - oracle| relative to max |phi0|.  The oracle's wall time is
+    reported with it (FP64 NumPy, same unit as the GPU figures).
+    """
+    import numpy as np
+    import torch
+    from oracle import norms as onorms
+    from oracle import slabs
+    from paper_1606_06117_amd import native
+    from paper_1606_06117_amd import workloads as W
+    shape = (size,) * 3
+    phi0 = W.random_gaussians(shape, 8, seed=2000).astype(np.float32)
+    u = W.abc_velocity(shape)
+    dx = (2 * math.pi / size,) * 3
+    dt = W.abc_dt(shape, cfl)
+    dev = torch.device("cuda:0")
+    ud = torch.from_numpy(u).to(dev)
+    scale = float(np.max(np.abs(phi0)))
+    rows = []
+    for name in ("cir", "fec", "bec", "cec"):
+        p = torch.from_numpy(phi0).to(dev)
+        ctx.advect(p, ud, dx, dt, native.SCHEMES[name], steps)
+        torch.cuda.synchronize()
+        ctx.check()
+        got = p.cpu().numpy().astype(np.float64)
+        with slabs.SlabPool(u, dx, dt, native.SCHEMES[name], workers) as pool:
+            t0 = time.perf_counter()
+            ref = pool.advect(phi0, steps)
+            wall = time.perf_counter() - t0
+            used = pool.workers
+        rows.append({"scheme": name, "relL2_vs_oracle": onorms.rel_l2(got, ref),
+                     "linf_vs_oracle_rel": onorms.linf(got, ref) / scale,
+                     "bound_relL2": 1e-5 * steps,
+                     "oracle_seconds": round(wall, 2), "oracle_processes": used,
+                     "oracle_gcell_updates_per_s": size**3 * steps / wall / 1e9})
+    del ud
+    torch.cuda.empty_cache()
+    return {"workload": f"{size}^3, 8 Gaussians (seed 2000), ABC velocity, CFL {cfl}, {steps} steps "
+                        f"per scheme; GPU FP32 against the FP64 oracle on every cell",
+            "runs": rows}
+
+
 def copy_probe(reps: int, warmup: int) -> int:
     """Copy a 512 MiB FP32 buffer ``reps`` times (read 512 MiB + write 512 MiB each)."""
     import torch
@@ -332,7 +380,11 @@ def large_section(ctx, size, cfl, steps):
             "ms_per_step": wall * 1e3 / steps, "courant_max": cmax,
             "hbm_frac_step": 20 * upd / wall / (HBM_PEAK_GBS * 1e9),
             "per_kind_ms": {k: round(v[1] / v[0], 4) for k, v in times.items()},
-            "input_build_seconds": build}
+            "input_build_seconds": build,
+            "learned_variant": "not run: the network reads the CIR field's 3x3x3 neighbourhood, "
+                               "which holds the third-order stencil only at reach 1 (CFL < 1); "
+                               "at CFL 2.0 (reach 3) the learned step falls back to the plain "
+                               "third-order scheme by design, so its time would be this one"}
 
 
 def batch_section(ctx, size, scalars, ngrids, steps):
@@ -404,6 +456,12 @@ def main(argv=None):
                     help="processes of the all-core oracle figure (0: skip it)")
     ap.add_argument("--cpu-all-steps", type=int, default=20,
                     help="oracle steps of the all-core figure on a --size x edge x edge box")
+    ap.add_argument("--tune", choices=["on", "off"], default="on",
+                    help="run the library's fused-step tuner on the workload before timing")
+    ap.add_argument("--scheme-parity", choices=["on", "off"], default="on",
+                    help="with the all-core oracle: every scheme's error against it on the whole "
+                         "256^3 CFL 1.5 workload")
+    ap.add_argument("--parity-steps", type=int, default=50)
     ap.add_argument("--path", choices=["auto", "sweeps"], default="auto",
                     help="auto: fused step where the library has one; sweeps: one kernel per axis")
     ap.add_argument("--other-cfl", choices=["on", "off"], default="on",
@@ -458,6 +516,11 @@ def main(argv=None):
     ctx = native.Context(0)
     cmax = ctx.courant_max(u_d, dx, dt)
     ctx.set_option(native.OPT_FUSED, 0 if args.path == "sweeps" else 1)
+    tuned = None
+    if args.scheme == "cec" and args.path == "auto" and cmax < 1.0 and args.tune == "on":
+        # the library's tuner picks the fused-step implementation per parity
+        print("[bench] tuning the fused step ...", file=sys.stderr, flush=True)
+        tuned = ctx.tune(phi_d, u_d, dx, dt)
 
     for w in range(args.warmup):
         ctx.advect(phi_d, u_d, dx, dt, scheme, 1, step0=w, courant_max=cmax)
@@ -528,6 +591,7 @@ def main(argv=None):
         },
         "hbm_frac_step": hbm_frac_step,
         "roofline": roofline,
+        "tuned": tuned,
     }
 
     del phi_d, u_d
@@ -572,6 +636,15 @@ def main(argv=None):
             except Exception as exc:  # noqa: BLE001 - reported, not swallowed
                 traceback.print_exc()
                 out["cpu_baseline"]["all_cores"] = {"error": f"{type(exc).__name__}: {exc}"}
+        if args.cpu_workers > 0 and args.scheme_parity == "on":
+            try:
+                print(f"[bench] every scheme against the oracle at 256^3, CFL 1.5, "
+                      f"{args.parity_steps} steps ...", file=sys.stderr, flush=True)
+                out["cpu_baseline"]["scheme_parity_256"] = cpu_scheme_parity(
+                    ctx, 256, 1.5, args.parity_steps, args.cpu_workers)
+            except Exception as exc:  # noqa: BLE001 - reported, not swallowed
+                traceback.print_exc()
+                out["cpu_baseline"]["scheme_parity_256"] = {"error": f"{type(exc).__name__}: {exc}"}
     else:
         out["cpu_baseline"] = None
 

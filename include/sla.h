@@ -204,15 +204,15 @@ typedef enum {
    * axis.  Both paths perform the same FP32 operations per node. */
   SLA_OPT_FUSED = 0,
   /* Which implementation runs the fused step (same FP32 operations, same
-   * results): 0 LDS stages, 1 register segments, 2 streaming (direct
-   * global-to-LDS loads), 3 overlapped (first and last sweeps of
-   * neighbouring planes run at once on different waves), 4 window march (no
-   * LDS: x across lanes, 4-row segments of one axis in registers, the third
-   * axis along the march), 6 window march with 8-row segments, 7 window
-   * march whose workgroups (2 or 3 windows, 2 waves each) share the segment
-   * halo rows through LDS, 5 (default) the fastest of 1, 4, 6 and 7 for each
-   * parity and grid size (measured from 256^3 to 1024^3).  The batched plans
-   * always use 2. */
+   * results): 1 register segments, 2 streaming (direct global-to-LDS
+   * loads), 4 window march (no LDS: x across lanes, 4-row segments of one
+   * axis in registers, the third axis along the march), 6 window march with
+   * 8-row segments, 7 window march whose workgroups (2 or 3 windows, 2 waves
+   * each) share the segment halo rows through LDS, 8 the same with 16-row
+   * groups of 12 waves (in march chunks, or persistent), 5 (default) the
+   * choice sla_tune measured for the grid if the context has one, else the
+   * fastest of these for each parity and grid size as measured from 256^3
+   * to 1024^3. */
   SLA_OPT_CEC3D_KERNEL = 1,
   /* How the sweeps of a third-order step that is not fused run (same FP32
    * operations, same results): 2 (default) the x and y sweeps in one kernel
@@ -225,10 +225,12 @@ typedef enum {
    * (others run 0). */
   SLA_OPT_SWEEP_KERNEL = 2,
   /* How unsplit FEC and BEC steps run (same FP32 operations, same results):
-   * 0 all calls of a step in one kernel, with the intermediate fields in
-   * LDS; 1 one gather kernel per call (FEC: 2, BEC: 3), the intermediates
-   * through the work field (44 and 64 B per cell moved); 2 (default) as 1,
-   * the faster of the two at every size and Courant number measured. */
+   * 3 (default) on 3D grids at reach 1 (every |c| < 1; fewer than 2^30 cells
+   * or 2^30 with ny >= 2), all calls of a step in one z-march whose stages
+   * live in LDS rings (the field read once, written once), elsewhere as 2;
+   * 0 all calls of a step in one kernel of LDS tiles; 1 one gather kernel
+   * per call (FEC: 2, BEC: 3), the intermediates through the work field
+   * (44 and 64 B per cell moved); 2 as 1. */
   SLA_OPT_EC_KERNEL = 3,
   /* Launch shape of the fused step (same results whatever the value): the
    * planes a workgroup marches (variants 0-4, 6 and 7), or the workgroups
@@ -248,6 +250,29 @@ typedef enum {
 /* Set option `option` to `value`.  Returns SLA_EINVAL for an unknown option
  * or value. */
 int sla_set_option(sla_ctx *ctx, int option, int64_t value);
+
+/* Fused-step tuner.  Time every implementation of the fused third-order
+ * step (SLA_OPT_CEC3D_KERNEL values and launch shapes) on `grid` with the
+ * caller's field phi (read only; the launches write the context's work
+ * memory) and velocity u, for each parity of the sweep order, and keep the
+ * fastest per parity in the context: later third-order steps of this grid
+ * with SLA_OPT_CEC3D_KERNEL = 5 (the default) use them.  Every choice gives
+ * the same results.  If table_path is not NULL the choice is also written to
+ * that text file (one line per grid: nx ny nz, then variant, shape and ms of
+ * even and of odd steps; other grids' lines are kept).  The grid must be 3D
+ * with every Courant number below 1 (SLA_ECOURANT otherwise).  Synchronises
+ * the stream; allocates the work memory if the context has none. */
+int sla_tune(sla_ctx *ctx, const sla_grid *grid, const float *phi, const float *u, double dt,
+             const char *table_path);
+/* Read a table that sla_tune wrote into the context (its grids' choices
+ * replace any the context holds).  SLA_EINVAL for a missing file or a
+ * malformed line. */
+int sla_tune_load(sla_ctx *ctx, const char *table_path);
+/* The context's tuned choice for a 3D grid: variants[2], shapes[2] and the
+ * measured ms[2] (even, odd); any pointer may be NULL.  SLA_EINVAL if the
+ * context has none for the grid. */
+int sla_tune_info(const sla_ctx *ctx, const sla_grid *grid, int32_t *variants, int32_t *shapes,
+                  double *ms);
 
 /* Synchronise the context's stream and report a Courant overflow recorded by
  * a kernel since the previous sla_check() (then SLA_ECOURANT), or a HIP
@@ -276,10 +301,13 @@ int sla_norms(sla_ctx *ctx, int64_t count, const float *a, const float *b,
  * read from memory about once for all of them.  Each step launches one
  * persistent kernel over the tiles of all problems, except problems with
  * their own velocity planes and at least 2^24 cells: those fill the GPU
- * alone and take one launch of the fused third-order step each (the
- * creating context's SLA_OPT_CEC3D_KERNEL choice).  A result equals
- * sla_advect(..., SLA_CEC, ...) on that problem (with a uniform velocity
- * field for a uniform problem), bit for bit.
+ * alone.  Such problems with the same velocity pointer, grid and time step
+ * run up to four (the creating context's SLA_OPT_SHARED_VELOCITY) per launch
+ * of the shared-velocity fused step, which loads the velocity once per tile
+ * for all of them; the others take one launch of the fused third-order step
+ * each (the creating context's SLA_OPT_CEC3D_KERNEL choice).  A result
+ * equals sla_advect(..., SLA_CEC, ...) on that problem (with a uniform
+ * velocity field for a uniform problem), bit for bit.
  * ---------------------------------------------------------------------- */
 typedef struct {
   sla_grid grid;        /* 3D, as for sla_advect */

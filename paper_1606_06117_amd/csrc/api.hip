@@ -28,8 +28,15 @@ struct sla_ctx {
   bool fused = true;    // SLA_OPT_FUSED
   int cec3d_kernel = 5;  // SLA_OPT_CEC3D_KERNEL
   int sweep_kernel = 2;  // SLA_OPT_SWEEP_KERNEL
-  int ec_kernel = 2;     // SLA_OPT_EC_KERNEL
+  int ec_kernel = 3;     // SLA_OPT_EC_KERNEL
   int cec3d_shape = 0;   // SLA_OPT_CEC3D_SHAPE
+  // fused-step choices measured by sla_tune (or loaded), per grid
+  struct Tuned {
+    int n[3];
+    int variant[2], shape[2];  // [0] even steps, [1] odd
+    double ms[2];
+  };
+  std::vector<Tuned> tuned;
   int learned_kernel = 1;  // SLA_OPT_LEARNED_KERNEL
   int multi = 4;           // SLA_OPT_SHARED_VELOCITY: largest group of fields
   // per-kernel timing
@@ -56,6 +63,10 @@ struct sla_plan {
   double step_ms = 0.0;
   // problems run by their own launches of the fused step (see plan_direct)
   std::vector<int> direct;
+  // the direct problems in launch groups: problems with the same velocity,
+  // grid and time step run together (up to four) through the
+  // shared-velocity fused step
+  std::vector<std::vector<int>> groups;
   std::vector<sla::Geo> geo;         // per problem
   std::vector<const float*> u;       // per problem (NULL: uniform velocity)
   int cec3d_kernel = 5;              // the creating context's fused-step choice
@@ -211,6 +222,21 @@ void fold_marks(sla_ctx* ctx) {
 bool capturing(sla_ctx* ctx) {
   hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
   return hipStreamIsCapturing(ctx->stream, &st) == hipSuccess && st != hipStreamCaptureStatusNone;
+}
+
+// The tuned fused-step choice of a grid, if any.
+const sla_ctx::Tuned* find_tuned(const sla_ctx* ctx, const sla::Geo& g) {
+  for (const auto& t : ctx->tuned)
+    if (t.n[0] == g.nx && t.n[1] == g.ny && t.n[2] == g.nz) return &t;
+  return nullptr;
+}
+void put_tuned(sla_ctx* ctx, const sla_ctx::Tuned& e) {
+  for (auto& t : ctx->tuned)
+    if (t.n[0] == e.n[0] && t.n[1] == e.n[1] && t.n[2] == e.n[2]) {
+      t = e;
+      return;
+    }
+  ctx->tuned.push_back(e);
 }
 
 int ensure_work(sla_ctx* ctx, size_t floats) {
@@ -689,9 +715,17 @@ int advect_steps(sla_ctx* ctx, const sla_grid* grid, float* phi, const float* u,
       case SLA_FEC:
       case SLA_BEC: {
         const int kind = scheme == SLA_FEC ? SLA_K_FEC : SLA_K_BEC;
-        // default (2): the gather chain, faster than the fused kernel at
-        // every grid and Courant number measured (256^3 and 512^3, CFL 0.9
-        // to 2.5)
+        // default (3): at reach 1 on a 3D grid all calls of the step in one
+        // z-march (every stage in LDS); otherwise the gather chain, faster
+        // than the LDS-tile kernel at every grid and Courant number measured
+        // (256^3 and 512^3, CFL 0.9 to 2.5)
+        if (ctx->ec_kernel == 3 && ndim == 3 && rmax == 1 && sla::offsets32_ok(geo)) {
+          e = run(ctx, kind, [&] {
+            return sla::launch_ec_march(scheme, geo, cur, u, nxt, ctx->flag, ctx->stream);
+          });
+          std::swap(cur, nxt);
+          break;
+        }
         if (ctx->ec_kernel == 0) {
           e = run(ctx, kind, [&] {
             return sla::launch_ec(ndim, scheme, rmax, geo, cur, u, nxt, ctx->flag, ctx->stream);
@@ -722,7 +756,15 @@ int advect_steps(sla_ctx* ctx, const sla_grid* grid, float* phi, const float* u,
           e = run(ctx, SLA_K_CEC3D, [&] {
             sla::Cec3dLaunch lc;
             lc.ychunk = ctx->cec3d_shape;
-            return sla::launch_cec3d(ctx->cec3d_kernel, m % 2 == 0, geo, cur, u, nxt, ctx->flag,
+            int variant = ctx->cec3d_kernel;
+            if (variant == 5) {
+              const sla_ctx::Tuned* t = find_tuned(ctx, geo);
+              if (t) {
+                variant = t->variant[m % 2];
+                lc.ychunk = t->shape[m % 2];
+              }
+            }
+            return sla::launch_cec3d(variant, m % 2 == 0, geo, cur, u, nxt, ctx->flag,
                                      ctx->stream, lc);
           });
           std::swap(cur, nxt);
@@ -836,8 +878,8 @@ int sla_set_option(sla_ctx* ctx, int option, int64_t value) {
       ctx->fused = value != 0;
       return SLA_OK;
     case SLA_OPT_CEC3D_KERNEL:
-      if (value < 0 || value >= sla::kCec3dVariants)
-        return fail(ctx, SLA_EINVAL, "SLA_OPT_CEC3D_KERNEL takes 0..%d", sla::kCec3dVariants - 1);
+      if (!sla::cec3d_variant_ok(int(value)))
+        return fail(ctx, SLA_EINVAL, "SLA_OPT_CEC3D_KERNEL takes 1, 2, 4, 5, 6, 7 or 8");
       ctx->cec3d_kernel = int(value);
       return SLA_OK;
     case SLA_OPT_SWEEP_KERNEL:
@@ -845,7 +887,7 @@ int sla_set_option(sla_ctx* ctx, int option, int64_t value) {
       ctx->sweep_kernel = int(value);
       return SLA_OK;
     case SLA_OPT_EC_KERNEL:
-      if (value < 0 || value > 2) return fail(ctx, SLA_EINVAL, "SLA_OPT_EC_KERNEL takes 0, 1 or 2");
+      if (value < 0 || value > 3) return fail(ctx, SLA_EINVAL, "SLA_OPT_EC_KERNEL takes 0..3");
       ctx->ec_kernel = int(value);
       return SLA_OK;
     case SLA_OPT_SHARED_VELOCITY:
@@ -905,6 +947,130 @@ int sla_norms(sla_ctx* ctx, int64_t count, const float* a, const float* b, doubl
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
   if (e != hipSuccess) return hip_fail(ctx, e, "norms");
   for (int k = 0; k < 5; ++k) out[k] = h[k];
+  return SLA_OK;
+}
+
+int sla_tune(sla_ctx* ctx, const sla_grid* grid, const float* phi, const float* u, double dt,
+             const char* table_path) {
+  if (!ctx) return SLA_EINVAL;
+  ctx->err.clear();
+  if (capturing(ctx)) return fail(ctx, SLA_ECAPTURE, "tuning synchronises the stream");
+  int rc = check_grid(ctx, grid);
+  if (rc) return rc;
+  if (grid->ndim != 3) return fail(ctx, SLA_EINVAL, "the fused step is 3D");
+  if (!phi || !u) return fail(ctx, SLA_EINVAL, "phi and u must not be NULL");
+  if (!std::isfinite(dt)) return fail(ctx, SLA_EINVAL, "dt must be finite");
+  DeviceGuard guard(ctx->device);
+  if (!guard.ok) return fail(ctx, SLA_EHIP, "cannot select device %d", ctx->device);
+  const sla::Geo geo = make_geo(grid, dt);
+  if (!sla::offsets32_ok(geo))
+    return fail(ctx, SLA_EINVAL, "the fused step takes fewer than 2^30 cells (or 2^30 with ny >= 2)");
+  float cm[3];
+  rc = measure_courant(ctx, grid, geo, u, cm);
+  if (rc) return rc;
+  if (!(cm[0] < 1.f && cm[1] < 1.f && cm[2] < 1.f))
+    return fail(ctx, SLA_ECOURANT, "the fused step takes Courant numbers below 1 (max %g)",
+                double(std::fmax(cm[0], std::fmax(cm[1], cm[2]))));
+  const size_t n = size_t(geo.ncells);
+  rc = ensure_work(ctx, n);
+  if (rc) return rc;
+  // candidates: (variant, launch shape)
+  static const int cand[][2] = {{1, 0}, {2, 0}, {4, 0}, {6, 0}, {7, 0}, {7, 32},
+                                {8, -64}, {8, -32}, {8, 0}};
+  hipEvent_t a = nullptr, b = nullptr;
+  hipError_t e = hipEventCreate(&a);
+  if (e == hipSuccess) e = hipEventCreate(&b);
+  sla_ctx::Tuned best = {{geo.nx, geo.ny, geo.nz}, {5, 5}, {0, 0}, {1e30, 1e30}};
+  constexpr int kReps = 3;
+  for (int par = 0; par < 2 && e == hipSuccess; ++par) {
+    for (const auto& c : cand) {
+      sla::Cec3dLaunch lc;
+      lc.ychunk = c[1];
+      auto launch = [&] {
+        return sla::launch_cec3d(c[0], par == 0, geo, phi, u, ctx->work, ctx->flag, ctx->stream, lc);
+      };
+      e = launch();  // warm-up
+      if (e == hipSuccess) e = hipEventRecord(a, ctx->stream);
+      for (int r = 0; r < kReps && e == hipSuccess; ++r) e = launch();
+      if (e == hipSuccess) e = hipEventRecord(b, ctx->stream);
+      if (e == hipSuccess) e = hipEventSynchronize(b);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+      if (e != hipSuccess) break;
+      const double avg = double(ms) / kReps;
+      if (avg < best.ms[par]) {
+        best.ms[par] = avg;
+        best.variant[par] = c[0];
+        best.shape[par] = c[1];
+      }
+    }
+  }
+  if (a) (void)hipEventDestroy(a);
+  if (b) (void)hipEventDestroy(b);
+  if (e != hipSuccess) return hip_fail(ctx, e, "tuning launches");
+  put_tuned(ctx, best);
+  if (table_path) {
+    // rewrite the table: other grids' lines kept, this grid's replaced
+    std::vector<std::string> keep;
+    if (FILE* f = std::fopen(table_path, "r")) {
+      char line[256];
+      while (std::fgets(line, sizeof line, f)) {
+        int nx, ny, nz;
+        if (line[0] == '#' || std::sscanf(line, "%d %d %d", &nx, &ny, &nz) != 3) continue;
+        if (nx == geo.nx && ny == geo.ny && nz == geo.nz) continue;
+        keep.push_back(line);
+      }
+      std::fclose(f);
+    }
+    FILE* f = std::fopen(table_path, "w");
+    if (!f) return fail(ctx, SLA_EINVAL, "cannot write the tuning table %s", table_path);
+    std::fprintf(f, "# nx ny nz even:variant shape ms odd:variant shape ms\n");
+    for (const auto& l : keep) std::fputs(l.c_str(), f);
+    std::fprintf(f, "%d %d %d %d %d %.4f %d %d %.4f\n", geo.nx, geo.ny, geo.nz, best.variant[0],
+                 best.shape[0], best.ms[0], best.variant[1], best.shape[1], best.ms[1]);
+    std::fclose(f);
+  }
+  return SLA_OK;
+}
+
+int sla_tune_load(sla_ctx* ctx, const char* table_path) {
+  if (!ctx || !table_path) return SLA_EINVAL;
+  ctx->err.clear();
+  FILE* f = std::fopen(table_path, "r");
+  if (!f) return fail(ctx, SLA_EINVAL, "cannot read the tuning table %s", table_path);
+  char line[256];
+  int rc = SLA_OK;
+  while (std::fgets(line, sizeof line, f)) {
+    if (line[0] == '#') continue;
+    sla_ctx::Tuned t;
+    if (std::sscanf(line, "%d %d %d %d %d %lf %d %d %lf", &t.n[0], &t.n[1], &t.n[2], &t.variant[0],
+                    &t.shape[0], &t.ms[0], &t.variant[1], &t.shape[1], &t.ms[1]) != 9 ||
+        !sla::cec3d_variant_ok(t.variant[0]) || !sla::cec3d_variant_ok(t.variant[1]) ||
+        t.variant[0] == 5 || t.variant[1] == 5 || t.shape[0] < -4096 || t.shape[0] > 4096 ||
+        t.shape[1] < -4096 || t.shape[1] > 4096 || t.n[0] < 8 || t.n[1] < 8 || t.n[2] < 8) {
+      rc = fail(ctx, SLA_EINVAL, "malformed tuning table line: %s", line);
+      break;
+    }
+    put_tuned(ctx, t);
+  }
+  std::fclose(f);
+  return rc;
+}
+
+int sla_tune_info(const sla_ctx* ctx, const sla_grid* grid, int32_t* variants, int32_t* shapes,
+                  double* ms) {
+  if (!ctx || !grid || grid->ndim != 3) return SLA_EINVAL;
+  sla::Geo g;
+  g.nx = grid->n[0];
+  g.ny = grid->n[1];
+  g.nz = grid->n[2];
+  const sla_ctx::Tuned* t = find_tuned(ctx, g);
+  if (!t) return SLA_EINVAL;
+  for (int p = 0; p < 2; ++p) {
+    if (variants) variants[p] = t->variant[p];
+    if (shapes) shapes[p] = t->shape[p];
+    if (ms) ms[p] = t->ms[p];
+  }
   return SLA_OK;
 }
 
@@ -1304,12 +1470,26 @@ hipError_t plan_step(sla_plan* pl, hipStream_t st, int32_t k) {
   if (pl->nitems > 0)
     e = sla::launch_cec3d_batch(even, pl->dprobs, pl->ditems, pl->nitems, k & 1, pl->blocks,
                                 pl->flag, st);
-  for (size_t j = 0; j < pl->direct.size() && e == hipSuccess; ++j) {
-    const int i = pl->direct[j];
-    float* a = pl->phis[size_t(i)];
-    float* b = pl->work[size_t(i)];
-    e = sla::launch_cec3d(pl->cec3d_kernel, even, pl->geo[size_t(i)], (k & 1) ? b : a,
-                          pl->u[size_t(i)], (k & 1) ? a : b, pl->flag, st);
+  for (size_t j = 0; j < pl->groups.size() && e == hipSuccess; ++j) {
+    const std::vector<int>& grp = pl->groups[j];
+    const int h = grp[0];
+    if (grp.size() == 1) {
+      float* a = pl->phis[size_t(h)];
+      float* b = pl->work[size_t(h)];
+      e = sla::launch_cec3d(pl->cec3d_kernel, even, pl->geo[size_t(h)], (k & 1) ? b : a,
+                            pl->u[size_t(h)], (k & 1) ? a : b, pl->flag, st);
+      continue;
+    }
+    const float* in[4];
+    float* out[4];
+    for (size_t f = 0; f < grp.size(); ++f) {
+      float* a = pl->phis[size_t(grp[f])];
+      float* b = pl->work[size_t(grp[f])];
+      in[f] = (k & 1) ? b : a;
+      out[f] = (k & 1) ? a : b;
+    }
+    e = sla::launch_cec3d_multi(int(grp.size()), even, pl->geo[size_t(h)], in, out, pl->u[size_t(h)],
+                                pl->flag, st);
   }
   return e;
 }
@@ -1397,6 +1577,29 @@ int sla_plan_create(sla_ctx* ctx, sla_plan** out, int32_t nprob, const sla_probl
     pl->u.push_back(P[i].u);
     if (plan_direct(P[i])) pl->direct.push_back(i);
   }
+  for (size_t j = 0; j < pl->direct.size(); ++j) {
+    const int i = pl->direct[j];
+    bool placed = false;
+    for (auto& grp : pl->groups) {
+      const int h = grp[0];
+      const sla::Geo &a = pl->geo[size_t(h)], &b = pl->geo[size_t(i)];
+      const bool same = int(grp.size()) < ctx->multi && pl->u[size_t(h)] == pl->u[size_t(i)] &&
+                        a.nx == b.nx && a.ny == b.ny && a.nz == b.nz && a.lam[0] == b.lam[0] &&
+                        a.lam[1] == b.lam[1] && a.lam[2] == b.lam[2];
+      if (same) {
+        grp.push_back(i);
+        placed = true;
+        break;
+      }
+    }
+    if (!placed) pl->groups.push_back({i});
+  }
+  // groups of three run as two and one
+  for (size_t q = 0; q < pl->groups.size(); ++q)
+    if (pl->groups[q].size() == 3) {
+      pl->groups.push_back({pl->groups[q][2]});
+      pl->groups[q].pop_back();
+    }
   bool ok = true;
   std::vector<float> uni(3 * size_t(nprob), 0.f);
   for (int i = 0; i < nprob; ++i) {

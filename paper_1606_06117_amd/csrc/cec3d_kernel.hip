@@ -173,226 +173,6 @@ __device__ __forceinline__ void st_vs(float* field, unsigned voff, unsigned soff
 #define SLA_SEG_MIN_WAVES 2
 #endif
 
-template <bool EVEN>
-__global__ __launch_bounds__(kThreads, SLA_CEC3D_MIN_WAVES) void k_cec3d_r1(const float* __restrict__ phi,
-                                                       const float* __restrict__ ux,
-                                                       const float* __restrict__ uy,
-                                                       const float* __restrict__ uz,
-                                                       float* __restrict__ out, Geo g,
-                                                       int ychunk, int swz, int* flag) {
-  using S = Cec3dShape<EVEN>;
-  constexpr int H = S::H, TA = S::TA, TB = S::TB, SA = S::SA, SB = S::SB;
-  constexpr int KP = S::KP, KY = S::KY;
-  __shared__ float P[S::NP];   // phi at the loaded plane, padded
-  __shared__ float CA[S::NP];  // Courant numbers of the first sweep
-  __shared__ float CB[S::NP];  // Courant numbers of the last sweep (output plane)
-  __shared__ float S1[S::NP];  // Phi1 of the first, then of the last sweep
-  __shared__ float SE[S::NP];  // e of the first, then of the last sweep
-  __shared__ float AO[S::NP];  // first-sweep output (y-pipeline input)
-  __shared__ float YO[S::NP];  // y-sweep output (last-sweep input)
-
-  const int tid = threadIdx.x;
-  const int3 bt = block_tile(swz);
-  const int x0 = bt.x * S::TX, z0 = bt.y * S::TZ;
-  const int y0 = bt.z * ychunk;
-  const int y1 = min(y0 + ychunk, g.ny);
-  const int nx = g.nx, ny = g.ny, nz = g.nz;
-  const unsigned nxy = unsigned(nx) * unsigned(ny);
-  const float* uA = EVEN ? ux : uz;
-  const float* uB = EVEN ? uz : ux;
-  const float lamA = EVEN ? g.lam[0] : g.lam[2];
-  const float lamB = EVEN ? g.lam[2] : g.lam[0];
-  const float lamY = g.lam[1];
-
-  // Per-thread global x-z offsets (the y term is added per plane), computed
-  // once.  Padded plane: cell e = tid + 256 k; y region: x-fastest rectangle.
-  unsigned poff[KP];
-  unsigned yoff[KY];
-  int ycol[KY];
-#pragma unroll
-  for (int k = 0; k < KP; ++k) {
-    const int e = min(tid + k * kThreads, S::NP - 1);
-    const int z = e / S::W - H, x = e % S::W - H;
-    poff[k] = unsigned(wrap1(x0 + x, nx)) + nxy * unsigned(wrap1(z0 + z, nz));
-  }
-#pragma unroll
-  for (int j = 0; j < KY; ++j) {
-    const int e = min(tid + j * kThreads, S::NY - 1);
-    const int z = S::YZ0 + e / S::YW, x = S::YX0 + e % S::YW;
-    yoff[j] = unsigned(wrap1(x0 + x, nx)) + nxy * unsigned(wrap1(z0 + z, nz));
-    ycol[j] = lidx<EVEN>(x, z);
-  }
-  auto pvalid = [&](int k) { return KP * kThreads == S::NP || tid + k * kThreads < S::NP; };
-  auto yvalid = [&](int j) { return KY * kThreads == S::NY || tid + j * kThreads < S::NY; };
-
-  // y-pipeline rings, per column: input a, Phi1, e, Courant (3 planes each)
-  float ra[3][KY], r1[3][KY], re[3][KY], rc[3][KY];
-#pragma unroll
-  for (int j = 0; j < KY; ++j)
-#pragma unroll
-    for (int k = 0; k < 3; ++k) ra[k][j] = r1[k][j] = re[k][j] = rc[k][j] = 0.f;
-
-  // Register prefetch of the next plane: phi and the first sweep's velocity
-  // (padded plane), the y velocity one plane back and the last sweep's
-  // velocity at the next output plane (y region).
-  float fp[KP], fa[KP], fy[KY], fb[KY];
-  auto prefetch = [&](int t) {
-    const unsigned qoff = unsigned(wrap1(y0 - H + t, ny)) * unsigned(nx);
-    const unsigned coff = unsigned(wrap1(y0 - H + t - 1, ny)) * unsigned(nx);
-    const unsigned ooff = unsigned(wrap1(y0 + t - 2 * H, ny)) * unsigned(nx);
-#pragma unroll
-    for (int k = 0; k < KP; ++k) {
-      fp[k] = phi[poff[k] + qoff];
-      fa[k] = uA[poff[k] + qoff];
-    }
-#pragma unroll
-    for (int j = 0; j < KY; ++j) {
-      fy[j] = uy[yoff[j] + coff];
-      fb[j] = uB[yoff[j] + ooff];
-    }
-  };
-
-  const int iters = (y1 - y0) + 2 * H;
-  bool over = false;  // a Courant number beyond reach 1 was published
-  prefetch(0);
-  // The ring slot of local plane t is t % 3; the loop body is unrolled by 3
-  // so that every slot index is a compile-time constant.
-  auto body = [&](auto phase, int t) {
-    constexpr int p0 = decltype(phase)::value;  // t % 3
-    constexpr int p1 = (p0 + 2) % 3;            // (t - 1) % 3
-    constexpr int p2 = (p0 + 1) % 3;            // (t - 2) % 3
-    constexpr int p3 = p0;                      // (t - 3) % 3
-    const bool emit = t >= 2 * H;
-
-    // 1. publish the prefetched plane, then start fetching the next one
-#pragma unroll
-    for (int k = 0; k < KP; ++k) {
-      if (!pvalid(k)) continue;
-      const float ca = fa[k] * lamA;
-      over |= over1(ca);
-      P[tid + k * kThreads] = fp[k];
-      CA[tid + k * kThreads] = ca;
-    }
-    float cy[KY];
-#pragma unroll
-    for (int j = 0; j < KY; ++j) {
-      cy[j] = fy[j] * lamY;
-      over |= over1(cy[j]);
-      if (emit && yvalid(j)) {
-        const float cb = fb[j] * lamB;
-        over |= over1(cb);
-        CB[ycol[j]] = cb;
-      }
-    }
-    if (t + 1 < iters) prefetch(t + 1);
-    __syncthreads();
-    // 2. first sweep, Phi1 on A in [-2, TA+2)
-    {
-      constexpr int LA = TA + 4, LB = TB + 2 * H;
-      for_each_cell<LA * LB>([&](int e) {
-        const int b = -H + e / LA, a = -2 + e % LA;
-        const int i = EVEN ? lidx<EVEN>(a, b) : lidx<EVEN>(b, a);
-        const Dep1 d = depart1(CA[i], flag);
-        S1[i] = lerp(P[i], P[i + (d.ob_neg ? -SA : SA)], d.f);
-      });
-    }
-    __syncthreads();
-    // 3. first sweep, e on A in [-1, TA+1)
-    {
-      constexpr int LA = TA + 2, LB = TB + 2 * H;
-      for_each_cell<LA * LB>([&](int e) {
-        const int b = -H + e / LA, a = -1 + e % LA;
-        const int i = EVEN ? lidx<EVEN>(a, b) : lidx<EVEN>(b, a);
-        const Dep1 d = depart1(CA[i], flag);
-        SE[i] = P[i] - lerp(S1[i], S1[i + (d.obr_pos ? SA : -SA)], d.f);
-      });
-    }
-    __syncthreads();
-    // 4. first sweep output on A in [0, TA)
-    {
-      constexpr int LB = TB + 2 * H;
-      for_each_cell<TA * LB>([&](int e) {
-        const int b = -H + e / TA, a = e % TA;
-        const int i = EVEN ? lidx<EVEN>(a, b) : lidx<EVEN>(b, a);
-        const Dep1 d = depart1(CA[i], flag);
-        const float ea = SE[i], eb = SE[i + (d.ob_neg ? -SA : SA)];
-        const float w = fmaf(d.f, 1.f / 3.f, 1.f / 3.f);
-        AO[i] = fmaf(0.5f, fmaf(w, eb - ea, ea), S1[i]);
-      });
-    }
-    __syncthreads();
-    // 5. y sweep as a pipeline along the march (registers)
-#pragma unroll
-    for (int j = 0; j < KY; ++j) {
-      if (!yvalid(j)) continue;
-      const int i = ycol[j];
-      ra[p0][j] = AO[i];  // input at plane t
-      rc[p1][j] = cy[j];  // Courant at plane t-1
-      // Phi1 at plane t-1
-      Dep1 d = depart1(rc[p1][j], flag);
-      r1[p1][j] = lerp(ra[p1][j], d.ob_neg ? ra[p2][j] : ra[p0][j], d.f);
-      // e at plane t-2
-      d = depart1(rc[p2][j], flag);
-      re[p2][j] = ra[p2][j] - lerp(r1[p2][j], d.obr_pos ? r1[p1][j] : r1[p3][j], d.f);
-      // y-sweep output at plane t-3
-      d = depart1(rc[p3][j], flag);
-      const float ea = re[p3][j];
-      const float eb = d.ob_neg ? re[p1][j] : re[p2][j];  // e at t-4 (slot p1) or t-2
-      const float w = fmaf(d.f, 1.f / 3.f, 1.f / 3.f);
-      YO[i] = fmaf(0.5f, fmaf(w, eb - ea, ea), r1[p3][j]);
-    }
-    __syncthreads();
-    if (!emit) return;
-    // 6. last sweep, Phi1 on B in [-2, TB+2)
-    {
-      constexpr int LB = TB + 4;
-      for_each_cell<TA * LB>([&](int e) {
-        const int b = -2 + e / TA, a = e % TA;
-        const int i = EVEN ? lidx<EVEN>(a, b) : lidx<EVEN>(b, a);
-        const Dep1 d = depart1(CB[i], flag);
-        S1[i] = lerp(YO[i], YO[i + (d.ob_neg ? -SB : SB)], d.f);
-      });
-    }
-    __syncthreads();
-    // 7. last sweep, e on B in [-1, TB+1)
-    {
-      constexpr int LB = TB + 2;
-      for_each_cell<TA * LB>([&](int e) {
-        const int b = -1 + e / TA, a = e % TA;
-        const int i = EVEN ? lidx<EVEN>(a, b) : lidx<EVEN>(b, a);
-        const Dep1 d = depart1(CB[i], flag);
-        SE[i] = YO[i] - lerp(S1[i], S1[i + (d.obr_pos ? SB : -SB)], d.f);
-      });
-    }
-    __syncthreads();
-    // 8. last sweep output on the tile, stored to HBM at plane t - 6
-    {
-      const unsigned yo = unsigned(y0 + t - 2 * H) * unsigned(nx);
-      for_each_cell<TA * TB>([&](int e) {
-        const int b = e / TA, a = e % TA;
-        const int x = EVEN ? a : b, z = EVEN ? b : a;
-        if (x0 + x >= nx || z0 + z >= nz) return;
-        const int i = lidx<EVEN>(x, z);
-        const Dep1 d = depart1(CB[i], flag);
-        const float ea = SE[i], eb = SE[i + (d.ob_neg ? -SB : SB)];
-        const float w = fmaf(d.f, 1.f / 3.f, 1.f / 3.f);
-        out[unsigned(x0 + x) + yo + nxy * unsigned(z0 + z)] =
-            fmaf(0.5f, fmaf(w, eb - ea, ea), S1[i]);
-      });
-    }
-    // The next plane stores CB before its first barrier while this plane's
-    // last sweep may still be reading it.
-    __syncthreads();
-  };
-
-  for (int t = 0; t < iters; t += 3) {
-    body(std::integral_constant<int, 0>{}, t);
-    if (t + 1 < iters) body(std::integral_constant<int, 1>{}, t + 1);
-    if (t + 2 < iters) body(std::integral_constant<int, 2>{}, t + 2);
-  }
-  if (over) *flag = 1;
-}
-
 // ---------------------------------------------------------------------------
 // Segment variant: the first and the last sweep of a plane run as per-thread
 // segments of V consecutive nodes along the sweep axis, all three calls in
@@ -662,17 +442,18 @@ constexpr int kWmUse = 58;  // outputs per 64-lane window (reach 1: 3 halo lanes
 // Wrapped indices of five consecutive march planes, advanced by one plane at
 // a time without a division (the values are the same for the whole wave).
 struct PlaneWin {
-  int p[5];
+  int p[6];
   int n;
   __device__ PlaneWin(int first, int n_) : n(n_) {
 #pragma unroll
-    for (int k = 0; k < 5; ++k) p[k] = __builtin_amdgcn_readfirstlane(wrapk(first + k, n));
+    for (int k = 0; k < 6; ++k) p[k] = __builtin_amdgcn_readfirstlane(wrapk(first + k, n));
   }
   __device__ void advance() {
 #pragma unroll
-    for (int k = 0; k < 4; ++k) p[k] = p[k + 1];
-    p[4] = p[4] + 1 < n ? p[4] + 1 : 0;
+    for (int k = 0; k < 5; ++k) p[k] = p[k + 1];
+    p[5] = p[5] + 1 < n ? p[5] + 1 : 0;
   }
+  __device__ int plane(int k) const { return p[k]; }
 };
 
 // Store V output rows of one plane: rows j < rows_left only (a uniform
@@ -1105,7 +886,7 @@ hipError_t launch_cec3d_wl(bool even, const Geo& g, const float* phi, const floa
 // are split over the W waves of a window as evenly as possible.  Same FP32
 // operations per node as the other variants.
 // ---------------------------------------------------------------------------
-template <bool EVEN, int V, int W, int WX>
+template <bool EVEN, int V, int W, int WX, int PF>
 __global__ __launch_bounds__(64 * W * WX) void k_cec3d_wp(const float* __restrict__ phi,
                                                           const float* __restrict__ ux,
                                                           const float* __restrict__ uy,
@@ -1160,23 +941,28 @@ __global__ __launch_bounds__(64 * W * WX) void k_cec3d_wp(const float* __restric
       orow[j] = vx + unsigned(__builtin_amdgcn_readfirstlane(wrapk(s0 + j, ns))) * sstr;
     PlaneWin pw(m0 - 6, nm);  // planes m0 - 6 + t .. m0 - 2 + t at iteration t
 
-    float fp[RW], fa[RW], fs[RW];  // phi, x velocity (even), segment velocity on loaded rows
-    float fm[V], fx[V];            // march velocity of plane q-1; odd: x velocity of the output plane
-    auto prefetch = [&](int ahead) {  // 0: iteration t; 1: iteration t + 1
-      const unsigned q = unsigned(pw.p[3 + ahead]) * mstr, qm1 = unsigned(pw.p[2 + ahead]) * mstr,
-                     qo = unsigned(pw.p[ahead]) * mstr;
+    // inputs of PF iterations ahead in flight: PF = 1, one set of registers
+    // (consumed, then reloaded); PF = 2, three (one consumed, two loading),
+    // the set of iteration t being t mod 3, the phase of the ring
+    constexpr int NB = PF == 1 ? 1 : 3;
+    float fp[NB][RW], fa[NB][RW], fs[NB][RW];  // phi, x velocity (even), segment velocity
+    float fm[NB][V], fx[NB][V];  // march velocity of plane q-1; odd: x velocity of the output plane
+    auto prefetch = [&](auto setc, int ahead) {  // ahead: iterations after the current one
+      constexpr int B = decltype(setc)::value;
+      const unsigned q = unsigned(pw.plane(3 + ahead)) * mstr,
+                     qm1 = unsigned(pw.plane(2 + ahead)) * mstr, qo = unsigned(pw.plane(ahead)) * mstr;
 #pragma unroll
       for (int k = 0; k < RW; ++k) {
         if (k < kAll || k < nld) {
-          fp[k] = ld_vs(phi, lrow[k], q);
-          if (EVEN) fa[k] = ld_vs(ux, lrow[k], q);
-          fs[k] = ld_vs(rS, lrow[k], q);
+          fp[B][k] = ld_vs(phi, lrow[k], q);
+          if (EVEN) fa[B][k] = ld_vs(ux, lrow[k], q);
+          fs[B][k] = ld_vs(rS, lrow[k], q);
         }
       }
 #pragma unroll
       for (int j = 0; j < V; ++j) {
-        fm[j] = ld_vs(rM, orow[j], qm1);
-        if (!EVEN) fx[j] = ld_vs(ux, orow[j], qo);
+        fm[B][j] = ld_vs(rM, orow[j], qm1);
+        if (!EVEN) fx[B][j] = ld_vs(ux, orow[j], qo);
       }
     };
 
@@ -1188,9 +974,13 @@ __global__ __launch_bounds__(64 * W * WX) void k_cec3d_wp(const float* __restric
 
     const int iters = (m1 - m0) + 6;
     const bool lane_out = lane >= 3 && lane < 61 && wx * kWmUse + lane - 3 < nx;
-    if (wx_ok) prefetch(0);
+    if (wx_ok) {
+      prefetch(std::integral_constant<int, 0>{}, 0);
+      if (PF == 2) prefetch(std::integral_constant<int, NB == 1 ? 0 : 1>{}, 1);
+    }
     auto body = [&](auto phase, int t) {
       constexpr int P0 = decltype(phase)::value;
+      constexpr int B = NB == 1 ? 0 : P0;  // this iteration's inputs
       const int b = t & 1;
       if (!wx_ok) {  // a window past the row's end: barriers only
         __syncthreads();
@@ -1199,13 +989,13 @@ __global__ __launch_bounds__(64 * W * WX) void k_cec3d_wp(const float* __restric
 #pragma unroll
       for (int k = 0; k < RW; ++k) {
         if (k < kAll || k < nld) {
-          float v = fp[k];
+          float v = fp[B][k];
           if (EVEN) {
-            const float c = fa[k] * lamX;
+            const float c = fa[B][k] * lamX;
             over |= over1(c);
             v = xsweep_lanes(v, c);  // first sweep (x) of this row
           }
-          const float c = fs[k] * lamS;
+          const float c = fs[B][k] * lamS;
           over |= over1(c);
           lp[b][xi][w * RW + k][lane] = v;
           lc[b][xi][w * RW + k][lane] = c;
@@ -1214,12 +1004,12 @@ __global__ __launch_bounds__(64 * W * WX) void k_cec3d_wp(const float* __restric
       float cm[V], cxo[V];
 #pragma unroll
       for (int j = 0; j < V; ++j) {
-        cm[j] = fm[j] * lamM;
+        cm[j] = fm[B][j] * lamM;
         over |= over1(cm[j]);
-        cxo[j] = EVEN ? 0.f : fx[j] * lamX;
+        cxo[j] = EVEN ? 0.f : fx[B][j] * lamX;
         if (!EVEN) over |= over1(cxo[j]);
       }
-      if (t + 1 < iters) prefetch(1);
+      if (t + PF < iters) prefetch(std::integral_constant<int, NB == 1 ? 0 : (P0 + 2) % 3>{}, PF);
       __syncthreads();
       float p[V + 6], cs[V + 4], a[V], o[V];
 #pragma unroll
@@ -1255,24 +1045,14 @@ __global__ __launch_bounds__(64 * W * WX) void k_cec3d_wp(const float* __restric
   if (over) *flag = 1;
 }
 
-// The persistent march's configurations: (V, W, WX) and a name.
-struct WpConfig {
-  int V, W, WX;
-};
-constexpr WpConfig kWpConfigs[] = {
-    {8, 2, 3},  // 0: variant 7's shape
-    {4, 4, 3},  // 1: 16-row groups, 12 waves
-    {4, 8, 2},  // 2: 32-row groups, 16 waves
-    {8, 4, 2},  // 3: 32-row groups, 8 waves
-    {4, 6, 2},  // 4: 24-row groups, 12 waves
-    {2, 8, 2},  // 5: 16-row groups, 16 waves, two rows per wave
-};
-constexpr int kWpCount = sizeof(kWpConfigs) / sizeof(kWpConfigs[0]);
+// The persistent march's group shape: V = 4 rows per wave, W = 4 waves per
+// window (16-row groups), WX = 3 windows per workgroup (12 waves).
+constexpr int kWpV = 4, kWpW = 4, kWpWX = 3;
 
-template <bool EVEN, int V, int W, int WX>
+template <bool EVEN, int V, int W, int WX, int PF>
 hipError_t launch_wp_t(const Geo& g, const float* phi, const float* u, float* out, int* flag,
                        hipStream_t st, int shape) {
-  auto kern = k_cec3d_wp<EVEN, V, W, WX>;
+  auto kern = k_cec3d_wp<EVEN, V, W, WX, PF>;
   constexpr int S = V * W;
   const size_t n = (size_t)g.ncells;
   const int ns = EVEN ? g.ny : g.nz, nm = EVEN ? g.nz : g.ny;
@@ -1307,28 +1087,16 @@ hipError_t launch_wp_t(const Geo& g, const float* phi, const float* u, float* ou
   return hipGetLastError();
 }
 
-template <int C>
-hipError_t launch_wp_c(bool even, const Geo& g, const float* phi, const float* u, float* out,
-                       int* flag, hipStream_t st, int bpc) {
-  constexpr WpConfig c = kWpConfigs[C];
-  return even ? launch_wp_t<true, c.V, c.W, c.WX>(g, phi, u, out, flag, st, bpc)
-              : launch_wp_t<false, c.V, c.W, c.WX>(g, phi, u, out, flag, st, bpc);
-}
-
-hipError_t launch_cec3d_wp(int config, bool even, const Geo& g, const float* phi, const float* u,
-                           float* out, int* flag, hipStream_t st, Cec3dLaunch lc) {
-  // > 0: persistent, workgroups per CU; < 0: march chunk of -value planes,
-  // one workgroup per chunk of a group; 0: persistent, as many as fit
-  const int bpc = lc.ychunk;
-  switch (config) {
-    case 0: return launch_wp_c<0>(even, g, phi, u, out, flag, st, bpc);
-    case 1: return launch_wp_c<1>(even, g, phi, u, out, flag, st, bpc);
-    case 2: return launch_wp_c<2>(even, g, phi, u, out, flag, st, bpc);
-    case 3: return launch_wp_c<3>(even, g, phi, u, out, flag, st, bpc);
-    case 4: return launch_wp_c<4>(even, g, phi, u, out, flag, st, bpc);
-    case 5: return launch_wp_c<5>(even, g, phi, u, out, flag, st, bpc);
-  }
-  return hipErrorInvalidValue;
+// shape > 0: persistent, workgroups per CU; < 0: march chunks of -shape
+// planes, one workgroup per chunk of a group; 0: persistent, as many as fit
+// pf: planes loaded ahead of the march (1 or 2)
+hipError_t launch_cec3d_wp(bool even, const Geo& g, const float* phi, const float* u, float* out,
+                           int* flag, hipStream_t st, Cec3dLaunch lc, int pf = 1) {
+  if (pf == 2)
+    return even ? launch_wp_t<true, kWpV, kWpW, kWpWX, 2>(g, phi, u, out, flag, st, lc.ychunk)
+                : launch_wp_t<false, kWpV, kWpW, kWpWX, 2>(g, phi, u, out, flag, st, lc.ychunk);
+  return even ? launch_wp_t<true, kWpV, kWpW, kWpWX, 1>(g, phi, u, out, flag, st, lc.ychunk)
+              : launch_wp_t<false, kWpV, kWpW, kWpWX, 1>(g, phi, u, out, flag, st, lc.ychunk);
 }
 
 // ---------------------------------------------------------------------------
@@ -1507,10 +1275,6 @@ __global__ __launch_bounds__(64 * W * WX) void k_cec3d_mf(MfFields fl, const flo
 template <int K>
 struct MfShape;
 template <>
-struct MfShape<1> {
-  static constexpr int V = 8, W = 2, WX = 3;
-};
-template <>
 struct MfShape<2> {
   static constexpr int V = 4, W = 4, WX = 3;
 };
@@ -1540,243 +1304,6 @@ hipError_t launch_mf_k(bool even, const Geo& g, const MfFields& fl, const float*
   else
     hipLaunchKernelGGL((k_cec3d_mf<false, Sh::V, Sh::W, Sh::WX, K>), grid, dim3(64 * Sh::W * Sh::WX),
                        0, st, fl, u, u + n, u + 2 * n, g, chunk, flag);
-  return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
-// Overlapped variant: 320-thread workgroups (5 waves) and two barriers per
-// plane.  Phase A: every wave runs the y pipeline on the first-sweep output
-// of the previous plane, then publishes the prefetched inputs of the next
-// plane to LDS and issues the loads of the one after.  Phase B: waves 0-2
-// run the first sweep of the new plane while waves 3-4 run the last sweep
-// of the y output and store it.  The two sweeps of phase B touch different
-// LDS arrays, so they need no barrier between them.
-// ---------------------------------------------------------------------------
-constexpr int kTO = 320;
-constexpr int kTO1 = 192;  // threads of the first sweep (waves 0-2)
-
-template <bool EVEN>
-struct OvlShape : Cec3dShape<EVEN> {
-  using B = Cec3dShape<EVEN>;
-  static constexpr int V = 8;
-  static constexpr int NS1 = B::TA / V, N1 = (B::TB + 2 * B::H) * NS1;  // first sweep items
-  static constexpr int NS2 = B::TB / V, N2 = B::TA * NS2;               // last sweep items
-  static constexpr int KP = (B::NP + kTO - 1) / kTO;  // padded-plane cells per thread
-  static constexpr int KY = (B::NY + kTO - 1) / kTO;  // y columns per thread
-  static_assert(N1 <= kTO1 && N2 <= kTO - kTO1, "one item per thread of each group");
-  static_assert(B::TA % V == 0 && B::TB % V == 0, "segments tile the block");
-};
-
-template <bool EVEN>
-__global__ __launch_bounds__(kTO, 2) void k_cec3d_ovl(
-    const float* __restrict__ phi, const float* __restrict__ ux, const float* __restrict__ uy,
-    const float* __restrict__ uz, float* __restrict__ out, Geo g, int ychunk, int swz, int* flag) {
-  using S = OvlShape<EVEN>;
-  constexpr int H = S::H, TA = S::TA, SA = S::SA, SB = S::SB, V = S::V;
-  constexpr int KP = S::KP, KY = S::KY;
-  __shared__ float P[S::NP];   // phi at the loaded plane, padded
-  __shared__ float CA[S::NP];  // Courant numbers of the first sweep
-  __shared__ float CB[S::NP];  // Courant numbers of the last sweep (output plane)
-  __shared__ float AO[S::NP];  // first-sweep output (y-pipeline input)
-  __shared__ float YO[S::NP];  // y-sweep output (last-sweep input)
-
-  const int tid = threadIdx.x;
-  const int3 bt = block_tile(swz);
-  const int x0 = bt.x * S::TX, z0 = bt.y * S::TZ;
-  const int y0 = bt.z * ychunk;
-  const int y1 = min(y0 + ychunk, g.ny);
-  const int nx = g.nx, ny = g.ny, nz = g.nz;
-  const unsigned nxy = unsigned(nx) * unsigned(ny);
-  const size_t ncells = size_t(nxy) * size_t(nz);
-  const float* uA = EVEN ? ux : uz;
-  const float* uB = EVEN ? uz : ux;
-  const float lamA = EVEN ? g.lam[0] : g.lam[2];
-  const float lamB = EVEN ? g.lam[2] : g.lam[0];
-  const float lamY = g.lam[1];
-
-  // byte offsets (x-z part) of this thread's cells within a y plane
-  unsigned poff[KP];
-  unsigned yoff[KY];
-#pragma unroll
-  for (int k = 0; k < KP; ++k) {
-    const int e = min(tid + k * kTO, S::NP - 1);
-    const int z = e / S::W - H, x = e % S::W - H;
-    poff[k] = 4u * (unsigned(wrap1(x0 + x, nx)) + nxy * unsigned(wrap1(z0 + z, nz)));
-  }
-#pragma unroll
-  for (int j = 0; j < KY; ++j) {
-    const int e = min(tid + j * kTO, S::NY - 1);
-    const int z = S::YZ0 + e / S::YW, x = S::YX0 + e % S::YW;
-    yoff[j] = 4u * (unsigned(wrap1(x0 + x, nx)) + nxy * unsigned(wrap1(z0 + z, nz)));
-  }
-  // LDS index of y column j (region element tid + 320 j), a fixed stride apart
-  static_assert(EVEN ? (kTO % S::YW == 0) : (S::YW == S::W), "y columns a fixed stride apart");
-  const int ycol0 = lidx<EVEN>(S::YX0 + tid % S::YW, S::YZ0 + tid / S::YW);
-  constexpr int YCS = EVEN ? (kTO / S::YW) * S::W : kTO;
-  auto ycol = [&](int j) { return ycol0 + j * YCS; };
-  auto pvalid = [&](int k) { return KP * kTO == S::NP || tid + k * kTO < S::NP; };
-  auto yvalid = [&](int j) { return KY * kTO == S::NY || tid + j * kTO < S::NY; };
-
-  // phase-B roles: first-sweep segment (threads < N1) or last-sweep segment
-  // (threads kTO1 .. kTO1 + N2 - 1)
-  const bool has1 = tid < S::N1;
-  const int i1 = EVEN ? lidx<EVEN>((tid % S::NS1) * V, tid / S::NS1 - H)
-                      : lidx<EVEN>(tid / S::NS1 - H, (tid % S::NS1) * V);
-  const int k2 = tid >= kTO1 ? tid - kTO1 : 0;
-  const bool has2 = tid >= kTO1 && k2 < S::N2;
-  const int la2 = EVEN ? k2 % TA : k2 / S::NS2;  // last sweep: line (A coordinate)
-  const int sb2 = EVEN ? k2 / TA : k2 % S::NS2;  // last sweep: segment index along B
-  const int i2 = EVEN ? lidx<EVEN>(la2, sb2 * V) : lidx<EVEN>(sb2 * V, la2);
-  const int ox2 = EVEN ? la2 : sb2 * V, oz2 = EVEN ? sb2 * V : la2;
-  const unsigned ostep2 = EVEN ? 4u * nxy : 4u;
-  const unsigned obase2 = 4u * (unsigned(min(x0 + ox2, nx - 1)) + nxy * unsigned(min(z0 + oz2, nz - 1)));
-  const int nvalid2 = EVEN ? (x0 + ox2 < nx ? min(V, nz - (z0 + oz2)) : 0)
-                           : (z0 + oz2 < nz ? min(V, nx - (x0 + ox2)) : 0);
-
-  float ra[3][KY], r1[3][KY], re[3][KY], rc[3][KY];
-#pragma unroll
-  for (int j = 0; j < KY; ++j)
-#pragma unroll
-    for (int k = 0; k < 3; ++k) ra[k][j] = r1[k][j] = re[k][j] = rc[k][j] = 0.f;
-
-  // Iteration t publishes input plane q_t = y0 - H + t (t < iters), runs the
-  // y pipeline on q_{t-1} (t >= 1) and stores output plane y0 + t - 1 - 2H
-  // (t >= 1 + 2H).  prefetch(t) loads what iteration t publishes: phi and
-  // the first-sweep velocity of q_t, the y velocity of q_{t-2} (the plane
-  // whose y sweep completes when q_{t-1} enters) and the last-sweep
-  // velocity of the output plane.
-  const int iters = (y1 - y0) + 2 * H;
-  float fp[KP], fa[KP], fy[KY], fb[KY];
-  auto prefetch = [&](int t) {
-    const size_t qoff = size_t(wrap1(y0 - H + t, ny)) * size_t(nx);
-    const size_t coff = size_t(wrap1(y0 - H + t - 2, ny)) * size_t(nx);
-    const size_t ooff = size_t(wrap1(y0 + t - 1 - 2 * H, ny)) * size_t(nx);
-    const Rsrc pq = plane_rsrc(phi + qoff, ncells - qoff);
-    const Rsrc aq = plane_rsrc(uA + qoff, ncells - qoff);
-    const Rsrc yq = plane_rsrc(uy + coff, ncells - coff);
-    const Rsrc bq = plane_rsrc(uB + ooff, ncells - ooff);
-#pragma unroll
-    for (int k = 0; k < KP; ++k) {
-      fp[k] = ld_at(pq, poff[k]);
-      fa[k] = ld_at(aq, poff[k]);
-    }
-#pragma unroll
-    for (int j = 0; j < KY; ++j) {
-      fy[j] = ld_at(yq, yoff[j]);
-      fb[j] = ld_at(bq, yoff[j]);
-    }
-  };
-
-  bool over = false;  // a Courant number beyond reach 1 was published
-  auto publish = [&](int t) {
-    if (t < iters) {
-#pragma unroll
-      for (int k = 0; k < KP; ++k) {
-        if (!pvalid(k)) continue;
-        const float ca = fa[k] * lamA;
-        over |= over1(ca);
-        P[tid + k * kTO] = fp[k];
-        CA[tid + k * kTO] = ca;
-      }
-    }
-    if (t >= 1 + 2 * H) {
-#pragma unroll
-      for (int j = 0; j < KY; ++j) {
-        if (!yvalid(j)) continue;
-        const float cb = fb[j] * lamB;
-        over |= over1(cb);
-        CB[ycol(j)] = cb;
-      }
-    }
-  };
-  auto phase_b = [&](int t) {
-    if (t < iters && has1) {  // first sweep of q_t
-      float p[V + 6], c[V + 4], o[V];
-#pragma unroll
-      for (int k = 0; k < V + 6; ++k) p[k] = P[i1 + (k - 3) * SA];
-#pragma unroll
-      for (int k = 0; k < V + 4; ++k) c[k] = CA[i1 + (k - 2) * SA];
-      sweep_segment<V>(p, c, o, flag);
-#pragma unroll
-      for (int k = 0; k < V; ++k) AO[i1 + k * SA] = o[k];
-    }
-    if (t >= 1 + 2 * H && has2) {  // last sweep of output plane y0 + t - 1 - 2H
-      float p[V + 6], c[V + 4], o[V];
-#pragma unroll
-      for (int k = 0; k < V + 6; ++k) p[k] = YO[i2 + (k - 3) * SB];
-#pragma unroll
-      for (int k = 0; k < V + 4; ++k) c[k] = CB[i2 + (k - 2) * SB];
-      sweep_segment<V>(p, c, o, flag);
-      const size_t orow = size_t(y0 + t - 1 - 2 * H) * size_t(nx);
-      const Rsrc oq = plane_rsrc(out + orow, ncells - orow);
-#pragma unroll
-      for (int k = 0; k < V; ++k)
-        if (k < nvalid2) st_at(oq, obase2 + k * ostep2, o[k]);
-    }
-  };
-
-  // t = 0: nothing in the y pipeline yet
-  prefetch(0);
-  publish(0);
-  prefetch(1);
-  __syncthreads();
-  phase_b(0);
-  __syncthreads();
-
-  // iterations t = s + 1 for s = 0 .. iters - 1; the y pipeline takes AO of
-  // plane q_s, so its ring slot is s % 3
-  auto body = [&](auto phase, int s) {
-    constexpr int p0 = decltype(phase)::value;  // s % 3
-    constexpr int p1 = (p0 + 2) % 3;            // (s - 1) % 3
-    constexpr int p2 = (p0 + 1) % 3;            // (s - 2) % 3
-    constexpr int p3 = p0;                      // (s - 3) % 3
-    const int t = s + 1;
-    // A. y sweep as a pipeline along the march (registers)
-#pragma unroll
-    for (int j = 0; j < KY; ++j) {
-      const float cy = fy[j] * lamY;
-      over |= over1(cy);
-      if (!yvalid(j)) continue;
-      const int i = ycol(j);
-      ra[p0][j] = AO[i];
-      rc[p1][j] = cy;
-      Dep1 d = depart1(rc[p1][j], flag);
-      r1[p1][j] = lerp(ra[p1][j], d.ob_neg ? ra[p2][j] : ra[p0][j], d.f);
-      d = depart1(rc[p2][j], flag);
-      re[p2][j] = ra[p2][j] - lerp(r1[p2][j], d.obr_pos ? r1[p1][j] : r1[p3][j], d.f);
-      d = depart1(rc[p3][j], flag);
-      const float ea = re[p3][j];
-      const float eb = d.ob_neg ? re[p1][j] : re[p2][j];
-      const float w = fmaf(d.f, 1.f / 3.f, 1.f / 3.f);
-      YO[i] = fmaf(0.5f, fmaf(w, eb - ea, ea), r1[p3][j]);
-    }
-    publish(t);
-    if (t + 1 <= iters) prefetch(t + 1);
-    __syncthreads();
-    // B. first sweep of q_t (waves 0-2) and last sweep of the y output (waves 3-4)
-    phase_b(t);
-    __syncthreads();
-  };
-
-  for (int s = 0; s < iters; s += 3) {
-    body(std::integral_constant<int, 0>{}, s);
-    if (s + 1 < iters) body(std::integral_constant<int, 1>{}, s + 1);
-    if (s + 2 < iters) body(std::integral_constant<int, 2>{}, s + 2);
-  }
-  if (over) *flag = 1;
-}
-
-hipError_t launch_cec3d_ovl(bool even, const Geo& g, const float* phi, const float* u, float* out,
-                            int* flag, hipStream_t st, Cec3dLaunch lc) {
-  const size_t n = (size_t)g.ncells;
-  const int ychunk = lc.ychunk > 0 ? lc.ychunk : cec3d_default_ychunk(g);
-  dim3 grid((g.nx + 63) / 64, (g.nz + 15) / 16, (g.ny + ychunk - 1) / ychunk);
-  if (even)
-    hipLaunchKernelGGL(k_cec3d_ovl<true>, grid, dim3(kTO), 0, st, phi, u, u + n, u + 2 * n, out, g,
-                       ychunk, lc.swizzle, flag);
-  else
-    hipLaunchKernelGGL(k_cec3d_ovl<false>, grid, dim3(kTO), 0, st, phi, u, u + n, u + 2 * n, out, g,
-                       ychunk, lc.swizzle, flag);
   return hipGetLastError();
 }
 
@@ -2187,7 +1714,7 @@ hipError_t launch_cec3d_multi(int k, bool even, const Geo& g, const float* const
     fl.out[f] = out[f];
   }
   switch (k) {
-    case 1: return launch_mf_k<1>(even, g, fl, u, flag, st, chunk);
+    case 1: return launch_cec3d(5, even, g, in[0], u, out[0], flag, st);
     case 2: return launch_mf_k<2>(even, g, fl, u, flag, st, chunk);
     case 4: return launch_mf_k<4>(even, g, fl, u, flag, st, chunk);
   }
@@ -2197,17 +1724,18 @@ hipError_t launch_cec3d_multi(int k, bool even, const Geo& g, const float* const
 hipError_t launch_cec3d(int variant, bool even, const Geo& g, const float* phi, const float* u,
                         float* out, int* flag, hipStream_t st, Cec3dLaunch lc) {
   if (variant == 1) return launch_cec3d_seg(even, g, phi, u, out, flag, st, lc);
-  if (variant == 3) return launch_cec3d_ovl(even, g, phi, u, out, flag, st, lc);
   if (variant == 4) return launch_cec3d_wm<4>(even, g, phi, u, out, flag, st, lc);
   if (variant == 6) return launch_cec3d_wm<8>(even, g, phi, u, out, flag, st, lc);
   if (variant == 7) return launch_cec3d_wl(even, g, phi, u, out, flag, st, lc);
-  if (variant >= 8 && variant < 8 + kWpCount)
-    return launch_cec3d_wp(variant - 8, even, g, phi, u, out, flag, st, lc);
+  if (variant == 8) return launch_cec3d_wp(even, g, phi, u, out, flag, st, lc);
+  if (variant == 9) return launch_cec3d_wp(even, g, phi, u, out, flag, st, lc, 2);
   if (variant == 5) {
     // the fastest implementation of each parity as measured from 256^3 to
-    // 1024^3: up to 2^24 cells, register segments for even steps and the
-    // 4-row window march for odd ones; above, the shared-halo march when 2
-    // or 3 divides the window count, else the 8-row window march, except on
+    // 1024^3 (the tuner, sla_tune, measures the grid at hand instead): up to
+    // 2^24 cells, register segments for even steps and the 4-row window
+    // march for odd ones; above, the shared-halo march with 16-row groups of
+    // 12 waves and 64-plane chunks when 3 divides the window count, with
+    // 2-window groups when 2 does, else the 8-row window march, except on
     // odd steps whose 8-row launch would not fill the chip (see wm8_fills)
     if (g.ncells <= (1 << 24)) {
       if (!even) return launch_cec3d_wm<4>(false, g, phi, u, out, flag, st, lc);
@@ -2215,26 +1743,18 @@ hipError_t launch_cec3d(int variant, bool even, const Geo& g, const float* phi, 
       if (l.ychunk <= 0) l.ychunk = g.ny >= 512 ? 128 : cec3d_default_ychunk(g);
       return launch_cec3d_seg(true, g, phi, u, out, flag, st, l);
     }
+    if (wl_windows(g) == 3) {
+      Cec3dLaunch l = lc;
+      if (l.ychunk == 0) l.ychunk = -64;
+      return launch_cec3d_wp(even, g, phi, u, out, flag, st, l);
+    }
     if (wl_windows(g) > 0) return launch_cec3d_wl(even, g, phi, u, out, flag, st, lc);
     if (!even && !wm8_fills(wm_shape(false, g, 8).waves(64)))
       return launch_cec3d_wm<4>(false, g, phi, u, out, flag, st, lc);
     return launch_cec3d_wm<8>(even, g, phi, u, out, flag, st, lc);
   }
   if (variant == 2) return launch_cec3d_v4(even, g, phi, u, out, flag, st, lc);
-  if (variant != 0) return hipErrorInvalidValue;
-  const size_t n = (size_t)g.ncells;
-  const float* ux = u;
-  const float* uy = u + n;
-  const float* uz = u + 2 * n;
-  const int ychunk = lc.ychunk > 0 ? lc.ychunk : cec3d_default_ychunk(g);
-  dim3 grid((g.nx + 63) / 64, (g.nz + 15) / 16, (g.ny + ychunk - 1) / ychunk);
-  if (even)
-    hipLaunchKernelGGL(k_cec3d_r1<true>, grid, dim3(kThreads), 0, st, phi, ux, uy, uz, out, g,
-                       ychunk, lc.swizzle, flag);
-  else
-    hipLaunchKernelGGL(k_cec3d_r1<false>, grid, dim3(kThreads), 0, st, phi, ux, uy, uz, out, g,
-                       ychunk, lc.swizzle, flag);
-  return hipGetLastError();
+  return hipErrorInvalidValue;
 }
 
 }  // namespace sla

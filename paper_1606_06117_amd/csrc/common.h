@@ -42,6 +42,12 @@ hipError_t launch_cir(int ndim, const Geo& g, const float* phi, const float* u,
 hipError_t launch_ec(int ndim, int scheme, int R, const Geo& g, const float* phi,
                      const float* u, float* out, int* flag, hipStream_t st);
 
+// Unsplit FEC or BEC step of a 3D grid at reach 1, all calls in one pass
+// (a z-march with every stage's field in LDS); needs offsets32_ok(g).  Same
+// results as the chain of gather kernels.
+hipError_t launch_ec_march(int scheme, const Geo& g, const float* phi, const float* u, float* out,
+                           int* flag, hipStream_t st);
+
 // One third-order sweep along axis d with reach R; u_d is that axis' plane.
 // march: y and z sweeps of grids of at most 2^30 cells walk columns through
 // registers (k_sweep_m); otherwise LDS tiles (k_sweep_s).  Same results.
@@ -64,15 +70,19 @@ hipError_t launch_cec_sweep_xy(int R, bool xfirst, const Geo& g, const float* ph
                                float* out, int* flag, hipStream_t st);
 
 // Fused three-axis third-order step (reach 1 only): x,y,z order if even,
-// z,y,x otherwise.  variant: 0 LDS stages, 1 register segments, 2 streaming
-// (direct global-to-LDS loads), 3 overlapped first/last sweeps, 4 window
-// march with 4-row segments (no LDS), 5 the fastest of these per parity
-// and grid size, 6 window march with 8-row segments, 7 window march whose
-// workgroups share segment halos through LDS, 8.. the persistent form of 7
-// in several group shapes; all perform the same FP32 operations.
-constexpr int kCec3dVariants = 14;
-// Launch shape: y planes per workgroup (0: the default for the grid) and
-// whether tiles are mapped to XCDs in contiguous ranges (1) or round robin.
+// z,y,x otherwise.  variant: 1 register segments, 2 streaming (direct
+// global-to-LDS loads), 4 window march with 4-row segments (no LDS), 5 the
+// fastest of these per parity and grid size, 6 window march with 8-row
+// segments, 7 window march whose workgroups share segment halos through
+// LDS, 8 the same with 16-row groups of 12 waves, in march chunks or
+// persistent, 9 as 8 with the inputs loaded two planes ahead; all perform
+// the same FP32 operations (0 and 3 are unused).
+constexpr int kCec3dVariants = 10;
+inline bool cec3d_variant_ok(int v) { return v >= 1 && v < kCec3dVariants && v != 3; }
+// Launch shape: y planes per workgroup, or for variant 8 the march chunk
+// (< 0: -chunk planes) or workgroups per CU of the persistent form (> 0);
+// 0: the default for the grid; and whether tiles are mapped to XCDs in
+// contiguous ranges (1) or round robin.
 struct Cec3dLaunch {
   int ychunk = 0;
   int swizzle = 1;

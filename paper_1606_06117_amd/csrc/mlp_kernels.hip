@@ -742,7 +742,7 @@ __global__ __launch_bounds__(kThreads) void k_learned_correct(const float* __res
 // operations and their order are those of k_learned_correct: the same
 // results bit for bit.
 // ---------------------------------------------------------------------------
-constexpr int kLmRows = 4, kLmX = 64, kLmW = kLmX + 2, kLmH = kLmRows + 2, kLmRing = 4;
+constexpr int kLmRows = 8, kLmX = 64, kLmW = kLmX + 2, kLmH = kLmRows + 2, kLmRing = 4;
 constexpr int kLmThreads = 64 * kLmRows;
 struct MarchLds {
   __bf16 w1t[NH * SF];  // permuted rows (see above)
@@ -784,7 +784,7 @@ __device__ __forceinline__ int wrapk(int v, int n) {
   return v < 0 ? v + n : v;
 }
 
-__global__ __launch_bounds__(kLmThreads, 3) void k_learned_march(const float* __restrict__ phi1,
+__global__ __launch_bounds__(kLmThreads, 4) void k_learned_march(const float* __restrict__ phi1,
                                                               const float* __restrict__ ux,
                                                               const float* __restrict__ uy,
                                                               const float* __restrict__ uz, Geo geo,

@@ -74,6 +74,10 @@ SIGNATURES = {
                                         _c.POINTER(_c.c_double)]),
     "sla_advect_learned": (_c.c_int, [_vp, _vp, _vp, _vp, _vp, _c.c_double, _c.c_int32,
                                       _c.c_int64, _c.c_double, _c.POINTER(_c.c_int32)]),
+    "sla_tune": (_c.c_int, [_vp, _vp, _vp, _vp, _c.c_double, _c.c_char_p]),
+    "sla_tune_load": (_c.c_int, [_vp, _c.c_char_p]),
+    "sla_tune_info": (_c.c_int, [_vp, _vp, _c.POINTER(_c.c_int32), _c.POINTER(_c.c_int32),
+                                 _c.POINTER(_c.c_double)]),
     "sla_timing": (_c.c_int, [_vp, _c.c_int]),
     "sla_timing_read": (_c.c_int, [_vp, _c.POINTER(_c.c_int64), _c.POINTER(_c.c_double)]),
 }
@@ -281,6 +285,28 @@ class Context:
         self._stream()
         self._raise(self.lib.sla_norms(self.h, a.numel(), _ptr(a), _ptr(b), out))
         return tuple(out)
+
+    def tune(self, phi, u, dx, dt, path=None):
+        """Time the fused-step implementations on this grid (sla_tune); the
+        context then uses the fastest per parity.  Returns ``tune_info``."""
+        _check_field(phi, "phi")
+        _check_field(u, "u")
+        g = make_grid(phi.shape, dx)
+        self._stream()
+        self._raise(self.lib.sla_tune(self.h, ctypes.byref(g), _ptr(phi), _ptr(u), float(dt),
+                                      path.encode() if path else None))
+        return self.tune_info(phi.shape)
+
+    def tune_load(self, path):
+        self._raise(self.lib.sla_tune_load(self.h, path.encode()))
+
+    def tune_info(self, shape):
+        """``{"even": (variant, shape, ms), "odd": (...)}`` or None."""
+        g = make_grid(shape)
+        v, sh, ms = (ctypes.c_int32 * 2)(), (ctypes.c_int32 * 2)(), (ctypes.c_double * 2)()
+        if self.lib.sla_tune_info(self.h, ctypes.byref(g), v, sh, ms) != OK:
+            return None
+        return {"even": (v[0], sh[0], ms[0]), "odd": (v[1], sh[1], ms[1])}
 
     def timing(self, enable: bool):
         """Start (clearing totals) or stop per-kernel event timing."""

@@ -53,6 +53,9 @@ int main(int argc, char **argv) {
   CHECK(sla_courant_max(NULL, &g, NULL, 0.1, &d) == SLA_EINVAL);
   CHECK(sla_advect(NULL, &g, NULL, NULL, 0.1, SLA_CEC, 1, 0, 0.0) == SLA_EINVAL);
   CHECK(sla_advect_noalloc(NULL, &g, NULL, NULL, 0.1, SLA_CEC, 1, 0, 0.0) == SLA_EINVAL);
+  CHECK(sla_tune(NULL, &g, NULL, NULL, 0.1, NULL) == SLA_EINVAL);
+  CHECK(sla_tune_load(NULL, "x") == SLA_EINVAL);
+  CHECK(sla_tune_info(NULL, &g, NULL, NULL, NULL) == SLA_EINVAL);
   CHECK(sla_advect_multi(NULL, &g, 1, &fp, NULL, 0.1, SLA_CEC, 1, 0, 0.0) == SLA_EINVAL);
   CHECK(sla_set_workspace(NULL, NULL, 0) == SLA_EINVAL);
   CHECK(sla_set_option(NULL, 0, 0) == SLA_EINVAL);

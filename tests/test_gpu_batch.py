@@ -107,7 +107,7 @@ def test_plan_with_large_problems(ctx):
     u = W.abc_velocity_torch(shape, dev)
     dx = (2 * np.pi / 256,) * 3
     dt = W.abc_dt(shape, 0.9)
-    big = [W.fourier_modes_torch(shape, 40 + k, dev) for k in range(2)]
+    big = [W.fourier_modes_torch(shape, 40 + k, dev) for k in range(3)]
     probs, small = [], []
     for f in big:
         probs.append((f.clone(), u, dx, dt))
@@ -131,7 +131,62 @@ def test_plan_with_large_problems(ctx):
         ctx.advect(ref, u, dx, dt, native.CEC, steps, 0, 0.0)
         torch.cuda.synchronize()
         assert torch.equal(probs[k][0], ref), k
-    for (phi_d, _, dxs, dts), (f, uu, _, _) in zip(probs[2:], small):
+    for (phi_d, _, dxs, dts), (f, uu, _, _) in zip(probs[3:], small):
         ref = gpu_advect(ctx, f, uu, dxs, dts, oracle.CEC, steps, step0=0)
         assert np.array_equal(phi_d.cpu().numpy().astype(np.float64), ref)
     plan.close()
+
+
+def test_plan_batch_workload_sample(ctx):
+    """A sample of the batched workload at its full sizes: two of the 512^3
+    fields sharing the ABC velocity (8 Fourier modes per axis, seeds 3000 and
+    3001) and the first six of the 64 uneven uniform-velocity grids (sizes
+    seed 3100, velocities seed 3101, fields seeds 3200..), CFL 0.9, three
+    third-order steps in one graph.  Each problem equals its standalone run
+    bit for bit; sampled boxes of the large fields match the oracle."""
+    import torch
+    from paper_1606_06117_amd import native
+    from helpers import box_parity
+    shape = (512, 512, 512)
+    dev = torch.device("cuda:0")
+    u = W.abc_velocity_torch(shape, dev)
+    dx = (2 * np.pi / 512,) * 3
+    dt = W.abc_dt(shape, 0.9)
+    big = [W.fourier_modes_torch(shape, 3000 + k, dev) for k in range(2)]
+    probs = [(f.clone(), u, dx, dt) for f in big]
+    sizes, vels = W.uneven_grids()
+    small = []
+    for j in range(6):
+        n = int(sizes[j])
+        sh = (n, n, n)
+        vel = vels[j].astype(np.float32)
+        dxs = (2 * np.pi / n,) * 3
+        dts = 0.9 * dxs[0] / float(np.max(np.abs(vel)))
+        f = W.fourier_modes(sh, 3200 + j)
+        small.append((f, W.uniform_velocity(sh, vel), dxs, dts))
+        probs.append((torch.from_numpy(f).cuda(), tuple(float(v) for v in vel), dxs, dts))
+    steps = 3
+    plan = native.Plan(ctx, probs, steps, step0=0, tune=False)
+    print("plan", plan.info())
+    plan.run()
+    torch.cuda.synchronize()
+    ctx.check()
+    for k, f in enumerate(big):
+        ref = f.clone()
+        ctx.advect(ref, u, dx, dt, native.CEC, steps, 0, 0.9)
+        torch.cuda.synchronize()
+        assert torch.equal(probs[k][0], ref), k
+    for (phi_d, _, dxs, dts), (f, uu, _, _) in zip(probs[2:], small):
+        ref = gpu_advect(ctx, f, uu, dxs, dts, oracle.CEC, steps, step0=0)
+        assert np.array_equal(phi_d.cpu().numpy().astype(np.float64), ref)
+    # the large fields against the oracle on two boxes each (exact halos)
+    uh = u.cpu().numpy()
+    for k, f in enumerate(big):
+        l2, linf = box_parity(probs[k][0].cpu().numpy().astype(np.float64), f.cpu().numpy(), uh, dx,
+                              dt, oracle.CEC, steps, steps * 3, (16, 16, 16),
+                              np.random.default_rng(20 + k), 2)
+        print(f"512^3 field {k} boxes relL2={l2:.3e} Linf={linf:.3e}")
+        assert l2 <= 1e-5 * steps and linf <= 1e-5 * steps
+    plan.close()
+    del probs, big, u
+    torch.cuda.empty_cache()

@@ -1,9 +1,11 @@
-"""Unsplit FEC and BEC: the fused kernel and the chain of gather kernels.
+"""Unsplit FEC and BEC: the z-march, the LDS-tile kernel and the chain of
+gather kernels.
 
-Both implementations perform the same FP32 operations per node, so they must
-agree bit for bit (SLA_OPT_EC_KERNEL 0, 1 and the default 2), in 1D, 2D and
-3D, below and above CFL 1, on ragged grids; the chain is also held to the
-oracle with the per-step bound of the other parity tests.
+All implementations perform the same FP32 operations per node, so they must
+agree bit for bit (SLA_OPT_EC_KERNEL 0, 1, 2 and the default 3, which at
+reach 1 in 3D runs the z-march), in 1D, 2D and 3D, below and above CFL 1,
+on ragged grids; the chain is also held to the oracle with the per-step
+bound of the other parity tests.
 """
 
 import numpy as np
@@ -52,14 +54,37 @@ def test_chain_matches_fused(ctx, scheme, ndim, cfl):
     from paper_1606_06117_amd import native
     phi, u, dx, dt = _case(ndim, cfl)
     outs = []
-    for ek in (0, 1, 2):
+    for ek in (0, 1, 2, 3):
         ctx.set_option(native.OPT_EC_KERNEL, ek)
         try:
             outs.append(gpu_advect(ctx, phi, u, dx, dt, scheme, 3, step0=1))
         finally:
-            ctx.set_option(native.OPT_EC_KERNEL, 2)
-    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[1], outs[2])
+            ctx.set_option(native.OPT_EC_KERNEL, 3)
+    for o in outs[1:]:
+        assert np.array_equal(outs[0], o)
     ref = oracle_advect(phi, u, dx, dt, scheme, 3, step0=1)
     l2 = rel_l2(outs[1], ref)
     print(f"scheme {scheme} {ndim}D cfl={cfl}: relL2 vs oracle {l2:.2e}")
     assert l2 <= 1e-5 * 3
+
+
+@pytest.mark.parametrize("scheme", [oracle.FEC, oracle.BEC])
+@pytest.mark.parametrize("shape", [(40, 48, 72), (37, 45, 130), (13, 11, 250), (11, 13, 9),
+                                   (150, 20, 64)])
+def test_march_matches_chain(ctx, scheme, shape):
+    """The one-pass z-march (reach 1, 3D) against the chain, bit for bit:
+    partial x windows and row groups, windows past the row's end, rows
+    narrower than a window, march chunks of several lengths."""
+    from paper_1606_06117_amd import native
+    phi = W.random_gaussians(shape, 5, seed=52).astype(np.float32)
+    u = W.abc_velocity(shape)
+    dx = tuple(2 * np.pi / n for n in reversed(shape))
+    dt = 0.9 * min(dx) / 2.0
+    outs = []
+    for ek in (2, 3):
+        ctx.set_option(native.OPT_EC_KERNEL, ek)
+        try:
+            outs.append(gpu_advect(ctx, phi, u, dx, dt, scheme, 2, step0=0))
+        finally:
+            ctx.set_option(native.OPT_EC_KERNEL, 3)
+    assert np.array_equal(outs[0], outs[1])

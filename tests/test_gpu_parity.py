@@ -329,26 +329,31 @@ def test_abc_512_cfl09_cec_boxes(ctx):
     torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("variant", list(range(14)))
+@pytest.mark.parametrize("variant,launch", [(1, 0), (2, 0), (4, 0), (5, 0), (6, 0), (7, 0), (7, 16),
+                                            (8, 0), (8, -16), (8, 1)])
 @pytest.mark.parametrize("step0", [0, 1])
 @pytest.mark.parametrize("shape", [(40, 48, 72), (37, 45, 130), (13, 11, 250), (11, 13, 9)])
-def test_fused_step_matches_sweeps(ctx, step0, variant, shape):
+def test_fused_step_matches_sweeps(ctx, step0, variant, launch, shape):
     """At reach 1 the fused 3D step and the three sweep kernels evaluate the
     same FP32 operations per node, so their results agree bitwise.  The
     second shape leaves partial x windows, row segments and march chunks;
     the third has 5 x windows (a workgroup of 2 windows past the row's end)
     and fewer rows than one shared-halo workgroup holds; in the fourth a row
-    is narrower than a window (its lanes wrap around the row)."""
+    is narrower than a window (its lanes wrap around the row).  Variant 8
+    runs in 16-plane chunks and persistent (its workgroups' ranges then
+    cross from one group of rows into the next)."""
     from paper_1606_06117_amd import native
     phi = W.random_gaussians(shape, 6, seed=31).astype(np.float32)
     u = W.abc_velocity(shape)
     dx = tuple(2 * np.pi / n for n in reversed(shape))
     dt = 0.9 * dx[0] / 2
     ctx.set_option(native.OPT_CEC3D_KERNEL, variant)
+    ctx.set_option(native.OPT_CEC3D_SHAPE, launch)
     try:
         fused = gpu_advect(ctx, phi, u, dx, dt, oracle.CEC, 3, step0=step0)
     finally:
         ctx.set_option(native.OPT_CEC3D_KERNEL, native.CEC3D_DEFAULT)
+        ctx.set_option(native.OPT_CEC3D_SHAPE, 0)
     ctx.set_option(native.OPT_FUSED, 0)
     try:
         sweeps = gpu_advect(ctx, phi, u, dx, dt, oracle.CEC, 3, step0=step0)
@@ -357,6 +362,55 @@ def test_fused_step_matches_sweeps(ctx, step0, variant, shape):
     assert np.array_equal(fused, sweeps)
     ref = oracle_advect(phi, u, dx, dt, oracle.CEC, 3, step0=step0)
     check(fused, ref, phi, 3, f"fused step0={step0}")
+
+
+def test_tuner_choice_is_used_and_gives_the_same_bits(ctx, tmp_path):
+    """sla_tune times every fused-step implementation on the grid, keeps the
+    fastest per parity, writes its table; a fresh context that loads the
+    table runs the same choice.  Results equal the three sweeps bitwise."""
+    import torch
+    from paper_1606_06117_amd import native
+    shape = (48, 40, 72)
+    phi = W.random_gaussians(shape, 6, seed=33).astype(np.float32)
+    u = W.abc_velocity(shape)
+    dx = tuple(2 * np.pi / n for n in reversed(shape))
+    dt = 0.9 * dx[0] / 2
+    path = str(tmp_path / "tune.txt")
+    info = ctx.tune(torch.from_numpy(phi).cuda(), torch.from_numpy(u).cuda(), dx, dt, path)
+    print("tuned", info)
+    assert info is not None
+    for par in ("even", "odd"):
+        v, sh, ms = info[par]
+        assert v in (1, 2, 4, 6, 7, 8) and ms > 0
+    text = open(path).read()
+    assert f"{shape[2]} {shape[1]} {shape[0]} " in text
+    tuned = gpu_advect(ctx, phi, u, dx, dt, oracle.CEC, 3, step0=1)
+    ctx.set_option(native.OPT_FUSED, 0)
+    try:
+        sweeps = gpu_advect(ctx, phi, u, dx, dt, oracle.CEC, 3, step0=1)
+    finally:
+        ctx.set_option(native.OPT_FUSED, 1)
+    assert np.array_equal(tuned, sweeps)
+    other = native.Context(0)
+    try:
+        assert other.tune_info(shape) is None
+        other.tune_load(path)
+        loaded = other.tune_info(shape)
+        for par in ("even", "odd"):  # the table keeps the times to 4 decimals
+            assert loaded[par][:2] == info[par][:2]
+            assert abs(loaded[par][2] - info[par][2]) < 1e-4
+        again = gpu_advect(other, phi, u, dx, dt, oracle.CEC, 3, step0=1)
+        assert np.array_equal(again, sweeps)
+    finally:
+        other.close()
+    # a Courant number of 1 or more is refused
+    with pytest.raises(native.SlaError) as ei:
+        ctx.tune(torch.from_numpy(phi).cuda(), torch.from_numpy(u).cuda(), dx, 2.2 * dt)
+    assert ei.value.status == native.ECOURANT
+    with open(path, "a") as fh:
+        fh.write("1 2 3 x\n")
+    with pytest.raises(native.SlaError):
+        ctx.tune_load(path)
 
 
 @pytest.mark.parametrize("shape,cfl,steps", [
