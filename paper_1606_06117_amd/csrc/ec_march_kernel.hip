@@ -61,12 +61,12 @@ __device__ __forceinline__ int xcd_block() {
   return int(xcd * q + min(xcd, r) + L / 8u);
 }
 
-template <int SCHEME>
+template <int SCHEME, int WX_>
 struct EcShape {
   static constexpr int K = SCHEME == FEC ? 2 : 3;  // calls per step
   static constexpr int S = 16;                     // output rows per workgroup
   static constexpr int NR = S + 2 * K;             // rows of the field (stage 0)
-  static constexpr int WX = SCHEME == FEC ? 2 : 1; // windows per workgroup
+  static constexpr int WX = WX_;                   // windows per workgroup
   static constexpr int W = 4;                      // waves per window
   static constexpr int USE = 64 - 2 * K;           // outputs per window
   static constexpr int LW = 66;                    // LDS row: lanes + 1 on each side
@@ -116,11 +116,11 @@ __device__ __forceinline__ float interp(const float* pm, const float* p0, const 
 
 __device__ __forceinline__ bool over1(float c) { return fabsf(c) >= 1.f; }
 
-template <int SCHEME>
-__global__ __launch_bounds__(64 * EcShape<SCHEME>::W * EcShape<SCHEME>::WX) void k_ec_march(
+template <int SCHEME, int WX_>
+__global__ __launch_bounds__(256 * WX_, (SCHEME == FEC && WX_ == 1) ? 3 : 2) void k_ec_march(
     const float* __restrict__ phi, const float* __restrict__ ux, const float* __restrict__ uy,
     const float* __restrict__ uz, float* __restrict__ out, Geo g, int chunk, int* flag) {
-  using Sh = EcShape<SCHEME>;
+  using Sh = EcShape<SCHEME, WX_>;
   constexpr int K = Sh::K, S = Sh::S, NR = Sh::NR, WX = Sh::WX, W = Sh::W, LW = Sh::LW;
   constexpr int PH = Sh::PH, RING = Sh::RING;
   // rows per wave: stage j covers rows j .. NR - 1 - j
@@ -156,10 +156,31 @@ __global__ __launch_bounds__(64 * EcShape<SCHEME>::W * EcShape<SCHEME>::WX) void
     row[0] = 0.f;
     row[LW - 1] = 0.f;
   }
-  // byte offset within a plane of stage row r (wrapped), the same for the wave
+  // Byte offsets within a plane of the rows each stage of this wave handles
+  // (stage j: rows j + w Rj + k), computed once: the divisions of the
+  // periodic wrap run on the vector unit even for wave-uniform values.
   auto rowoff = [&](int r) { return unsigned(__builtin_amdgcn_readfirstlane(wrapk(y0 - K + r, ny))) * rowb; };
-  auto plane = [&](int p) { return unsigned(__builtin_amdgcn_readfirstlane(wrapk(p, nz))); };
-  // ring slots of a march plane p (p >= m0 - K - 8 > -inf: offset to stay >= 0)
+  // A wave's rows past the end of a stage's range repeat the stage's last
+  // row: they recompute (and rewrite) the same values, so every row runs
+  // the same branch-free code and the rows' LDS reads overlap.
+  auto srow = [&](int j, int rj, int k) { return min(j + w * rj + k, NR - 1 - j); };
+  unsigned off0[R0], off1[R1], off2[R2], off3[R3];
+#pragma unroll
+  for (int k = 0; k < R0; ++k) off0[k] = rowoff(srow(0, R0, k));
+#pragma unroll
+  for (int k = 0; k < R1; ++k) off1[k] = rowoff(srow(1, R1, k));
+#pragma unroll
+  for (int k = 0; k < R2; ++k) off2[k] = rowoff(srow(2, R2, k));
+#pragma unroll
+  for (int k = 0; k < R3; ++k) off3[k] = rowoff(srow(3, R3, k));
+  // plane of stage j at iteration t: q - 2 j with q = m0 - K + t, wrapped;
+  // advanced by one plane per iteration without a division
+  const unsigned plb = unsigned(ny) * rowb;
+  int pl[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) pl[j] = __builtin_amdgcn_readfirstlane(wrapk(m0 - K - 2 * j, nz));
+  auto next = [&](int p) { return p + 1 < nz ? p + 1 : 0; };
+  // ring slots of a march plane p (p >= m0 - K - 8: offset to stay >= 0)
   auto slot5 = [&](int p) { return (p - m0 + 20) % PH; };
   auto slot4 = [&](int p) { return (p - m0 + 20) & (RING - 1); };
 
@@ -169,62 +190,50 @@ __global__ __launch_bounds__(64 * EcShape<SCHEME>::W * EcShape<SCHEME>::WX) void
   // stage's rows (stage j works on plane q - 2 j at iteration t, q = m0 - K + t)
   float fp[R0];
   float fu1[3][R1], fu2[3][R2], fu3[3][R3];
-  auto prefetch = [&](int t) {
-    const int q = m0 - K + t;
-    const unsigned pq = plane(q) * unsigned(ny) * rowb;
+  // np[j]: the plane of stage j at the iteration being prefetched
+  auto prefetch = [&](const int (&np)[4]) {
+    const unsigned pq = unsigned(np[0]) * plb;
 #pragma unroll
-    for (int k = 0; k < R0; ++k) {
-      const int r = w * R0 + k;
-      if (r < NR) fp[k] = ld_vs(phi, vx, pq + rowoff(r));
-    }
-    const unsigned p1 = plane(q - 2) * unsigned(ny) * rowb;
+    for (int k = 0; k < R0; ++k) fp[k] = ld_vs(phi, vx, pq + off0[k]);
+    const unsigned p1 = unsigned(np[1]) * plb;
 #pragma unroll
     for (int k = 0; k < R1; ++k) {
-      const int r = 1 + w * R1 + k;
-      if (r < NR - 1) {
-        const unsigned o = p1 + rowoff(r);
-        fu1[0][k] = ld_vs(ux, vx, o);
-        fu1[1][k] = ld_vs(uy, vx, o);
-        fu1[2][k] = ld_vs(uz, vx, o);
-      }
+      const unsigned o = p1 + off1[k];
+      fu1[0][k] = ld_vs(ux, vx, o);
+      fu1[1][k] = ld_vs(uy, vx, o);
+      fu1[2][k] = ld_vs(uz, vx, o);
     }
-    const unsigned p2 = plane(q - 4) * unsigned(ny) * rowb;
+    const unsigned p2 = unsigned(np[2]) * plb;
 #pragma unroll
     for (int k = 0; k < R2; ++k) {
-      const int r = 2 + w * R2 + k;
-      if (r < NR - 2) {
-        const unsigned o = p2 + rowoff(r);
-        fu2[0][k] = ld_vs(ux, vx, o);
-        fu2[1][k] = ld_vs(uy, vx, o);
-        fu2[2][k] = ld_vs(uz, vx, o);
-      }
+      const unsigned o = p2 + off2[k];
+      fu2[0][k] = ld_vs(ux, vx, o);
+      fu2[1][k] = ld_vs(uy, vx, o);
+      fu2[2][k] = ld_vs(uz, vx, o);
     }
     if (SCHEME == BEC) {
-      const unsigned p3 = plane(q - 6) * unsigned(ny) * rowb;
+      const unsigned p3 = unsigned(np[3]) * plb;
 #pragma unroll
       for (int k = 0; k < R3; ++k) {
-        const int r = 3 + w * R3 + k;
-        if (r < NR - 3) {
-          const unsigned o = p3 + rowoff(r);
-          fu3[0][k] = ld_vs(ux, vx, o);
-          fu3[1][k] = ld_vs(uy, vx, o);
-          fu3[2][k] = ld_vs(uz, vx, o);
-        }
+        const unsigned o = p3 + off3[k];
+        fu3[0][k] = ld_vs(ux, vx, o);
+        fu3[1][k] = ld_vs(uy, vx, o);
+        fu3[2][k] = ld_vs(uz, vx, o);
       }
     }
   };
   const bool lane_out = lane >= K && lane < 64 - K && wx * Sh::USE + lane - K < nx;
-  if (wx_ok) prefetch(0);
+  if (wx_ok) prefetch(pl);
   for (int t = 0; t < iters; ++t) {
     const int q = m0 - K + t;
+    int npl[4];  // the planes of iteration t + 1
+#pragma unroll
+    for (int j = 0; j < 4; ++j) npl[j] = next(pl[j]);
     __syncthreads();  // the writes of earlier iterations are visible, their reads done
     if (wx_ok) {
       // stage 0: the field of plane q
 #pragma unroll
-      for (int k = 0; k < R0; ++k) {
-        const int r = w * R0 + k;
-        if (r < NR) lphi[slot5(q)][xi][r][l] = fp[k];
-      }
+      for (int k = 0; k < R0; ++k) lphi[slot5(q)][xi][srow(0, R0, k)][l] = fp[k];
       float u1[3][R1], u2[3][R2], u3[3][R3];
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
@@ -236,7 +245,7 @@ __global__ __launch_bounds__(64 * EcShape<SCHEME>::W * EcShape<SCHEME>::WX) void
 #pragma unroll
           for (int k = 0; k < R3; ++k) u3[d][k] = fu3[d][k];
       }
-      if (t + 1 < iters) prefetch(t + 1);
+      if (t + 1 < iters) prefetch(npl);
       // stage 1 at plane q - 2: Phi1 = L_U Phi
       {
         const int p = q - 2;
@@ -245,12 +254,10 @@ __global__ __launch_bounds__(64 * EcShape<SCHEME>::W * EcShape<SCHEME>::WX) void
         const float* pp = &lphi[slot5(p + 1)][xi][0][0];
 #pragma unroll
         for (int k = 0; k < R1; ++k) {
-          const int r = 1 + w * R1 + k;
-          if (r < NR - 1) {
-            const float cx = u1[0][k] * lx, cy = u1[1][k] * ly, cz = u1[2][k] * lz;
-            over |= over1(cx) || over1(cy) || over1(cz);
-            lst[0][slot4(p)][xi][r][l] = interp<LW>(pm, p0, pp, r, l, cx, cy, cz);
-          }
+          const int r = srow(1, R1, k);
+          const float cx = u1[0][k] * lx, cy = u1[1][k] * ly, cz = u1[2][k] * lz;
+          over |= over1(cx) || over1(cy) || over1(cz);
+          lst[0][slot4(p)][xi][r][l] = interp<LW>(pm, p0, pp, r, l, cx, cy, cz);
         }
       }
       // stage 2 at plane q - 4: the reverse call on Phi1, then FEC's result
@@ -261,21 +268,19 @@ __global__ __launch_bounds__(64 * EcShape<SCHEME>::W * EcShape<SCHEME>::WX) void
         const float* p0 = &lst[0][slot4(p)][xi][0][0];
         const float* pp = &lst[0][slot4(p + 1)][xi][0][0];
         const float* f0 = &lphi[slot5(p)][xi][0][0];
-        const unsigned po = plane(p) * unsigned(ny) * rowb;
+        const unsigned po = unsigned(pl[2]) * plb;
 #pragma unroll
         for (int k = 0; k < R2; ++k) {
-          const int r = 2 + w * R2 + k;
-          if (r < NR - 2) {
-            const float cx = -(u2[0][k] * lx), cy = -(u2[1][k] * ly), cz = -(u2[2][k] * lz);
-            const float rv = interp<LW>(pm, p0, pp, r, l, cx, cy, cz);
-            const float fv = f0[r * LW + l];
-            if (SCHEME == FEC) {
-              // out = Phi1 + (Phi - L_{-U} Phi1)/2
-              const float o = fmaf(0.5f, fv - rv, p0[r * LW + l]);
-              if (t >= 3 * K && lane_out && y0 - K + r < ny) st_vs(out, vx, po + rowoff(r), o);
-            } else {
-              lst[Sh::STAGES - 1][slot4(p)][xi][r][l] = fmaf(0.5f, fv - rv, fv);  // psi
-            }
+          const int r = srow(2, R2, k);
+          const float cx = -(u2[0][k] * lx), cy = -(u2[1][k] * ly), cz = -(u2[2][k] * lz);
+          const float rv = interp<LW>(pm, p0, pp, r, l, cx, cy, cz);
+          const float fv = f0[r * LW + l];
+          if (SCHEME == FEC) {
+            // out = Phi1 + (Phi - L_{-U} Phi1)/2
+            const float o = fmaf(0.5f, fv - rv, p0[r * LW + l]);
+            if (t >= 3 * K && lane_out && y0 - K + r < ny) st_vs(out, vx, po + off2[k], o);
+          } else {
+            lst[Sh::STAGES - 1][slot4(p)][xi][r][l] = fmaf(0.5f, fv - rv, fv);  // psi
           }
         }
       }
@@ -285,18 +290,18 @@ __global__ __launch_bounds__(64 * EcShape<SCHEME>::W * EcShape<SCHEME>::WX) void
         const float* pm = &lst[Sh::STAGES - 1][slot4(p - 1)][xi][0][0];
         const float* p0 = &lst[Sh::STAGES - 1][slot4(p)][xi][0][0];
         const float* pp = &lst[Sh::STAGES - 1][slot4(p + 1)][xi][0][0];
-        const unsigned po = plane(p) * unsigned(ny) * rowb;
+        const unsigned po = unsigned(pl[3]) * plb;
 #pragma unroll
         for (int k = 0; k < R3; ++k) {
-          const int r = 3 + w * R3 + k;
-          if (r < NR - 3) {
-            const float cx = u3[0][k] * lx, cy = u3[1][k] * ly, cz = u3[2][k] * lz;
-            const float o = interp<LW>(pm, p0, pp, r, l, cx, cy, cz);
-            if (t >= 3 * K && lane_out && y0 - K + r < ny) st_vs(out, vx, po + rowoff(r), o);
-          }
+          const int r = srow(3, R3, k);
+          const float cx = u3[0][k] * lx, cy = u3[1][k] * ly, cz = u3[2][k] * lz;
+          const float o = interp<LW>(pm, p0, pp, r, l, cx, cy, cz);
+          if (t >= 3 * K && lane_out && y0 - K + r < ny) st_vs(out, vx, po + off3[k], o);
         }
       }
     }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) pl[j] = npl[j];
   }
   if (over) *flag = 1;
 }
@@ -310,15 +315,15 @@ hipError_t launch_ec_march(int scheme, const Geo& g, const float* phi, const flo
   const size_t n = (size_t)g.ncells;
   auto shape = [&](auto sch) {
     constexpr int SC = decltype(sch)::value;
-    using Sh = EcShape<SC>;
+    using Sh = EcShape<SC, 1>;
     const long long groups =
         (long long)(((g.nx + Sh::USE - 1) / Sh::USE + Sh::WX - 1) / Sh::WX) * ((g.ny + Sh::S - 1) / Sh::S);
     // march chunks of 128 planes, shorter while that leaves under 1024 workgroups
     int chunk = 128;
     while (chunk > 16 && groups * ((g.nz + chunk - 1) / chunk) < 1024) chunk /= 2;
     const dim3 grid(unsigned(groups * ((g.nz + chunk - 1) / chunk)));
-    hipLaunchKernelGGL(k_ec_march<SC>, grid, dim3(64 * Sh::W * Sh::WX), 0, st, phi, u, u + n, u + 2 * n,
-                       out, g, chunk, flag);
+    hipLaunchKernelGGL((k_ec_march<SC, 1>), grid, dim3(64 * Sh::W * Sh::WX), 0, st, phi, u, u + n,
+                       u + 2 * n, out, g, chunk, flag);
     return hipGetLastError();
   };
   if (scheme == FEC) return shape(std::integral_constant<int, FEC>{});
