@@ -245,7 +245,14 @@ typedef enum {
    * kernel that reads the shared velocity once per tile for all of them
    * (third-order 3D steps at reach 1): 4 (default) or 2; 0 or 1: field after
    * field.  Same results. */
-  SLA_OPT_SHARED_VELOCITY = 6
+  SLA_OPT_SHARED_VELOCITY = 6,
+  /* Launch shape of the unsplit FEC/BEC z-march (same results whatever the
+   * value): < 0 one workgroup per chunk of -value planes of a group; > 0
+   * that many persistent workgroups per CU (at most as many as fit), each
+   * marching one range of the groups' planes laid end to end; 0 (default)
+   * chunks of 64 planes, or 32 or 16 when that leaves under 2048
+   * workgroups. */
+  SLA_OPT_EC_SHAPE = 7
 } sla_option;
 /* Set option `option` to `value`.  Returns SLA_EINVAL for an unknown option
  * or value. */

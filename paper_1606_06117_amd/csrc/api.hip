@@ -30,6 +30,7 @@ struct sla_ctx {
   int sweep_kernel = 2;  // SLA_OPT_SWEEP_KERNEL
   int ec_kernel = 3;     // SLA_OPT_EC_KERNEL
   int cec3d_shape = 0;   // SLA_OPT_CEC3D_SHAPE
+  int ec_shape = 0;      // SLA_OPT_EC_SHAPE
   // fused-step choices measured by sla_tune (or loaded), per grid
   struct Tuned {
     int n[3];
@@ -721,7 +722,7 @@ int advect_steps(sla_ctx* ctx, const sla_grid* grid, float* phi, const float* u,
         // (256^3 and 512^3, CFL 0.9 to 2.5)
         if (ctx->ec_kernel == 3 && ndim == 3 && rmax == 1 && sla::offsets32_ok(geo)) {
           e = run(ctx, kind, [&] {
-            return sla::launch_ec_march(scheme, geo, cur, u, nxt, ctx->flag, ctx->stream);
+            return sla::launch_ec_march(scheme, geo, cur, u, nxt, ctx->flag, ctx->stream, ctx->ec_shape);
           });
           std::swap(cur, nxt);
           break;
@@ -894,6 +895,10 @@ int sla_set_option(sla_ctx* ctx, int option, int64_t value) {
       if (value != 0 && value != 1 && value != 2 && value != 4)
         return fail(ctx, SLA_EINVAL, "SLA_OPT_SHARED_VELOCITY takes 0, 1, 2 or 4");
       ctx->multi = value <= 1 ? 1 : int(value);
+      return SLA_OK;
+    case SLA_OPT_EC_SHAPE:
+      if (value < -4096 || value > 64) return fail(ctx, SLA_EINVAL, "SLA_OPT_EC_SHAPE takes -4096..64");
+      ctx->ec_shape = int(value);
       return SLA_OK;
     case SLA_OPT_LEARNED_KERNEL:
       if (value != 0 && value != 1) return fail(ctx, SLA_EINVAL, "SLA_OPT_LEARNED_KERNEL takes 0 or 1");

@@ -1089,14 +1089,20 @@ hipError_t launch_wp_t(const Geo& g, const float* phi, const float* u, float* ou
 
 // shape > 0: persistent, workgroups per CU; < 0: march chunks of -shape
 // planes, one workgroup per chunk of a group; 0: persistent, as many as fit
-// pf: planes loaded ahead of the march (1 or 2)
+// pf: planes loaded ahead of the march (1 or 2); wx: windows per workgroup
 hipError_t launch_cec3d_wp(bool even, const Geo& g, const float* phi, const float* u, float* out,
-                           int* flag, hipStream_t st, Cec3dLaunch lc, int pf = 1) {
-  if (pf == 2)
-    return even ? launch_wp_t<true, kWpV, kWpW, kWpWX, 2>(g, phi, u, out, flag, st, lc.ychunk)
-                : launch_wp_t<false, kWpV, kWpW, kWpWX, 2>(g, phi, u, out, flag, st, lc.ychunk);
-  return even ? launch_wp_t<true, kWpV, kWpW, kWpWX, 1>(g, phi, u, out, flag, st, lc.ychunk)
-              : launch_wp_t<false, kWpV, kWpW, kWpWX, 1>(g, phi, u, out, flag, st, lc.ychunk);
+                           int* flag, hipStream_t st, Cec3dLaunch lc, int pf = 1, int wx = kWpWX) {
+  auto go = [&](auto wxc) {
+    constexpr int WXC = decltype(wxc)::value;
+    if (pf == 2)
+      return even ? launch_wp_t<true, kWpV, kWpW, WXC, 2>(g, phi, u, out, flag, st, lc.ychunk)
+                  : launch_wp_t<false, kWpV, kWpW, WXC, 2>(g, phi, u, out, flag, st, lc.ychunk);
+    return even ? launch_wp_t<true, kWpV, kWpW, WXC, 1>(g, phi, u, out, flag, st, lc.ychunk)
+                : launch_wp_t<false, kWpV, kWpW, WXC, 1>(g, phi, u, out, flag, st, lc.ychunk);
+  };
+  if (wx == 1) return go(std::integral_constant<int, 1>{});
+  if (wx == 2) return go(std::integral_constant<int, 2>{});
+  return go(std::integral_constant<int, kWpWX>{});
 }
 
 // ---------------------------------------------------------------------------
@@ -1729,6 +1735,8 @@ hipError_t launch_cec3d(int variant, bool even, const Geo& g, const float* phi, 
   if (variant == 7) return launch_cec3d_wl(even, g, phi, u, out, flag, st, lc);
   if (variant == 8) return launch_cec3d_wp(even, g, phi, u, out, flag, st, lc);
   if (variant == 9) return launch_cec3d_wp(even, g, phi, u, out, flag, st, lc, 2);
+  if (variant >= 10 && variant <= 13)
+    return launch_cec3d_wp(even, g, phi, u, out, flag, st, lc, 1 + (variant & 1), variant < 12 ? 1 : 2);
   if (variant == 5) {
     // the fastest implementation of each parity as measured from 256^3 to
     // 1024^3 (the tuner, sla_tune, measures the grid at hand instead): up to

@@ -46,7 +46,7 @@ hipError_t launch_ec(int ndim, int scheme, int R, const Geo& g, const float* phi
 // (a z-march with every stage's field in LDS); needs offsets32_ok(g).  Same
 // results as the chain of gather kernels.
 hipError_t launch_ec_march(int scheme, const Geo& g, const float* phi, const float* u, float* out,
-                           int* flag, hipStream_t st);
+                           int* flag, hipStream_t st, int shape = 0);
 
 // One third-order sweep along axis d with reach R; u_d is that axis' plane.
 // march: y and z sweeps of grids of at most 2^30 cells walk columns through
@@ -77,7 +77,7 @@ hipError_t launch_cec_sweep_xy(int R, bool xfirst, const Geo& g, const float* ph
 // LDS, 8 the same with 16-row groups of 12 waves, in march chunks or
 // persistent, 9 as 8 with the inputs loaded two planes ahead; all perform
 // the same FP32 operations (0 and 3 are unused).
-constexpr int kCec3dVariants = 10;
+constexpr int kCec3dVariants = 14;
 inline bool cec3d_variant_ok(int v) { return v >= 1 && v < kCec3dVariants && v != 3; }
 // Launch shape: y planes per workgroup, or for variant 8 the march chunk
 // (< 0: -chunk planes) or workgroups per CU of the persistent form (> 0);

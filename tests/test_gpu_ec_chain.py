@@ -71,10 +71,12 @@ def test_chain_matches_fused(ctx, scheme, ndim, cfl):
 @pytest.mark.parametrize("scheme", [oracle.FEC, oracle.BEC])
 @pytest.mark.parametrize("shape", [(40, 48, 72), (37, 45, 130), (13, 11, 250), (11, 13, 9),
                                    (150, 20, 64)])
-def test_march_matches_chain(ctx, scheme, shape):
+@pytest.mark.parametrize("launch", [0, -16, 1])
+def test_march_matches_chain(ctx, scheme, shape, launch):
     """The one-pass z-march (reach 1, 3D) against the chain, bit for bit:
     partial x windows and row groups, windows past the row's end, rows
-    narrower than a window, march chunks of several lengths."""
+    narrower than a window; persistent workgroups whose plane ranges cross
+    from one group into the next (0, 1 per CU) and march chunks (-16)."""
     from paper_1606_06117_amd import native
     phi = W.random_gaussians(shape, 5, seed=52).astype(np.float32)
     u = W.abc_velocity(shape)
@@ -83,8 +85,10 @@ def test_march_matches_chain(ctx, scheme, shape):
     outs = []
     for ek in (2, 3):
         ctx.set_option(native.OPT_EC_KERNEL, ek)
+        ctx.set_option(native.OPT_EC_SHAPE, launch)
         try:
             outs.append(gpu_advect(ctx, phi, u, dx, dt, scheme, 2, step0=0))
         finally:
             ctx.set_option(native.OPT_EC_KERNEL, 3)
+            ctx.set_option(native.OPT_EC_SHAPE, 0)
     assert np.array_equal(outs[0], outs[1])
