@@ -250,8 +250,8 @@ typedef enum {
    * value): < 0 one workgroup per chunk of -value planes of a group; > 0
    * that many persistent workgroups per CU (at most as many as fit), each
    * marching one range of the groups' planes laid end to end; 0 (default)
-   * chunks of 64 planes, or 32 or 16 when that leaves under 2048
-   * workgroups. */
+   * chunks whose count minimises rounds of workgroups x (planes per chunk +
+   * pipeline fill). */
   SLA_OPT_EC_SHAPE = 7
 } sla_option;
 /* Set option `option` to `value`.  Returns SLA_EINVAL for an unknown option

@@ -385,12 +385,22 @@ hipError_t launch_ec_march(int scheme, const Geo& g, const float* phi, const flo
     long long blocks;
     int span;
     if (shape == 0) {
-      // march chunks of 64 planes, shorter while that leaves under 2048
-      // workgroups (several rounds per CU); faster than persistent ranges
-      // because the workgroups in flight then march the same planes of
-      // neighbouring groups, whose shared halo rows meet in L2
-      shape = -64;
-      while (shape < -16 && groups * ((g.nz - shape - 1) / -shape) < 2048) shape /= 2;
+      // March chunks (faster than persistent ranges: the workgroups in
+      // flight then march the same planes of neighbouring groups, whose
+      // shared halo rows meet in L2).  The chunk count minimises the time
+      // model rounds x (planes per chunk + pipeline fill), rounds being the
+      // waves of workgroups the chip holds at once; chunks of 16 planes or
+      // more.
+      const long long slots = (long long)cus * fit;
+      long long best = -1;
+      for (int nch = 1; nch == 1 || (g.nz + nch - 1) / nch >= 16; ++nch) {
+        const long long rounds = (groups * nch + slots - 1) / slots;
+        const long long cost = rounds * ((g.nz + nch - 1) / nch + 3 * Sh::K);
+        if (best < 0 || cost < best) {
+          best = cost;
+          shape = -((g.nz + nch - 1) / nch);
+        }
+      }
     }
     if (shape < 0) {  // chunks of -shape planes, one workgroup each
       span = shape;
