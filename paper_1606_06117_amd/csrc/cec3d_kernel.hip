@@ -165,6 +165,11 @@ __device__ __forceinline__ void st_vs(float* field, unsigned voff, unsigned soff
                                         0, 0);
 }
 
+// Prefetches are unconditional: a load under a condition merges the old and
+// new register values, and the compiler then makes the wave wait for the
+// loads it has just issued; past the end of a march they read valid
+// (wrapped or repeated) planes whose values go unused.
+
 // Minimum waves per SIMD the compiler must leave room for (register budget).
 #ifndef SLA_CEC3D_MIN_WAVES
 #define SLA_CEC3D_MIN_WAVES 2
@@ -361,7 +366,7 @@ __global__ __launch_bounds__(kThreads, SLA_SEG_MIN_WAVES) void k_cec3d_seg(
         CB[ycol(j)] = cb;
       }
     }
-    if (t + 1 < iters) prefetch(t + 1);
+    prefetch(min(t + 1, iters - 1));  // unconditional (see the top of the file)
     __syncthreads();
     // 2. first sweep, one segment per thread
     if (has1) {
@@ -624,7 +629,7 @@ __global__ __launch_bounds__(kThreads) void k_cec3d_wm(const float* __restrict__
       cxo[j] = EVEN ? 0.f : fx[j] * lamX;
       if (!EVEN) over |= over1(cxo[j]);
     }
-    if (t + 1 < iters) prefetch(1);
+    prefetch(1);  // unconditional (see the top of the file)
     // sweep along the segment axis (second for even, first for odd)
     sweep_segment<V>(p, cs, a, flag);
     // sweep along the march axis (even: last; odd: second)
@@ -807,7 +812,7 @@ __global__ __launch_bounds__(64 * W * WX) void k_cec3d_wl(const float* __restric
       cxo[j] = EVEN ? 0.f : fx[j] * lamX;
       if (!EVEN) over |= over1(cxo[j]);
     }
-    if (t + 1 < iters) prefetch(1);
+    prefetch(1);  // unconditional (see the top of the file)
     __syncthreads();
     float p[V + 6], cs[V + 4], a[V], o[V];
 #pragma unroll
@@ -1009,7 +1014,7 @@ __global__ __launch_bounds__(64 * W * WX) void k_cec3d_wp(const float* __restric
         cxo[j] = EVEN ? 0.f : fx[B][j] * lamX;
         if (!EVEN) over |= over1(cxo[j]);
       }
-      if (t + PF < iters) prefetch(std::integral_constant<int, NB == 1 ? 0 : (P0 + 2) % 3>{}, PF);
+      prefetch(std::integral_constant<int, NB == 1 ? 0 : (P0 + 2) % 3>{}, PF);  // unconditional (see the top of the file)
       __syncthreads();
       float p[V + 6], cs[V + 4], a[V], o[V];
 #pragma unroll
@@ -1225,7 +1230,7 @@ __global__ __launch_bounds__(64 * W * WX) void k_cec3d_mf(MfFields fl, const flo
       cxo[j] = EVEN ? 0.f : fx[j] * lamX;
       if (!EVEN) over |= over1(cxo[j]);
     }
-    if (t + 1 < iters) prefetch(1);
+    prefetch(1);  // unconditional (see the top of the file)
 #pragma unroll
     for (int f = 0; f < K; ++f) {
       const int bf = (t * K + f) & 1;

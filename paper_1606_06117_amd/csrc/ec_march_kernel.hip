@@ -274,7 +274,10 @@ __global__ __launch_bounds__(256 * WX_, (SCHEME == FEC && WX_ == 1) ? 3 : 2) voi
         // stage 0: the field of plane q
   #pragma unroll
         for (int k = 0; k < R0; ++k) lphi[slot5(q)][xi][srow(0, R0, k)][l] = fp[k];
-        if (t + 1 < iters) prefetch(std::integral_constant<int, B ^ 1>{}, npl);
+      // unconditional: past the run's end it reads valid planes whose values
+      // go unused (a conditional load would merge old and new register values
+      // and make the wave wait for the loads it has just issued)
+      prefetch(std::integral_constant<int, B ^ 1>{}, npl);
         // Stage j reads planes written in earlier iterations only (its input
         // stage ran two planes ahead) and writes other ring slots, so the
         // stages of one iteration are independent: each issues the reads of

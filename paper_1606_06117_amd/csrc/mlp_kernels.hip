@@ -818,7 +818,10 @@ __global__ __launch_bounds__(kLmThreads, 4) void k_learned_march(const float* __
   // this lane's x (wrapped, so the lanes past a short row hold the nodes
   // that follow it periodically) and the two halo nodes (lanes 0 and 1)
   const unsigned vxl = 4u * unsigned(wrapk(x0 + lane, nx));
-  const unsigned vxh = 4u * unsigned(lane == 0 ? wrapk(x0 - 1, nx) : wrapk(x0 + kLmX, nx));
+  // the halo nodes' offsets: two scalars, chosen per lane where used (a
+  // per-lane register held across the march does not fit)
+  const unsigned hxm = 4u * unsigned(__builtin_amdgcn_readfirstlane(wrapk(x0 - 1, nx)));
+  const unsigned hxp = 4u * unsigned(__builtin_amdgcn_readfirstlane(wrapk(x0 + kLmX, nx)));
   // staged rows: wave w loads row w of y0 - 1 .. y0 + kLmRows, waves 0 and 1
   // also rows kLmRows and kLmRows + 1
   int srow[2];
@@ -831,13 +834,17 @@ __global__ __launch_bounds__(kLmThreads, 4) void k_learned_march(const float* __
   float pre[2], preh[2];
   auto fetch = [&](int zp) {  // the staged rows of plane zp (wrapped)
     const unsigned pz = unsigned(__builtin_amdgcn_readfirstlane(wrapk(zp, nz))) * unsigned(ny);
+    // Every load is unconditional (a load under a condition would make the
+    // wave wait for it at once): the waves that stage one row load a second,
+    // valid, row that goes unused, and lanes past 1 load their own node again
+    // as the unused halo value.
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
-      if (r < nsr) {
-        const unsigned row = (pz + unsigned(srow[r])) * rowb;
-        pre[r] = ld_row(phi1, vxl, row);
-        preh[r] = lane < 2 ? ld_row(phi1, vxh, row) : 0.f;
-      }
+      const unsigned row = (pz + unsigned(srow[r])) * rowb;
+      pre[r] = ld_row(phi1, vxl, row);
+      int ln = lane;
+      asm volatile("" : "+v"(ln));  // recomputes the choice here, every plane
+      preh[r] = ld_row(phi1, ln == 0 ? hxm : ln == 1 ? hxp : vxl, row);
     }
   };
   auto stage = [&](int slot) {
@@ -868,11 +875,13 @@ __global__ __launch_bounds__(kLmThreads, 4) void k_learned_march(const float* __
   for (int z = z0; z < z1; ++z) {
     const int t = z - z0;  // plane z sits in slot (t + 1) % 4
     stage((t + 2) % kLmRing);  // plane z + 1
-    fetch(z + 2);              // in flight while this plane's nodes run
-    // node velocity of this lane (only its Courant numbers are features)
+    // node velocity of this lane (only its Courant numbers are features),
+    // loaded before the next plane's rows: loads complete in order, so the
+    // wait for these leaves that fetch in flight
     const unsigned rowz = (unsigned(z) * unsigned(ny) + unsigned(yc)) * rowb;
-    const float cx = ld_row(ux, vxl, rowz) * geo.lam[0], cy = ld_row(uy, vxl, rowz) * geo.lam[1],
-                cz = ld_row(uz, vxl, rowz) * geo.lam[2];
+    const float ucx = ld_row(ux, vxl, rowz), ucy = ld_row(uy, vxl, rowz), ucz = ld_row(uz, vxl, rowz);
+    fetch(z + 2);  // in flight while this plane's nodes run
+    const float cx = ucx * geo.lam[0], cy = ucy * geo.lam[1], cz = ucz * geo.lam[2];
     __syncthreads();
     // the 27 values around this lane's node: slots of planes z-1, z, z+1,
     // staged rows w .. w + 2, x positions lane .. lane + 2
