@@ -980,8 +980,8 @@ int sla_tune(sla_ctx* ctx, const sla_grid* grid, const float* phi, const float* 
   rc = ensure_work(ctx, n);
   if (rc) return rc;
   // candidates: (variant, launch shape)
-  static const int cand[][2] = {{1, 0}, {2, 0}, {4, 0}, {6, 0}, {7, 0}, {7, 32},
-                                {8, -64}, {8, -32}, {8, 0}};
+  static const int cand[][2] = {{1, 0},   {2, 0},   {4, 0},   {6, 0},    {7, 0},    {7, 32},
+                                {8, -64}, {8, -32}, {8, 0},   {9, -64},  {10, -32}, {11, -32}};
   hipEvent_t a = nullptr, b = nullptr;
   hipError_t e = hipEventCreate(&a);
   if (e == hipSuccess) e = hipEventCreate(&b);

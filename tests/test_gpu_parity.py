@@ -330,7 +330,8 @@ def test_abc_512_cfl09_cec_boxes(ctx):
 
 
 @pytest.mark.parametrize("variant,launch", [(1, 0), (2, 0), (4, 0), (5, 0), (6, 0), (7, 0), (7, 16),
-                                            (8, 0), (8, -16), (8, 1)])
+                                            (8, 0), (8, -16), (8, 1),
+                                            (9, -16), (10, 0), (11, -16), (12, 0), (13, 1)])
 @pytest.mark.parametrize("step0", [0, 1])
 @pytest.mark.parametrize("shape", [(40, 48, 72), (37, 45, 130), (13, 11, 250), (11, 13, 9)])
 def test_fused_step_matches_sweeps(ctx, step0, variant, launch, shape):
