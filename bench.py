@@ -200,6 +200,44 @@ def copy_probe(reps: int, warmup: int) -> int:
     return 0
 
 
+def learned_probe(size: int, reps: int, warmup: int) -> int:
+    """Time the learned step alone (CIR pass + correction) at ``size``^3 with
+    seeded random weights (the limiter keeps the field bounded whatever the
+    network outputs): per-kind kernel times, and the correction's share of
+    the matrix cores' BF16 peak at 12 416 FLOP per node."""
+    import numpy as np
+    import torch
+    sys.path.insert(0, ROOT)
+    from paper_1606_06117_amd import native
+    from paper_1606_06117_amd import workloads as W
+    shape = (size,) * 3
+    dev = torch.device("cuda:0")
+    phi = torch.from_numpy(W.random_gaussians(shape, 8, seed=2000).astype(np.float32)).to(dev)
+    u = W.abc_velocity_torch(shape, dev)
+    dx = (2 * math.pi / size,) * 3
+    dt = W.abc_dt(shape, 0.9)
+    ctx = native.Context(0)
+    model = native.Model(ctx)
+    rng = np.random.default_rng(5)
+    model.set_params((rng.standard_normal(native.MLP_PARAMS) * 0.2).astype(np.float32))
+    model.set_courant_range(1.0)
+    native.advect_learned(ctx, model, phi, u, dx, dt, max(1, warmup), courant_max=0.9)
+    torch.cuda.synchronize()
+    ctx.timing(True)
+    native.advect_learned(ctx, model, phi, u, dx, dt, reps, step0=warmup, courant_max=0.9)
+    torch.cuda.synchronize()
+    times = ctx.timing_read()
+    ctx.timing(False)
+    per = {k: v[1] / v[0] for k, v in times.items()}
+    flops = 12416 * size**3
+    print(json.dumps({"probe": "learned", "grid": [size] * 3, "steps": reps, "per_kind_ms": per,
+                      "ms_per_step": sum(per.values()),
+                      "mfma_frac": flops / (per["learned"] * 1e-3) / 2.5e15}), flush=True)
+    model.close()
+    ctx.close()
+    return 0
+
+
 def learned_section(ctx, size, fields, steps_per_field, cells, iters, batch, lr, rounds):
     """Learned correction vs the plain third-order scheme on the time-modulated
     ABC flow (CFL 0.9 at peak amplitude): training on pairs from the GPU
@@ -333,6 +371,42 @@ def schemes_section(ctx, size, cfl, steps):
     torch.cuda.empty_cache()
     return {"workload": f"every scheme, {size}^3, 8 Gaussians, ABC velocity, CFL {cfl}, {steps} steps each",
             "runs": rows}
+
+
+def ec_section(ctx, size, cfl, steps):
+    """Unsplit FEC and BEC on the headline workload: the one-pass z-march
+    (the default, SLA_OPT_EC_KERNEL 3) against the chain of gather kernels
+    (2), same inputs, same results bit for bit."""
+    import numpy as np
+    import torch
+    from paper_1606_06117_amd import native
+    from paper_1606_06117_amd import workloads as W
+    shape = (size,) * 3
+    dev = torch.device("cuda:0")
+    phi0 = torch.from_numpy(W.random_gaussians(shape, 8, seed=2000).astype(np.float32)).to(dev)
+    u = W.abc_velocity_torch(shape, dev)
+    dx = (2 * math.pi / size,) * 3
+    dt = W.abc_dt(shape, cfl)
+    rows = []
+    for name in ("fec", "bec"):
+        res, ms = {}, {}
+        for ek in (3, 2):
+            ctx.set_option(native.OPT_EC_KERNEL, ek)
+            try:
+                phi = phi0.clone()
+                wall, _, _ = timed_steps(ctx, phi, u, dx, dt, steps, 2, native.SCHEMES[name])
+            finally:
+                ctx.set_option(native.OPT_EC_KERNEL, 3)
+            res[ek] = phi
+            ms[ek] = wall * 1e3 / steps
+        rows.append({"scheme": name, "ms_per_step_march": ms[3], "ms_per_step_chain": ms[2],
+                     "speedup": ms[2] / ms[3], "value_march": size**3 / ms[3] / 1e6,
+                     "unit": "Gcell-updates/s", "same_bits": bool(torch.equal(res[2], res[3]))})
+        del res
+    del phi0, u
+    torch.cuda.empty_cache()
+    return {"workload": f"unsplit FEC and BEC, {size}^3, 8 Gaussians, ABC velocity, CFL {cfl}, "
+                        f"{steps} steps each (after 2 warm-up steps)", "runs": rows}
 
 
 def norms_section(ctx, size, reps):
@@ -481,9 +555,10 @@ def main(argv=None):
     ap.add_argument("--learned-iters", type=int, default=4000, help="Adam steps per training round")
     ap.add_argument("--learned-rounds", type=int, default=2,
                     help="rounds of pairs from the model's own rollouts after the first training")
-    ap.add_argument("--probe", choices=["copy"], default=None,
-                    help="instead of the benchmark, time a plain device copy of known size "
-                         "(achievable bandwidth; calibrates HBM byte counters)")
+    ap.add_argument("--probe", choices=["copy", "learned"], default=None,
+                    help="instead of the benchmark: copy, time a plain device copy of known size "
+                         "(achievable bandwidth; calibrates HBM byte counters); learned, time the "
+                         "learned step alone at --learned-size with random weights")
     args = ap.parse_args(argv)
 
     if args.gpus != 1:
@@ -496,6 +571,8 @@ def main(argv=None):
 
     if args.probe == "copy":
         return copy_probe(args.steps, args.warmup)
+    if args.probe == "learned":
+        return learned_probe(args.learned_size, args.steps, args.warmup)
 
     sys.path.insert(0, ROOT)
     from paper_1606_06117_amd import native
@@ -611,6 +688,7 @@ def main(argv=None):
         section("strang", "Strang splitting at CFL 0.9 and 1.5", cfl_section, ctx, args.size,
                 (0.9, 1.5), 10, native.CEC_STRANG, "third order with Strang splitting")
         section("schemes_256", "every scheme at 256^3, CFL 1.5", schemes_section, ctx, 256, 1.5, 10)
+        section("ec_512", "unsplit FEC and BEC, march against chain", ec_section, ctx, args.size, 0.9, 10)
         section("norms_512", "FP64 reductions at 512^3", norms_section, ctx, 512, 20)
     if args.large == "on":
         section("large", "1024^3 at CFL 2.0", large_section, ctx, 1024, 2.0, 10)
