@@ -128,9 +128,15 @@ __global__ __launch_bounds__(256 * WX_, (SCHEME == FEC && WX_ == 1) ? 3 : 2) voi
   constexpr int PH = Sh::PH, RING = Sh::RING;
   // rows per wave: stage j covers rows j .. NR - 1 - j
   constexpr int R0 = (NR + W - 1) / W;
-  constexpr int R1 = (NR - 2 + W - 1) / W;
   constexpr int R2 = (NR - 4 + W - 1) / W;
   constexpr int R3 = (NR - 6 + W - 1) / W;
+  // FEC keeps the velocity a wave loaded for stage 1 for its stage 2, two
+  // iterations later, in a ring of registers: a wave's stage-1 rows are then
+  // 1 + R2 w .. 2 + R2 w + R2 (the rows of its stage 2 and one on each side,
+  // neighbouring waves overlapping by two rows, computed twice)
+  constexpr bool VRING = SCHEME == FEC && (NR - 4) % W == 0;
+  constexpr int R1 = VRING ? R2 + 2 : (NR - 2 + W - 1) / W;
+  constexpr int NSET = VRING ? 4 : 2;  // velocity register sets
   __shared__ float lphi[PH][WX][NR][LW];
   __shared__ float lst[Sh::STAGES][RING][WX][NR][LW];
   // the wave's window and row group, the same for all its lanes (made
@@ -184,21 +190,23 @@ __global__ __launch_bounds__(256 * WX_, (SCHEME == FEC && WX_ == 1) ? 3 : 2) voi
     // A wave's rows past the end of a stage's range repeat the stage's last
     // row: they recompute (and rewrite) the same values, so every row runs
     // the same branch-free code and the rows' LDS reads overlap.
-    auto srow = [&](int j, int rj, int k) { return min(j + w * rj + k, NR - 1 - j); };
+    auto srow = [&](int j, int rj, int k) {
+      return min(j + w * (VRING && j == 1 ? R2 : rj) + k, NR - 1 - j);
+    };
     unsigned off0[R0], off1[R1], off2[R2], off3[R3];
-  #pragma unroll
+#pragma unroll
     for (int k = 0; k < R0; ++k) off0[k] = rowoff(srow(0, R0, k));
-  #pragma unroll
+#pragma unroll
     for (int k = 0; k < R1; ++k) off1[k] = rowoff(srow(1, R1, k));
-  #pragma unroll
+#pragma unroll
     for (int k = 0; k < R2; ++k) off2[k] = rowoff(srow(2, R2, k));
-  #pragma unroll
+#pragma unroll
     for (int k = 0; k < R3; ++k) off3[k] = rowoff(srow(3, R3, k));
     // plane of stage j at iteration t: q - 2 j with q = m0 - K + t, wrapped;
     // advanced by one plane per iteration without a division
     const unsigned plb = unsigned(ny) * rowb;
     int pl[4];
-  #pragma unroll
+#pragma unroll
     for (int j = 0; j < 4; ++j) pl[j] = __builtin_amdgcn_readfirstlane(wrapk(m0 - K - 2 * j, nz));
     auto next = [&](int p) { return p + 1 < nz ? p + 1 : 0; };
     // ring slots of a march plane p (p >= m0 - K - 8: offset to stay >= 0)
@@ -211,27 +219,35 @@ __global__ __launch_bounds__(256 * WX_, (SCHEME == FEC && WX_ == 1) ? 3 : 2) voi
     // stage's rows, the one in use and the one loading (stage j works on
     // plane q - 2 j at iteration t, q = m0 - K + t)
     float fp[R0];
-    float fu1[2][3][R1], fu2[2][3][R2], fu3[2][3][R3];
+    float fu1[NSET][3][R1], fu2[VRING ? 1 : 2][3][R2], fu3[2][3][R3];
+    if (VRING) {  // sets read (by stage 2) before any load reached them
+#pragma unroll
+      for (int b = 0; b < NSET; ++b)
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+#pragma unroll
+          for (int k = 0; k < R1; ++k) fu1[b][d][k] = 0.f;
+    }
     // np[j]: the plane of stage j at the iteration being prefetched
     auto prefetch = [&](auto setc, const int (&np)[4]) {
       constexpr int B = decltype(setc)::value;
       const Rsrc rp = plane_rsrc(phi, unsigned(np[0]) * plb);
-  #pragma unroll
+#pragma unroll
       for (int k = 0; k < R0; ++k) fp[k] = ld_row(rp, vx, off0[k]);
       {
         const unsigned o = unsigned(np[1]) * plb;
         const Rsrc rx = plane_rsrc(ux, o), ry = plane_rsrc(uy, o), rz = plane_rsrc(uz, o);
-  #pragma unroll
+#pragma unroll
         for (int k = 0; k < R1; ++k) {
           fu1[B][0][k] = ld_row(rx, vx, off1[k]);
           fu1[B][1][k] = ld_row(ry, vx, off1[k]);
           fu1[B][2][k] = ld_row(rz, vx, off1[k]);
         }
       }
-      {
+      if (!VRING) {
         const unsigned o = unsigned(np[2]) * plb;
         const Rsrc rx = plane_rsrc(ux, o), ry = plane_rsrc(uy, o), rz = plane_rsrc(uz, o);
-  #pragma unroll
+#pragma unroll
         for (int k = 0; k < R2; ++k) {
           fu2[B][0][k] = ld_row(rx, vx, off2[k]);
           fu2[B][1][k] = ld_row(ry, vx, off2[k]);
@@ -241,7 +257,7 @@ __global__ __launch_bounds__(256 * WX_, (SCHEME == FEC && WX_ == 1) ? 3 : 2) voi
       if (SCHEME == BEC) {
         const unsigned o = unsigned(np[3]) * plb;
         const Rsrc rx = plane_rsrc(ux, o), ry = plane_rsrc(uy, o), rz = plane_rsrc(uz, o);
-  #pragma unroll
+#pragma unroll
         for (int k = 0; k < R3; ++k) {
           fu3[B][0][k] = ld_row(rx, vx, off3[k]);
           fu3[B][1][k] = ld_row(ry, vx, off3[k]);
@@ -267,17 +283,17 @@ __global__ __launch_bounds__(256 * WX_, (SCHEME == FEC && WX_ == 1) ? 3 : 2) voi
       constexpr int B = decltype(setc)::value;
       const int q = m0 - K + t;
       int npl[4];  // the planes of iteration t + 1
-  #pragma unroll
+#pragma unroll
       for (int j = 0; j < 4; ++j) npl[j] = next(pl[j]);
       __syncthreads();  // the writes of earlier iterations are visible, their reads done
       if (wx_ok) {
         // stage 0: the field of plane q
-  #pragma unroll
+#pragma unroll
         for (int k = 0; k < R0; ++k) lphi[slot5(q)][xi][srow(0, R0, k)][l] = fp[k];
       // unconditional: past the run's end it reads valid planes whose values
       // go unused (a conditional load would merge old and new register values
       // and make the wave wait for the loads it has just issued)
-      prefetch(std::integral_constant<int, B ^ 1>{}, npl);
+      prefetch(std::integral_constant<int, (B + 1) % NSET>{}, npl);
         // Stage j reads planes written in earlier iterations only (its input
         // stage ran two planes ahead) and writes other ring slots, so the
         // stages of one iteration are independent: each issues the reads of
@@ -287,7 +303,7 @@ __global__ __launch_bounds__(256 * WX_, (SCHEME == FEC && WX_ == 1) ? 3 : 2) voi
         if (SCHEME == BEC) {
           const float* a0 = col(&lst[Sh::STAGES - 1][slot4(p3)][xi][0][0]);
           Call c[R3];
-  #pragma unroll
+#pragma unroll
           for (int k = 0; k < R3; ++k) {
             const int r = srow(3, R3, k);
             const float cx = fu3[B][0][k] * lx, cy = fu3[B][1][k] * ly, cz = fu3[B][2][k] * lz;
@@ -295,7 +311,7 @@ __global__ __launch_bounds__(256 * WX_, (SCHEME == FEC && WX_ == 1) ? 3 : 2) voi
             corners<LW>(c[k], na, na + far_off(slot4(p3), slot4(p3 - 1), slot4(p3 + 1), cz), cx, cy, cz);
           }
           const Rsrc ro = plane_rsrc(out, unsigned(pl[3]) * plb);
-  #pragma unroll
+#pragma unroll
           for (int k = 0; k < R3; ++k) {
             const float o = blend(c[k]);
             if (t >= 3 * K && lane_out && y0 - K + srow(3, R3, k) < ny) st_row(ro, vx, off3[k], o);
@@ -308,16 +324,22 @@ __global__ __launch_bounds__(256 * WX_, (SCHEME == FEC && WX_ == 1) ? 3 : 2) voi
           const float* f0 = col(&lphi[slot5(p2)][xi][0][0]);
           Call c[R2];
           float fv[R2];
-  #pragma unroll
+#pragma unroll
           for (int k = 0; k < R2; ++k) {
             const int r = srow(2, R2, k);
-            const float cx = -(fu2[B][0][k] * lx), cy = -(fu2[B][1][k] * ly), cz = -(fu2[B][2][k] * lz);
+            // the velocity of row r: FEC's ring set of two iterations ago
+            // (stage 1 then worked on this plane; row r is its row k + 1)
+            constexpr int B2 = (B + NSET - 2) % NSET;
+            const float vx_ = VRING ? fu1[B2][0][k + 1] : fu2[VRING ? 0 : B][0][k];
+            const float vy_ = VRING ? fu1[B2][1][k + 1] : fu2[VRING ? 0 : B][1][k];
+            const float vz_ = VRING ? fu1[B2][2][k + 1] : fu2[VRING ? 0 : B][2][k];
+            const float cx = -(vx_ * lx), cy = -(vy_ * ly), cz = -(vz_ * lz);
             const float* na = a0 + r * LW;
             corners<LW>(c[k], na, na + far_off(slot4(p2), slot4(p2 - 1), slot4(p2 + 1), cz), cx, cy, cz);
             fv[k] = f0[r * LW];
           }
           const Rsrc ro = plane_rsrc(out, unsigned(pl[2]) * plb);
-  #pragma unroll
+#pragma unroll
           for (int k = 0; k < R2; ++k) {
             const int r = srow(2, R2, k);
             const float rv = blend(c[k]);
@@ -337,7 +359,7 @@ __global__ __launch_bounds__(256 * WX_, (SCHEME == FEC && WX_ == 1) ? 3 : 2) voi
         {
           const float* a0 = col(&lphi[slot5(p1)][xi][0][0]);
           Call c[R1];
-  #pragma unroll
+#pragma unroll
           for (int k = 0; k < R1; ++k) {
             const int r = srow(1, R1, k);
             const float cx = fu1[B][0][k] * lx, cy = fu1[B][1][k] * ly, cz = fu1[B][2][k] * lz;
@@ -345,17 +367,21 @@ __global__ __launch_bounds__(256 * WX_, (SCHEME == FEC && WX_ == 1) ? 3 : 2) voi
             const float* na = a0 + r * LW;
             corners<LW>(c[k], na, na + far_off(slot5(p1), slot5(p1 - 1), slot5(p1 + 1), cz), cx, cy, cz);
           }
-  #pragma unroll
+#pragma unroll
           for (int k = 0; k < R1; ++k) lst[0][slot4(p1)][xi][srow(1, R1, k)][l] = blend(c[k]);
         }
       }
-  #pragma unroll
+#pragma unroll
       for (int j = 0; j < 4; ++j) pl[j] = npl[j];
     };
     if (wx_ok) prefetch(std::integral_constant<int, 0>{}, pl);
-    for (int t = 0; t < iters; t += 2) {
+    for (int t = 0; t < iters; t += NSET) {
       body(std::integral_constant<int, 0>{}, t);
       if (t + 1 < iters) body(std::integral_constant<int, 1>{}, t + 1);
+      if (NSET == 4) {
+        if (t + 2 < iters) body(std::integral_constant<int, 2 % NSET>{}, t + 2);
+        if (t + 3 < iters) body(std::integral_constant<int, 3 % NSET>{}, t + 3);
+      }
     }
   }
   if (over) *flag = 1;
