@@ -126,17 +126,22 @@ __global__ __launch_bounds__(256 * WX_, (SCHEME == FEC && WX_ == 1) ? 3 : 2) voi
   using Sh = EcShape<SCHEME, WX_>;
   constexpr int K = Sh::K, S = Sh::S, NR = Sh::NR, WX = Sh::WX, W = Sh::W, LW = Sh::LW;
   constexpr int PH = Sh::PH, RING = Sh::RING;
-  // rows per wave: stage j covers rows j .. NR - 1 - j
-  constexpr int R0 = (NR + W - 1) / W;
-  constexpr int R2 = (NR - 4 + W - 1) / W;
-  constexpr int R3 = (NR - 6 + W - 1) / W;
-  // FEC keeps the velocity a wave loaded for stage 1 for its stage 2, two
-  // iterations later, in a ring of registers: a wave's stage-1 rows are then
-  // 1 + R2 w .. 2 + R2 w + R2 (the rows of its stage 2 and one on each side,
-  // neighbouring waves overlapping by two rows, computed twice)
+  // Rows per wave: stage j covers rows j .. NR - 1 - j.  A wave keeps the
+  // velocity it loaded for its stage-1 rows for its later stages (two and
+  // four iterations later) in a ring of register sets, so each node's
+  // velocity is read once.  FEC: a wave's stage-1 rows are 1 + R2 w ..
+  // 2 + R2 w + R2, its stage-2 rows and one on each side (neighbouring waves
+  // overlap by two rows, computed twice).  BEC: every stage of a wave works
+  // on the same RU rows 1 + RU w .., each stage writing only those in its
+  // own range.
   constexpr bool VRING = SCHEME == FEC && (NR - 4) % W == 0;
-  constexpr int R1 = VRING ? R2 + 2 : (NR - 2 + W - 1) / W;
-  constexpr int NSET = VRING ? 4 : 2;  // velocity register sets
+  constexpr bool URING = SCHEME == BEC && (NR - 2) % W == 0;
+  constexpr int RU = (NR - 2 + W - 1) / W;
+  constexpr int R0 = (NR + W - 1) / W;
+  constexpr int R2 = URING ? RU : (NR - 4 + W - 1) / W;
+  constexpr int R3 = URING ? RU : (NR - 6 + W - 1) / W;
+  constexpr int R1 = VRING ? R2 + 2 : RU;
+  constexpr int NSET = VRING ? 4 : URING ? 6 : 2;  // velocity register sets
   __shared__ float lphi[PH][WX][NR][LW];
   __shared__ float lst[Sh::STAGES][RING][WX][NR][LW];
   // the wave's window and row group, the same for all its lanes (made
@@ -191,8 +196,11 @@ __global__ __launch_bounds__(256 * WX_, (SCHEME == FEC && WX_ == 1) ? 3 : 2) voi
     // row: they recompute (and rewrite) the same values, so every row runs
     // the same branch-free code and the rows' LDS reads overlap.
     auto srow = [&](int j, int rj, int k) {
+      if (URING && j >= 1) return 1 + RU * w + k;
       return min(j + w * (VRING && j == 1 ? R2 : rj) + k, NR - 1 - j);
     };
+    // a row of stage j that the stage writes (URING: all rows are computed)
+    auto mine = [&](int j, int r) { return !URING || (r >= j && r <= NR - 1 - j); };
     unsigned off0[R0], off1[R1], off2[R2], off3[R3];
 #pragma unroll
     for (int k = 0; k < R0; ++k) off0[k] = rowoff(srow(0, R0, k));
@@ -219,8 +227,9 @@ __global__ __launch_bounds__(256 * WX_, (SCHEME == FEC && WX_ == 1) ? 3 : 2) voi
     // stage's rows, the one in use and the one loading (stage j works on
     // plane q - 2 j at iteration t, q = m0 - K + t)
     float fp[R0];
-    float fu1[NSET][3][R1], fu2[VRING ? 1 : 2][3][R2], fu3[2][3][R3];
-    if (VRING) {  // sets read (by stage 2) before any load reached them
+    constexpr bool RINGED = VRING || URING;
+    float fu1[NSET][3][R1], fu2[RINGED ? 1 : 2][3][R2], fu3[RINGED ? 1 : 2][3][R3];
+    if (RINGED) {  // sets read (by later stages) before any load reached them
 #pragma unroll
       for (int b = 0; b < NSET; ++b)
 #pragma unroll
@@ -244,7 +253,7 @@ __global__ __launch_bounds__(256 * WX_, (SCHEME == FEC && WX_ == 1) ? 3 : 2) voi
           fu1[B][2][k] = ld_row(rz, vx, off1[k]);
         }
       }
-      if (!VRING) {
+      if (!RINGED) {
         const unsigned o = unsigned(np[2]) * plb;
         const Rsrc rx = plane_rsrc(ux, o), ry = plane_rsrc(uy, o), rz = plane_rsrc(uz, o);
 #pragma unroll
@@ -254,7 +263,7 @@ __global__ __launch_bounds__(256 * WX_, (SCHEME == FEC && WX_ == 1) ? 3 : 2) voi
           fu2[B][2][k] = ld_row(rz, vx, off2[k]);
         }
       }
-      if (SCHEME == BEC) {
+      if (SCHEME == BEC && !RINGED) {
         const unsigned o = unsigned(np[3]) * plb;
         const Rsrc rx = plane_rsrc(ux, o), ry = plane_rsrc(uy, o), rz = plane_rsrc(uz, o);
 #pragma unroll
@@ -306,7 +315,10 @@ __global__ __launch_bounds__(256 * WX_, (SCHEME == FEC && WX_ == 1) ? 3 : 2) voi
 #pragma unroll
           for (int k = 0; k < R3; ++k) {
             const int r = srow(3, R3, k);
-            const float cx = fu3[B][0][k] * lx, cy = fu3[B][1][k] * ly, cz = fu3[B][2][k] * lz;
+            constexpr int B3 = (B + NSET - 4) % NSET;  // the ring set of four iterations ago
+            const float cx = (URING ? fu1[B3][0][k] : fu3[RINGED ? 0 : B][0][k]) * lx;
+            const float cy = (URING ? fu1[B3][1][k] : fu3[RINGED ? 0 : B][1][k]) * ly;
+            const float cz = (URING ? fu1[B3][2][k] : fu3[RINGED ? 0 : B][2][k]) * lz;
             const float* na = a0 + r * LW;
             corners<LW>(c[k], na, na + far_off(slot4(p3), slot4(p3 - 1), slot4(p3 + 1), cz), cx, cy, cz);
           }
@@ -314,7 +326,8 @@ __global__ __launch_bounds__(256 * WX_, (SCHEME == FEC && WX_ == 1) ? 3 : 2) voi
 #pragma unroll
           for (int k = 0; k < R3; ++k) {
             const float o = blend(c[k]);
-            if (t >= 3 * K && lane_out && y0 - K + srow(3, R3, k) < ny) st_row(ro, vx, off3[k], o);
+            const int r = srow(3, R3, k);
+            if (t >= 3 * K && lane_out && y0 - K + r < ny && mine(3, r)) st_row(ro, vx, off3[k], o);
           }
         }
         // stage 2 at plane q - 4: the reverse call on Phi1, then FEC's result
@@ -330,9 +343,10 @@ __global__ __launch_bounds__(256 * WX_, (SCHEME == FEC && WX_ == 1) ? 3 : 2) voi
             // the velocity of row r: FEC's ring set of two iterations ago
             // (stage 1 then worked on this plane; row r is its row k + 1)
             constexpr int B2 = (B + NSET - 2) % NSET;
-            const float vx_ = VRING ? fu1[B2][0][k + 1] : fu2[VRING ? 0 : B][0][k];
-            const float vy_ = VRING ? fu1[B2][1][k + 1] : fu2[VRING ? 0 : B][1][k];
-            const float vz_ = VRING ? fu1[B2][2][k + 1] : fu2[VRING ? 0 : B][2][k];
+            constexpr int K1 = VRING ? 1 : 0;  // FEC: row r is stage 1's row k + 1
+            const float vx_ = RINGED ? fu1[B2][0][k + K1] : fu2[RINGED ? 0 : B][0][k];
+            const float vy_ = RINGED ? fu1[B2][1][k + K1] : fu2[RINGED ? 0 : B][1][k];
+            const float vz_ = RINGED ? fu1[B2][2][k + K1] : fu2[RINGED ? 0 : B][2][k];
             const float cx = -(vx_ * lx), cy = -(vy_ * ly), cz = -(vz_ * lz);
             const float* na = a0 + r * LW;
             corners<LW>(c[k], na, na + far_off(slot4(p2), slot4(p2 - 1), slot4(p2 + 1), cz), cx, cy, cz);
@@ -349,7 +363,7 @@ __global__ __launch_bounds__(256 * WX_, (SCHEME == FEC && WX_ == 1) ? 3 : 2) voi
               const float o = fmaf(0.5f, fv[k] - rv, c[k].v[0]);
               if (t >= 3 * K && lane_out && y0 - K + r < ny) st_row(ro, vx, off2[k], o);
             } else {
-              lst[Sh::STAGES - 1][slot4(p2)][xi][r][l] = fmaf(0.5f, fv[k] - rv, fv[k]);  // psi
+              if (mine(2, r)) lst[Sh::STAGES - 1][slot4(p2)][xi][r][l] = fmaf(0.5f, fv[k] - rv, fv[k]);  // psi
             }
           }
         }
@@ -378,9 +392,13 @@ __global__ __launch_bounds__(256 * WX_, (SCHEME == FEC && WX_ == 1) ? 3 : 2) voi
     for (int t = 0; t < iters; t += NSET) {
       body(std::integral_constant<int, 0>{}, t);
       if (t + 1 < iters) body(std::integral_constant<int, 1>{}, t + 1);
-      if (NSET == 4) {
+      if (NSET >= 4) {
         if (t + 2 < iters) body(std::integral_constant<int, 2 % NSET>{}, t + 2);
         if (t + 3 < iters) body(std::integral_constant<int, 3 % NSET>{}, t + 3);
+      }
+      if (NSET == 6) {
+        if (t + 4 < iters) body(std::integral_constant<int, 4 % NSET>{}, t + 4);
+        if (t + 5 < iters) body(std::integral_constant<int, 5 % NSET>{}, t + 5);
       }
     }
   }
