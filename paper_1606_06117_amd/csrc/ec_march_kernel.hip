@@ -16,9 +16,10 @@
 // planes); a stage at iteration t works on the plane two behind the plane
 // its input stage worked on, so all it reads was written in earlier
 // iterations and one barrier per plane suffices.  Stage 0 is the field
-// itself, loaded once (plus the K halo rows on each side); the velocity of a
-// stage's nodes is read where the stage runs (its second and later reads
-// come from L2).  Each node goes through the same FP32 operations, in the
+// itself, loaded once (plus the K halo rows on each side); the velocity of
+// a node is loaded once, for stage 1, and kept in registers for the node's
+// later stages, which reach it two and four iterations later (a ring of
+// register sets).  Each node goes through the same FP32 operations, in the
 // same order, as the one-call-per-kernel gather chain: the same bits.
 
 #include <type_traits>
