@@ -221,7 +221,9 @@ def learned_probe(size: int, reps: int, warmup: int) -> int:
     rng = np.random.default_rng(5)
     model.set_params((rng.standard_normal(native.MLP_PARAMS) * 0.2).astype(np.float32))
     model.set_courant_range(1.0)
-    native.advect_learned(ctx, model, phi, u, dx, dt, max(1, warmup), courant_max=0.9)
+    # at least 30 warm-up steps (about 15 ms of GPU work): the clocks of an
+    # idle GPU take that long to come up
+    native.advect_learned(ctx, model, phi, u, dx, dt, max(30, warmup), courant_max=0.9)
     torch.cuda.synchronize()
     ctx.timing(True)
     native.advect_learned(ctx, model, phi, u, dx, dt, reps, step0=warmup, courant_max=0.9)

@@ -29,6 +29,7 @@ typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef unsigned uintx4 __attribute__((ext_vector_type(4)));
+typedef unsigned uintx2 __attribute__((ext_vector_type(2)));
 
 // Two values rounded to BF16 (to nearest, ties to even) in one register, lo
 // in bits 0-15: written this way the pair becomes one conversion
@@ -728,8 +729,9 @@ __global__ __launch_bounds__(kThreads) void k_learned_correct(const float* __res
 // is staged in LDS over the window plus one node on each side and the rows
 // plus one on each side (a ring of 4 planes, so one barrier per plane); each
 // lane then builds the features of one node from the 27 staged values
-// around it.  The features reach the matrix-core operand layout through a
-// per-wave LDS tile, and the network runs on the wave's 64 nodes at once.
+// around it.  The features reach the matrix-core operand layout by a
+// transpose across the wave's 16-lane rows on the vector ALU, and the
+// network runs on the wave's 64 nodes at once.
 //
 // The hidden units of the first layer are computed in a permuted row order
 // (W1's columns and b1 are permuted when they are staged): matrix-core tile
@@ -749,7 +751,6 @@ struct MarchLds {
   __bf16 w2t[NH * SH];
   float b1[NH];         // permuted like W1's rows
   float b2[NH], w3[NH], b3;
-  __bf16 feat[kLmRows][64 * SF];
   float phi[kLmRing][kLmH][kLmW];
 };
 static_assert(offsetof(MarchLds, b1) % 16 == 0 && offsetof(MarchLds, b2) % 16 == 0,
@@ -871,7 +872,6 @@ __global__ __launch_bounds__(kLmThreads, 4) void k_learned_march(const float* __
 #pragma unroll
     for (int q = 0; q < 4; ++q) w3r[it][q] = L.w3[16 * it + 4 * g + q];
   const float b3 = L.b3;
-  __bf16* feat = L.feat[w];
   for (int z = z0; z < z1; ++z) {
     const int t = z - z0;  // plane z sits in slot (t + 1) % 4
     stage((t + 2) % kLmRing);  // plane z + 1
@@ -920,17 +920,32 @@ __global__ __launch_bounds__(kLmThreads, 4) void k_learned_march(const float* __
       else if (k == 28) fv[k] = cy;
       else if (k == 29) fv[k] = cz;
     }
+    // chunk j: features 8j..8j+7 of this lane's node (node 16 g + c)
+    uintx4 ch[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      uintx4 fx;
+    for (int j = 0; j < 4; ++j)
 #pragma unroll
-      for (int h = 0; h < 4; ++h) fx[h] = cvt_pk_bf16(fv[8 * q + 2 * h], fv[8 * q + 2 * h + 1]);
-      *reinterpret_cast<uintx4*>(&feat[lane * SF + 8 * q]) = fx;
+      for (int h = 0; h < 4; ++h) ch[j][h] = cvt_pk_bf16(fv[8 * j + 2 * h], fv[8 * j + 2 * h + 1]);
+    // The matrix-core operand of node tile jt on lane (g, c) is chunk g of
+    // node 16 jt + c, held by lane (jt, c): a 4 x 4 transpose of chunks
+    // across the four 16-lane rows, done with gfx950's row swaps between
+    // register pairs (rows r and r ^ 1, then rows r and r ^ 2) on the vector
+    // ALU instead of a round trip through LDS.
+    uintx4 xt[4];
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      const uintx2 p01 = __builtin_amdgcn_permlane16_swap(ch[0][h], ch[1][h], false, false);
+      const uintx2 p23 = __builtin_amdgcn_permlane16_swap(ch[2][h], ch[3][h], false, false);
+      const uintx2 q02 = __builtin_amdgcn_permlane32_swap(p01[0], p23[0], false, false);
+      const uintx2 q13 = __builtin_amdgcn_permlane32_swap(p01[1], p23[1], false, false);
+      unsigned r[4] = {q02[0], q13[0], q02[1], q13[1]};
+      asm("" : "+v"(r[0]), "+v"(r[1]), "+v"(r[2]), "+v"(r[3]));  // see the sum below
+#pragma unroll
+      for (int jt = 0; jt < 4; ++jt) xt[jt][h] = r[jt];
     }
-    wave_lds_sync();
     bf16x8 xb[4];  // node tile jt: features 8g..8g+7 of node 16 jt + c
 #pragma unroll
-    for (int jt = 0; jt < 4; ++jt) xb[jt] = ld8(&feat[(16 * jt + c) * SF + 8 * g]);
+    for (int jt = 0; jt < 4; ++jt) xb[jt] = __builtin_bit_cast(bf16x8, xt[jt]);
     // layer 1 (permuted rows), BF16, ReLU: the second layer's operands in place
     uintx4 h1[4][2];
 #pragma unroll
@@ -959,14 +974,27 @@ __global__ __launch_bounds__(kLmThreads, 4) void k_learned_march(const float* __
         for (int q = 0; q < 4; ++q) s[jt] = fmaf(relu_bits(acc[q]), w3r[it][q], s[jt]);
       }
     }
-    // y of node 16 jt + c, summed over the four lanes that hold the node;
-    // node `lane` (jt = g) is then on this lane
-    float yv[4];
+    // y of node `lane` (16 g + c): the four partial sums of that node are
+    // s[g] on the lanes (j, c), j = 0..3; the same row transpose brings them
+    // to this lane as ps[j], added in the order of sum4g ((0+1) + (2+3))
+    float ps[4];
+    {
+      const uintx2 p01 = __builtin_amdgcn_permlane16_swap(__builtin_bit_cast(unsigned, s[0]),
+                                                          __builtin_bit_cast(unsigned, s[1]), false, false);
+      const uintx2 p23 = __builtin_amdgcn_permlane16_swap(__builtin_bit_cast(unsigned, s[2]),
+                                                          __builtin_bit_cast(unsigned, s[3]), false, false);
+      const uintx2 q02 = __builtin_amdgcn_permlane32_swap(p01[0], p23[0], false, false);
+      const uintx2 q13 = __builtin_amdgcn_permlane32_swap(p01[1], p23[1], false, false);
+      unsigned r[4] = {q02[0], q13[0], q02[1], q13[1]};
+      // the compiler takes the two results of a row swap to be
+      // interchangeable in a sum and folds (a + b) + (c + d) into 2 (a + b):
+      // empty asm statements keep the four values apart
+      asm("" : "+v"(r[0]), "+v"(r[1]), "+v"(r[2]), "+v"(r[3]));
 #pragma unroll
-    for (int jt = 0; jt < 4; ++jt) yv[jt] = sum4g(s[jt]) + b3;
-    const float yn = g == 0 ? yv[0] : g == 1 ? yv[1] : g == 2 ? yv[2] : yv[3];
+      for (int j = 0; j < 4; ++j) ps[j] = __builtin_bit_cast(float, r[j]);
+    }
+    const float yn = ((ps[0] + ps[1]) + (ps[2] + ps[3])) + b3;
     if (lane_ok) st_row(out, vxl, rowz, fminf(fmaxf(fmaf(sigma, yn, centre), lo), hi));
-    wave_lds_sync();  // the feature tile is rewritten at the next plane
   }
 }
 }  // namespace
