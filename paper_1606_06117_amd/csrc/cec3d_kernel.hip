@@ -1111,6 +1111,342 @@ hipError_t launch_cec3d_wp(bool even, const Geo& g, const float* phi, const floa
 }
 
 // ---------------------------------------------------------------------------
+// Aligned two-node window march (variant 14).  The shared-halo march of
+// variant 8 laid out on x windows of 128 nodes that start on 512-byte
+// boundaries: lane l holds nodes 2l and 2l+1 (8-byte loads and stores) and a
+// window computes all 128 of its outputs, so no lane computes a node that
+// another window stores.  The three nodes beyond each end of the window (its
+// x halo) are loaded apart, by six lanes per row.  The x sweep runs across
+// the lanes as in the other variants; it is wrong at the window's first and
+// last three nodes, whose stencils reach into the halo, and those six outputs
+// of a row are computed again by a packed set of edge lanes (one per row and
+// edge node) from the row's two 9-node end segments, gathered in a small LDS
+// area of the wave.  On odd steps, whose x sweep comes last, the halo nodes
+// also go through the z and y sweeps, one (row, node) per lane.  Groups of
+// S = V*W = 32 segment rows (38 loaded), W = 8 waves, one workgroup per CU,
+// march chunks of up to 128 planes.  Per node the same FP32 operations as
+// the other variants.  Needs an even nx (a lane's two nodes are adjacent in
+// memory, also where the window wraps around the row).
+// ---------------------------------------------------------------------------
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned b64_t __attribute__((ext_vector_type(2)));  // the 64-bit buffer builtins' type
+__device__ __forceinline__ f32x2 ld2_vs(const float* field, unsigned voff, unsigned soff) {
+  return __builtin_bit_cast(f32x2, __builtin_amdgcn_raw_buffer_load_b64(based_rsrc(field, soff), voff, 0, 0));
+}
+__device__ __forceinline__ void st2_vs(float* field, unsigned voff, unsigned soff, f32x2 v) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(b64_t, v), based_rsrc(field, soff), voff, 0, 0);
+}
+
+// Third-order sweep along x of a row held as two nodes per lane (lane l:
+// nodes 2l and 2l+1): the same operations per node as xsweep_lanes.  Node
+// 2l-1 is lane l-1's second node, node 2l+2 lane l+1's first; the results of
+// the first and last three nodes of the window are not valid.
+__device__ __forceinline__ void xsweep_pairs(float& a, float& b, float ca, float cb) {
+  const Dep1 da = depart1(ca, nullptr), db = depart1(cb, nullptr);
+  const float pma = from_below(b), ppb = from_above(a);
+  const float p1a = lerp(a, da.ob_neg ? pma : b, da.f);
+  const float p1b = lerp(b, db.ob_neg ? a : ppb, db.f);
+  const float qma = from_below(p1b), qpb = from_above(p1a);
+  const float ea = a - lerp(p1a, da.obr_pos ? p1b : qma, da.f);
+  const float eb = b - lerp(p1b, db.obr_pos ? qpb : p1a, db.f);
+  const float ema = from_below(eb), epb = from_above(ea);
+  const float ba = da.ob_neg ? ema : eb, bb = db.ob_neg ? ea : epb;
+  const float wa = fmaf(da.f, 1.f / 3.f, 1.f / 3.f), wb = fmaf(db.f, 1.f / 3.f, 1.f / 3.f);
+  a = fmaf(0.5f, fmaf(wa, ba - ea, ea), p1a);
+  b = fmaf(0.5f, fmaf(wb, bb - eb, eb), p1b);
+}
+
+constexpr int kWqV = 4, kWqW = 8, kWqN = 128;  // rows per wave, waves per window, window nodes
+
+// Slot of a window-relative node in a row's end segments (24 floats: nodes
+// -3..5 at 1..9, nodes 122..130 at 12..20; a lane's pair starts on an even
+// slot).
+__device__ __forceinline__ int end_slot(int node) { return node < 64 ? node + 4 : node - 110; }
+
+template <bool EVEN, int V, int W>
+__global__ __launch_bounds__(64 * W) void k_cec3d_wq(const float* __restrict__ phi,
+                                                     const float* __restrict__ ux,
+                                                     const float* __restrict__ uy,
+                                                     const float* __restrict__ uz,
+                                                     float* __restrict__ out, Geo g, int chunk,
+                                                     int* flag) {
+  constexpr int S = V * W, NR = S + 6, RW = (NR + W - 1) / W, kAll = NR - (W - 1) * RW;
+  constexpr int LW = kWqN + 8;         // LDS row: the window's nodes, then (odd) its 6 halo nodes
+  constexpr int NE = RW > V ? RW : V;  // rows with end segments per wave
+  static_assert(6 * NE <= 64, "one edge lane per row and end node");
+  __shared__ __align__(16) float lp[2][NR][LW];     // segment sweep input (x-swept if even)
+  __shared__ __align__(16) float lc[2][NR][LW];     // segment-axis Courant numbers
+  __shared__ __align__(16) float es[W][NE][2][24];  // end segments: values, x Courant numbers
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  const int ns = EVEN ? ny : nz, nm = EVEN ? nz : ny;
+  const int nwx = (nx + kWqN - 1) / kWqN, ngs = (ns + S - 1) / S, ng = nwx * ngs;
+  const int blk = block_tile(1).x;  // XCD-mapped 1D grid
+  if (blk >= ng * ((nm + chunk - 1) / chunk)) return;  // the whole workgroup
+  const int ch = blk / ng, grp = blk - ch * ng;
+  const int x0 = (grp % nwx) * kWqN, g0 = (grp / nwx) * S, s0 = g0 + w * V;
+  const int m0 = ch * chunk, m1 = min(nm, m0 + chunk);
+  const unsigned rowb = 4u * unsigned(nx), plb = 4u * unsigned(nx) * unsigned(ny);
+  const unsigned sstr = EVEN ? rowb : plb, mstr = EVEN ? plb : rowb;
+  const float* rS = EVEN ? uy : uz;  // segment-axis velocity
+  const float* rM = EVEN ? uz : uy;  // march-axis velocity
+  const float lamX = g.lam[0], lamS = EVEN ? g.lam[1] : g.lam[2], lamM = EVEN ? g.lam[2] : g.lam[1];
+  const int nld = min(RW, NR - w * RW);  // rows this wave loads: w*RW + k, k < nld
+  // lane 6k + i serves row k of the wave and end node i: the window's nodes
+  // 0..2 and 125..127 (edge nodes), halo nodes -3..-1 and 128..130; lanes
+  // past the rows repeat the last row and their results go unused
+  const int ek = min(lane / 6, NE - 1), ei = lane - 6 * (lane / 6);
+  const int hnode = ei < 3 ? ei - 3 : kWqN + ei - 3;  // window-relative halo node
+  const int enode = ei < 3 ? ei : kWqN - 6 + ei;      // window-relative edge node
+  const unsigned vx = 4u * unsigned(wrapk(x0 + 2 * lane, nx));
+  const unsigned hx = 4u * unsigned(wrapk(x0 + hnode, nx));
+  // per-lane offsets within a march plane of the loaded rows (rows past the
+  // wave's share repeat its last row: every wave issues the same loads, none
+  // under a condition) and of the output rows
+  unsigned lrow[RW], orow[V];
+#pragma unroll
+  for (int k = 0; k < RW; ++k)
+    lrow[k] = vx + unsigned(__builtin_amdgcn_readfirstlane(wrapk(g0 - 3 + w * RW + min(k, nld - 1), ns))) * sstr;
+#pragma unroll
+  for (int j = 0; j < V; ++j)
+    orow[j] = vx + unsigned(__builtin_amdgcn_readfirstlane(wrapk(s0 + j, ns))) * sstr;
+  // the halo node's offsets in loaded row min(ek, nld - 1) and output row min(ek, V - 1)
+  const unsigned hlrow = hx + unsigned(wrapk(g0 - 3 + w * RW + min(ek, nld - 1), ns)) * sstr;
+  const unsigned horow = hx + unsigned(wrapk(s0 + min(ek, V - 1), ns)) * sstr;
+  PlaneWin pw(m0 - 6, nm);  // planes m0 - 6 + t .. m0 - 1 + t at iteration t
+
+  f32x2 fp[RW], fa[RW], fs[RW];  // loaded rows: phi, x velocity (even), segment velocity
+  f32x2 fm[V], fx[V];            // output rows: march velocity of plane q-1; odd: x velocity
+  float hp, ha, hs, hm, hxv;     // the same at this lane's halo node
+  auto prefetch = [&](int ahead) {  // ahead: iterations after the current one
+    const unsigned q = unsigned(pw.plane(3 + ahead)) * mstr,
+                   qm1 = unsigned(pw.plane(2 + ahead)) * mstr, qo = unsigned(pw.plane(ahead)) * mstr;
+#pragma unroll
+    for (int k = 0; k < RW; ++k) {
+      fp[k] = ld2_vs(phi, lrow[k], q);
+      if (EVEN) fa[k] = ld2_vs(ux, lrow[k], q);
+      fs[k] = ld2_vs(rS, lrow[k], q);
+    }
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+      fm[j] = ld2_vs(rM, orow[j], qm1);
+      if (!EVEN) fx[j] = ld2_vs(ux, orow[j], qo);
+    }
+    hp = ld_vs(phi, hlrow, q);
+    if (EVEN) {
+      ha = ld_vs(ux, hlrow, q);
+    } else {
+      hs = ld_vs(rS, hlrow, q);
+      hm = ld_vs(rM, horow, qm1);
+      hxv = ld_vs(ux, horow, qo);
+    }
+  };
+
+  // march rings: node 2l of output row j in column j, node 2l+1 in column
+  // V + j; odd steps: the halo node of lane 6j + i in a ring of its own
+  float ra[3][2 * V], r1[3][2 * V], re[3][2 * V], rc[3][2 * V];
+  float hra[3][1], hr1[3][1], hre[3][1], hrc[3][1];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+#pragma unroll
+    for (int j = 0; j < 2 * V; ++j) ra[k][j] = r1[k][j] = re[k][j] = rc[k][j] = 0.f;
+    hra[k][0] = hr1[k][0] = hre[k][0] = hrc[k][0] = 0.f;
+  }
+
+  const int iters = (m1 - m0) + 6;
+  const bool lane_out = x0 + 2 * lane < nx;
+  const bool end_lane = lane < 3 || lane >= 61;  // holds nodes of the end segments
+  const int eslot = end_slot(2 * lane);
+  const int hslot = end_slot(hnode), e0slot = end_slot(enode);
+  bool over = false;
+  prefetch(0);
+  auto body = [&](auto phase, int t) {
+    constexpr int P0 = decltype(phase)::value;
+    const int b = t & 1;
+#pragma unroll
+    for (int k = 0; k < RW; ++k) {
+      if (k < kAll || k < nld) {
+        float va = fp[k].x, vb = fp[k].y;
+        if (EVEN) {
+          const float ca = fa[k].x * lamX, cb = fa[k].y * lamX;
+          over |= over1(ca) | over1(cb);
+          if (end_lane) {
+            *reinterpret_cast<f32x2*>(&es[w][k][0][eslot]) = f32x2{va, vb};
+            *reinterpret_cast<f32x2*>(&es[w][k][1][eslot]) = f32x2{ca, cb};
+          }
+          xsweep_pairs(va, vb, ca, cb);  // first sweep (x) of this row; its ends below
+        }
+        const float sa = fs[k].x * lamS, sb = fs[k].y * lamS;
+        over |= over1(sa) | over1(sb);
+        *reinterpret_cast<f32x2*>(&lp[b][w * RW + k][2 * lane]) = f32x2{va, vb};
+        *reinterpret_cast<f32x2*>(&lc[b][w * RW + k][2 * lane]) = f32x2{sa, sb};
+      }
+    }
+    if (EVEN) {  // the x sweep at the first and last three nodes of each loaded row
+      if (lane < 6 * nld) {
+        es[w][ek][0][hslot] = hp;
+        es[w][ek][1][hslot] = ha * lamX;
+      }
+      float p[7], c[5], o[1];
+#pragma unroll
+      for (int i = 0; i < 7; ++i) p[i] = es[w][ek][0][e0slot - 3 + i];
+#pragma unroll
+      for (int i = 0; i < 5; ++i) c[i] = es[w][ek][1][e0slot - 2 + i];
+      sweep_segment<1>(p, c, o, flag);
+      if (lane < 6 * nld) lp[b][w * RW + ek][enode] = o[0];
+    } else {  // the halo nodes' segment-sweep inputs
+      if (lane < 6 * nld) {
+        lp[b][w * RW + ek][kWqN + ei] = hp;
+        lc[b][w * RW + ek][kWqN + ei] = hs * lamS;
+      }
+    }
+    float cm[2 * V], cxa[V], cxb[V];
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+      cm[j] = fm[j].x * lamM;
+      cm[V + j] = fm[j].y * lamM;
+      over |= over1(cm[j]) | over1(cm[V + j]);
+      cxa[j] = EVEN ? 0.f : fx[j].x * lamX;
+      cxb[j] = EVEN ? 0.f : fx[j].y * lamX;
+      if (!EVEN) over |= over1(cxa[j]) | over1(cxb[j]);
+    }
+    const float hcm = EVEN ? 0.f : hm * lamM, hcx = EVEN ? 0.f : hxv * lamX;
+    prefetch(1);  // unconditional (see the top of the file)
+    __syncthreads();
+    float a[2 * V], o[2 * V];
+    {
+      float pa[V + 6], pb[V + 6], csa[V + 4], csb[V + 4], aa[V], ab[V];
+#pragma unroll
+      for (int k = 0; k < V + 6; ++k) {
+        const f32x2 v = *reinterpret_cast<const f32x2*>(&lp[b][w * V + k][2 * lane]);
+        pa[k] = v.x;
+        pb[k] = v.y;
+      }
+#pragma unroll
+      for (int k = 0; k < V + 4; ++k) {
+        const f32x2 c = *reinterpret_cast<const f32x2*>(&lc[b][w * V + 1 + k][2 * lane]);
+        csa[k] = c.x;
+        csb[k] = c.y;
+      }
+      // sweep along the segment axis (second for even, first for odd)
+      sweep_segment<V>(pa, csa, aa, flag);
+      sweep_segment<V>(pb, csb, ab, flag);
+#pragma unroll
+      for (int j = 0; j < V; ++j) {
+        a[j] = aa[j];
+        a[V + j] = ab[j];
+      }
+    }
+    // sweep along the march axis (even: last; odd: second)
+    march_step<2 * V, P0>(ra, r1, re, rc, a, cm, o);
+    float oh[1] = {0.f};
+    if (!EVEN) {  // the same two sweeps at the halo node of lane 6j + i (output row j)
+      float ph[7], chh[5], ah[1];
+      const int r0 = w * V + min(ek, V - 1);
+#pragma unroll
+      for (int i = 0; i < 7; ++i) ph[i] = lp[b][r0 + i][kWqN + ei];
+#pragma unroll
+      for (int i = 0; i < 5; ++i) chh[i] = lc[b][r0 + 1 + i][kWqN + ei];
+      sweep_segment<1>(ph, chh, ah, flag);
+      const float hcmv[1] = {hcm};
+      march_step<1, P0>(hra, hr1, hre, hrc, ah, hcmv, oh);
+    }
+    if (t >= 6) {
+      const unsigned qo = unsigned(pw.p[0]) * mstr;
+      float xa[V], xb[V];
+#pragma unroll
+      for (int j = 0; j < V; ++j) {
+        xa[j] = o[j];
+        xb[j] = o[V + j];
+      }
+      if (!EVEN) {  // last sweep (x), the ends from the edge lanes
+#pragma unroll
+        for (int j = 0; j < V; ++j) {
+          if (end_lane) {
+            *reinterpret_cast<f32x2*>(&es[w][j][0][eslot]) = f32x2{xa[j], xb[j]};
+            *reinterpret_cast<f32x2*>(&es[w][j][1][eslot]) = f32x2{cxa[j], cxb[j]};
+          }
+          xsweep_pairs(xa[j], xb[j], cxa[j], cxb[j]);
+        }
+        if (lane < 6 * V) {
+          es[w][ek][0][hslot] = oh[0];
+          es[w][ek][1][hslot] = hcx;
+        }
+        float p[7], c[5], eo[1];
+#pragma unroll
+        for (int i = 0; i < 7; ++i) p[i] = es[w][ek][0][e0slot - 3 + i];
+#pragma unroll
+        for (int i = 0; i < 5; ++i) c[i] = es[w][ek][1][e0slot - 2 + i];
+        sweep_segment<1>(p, c, eo, flag);
+        // lane 0 takes nodes 0 and 1, lane 1 node 2, lane 62 node 125, lane
+        // 63 nodes 126 and 127 from the edge lanes 6j + 0..5
+        const int sa = lane == 0 ? 0 : lane == 1 ? 2 : 4, sb = lane == 0 ? 1 : lane == 62 ? 3 : 5;
+        const bool ta = lane == 0 || lane == 1 || lane == 63, tb = lane == 0 || lane == 62 || lane == 63;
+        const int eoi = __builtin_bit_cast(int, eo[0]);
+#pragma unroll
+        for (int j = 0; j < V; ++j) {
+          const float va = __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(4 * (6 * j + sa), eoi));
+          const float vb = __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(4 * (6 * j + sb), eoi));
+          if (ta) xa[j] = va;
+          if (tb) xb[j] = vb;
+        }
+      }
+      if (lane_out) {
+        const int rows_left = ns - s0;
+#pragma unroll
+        for (int j = 0; j < V; ++j)
+          if (j < rows_left) st2_vs(out, orow[j], qo, f32x2{xa[j], xb[j]});
+      }
+    }
+    pw.advance();
+  };
+  for (int t = 0; t < iters; t += 3) {
+    body(std::integral_constant<int, 0>{}, t);
+    if (t + 1 < iters) body(std::integral_constant<int, 1>{}, t + 1);
+    if (t + 2 < iters) body(std::integral_constant<int, 2>{}, t + 2);
+  }
+  if (over) *flag = 1;
+}
+
+// Launch of the aligned two-node march: shape < 0 gives the march chunk
+// (-shape planes); 0 the longest of 128, 64, 32 and 16 planes that still
+// gives every CU a workgroup.
+template <bool EVEN>
+hipError_t launch_wq_t(const Geo& g, const float* phi, const float* u, float* out, int* flag,
+                       hipStream_t st, int shape) {
+  constexpr int V = kWqV, W = kWqW, S = V * W;
+  const size_t n = (size_t)g.ncells;
+  const int ns = EVEN ? g.ny : g.nz, nm = EVEN ? g.nz : g.ny;
+  const long long groups = (long long)((g.nx + kWqN - 1) / kWqN) * ((ns + S - 1) / S);
+  int chunk = shape < 0 ? -shape : 0;
+  if (chunk <= 0) {
+    static int cus = 0;
+    if (!cus) {
+      int dev = 0;
+      if (hipGetDevice(&dev) != hipSuccess ||
+          hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        cus = 256;
+    }
+    chunk = 16;
+    for (int c : {128, 64, 32})
+      if (groups * ((nm + c - 1) / c) >= cus) {
+        chunk = c;
+        break;
+      }
+  }
+  const long long blocks = groups * ((nm + chunk - 1) / chunk);
+  hipLaunchKernelGGL((k_cec3d_wq<EVEN, V, W>), dim3(unsigned(blocks)), dim3(64 * W), 0, st, phi, u,
+                     u + n, u + 2 * n, out, g, chunk, flag);
+  return hipGetLastError();
+}
+hipError_t launch_cec3d_wq(bool even, const Geo& g, const float* phi, const float* u, float* out,
+                           int* flag, hipStream_t st, Cec3dLaunch lc) {
+  if (g.nx % 2) return hipErrorInvalidValue;
+  return even ? launch_wq_t<true>(g, phi, u, out, flag, st, lc.ychunk)
+              : launch_wq_t<false>(g, phi, u, out, flag, st, lc.ychunk);
+}
+
+// ---------------------------------------------------------------------------
 // Several fields sharing one velocity (K per launch): the shared-halo window
 // march of variant 7 with the velocity loaded once per tile for all K
 // fields.  Per march plane a workgroup loads the velocity rows its tile
@@ -1742,6 +2078,9 @@ hipError_t launch_cec3d(int variant, bool even, const Geo& g, const float* phi, 
   if (variant == 9) return launch_cec3d_wp(even, g, phi, u, out, flag, st, lc, 2);
   if (variant >= 10 && variant <= 13)
     return launch_cec3d_wp(even, g, phi, u, out, flag, st, lc, 1 + (variant & 1), variant < 12 ? 1 : 2);
+  if (variant == 14)  // an odd nx has no two-node layout: variant 8 there
+    return g.nx % 2 ? launch_cec3d_wp(even, g, phi, u, out, flag, st, lc)
+                    : launch_cec3d_wq(even, g, phi, u, out, flag, st, lc);
   if (variant == 5) {
     // the fastest implementation of each parity as measured from 256^3 to
     // 1024^3 (the tuner, sla_tune, measures the grid at hand instead): up to

@@ -75,9 +75,11 @@ hipError_t launch_cec_sweep_xy(int R, bool xfirst, const Geo& g, const float* ph
 // fastest of these per parity and grid size, 6 window march with 8-row
 // segments, 7 window march whose workgroups share segment halos through
 // LDS, 8 the same with 16-row groups of 12 waves, in march chunks or
-// persistent, 9 as 8 with the inputs loaded two planes ahead; all perform
-// the same FP32 operations (0 and 3 are unused).
-constexpr int kCec3dVariants = 14;
+// persistent, 9 as 8 with the inputs loaded two planes ahead, 10-13 as 8
+// and 9 with one or two windows per workgroup, 14 the march on aligned
+// 128-node windows of two nodes per lane; all perform the same FP32
+// operations (0 and 3 are unused).
+constexpr int kCec3dVariants = 15;
 inline bool cec3d_variant_ok(int v) { return v >= 1 && v < kCec3dVariants && v != 3; }
 // Launch shape: y planes per workgroup, or for variant 8 the march chunk
 // (< 0: -chunk planes) or workgroups per CU of the persistent form (> 0);

@@ -331,7 +331,8 @@ def test_abc_512_cfl09_cec_boxes(ctx):
 
 @pytest.mark.parametrize("variant,launch", [(1, 0), (2, 0), (4, 0), (5, 0), (6, 0), (7, 0), (7, 16),
                                             (8, 0), (8, -16), (8, 1),
-                                            (9, -16), (10, 0), (11, -16), (12, 0), (13, 1)])
+                                            (9, -16), (10, 0), (11, -16), (12, 0), (13, 1),
+                                            (14, 0), (14, -16)])
 @pytest.mark.parametrize("step0", [0, 1])
 @pytest.mark.parametrize("shape", [(40, 48, 72), (37, 45, 130), (13, 11, 250), (11, 13, 9)])
 def test_fused_step_matches_sweeps(ctx, step0, variant, launch, shape):
@@ -342,7 +343,10 @@ def test_fused_step_matches_sweeps(ctx, step0, variant, launch, shape):
     and fewer rows than one shared-halo workgroup holds; in the fourth a row
     is narrower than a window (its lanes wrap around the row).  Variant 8
     runs in 16-plane chunks and persistent (its workgroups' ranges then
-    cross from one group of rows into the next)."""
+    cross from one group of rows into the next).  Variant 14 (128-node
+    windows of two nodes per lane) has one window narrower than the row in
+    the first shape, a 2-node last window in the second, and falls back to
+    variant 8 on the fourth's odd nx."""
     from paper_1606_06117_amd import native
     phi = W.random_gaussians(shape, 6, seed=31).astype(np.float32)
     u = W.abc_velocity(shape)
