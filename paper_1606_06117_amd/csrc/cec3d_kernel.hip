@@ -1121,10 +1121,12 @@ hipError_t launch_cec3d_wp(bool even, const Geo& g, const float* phi, const floa
 // last three nodes, whose stencils reach into the halo, and those six outputs
 // of a row are computed again by a packed set of edge lanes (one per row and
 // edge node) from the row's two 9-node end segments, gathered in a small LDS
-// area of the wave.  On odd steps, whose x sweep comes last, the halo nodes
-// also go through the z and y sweeps, one (row, node) per lane.  Groups of
-// S = V*W = 32 segment rows (38 loaded), W = 8 waves, one workgroup per CU,
-// march chunks of up to 128 planes.  Per node the same FP32 operations as
+// area of the wave.  Both parities march along z over groups of S = V*W =
+// 32 y rows (38 loaded): odd steps, whose order is z, y, x, run the z sweep
+// first, along the march on every loaded row, then y across the rows and x
+// last; their halo nodes also go through the z and y sweeps, one (row, node)
+// per lane.  W = 8 waves, one workgroup per CU, march chunks of up to 128
+// planes.  Per node the same FP32 operations as
 // the other variants.  Needs an even nx (a lane's two nodes are adjacent in
 // memory, also where the window wraps around the row).
 // ---------------------------------------------------------------------------
@@ -1170,27 +1172,24 @@ __global__ __launch_bounds__(64 * W) void k_cec3d_wq(const float* __restrict__ p
                                                      const float* __restrict__ uz,
                                                      float* __restrict__ out, Geo g, int chunk,
                                                      int* flag) {
-  constexpr int S = V * W, NR = S + 6, RW = (NR + W - 1) / W, kAll = NR - (W - 1) * RW;
+  constexpr int S = V * W, NR = S + 6, RW = (NR + W - 1) / W;
   constexpr int LW = kWqN + 8;         // LDS row: the window's nodes, then (odd) its 6 halo nodes
   constexpr int NE = RW > V ? RW : V;  // rows with end segments per wave
+  constexpr int NC = EVEN ? 2 * V : 2 * RW;  // march columns per lane: output rows (even), loaded rows (odd)
   static_assert(6 * NE <= 64, "one edge lane per row and end node");
-  __shared__ __align__(16) float lp[2][NR][LW];     // segment sweep input (x-swept if even)
-  __shared__ __align__(16) float lc[2][NR][LW];     // segment-axis Courant numbers
+  __shared__ __align__(16) float lp[2][NR][LW];     // y sweep input (x-swept if even, z-swept if odd)
+  __shared__ __align__(16) float lc[2][NR][LW];     // y Courant numbers
   __shared__ __align__(16) float es[W][NE][2][24];  // end segments: values, x Courant numbers
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int nx = g.nx, ny = g.ny, nz = g.nz;
-  const int ns = EVEN ? ny : nz, nm = EVEN ? nz : ny;
-  const int nwx = (nx + kWqN - 1) / kWqN, ngs = (ns + S - 1) / S, ng = nwx * ngs;
+  const int nwx = (nx + kWqN - 1) / kWqN, ngs = (ny + S - 1) / S, ng = nwx * ngs;
   const int blk = block_tile(1).x;  // XCD-mapped 1D grid
-  if (blk >= ng * ((nm + chunk - 1) / chunk)) return;  // the whole workgroup
+  if (blk >= ng * ((nz + chunk - 1) / chunk)) return;  // the whole workgroup
   const int ch = blk / ng, grp = blk - ch * ng;
   const int x0 = (grp % nwx) * kWqN, g0 = (grp / nwx) * S, s0 = g0 + w * V;
-  const int m0 = ch * chunk, m1 = min(nm, m0 + chunk);
+  const int m0 = ch * chunk, m1 = min(nz, m0 + chunk);
   const unsigned rowb = 4u * unsigned(nx), plb = 4u * unsigned(nx) * unsigned(ny);
-  const unsigned sstr = EVEN ? rowb : plb, mstr = EVEN ? plb : rowb;
-  const float* rS = EVEN ? uy : uz;  // segment-axis velocity
-  const float* rM = EVEN ? uz : uy;  // march-axis velocity
-  const float lamX = g.lam[0], lamS = EVEN ? g.lam[1] : g.lam[2], lamM = EVEN ? g.lam[2] : g.lam[1];
+  const float lamX = g.lam[0], lamY = g.lam[1], lamZ = g.lam[2];
   const int nld = min(RW, NR - w * RW);  // rows this wave loads: w*RW + k, k < nld
   // lane 6k + i serves row k of the wave and end node i: the window's nodes
   // 0..2 and 125..127 (edge nodes), halo nodes -3..-1 and 128..130; lanes
@@ -1200,56 +1199,68 @@ __global__ __launch_bounds__(64 * W) void k_cec3d_wq(const float* __restrict__ p
   const int enode = ei < 3 ? ei : kWqN - 6 + ei;      // window-relative edge node
   const unsigned vx = 4u * unsigned(wrapk(x0 + 2 * lane, nx));
   const unsigned hx = 4u * unsigned(wrapk(x0 + hnode, nx));
-  // per-lane offsets within a march plane of the loaded rows (rows past the
+  // per-lane offsets within a z plane of the loaded rows (rows past the
   // wave's share repeat its last row: every wave issues the same loads, none
   // under a condition) and of the output rows
   unsigned lrow[RW], orow[V];
 #pragma unroll
   for (int k = 0; k < RW; ++k)
-    lrow[k] = vx + unsigned(__builtin_amdgcn_readfirstlane(wrapk(g0 - 3 + w * RW + min(k, nld - 1), ns))) * sstr;
+    lrow[k] = vx + unsigned(__builtin_amdgcn_readfirstlane(wrapk(g0 - 3 + w * RW + min(k, nld - 1), ny))) * rowb;
 #pragma unroll
   for (int j = 0; j < V; ++j)
-    orow[j] = vx + unsigned(__builtin_amdgcn_readfirstlane(wrapk(s0 + j, ns))) * sstr;
+    orow[j] = vx + unsigned(__builtin_amdgcn_readfirstlane(wrapk(s0 + j, ny))) * rowb;
   // the halo node's offsets in loaded row min(ek, nld - 1) and output row min(ek, V - 1)
-  const unsigned hlrow = hx + unsigned(wrapk(g0 - 3 + w * RW + min(ek, nld - 1), ns)) * sstr;
-  const unsigned horow = hx + unsigned(wrapk(s0 + min(ek, V - 1), ns)) * sstr;
-  PlaneWin pw(m0 - 6, nm);  // planes m0 - 6 + t .. m0 - 1 + t at iteration t
+  const unsigned hlrow = hx + unsigned(wrapk(g0 - 3 + w * RW + min(ek, nld - 1), ny)) * rowb;
+  const unsigned horow = hx + unsigned(wrapk(s0 + min(ek, V - 1), ny)) * rowb;
+  PlaneWin pw(m0 - 6, nz);  // planes m0 - 6 + t .. m0 - 1 + t at iteration t
 
-  f32x2 fp[RW], fa[RW], fs[RW];  // loaded rows: phi, x velocity (even), segment velocity
-  f32x2 fm[V], fx[V];            // output rows: march velocity of plane q-1; odd: x velocity
-  float hp, ha, hs, hm, hxv;     // the same at this lane's halo node
-  auto prefetch = [&](int ahead) {  // ahead: iterations after the current one
-    const unsigned q = unsigned(pw.plane(3 + ahead)) * mstr,
-                   qm1 = unsigned(pw.plane(2 + ahead)) * mstr, qo = unsigned(pw.plane(ahead)) * mstr;
+  // Iteration t loads plane q = m0 - 3 + t and writes plane q - 3.  Even
+  // steps sweep x on the loaded rows of plane q, y on its output rows, and z
+  // along the march (plane q - 3 out).  Odd steps sweep z first, along the
+  // march on the loaded rows (plane q - 3 out of the rings), then y and x on
+  // plane q - 3, whose y and x velocities are loaded three planes late.
+  f32x2 fp[RW], fa[RW], fs[RW];  // loaded rows: phi; even: x, y velocity; odd: z (plane q-1), y (q-3)
+  f32x2 fm[V];                   // output rows: even: z velocity (q-1); odd: x velocity (q-3)
+  float hp, ha, hs, hm;          // this lane's halo node: phi, and velocities as the rows'
+  // ahead: iterations after the current one.  Part 1: what the first
+  // sweep of the iteration needs (even: all); part 2 (odd): the y and x
+  // velocities of plane q - 3, issued after the iteration's stores so that
+  // their registers are not held through its y sweep.
+  auto prefetch = [&](int ahead, int part) {
+    const unsigned q = unsigned(pw.plane(3 + ahead)) * plb,
+                   qm1 = unsigned(pw.plane(2 + ahead)) * plb, qo = unsigned(pw.plane(ahead)) * plb;
+    if (part & 1) {
 #pragma unroll
-    for (int k = 0; k < RW; ++k) {
-      fp[k] = ld2_vs(phi, lrow[k], q);
-      if (EVEN) fa[k] = ld2_vs(ux, lrow[k], q);
-      fs[k] = ld2_vs(rS, lrow[k], q);
-    }
+      for (int k = 0; k < RW; ++k) {
+        fp[k] = ld2_vs(phi, lrow[k], q);
+        fa[k] = EVEN ? ld2_vs(ux, lrow[k], q) : ld2_vs(uz, lrow[k], qm1);
+        if (EVEN) fs[k] = ld2_vs(uy, lrow[k], q);
+      }
+      if (EVEN)
 #pragma unroll
-    for (int j = 0; j < V; ++j) {
-      fm[j] = ld2_vs(rM, orow[j], qm1);
-      if (!EVEN) fx[j] = ld2_vs(ux, orow[j], qo);
+        for (int j = 0; j < V; ++j) fm[j] = ld2_vs(uz, orow[j], qm1);
+      hp = ld_vs(phi, hlrow, q);
+      ha = EVEN ? ld_vs(ux, hlrow, q) : ld_vs(uz, hlrow, qm1);
     }
-    hp = ld_vs(phi, hlrow, q);
-    if (EVEN) {
-      ha = ld_vs(ux, hlrow, q);
-    } else {
-      hs = ld_vs(rS, hlrow, q);
-      hm = ld_vs(rM, horow, qm1);
-      hxv = ld_vs(ux, horow, qo);
+    if (!EVEN && (part & 2)) {
+#pragma unroll
+      for (int k = 0; k < RW; ++k) fs[k] = ld2_vs(uy, lrow[k], qo);
+#pragma unroll
+      for (int j = 0; j < V; ++j) fm[j] = ld2_vs(ux, orow[j], qo);
+      hs = ld_vs(uy, hlrow, qo);
+      hm = ld_vs(ux, horow, qo);
     }
   };
 
-  // march rings: node 2l of output row j in column j, node 2l+1 in column
-  // V + j; odd steps: the halo node of lane 6j + i in a ring of its own
-  float ra[3][2 * V], r1[3][2 * V], re[3][2 * V], rc[3][2 * V];
+  // march rings (z): even: node 2l of output row j in column j, node 2l+1 in
+  // column V + j; odd: the loaded rows likewise (RW for V), and the halo
+  // node of lane 6k + i (loaded row k) in a ring of its own
+  float ra[3][NC], r1[3][NC], re[3][NC], rc[3][NC];
   float hra[3][1], hr1[3][1], hre[3][1], hrc[3][1];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
 #pragma unroll
-    for (int j = 0; j < 2 * V; ++j) ra[k][j] = r1[k][j] = re[k][j] = rc[k][j] = 0.f;
+    for (int j = 0; j < NC; ++j) ra[k][j] = r1[k][j] = re[k][j] = rc[k][j] = 0.f;
     hra[k][0] = hr1[k][0] = hre[k][0] = hrc[k][0] = 0.f;
   }
 
@@ -1259,15 +1270,26 @@ __global__ __launch_bounds__(64 * W) void k_cec3d_wq(const float* __restrict__ p
   const int eslot = end_slot(2 * lane);
   const int hslot = end_slot(hnode), e0slot = end_slot(enode);
   bool over = false;
-  prefetch(0);
+  // x sweep of the end nodes of rows 0..nrows-1 of the wave, from their end
+  // segments (lane 6k + i: row k, edge node i); returns this lane's result
+  auto edge_x = [&]() {
+    float p[7], c[5], o[1];
+#pragma unroll
+    for (int i = 0; i < 7; ++i) p[i] = es[w][ek][0][e0slot - 3 + i];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) c[i] = es[w][ek][1][e0slot - 2 + i];
+    sweep_segment<1>(p, c, o, flag);
+    return o[0];
+  };
+  prefetch(0, 3);
   auto body = [&](auto phase, int t) {
     constexpr int P0 = decltype(phase)::value;
     const int b = t & 1;
+    if constexpr (EVEN) {
 #pragma unroll
-    for (int k = 0; k < RW; ++k) {
-      if (k < kAll || k < nld) {
-        float va = fp[k].x, vb = fp[k].y;
-        if (EVEN) {
+      for (int k = 0; k < RW; ++k) {
+        if (k < nld) {
+          float va = fp[k].x, vb = fp[k].y;
           const float ca = fa[k].x * lamX, cb = fa[k].y * lamX;
           over |= over1(ca) | over1(cb);
           if (end_lane) {
@@ -1275,45 +1297,59 @@ __global__ __launch_bounds__(64 * W) void k_cec3d_wq(const float* __restrict__ p
             *reinterpret_cast<f32x2*>(&es[w][k][1][eslot]) = f32x2{ca, cb};
           }
           xsweep_pairs(va, vb, ca, cb);  // first sweep (x) of this row; its ends below
+          const float sa = fs[k].x * lamY, sb = fs[k].y * lamY;
+          over |= over1(sa) | over1(sb);
+          *reinterpret_cast<f32x2*>(&lp[b][w * RW + k][2 * lane]) = f32x2{va, vb};
+          *reinterpret_cast<f32x2*>(&lc[b][w * RW + k][2 * lane]) = f32x2{sa, sb};
         }
-        const float sa = fs[k].x * lamS, sb = fs[k].y * lamS;
-        over |= over1(sa) | over1(sb);
-        *reinterpret_cast<f32x2*>(&lp[b][w * RW + k][2 * lane]) = f32x2{va, vb};
-        *reinterpret_cast<f32x2*>(&lc[b][w * RW + k][2 * lane]) = f32x2{sa, sb};
       }
-    }
-    if (EVEN) {  // the x sweep at the first and last three nodes of each loaded row
+      // the x sweep at the first and last three nodes of each loaded row
       if (lane < 6 * nld) {
         es[w][ek][0][hslot] = hp;
         es[w][ek][1][hslot] = ha * lamX;
       }
-      float p[7], c[5], o[1];
+      const float eo = edge_x();
+      if (lane < 6 * nld) lp[b][w * RW + ek][enode] = eo;
+    } else {
+      // first sweep (z) along the march on the loaded rows: plane q - 3 out
+      float za[NC], zc[NC], zo[NC];
 #pragma unroll
-      for (int i = 0; i < 7; ++i) p[i] = es[w][ek][0][e0slot - 3 + i];
+      for (int k = 0; k < RW; ++k) {
+        za[k] = fp[k].x;
+        za[RW + k] = fp[k].y;
+        zc[k] = fa[k].x * lamZ;
+        zc[RW + k] = fa[k].y * lamZ;
+        over |= over1(zc[k]) | over1(zc[RW + k]);
+      }
+      march_step<NC, P0>(ra, r1, re, rc, za, zc, zo);
+      float hza[1] = {hp}, hzc[1] = {ha * lamZ}, hzo[1];
+      march_step<1, P0>(hra, hr1, hre, hrc, hza, hzc, hzo);
 #pragma unroll
-      for (int i = 0; i < 5; ++i) c[i] = es[w][ek][1][e0slot - 2 + i];
-      sweep_segment<1>(p, c, o, flag);
-      if (lane < 6 * nld) lp[b][w * RW + ek][enode] = o[0];
-    } else {  // the halo nodes' segment-sweep inputs
-      if (lane < 6 * nld) {
-        lp[b][w * RW + ek][kWqN + ei] = hp;
-        lc[b][w * RW + ek][kWqN + ei] = hs * lamS;
+      for (int k = 0; k < RW; ++k) {
+        if (k < nld) {
+          const float sa = fs[k].x * lamY, sb = fs[k].y * lamY;
+          over |= over1(sa) | over1(sb);
+          *reinterpret_cast<f32x2*>(&lp[b][w * RW + k][2 * lane]) = f32x2{zo[k], zo[RW + k]};
+          *reinterpret_cast<f32x2*>(&lc[b][w * RW + k][2 * lane]) = f32x2{sa, sb};
+        }
+      }
+      if (lane < 6 * nld) {  // the halo nodes' y sweep inputs
+        lp[b][w * RW + ek][kWqN + ei] = hzo[0];
+        lc[b][w * RW + ek][kWqN + ei] = hs * lamY;
       }
     }
-    float cm[2 * V], cxa[V], cxb[V];
+    float cm[2 * V];  // even: z Courant numbers of plane q-1; odd: x Courant numbers of plane q-3
 #pragma unroll
     for (int j = 0; j < V; ++j) {
-      cm[j] = fm[j].x * lamM;
-      cm[V + j] = fm[j].y * lamM;
+      const float lm = EVEN ? lamZ : lamX;
+      cm[j] = fm[j].x * lm;
+      cm[V + j] = fm[j].y * lm;
       over |= over1(cm[j]) | over1(cm[V + j]);
-      cxa[j] = EVEN ? 0.f : fx[j].x * lamX;
-      cxb[j] = EVEN ? 0.f : fx[j].y * lamX;
-      if (!EVEN) over |= over1(cxa[j]) | over1(cxb[j]);
     }
-    const float hcm = EVEN ? 0.f : hm * lamM, hcx = EVEN ? 0.f : hxv * lamX;
-    prefetch(1);  // unconditional (see the top of the file)
+    const float hcx = EVEN ? 0.f : hm * lamX;
+    prefetch(1, 1);  // unconditional (see the top of the file)
     __syncthreads();
-    float a[2 * V], o[2 * V];
+    float a[2 * V];  // y sweep (second) of the output rows
     {
       float pa[V + 6], pb[V + 6], csa[V + 4], csb[V + 4], aa[V], ab[V];
 #pragma unroll
@@ -1328,7 +1364,6 @@ __global__ __launch_bounds__(64 * W) void k_cec3d_wq(const float* __restrict__ p
         csa[k] = c.x;
         csb[k] = c.y;
       }
-      // sweep along the segment axis (second for even, first for odd)
       sweep_segment<V>(pa, csa, aa, flag);
       sweep_segment<V>(pb, csb, ab, flag);
 #pragma unroll
@@ -1337,10 +1372,14 @@ __global__ __launch_bounds__(64 * W) void k_cec3d_wq(const float* __restrict__ p
         a[V + j] = ab[j];
       }
     }
-    // sweep along the march axis (even: last; odd: second)
-    march_step<2 * V, P0>(ra, r1, re, rc, a, cm, o);
-    float oh[1] = {0.f};
-    if (!EVEN) {  // the same two sweeps at the halo node of lane 6j + i (output row j)
+    float o[2 * V];
+    float yh = 0.f;
+    if constexpr (EVEN) {
+      march_step<NC, P0>(ra, r1, re, rc, a, cm, o);  // last sweep (z): plane q - 3 out
+    } else {
+#pragma unroll
+      for (int j = 0; j < 2 * V; ++j) o[j] = a[j];
+      // the y sweep at the halo node of lane 6j + i (output row j)
       float ph[7], chh[5], ah[1];
       const int r0 = w * V + min(ek, V - 1);
 #pragma unroll
@@ -1348,11 +1387,10 @@ __global__ __launch_bounds__(64 * W) void k_cec3d_wq(const float* __restrict__ p
 #pragma unroll
       for (int i = 0; i < 5; ++i) chh[i] = lc[b][r0 + 1 + i][kWqN + ei];
       sweep_segment<1>(ph, chh, ah, flag);
-      const float hcmv[1] = {hcm};
-      march_step<1, P0>(hra, hr1, hre, hrc, ah, hcmv, oh);
+      yh = ah[0];
     }
     if (t >= 6) {
-      const unsigned qo = unsigned(pw.p[0]) * mstr;
+      const unsigned qo = unsigned(pw.p[0]) * plb;
       float xa[V], xb[V];
 #pragma unroll
       for (int j = 0; j < V; ++j) {
@@ -1364,25 +1402,19 @@ __global__ __launch_bounds__(64 * W) void k_cec3d_wq(const float* __restrict__ p
         for (int j = 0; j < V; ++j) {
           if (end_lane) {
             *reinterpret_cast<f32x2*>(&es[w][j][0][eslot]) = f32x2{xa[j], xb[j]};
-            *reinterpret_cast<f32x2*>(&es[w][j][1][eslot]) = f32x2{cxa[j], cxb[j]};
+            *reinterpret_cast<f32x2*>(&es[w][j][1][eslot]) = f32x2{cm[j], cm[V + j]};
           }
-          xsweep_pairs(xa[j], xb[j], cxa[j], cxb[j]);
+          xsweep_pairs(xa[j], xb[j], cm[j], cm[V + j]);
         }
         if (lane < 6 * V) {
-          es[w][ek][0][hslot] = oh[0];
+          es[w][ek][0][hslot] = yh;
           es[w][ek][1][hslot] = hcx;
         }
-        float p[7], c[5], eo[1];
-#pragma unroll
-        for (int i = 0; i < 7; ++i) p[i] = es[w][ek][0][e0slot - 3 + i];
-#pragma unroll
-        for (int i = 0; i < 5; ++i) c[i] = es[w][ek][1][e0slot - 2 + i];
-        sweep_segment<1>(p, c, eo, flag);
+        const int eoi = __builtin_bit_cast(int, edge_x());
         // lane 0 takes nodes 0 and 1, lane 1 node 2, lane 62 node 125, lane
         // 63 nodes 126 and 127 from the edge lanes 6j + 0..5
         const int sa = lane == 0 ? 0 : lane == 1 ? 2 : 4, sb = lane == 0 ? 1 : lane == 62 ? 3 : 5;
         const bool ta = lane == 0 || lane == 1 || lane == 63, tb = lane == 0 || lane == 62 || lane == 63;
-        const int eoi = __builtin_bit_cast(int, eo[0]);
 #pragma unroll
         for (int j = 0; j < V; ++j) {
           const float va = __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(4 * (6 * j + sa), eoi));
@@ -1392,12 +1424,13 @@ __global__ __launch_bounds__(64 * W) void k_cec3d_wq(const float* __restrict__ p
         }
       }
       if (lane_out) {
-        const int rows_left = ns - s0;
+        const int rows_left = ny - s0;
 #pragma unroll
         for (int j = 0; j < V; ++j)
           if (j < rows_left) st2_vs(out, orow[j], qo, f32x2{xa[j], xb[j]});
       }
     }
+    if (!EVEN) prefetch(1, 2);
     pw.advance();
   };
   for (int t = 0; t < iters; t += 3) {
@@ -1416,8 +1449,8 @@ hipError_t launch_wq_t(const Geo& g, const float* phi, const float* u, float* ou
                        hipStream_t st, int shape) {
   constexpr int V = kWqV, W = kWqW, S = V * W;
   const size_t n = (size_t)g.ncells;
-  const int ns = EVEN ? g.ny : g.nz, nm = EVEN ? g.nz : g.ny;
-  const long long groups = (long long)((g.nx + kWqN - 1) / kWqN) * ((ns + S - 1) / S);
+  const int nm = g.nz;  // both parities march along z
+  const long long groups = (long long)((g.nx + kWqN - 1) / kWqN) * ((g.ny + S - 1) / S);
   int chunk = shape < 0 ? -shape : 0;
   if (chunk <= 0) {
     static int cus = 0;
