@@ -211,10 +211,14 @@ typedef enum {
    * each) share the segment halo rows through LDS, 8 the same with 16-row
    * groups of 12 waves (in march chunks, or persistent), 9 as 8 with the
    * inputs loaded two planes ahead, 10 and 11 as 8 and 9 with one window (4
-   * waves) per workgroup, 12 and 13 with two, 5 (default) the choice
+   * waves) per workgroup, 12 and 13 with two, 14 a march along z on x
+   * windows of 128 nodes aligned to 512-byte lines, two nodes per lane,
+   * with 32-row groups of 8 waves (the window's x halo loaded apart, its
+   * edge outputs computed by packed edge lanes; odd steps sweep z first
+   * along the march; needs an even nx, else runs 8), 5 (default) the choice
    * sla_tune measured for the grid if the context has one, else the fastest
    * of these for each parity and grid size as measured from 256^3 to
-   * 1024^3. */
+   * 1024^3 (14 from 2^24 cells on with an even nx). */
   SLA_OPT_CEC3D_KERNEL = 1,
   /* How the sweeps of a third-order step that is not fused run (same FP32
    * operations, same results): 2 (default) the x and y sweeps in one kernel
@@ -235,10 +239,11 @@ typedef enum {
    * (44 and 64 B per cell moved); 2 as 1. */
   SLA_OPT_EC_KERNEL = 3,
   /* Launch shape of the fused step (same results whatever the value): the
-   * planes a workgroup marches (variants 1-7); for variants 8 and up, > 0
-   * the persistent workgroups launched per compute unit, < 0 one workgroup
-   * per chunk of -value planes; 0 (default): the implementation's own
-   * rule. */
+   * planes a workgroup marches (variants 1-7); for variants 8-13, > 0 the
+   * persistent workgroups launched per compute unit, < 0 one workgroup per
+   * chunk of -value planes; for variant 14, < 0 the chunk, else the longest
+   * of 128, 64, 32 and 16 planes that still gives every compute unit a
+   * workgroup; 0 (default): the implementation's own rule. */
   SLA_OPT_CEC3D_SHAPE = 4,
   /* How the learned step's correction runs (same results): 1 (default) a
    * march along z with each node's neighbourhood staged in LDS; 0 a gather

@@ -880,7 +880,7 @@ int sla_set_option(sla_ctx* ctx, int option, int64_t value) {
       return SLA_OK;
     case SLA_OPT_CEC3D_KERNEL:
       if (!sla::cec3d_variant_ok(int(value)))
-        return fail(ctx, SLA_EINVAL, "SLA_OPT_CEC3D_KERNEL takes 1, 2, 4, 5, 6, 7 or 8");
+        return fail(ctx, SLA_EINVAL, "SLA_OPT_CEC3D_KERNEL takes 1, 2 or 4 to 14");
       ctx->cec3d_kernel = int(value);
       return SLA_OK;
     case SLA_OPT_SWEEP_KERNEL:
@@ -980,8 +980,9 @@ int sla_tune(sla_ctx* ctx, const sla_grid* grid, const float* phi, const float* 
   rc = ensure_work(ctx, n);
   if (rc) return rc;
   // candidates: (variant, launch shape)
-  static const int cand[][2] = {{1, 0},   {2, 0},   {4, 0},   {6, 0},    {7, 0},    {7, 32},
-                                {8, -64}, {8, -32}, {8, 0},   {9, -64},  {10, -32}, {11, -32}};
+  static const int cand[][2] = {{1, 0},    {2, 0},    {4, 0},   {6, 0},     {7, 0},     {7, 32},
+                                {8, -64},  {8, -32},  {8, 0},   {9, -64},   {10, -32},  {11, -32},
+                                {14, 0},   {14, -128}, {14, -64}, {14, -32}, {14, -16}};
   hipEvent_t a = nullptr, b = nullptr;
   hipError_t e = hipEventCreate(&a);
   if (e == hipSuccess) e = hipEventCreate(&b);

@@ -2116,12 +2116,16 @@ hipError_t launch_cec3d(int variant, bool even, const Geo& g, const float* phi, 
                     : launch_cec3d_wq(even, g, phi, u, out, flag, st, lc);
   if (variant == 5) {
     // the fastest implementation of each parity as measured from 256^3 to
-    // 1024^3 (the tuner, sla_tune, measures the grid at hand instead): up to
-    // 2^24 cells, register segments for even steps and the 4-row window
-    // march for odd ones; above, the shared-halo march with 16-row groups of
-    // 12 waves and 64-plane chunks when 3 divides the window count, with
-    // 2-window groups when 2 does, else the 8-row window march, except on
-    // odd steps whose 8-row launch would not fill the chip (see wm8_fills)
+    // 1024^3 (the tuner, sla_tune, measures the grid at hand instead): from
+    // 2^24 cells on with an even nx, the march on aligned two-node windows;
+    // below, register segments for even steps and the 4-row window march
+    // for odd ones; above with an odd nx, the shared-halo march with 16-row
+    // groups of 12 waves and 64-plane chunks when 3 divides the window
+    // count, with 2-window groups when 2 does, else the 8-row window march,
+    // except on odd steps whose 8-row launch would not fill the chip (see
+    // wm8_fills)
+    if (g.ncells >= (1 << 24) && g.nx % 2 == 0)
+      return launch_cec3d_wq(even, g, phi, u, out, flag, st, lc);
     if (g.ncells <= (1 << 24)) {
       if (!even) return launch_cec3d_wm<4>(false, g, phi, u, out, flag, st, lc);
       Cec3dLaunch l = lc;
