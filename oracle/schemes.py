@@ -54,9 +54,9 @@ import itertools
 
 import numpy as np
 
-CIR, FEC, BEC, CEC, CEC_STRANG, FEC_SPLIT, BEC_SPLIT = 0, 1, 2, 3, 4, 5, 6
+CIR, FEC, BEC, CEC, CEC_STRANG, FEC_SPLIT, BEC_SPLIT, CEC_LITERAL = 0, 1, 2, 3, 4, 5, 6, 7
 SCHEMES = {"cir": CIR, "fec": FEC, "bec": BEC, "cec": CEC, "cec_strang": CEC_STRANG,
-           "fec_split": FEC_SPLIT, "bec_split": BEC_SPLIT}
+           "fec_split": FEC_SPLIT, "bec_split": BEC_SPLIT, "cec_literal": CEC_LITERAL}
 
 
 # ---------------------------------------------------------------------------
@@ -259,9 +259,35 @@ def ec_split(phi, c, scheme, m=0):
     return out
 
 
+def cec_literal(phi, c, m=0):
+    """The weights of eq. intro:CECcoefSL read literally, one axis at a time
+    (a second-order comparison, not the third-order scheme).
+
+    Along axis ``d`` (Courant numbers of the other axes set to zero, in the
+    order of ``sweep_order``) the step is ``A FEC + B BEC``: FEC as in eq.
+    intro:FEC, its correction ``(phi - phibar)/2`` added at the arrival
+    node, BEC as in eq. intro:BEC, the correction re-interpolated at the
+    departure point, and ``3A = 2 - 1/(U % 1)``, ``B = 1 - A`` with
+    ``U = |c|``.  For ``U < 1`` this is eq. intro:CECcoef and equals
+    ``cec_split``; for ``U > 1`` the arrival-node correction no longer
+    matches the shifted interpolation and the scheme is second order.  An
+    integer ``U`` divides by zero: the result there is not finite, as the
+    formula is.
+    """
+    out = np.asarray(phi, dtype=np.float64)
+    for d in sweep_order(m, out.ndim):
+        cd = np.zeros_like(c)
+        cd[d] = c[d]
+        frac = np.abs(np.asarray(c[d], dtype=np.float64)) % 1.0
+        with np.errstate(divide="ignore", invalid="ignore"):
+            a = (2.0 - 1.0 / frac) / 3.0
+            out = a * fec(out, cd) + (1.0 - a) * bec(out, cd)
+    return out
+
+
 def step(phi, c, scheme, m=0):
-    """One time step of ``scheme`` (CIR, FEC, BEC, CEC, CEC_STRANG, FEC_SPLIT
-    or BEC_SPLIT) at global step ``m``."""
+    """One time step of ``scheme`` (CIR, FEC, BEC, CEC, CEC_STRANG, FEC_SPLIT,
+    BEC_SPLIT or CEC_LITERAL) at global step ``m``."""
     if scheme == CIR:
         return cir(phi, c)
     if scheme == FEC:
@@ -276,6 +302,8 @@ def step(phi, c, scheme, m=0):
         return ec_split(phi, c, FEC, m)
     if scheme == BEC_SPLIT:
         return ec_split(phi, c, BEC, m)
+    if scheme == CEC_LITERAL:
+        return cec_literal(phi, c, m)
     raise ValueError(f"unknown scheme {scheme!r}")
 
 
