@@ -60,7 +60,15 @@ typedef enum {
      intro:BEC): one one-dimensional FEC or BEC sweep per axis, the order
      alternating like SLA_CEC's */
   SLA_FEC_SPLIT = 5,
-  SLA_BEC_SPLIT = 6
+  SLA_BEC_SPLIT = 6,
+  /* the large-CFL weights of eq. intro:CECcoefSL read literally, per axis
+     and order as SLA_CEC: A FEC + B BEC with 3A = 2 - 1/(|c| mod 1) and
+     B = 1 - A, FEC's correction added at the arrival node.  Equal to SLA_CEC
+     (up to rounding) while every |c| < 1; second order beyond, and not
+     finite where |c| is a whole number (the formula divides by zero); near
+     a whole number, rounding is amplified by |A|, about 1/(3 (|c| mod 1)).
+     A comparison, not the third-order scheme. */
+  SLA_CEC_LITERAL = 7
 } sla_scheme;
 
 typedef enum {

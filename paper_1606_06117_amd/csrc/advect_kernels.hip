@@ -359,12 +359,20 @@ __global__ __launch_bounds__(kThreads) void k_ec(const float* __restrict__ phi,
 // The last stage of a sweep, from Phi1 and e at the arrival node (ei) and at
 // the anchor and far nodes of the departure interval (ea, eb).  COMB selects
 // the scheme the sweep applies along its axis: the third order (lerp form of
-// A FEC + B BEC), FEC (eq. intro:FEC: Phi1 + e/2 at the arrival node) or BEC
-// (eq. intro:BEC: L_U[Phi + e/2] = Phi1 + 1/2 [e_a + f (e_b - e_a)]).
-constexpr int kCombCec = 0, kCombFec = 1, kCombBec = 2;
+// A FEC + B BEC), FEC (eq. intro:FEC: Phi1 + e/2 at the arrival node), BEC
+// (eq. intro:BEC: L_U[Phi + e/2] = Phi1 + 1/2 [e_a + f (e_b - e_a)]) or the
+// weights of eq. intro:CECcoefSL read literally, A FEC + B BEC with
+// 3A = 2 - 1/f and B = 1 - A (f = |c| mod 1: second order beyond |c| = 1,
+// not finite at f = 0), formed as B = 1 - A does: A (FEC - BEC) + BEC.
+constexpr int kCombCec = 0, kCombFec = 1, kCombBec = 2, kCombCecLit = 3;
 template <int COMB>
 __device__ __forceinline__ float sweep_combine(float p1, float ei, float ea, float eb, float f) {
   if (COMB == kCombFec) return fmaf(0.5f, ei, p1);
+  if (COMB == kCombCecLit) {
+    const float a = (2.f - 1.f / f) / 3.f;
+    const float fecv = fmaf(0.5f, ei, p1), becv = fmaf(0.5f, fmaf(f, eb - ea, ea), p1);
+    return fmaf(a, fecv - becv, becv);
+  }
   const float w = COMB == kCombBec ? f : fmaf(f, 1.f / 3.f, 1.f / 3.f);
   return fmaf(0.5f, fmaf(w, eb - ea, ea), p1);
 }
@@ -1045,6 +1053,7 @@ hipError_t launch_ec_sweep(int scheme, int d, int R, const Geo& g, const float* 
                            const float* ud, float* out, int* flag, hipStream_t st) {
   if (scheme == FEC) return launch_split_r<kCombFec>(d, R, g, phi, ud, out, flag, st);
   if (scheme == BEC) return launch_split_r<kCombBec>(d, R, g, phi, ud, out, flag, st);
+  if (scheme == CEC_LITERAL) return launch_split_r<kCombCecLit>(d, R, g, phi, ud, out, flag, st);
   return hipErrorInvalidValue;
 }
 

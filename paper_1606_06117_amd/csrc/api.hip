@@ -394,7 +394,7 @@ int check_advect(sla_ctx* ctx, const sla_grid* grid, const float* phi, const flo
   if (rc) return rc;
   if (!phi || !u) return fail(ctx, SLA_EINVAL, "phi and u must not be NULL");
   if (!std::isfinite(dt)) return fail(ctx, SLA_EINVAL, "dt must be finite");
-  if (scheme < SLA_CIR || scheme > SLA_BEC_SPLIT)
+  if (scheme < SLA_CIR || scheme > SLA_CEC_LITERAL)
     return fail(ctx, SLA_EINVAL, "unknown scheme %d", scheme);
   if (steps < 0) return fail(ctx, SLA_EINVAL, "steps must be >= 0");
   if (std::isnan(courant_max)) return fail(ctx, SLA_EINVAL, "courant_max is NaN");
@@ -479,7 +479,7 @@ int sla_advect_noalloc(sla_ctx* ctx, const sla_grid* grid, float* phi, const flo
 
 size_t sla_workspace_size(const sla_grid* grid, int32_t scheme, int32_t nscalars) {
   // the grid rules of sla_advect (check_grid records no message without a context)
-  if (check_grid(nullptr, grid) != SLA_OK || scheme < SLA_CIR || scheme > SLA_BEC_SPLIT ||
+  if (check_grid(nullptr, grid) != SLA_OK || scheme < SLA_CIR || scheme > SLA_CEC_LITERAL ||
       nscalars < 0)
     return 0;
   size_t cells = 1;
@@ -807,12 +807,17 @@ int advect_steps(sla_ctx* ctx, const sla_grid* grid, float* phi, const float* u,
       }
       case SLA_FEC_SPLIT:
       case SLA_BEC_SPLIT:
-        // one 1D FEC or BEC sweep per axis, x,y,z on even steps, z,y,x on odd
+      case SLA_CEC_LITERAL:
+        // one 1D FEC, BEC or literal-weight sweep per axis, x,y,z on even
+        // steps, z,y,x on odd
         for (int j = 0; j < ndim && e == hipSuccess; ++j) {
           const int d = (m % 2 == 0) ? j : ndim - 1 - j;
+          const int one = scheme == SLA_FEC_SPLIT ? sla::FEC
+                          : scheme == SLA_BEC_SPLIT ? sla::BEC
+                                                    : sla::CEC_LITERAL;
           e = run(ctx, SLA_K_SWEEP_X + d, [&] {
-            return sla::launch_ec_sweep(scheme == SLA_FEC_SPLIT ? sla::FEC : sla::BEC, d, reach[d],
-                                        geo, cur, u + size_t(d) * n, nxt, ctx->flag, ctx->stream);
+            return sla::launch_ec_sweep(one, d, reach[d], geo, cur, u + size_t(d) * n, nxt,
+                                        ctx->flag, ctx->stream);
           });
           std::swap(cur, nxt);
         }

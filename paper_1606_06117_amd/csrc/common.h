@@ -6,7 +6,7 @@
 
 namespace sla {
 
-enum { CIR = 0, FEC = 1, BEC = 2, CEC = 3 };
+enum { CIR = 0, FEC = 1, BEC = 2, CEC = 3, CEC_LITERAL = 4 };  // CEC_LITERAL: sweep combination only
 
 // Grid geometry as the kernels see it.  lam[d] = fl32(dt / dx[d]); unused
 // axes have n = 1 and lam = 0.
@@ -56,8 +56,9 @@ hipError_t launch_ec_march(int scheme, const Geo& g, const float* phi, const flo
 // b + (b - L_{-U}[a])/2 (BEC's psi).  out may equal b.
 hipError_t launch_ec_gather(int ndim, int mode, const Geo& g, const float* a, const float* b,
                             const float* u, float* out, int* flag, hipStream_t st);
-// One FEC (scheme FEC) or BEC (scheme BEC) sweep along axis d: the
-// one-dimensional scheme applied along one axis (tile kernels, reach 1-4).
+// One FEC (scheme FEC), BEC (scheme BEC) or literal large-CFL third-order
+// (scheme CEC_LITERAL) sweep along axis d: the one-dimensional scheme
+// applied along one axis (tile kernels, reach 1-4).
 hipError_t launch_ec_sweep(int scheme, int d, int R, const Geo& g, const float* phi,
                            const float* ud, float* out, int* flag, hipStream_t st);
 hipError_t launch_cec_sweep(int d, int R, const Geo& g, const float* phi,

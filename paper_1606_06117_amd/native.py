@@ -14,9 +14,9 @@ import os
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libsla.so")
 
-CIR, FEC, BEC, CEC, CEC_STRANG, FEC_SPLIT, BEC_SPLIT = 0, 1, 2, 3, 4, 5, 6
+CIR, FEC, BEC, CEC, CEC_STRANG, FEC_SPLIT, BEC_SPLIT, CEC_LITERAL = 0, 1, 2, 3, 4, 5, 6, 7
 SCHEMES = {"cir": CIR, "fec": FEC, "bec": BEC, "cec": CEC, "cec_strang": CEC_STRANG,
-           "fec_split": FEC_SPLIT, "bec_split": BEC_SPLIT}
+           "fec_split": FEC_SPLIT, "bec_split": BEC_SPLIT, "cec_literal": CEC_LITERAL}
 MAX_REACH = 4
 NOALLOC_MAX_CELLS = 1 << 23
 

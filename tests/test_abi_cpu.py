@@ -56,13 +56,13 @@ def test_workspace_size():
     lib = native.load()
     g = native.make_grid((12, 34, 56), (0.1, 0.1, 0.1))
     field = 4 * 12 * 34 * 56
-    for scheme in range(7):
+    for scheme in range(8):
         for ns in (1, 2, 3, 16):
             want = field * (min(ns, 4) if scheme == native.CEC else 1)
             assert lib.sla_workspace_size(ctypes.byref(g), scheme, ns) == want
     g2 = native.make_grid((34, 56), (0.1, 0.1))
     assert lib.sla_workspace_size(ctypes.byref(g2), native.CEC, 16) == 4 * 34 * 56
-    assert lib.sla_workspace_size(ctypes.byref(g), 7, 1) == 0
+    assert lib.sla_workspace_size(ctypes.byref(g), 8, 1) == 0
     assert lib.sla_workspace_size(ctypes.byref(g), 3, -1) == 0
     # grids of 2^31 cells or more, including extents whose product would
     # wrap a 64-bit integer, are invalid

@@ -207,7 +207,7 @@ def test_errors(ctx):
         ctx.advect(phi, u, dx, float("nan"), "cec", 1)
     assert ei.value.status == native.EINVAL
     with pytest.raises(native.SlaError) as ei:
-        ctx.advect(phi, u, dx, 1.0, 7, 1)
+        ctx.advect(phi, u, dx, 1.0, 8, 1)
     assert ei.value.status == native.EINVAL
     with pytest.raises(native.SlaError) as ei:
         ctx.advect(phi, u, dx, 1.0, "cec", -1)
