@@ -30,7 +30,7 @@ measured convergence orders.
 from .schemes import (  # noqa: F401
     CIR, FEC, BEC, CEC, CEC_STRANG, FEC_SPLIT, BEC_SPLIT, CEC_LITERAL, SCHEMES,
     courant, departure, interp, cir, fec, bec, cec_sweep, cec_split, cec_strang, ec_split,
-    cec_literal,
+    cec_literal, midpoint_courant, cec_sweep_pair, cec_split_midpoint,
     step, run, advect, sweep_order,
 )
 from .norms import reductions, rel_l2, linf, mass_error  # noqa: F401
