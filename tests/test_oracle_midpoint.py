@@ -87,10 +87,30 @@ def _orders(stepper):
     return errs, [np.log2(errs[i] / errs[i + 1]) for i in range(len(errs) - 1)]
 
 
+def _rk3_stepper(p, c, k):
+    """Departures from a third-order Runge-Kutta foot of the analytic
+    velocity (no interpolation error in the velocity either)."""
+    n = p.shape[-1]
+    x = np.arange(n) * (2 * np.pi / n)
+    scale = c[0] / (1.0 + 0.5 * np.sin(x))  # dt / dx
+    u = lambda y: 1.0 + 0.5 * np.sin(y)  # noqa: E731
+    h = scale * (2 * np.pi / n)  # dt, the same at every node
+
+    def disp(sign):
+        k1 = u(x)
+        k2 = u(x - sign * 0.5 * h * k1)
+        k3 = u(x - sign * h * (2.0 * k2 - k1))
+        return scale * (k1 + 4.0 * k2 + k3) / 6.0
+
+    return oracle.cec_sweep_pair(p, disp(1.0), disp(-1.0), 0)
+
+
 def test_variable_velocity_order_stays_two():
     e_euler, o_euler = _orders(lambda p, c, k: oracle.cec_split(p, c, k))
     e_mid, o_mid = _orders(lambda p, c, k: oracle.cec_split_midpoint(p, c, k))
+    e_rk3, o_rk3 = _orders(_rk3_stepper)
     print("arrival-node backtrace", ["%.2e" % e for e in e_euler], ["%.2f" % o for o in o_euler])
     print("midpoint backtrace    ", ["%.2e" % e for e in e_mid], ["%.2f" % o for o in o_mid])
-    for o in o_euler[1:] + o_mid[1:]:
+    print("RK3, exact velocity   ", ["%.2e" % e for e in e_rk3], ["%.2f" % o for o in o_rk3])
+    for o in o_euler[1:] + o_mid[1:] + o_rk3[1:]:
         assert 1.7 < o < 2.3
