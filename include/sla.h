@@ -268,7 +268,16 @@ typedef enum {
    * marching one range of the groups' planes laid end to end; 0 (default)
    * chunks whose count minimises rounds of workgroups x (planes per chunk +
    * pipeline fill). */
-  SLA_OPT_EC_SHAPE = 7
+  SLA_OPT_EC_SHAPE = 7,
+  /* Departure points of third-order steps (SLA_CEC): 0 (default) one explicit
+   * step from the arrival node, x - c(x) (the paper's); 1 a midpoint
+   * (second-order Runge-Kutta) backtrace, beyond the paper: along each axis
+   * the calls of L_U depart from x - c(x - c(x)/2) and the call of L_{-U}
+   * from x + c(x + c(x)/2), c interpolated linearly between nodes.  With 1,
+   * third-order steps run one tile sweep per axis (no fused or marching
+   * kernel) and sla_plan_create refuses the context; uniform velocities
+   * give the default's results to rounding. */
+  SLA_OPT_BACKTRACE = 8
 } sla_option;
 /* Set option `option` to `value`.  Returns SLA_EINVAL for an unknown option
  * or value. */

@@ -377,15 +377,32 @@ __device__ __forceinline__ float sweep_combine(float p1, float ei, float ea, flo
   return fmaf(0.5f, fmaf(w, eb - ea, ea), p1);
 }
 
+// The Courant number at a midpoint of a node's backtrace (MID sweeps): the
+// Courant numbers c of one column of a tile, cs apart in LDS, linearly
+// interpolated at local position pos (within the column: callers keep pos
+// at least one node inside it).
+__device__ __forceinline__ float mid_courant(const float* c, int cs, float pos, int nmax) {
+  float i0f = floorf(pos);
+  const float fr = pos - i0f;
+  const int i0 = min(max(int(i0f), 0), nmax - 2);
+  return (1.f - fr) * c[i0 * cs] + fr * c[(i0 + 1) * cs];
+}
+
 // Strided axis (y or z): tile = 64 consecutive x (coalesced) x TL along the axis.
-template <int R, int COMB = kCombCec>
+// MID: a midpoint backtrace (beyond the paper): the calls of L_U depart
+// from x - c(x - c/2) and the call of L_{-U} from x + c(x + c/2), the
+// Courant numbers interpolated along the axis from the tile's own, which
+// then reach 3R nodes out like phi.
+template <int R, int COMB = kCombCec, bool MID = false>
 __global__ __launch_bounds__(kThreads) void k_sweep_s(const float* __restrict__ phi,
                                                       const float* __restrict__ ud,
                                                       float* __restrict__ out, int nx, int L,
                                                       int64_t S, int64_t So, float lam, int* flag) {
   constexpr int TL = 32, TW = 64;
   constexpr int NP = TL + 6 * R, NC = TL + 4 * R, NE = TL + 2 * R;
-  __shared__ float P[NP * TW], C[NC * TW], P1[NC * TW], E[NE * TW];
+  constexpr int NL = MID ? NP : NC, CO = MID ? 3 * R : 2 * R;  // Courant rows loaded, their start
+  __shared__ float P[NP * TW], C[NL * TW], P1[NC * TW], E[NE * TW];
+  __shared__ float CM[MID ? 2 * NC * TW : 1];  // midpoint Courant numbers: forward, then reverse
   const int tx = threadIdx.x & (TW - 1), ty = threadIdx.x / TW;
   const int x = blockIdx.x * TW + tx;
   const int l0 = blockIdx.y * TL;
@@ -393,7 +410,7 @@ __global__ __launch_bounds__(kThreads) void k_sweep_s(const float* __restrict__ 
   const size_t base = (size_t)blockIdx.z * So + (xin ? x : 0);
   // issue every load of the tile before the first LDS store
   constexpr int RS = kThreads / TW;  // rows per pass
-  constexpr int KPr = (NP + RS - 1) / RS, KCr = (NC + RS - 1) / RS;
+  constexpr int KPr = (NP + RS - 1) / RS, KCr = (NL + RS - 1) / RS;
   float vp[KPr], vc[KCr];
 #pragma unroll
   for (int k = 0; k < KPr; ++k) {
@@ -404,23 +421,34 @@ __global__ __launch_bounds__(kThreads) void k_sweep_s(const float* __restrict__ 
 #pragma unroll
   for (int k = 0; k < KCr; ++k) {
     const int r = ty + k * RS;
-    const int l = wrapk(l0 - 2 * R + r, L);
-    vc[k] = (xin && r < NC) ? ud[base + (size_t)l * S] : 0.f;
+    const int l = wrapk(l0 - CO + r, L);
+    vc[k] = (xin && r < NL) ? ud[base + (size_t)l * S] : 0.f;
   }
 #pragma unroll
   for (int k = 0; k < KPr; ++k)
     if (ty + k * RS < NP) P[(ty + k * RS) * TW + tx] = vp[k];
 #pragma unroll
   for (int k = 0; k < KCr; ++k)
-    if (ty + k * RS < NC) C[(ty + k * RS) * TW + tx] = vc[k] * lam;
+    if (ty + k * RS < NL) C[(ty + k * RS) * TW + tx] = vc[k] * lam;
   __syncthreads();
+  // forward and reverse Courant numbers of the tile's nodes a0 - 2R + r
+  const float* CF = MID ? CM : C;
+  const float* CB = MID ? CM + NC * TW : C;
+  if (MID) {
+    for_strided<NC, kThreads / TW>(ty, [&](int r) {
+      const float c = C[(r + R) * TW + tx];
+      CM[r * TW + tx] = mid_courant(C + tx, TW, float(r + R) - 0.5f * c, NL);
+      CM[(NC + r) * TW + tx] = mid_courant(C + tx, TW, float(r + R) + 0.5f * c, NL);
+    });
+    __syncthreads();
+  }
   for_strided<NC, kThreads / TW>(ty, [&](int r) {
-    const Dep d = depart<R>(C[r * TW + tx], flag);
+    const Dep d = depart<R>(CF[r * TW + tx], flag);
     P1[r * TW + tx] = lerp(P[(r + R + d.oa) * TW + tx], P[(r + R + d.ob) * TW + tx], d.f);
   });
   __syncthreads();
   for_strided<NE, kThreads / TW>(ty, [&](int r) {
-    const Dep d = depart<R>(-C[(r + R) * TW + tx], flag);
+    const Dep d = depart<R>(-CB[(r + R) * TW + tx], flag);
     const float bar = lerp(P1[(r + R + d.oa) * TW + tx], P1[(r + R + d.ob) * TW + tx], d.f);
     E[r * TW + tx] = P[(r + 2 * R) * TW + tx] - bar;
   });
@@ -429,28 +457,31 @@ __global__ __launch_bounds__(kThreads) void k_sweep_s(const float* __restrict__ 
   for_strided<TL, kThreads / TW>(ty, [&](int r) {
     const int l = l0 + r;
     if (l >= L) return;
-    const Dep d = depart<R>(C[(r + 2 * R) * TW + tx], flag);
+    const Dep d = depart<R>(CF[(r + 2 * R) * TW + tx], flag);
     const float ea = E[(r + R + d.oa) * TW + tx], eb = E[(r + R + d.ob) * TW + tx];
     out[base + (size_t)l * S] =
         sweep_combine<COMB>(P1[(r + 2 * R) * TW + tx], E[(r + R) * TW + tx], ea, eb, d.f);
   });
 }
 
-// Contiguous axis (x): tile = TL consecutive x in each of ROWS rows.
-template <int R, int COMB = kCombCec>
+// Contiguous axis (x): tile = TL consecutive x in each of ROWS rows.  MID
+// as in k_sweep_s.
+template <int R, int COMB = kCombCec, bool MID = false>
 __global__ __launch_bounds__(kThreads) void k_sweep_x(const float* __restrict__ phi,
                                                       const float* __restrict__ ud,
                                                       float* __restrict__ out, int nx, int ny,
                                                       float lam, int* flag) {
   constexpr int TL = 256, ROWS = 4;
   constexpr int NP = TL + 6 * R, NC = TL + 4 * R, NE = TL + 2 * R;
-  __shared__ float P[ROWS * NP], C[ROWS * NC], P1[ROWS * NC], E[ROWS * NE];
+  constexpr int NL = MID ? NP : NC, CO = MID ? 3 * R : 2 * R;  // Courant entries loaded, their start
+  __shared__ float P[ROWS * NP], C[ROWS * NL], P1[ROWS * NC], E[ROWS * NE];
+  __shared__ float CM[MID ? 2 * ROWS * NC : 1];  // midpoint Courant numbers: forward, then reverse
   const int l0 = blockIdx.x * TL;
   const int y0 = blockIdx.y * ROWS;
   const size_t zoff = (size_t)blockIdx.z * nx * ny;
   // issue every load of the tile before the first LDS store
   constexpr int KPe = (ROWS * NP + kThreads - 1) / kThreads;
-  constexpr int KCe = (ROWS * NC + kThreads - 1) / kThreads;
+  constexpr int KCe = (ROWS * NL + kThreads - 1) / kThreads;
   float vp[KPe], vc[KCe];
 #pragma unroll
   for (int k = 0; k < KPe; ++k) {
@@ -462,9 +493,9 @@ __global__ __launch_bounds__(kThreads) void k_sweep_x(const float* __restrict__ 
 #pragma unroll
   for (int k = 0; k < KCe; ++k) {
     const int e = threadIdx.x + k * kThreads;
-    const int rr = e / NC, col = e - rr * NC;
+    const int rr = e / NL, col = e - rr * NL;
     const int y = y0 + rr;
-    vc[k] = (e < ROWS * NC && y < ny) ? ud[zoff + (size_t)y * nx + wrapk(l0 - 2 * R + col, nx)] : 0.f;
+    vc[k] = (e < ROWS * NL && y < ny) ? ud[zoff + (size_t)y * nx + wrapk(l0 - CO + col, nx)] : 0.f;
   }
 #pragma unroll
   for (int k = 0; k < KPe; ++k) {
@@ -474,19 +505,33 @@ __global__ __launch_bounds__(kThreads) void k_sweep_x(const float* __restrict__ 
 #pragma unroll
   for (int k = 0; k < KCe; ++k) {
     const int e = threadIdx.x + k * kThreads;
-    if (e < ROWS * NC) C[e] = vc[k] * lam;
+    if (e < ROWS * NL) C[e] = vc[k] * lam;
   }
   __syncthreads();
+  // forward and reverse Courant numbers of node l0 - 2R + col of row rr at
+  // rr * NC + col
+  const float* CF = MID ? CM : C;
+  const float* CB = MID ? CM + ROWS * NC : C;
+  if (MID) {
+    for_strided<ROWS * NC, kThreads>(threadIdx.x, [&](int e) {
+      const int rr = e / NC, col = e - rr * NC;
+      const float* row = C + rr * NL;
+      const float c = row[col + R];
+      CM[e] = mid_courant(row, 1, float(col + R) - 0.5f * c, NL);
+      CM[ROWS * NC + e] = mid_courant(row, 1, float(col + R) + 0.5f * c, NL);
+    });
+    __syncthreads();
+  }
   for_strided<ROWS * NC, kThreads>(threadIdx.x, [&](int e) {
     const int rr = e / NC, col = e - rr * NC;
-    const Dep d = depart<R>(C[e], flag);
+    const Dep d = depart<R>(CF[e], flag);
     const float* p = P + rr * NP + col + R;
     P1[e] = lerp(p[d.oa], p[d.ob], d.f);
   });
   __syncthreads();
   for_strided<ROWS * NE, kThreads>(threadIdx.x, [&](int e) {
     const int rr = e / NE, col = e - rr * NE;
-    const Dep d = depart<R>(-C[rr * NC + col + R], flag);
+    const Dep d = depart<R>(-CB[rr * NC + col + R], flag);
     const float* p1 = P1 + rr * NC + col + R;
     E[e] = P[rr * NP + col + 2 * R] - lerp(p1[d.oa], p1[d.ob], d.f);
   });
@@ -495,7 +540,7 @@ __global__ __launch_bounds__(kThreads) void k_sweep_x(const float* __restrict__ 
     const int rr = e / TL, col = e - rr * TL;
     const int y = y0 + rr, x = l0 + col;
     if (y >= ny || x >= nx) return;
-    const Dep d = depart<R>(C[rr * NC + col + 2 * R], flag);
+    const Dep d = depart<R>(CF[rr * NC + col + 2 * R], flag);
     const float* ee = E + rr * NE + col + R;
     out[zoff + (size_t)y * nx + x] =
         sweep_combine<COMB>(P1[rr * NC + col + 2 * R], ee[0], ee[d.oa], ee[d.ob], d.f);
@@ -1018,12 +1063,12 @@ hipError_t launch_cec_sweep_xy(int R, bool xfirst, const Geo& g, const float* ph
 }
 
 namespace {
-template <int R, int COMB>
+template <int R, int COMB, bool MID = false>
 hipError_t launch_split_t(int d, const Geo& g, const float* phi, const float* ud, float* out,
                           int* flag, hipStream_t st) {
   if (d == 0) {
     dim3 grid((g.nx + 255) / 256, (g.ny + 3) / 4, g.nz);
-    hipLaunchKernelGGL((k_sweep_x<R, COMB>), grid, dim3(kThreads), 0, st, phi, ud, out, g.nx, g.ny,
+    hipLaunchKernelGGL((k_sweep_x<R, COMB, MID>), grid, dim3(kThreads), 0, st, phi, ud, out, g.nx, g.ny,
                        g.lam[0], flag);
   } else {
     const int L = d == 1 ? g.ny : g.nz;
@@ -1031,19 +1076,19 @@ hipError_t launch_split_t(int d, const Geo& g, const float* phi, const float* ud
     const int other = d == 1 ? g.nz : g.ny;
     const int64_t So = d == 1 ? (int64_t)g.nx * g.ny : (int64_t)g.nx;
     dim3 grid((g.nx + 63) / 64, (L + 31) / 32, other);
-    hipLaunchKernelGGL((k_sweep_s<R, COMB>), grid, dim3(kThreads), 0, st, phi, ud, out, g.nx, L, S,
+    hipLaunchKernelGGL((k_sweep_s<R, COMB, MID>), grid, dim3(kThreads), 0, st, phi, ud, out, g.nx, L, S,
                        So, g.lam[d], flag);
   }
   return hipGetLastError();
 }
-template <int COMB>
+template <int COMB, bool MID = false>
 hipError_t launch_split_r(int d, int R, const Geo& g, const float* phi, const float* ud, float* out,
                           int* flag, hipStream_t st) {
   switch (R) {
-    case 1: return launch_split_t<1, COMB>(d, g, phi, ud, out, flag, st);
-    case 2: return launch_split_t<2, COMB>(d, g, phi, ud, out, flag, st);
-    case 3: return launch_split_t<3, COMB>(d, g, phi, ud, out, flag, st);
-    case 4: return launch_split_t<4, COMB>(d, g, phi, ud, out, flag, st);
+    case 1: return launch_split_t<1, COMB, MID>(d, g, phi, ud, out, flag, st);
+    case 2: return launch_split_t<2, COMB, MID>(d, g, phi, ud, out, flag, st);
+    case 3: return launch_split_t<3, COMB, MID>(d, g, phi, ud, out, flag, st);
+    case 4: return launch_split_t<4, COMB, MID>(d, g, phi, ud, out, flag, st);
   }
   return hipErrorInvalidValue;
 }
@@ -1055,6 +1100,11 @@ hipError_t launch_ec_sweep(int scheme, int d, int R, const Geo& g, const float* 
   if (scheme == BEC) return launch_split_r<kCombBec>(d, R, g, phi, ud, out, flag, st);
   if (scheme == CEC_LITERAL) return launch_split_r<kCombCecLit>(d, R, g, phi, ud, out, flag, st);
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_cec_sweep_mid(int d, int R, const Geo& g, const float* phi, const float* ud,
+                                float* out, int* flag, hipStream_t st) {
+  return launch_split_r<kCombCec, true>(d, R, g, phi, ud, out, flag, st);
 }
 
 hipError_t launch_cec_sweep(int d, int R, const Geo& g, const float* phi, const float* ud,

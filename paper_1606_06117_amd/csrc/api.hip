@@ -31,6 +31,7 @@ struct sla_ctx {
   int ec_kernel = 3;     // SLA_OPT_EC_KERNEL
   int cec3d_shape = 0;   // SLA_OPT_CEC3D_SHAPE
   int ec_shape = 0;      // SLA_OPT_EC_SHAPE
+  int backtrace = 0;     // SLA_OPT_BACKTRACE
   // fused-step choices measured by sla_tune (or loaded), per grid
   struct Tuned {
     int n[3];
@@ -528,6 +529,7 @@ int sla_advect_multi(sla_ctx* ctx, const sla_grid* grid, int32_t nscalars, float
   // third order in 3D at reach 1: the fields run up to four at a time
   // through the shared-velocity fused step, each with its own work field
   const bool shared = scheme == SLA_CEC && grid->ndim == 3 && ctx->fused && ctx->multi > 1 &&
+                      ctx->backtrace == 0 &&
                       reach[0] == 1 && reach[1] == 1 && reach[2] == 1 && nscalars >= 2 &&
                       sla::offsets32_ok(geo);
   if (!shared) {
@@ -611,7 +613,7 @@ int sla_advect_batch(sla_ctx* ctx, int32_t nprob, const sla_problem* probs, int3
   if (steps == 0 || nprob == 0) return SLA_OK;
   DeviceGuard guard(ctx->device);
   if (!guard.ok) return fail(ctx, SLA_EHIP, "cannot select device %d", ctx->device);
-  if (scheme == SLA_CEC && all3d) {
+  if (scheme == SLA_CEC && all3d && ctx->backtrace == 0) {
     // every Courant number below 1: one plan (a graph of all steps), run once
     sla_plan* plan = nullptr;
     int rc = sla_plan_create(ctx, &plan, nprob, probs, steps, step0, courant_max, 0);
@@ -753,6 +755,17 @@ int advect_steps(sla_ctx* ctx, const sla_grid* grid, float* phi, const float* u,
         break;
       }
       case SLA_CEC: {
+        if (ctx->backtrace == 1) {  // midpoint backtrace: tile sweeps, the alternating order
+          for (int j = 0; j < ndim && e == hipSuccess; ++j) {
+            const int d = (m % 2 == 0) ? j : ndim - 1 - j;
+            e = run(ctx, SLA_K_SWEEP_X + d, [&] {
+              return sla::launch_cec_sweep_mid(d, reach[d], geo, cur, u + size_t(d) * n, nxt,
+                                               ctx->flag, ctx->stream);
+            });
+            std::swap(cur, nxt);
+          }
+          break;
+        }
         if (fused3d) {
           e = run(ctx, SLA_K_CEC3D, [&] {
             sla::Cec3dLaunch lc;
@@ -904,6 +917,10 @@ int sla_set_option(sla_ctx* ctx, int option, int64_t value) {
     case SLA_OPT_EC_SHAPE:
       if (value < -4096 || value > 64) return fail(ctx, SLA_EINVAL, "SLA_OPT_EC_SHAPE takes -4096..64");
       ctx->ec_shape = int(value);
+      return SLA_OK;
+    case SLA_OPT_BACKTRACE:
+      if (value != 0 && value != 1) return fail(ctx, SLA_EINVAL, "SLA_OPT_BACKTRACE takes 0 or 1");
+      ctx->backtrace = int(value);
       return SLA_OK;
     case SLA_OPT_LEARNED_KERNEL:
       if (value != 0 && value != 1) return fail(ctx, SLA_EINVAL, "SLA_OPT_LEARNED_KERNEL takes 0 or 1");
@@ -1541,6 +1558,8 @@ int sla_plan_create(sla_ctx* ctx, sla_plan** out, int32_t nprob, const sla_probl
   *out = nullptr;
   if (steps < 0) return fail(ctx, SLA_EINVAL, "steps must be >= 0");
   if (std::isnan(courant_max)) return fail(ctx, SLA_EINVAL, "courant_max is NaN");
+  if (ctx->backtrace != 0)
+    return fail(ctx, SLA_EINVAL, "plans run the arrival-node backtrace (SLA_OPT_BACKTRACE = 0)");
   if (capturing(ctx))
     return fail(ctx, SLA_ECAPTURE, "creating a plan allocates and synchronises the stream");
   DeviceGuard guard(ctx->device);

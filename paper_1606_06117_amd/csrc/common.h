@@ -61,6 +61,11 @@ hipError_t launch_ec_gather(int ndim, int mode, const Geo& g, const float* a, co
 // applied along one axis (tile kernels, reach 1-4).
 hipError_t launch_ec_sweep(int scheme, int d, int R, const Geo& g, const float* phi,
                            const float* ud, float* out, int* flag, hipStream_t st);
+// One third-order sweep along axis d with a midpoint backtrace: the calls of
+// L_U depart from x - c(x - c/2), the call of L_{-U} from x + c(x + c/2)
+// (tile kernels, reach 1-4).
+hipError_t launch_cec_sweep_mid(int d, int R, const Geo& g, const float* phi, const float* ud,
+                                float* out, int* flag, hipStream_t st);
 hipError_t launch_cec_sweep(int d, int R, const Geo& g, const float* phi,
                             const float* u_d, float* out, int* flag, hipStream_t st,
                             bool march = true);

@@ -30,6 +30,7 @@ OPT_CEC3D_SHAPE = 4
 OPT_LEARNED_KERNEL = 5
 OPT_SHARED_VELOCITY = 6
 OPT_EC_SHAPE = 7
+OPT_BACKTRACE = 8
 
 # every symbol include/sla.h declares, with (restype, argtypes)
 _c = ctypes
