@@ -1260,16 +1260,28 @@ int sla_model_forward(sla_ctx* ctx, const sla_model* model, const uint16_t* feat
 }  // extern "C"
 
 namespace {
+// The gradient of the mean squared error over the m rows into model->grad and
+// the loss sum into model->loss; with lr >= 0 also the Adam step (the update
+// in the reduction's kernel).
 int model_gradient(sla_ctx* ctx, sla_model* model, const uint16_t* feats, const float* target,
-                   int64_t m) {
+                   int64_t m, double lr = -1.0) {
   if (!model || !feats || !target) return fail(ctx, SLA_EINVAL, "pointer arguments must not be NULL");
   if (m <= 0 || m > (int64_t(1) << 30)) return fail(ctx, SLA_EINVAL, "bad row count");
   int nblk = 0;
   hipError_t e = sla::launch_mlp(true, feats, target, int(m), float(2.0 / double(m)), model->wpack,
                                  model->wr, nullptr, model->gpart, model->lpart, &nblk, ctx->stream);
-  if (e == hipSuccess)
+  if (e == hipSuccess && lr < 0.0)
     e = sla::launch_grad_reduce(model->gpart, model->lpart, nblk, model->grad, model->loss,
                                 ctx->stream);
+  if (e == hipSuccess && lr >= 0.0) {
+    model->adam_t += 1;
+    const double b1 = 0.9, b2 = 0.999;
+    const float bc1 = float(1.0 - std::pow(b1, double(model->adam_t)));
+    const float bc2 = float(1.0 - std::pow(b2, double(model->adam_t)));
+    e = sla::launch_grad_adam(model->gpart, model->lpart, nblk, model->grad, model->loss,
+                              model->master, model->mo, model->vo, float(lr), float(b1), float(b2),
+                              1e-8f, bc1, bc2, model->wr, model->wpack, ctx->stream);
+  }
   if (e != hipSuccess) return hip_fail(ctx, e, "network gradient launch");
   return SLA_OK;
 }
@@ -1306,16 +1318,8 @@ int sla_model_train_step(sla_ctx* ctx, sla_model* model, const uint16_t* feats, 
   ctx->err.clear();
   if (!(lr >= 0.0) || !std::isfinite(lr)) return fail(ctx, SLA_EINVAL, "bad learning rate");
   DeviceGuard guard(ctx->device);
-  int rc = model_gradient(ctx, model, feats, target, m);
+  int rc = model_gradient(ctx, model, feats, target, m, lr);
   if (rc) return rc;
-  model->adam_t += 1;
-  const double b1 = 0.9, b2 = 0.999;
-  const float bc1 = float(1.0 - std::pow(b1, double(model->adam_t)));
-  const float bc2 = float(1.0 - std::pow(b2, double(model->adam_t)));
-  hipError_t e = sla::launch_adam(model->master, model->mo, model->vo, model->grad, float(lr),
-                                  float(b1), float(b2), 1e-8f, bc1, bc2, model->wr, model->wpack,
-                                  ctx->stream);
-  if (e != hipSuccess) return hip_fail(ctx, e, "Adam launch");
   if (loss) return read_loss(ctx, model, m, loss);
   return SLA_OK;
 }

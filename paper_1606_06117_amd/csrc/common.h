@@ -123,10 +123,13 @@ hipError_t launch_mlp(bool train, const void* X, const float* target, int m, flo
                       float* lpart, int* nblk_out, hipStream_t st);
 hipError_t launch_grad_reduce(const float* gpart, const float* lpart, int nblk, float* grad,
                               double* loss_sum, hipStream_t st);
+// launch_grad_reduce with the training step's Adam update of every parameter
+// (Adam, Kingma & Ba, on the FP32 master weights) in the same kernel.
+hipError_t launch_grad_adam(const float* gpart, const float* lpart, int nblk, float* grad,
+                            double* loss_sum, float* master, float* m, float* v, float lr,
+                            float beta1, float beta2, float eps, float bc1, float bc2, float* wr,
+                            void* wpack, hipStream_t st);
 hipError_t launch_pack(const float* master, float* wr, void* wpack, hipStream_t st);
-hipError_t launch_adam(float* master, float* m, float* v, const float* grad, float lr, float beta1,
-                       float beta2, float eps, float bc1, float bc2, float* wr, void* wpack,
-                       hipStream_t st);
 hipError_t launch_make_pairs(const Geo& g, const float* phi1, const float* phi_next, const float* u,
                              const int* cells, int m, void* X, float* target, float* sigma,
                              hipStream_t st);

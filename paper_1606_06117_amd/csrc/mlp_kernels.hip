@@ -112,7 +112,7 @@ constexpr int SC = 32 + 8;  // rows of 32 cells
 // Weights in LDS: W1T [n][k] (64 x 32), W2T [n][k] (64 x 64), all BF16 with
 // padded rows; biases and w3 FP32 (already BF16-rounded).  Training also
 // keeps W2R [k][n] (64 x 64).
-struct WeightsLds {
+struct alignas(16) WeightsLds {
   __bf16 w1t[NH * SF];
   __bf16 w2t[NH * SH];
   float b1[NH], b2[NH], w3[NH], b3;
@@ -196,58 +196,25 @@ __device__ __forceinline__ void forward_tile(const WeightsLds& W, const bf16x8 x
 }
 
 // ---------------------------------------------------------------------------
-// Training / evaluation on feature rows.
-// X: m rows of 32 BF16 features.  TRAIN: accumulate the gradient of
-// mean((y - t)^2) (inv_m2 = 2 / m_total) into per-workgroup partials
-// gpart[blockIdx][kMlpParams] and the squared error into lpart[blockIdx].
-// Otherwise write y.  Every wave of a block runs the same number of tiles.
+// Evaluation on feature rows: X holds m rows of 32 BF16 features; y of every
+// row to yout.  Every wave of a block runs the same number of tiles.
 // ---------------------------------------------------------------------------
-struct TrainLds {
+struct EvalLds {
   WeightsLds W;
-  __bf16 w2r[NH * SH];     // W2R [k][n]
-  __bf16 h1[4][32 * SH];   // [cell][hidden]
-  __bf16 h1t[4][NH * SC];  // [hidden][cell]
-  __bf16 dh2[4][32 * SH];  // [cell][n]
-  __bf16 dh2t[4][NH * SC]; // [n][cell]
-  __bf16 dh1t[4][NH * SC]; // [k][cell]
-  __bf16 xt[4][NF * SC];   // [feature][cell]
+  __bf16 h1[4][32 * SH];  // [cell][hidden]
 };
 
-template <bool TRAIN>
-__global__ __launch_bounds__(kThreads) void k_mlp(const __bf16* __restrict__ X,
-                                                  const float* __restrict__ target, int m,
-                                                  float inv_m2, int tiles_per_wave,
-                                                  const __bf16* __restrict__ wpack,
-                                                  const float* __restrict__ wr,
-                                                  float* __restrict__ yout,
-                                                  float* __restrict__ gpart,
-                                                  float* __restrict__ lpart) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  TrainLds& L = *reinterpret_cast<TrainLds*>(smem);
-  load_weights(L.W, TRAIN ? L.w2r : nullptr, wpack, wr);
+__global__ __launch_bounds__(kThreads) void k_mlp_eval(const __bf16* __restrict__ X, int m,
+                                                       int tiles_per_wave,
+                                                       const __bf16* __restrict__ wpack,
+                                                       const float* __restrict__ wr,
+                                                       float* __restrict__ yout) {
+  __shared__ __align__(16) EvalLds L;
+  load_weights(L.W, nullptr, wpack, wr);
   __syncthreads();
   const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15, w = threadIdx.x >> 6;
-  __bf16* h1 = L.h1[w];
-
-  floatx4 dw2[4][4], dw1[4][2];
-  float dw3[4][4], db2[4][4], db1[4][4], db3 = 0.f, sq = 0.f;
-  if (TRAIN) {
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        dw2[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
-        dw3[a][b] = db2[a][b] = db1[a][b] = 0.f;
-      }
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-      for (int b = 0; b < 2; ++b) dw1[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
-  }
-
   for (int tt = 0; tt < tiles_per_wave; ++tt) {
-    const int tile = (blockIdx.x * tiles_per_wave + tt) * 4 + w;
-    const int r0 = tile * 32;
+    const int r0 = ((blockIdx.x * tiles_per_wave + tt) * 4 + w) * 32;
     bf16x8 xb[2];
 #pragma unroll
     for (int jt = 0; jt < 2; ++jt) {
@@ -258,65 +225,266 @@ __global__ __launch_bounds__(kThreads) void k_mlp(const __bf16* __restrict__ X,
 #pragma unroll
         for (int v = 0; v < 8; ++v) xb[jt][v] = (__bf16)0.f;
       }
-      if (TRAIN) {
-#pragma unroll
-        for (int v = 0; v < 8; ++v) L.xt[w][(8 * g + v) * SC + 16 * jt + c] = xb[jt][v];
-      }
     }
     floatx4 h2[4][2];
     float y[2];
-    forward_tile(L.W, xb, h1, h2, y);
-    if (!TRAIN) {
+    forward_tile(L.W, xb, L.h1[w], h2, y);
+#pragma unroll
+    for (int jt = 0; jt < 2; ++jt) {
+      const int row = r0 + 16 * jt + c;
+      if (g == 0 && row < m) yout[row] = y[jt];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Training on feature rows: the gradient of mean((y - t)^2) (inv_m2 =
+// 2 / m_total) summed over the block's rows into gpart[blockIdx][kMlpParams]
+// and the squared error into lpart[blockIdx].  A wave runs 32-row tiles;
+// every product of the backward pass is a matrix-core product.  Those whose
+// reduction runs over the tile's rows (the weight gradients) take both
+// operands with the rows as the K index: each operand is kept in LDS as a
+// row-major [row][unit] tile, written with one vector store per lane from
+// the layout the forward pass produced, and read into the operand layout by
+// gfx950's transposing LDS load (ds_read_b64_tr_b16: within 16 lanes, lane r
+// gives the address of 4 consecutive 16-bit values and receives value q
+// from lane r/4 + 4q, element r%4).  The tiles belong to one wave: a
+// wave-scope LDS fence orders them, no workgroup barrier.  The waves' sums
+// are added in a fixed order at the end (deterministic).
+// ---------------------------------------------------------------------------
+// Order of a training block's gradient partials (and of the slots they are
+// summed in): lane-major, value v of lane l (l = 16 g + c) at v * 64 + l.
+// Values 0..63 are the W2 tiles, (nt * 4 + kt) * 4 + q for W2[16 kt + c]
+// [16 nt + 4 g + q]; 64..95 the W1 tiles, 64 + (kt * 2 + it) * 4 + q for
+// W1[16 it + c][16 kt + 4 g + q]; then, from kPosUnits, w3, b2 and b1 by
+// unit, b3, and the squared error.
+constexpr int kPosW1 = 64 * 64, kPosUnits = 96 * 64, kPosLoss = kPosUnits + 193;
+static_assert(kPosLoss == kMlpParams, "one position per parameter, then the loss");
+__device__ __forceinline__ int param_of_pos(int pos) {
+  if (pos < kPosW1) {
+    const int v = pos / 64, l = pos % 64;
+    return W2_OFF + (16 * ((v / 4) % 4) + l % 16) * NH + 16 * (v / 16) + 4 * (l / 16) + v % 4;
+  }
+  if (pos < kPosUnits) {
+    const int v = (pos - kPosW1) / 64, l = pos % 64;
+    return W1_OFF + (16 * ((v / 4) % 2) + l % 16) * NH + 16 * (v / 8) + 4 * (l / 16) + v % 4;
+  }
+  const int j = pos - kPosUnits;
+  return j < 64 ? W3_OFF + j : j < 128 ? B2_OFF + (j - 64) : j < 192 ? B1_OFF + (j - 128) : B3_OFF;
+}
+
+constexpr int kTrWaves = 4;
+struct TrainLds {
+  WeightsLds W;
+  alignas(16) __bf16 w2r[NH * SH];  // W2R [k][n]
+  union alignas(16) {
+    struct {
+      __bf16 x[kTrWaves][32 * SF];    // [row][feature]
+      __bf16 h1[kTrWaves][32 * SH];   // [row][hidden]
+      __bf16 dh2[kTrWaves][32 * SH];  // [row][n]
+      __bf16 dh1[kTrWaves][32 * SH];  // [row][k]
+    } t;
+    float red[4][kPosLoss + 1];  // the waves' sums, four slots in partial order
+  } u;
+};
+
+// Operands of products whose K index is the tile's 32 rows, from a
+// row-major tile T (row stride S BF16 values): operand t of NOPS receives
+// at lane (g, c) T[8g .. 8g+7][16 t + c], the A operand of rows 16t..16t+15
+// of the product's left factor, or the B operand of its columns
+// 16t..16t+15.  Lane (g, r) addresses row 8g + r/4, columns 4 (r%4) ..
+// +3 of each 16-column block, for rows 8g..8g+3 and again 4 rows down.
+// The reads are written in assembly: the compiler's builtin for this
+// instruction returns each lane's four values as copies of the first.  The
+// block waits for its own reads, so no load is left in flight.
+template <int S, int NOPS>
+__device__ __forceinline__ void ld_rows_ops(const __bf16* T, int lane, bf16x8 (&o)[NOPS]) {
+  static_assert(NOPS == 2 || NOPS == 4, "two or four 16-column blocks");
+  const int g = lane >> 4, r = lane & 15;
+  typedef __attribute__((address_space(3))) const __bf16 lds_bf16;
+  const unsigned a = unsigned(reinterpret_cast<size_t>((lds_bf16*)(T + (8 * g + r / 4) * S + 4 * (r % 4))));
+  uintx2 v[8];
+  if constexpr (NOPS == 4) {
+    asm volatile(
+        "ds_read_b64_tr_b16 %0, %8\n\t"
+        "ds_read_b64_tr_b16 %1, %8 offset:%9\n\t"
+        "ds_read_b64_tr_b16 %2, %8 offset:32\n\t"
+        "ds_read_b64_tr_b16 %3, %8 offset:%10\n\t"
+        "ds_read_b64_tr_b16 %4, %8 offset:64\n\t"
+        "ds_read_b64_tr_b16 %5, %8 offset:%11\n\t"
+        "ds_read_b64_tr_b16 %6, %8 offset:96\n\t"
+        "ds_read_b64_tr_b16 %7, %8 offset:%12\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        : "=&v"(v[0]), "=&v"(v[1]), "=&v"(v[2]), "=&v"(v[3]), "=&v"(v[4]), "=&v"(v[5]), "=&v"(v[6]),
+          "=&v"(v[7])
+        : "v"(a), "i"(8 * S), "i"(8 * S + 32), "i"(8 * S + 64), "i"(8 * S + 96)
+        : "memory");
+  } else {
+    asm volatile(
+        "ds_read_b64_tr_b16 %0, %4\n\t"
+        "ds_read_b64_tr_b16 %1, %4 offset:%5\n\t"
+        "ds_read_b64_tr_b16 %2, %4 offset:32\n\t"
+        "ds_read_b64_tr_b16 %3, %4 offset:%6\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        : "=&v"(v[0]), "=&v"(v[1]), "=&v"(v[2]), "=&v"(v[3])
+        : "v"(a), "i"(8 * S), "i"(8 * S + 32)
+        : "memory");
+  }
+#pragma unroll
+  for (int t = 0; t < NOPS; ++t)
+    o[t] = __builtin_bit_cast(bf16x8, uintx4{v[2 * t][0], v[2 * t][1], v[2 * t + 1][0], v[2 * t + 1][1]});
+}
+
+__global__ __launch_bounds__(64 * kTrWaves) void k_mlp_train(const __bf16* __restrict__ X,
+                                                             const float* __restrict__ target,
+                                                             int m, float inv_m2, int tiles_per_wave,
+                                                             const __bf16* __restrict__ wpack,
+                                                             const float* __restrict__ wr,
+                                                             float* __restrict__ gpart,
+                                                             float* __restrict__ lpart) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  TrainLds& L = *reinterpret_cast<TrainLds*>(smem);
+  constexpr int NT = 64 * kTrWaves;
+  const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15, w = threadIdx.x >> 6;
+  // rows of tile tt: B operands of the forward's first layer (features
+  // 8g..8g+7 of rows 16 jt + c), loaded from a clamped row and zeroed past m
+  // (no load under a condition)
+  // (and their targets, 0 past m)
+  auto load_x = [&](int tt, bf16x8 (&xb)[2], float (&tg)[2]) {
+    const int r0 = ((blockIdx.x * tiles_per_wave + tt) * kTrWaves + w) * 32;
+#pragma unroll
+    for (int jt = 0; jt < 2; ++jt) {
+      const int row = r0 + 16 * jt + c;
+      const uintx4 v = __builtin_bit_cast(uintx4, ld8(&X[(size_t)min(row, m - 1) * NF + 8 * g]));
+      const float t = target[min(row, m - 1)];
+      const unsigned keep = row < m ? ~0u : 0u;
+      xb[jt] = __builtin_bit_cast(bf16x8, uintx4{v[0] & keep, v[1] & keep, v[2] & keep, v[3] & keep});
+      tg[jt] = row < m ? t : 0.f;
+    }
+  };
+  bf16x8 xnext[2];
+  float tnext[2];
+  load_x(0, xnext, tnext);  // in flight while the weights are staged
+  // weights: 16-byte loads of the packed operand layouts into padded rows
+  for (int i = threadIdx.x; i < NH * NF / 8; i += NT)
+    *reinterpret_cast<bf16x8*>(&L.W.w1t[(i / (NF / 8)) * SF + 8 * (i % (NF / 8))]) = ld8(&wpack[8 * i]);
+  for (int i = threadIdx.x; i < NH * NH / 8; i += NT) {
+    const int row = i / (NH / 8), col = 8 * (i % (NH / 8));
+    *reinterpret_cast<bf16x8*>(&L.W.w2t[row * SH + col]) = ld8(&wpack[NH * NF + 8 * i]);
+    *reinterpret_cast<bf16x8*>(&L.w2r[row * SH + col]) = ld8(&wpack[NH * NF + NH * NH + 8 * i]);
+  }
+  for (int i = threadIdx.x; i < NH; i += NT) {
+    L.W.b1[i] = wr[B1_OFF + i];
+    L.W.b2[i] = wr[B2_OFF + i];
+    L.W.w3[i] = wr[W3_OFF + i];
+  }
+  if (threadIdx.x == 0) L.W.b3 = wr[B3_OFF];
+  __syncthreads();
+  __bf16* xs = L.u.t.x[w];
+  __bf16* h1 = L.u.t.h1[w];
+  __bf16* dh2 = L.u.t.dh2[w];
+  __bf16* dh1 = L.u.t.dh1[w];
+
+  floatx4 dw2[4][4], dw1[4][2];  // dW2T[n][k], dW1T[k][i] tiles (D layout)
+  float dw3[4][4], db2[4][4], db1[4][4], db3 = 0.f, sq = 0.f;
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      dw2[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
+      dw3[a][b] = db2[a][b] = db1[a][b] = 0.f;
+    }
+#pragma unroll
+    for (int b = 0; b < 2; ++b) dw1[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
+  }
+
+  for (int tt = 0; tt < tiles_per_wave; ++tt) {
+    const int r0 = ((blockIdx.x * tiles_per_wave + tt) * kTrWaves + w) * 32;
+    bf16x8 xb[2] = {xnext[0], xnext[1]};
+    const float tg[2] = {tnext[0], tnext[1]};
+    load_x(min(tt + 1, tiles_per_wave - 1), xnext, tnext);  // the next tile's rows
+#pragma unroll
+    for (int jt = 0; jt < 2; ++jt) *reinterpret_cast<bf16x8*>(&xs[(16 * jt + c) * SF + 8 * g]) = xb[jt];
+    // ---- forward (as forward_tile), keeping which H1 entries are positive
+    unsigned h1pos = 0;  // bit 8 it + 4 jt + q: H1[16 jt + c][16 it + 4g + q] > 0
+#pragma unroll
+    for (int it = 0; it < 4; ++it) {
+      const bf16x8 a = ld8(&L.W.w1t[(16 * it + c) * SF + 8 * g]);
+      const int k = 16 * it + 4 * g;
+      const floatx4 bias = *reinterpret_cast<const floatx4*>(&L.W.b1[k]);
 #pragma unroll
       for (int jt = 0; jt < 2; ++jt) {
-        const int row = r0 + 16 * jt + c;
-        if (g == 0 && row < m) yout[row] = y[jt];
+        const floatx4 acc = mfma(a, xb[jt], bias);
+        float hv[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          hv[q] = fmaxf(acc[q], 0.f);
+          if ((float)(__bf16)hv[q] > 0.f) h1pos |= 1u << (8 * it + 4 * jt + q);
+        }
+        st4(&h1[(16 * jt + c) * SH + k], hv[0], hv[1], hv[2], hv[3]);
       }
-      continue;
     }
-    // ---- backward
+    wave_lds_sync();
+    floatx4 h2[4][2];
+    float s[2] = {0.f, 0.f};
+#pragma unroll
+    for (int it = 0; it < 4; ++it) {
+#pragma unroll
+      for (int jt = 0; jt < 2; ++jt) {
+        const int n = 16 * it + 4 * g;
+        floatx4 acc = *reinterpret_cast<const floatx4*>(&L.W.b2[n]);
+#pragma unroll
+        for (int kk = 0; kk < 2; ++kk)
+          acc = mfma(ld8(&L.W.w2t[(16 * it + c) * SH + 32 * kk + 8 * g]),
+                     ld8(&h1[(16 * jt + c) * SH + 32 * kk + 8 * g]), acc);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          acc[q] = fmaxf(acc[q], 0.f);
+          s[jt] = fmaf(acc[q], L.W.w3[n + q], s[jt]);
+        }
+        h2[it][jt] = acc;
+      }
+    }
     float dy[2];
 #pragma unroll
     for (int jt = 0; jt < 2; ++jt) {
       const int row = r0 + 16 * jt + c;
-      const float err = row < m ? y[jt] - target[row] : 0.f;
+      const float y = sum4g(s[jt]) + L.W.b3;
+      const float err = row < m ? y - tg[jt] : 0.f;
       dy[jt] = err * inv_m2;
       if (g == 0) {
         sq = fmaf(err, err, sq);
         db3 += dy[jt];
       }
     }
-    // H1 transposed copy for the W2 gradient (this wave's tile only)
-    for (int e = lane; e < 32 * NH; e += 64) {
-      const int j = e / NH, k = e % NH;
-      L.h1t[w][k * SC + j] = h1[j * SH + k];
-    }
+    // ---- backward: dH2 = dy w3 where H2 > 0, as [row][n]
 #pragma unroll
     for (int it = 0; it < 4; ++it) {
 #pragma unroll
       for (int jt = 0; jt < 2; ++jt) {
-        const int n = 16 * it + 4 * g, j = 16 * jt + c;
+        const int n = 16 * it + 4 * g;
         float d[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           dw3[it][q] = fmaf(h2[it][jt][q], dy[jt], dw3[it][q]);
           d[q] = h2[it][jt][q] > 0.f ? dy[jt] * L.W.w3[n + q] : 0.f;
           db2[it][q] += d[q];
-          L.dh2t[w][(n + q) * SC + j] = (__bf16)d[q];
         }
-        st4(&L.dh2[w][j * SH + n], d[0], d[1], d[2], d[3]);
+        st4(&dh2[(16 * jt + c) * SH + n], d[0], d[1], d[2], d[3]);
       }
     }
-    __syncthreads();
-    // dW2T[n][k] += sum_j dH2T[n][j] H1[j][k]
+    wave_lds_sync();
+    // dW2T[n][k] += sum over rows of dH2[row][n] H1[row][k]
+    {
+      bf16x8 a[4], bk[4];
+      ld_rows_ops<SH, 4>(dh2, lane, a);
+      ld_rows_ops<SH, 4>(h1, lane, bk);
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt) {
-      const bf16x8 a = ld8(&L.dh2t[w][(16 * nt + c) * SC + 8 * g]);
+      for (int nt = 0; nt < 4; ++nt)
 #pragma unroll
-      for (int kt = 0; kt < 4; ++kt)
-        dw2[nt][kt] = mfma(a, ld8(&L.h1t[w][(16 * kt + c) * SC + 8 * g]), dw2[nt][kt]);
+        for (int kt = 0; kt < 4; ++kt) dw2[nt][kt] = mfma(a[nt], bk[kt], dw2[nt][kt]);
     }
-    // dH1T[k][j] = sum_n W2R[k][n] dH2[j][n], masked by H1 > 0
+    // dH1T[k][row] = sum_n W2R[k][n] dH2[row][n], where H1 > 0; stored as [row][k]
 #pragma unroll
     for (int kt = 0; kt < 4; ++kt) {
 #pragma unroll
@@ -325,57 +493,34 @@ __global__ __launch_bounds__(kThreads) void k_mlp(const __bf16* __restrict__ X,
 #pragma unroll
         for (int nn = 0; nn < 2; ++nn)
           acc = mfma(ld8(&L.w2r[(16 * kt + c) * SH + 32 * nn + 8 * g]),
-                     ld8(&L.dh2[w][(16 * jt + c) * SH + 32 * nn + 8 * g]), acc);
-        const int k = 16 * kt + 4 * g, j = 16 * jt + c;
+                     ld8(&dh2[(16 * jt + c) * SH + 32 * nn + 8 * g]), acc);
+        float d[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          const float d = (float)h1[j * SH + k + q] > 0.f ? acc[q] : 0.f;
-          db1[kt][q] += d;
-          L.dh1t[w][(k + q) * SC + j] = (__bf16)d;
+          d[q] = (h1pos >> (8 * kt + 4 * jt + q)) & 1u ? acc[q] : 0.f;
+          db1[kt][q] += d[q];
         }
+        st4(&dh1[(16 * jt + c) * SH + 16 * kt + 4 * g], d[0], d[1], d[2], d[3]);
       }
     }
-    __syncthreads();
-    // dW1T[k][i] += sum_j dH1T[k][j] X[j][i]
-#pragma unroll
-    for (int kt = 0; kt < 4; ++kt) {
-      const bf16x8 a = ld8(&L.dh1t[w][(16 * kt + c) * SC + 8 * g]);
-#pragma unroll
-      for (int it = 0; it < 2; ++it)
-        dw1[kt][it] = mfma(a, ld8(&L.xt[w][(16 * it + c) * SC + 8 * g]), dw1[kt][it]);
-    }
-    __syncthreads();  // tile buffers are rewritten by the next tile
-  }
-  if (!TRAIN) return;
-
-  // ---- per-block gradient: waves add their partials in a fixed order
-  float* acc = reinterpret_cast<float*>(L.h1);  // kMlpParams floats fit in h1..dh2
-  static_assert(sizeof(L.h1) + sizeof(L.h1t) + sizeof(L.dh2) >= kMlpParams * sizeof(float),
-                "gradient staging");
-  // lane-owned entries
-  auto contribute = [&](bool first) {
-#pragma unroll
-    for (int nt = 0; nt < 4; ++nt)
+    wave_lds_sync();
+    // dW1T[k][i] += sum over rows of dH1[row][k] X[row][i]
+    {
+      bf16x8 a[4], bx[2];
+      ld_rows_ops<SH, 4>(dh1, lane, a);
+      ld_rows_ops<SF, 2>(xs, lane, bx);
 #pragma unroll
       for (int kt = 0; kt < 4; ++kt)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int n = 16 * nt + 4 * g + q, k = 16 * kt + c;  // dW2T[n][k] -> W2[k][n]
-          float* p = &acc[W2_OFF + k * NH + n];
-          *p = first ? dw2[nt][kt][q] : *p + dw2[nt][kt][q];
-        }
-#pragma unroll
-    for (int kt = 0; kt < 4; ++kt)
-#pragma unroll
-      for (int it = 0; it < 2; ++it)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int k = 16 * kt + 4 * g + q, i = 16 * it + c;  // dW1T[k][i] -> W1[i][k]
-          float* p = &acc[W1_OFF + i * NH + k];
-          *p = first ? dw1[kt][it][q] : *p + dw1[kt][it][q];
-        }
-  };
-  // reduce the lane-local vector partials over the 16 cells of a lane group
+        for (int it = 0; it < 2; ++it) dw1[kt][it] = mfma(a[kt], bx[it], dw1[kt][it]);
+    }
+    wave_lds_sync();  // the tiles are rewritten by the wave's next tile
+  }
+
+  // ---- the block's sum, in partial order: waves 0-3 write slots 0-3, waves
+  // 4-7 add theirs to slot w - 4, then every position is summed over the
+  // slots in slot order (lane-major, so no two lanes of an access share a
+  // bank)
   float rw3[4][4], rb2[4][4], rb1[4][4];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
@@ -387,78 +532,68 @@ __global__ __launch_bounds__(kThreads) void k_mlp(const __bf16* __restrict__ X,
     }
   const float rb3 = sum16(sum4g(db3));
   const float rsq = sum16(sum4g(sq));
-  __syncthreads();
-  for (int ww = 0; ww < 4; ++ww) {
-    if (w == ww) {
-      contribute(ww == 0);
+  __syncthreads();  // the tiles' LDS becomes the slots
+  for (int phase = 0; phase < 2; ++phase) {
+    if ((w >= 4) == (phase == 1)) {
+      float* acc = L.u.red[w & 3];
+      const bool first = phase == 0;
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+        for (int kt = 0; kt < 4; ++kt)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            float* p = &acc[((nt * 4 + kt) * 4 + q) * 64 + lane];
+            *p = first ? dw2[nt][kt][q] : *p + dw2[nt][kt][q];
+          }
+#pragma unroll
+      for (int kt = 0; kt < 4; ++kt)
+#pragma unroll
+        for (int it = 0; it < 2; ++it)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            float* p = &acc[kPosW1 + ((kt * 2 + it) * 4 + q) * 64 + lane];
+            *p = first ? dw1[kt][it][q] : *p + dw1[kt][it][q];
+          }
       if (c == 0) {
 #pragma unroll
         for (int a = 0; a < 4; ++a)
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
-            const int n = 16 * a + 4 * g + q;
-            acc[W3_OFF + n] = ww == 0 ? rw3[a][q] : acc[W3_OFF + n] + rw3[a][q];
-            acc[B2_OFF + n] = ww == 0 ? rb2[a][q] : acc[B2_OFF + n] + rb2[a][q];
-            acc[B1_OFF + n] = ww == 0 ? rb1[a][q] : acc[B1_OFF + n] + rb1[a][q];
+            const int n = kPosUnits + 16 * a + 4 * g + q;
+            acc[n] = first ? rw3[a][q] : acc[n] + rw3[a][q];
+            acc[n + 64] = first ? rb2[a][q] : acc[n + 64] + rb2[a][q];
+            acc[n + 128] = first ? rb1[a][q] : acc[n + 128] + rb1[a][q];
           }
       }
       if (lane == 0) {
-        acc[B3_OFF] = ww == 0 ? rb3 : acc[B3_OFF] + rb3;
-        acc[kMlpParams] = ww == 0 ? rsq : acc[kMlpParams] + rsq;
+        acc[kPosUnits + 192] = first ? rb3 : acc[kPosUnits + 192] + rb3;
+        acc[kPosLoss] = first ? rsq : acc[kPosLoss] + rsq;
       }
     }
     __syncthreads();
   }
-  for (int i = threadIdx.x; i < kMlpParams; i += kThreads)
-    gpart[(size_t)blockIdx.x * kMlpParams + i] = acc[i];
-  if (threadIdx.x == 0) lpart[blockIdx.x] = acc[kMlpParams];
+  for (int i = threadIdx.x; i <= kPosLoss; i += NT) {
+    const float v = (L.u.red[0][i] + L.u.red[1][i]) + (L.u.red[2][i] + L.u.red[3][i]);
+    if (i < kPosLoss)
+      gpart[(size_t)blockIdx.x * kMlpParams + i] = v;
+    else
+      lpart[blockIdx.x] = v;
+  }
 }
 
-// Sum per-block partials in a fixed order (deterministic).  A workgroup
-// takes 32 parameters; its 8 row groups each sum every 8th partial in
-// block order, and the 8 sums are added in group order.  Workgroup 0 also
-// sums the loss partials: 256 fixed strided sums, then a fixed tree.
-constexpr int kRedParams = 32, kRedParts = kThreads / kRedParams;
-__global__ __launch_bounds__(kThreads) void k_grad_reduce(const float* __restrict__ gpart,
-                                                          const float* __restrict__ lpart,
-                                                          int nblk, float* __restrict__ grad,
-                                                          double* __restrict__ loss_sum) {
-  __shared__ float part[kRedParts][kRedParams];
-  __shared__ double lsum[kThreads];
-  const int pl = threadIdx.x % kRedParams, grp = threadIdx.x / kRedParams;
-  const int p = blockIdx.x * kRedParams + pl;
-  float s = 0.f;
-  if (p < kMlpParams) {
-    int b = grp;
-    for (; b + 3 * kRedParts < nblk; b += 4 * kRedParts) {  // four loads in flight
-      const float v0 = gpart[(size_t)b * kMlpParams + p];
-      const float v1 = gpart[(size_t)(b + kRedParts) * kMlpParams + p];
-      const float v2 = gpart[(size_t)(b + 2 * kRedParts) * kMlpParams + p];
-      const float v3 = gpart[(size_t)(b + 3 * kRedParts) * kMlpParams + p];
-      s = (((s + v0) + v1) + v2) + v3;
-    }
-    for (; b < nblk; b += kRedParts) s += gpart[(size_t)b * kMlpParams + p];
-  }
-  part[grp][pl] = s;
-  if (blockIdx.x == 0) {
-    double l = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += kThreads) l += lpart[b];
-    lsum[threadIdx.x] = l;
-  }
-  __syncthreads();
-  if (grp == 0 && p < kMlpParams) {
-    float t = part[0][pl];
-#pragma unroll
-    for (int q = 1; q < kRedParts; ++q) t += part[q][pl];
-    grad[p] = t;
-  }
-  if (blockIdx.x == 0) {
-    for (int h = kThreads / 2; h > 0; h /= 2) {
-      if (int(threadIdx.x) < h) lsum[threadIdx.x] += lsum[threadIdx.x + h];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) *loss_sum = lsum[0];
-  }
+// Adam (Kingma & Ba) on master weight p with gradient gr; bc1 = 1 - beta1^t,
+// bc2 = 1 - beta2^t.  Returns the new weight.
+__device__ __forceinline__ float adam_one(int p, float gr, float* __restrict__ master,
+                                          float* __restrict__ mo, float* __restrict__ vo, float lr,
+                                          float beta1, float beta2, float eps, float bc1, float bc2) {
+  const float m1 = beta1 * mo[p] + (1.f - beta1) * gr;
+  const float v1 = beta2 * vo[p] + (1.f - beta2) * gr * gr;
+  mo[p] = m1;
+  vo[p] = v1;
+  const float w = master[p] - lr * (m1 / bc1) / (sqrtf(v1 / bc2) + eps);
+  master[p] = w;
+  return w;
 }
 
 // Round the FP32 master weights to BF16 (FP32 copy `wr`) and write the
@@ -477,31 +612,75 @@ __device__ __forceinline__ void pack_one(int p, float v, float* __restrict__ wr,
   }
 }
 
+// Sum per-block partials in a fixed order (deterministic), position by
+// position (the training blocks' partial order), into the gradient of the
+// parameter at that position.  A workgroup takes 32 positions; its 8 row groups each sum every 8th partial in
+// block order, and the 8 sums are added in group order.  Workgroup 0 also
+// sums the loss partials: 256 fixed strided sums, then a fixed tree.
+constexpr int kRedParams = 32, kRedParts = kThreads / kRedParams;
+struct AdamArgs {
+  float* master;
+  float* mo;
+  float* vo;
+  float lr, beta1, beta2, eps, bc1, bc2;
+  float* wr;
+  __bf16* wpack;
+};
+template <bool ADAM>
+__global__ __launch_bounds__(kThreads) void k_grad_reduce(const float* __restrict__ gpart,
+                                                          const float* __restrict__ lpart,
+                                                          int nblk, float* __restrict__ grad,
+                                                          double* __restrict__ loss_sum,
+                                                          AdamArgs ad) {
+  __shared__ float part[kRedParts][kRedParams];
+  __shared__ double lsum[kThreads];
+  const int pl = threadIdx.x % kRedParams, grp = threadIdx.x / kRedParams;
+  const int p = blockIdx.x * kRedParams + pl;
+  float s = 0.f;
+  if (p < kMlpParams) {
+    int b = grp;
+    constexpr int kInFlight = 16;
+    for (; b + (kInFlight - 1) * kRedParts < nblk; b += kInFlight * kRedParts) {
+      float v[kInFlight];
+#pragma unroll
+      for (int q = 0; q < kInFlight; ++q) v[q] = gpart[(size_t)(b + q * kRedParts) * kMlpParams + p];
+#pragma unroll
+      for (int q = 0; q < kInFlight; ++q) s += v[q];
+    }
+    for (; b < nblk; b += kRedParts) s += gpart[(size_t)b * kMlpParams + p];
+  }
+  part[grp][pl] = s;
+  if (blockIdx.x == 0) {
+    double l = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += kThreads) l += lpart[b];
+    lsum[threadIdx.x] = l;
+  }
+  __syncthreads();
+  if (grp == 0 && p < kMlpParams) {  // p: a partial's position
+    float t = part[0][pl];
+#pragma unroll
+    for (int q = 1; q < kRedParts; ++q) t += part[q][pl];
+    const int pp = param_of_pos(p);
+    grad[pp] = t;
+    if (ADAM)  // the training step's Adam update of this parameter
+      pack_one(pp, adam_one(pp, t, ad.master, ad.mo, ad.vo, ad.lr, ad.beta1, ad.beta2, ad.eps, ad.bc1,
+                            ad.bc2),
+               ad.wr, ad.wpack);
+  }
+  if (blockIdx.x == 0) {
+    for (int h = kThreads / 2; h > 0; h /= 2) {
+      if (int(threadIdx.x) < h) lsum[threadIdx.x] += lsum[threadIdx.x + h];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) *loss_sum = lsum[0];
+  }
+}
+
 __global__ __launch_bounds__(kThreads) void k_pack(const float* __restrict__ master,
                                                    float* __restrict__ wr,
                                                    __bf16* __restrict__ wpack) {
   const int p = blockIdx.x * kThreads + threadIdx.x;
   if (p < kMlpParams) pack_one(p, master[p], wr, wpack);
-}
-
-// Adam (Kingma & Ba) on the FP32 master weights; bc1 = 1 - beta1^t,
-// bc2 = 1 - beta2^t.
-__global__ __launch_bounds__(kThreads) void k_adam(float* __restrict__ master, float* __restrict__ mo,
-                                                   float* __restrict__ vo,
-                                                   const float* __restrict__ grad, float lr,
-                                                   float beta1, float beta2, float eps, float bc1,
-                                                   float bc2, float* __restrict__ wr,
-                                                   __bf16* __restrict__ wpack) {
-  const int p = blockIdx.x * kThreads + threadIdx.x;
-  if (p >= kMlpParams) return;
-  const float gr = grad[p];
-  const float m1 = beta1 * mo[p] + (1.f - beta1) * gr;
-  const float v1 = beta2 * vo[p] + (1.f - beta2) * gr * gr;
-  mo[p] = m1;
-  vo[p] = v1;
-  const float w = master[p] - lr * (m1 / bc1) / (sqrtf(v1 / bc2) + eps);
-  master[p] = w;
-  pack_one(p, w, wr, wpack);
 }
 
 // ---------------------------------------------------------------------------
@@ -1005,48 +1184,57 @@ hipError_t launch_mlp(bool train, const void* X, const float* target, int m, flo
                       const void* wpack, const float* wr, float* yout, float* gpart,
                       float* lpart, int* nblk_out, hipStream_t st) {
   const int tiles = (m + 31) / 32;
-  const int waves = (tiles + 3) / 4 * 4;
-  // enough blocks to fill the chip, each wave running tiles_per_wave tiles
-  const int tpw = max(1, (waves / 4 + kMlpMaxBlocks - 1) / kMlpMaxBlocks);
-  const int nblk = ((tiles + 4 * tpw - 1) / (4 * tpw));
+  if (!train) {
+    // enough blocks to fill the chip, each wave running tiles_per_wave tiles
+    const int tpw = max(1, (tiles + 4 * kMlpMaxBlocks - 1) / (4 * kMlpMaxBlocks));
+    const int nblk = max(1, (tiles + 4 * tpw - 1) / (4 * tpw));
+    if (nblk_out) *nblk_out = nblk;
+    hipLaunchKernelGGL(k_mlp_eval, dim3(nblk), dim3(kThreads), 0, st, static_cast<const __bf16*>(X), m,
+                       tpw, static_cast<const __bf16*>(wpack), wr, yout);
+    return hipGetLastError();
+  }
+  // about one block per compute unit (one fits), at most the partials' room
+  static int cus = 0;
+  if (!cus) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      cus = 256;
+    cus = min(cus, kMlpMaxBlocks);
+  }
+  const int tpw = max(1, (tiles + kTrWaves * cus - 1) / (kTrWaves * cus));
+  const int nblk = max(1, (tiles + kTrWaves * tpw - 1) / (kTrWaves * tpw));
   const int bytes = int(sizeof(TrainLds));
-  static hipError_t a1 = hipFuncSetAttribute(reinterpret_cast<const void*>(k_mlp<true>),
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-  static hipError_t a2 = hipFuncSetAttribute(reinterpret_cast<const void*>(k_mlp<false>),
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-  if (a1 != hipSuccess) return a1;
-  if (a2 != hipSuccess) return a2;
+  static hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(k_mlp_train),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (attr != hipSuccess) return attr;
   if (nblk_out) *nblk_out = nblk;
-  if (train)
-    hipLaunchKernelGGL(k_mlp<true>, dim3(nblk), dim3(kThreads), bytes, st,
-                       static_cast<const __bf16*>(X), target, m, inv_m2, tpw,
-                       static_cast<const __bf16*>(wpack), wr, yout, gpart, lpart);
-  else
-    hipLaunchKernelGGL(k_mlp<false>, dim3(nblk), dim3(kThreads), bytes, st,
-                       static_cast<const __bf16*>(X), target, m, inv_m2, tpw,
-                       static_cast<const __bf16*>(wpack), wr, yout, gpart, lpart);
+  hipLaunchKernelGGL(k_mlp_train, dim3(nblk), dim3(64 * kTrWaves), bytes, st,
+                     static_cast<const __bf16*>(X), target, m, inv_m2, tpw,
+                     static_cast<const __bf16*>(wpack), wr, gpart, lpart);
   return hipGetLastError();
 }
 
 hipError_t launch_grad_reduce(const float* gpart, const float* lpart, int nblk, float* grad,
                               double* loss_sum, hipStream_t st) {
-  hipLaunchKernelGGL(k_grad_reduce, dim3((kMlpParams + kRedParams - 1) / kRedParams), dim3(kThreads), 0,
-                     st, gpart, lpart, nblk, grad, loss_sum);
+  hipLaunchKernelGGL(k_grad_reduce<false>, dim3((kMlpParams + kRedParams - 1) / kRedParams),
+                     dim3(kThreads), 0, st, gpart, lpart, nblk, grad, loss_sum, AdamArgs{});
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_adam(const float* gpart, const float* lpart, int nblk, float* grad,
+                            double* loss_sum, float* master, float* m, float* v, float lr,
+                            float beta1, float beta2, float eps, float bc1, float bc2, float* wr,
+                            void* wpack, hipStream_t st) {
+  const AdamArgs ad{master, m, v, lr, beta1, beta2, eps, bc1, bc2, wr, static_cast<__bf16*>(wpack)};
+  hipLaunchKernelGGL(k_grad_reduce<true>, dim3((kMlpParams + kRedParams - 1) / kRedParams),
+                     dim3(kThreads), 0, st, gpart, lpart, nblk, grad, loss_sum, ad);
   return hipGetLastError();
 }
 
 hipError_t launch_pack(const float* master, float* wr, void* wpack, hipStream_t st) {
   hipLaunchKernelGGL(k_pack, dim3((kMlpParams + kThreads - 1) / kThreads), dim3(kThreads), 0, st,
                      master, wr, static_cast<__bf16*>(wpack));
-  return hipGetLastError();
-}
-
-hipError_t launch_adam(float* master, float* m, float* v, const float* grad, float lr, float beta1,
-                       float beta2, float eps, float bc1, float bc2, float* wr, void* wpack,
-                       hipStream_t st) {
-  hipLaunchKernelGGL(k_adam, dim3((kMlpParams + kThreads - 1) / kThreads), dim3(kThreads), 0, st,
-                     master, m, v, grad, lr, beta1, beta2, eps, bc1, bc2, wr,
-                     static_cast<__bf16*>(wpack));
   return hipGetLastError();
 }
 
