@@ -1165,7 +1165,8 @@ int sla_model_create(sla_ctx* ctx, sla_model** out) {
   ok = ok && hipMalloc(&m->wr, P) == hipSuccess;
   ok = ok && hipMalloc(&m->wpack, sla::kMlpPackElems * 2) == hipSuccess;
   ok = ok && hipMalloc(&m->grad, P) == hipSuccess;
-  ok = ok && hipMalloc(&m->gpart, size_t(sla::kMlpMaxBlocks) * P) == hipSuccess;
+  ok = ok && hipMalloc(&m->gpart, size_t(sla::kMlpMaxBlocks) * sla::kMlpPartStride * sizeof(float)) ==
+                  hipSuccess;
   ok = ok && hipMalloc(&m->lpart, sla::kMlpMaxBlocks * sizeof(float)) == hipSuccess;
   ok = ok && hipMalloc(&m->loss, sizeof(double)) == hipSuccess;
   if (!ok) {

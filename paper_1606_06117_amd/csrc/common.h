@@ -112,6 +112,8 @@ constexpr int kMlpHidden = 64;
 constexpr int kMlpParams = kMlpInputs * kMlpHidden + kMlpHidden + kMlpHidden * kMlpHidden +
                            kMlpHidden + kMlpHidden + 1;
 constexpr int kMlpMaxBlocks = 512;  // training blocks (gradient partials)
+// floats per block of gradient partials (whole 16-byte groups)
+constexpr int kMlpPartStride = (kMlpParams + 3) / 4 * 4;
 constexpr int kLearnedBlocks = 1024;  // workgroups of a learned-step launch (each loads the weights once)
 constexpr int kMlpPackElems = kMlpHidden * kMlpInputs + 2 * kMlpHidden * kMlpHidden;
 

@@ -78,12 +78,19 @@ __device__ __forceinline__ void st4(__bf16* p, float a, float b, float c, float 
   *reinterpret_cast<bf16x4*>(p) = v;
 }
 
-// sum over the 16 lanes that share g (lane bits 0..3)
+// sum over the 16 lanes that share g (lane bits 0..3), by DPP within the
+// 16-lane row (no LDS): swap neighbours, swap pairs, mirror the half rows,
+// mirror the row.  Each step adds two sums that every lane forms in the
+// same order, so all 16 lanes end with the same value.
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xf, 0xf, false));
+}
 __device__ __forceinline__ float sum16(float v) {
-  v += __shfl_xor(v, 1);
-  v += __shfl_xor(v, 2);
-  v += __shfl_xor(v, 4);
-  v += __shfl_xor(v, 8);
+  v += dpp_f<0xB1>(v);   // quad_perm [1,0,3,2]: lane ^ 1
+  v += dpp_f<0x4E>(v);   // quad_perm [2,3,0,1]: lane ^ 2
+  v += dpp_f<0x141>(v);  // row_half_mirror: quads 0-1 and 2-3 swap
+  v += dpp_f<0x140>(v);  // row_mirror: the 8-lane halves swap
   return v;
 }
 // sum over the 4 lanes that share c (lane bits 4..5)
@@ -239,8 +246,9 @@ __global__ __launch_bounds__(kThreads) void k_mlp_eval(const __bf16* __restrict_
 
 // ---------------------------------------------------------------------------
 // Training on feature rows: the gradient of mean((y - t)^2) (inv_m2 =
-// 2 / m_total) summed over the block's rows into gpart[blockIdx][kMlpParams]
-// and the squared error into lpart[blockIdx].  A wave runs 32-row tiles;
+// 2 / m_total) summed over the block's rows into gpart[blockIdx]
+// [kMlpPartStride] (in the partial order below) and the squared error into
+// lpart[blockIdx].  A wave runs 32-row tiles;
 // every product of the backward pass is a matrix-core product.  Those whose
 // reduction runs over the tile's rows (the weight gradients) take both
 // operands with the rows as the K index: each operand is kept in LDS as a
@@ -253,21 +261,22 @@ __global__ __launch_bounds__(kThreads) void k_mlp_eval(const __bf16* __restrict_
 // are added in a fixed order at the end (deterministic).
 // ---------------------------------------------------------------------------
 // Order of a training block's gradient partials (and of the slots they are
-// summed in): lane-major, value v of lane l (l = 16 g + c) at v * 64 + l.
-// Values 0..63 are the W2 tiles, (nt * 4 + kt) * 4 + q for W2[16 kt + c]
-// [16 nt + 4 g + q]; 64..95 the W1 tiles, 64 + (kt * 2 + it) * 4 + q for
-// W1[16 it + c][16 kt + 4 g + q]; then, from kPosUnits, w3, b2 and b1 by
-// unit, b3, and the squared error.
+// summed in): four values of a lane together, then the next lane: value v
+// of lane l (l = 16 g + c) at (v / 4) * 256 + 4 l + v % 4, so a lane writes
+// an MFMA tile's four results with one 16-byte store and a store of the
+// wave covers 1 KB without a bank conflict.  Values 0..63 are the W2 tiles,
+// (nt * 4 + kt) * 4 + q for W2[16 kt + c][16 nt + 4 g + q]; 64..95 the W1
+// tiles, 64 + (kt * 2 + it) * 4 + q for W1[16 it + c][16 kt + 4 g + q];
+// then, from kPosUnits, w3, b2 and b1 by unit, b3, and the squared error.
 constexpr int kPosW1 = 64 * 64, kPosUnits = 96 * 64, kPosLoss = kPosUnits + 193;
 static_assert(kPosLoss == kMlpParams, "one position per parameter, then the loss");
 __device__ __forceinline__ int param_of_pos(int pos) {
-  if (pos < kPosW1) {
-    const int v = pos / 64, l = pos % 64;
-    return W2_OFF + (16 * ((v / 4) % 4) + l % 16) * NH + 16 * (v / 16) + 4 * (l / 16) + v % 4;
-  }
   if (pos < kPosUnits) {
-    const int v = (pos - kPosW1) / 64, l = pos % 64;
-    return W1_OFF + (16 * ((v / 4) % 2) + l % 16) * NH + 16 * (v / 8) + 4 * (l / 16) + v % 4;
+    const int v = (pos / 256) * 4 + pos % 4, l = (pos / 4) % 64;
+    if (v < 64)
+      return W2_OFF + (16 * ((v / 4) % 4) + l % 16) * NH + 16 * (v / 16) + 4 * (l / 16) + v % 4;
+    const int u = v - 64;
+    return W1_OFF + (16 * ((u / 4) % 2) + l % 16) * NH + 16 * (u / 8) + 4 * (l / 16) + u % 4;
   }
   const int j = pos - kPosUnits;
   return j < 64 ? W3_OFF + j : j < 128 ? B2_OFF + (j - 64) : j < 192 ? B1_OFF + (j - 128) : B3_OFF;
@@ -284,7 +293,7 @@ struct TrainLds {
       __bf16 dh2[kTrWaves][32 * SH];  // [row][n]
       __bf16 dh1[kTrWaves][32 * SH];  // [row][k]
     } t;
-    float red[4][kPosLoss + 1];  // the waves' sums, four slots in partial order
+    float red[4][kMlpPartStride];  // the waves' sums, four slots in partial order
   } u;
 };
 
@@ -540,21 +549,17 @@ __global__ __launch_bounds__(64 * kTrWaves) void k_mlp_train(const __bf16* __res
 #pragma unroll
       for (int nt = 0; nt < 4; ++nt)
 #pragma unroll
-        for (int kt = 0; kt < 4; ++kt)
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            float* p = &acc[((nt * 4 + kt) * 4 + q) * 64 + lane];
-            *p = first ? dw2[nt][kt][q] : *p + dw2[nt][kt][q];
-          }
+        for (int kt = 0; kt < 4; ++kt) {
+          floatx4* p = reinterpret_cast<floatx4*>(&acc[(nt * 4 + kt) * 256 + 4 * lane]);
+          *p = first ? dw2[nt][kt] : *p + dw2[nt][kt];
+        }
 #pragma unroll
       for (int kt = 0; kt < 4; ++kt)
 #pragma unroll
-        for (int it = 0; it < 2; ++it)
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            float* p = &acc[kPosW1 + ((kt * 2 + it) * 4 + q) * 64 + lane];
-            *p = first ? dw1[kt][it][q] : *p + dw1[kt][it][q];
-          }
+        for (int it = 0; it < 2; ++it) {
+          floatx4* p = reinterpret_cast<floatx4*>(&acc[kPosW1 + (kt * 2 + it) * 256 + 4 * lane]);
+          *p = first ? dw1[kt][it] : *p + dw1[kt][it];
+        }
       if (c == 0) {
 #pragma unroll
         for (int a = 0; a < 4; ++a)
@@ -573,10 +578,18 @@ __global__ __launch_bounds__(64 * kTrWaves) void k_mlp_train(const __bf16* __res
     }
     __syncthreads();
   }
-  for (int i = threadIdx.x; i <= kPosLoss; i += NT) {
+  float* gp = gpart + (size_t)blockIdx.x * kMlpPartStride;
+  for (int i = 4 * threadIdx.x; i < kPosUnits; i += 4 * NT) {
+    const floatx4* r0 = reinterpret_cast<const floatx4*>(&L.u.red[0][i]);
+    const floatx4* r1 = reinterpret_cast<const floatx4*>(&L.u.red[1][i]);
+    const floatx4* r2 = reinterpret_cast<const floatx4*>(&L.u.red[2][i]);
+    const floatx4* r3 = reinterpret_cast<const floatx4*>(&L.u.red[3][i]);
+    *reinterpret_cast<floatx4*>(&gp[i]) = (*r0 + *r1) + (*r2 + *r3);
+  }
+  for (int i = kPosUnits + threadIdx.x; i <= kPosLoss; i += NT) {
     const float v = (L.u.red[0][i] + L.u.red[1][i]) + (L.u.red[2][i] + L.u.red[3][i]);
     if (i < kPosLoss)
-      gpart[(size_t)blockIdx.x * kMlpParams + i] = v;
+      gp[i] = v;
     else
       lpart[blockIdx.x] = v;
   }
@@ -643,11 +656,11 @@ __global__ __launch_bounds__(kThreads) void k_grad_reduce(const float* __restric
     for (; b + (kInFlight - 1) * kRedParts < nblk; b += kInFlight * kRedParts) {
       float v[kInFlight];
 #pragma unroll
-      for (int q = 0; q < kInFlight; ++q) v[q] = gpart[(size_t)(b + q * kRedParts) * kMlpParams + p];
+      for (int q = 0; q < kInFlight; ++q) v[q] = gpart[(size_t)(b + q * kRedParts) * kMlpPartStride + p];
 #pragma unroll
       for (int q = 0; q < kInFlight; ++q) s += v[q];
     }
-    for (; b < nblk; b += kRedParts) s += gpart[(size_t)b * kMlpParams + p];
+    for (; b < nblk; b += kRedParts) s += gpart[(size_t)b * kMlpPartStride + p];
   }
   part[grp][pl] = s;
   if (blockIdx.x == 0) {
