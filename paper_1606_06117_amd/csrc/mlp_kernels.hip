@@ -282,7 +282,7 @@ __device__ __forceinline__ int param_of_pos(int pos) {
   return j < 64 ? W3_OFF + j : j < 128 ? B2_OFF + (j - 64) : j < 192 ? B1_OFF + (j - 128) : B3_OFF;
 }
 
-constexpr int kTrWaves = 4;
+constexpr int kTrWaves = 8;
 struct TrainLds {
   WeightsLds W;
   alignas(16) __bf16 w2r[NH * SH];  // W2R [k][n]
@@ -395,17 +395,26 @@ __global__ __launch_bounds__(64 * kTrWaves) void k_mlp_train(const __bf16* __res
   __bf16* dh1 = L.u.t.dh1[w];
 
   floatx4 dw2[4][4], dw1[4][2];  // dW2T[n][k], dW1T[k][i] tiles (D layout)
-  float dw3[4][4], db2[4][4], db1[4][4], db3 = 0.f, sq = 0.f;
+  // w3, b2 and b1 gradients of unit 16 (c / 4) + 4 g + c % 4: each tile's
+  // sums over its rows, reduced over the 16 lanes of a row at once
+  float own_w3 = 0.f, own_b2 = 0.f, own_b1 = 0.f, db3 = 0.f, sq = 0.f;
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      dw2[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
-      dw3[a][b] = db2[a][b] = db1[a][b] = 0.f;
-    }
+    for (int b = 0; b < 4; ++b) dw2[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int b = 0; b < 2; ++b) dw1[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
   }
+  // add this row's sums of a 16-value set (index 4a + q) to the lane's own
+  auto own_add = [&](float& own, float (&t)[4][4]) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float v = sum16(t[a][q]);
+        own += c == 4 * a + q ? v : 0.f;
+      }
+  };
 
   for (int tt = 0; tt < tiles_per_wave; ++tt) {
     const int r0 = ((blockIdx.x * tiles_per_wave + tt) * kTrWaves + w) * 32;
@@ -467,20 +476,27 @@ __global__ __launch_bounds__(64 * kTrWaves) void k_mlp_train(const __bf16* __res
       }
     }
     // ---- backward: dH2 = dy w3 where H2 > 0, as [row][n]
+    {
+      float t3[4][4], t2[4][4];
 #pragma unroll
-    for (int it = 0; it < 4; ++it) {
+      for (int it = 0; it < 4; ++it) {
 #pragma unroll
-      for (int jt = 0; jt < 2; ++jt) {
-        const int n = 16 * it + 4 * g;
-        float d[4];
+        for (int q = 0; q < 4; ++q) t3[it][q] = t2[it][q] = 0.f;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          dw3[it][q] = fmaf(h2[it][jt][q], dy[jt], dw3[it][q]);
-          d[q] = h2[it][jt][q] > 0.f ? dy[jt] * L.W.w3[n + q] : 0.f;
-          db2[it][q] += d[q];
+        for (int jt = 0; jt < 2; ++jt) {
+          const int n = 16 * it + 4 * g;
+          float d[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            t3[it][q] = fmaf(h2[it][jt][q], dy[jt], t3[it][q]);
+            d[q] = h2[it][jt][q] > 0.f ? dy[jt] * L.W.w3[n + q] : 0.f;
+            t2[it][q] += d[q];
+          }
+          st4(&dh2[(16 * jt + c) * SH + n], d[0], d[1], d[2], d[3]);
         }
-        st4(&dh2[(16 * jt + c) * SH + n], d[0], d[1], d[2], d[3]);
       }
+      own_add(own_w3, t3);
+      own_add(own_b2, t2);
     }
     wave_lds_sync();
     // dW2T[n][k] += sum over rows of dH2[row][n] H1[row][k]
@@ -494,23 +510,29 @@ __global__ __launch_bounds__(64 * kTrWaves) void k_mlp_train(const __bf16* __res
         for (int kt = 0; kt < 4; ++kt) dw2[nt][kt] = mfma(a[nt], bk[kt], dw2[nt][kt]);
     }
     // dH1T[k][row] = sum_n W2R[k][n] dH2[row][n], where H1 > 0; stored as [row][k]
+    {
+      float t1[4][4];
 #pragma unroll
-    for (int kt = 0; kt < 4; ++kt) {
+      for (int kt = 0; kt < 4; ++kt) {
 #pragma unroll
-      for (int jt = 0; jt < 2; ++jt) {
-        floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+        for (int q = 0; q < 4; ++q) t1[kt][q] = 0.f;
 #pragma unroll
-        for (int nn = 0; nn < 2; ++nn)
-          acc = mfma(ld8(&L.w2r[(16 * kt + c) * SH + 32 * nn + 8 * g]),
-                     ld8(&dh2[(16 * jt + c) * SH + 32 * nn + 8 * g]), acc);
-        float d[4];
+        for (int jt = 0; jt < 2; ++jt) {
+          floatx4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          d[q] = (h1pos >> (8 * kt + 4 * jt + q)) & 1u ? acc[q] : 0.f;
-          db1[kt][q] += d[q];
+          for (int nn = 0; nn < 2; ++nn)
+            acc = mfma(ld8(&L.w2r[(16 * kt + c) * SH + 32 * nn + 8 * g]),
+                       ld8(&dh2[(16 * jt + c) * SH + 32 * nn + 8 * g]), acc);
+          float d[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            d[q] = (h1pos >> (8 * kt + 4 * jt + q)) & 1u ? acc[q] : 0.f;
+            t1[kt][q] += d[q];
+          }
+          st4(&dh1[(16 * jt + c) * SH + 16 * kt + 4 * g], d[0], d[1], d[2], d[3]);
         }
-        st4(&dh1[(16 * jt + c) * SH + 16 * kt + 4 * g], d[0], d[1], d[2], d[3]);
       }
+      own_add(own_b1, t1);
     }
     wave_lds_sync();
     // dW1T[k][i] += sum over rows of dH1[row][k] X[row][i]
@@ -530,15 +552,6 @@ __global__ __launch_bounds__(64 * kTrWaves) void k_mlp_train(const __bf16* __res
   // 4-7 add theirs to slot w - 4, then every position is summed over the
   // slots in slot order (lane-major, so no two lanes of an access share a
   // bank)
-  float rw3[4][4], rb2[4][4], rb1[4][4];
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      rw3[a][q] = sum16(dw3[a][q]);
-      rb2[a][q] = sum16(db2[a][q]);
-      rb1[a][q] = sum16(db1[a][q]);
-    }
   const float rb3 = sum16(sum4g(db3));
   const float rsq = sum16(sum4g(sq));
   __syncthreads();  // the tiles' LDS becomes the slots
@@ -560,16 +573,11 @@ __global__ __launch_bounds__(64 * kTrWaves) void k_mlp_train(const __bf16* __res
           floatx4* p = reinterpret_cast<floatx4*>(&acc[kPosW1 + (kt * 2 + it) * 256 + 4 * lane]);
           *p = first ? dw1[kt][it] : *p + dw1[kt][it];
         }
-      if (c == 0) {
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const int n = kPosUnits + 16 * a + 4 * g + q;
-            acc[n] = first ? rw3[a][q] : acc[n] + rw3[a][q];
-            acc[n + 64] = first ? rb2[a][q] : acc[n + 64] + rb2[a][q];
-            acc[n + 128] = first ? rb1[a][q] : acc[n + 128] + rb1[a][q];
-          }
+      {
+        const int n = kPosUnits + 16 * (c / 4) + 4 * g + c % 4;  // this lane's unit
+        acc[n] = first ? own_w3 : acc[n] + own_w3;
+        acc[n + 64] = first ? own_b2 : acc[n + 64] + own_b2;
+        acc[n + 128] = first ? own_b1 : acc[n + 128] + own_b1;
       }
       if (lane == 0) {
         acc[kPosUnits + 192] = first ? rb3 : acc[kPosUnits + 192] + rb3;
