@@ -240,6 +240,41 @@ def learned_probe(size: int, reps: int, warmup: int) -> int:
     return 0
 
 
+def train_probe(rows: int, reps: int, warmup: int) -> int:
+    """Time training steps alone (forward, backward, gradient reduction and
+    Adam) on ``rows`` seeded random feature rows and targets: microseconds
+    per step (HIP events), and the steps' share of the matrix cores' BF16
+    peak at 32 768 FLOP of matrix products per row (12 288 forward, 20 480
+    backward)."""
+    import numpy as np
+    import torch
+    sys.path.insert(0, ROOT)
+    from paper_1606_06117_amd import native
+    ctx = native.Context(0)
+    model = native.Model(ctx)
+    rng = np.random.default_rng(7)
+    model.set_params((rng.standard_normal(native.MLP_PARAMS) * 0.1).astype(np.float32))
+    x = rng.standard_normal((rows, native.MLP_INPUTS)).astype(np.float32)
+    x[:, 30:] = 0.0
+    feats = torch.from_numpy(x).to(torch.bfloat16).view(torch.int16).cuda()
+    target = torch.from_numpy(rng.standard_normal(rows).astype(np.float32)).cuda()
+    for _ in range(max(50, warmup)):
+        model.train_step(feats, target, 1e-4)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        model.train_step(feats, target, 1e-4)
+    b.record()
+    torch.cuda.synchronize()
+    us = a.elapsed_time(b) * 1e3 / reps
+    print(json.dumps({"probe": "train", "rows": rows, "steps": reps, "us_per_step": us,
+                      "mfma_frac_step": 32768 * rows / (us * 1e-6) / 2.5e15}), flush=True)
+    model.close()
+    ctx.close()
+    return 0
+
+
 def learned_section(ctx, size, fields, steps_per_field, cells, iters, batch, lr, rounds):
     """Learned correction vs the plain third-order scheme on the time-modulated
     ABC flow (CFL 0.9 at peak amplitude): training on pairs from the GPU
@@ -557,10 +592,11 @@ def main(argv=None):
     ap.add_argument("--learned-iters", type=int, default=4000, help="Adam steps per training round")
     ap.add_argument("--learned-rounds", type=int, default=2,
                     help="rounds of pairs from the model's own rollouts after the first training")
-    ap.add_argument("--probe", choices=["copy", "learned"], default=None,
+    ap.add_argument("--probe", choices=["copy", "learned", "train"], default=None,
                     help="instead of the benchmark: copy, time a plain device copy of known size "
                          "(achievable bandwidth; calibrates HBM byte counters); learned, time the "
-                         "learned step alone at --learned-size with random weights")
+                         "learned step alone at --learned-size with random weights; train, time "
+                         "training steps on 65 536 random feature rows")
     args = ap.parse_args(argv)
 
     if args.gpus != 1:
@@ -575,6 +611,8 @@ def main(argv=None):
         return copy_probe(args.steps, args.warmup)
     if args.probe == "learned":
         return learned_probe(args.learned_size, args.steps, args.warmup)
+    if args.probe == "train":
+        return train_probe(65536, args.steps, args.warmup)
 
     sys.path.insert(0, ROOT)
     from paper_1606_06117_amd import native

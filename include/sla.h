@@ -16,7 +16,7 @@
  *
  * and, as options, the third order under Strang's symmetric splitting
  * (SLA_CEC_STRANG) and FEC and BEC one axis at a time (SLA_FEC_SPLIT,
- * SLA_BEC_SPLIT).
+ * SLA_BEC_SPLIT), and the large-CFL weights read literally (SLA_CEC_LITERAL).
  *
  * Conventions shared by every entry point
  * ---------------------------------------

@@ -81,14 +81,14 @@ int main(int argc, char **argv) {
 
   /* workspace sizes: one FP32 field of a valid grid, 0 otherwise */
   const size_t field = (size_t)16 * 16 * 16 * sizeof(float);
-  for (int s = SLA_CIR; s <= SLA_BEC_SPLIT; ++s)
+  for (int s = SLA_CIR; s <= SLA_CEC_LITERAL; ++s)
     CHECK(sla_workspace_size(&g, s, 4) == (s == SLA_CEC ? 4 * field : field));
   CHECK(sla_workspace_size(&g, SLA_CEC, 1) == field);
   CHECK(sla_workspace_size(&g, SLA_CEC, 0) == field);
   CHECK(sla_workspace_size(&g, SLA_CEC, 3) == 3 * field);
   CHECK(sla_workspace_size(&g, SLA_CEC, 16) == 4 * field);
   CHECK(sla_workspace_size(NULL, SLA_CEC, 1) == 0);
-  CHECK(sla_workspace_size(&g, SLA_BEC_SPLIT + 1, 1) == 0);
+  CHECK(sla_workspace_size(&g, SLA_CEC_LITERAL + 1, 1) == 0);
   CHECK(sla_workspace_size(&g, -1, 1) == 0);
   CHECK(sla_workspace_size(&g, SLA_CEC, -1) == 0);
   sla_grid bad = g;
