@@ -229,14 +229,15 @@ typedef enum {
    * 1024^3 (14 from 2^24 cells on with an even nx). */
   SLA_OPT_CEC3D_KERNEL = 1,
   /* How the sweeps of a third-order step that is not fused run (same FP32
-   * operations, same results): 2 (default) the x and y sweeps in one kernel
-   * when their reach is at most 2 (x then y on even steps, y then x on odd
-   * ones: 64-lane x windows marching along y) and z by column walks, else
-   * as 1; 1 one kernel per axis, x in
-   * 64-lane windows, y and z by each thread walking one column with its
-   * stencil in registers; 0 one kernel per axis with LDS tiles.  2 and 1
-   * need grids of fewer than 2^30 cells, or of 2^30 cells with ny >= 2
-   * (others run 0). */
+   * operations, same results): 3 (default) the x and y sweeps in one kernel
+   * (x then y on even steps, y then x on odd ones) with two nodes per lane
+   * (128-node x windows marching along y) when nx is even and their reach
+   * is at most 3, z by column walks, else as 2; 2 the x and y sweeps in
+   * one kernel with 64-lane x windows when their reach is at most 2, else
+   * as 1; 1 one kernel per axis, x in 64-lane windows, y and z by each
+   * thread walking one column with its stencil in registers; 0 one kernel
+   * per axis with LDS tiles.  1 to 3 need grids of fewer than 2^30 cells,
+   * or of 2^30 cells with ny >= 2 (others run 0). */
   SLA_OPT_SWEEP_KERNEL = 2,
   /* How unsplit FEC and BEC steps run (same FP32 operations, same results):
    * 3 (default) on 3D grids at reach 1 (every |c| < 1; fewer than 2^30 cells

@@ -549,8 +549,9 @@ __global__ __launch_bounds__(kThreads) void k_sweep_x(const float* __restrict__ 
 
 // ---------------------------------------------------------------------------
 // Marching sweep along a strided axis (y or z), any reach R.  A thread owns
-// one column (x from the lane, the other strided coordinate from the
-// workgroup) and walks along the sweep axis over positions m = l0 - 3R ..
+// V = 1 or 2 neighbouring columns (x from the lane, the other strided
+// coordinate from the workgroup; V = 2 with even nx: one 8-byte access per
+// row) and walks along the sweep axis over positions m = l0 - 3R ..
 // l1 - 1 + 3R, loading phi and the velocity once per node.  At step m:
 //   Phi1 of node m - R  (needs phi of m - 2R .. m),
 //   e    of node m - 2R (needs Phi1 of m - 3R .. m - R),
@@ -587,6 +588,42 @@ __device__ __forceinline__ void st_row(float* field, unsigned voff, unsigned sof
   __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), based_rsrc(field, soff), voff,
                                         0, 0);
 }
+// Two consecutive nodes at an 8-byte aligned voff.
+// The 64-bit builtins' type is cast whole to a float pair: bit-casting its
+// integer elements one by one compiled to a 32-bit load whose value served
+// both nodes.
+typedef unsigned b64v __attribute__((ext_vector_type(2)));  // the 64-bit buffer builtins' type
+typedef float f2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void ld2_row(const float* field, unsigned voff, unsigned soff, float& a,
+                                        float& b) {
+  const f2v v = __builtin_bit_cast(
+      f2v, __builtin_amdgcn_raw_buffer_load_b64(based_rsrc(field, soff), voff, 0, 0));
+  a = v.x;
+  b = v.y;
+}
+__device__ __forceinline__ void st2_row(float* field, unsigned voff, unsigned soff, float a, float b) {
+  const f2v v = {a, b};
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(b64v, v), based_rsrc(field, soff), voff, 0,
+                                        0);
+}
+
+// V = 1 or 2 consecutive nodes
+template <int V>
+__device__ __forceinline__ void ld_rowv(const float* field, unsigned voff, unsigned soff,
+                                        float (&o)[V]) {
+  if constexpr (V == 1)
+    o[0] = ld_row(field, voff, soff);
+  else
+    ld2_row(field, voff, soff, o[0], o[1]);
+}
+template <int V>
+__device__ __forceinline__ void st_rowv(float* field, unsigned voff, unsigned soff,
+                                        const float (&o)[V]) {
+  if constexpr (V == 1)
+    st_row(field, voff, soff, o[0]);
+  else
+    st2_row(field, voff, soff, o[0], o[1]);
+}
 
 template <typename F, int... Is>
 __device__ __forceinline__ void static_for_impl(F& f, std::integer_sequence<int, Is...>) {
@@ -601,28 +638,43 @@ __device__ __forceinline__ void static_for(F&& f) {
 constexpr int pmod(int a, int k) { return ((a % k) + k) % k; }
 
 // Departure of a node as anchor direction and distance (the decomposition
-// of depart<R>, same clamp and flag): anchor = node - n if pos, node + n
-// otherwise; far = one further.
+// of depart<R>, same clamp): anchor = node - n if pos, node + n otherwise;
+// far = one further.  An overflow is recorded in *over*, which the kernel
+// stores to the flag once at its end: a store under a condition at every
+// departure costs a branch per call.
 struct DepN {
   float f;
-  int n;
+  float n;  // a whole number, compared as a float (no conversion)
   bool pos;
 };
 template <int R>
-__device__ __forceinline__ DepN depart_n(float c, int* flag) {
+__device__ __forceinline__ DepN depart_n(float c, bool& over) {
   const float mag = fabsf(c);
-  float nf = floorf(mag);
+  const float nf = floorf(mag);
   const float f = mag - nf;
-  if (!(nf <= float(R - 1))) {
-    if (nf == nf) *flag = 1;
-    nf = float(R - 1);
-  }
-  return DepN{f, int(nf), c >= 0.f};
+  over |= nf > float(R - 1);  // false for NaN, which propagates
+  return DepN{f, fminf(nf, float(R - 1)), c >= 0.f};
 }
+// The fraction and clamped distance of a Courant number, shared by the
+// forward and the reverse departure (|c| is the same); the ring marches
+// keep them per ring slot, computed once per row.
+template <int R>
+__device__ __forceinline__ void depart_fn(float c, float& f, float& n, bool& over) {
+  const float mag = fabsf(c);
+  const float nf = floorf(mag);
+  f = mag - nf;
+  over |= nf > float(R - 1);
+  n = fminf(nf, float(R - 1));
+}
+// forward (depart_n(c)) and reverse (depart_n(-c)) from them: -c >= 0 is
+// c <= 0 (both false for NaN; -0.0 >= 0 holds)
+__device__ __forceinline__ DepN dep_fwd(float c, float f, float n) { return DepN{f, n, c >= 0.f}; }
+__device__ __forceinline__ DepN dep_rev(float c, float f, float n) { return DepN{f, n, c <= 0.f}; }
 
-// A value passed through an empty asm statement: selects between such values
-// stay selects (the compiler otherwise turns selects between elements of one
-// register array into a dynamically indexed array in scratch memory).
+// A value passed through an empty asm statement: the compiler cannot move
+// an operation on it to where v was produced (the ring marches use it on
+// prefetched values: see k_sweep_m).  Elsewhere it kept selects between
+// elements of one register array from becoming a dynamically indexed array.
 __device__ __forceinline__ float opaque(float v) {
   asm("" : "+v"(v));
   return v;
@@ -632,14 +684,14 @@ __device__ __forceinline__ float opaque(float v) {
 // ring[BASE -+ k], k = 0 .. R, chosen by distance n, then by direction.
 template <int R, int K, int BASE>
 __device__ __forceinline__ void ring_pair(const float (&ring)[K], const DepN& d, float& a, float& b) {
-  const float c0 = opaque(ring[pmod(BASE, K)]);
+  const float c0 = ring[pmod(BASE, K)];
   float an_l = c0, an_r = c0;
-  float fa_l = opaque(ring[pmod(BASE - 1, K)]), fa_r = opaque(ring[pmod(BASE + 1, K)]);
+  float fa_l = ring[pmod(BASE - 1, K)], fa_r = ring[pmod(BASE + 1, K)];
   float pl = fa_l, pr = fa_r;  // candidates at distance k
 #pragma unroll
   for (int k = 1; k < R; ++k) {
-    const float nl = opaque(ring[pmod(BASE - k - 1, K)]), nr = opaque(ring[pmod(BASE + k + 1, K)]);
-    const bool hit = d.n == k;
+    const float nl = ring[pmod(BASE - k - 1, K)], nr = ring[pmod(BASE + k + 1, K)];
+    const bool hit = d.n == float(k);
     an_l = hit ? pl : an_l;
     an_r = hit ? pr : an_r;
     fa_l = hit ? nl : fa_l;
@@ -651,15 +703,15 @@ __device__ __forceinline__ void ring_pair(const float (&ring)[K], const DepN& d,
   b = d.pos ? fa_l : fa_r;
 }
 
-template <int R>
+template <int R, int V>
 __global__ __launch_bounds__(kThreads) void k_sweep_m(const float* __restrict__ phi,
                                                       const float* __restrict__ ud,
                                                       float* __restrict__ out, int nx, int L,
                                                       unsigned S4, unsigned So4, int nother,
                                                       int chunk, float lam, int* flag) {
   constexpr int K = 3 * R + 1;
-  const int x = blockIdx.x * 64 + (threadIdx.x & 63);
-  const int other = blockIdx.y * (kThreads / 64) + (threadIdx.x >> 6);
+  const int x = blockIdx.x * (64 * V) + V * (threadIdx.x & 63);  // the lane's first column
+  const int other = blockIdx.y * (kThreads / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (x >= nx || other >= nother) return;
   const int l0 = blockIdx.z * chunk;
   const int l1 = min(l0 + chunk, L);
@@ -671,59 +723,89 @@ __global__ __launch_bounds__(kThreads) void k_sweep_m(const float* __restrict__ 
     return m < 0 ? m + L : m;
   };
   const int m0 = l0 - 3 * R, m1 = l1 + 3 * R;  // steps m0 .. m1 - 1
-  float pr[K], p1[K], er[K], cr[K];  // rings
-  float np[K], nc[K];                // loads of the next K steps
-  int lrow = wrapped(m0);            // wrapped axis position of the next load
+  float pr[V][K], p1[V][K], er[V][K], cr[V][K];  // rings, per column
+  float fr[V][K], nr[V][K];  // departure fraction and distance of each ring slot
+  float np[V][K], nc[V][K];  // loads of the next K steps
+  int lrow = wrapped(m0);    // wrapped axis position of the next load
 #pragma unroll
   for (int i = 0; i < K; ++i) {
-    pr[i] = p1[i] = er[i] = cr[i] = 0.f;
     const unsigned ro_i = unsigned(lrow) * S4;
-    np[i] = ld_row(rp, voff, ro_i);
-    nc[i] = ld_row(ru, voff, ro_i);
+    float a[V], c[V];
+    ld_rowv<V>(rp, voff, ro_i, a);
+    ld_rowv<V>(ru, voff, ro_i, c);
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      pr[v][i] = p1[v][i] = er[v][i] = cr[v][i] = fr[v][i] = nr[v][i] = 0.f;
+      np[v][i] = a[v];
+      nc[v][i] = c[v];
+    }
     lrow = lrow + 1 == L ? 0 : lrow + 1;
+    // issued in step order: the loop's first step then waits for the
+    // oldest loads only
+    __builtin_amdgcn_sched_barrier(0);
   }
   int srow = wrapped(m0 - 3 * R);  // wrapped axis position of node m - 3R
+  bool over = false;
   for (int mb = m0; mb < m1; mb += K) {
     static_for<K>([&](auto ic) {
       constexpr int i = decltype(ic)::value;
       const int m = mb + i;
-      if (m >= m1) return;
-      pr[i] = np[i];
-      cr[i] = nc[i] * lam;
-      if (m + K < m1) {
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        // the loaded values pass through opaque() where they are used: the
+        // compiler would otherwise move these products into the previous
+        // iteration, right after the loads, and wait for them there
+        pr[v][i] = opaque(np[v][i]);
+        cr[v][i] = opaque(nc[v][i]) * lam;
+        depart_fn<R>(cr[v][i], fr[v][i], nr[v][i], over);
+      }
+      {  // unconditional, and every iteration runs all K steps (past m1 the
+         // loads read wrapped rows whose results go unused): a load under a
+         // condition makes the wave wait for the loads in flight
         const unsigned rn = unsigned(lrow) * S4;
-        np[i] = ld_row(rp, voff, rn);
-        nc[i] = ld_row(ru, voff, rn);
+        float a[V], c[V];
+        ld_rowv<V>(rp, voff, rn, a);
+        ld_rowv<V>(ru, voff, rn, c);
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          np[v][i] = a[v];
+          nc[v][i] = c[v];
+        }
       }
       lrow = lrow + 1 == L ? 0 : lrow + 1;
-      // Phi1 of node m - R
-      constexpr int j1 = pmod(i - R, K);
-      {
-        const DepN d = depart_n<R>(cr[j1], flag);
-        float a, b;
-        ring_pair<R, K, j1>(pr, d, a, b);
-        p1[j1] = lerp(a, b, d.f);
-      }
-      // e of node m - 2R
-      constexpr int j2 = pmod(i - 2 * R, K);
-      {
-        const DepN d = depart_n<R>(-cr[j2], flag);
-        float a, b;
-        ring_pair<R, K, j2>(p1, d, a, b);
-        er[j2] = pr[j2] - lerp(a, b, d.f);
+      constexpr int j1 = pmod(i - R, K), j2 = pmod(i - 2 * R, K), j3 = pmod(i - 3 * R, K);
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        {  // Phi1 of node m - R
+          const DepN d = dep_fwd(cr[v][j1], fr[v][j1], nr[v][j1]);
+          float a, b;
+          ring_pair<R, K, j1>(pr[v], d, a, b);
+          p1[v][j1] = lerp(a, b, d.f);
+        }
+        {  // e of node m - 2R
+          const DepN d = dep_rev(cr[v][j2], fr[v][j2], nr[v][j2]);
+          float a, b;
+          ring_pair<R, K, j2>(p1[v], d, a, b);
+          er[v][j2] = pr[v][j2] - lerp(a, b, d.f);
+        }
       }
       // out of node m - 3R
-      constexpr int j3 = pmod(i - 3 * R, K);
-      if (m - 3 * R >= l0) {
-        const DepN d = depart_n<R>(cr[j3], flag);
-        float ea, eb;
-        ring_pair<R, K, j3>(er, d, ea, eb);
-        const float w = fmaf(d.f, 1.f / 3.f, 1.f / 3.f);
-        st_row(ro, voff, unsigned(srow) * S4, fmaf(0.5f, fmaf(w, eb - ea, ea), p1[j3]));
+      if (m - 3 * R >= l0 && m - 3 * R < l1) {
+        float o[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          const DepN d = dep_fwd(cr[v][j3], fr[v][j3], nr[v][j3]);
+          float ea, eb;
+          ring_pair<R, K, j3>(er[v], d, ea, eb);
+          const float w = fmaf(d.f, 1.f / 3.f, 1.f / 3.f);
+          o[v] = fmaf(0.5f, fmaf(w, eb - ea, ea), p1[v][j3]);
+        }
+        st_rowv<V>(ro, voff, unsigned(srow) * S4, o);
       }
       srow = srow + 1 == L ? 0 : srow + 1;
     });
   }
+  if (over) *flag = 1;
 }
 
 // ---------------------------------------------------------------------------
@@ -736,16 +818,78 @@ __global__ __launch_bounds__(kThreads) void k_sweep_m(const float* __restrict__ 
 // 2R .. 63 - 2R, the output on 3R .. 63 - 3R.  No LDS memory, no barriers.
 // The arithmetic per node is that of k_sweep_x.
 // ---------------------------------------------------------------------------
-// Third-order sweep along x of one value per lane (lanes are consecutive
-// x): the anchor and far values of each call are read from the lanes at the
-// departure offsets (__shfl).  Exact on lanes 3R .. 63 - 3R.
+// Value of the lane below (lane - 1) and above (lane + 1): DPP wave shifts,
+// one vector move each; lanes 0 and 63 receive 0.
+__device__ __forceinline__ float lane_below(float v) {
+  const int i = __builtin_bit_cast(int, v);
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, i, 0x138, 0xf, 0xf, true));
+}
+__device__ __forceinline__ float lane_above(float v) {
+  const int i = __builtin_bit_cast(int, v);
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, i, 0x130, 0xf, 0xf, true));
+}
+
+// Anchor and far values of a call from the values of the lanes k = 0 .. R
+// below (lo[k]) and above (hi[k]): the selection of ring_pair.
 template <int R>
-__device__ __forceinline__ float xsweep_lanes(float p, float c, int lane, int* flag) {
-  const Dep d = depart<R>(c, flag);
-  const float p1 = lerp(__shfl(p, lane + d.oa), __shfl(p, lane + d.ob), d.f);
-  const Dep dr = depart<R>(-c, flag);
-  const float e = p - lerp(__shfl(p1, lane + dr.oa), __shfl(p1, lane + dr.ob), dr.f);
-  const float ea = __shfl(e, lane + d.oa), eb = __shfl(e, lane + d.ob);
+__device__ __forceinline__ void view_pair(const float (&lo)[R + 1], const float (&hi)[R + 1],
+                                          const DepN& d, float& a, float& b) {
+  const float c0 = lo[0];
+  float an_l = c0, an_r = c0;
+  float fa_l = lo[1], fa_r = hi[1];
+  float pl = fa_l, pr = fa_r;
+#pragma unroll
+  for (int k = 1; k < R; ++k) {
+    const float nl = lo[k + 1], nr = hi[k + 1];
+    const bool hit = d.n == float(k);
+    an_l = hit ? pl : an_l;
+    an_r = hit ? pr : an_r;
+    fa_l = hit ? nl : fa_l;
+    fa_r = hit ? nr : fa_r;
+    pl = nl;
+    pr = nr;
+  }
+  a = d.pos ? an_l : an_r;
+  b = d.pos ? fa_l : fa_r;
+}
+template <int R>
+__device__ __forceinline__ void lane_views(float v, float (&lo)[R + 1], float (&hi)[R + 1]) {
+  lo[0] = hi[0] = v;
+#pragma unroll
+  for (int k = 1; k <= R; ++k) {
+    lo[k] = lane_below(lo[k - 1]);
+    hi[k] = lane_above(hi[k - 1]);
+  }
+}
+
+// Third-order sweep along x of one value per lane (lanes are consecutive
+// x): the anchor and far values of each call come from the lanes at the
+// departure offsets, by DPP shifts at reach 1 and 2 (2R vector moves per
+// value, no LDS) and by __shfl (a cross-lane read through LDS hardware)
+// beyond.  Exact on lanes 3R .. 63 - 3R; an overflow is recorded in over.
+template <int R>
+__device__ __forceinline__ float xsweep_lanes(float p, float c, int lane, bool& over) {
+  const DepN d = depart_n<R>(c, over), dr = depart_n<R>(-c, over);
+  float p1, e, ea, eb;
+  if constexpr (R <= 2) {
+    float lo[R + 1], hi[R + 1], a, b;
+    lane_views<R>(p, lo, hi);
+    view_pair<R>(lo, hi, d, a, b);
+    p1 = lerp(a, b, d.f);
+    lane_views<R>(p1, lo, hi);
+    view_pair<R>(lo, hi, dr, a, b);
+    e = p - lerp(a, b, dr.f);
+    lane_views<R>(e, lo, hi);
+    view_pair<R>(lo, hi, d, ea, eb);
+  } else {
+    const int n = int(d.n), nr = int(dr.n);
+    const int oa = d.pos ? -n : n, ob = d.pos ? -(n + 1) : n + 1;
+    const int ra = dr.pos ? -nr : nr, rb = dr.pos ? -(nr + 1) : nr + 1;
+    p1 = lerp(__shfl(p, lane + oa), __shfl(p, lane + ob), d.f);
+    e = p - lerp(__shfl(p1, lane + ra), __shfl(p1, lane + rb), dr.f);
+    ea = __shfl(e, lane + oa);
+    eb = __shfl(e, lane + ob);
+  }
   const float w = fmaf(d.f, 1.f / 3.f, 1.f / 3.f);
   return fmaf(0.5f, fmaf(w, eb - ea, ea), p1);
 }
@@ -758,8 +902,10 @@ __global__ __launch_bounds__(kThreads) void k_sweep_xw(const float* __restrict__
   constexpr int USE = 64 - 6 * R;  // outputs per window
   constexpr int WPW = 4;           // windows per wave, loaded together
   const int lane = threadIdx.x & 63;
-  const int wid = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
+  // the wave's index, in a scalar register (row arithmetic stays scalar)
+  const int wid = blockIdx.x * (kThreads / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int ngrp = (nwin + WPW - 1) / WPW;
+  bool over = false;
   const int row = wid / ngrp;
   if (row >= nrows) return;
   const int w0 = (wid - row * ngrp) * WPW;
@@ -779,10 +925,11 @@ __global__ __launch_bounds__(kThreads) void k_sweep_xw(const float* __restrict__
 #pragma unroll
   for (int k = 0; k < WPW; ++k) {
     if (w0 + k >= nwin) break;
-    const float o = xsweep_lanes<R>(p[k], c[k] * lam, lane, flag);
+    const float o = xsweep_lanes<R>(p[k], c[k] * lam, lane, over);
     const int xo = (w0 + k) * USE + lane - 3 * R;  // output node of this lane
     if (lane >= 3 * R && lane < 64 - 3 * R && xo < nx) st_row(out, off[k], rowoff, o);
   }
+  if (over) *flag = 1;
 }
 
 // ---------------------------------------------------------------------------
@@ -813,7 +960,8 @@ __global__ __launch_bounds__(kThreads) void k_sweep_xym(const float* __restrict_
   constexpr int K = 3 * R + 1;
   constexpr int USE = 64 - 6 * R;  // outputs per window
   const int lane = threadIdx.x & 63;
-  const int wid = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
+  // the wave's index, in a scalar register (row arithmetic stays scalar)
+  const int wid = blockIdx.x * (kThreads / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int win = wid % nwin, z = (wid / nwin) % nz, ch = wid / (nwin * nz);
   const int l0 = ch * chunk;
   if (l0 >= ny) return;  // the whole wave
@@ -828,29 +976,35 @@ __global__ __launch_bounds__(kThreads) void k_sweep_xym(const float* __restrict_
   };
   const int m0 = l0 - 3 * R, m1 = l1 + 3 * R;  // steps m0 .. m1 - 1
   float pr[K], p1[K], er[K], cr[K];  // rings
+  float fr[K], nr[K];                // departure fraction and distance of each ring slot
   float np[K], nc[K], nx_[K];        // loads of the next K steps (nx_: x velocity)
   int lrow = wrapped(m0);            // row of the next phi / y-velocity load
   int xrow = XFIRST ? lrow : wrapped(m0 - 3 * R);  // row of the next x-velocity load
 #pragma unroll
   for (int i = 0; i < K; ++i) {
-    pr[i] = p1[i] = er[i] = cr[i] = 0.f;
+    pr[i] = p1[i] = er[i] = cr[i] = fr[i] = nr[i] = 0.f;
     const unsigned ro = zoff + unsigned(lrow) * rowb;
     np[i] = ld_row(phi, vx, ro);
     nc[i] = ld_row(uy, vx, ro);
     nx_[i] = ld_row(ux, vx, zoff + unsigned(xrow) * rowb);
     lrow = lrow + 1 == ny ? 0 : lrow + 1;
     xrow = xrow + 1 == ny ? 0 : xrow + 1;
+    __builtin_amdgcn_sched_barrier(0);  // in step order, as in k_sweep_m
   }
   int srow = wrapped(m0 - 3 * R);  // row of node m - 3R
+  bool over = false;
   for (int mb = m0; mb < m1; mb += K) {
     static_for<K>([&](auto ic) {
       constexpr int i = decltype(ic)::value;
       const int m = mb + i;
-      if (m >= m1) return;
-      const float cx = nx_[i] * lamx;  // x Courant number of row m (XFIRST) or of row m - 3R
-      pr[i] = XFIRST ? xsweep_lanes<R>(np[i], cx, lane, flag) : np[i];
-      cr[i] = nc[i] * lamy;
-      if (m + K < m1) {
+      // the loaded values pass through opaque() where they are used: the
+      // compiler would otherwise move these products into the previous
+      // iteration, right after the loads, and wait for them there
+      const float cx = opaque(nx_[i]) * lamx;  // x Courant number of row m (XFIRST) or of row m - 3R
+      pr[i] = XFIRST ? xsweep_lanes<R>(opaque(np[i]), cx, lane, over) : opaque(np[i]);
+      cr[i] = opaque(nc[i]) * lamy;
+      depart_fn<R>(cr[i], fr[i], nr[i], over);
+      {  // unconditional, all K steps, as in k_sweep_m
         const unsigned rn = zoff + unsigned(lrow) * rowb;
         np[i] = ld_row(phi, vx, rn);
         nc[i] = ld_row(uy, vx, rn);
@@ -861,7 +1015,7 @@ __global__ __launch_bounds__(kThreads) void k_sweep_xym(const float* __restrict_
       // Phi1 of node m - R
       constexpr int j1 = pmod(i - R, K);
       {
-        const DepN d = depart_n<R>(cr[j1], flag);
+        const DepN d = dep_fwd(cr[j1], fr[j1], nr[j1]);
         float a, b;
         ring_pair<R, K, j1>(pr, d, a, b);
         p1[j1] = lerp(a, b, d.f);
@@ -869,25 +1023,194 @@ __global__ __launch_bounds__(kThreads) void k_sweep_xym(const float* __restrict_
       // e of node m - 2R
       constexpr int j2 = pmod(i - 2 * R, K);
       {
-        const DepN d = depart_n<R>(-cr[j2], flag);
+        const DepN d = dep_rev(cr[j2], fr[j2], nr[j2]);
         float a, b;
         ring_pair<R, K, j2>(p1, d, a, b);
         er[j2] = pr[j2] - lerp(a, b, d.f);
       }
       // out of node m - 3R
       constexpr int j3 = pmod(i - 3 * R, K);
-      if (m - 3 * R >= l0) {
-        const DepN d = depart_n<R>(cr[j3], flag);
+      if (m - 3 * R >= l0 && m - 3 * R < l1) {
+        const DepN d = dep_fwd(cr[j3], fr[j3], nr[j3]);
         float ea, eb;
         ring_pair<R, K, j3>(er, d, ea, eb);
         const float w = fmaf(d.f, 1.f / 3.f, 1.f / 3.f);
         float o = fmaf(0.5f, fmaf(w, eb - ea, ea), p1[j3]);
-        if (!XFIRST) o = xsweep_lanes<R>(o, cx, lane, flag);
+        if (!XFIRST) o = xsweep_lanes<R>(o, cx, lane, over);
         if (lane_out) st_row(out, vx, zoff + unsigned(srow) * rowb, o);
       }
       srow = srow + 1 == ny ? 0 : srow + 1;
     });
   }
+  if (over) *flag = 1;
+}
+
+// ---------------------------------------------------------------------------
+// The fused x and y sweeps of k_sweep_xym with two nodes per lane, for even
+// nx: a wave's window is 128 consecutive x of one z plane (lane l: nodes 2l
+// and 2l+1, one 8-byte access), HL = 3R rounded up to even nodes of halo
+// on each side, and up to 128 - 2 HL outputs.  The windows of a row are
+// balanced (usew outputs each, even, the last one shorter); lanes past the
+// nodes a window needs repeat its last pair, so every load is unconditional
+// and reads no line twice.  Pairs start on even x and never straddle the
+// periodic end.  Per node the same FP32 operations as k_sweep_xym, which
+// this kernel matches bit for bit; the halo costs 2 HL / usew of the loads
+// instead of 6R / (64 - 6R).
+// ---------------------------------------------------------------------------
+// Values at distance k = 0 .. R below (l*) and above (h*) nodes a = 2l and
+// b = 2l + 1 of a row held as pairs: node 2l - 1 is lane l-1's b, 2l + 2
+// lane l+1's a, and so on (DPP wave shifts; R <= 3).
+template <int R>
+__device__ __forceinline__ void pair_views(float a, float b, float (&la)[R + 1], float (&ha)[R + 1],
+                                           float (&lb)[R + 1], float (&hb)[R + 1]) {
+  static_assert(R >= 1 && R <= 3, "pair views reach three nodes");
+  const float ba = lane_below(a), bb = lane_below(b), aa = lane_above(a), ab = lane_above(b);
+  la[0] = ha[0] = a;
+  lb[0] = hb[0] = b;
+  la[1] = bb;
+  ha[1] = b;
+  lb[1] = a;
+  hb[1] = aa;
+  if constexpr (R >= 2) {
+    la[2] = ba;
+    ha[2] = aa;
+    lb[2] = bb;
+    hb[2] = ab;
+  }
+  if constexpr (R >= 3) {
+    la[3] = lane_below(bb);
+    ha[3] = ab;
+    lb[3] = ba;
+    hb[3] = lane_above(aa);
+  }
+}
+
+// xsweep_lanes for a row held as pairs: the same operations per node.
+template <int R>
+__device__ __forceinline__ void xsweep_pair(float& a, float& b, float ca, float cb, bool& over) {
+  const DepN da = depart_n<R>(ca, over), ra = depart_n<R>(-ca, over);
+  const DepN db = depart_n<R>(cb, over), rb = depart_n<R>(-cb, over);
+  float la[R + 1], ha[R + 1], lb[R + 1], hb[R + 1], u, v;
+  pair_views<R>(a, b, la, ha, lb, hb);
+  view_pair<R>(la, ha, da, u, v);
+  const float p1a = lerp(u, v, da.f);
+  view_pair<R>(lb, hb, db, u, v);
+  const float p1b = lerp(u, v, db.f);
+  pair_views<R>(p1a, p1b, la, ha, lb, hb);
+  view_pair<R>(la, ha, ra, u, v);
+  const float ea = a - lerp(u, v, ra.f);
+  view_pair<R>(lb, hb, rb, u, v);
+  const float eb = b - lerp(u, v, rb.f);
+  pair_views<R>(ea, eb, la, ha, lb, hb);
+  view_pair<R>(la, ha, da, u, v);
+  a = fmaf(0.5f, fmaf(fmaf(da.f, 1.f / 3.f, 1.f / 3.f), v - u, u), p1a);
+  view_pair<R>(lb, hb, db, u, v);
+  b = fmaf(0.5f, fmaf(fmaf(db.f, 1.f / 3.f, 1.f / 3.f), v - u, u), p1b);
+}
+
+template <int R>
+constexpr int pair_halo() { return (3 * R + 1) / 2 * 2; }  // 3R rounded up to even
+
+template <int R, bool XFIRST>
+__global__ __launch_bounds__(kThreads) void k_sweep_xyp(const float* __restrict__ phi,
+                                                        const float* __restrict__ ux,
+                                                        const float* __restrict__ uy,
+                                                        float* __restrict__ out, int nx, int ny,
+                                                        int nz, int nwin, int usew, int chunk,
+                                                        float lamx, float lamy, int* flag) {
+  constexpr int K = 3 * R + 1;
+  constexpr int HL = pair_halo<R>();
+  const int lane = threadIdx.x & 63;
+  const int wid = blockIdx.x * (kThreads / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int win = wid % nwin, z = (wid / nwin) % nz, ch = wid / (nwin * nz);
+  const int l0 = ch * chunk;
+  if (l0 >= ny) return;  // the whole wave
+  const int l1 = min(l0 + chunk, ny);
+  const int x0 = win * usew, nout = min(usew, nx - x0);  // the window's outputs x0 .. x0 + nout - 1
+  const int wl = min(2 * lane, nout + 2 * HL - 2);        // window node of the lane's pair
+  const unsigned vx = 4u * unsigned(wrapk(x0 - HL + wl, nx));
+  const bool lane_out = 2 * lane >= HL && 2 * lane < HL + nout;
+  const unsigned rowb = 4u * unsigned(nx);
+  const unsigned zoff = unsigned(z) * unsigned(ny) * rowb;
+  auto wrapped = [&](int m) {
+    m %= ny;
+    return m < 0 ? m + ny : m;
+  };
+  const int m0 = l0 - 3 * R, m1 = l1 + 3 * R;  // steps m0 .. m1 - 1
+  float pr[2][K], p1[2][K], er[2][K], cr[2][K];  // rings, per node of the pair
+  float np[2][K], nc[2][K], nu[2][K];            // loads of the next K steps (nu: x velocity)
+  int lrow = wrapped(m0);                         // row of the next phi / y-velocity load
+  int xrow = XFIRST ? lrow : wrapped(m0 - 3 * R); // row of the next x-velocity load
+#pragma unroll
+  for (int i = 0; i < K; ++i) {
+#pragma unroll
+    for (int v = 0; v < 2; ++v) pr[v][i] = p1[v][i] = er[v][i] = cr[v][i] = 0.f;
+    const unsigned ro = zoff + unsigned(lrow) * rowb;
+    ld2_row(phi, vx, ro, np[0][i], np[1][i]);
+    ld2_row(uy, vx, ro, nc[0][i], nc[1][i]);
+    ld2_row(ux, vx, zoff + unsigned(xrow) * rowb, nu[0][i], nu[1][i]);
+    lrow = lrow + 1 == ny ? 0 : lrow + 1;
+    xrow = xrow + 1 == ny ? 0 : xrow + 1;
+    __builtin_amdgcn_sched_barrier(0);  // in step order, as in k_sweep_m
+  }
+  int srow = wrapped(m0 - 3 * R);  // row of node m - 3R
+  bool over = false;
+  for (int mb = m0; mb < m1; mb += K) {
+    static_for<K>([&](auto ic) {
+      constexpr int i = decltype(ic)::value;
+      const int m = mb + i;
+      // x Courant numbers of row m (XFIRST) or of row m - 3R
+      const float cxa = opaque(nu[0][i]) * lamx, cxb = opaque(nu[1][i]) * lamx;
+      {
+        float a = opaque(np[0][i]), b = opaque(np[1][i]);
+        if (XFIRST) xsweep_pair<R>(a, b, cxa, cxb, over);
+        pr[0][i] = a;
+        pr[1][i] = b;
+      }
+#pragma unroll
+      for (int v = 0; v < 2; ++v) cr[v][i] = opaque(nc[v][i]) * lamy;
+      {  // unconditional, all K steps, as in k_sweep_m
+        const unsigned rn = zoff + unsigned(lrow) * rowb;
+        ld2_row(phi, vx, rn, np[0][i], np[1][i]);
+        ld2_row(uy, vx, rn, nc[0][i], nc[1][i]);
+        ld2_row(ux, vx, zoff + unsigned(xrow) * rowb, nu[0][i], nu[1][i]);
+      }
+      lrow = lrow + 1 == ny ? 0 : lrow + 1;
+      xrow = xrow + 1 == ny ? 0 : xrow + 1;
+      constexpr int j1 = pmod(i - R, K), j2 = pmod(i - 2 * R, K), j3 = pmod(i - 3 * R, K);
+#pragma unroll
+      for (int v = 0; v < 2; ++v) {
+        {  // Phi1 of node m - R
+          const DepN d = depart_n<R>(cr[v][j1], over);
+          float a, b;
+          ring_pair<R, K, j1>(pr[v], d, a, b);
+          p1[v][j1] = lerp(a, b, d.f);
+        }
+        {  // e of node m - 2R
+          const DepN d = depart_n<R>(-cr[v][j2], over);
+          float a, b;
+          ring_pair<R, K, j2>(p1[v], d, a, b);
+          er[v][j2] = pr[v][j2] - lerp(a, b, d.f);
+        }
+      }
+      // out of node m - 3R
+      if (m - 3 * R >= l0 && m - 3 * R < l1) {
+        float o[2];
+#pragma unroll
+        for (int v = 0; v < 2; ++v) {
+          const DepN d = depart_n<R>(cr[v][j3], over);
+          float ea, eb;
+          ring_pair<R, K, j3>(er[v], d, ea, eb);
+          const float w = fmaf(d.f, 1.f / 3.f, 1.f / 3.f);
+          o[v] = fmaf(0.5f, fmaf(w, eb - ea, ea), p1[v][j3]);
+        }
+        if (!XFIRST) xsweep_pair<R>(o[0], o[1], cxa, cxb, over);
+        if (lane_out) st2_row(out, vx, zoff + unsigned(srow) * rowb, o[0], o[1]);
+      }
+      srow = srow + 1 == ny ? 0 : srow + 1;
+    });
+  }
+  if (over) *flag = 1;
 }
 
 template <typename F>
@@ -938,13 +1261,24 @@ hipError_t launch_sweep_t(int d, const Geo& g, const float* phi, const float* ud
     const int other = d == 1 ? g.nz : g.ny;
     const unsigned S4 = 4u * unsigned(d == 1 ? g.nx : g.nx * g.ny);
     const unsigned So4 = 4u * unsigned(d == 1 ? g.nx * g.ny : g.nx);
-    // enough waves to fill the chip (about 8 per CU), chunks of >= 16R nodes
-    const long long waves = (long long)((g.nx + 63) / 64) * other;
+    // two columns per lane with an even nx up to reach 2 (more rings would
+    // cost occupancy); enough waves to fill the chip (about 8 per CU),
+    // chunks of >= 16R nodes
+    const bool two = g.nx % 2 == 0 && R <= 2;
+    const int cols = two ? 128 : 64;
+    const long long waves = (long long)((g.nx + cols - 1) / cols) * other;
     const int want = int(std::min<long long>((2048 + waves - 1) / waves, std::max(1, L / (16 * R))));
     const int chunk = (L + want - 1) / want;
-    dim3 grid((g.nx + 63) / 64, (other + 3) / 4, (L + chunk - 1) / chunk);
-    hipLaunchKernelGGL(k_sweep_m<R>, grid, dim3(kThreads), 0, st, phi, ud, out, g.nx, L, S4, So4,
-                       other, chunk, g.lam[d], flag);
+    dim3 grid((g.nx + cols - 1) / cols, (other + 3) / 4, (L + chunk - 1) / chunk);
+    if constexpr (R <= 2) {
+      if (two) {
+        hipLaunchKernelGGL((k_sweep_m<R, 2>), grid, dim3(kThreads), 0, st, phi, ud, out, g.nx, L, S4,
+                           So4, other, chunk, g.lam[d], flag);
+        return hipGetLastError();
+      }
+    }
+    hipLaunchKernelGGL((k_sweep_m<R, 1>), grid, dim3(kThreads), 0, st, phi, ud, out, g.nx, L, S4,
+                       So4, other, chunk, g.lam[d], flag);
     return hipGetLastError();
   }
   if (d == 0 && march && offsets32_ok(g)) {
@@ -1052,10 +1386,53 @@ hipError_t launch_sweep_xy_t(bool xfirst, const Geo& g, const float* phi, const 
   return hipGetLastError();
 }
 
+// Waves a launch of k_sweep_xyp aims for at reach 1 and 2 (32 per CU;
+// half as many at reach 3, whose chunks carry 18 halo rows): its chunks
+// along y are the longest that still give that many, and at least 16R rows.
+// Measured at 512^3: 4096 and 16384 are 2-3% slower at reach 2; 8192 is
+// 1% slower than 4096 at reach 3.
+#ifndef SLA_XYP_WAVES
+#define SLA_XYP_WAVES 8192
+#endif
+
+template <int R>
+hipError_t launch_sweep_xyp_t(bool xfirst, const Geo& g, const float* phi, const float* u,
+                              float* out, int* flag, hipStream_t st) {
+  constexpr int USE = 128 - 2 * pair_halo<R>();  // most outputs of a window
+  const size_t n = (size_t)g.ncells;
+  // balanced windows: usew outputs each (even), every window non-empty
+  int nwin = (g.nx + USE - 1) / USE;
+  int usew = (g.nx + nwin - 1) / nwin;
+  usew += usew & 1;
+  nwin = (g.nx + usew - 1) / usew;
+  const long long per = (long long)nwin * g.nz;
+  constexpr long long target = R >= 3 ? SLA_XYP_WAVES / 2 : SLA_XYP_WAVES;
+  const int want = int(std::min<long long>((target + per - 1) / per, std::max(1, g.ny / (16 * R))));
+  const int chunk = (g.ny + want - 1) / want;
+  const long long waves = per * ((g.ny + chunk - 1) / chunk);
+  const dim3 grid(unsigned((waves + 3) / 4));
+  if (xfirst)
+    hipLaunchKernelGGL((k_sweep_xyp<R, true>), grid, dim3(kThreads), 0, st, phi, u, u + n, out, g.nx,
+                       g.ny, g.nz, nwin, usew, chunk, g.lam[0], g.lam[1], flag);
+  else
+    hipLaunchKernelGGL((k_sweep_xyp<R, false>), grid, dim3(kThreads), 0, st, phi, u, u + n, out,
+                       g.nx, g.ny, g.nz, nwin, usew, chunk, g.lam[0], g.lam[1], flag);
+  return hipGetLastError();
+}
+
 hipError_t launch_cec_sweep_xy(int R, bool xfirst, const Geo& g, const float* phi, const float* u,
-                               float* out, int* flag, hipStream_t st) {
+                               float* out, int* flag, hipStream_t st, bool pairs) {
   if (!offsets32_ok(g)) return hipErrorInvalidValue;
-  switch (R) {  // reach 3 and more run one sweep per axis (see the caller)
+  if (pairs) {
+    if (g.nx % 2 != 0) return hipErrorInvalidValue;
+    switch (R) {
+      case 1: return launch_sweep_xyp_t<1>(xfirst, g, phi, u, out, flag, st);
+      case 2: return launch_sweep_xyp_t<2>(xfirst, g, phi, u, out, flag, st);
+      case 3: return launch_sweep_xyp_t<3>(xfirst, g, phi, u, out, flag, st);
+    }
+    return hipErrorInvalidValue;
+  }
+  switch (R) {  // one node per lane: reach 3 and more run one sweep per axis (see the caller)
     case 1: return launch_sweep_xy_t<1>(xfirst, g, phi, u, out, flag, st);
     case 2: return launch_sweep_xy_t<2>(xfirst, g, phi, u, out, flag, st);
   }

@@ -27,7 +27,7 @@ struct sla_ctx {
   std::string err;
   bool fused = true;    // SLA_OPT_FUSED
   int cec3d_kernel = 5;  // SLA_OPT_CEC3D_KERNEL
-  int sweep_kernel = 2;  // SLA_OPT_SWEEP_KERNEL
+  int sweep_kernel = 3;  // SLA_OPT_SWEEP_KERNEL
   int ec_kernel = 3;     // SLA_OPT_EC_KERNEL
   int cec3d_shape = 0;   // SLA_OPT_CEC3D_SHAPE
   int ec_shape = 0;      // SLA_OPT_EC_SHAPE
@@ -683,6 +683,13 @@ int sla_model_save(sla_ctx* ctx, const sla_model* model, float* params, int64_t 
 
 namespace {
 
+// True if the x and y sweeps of a third-order step at reach rxy (the larger
+// of the two axes') run in the kernel with two nodes per lane:
+// SLA_OPT_SWEEP_KERNEL 3, an even nx and a reach of at most 3.
+bool xy_pairs(const sla_ctx* ctx, const sla::Geo& g, int rxy) {
+  return ctx->sweep_kernel == 3 && g.nx % 2 == 0 && rxy <= 3;
+}
+
 // The steps of sla_advect once the arguments are checked and the reach per
 // axis is known (the device is selected).
 int advect_steps(sla_ctx* ctx, const sla_grid* grid, float* phi, const float* u, double dt,
@@ -785,17 +792,21 @@ int advect_steps(sla_ctx* ctx, const sla_grid* grid, float* phi, const float* u,
           break;
         }
         const int rxy = reach[0] > reach[1] ? reach[0] : reach[1];
-        if (ndim >= 2 && ctx->sweep_kernel == 2 && rxy <= 2 && sla::offsets32_ok(geo)) {
+        const bool pairs = xy_pairs(ctx, geo, rxy);
+        if (ndim >= 2 && (pairs || (ctx->sweep_kernel >= 2 && rxy <= 2)) &&
+            sla::offsets32_ok(geo)) {
           // x and y in one kernel: x,y then z on even steps, z then y,x on
-          // odd.  Up to reach 2: a 64-lane window then yields 52 or more
-          // outputs; at reach 3 (46) the y sweep's work on the halo lanes
-          // outweighs the saved traffic, and the sweeps run one per axis.
+          // odd.  With one node per lane up to reach 2: a 64-lane window
+          // then yields 52 or more outputs; at reach 3 (46) the y sweep's
+          // work on the halo lanes outweighs the saved traffic, and the
+          // sweeps run one per axis.  Two nodes per lane: 108 at reach 3.
           const bool even = m % 2 == 0;
           for (int part = 0; part < 2 && e == hipSuccess; ++part) {
             const bool xy = (part == 0) == even;
             if (xy) {
               e = run(ctx, SLA_K_SWEEP_XY, [&] {
-                return sla::launch_cec_sweep_xy(rxy, even, geo, cur, u, nxt, ctx->flag, ctx->stream);
+                return sla::launch_cec_sweep_xy(rxy, even, geo, cur, u, nxt, ctx->flag, ctx->stream,
+                                                pairs);
               });
             } else {
               if (ndim < 3) continue;
@@ -852,7 +863,8 @@ int advect_steps(sla_ctx* ctx, const sla_grid* grid, float* phi, const float* u,
           std::swap(cur, nxt);
         };
         const int rxy = rh[0] > rh[1] ? rh[0] : rh[1];
-        if (ndim == 3 && ctx->sweep_kernel == 2 && rxy <= 2 && sla::offsets32_ok(geo)) {
+        const bool pairs = xy_pairs(ctx, geo, rxy);
+        if (ndim == 3 && (pairs || (ctx->sweep_kernel >= 2 && rxy <= 2)) && sla::offsets32_ok(geo)) {
           // x/2 then y/2 in one kernel, z, then y/2 then x/2 in one kernel
           for (int part = 0; part < 3 && e == hipSuccess; ++part) {
             if (part == 1) {
@@ -861,7 +873,7 @@ int advect_steps(sla_ctx* ctx, const sla_grid* grid, float* phi, const float* u,
             }
             e = run(ctx, SLA_K_SWEEP_XY, [&] {
               return sla::launch_cec_sweep_xy(rxy, part == 0, half, cur, u, nxt, ctx->flag,
-                                              ctx->stream);
+                                              ctx->stream, pairs);
             });
             std::swap(cur, nxt);
           }
@@ -902,7 +914,7 @@ int sla_set_option(sla_ctx* ctx, int option, int64_t value) {
       ctx->cec3d_kernel = int(value);
       return SLA_OK;
     case SLA_OPT_SWEEP_KERNEL:
-      if (value < 0 || value > 2) return fail(ctx, SLA_EINVAL, "SLA_OPT_SWEEP_KERNEL takes 0, 1 or 2");
+      if (value < 0 || value > 3) return fail(ctx, SLA_EINVAL, "SLA_OPT_SWEEP_KERNEL takes 0 to 3");
       ctx->sweep_kernel = int(value);
       return SLA_OK;
     case SLA_OPT_EC_KERNEL:

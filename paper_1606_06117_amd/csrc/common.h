@@ -69,11 +69,12 @@ hipError_t launch_cec_sweep_mid(int d, int R, const Geo& g, const float* phi, co
 hipError_t launch_cec_sweep(int d, int R, const Geo& g, const float* phi,
                             const float* u_d, float* out, int* flag, hipStream_t st,
                             bool march = true);
-// The x and y sweeps of a third-order step in one kernel (reach R <= 2 on
-// both axes): x then y if xfirst, else y then x; u holds the x and y
-// planes.  Same results as the two sweeps.  Needs offsets32_ok(g).
+// The x and y sweeps of a third-order step in one kernel: x then y if
+// xfirst, else y then x; u holds the x and y planes.  Same results as the
+// two sweeps.  pairs: two nodes per lane, even nx, reach R <= 3 on both
+// axes; otherwise one node per lane, R <= 2.  Needs offsets32_ok(g).
 hipError_t launch_cec_sweep_xy(int R, bool xfirst, const Geo& g, const float* phi, const float* u,
-                               float* out, int* flag, hipStream_t st);
+                               float* out, int* flag, hipStream_t st, bool pairs);
 
 // Fused three-axis third-order step (reach 1 only): x,y,z order if even,
 // z,y,x otherwise.  variant: 1 register segments, 2 streaming (direct

@@ -284,7 +284,7 @@ def test_cec_1d_reads_only_its_plane(ctx):
         ctx.advect(q, u, dx, dt, native.CEC, 4)
         torch.cuda.synchronize()
     finally:
-        ctx.set_option(native.OPT_SWEEP_KERNEL, 2)
+        ctx.set_option(native.OPT_SWEEP_KERNEL, 3)
     assert np.array_equal(got, q.cpu().numpy())
     ref = oracle_advect(phi, u.cpu().numpy(), dx, dt, oracle.CEC, 4)
     check(got.astype(np.float64), ref, phi, 4, "1d cec, NaN after u")
@@ -422,6 +422,8 @@ def test_tuner_choice_is_used_and_gives_the_same_bits(ctx, tmp_path):
     ((40, 96, 24), 0.9, 2),    # reach 1, y axis chunked
     ((40, 96, 24), 1.5, 3),    # reach 2
     ((12, 33, 70), 1.8, 3),    # reach 2, ragged (x windows, y chunks)
+    ((12, 33, 69), 1.8, 3),    # odd nx: no two-node windows
+    ((8, 20, 250), 1.5, 2),    # three two-node windows of 84 outputs
     ((1, 50, 66), 1.5, 2),     # 2D, reach 2
     ((12, 33, 70), 2.5, 2),    # reach 3, ragged
     ((8, 9, 70), 3.5, 2),      # reach 4: halo 12 > axis length 8 and 9
@@ -429,10 +431,11 @@ def test_tuner_choice_is_used_and_gives_the_same_bits(ctx, tmp_path):
     ((64, 8, 16), 0.9, 2),     # z columns walked in 2 chunks
 ])
 def test_marching_sweeps_match_tiles(ctx, shape, cfl, steps):
-    """The three ways the sweeps run give the same bits (same FP32 operations
-    per node): the fused x+y kernel with z walking columns (default), one
-    kernel per axis with x in lane windows and y, z walking columns, and the
-    LDS-tile sweeps.  Odd then even steps, so both orders of the x+y kernel
+    """The four ways the sweeps run give the same bits (same FP32 operations
+    per node): the fused x+y kernel with two nodes per lane (default; even
+    nx, reach <= 3) and with one (reach <= 2), z walking columns, one kernel
+    per axis with x in lane windows and y, z walking columns, and the
+    LDS-tile sweeps.  Odd then even steps, so both orders of the x+y kernels
     run."""
     from paper_1606_06117_amd import native
     if shape[0] == 1:
@@ -448,16 +451,19 @@ def test_marching_sweeps_match_tiles(ctx, shape, cfl, steps):
     dt = cfl * min(dx) / umax
     ctx.set_option(native.OPT_FUSED, 0)
     try:
+        pairs = gpu_advect(ctx, phi, u, dx, dt, oracle.CEC, steps, step0=1)
+        ctx.set_option(native.OPT_SWEEP_KERNEL, 2)
         fused_xy = gpu_advect(ctx, phi, u, dx, dt, oracle.CEC, steps, step0=1)
         ctx.set_option(native.OPT_SWEEP_KERNEL, 1)
         march = gpu_advect(ctx, phi, u, dx, dt, oracle.CEC, steps, step0=1)
         ctx.set_option(native.OPT_SWEEP_KERNEL, 0)
         tiles = gpu_advect(ctx, phi, u, dx, dt, oracle.CEC, steps, step0=1)
     finally:
-        ctx.set_option(native.OPT_SWEEP_KERNEL, 2)
+        ctx.set_option(native.OPT_SWEEP_KERNEL, 3)
         ctx.set_option(native.OPT_FUSED, 1)
     assert np.array_equal(march, tiles)
     assert np.array_equal(fused_xy, tiles)
+    assert np.array_equal(pairs, tiles)
 
 
 def test_fused_1024_matches_sweeps_and_last_cell(ctx):

@@ -77,23 +77,24 @@ def test_cosine_1d(ctx):
 @pytest.mark.parametrize("shape,cfl", [((40, 96, 24), 0.9), ((12, 33, 70), 2.5), ((8, 9, 70), 3.5),
                                        ((50, 66), 1.5)])
 def test_sweep_kernels_agree(ctx, shape, cfl):
-    """Tile sweeps (0), marching and window sweeps (1), fused x+y (2); the 2D
-    case under the cellular flow."""
+    """Tile sweeps (0), marching and window sweeps (1), fused x+y with one
+    (2) and two (3) nodes per lane; the 2D case under the cellular flow."""
     from paper_1606_06117_amd import native
     phi = W.random_gaussians(shape, 5, seed=41).astype(np.float32)
     u = W.abc_velocity(shape) if len(shape) == 3 else W.cellular_velocity_2d(shape)
     dx = tuple(2 * np.pi / n for n in reversed(shape))
     dt = cfl * min(dx) / (2.0 if len(shape) == 3 else 1.0)
     outs = []
-    for kern in (0, 1, 2):
+    for kern in (0, 1, 2, 3):
         ctx.set_option(native.OPT_SWEEP_KERNEL, kern)
         try:
             outs.append(gpu_advect(ctx, phi, u, dx, dt, STRANG, 2))
         finally:
-            ctx.set_option(native.OPT_SWEEP_KERNEL, 2)
-    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[1], outs[2])
+            ctx.set_option(native.OPT_SWEEP_KERNEL, 3)
+    for o in outs[1:]:
+        assert np.array_equal(outs[0], o)
     ref = oracle_advect(phi, u, dx, dt, STRANG, 2)
-    check(outs[2], ref, phi, 2, f"strang kernels {shape} cfl={cfl}")
+    check(outs[3], ref, phi, 2, f"strang kernels {shape} cfl={cfl}")
 
 
 def test_whole_cell_half_steps_are_exact(ctx):
