@@ -605,16 +605,13 @@ __global__ __launch_bounds__(64 * kTrWaves) void k_mlp_train(const __bf16* __res
 
 // Adam (Kingma & Ba) on master weight p with gradient gr; bc1 = 1 - beta1^t,
 // bc2 = 1 - beta2^t.  Returns the new weight.
-__device__ __forceinline__ float adam_one(int p, float gr, float* __restrict__ master,
-                                          float* __restrict__ mo, float* __restrict__ vo, float lr,
+// One Adam update in registers: moments m, v and weight w of a parameter
+// with gradient gr.
+__device__ __forceinline__ void adam_step(float& m, float& v, float& w, float gr, float lr,
                                           float beta1, float beta2, float eps, float bc1, float bc2) {
-  const float m1 = beta1 * mo[p] + (1.f - beta1) * gr;
-  const float v1 = beta2 * vo[p] + (1.f - beta2) * gr * gr;
-  mo[p] = m1;
-  vo[p] = v1;
-  const float w = master[p] - lr * (m1 / bc1) / (sqrtf(v1 / bc2) + eps);
-  master[p] = w;
-  return w;
+  m = beta1 * m + (1.f - beta1) * gr;
+  v = beta2 * v + (1.f - beta2) * gr * gr;
+  w = w - lr * (m / bc1) / (sqrtf(v / bc2) + eps);
 }
 
 // Round the FP32 master weights to BF16 (FP32 copy `wr`) and write the
@@ -657,10 +654,20 @@ __global__ __launch_bounds__(kThreads) void k_grad_reduce(const float* __restric
   __shared__ double lsum[kThreads];
   const int pl = threadIdx.x % kRedParams, grp = threadIdx.x / kRedParams;
   const int p = blockIdx.x * kRedParams + pl;
+  const bool own = grp == 0 && p < kMlpParams;  // the thread that finishes position p
+  // Adam state of the position's parameter, loaded with the partials
+  // instead of after the workgroup's sum
+  const int pp = own ? param_of_pos(p) : 0;
+  float am = 0.f, av = 0.f, aw = 0.f;
+  if (ADAM && own) {
+    am = ad.mo[pp];
+    av = ad.vo[pp];
+    aw = ad.master[pp];
+  }
   float s = 0.f;
   if (p < kMlpParams) {
     int b = grp;
-    constexpr int kInFlight = 16;
+    constexpr int kInFlight = 32;  // 256 partials: every load of a thread in flight at once
     for (; b + (kInFlight - 1) * kRedParts < nblk; b += kInFlight * kRedParts) {
       float v[kInFlight];
 #pragma unroll
@@ -677,16 +684,18 @@ __global__ __launch_bounds__(kThreads) void k_grad_reduce(const float* __restric
     lsum[threadIdx.x] = l;
   }
   __syncthreads();
-  if (grp == 0 && p < kMlpParams) {  // p: a partial's position
+  if (own) {  // p: a partial's position
     float t = part[0][pl];
 #pragma unroll
     for (int q = 1; q < kRedParts; ++q) t += part[q][pl];
-    const int pp = param_of_pos(p);
     grad[pp] = t;
-    if (ADAM)  // the training step's Adam update of this parameter
-      pack_one(pp, adam_one(pp, t, ad.master, ad.mo, ad.vo, ad.lr, ad.beta1, ad.beta2, ad.eps, ad.bc1,
-                            ad.bc2),
-               ad.wr, ad.wpack);
+    if (ADAM) {  // the training step's Adam update of this parameter
+      adam_step(am, av, aw, t, ad.lr, ad.beta1, ad.beta2, ad.eps, ad.bc1, ad.bc2);
+      ad.mo[pp] = am;
+      ad.vo[pp] = av;
+      ad.master[pp] = aw;
+      pack_one(pp, aw, ad.wr, ad.wpack);
+    }
   }
   if (blockIdx.x == 0) {
     for (int h = kThreads / 2; h > 0; h /= 2) {
