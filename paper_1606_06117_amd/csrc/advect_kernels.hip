@@ -703,7 +703,7 @@ __device__ __forceinline__ void ring_pair(const float (&ring)[K], const DepN& d,
   b = d.pos ? fa_l : fa_r;
 }
 
-template <int R, int V>
+template <int R, int V, int COMB = kCombCec>
 __global__ __launch_bounds__(kThreads) void k_sweep_m(const float* __restrict__ phi,
                                                       const float* __restrict__ ud,
                                                       float* __restrict__ out, int nx, int L,
@@ -797,8 +797,7 @@ __global__ __launch_bounds__(kThreads) void k_sweep_m(const float* __restrict__ 
           const DepN d = dep_fwd(cr[v][j3], fr[v][j3], nr[v][j3]);
           float ea, eb;
           ring_pair<R, K, j3>(er[v], d, ea, eb);
-          const float w = fmaf(d.f, 1.f / 3.f, 1.f / 3.f);
-          o[v] = fmaf(0.5f, fmaf(w, eb - ea, ea), p1[v][j3]);
+          o[v] = sweep_combine<COMB>(p1[v][j3], er[v][j3], ea, eb, d.f);
         }
         st_rowv<V>(ro, voff, unsigned(srow) * S4, o);
       }
@@ -867,7 +866,7 @@ __device__ __forceinline__ void lane_views(float v, float (&lo)[R + 1], float (&
 // departure offsets, by DPP shifts at reach 1 and 2 (2R vector moves per
 // value, no LDS) and by __shfl (a cross-lane read through LDS hardware)
 // beyond.  Exact on lanes 3R .. 63 - 3R; an overflow is recorded in over.
-template <int R>
+template <int R, int COMB = kCombCec>
 __device__ __forceinline__ float xsweep_lanes(float p, float c, int lane, bool& over) {
   const DepN d = depart_n<R>(c, over), dr = depart_n<R>(-c, over);
   float p1, e, ea, eb;
@@ -890,11 +889,10 @@ __device__ __forceinline__ float xsweep_lanes(float p, float c, int lane, bool& 
     ea = __shfl(e, lane + oa);
     eb = __shfl(e, lane + ob);
   }
-  const float w = fmaf(d.f, 1.f / 3.f, 1.f / 3.f);
-  return fmaf(0.5f, fmaf(w, eb - ea, ea), p1);
+  return sweep_combine<COMB>(p1, e, ea, eb, d.f);
 }
 
-template <int R>
+template <int R, int COMB = kCombCec>
 __global__ __launch_bounds__(kThreads) void k_sweep_xw(const float* __restrict__ phi,
                                                        const float* __restrict__ ud,
                                                        float* __restrict__ out, int nx, int nrows,
@@ -925,7 +923,7 @@ __global__ __launch_bounds__(kThreads) void k_sweep_xw(const float* __restrict__
 #pragma unroll
   for (int k = 0; k < WPW; ++k) {
     if (w0 + k >= nwin) break;
-    const float o = xsweep_lanes<R>(p[k], c[k] * lam, lane, over);
+    const float o = xsweep_lanes<R, COMB>(p[k], c[k] * lam, lane, over);
     const int xo = (w0 + k) * USE + lane - 3 * R;  // output node of this lane
     if (lane >= 3 * R && lane < 64 - 3 * R && xo < nx) st_row(out, off[k], rowoff, o);
   }
@@ -950,7 +948,7 @@ __global__ __launch_bounds__(kThreads) void k_sweep_xw(const float* __restrict__
 // velocity planes are read once and Phi written once: 16 B per node
 // instead of 24 for the two sweeps.
 // ---------------------------------------------------------------------------
-template <int R, bool XFIRST>
+template <int R, bool XFIRST, int COMB = kCombCec>
 __global__ __launch_bounds__(kThreads) void k_sweep_xym(const float* __restrict__ phi,
                                                         const float* __restrict__ ux,
                                                         const float* __restrict__ uy,
@@ -1001,7 +999,7 @@ __global__ __launch_bounds__(kThreads) void k_sweep_xym(const float* __restrict_
       // compiler would otherwise move these products into the previous
       // iteration, right after the loads, and wait for them there
       const float cx = opaque(nx_[i]) * lamx;  // x Courant number of row m (XFIRST) or of row m - 3R
-      pr[i] = XFIRST ? xsweep_lanes<R>(opaque(np[i]), cx, lane, over) : opaque(np[i]);
+      pr[i] = XFIRST ? xsweep_lanes<R, COMB>(opaque(np[i]), cx, lane, over) : opaque(np[i]);
       cr[i] = opaque(nc[i]) * lamy;
       depart_fn<R>(cr[i], fr[i], nr[i], over);
       {  // unconditional, all K steps, as in k_sweep_m
@@ -1034,9 +1032,8 @@ __global__ __launch_bounds__(kThreads) void k_sweep_xym(const float* __restrict_
         const DepN d = dep_fwd(cr[j3], fr[j3], nr[j3]);
         float ea, eb;
         ring_pair<R, K, j3>(er, d, ea, eb);
-        const float w = fmaf(d.f, 1.f / 3.f, 1.f / 3.f);
-        float o = fmaf(0.5f, fmaf(w, eb - ea, ea), p1[j3]);
-        if (!XFIRST) o = xsweep_lanes<R>(o, cx, lane, over);
+        float o = sweep_combine<COMB>(p1[j3], er[j3], ea, eb, d.f);
+        if (!XFIRST) o = xsweep_lanes<R, COMB>(o, cx, lane, over);
         if (lane_out) st_row(out, vx, zoff + unsigned(srow) * rowb, o);
       }
       srow = srow + 1 == ny ? 0 : srow + 1;
@@ -1086,7 +1083,7 @@ __device__ __forceinline__ void pair_views(float a, float b, float (&la)[R + 1],
 }
 
 // xsweep_lanes for a row held as pairs: the same operations per node.
-template <int R>
+template <int R, int COMB = kCombCec>
 __device__ __forceinline__ void xsweep_pair(float& a, float& b, float ca, float cb, bool& over) {
   const DepN da = depart_n<R>(ca, over), ra = depart_n<R>(-ca, over);
   const DepN db = depart_n<R>(cb, over), rb = depart_n<R>(-cb, over);
@@ -1103,15 +1100,15 @@ __device__ __forceinline__ void xsweep_pair(float& a, float& b, float ca, float 
   const float eb = b - lerp(u, v, rb.f);
   pair_views<R>(ea, eb, la, ha, lb, hb);
   view_pair<R>(la, ha, da, u, v);
-  a = fmaf(0.5f, fmaf(fmaf(da.f, 1.f / 3.f, 1.f / 3.f), v - u, u), p1a);
+  a = sweep_combine<COMB>(p1a, ea, u, v, da.f);
   view_pair<R>(lb, hb, db, u, v);
-  b = fmaf(0.5f, fmaf(fmaf(db.f, 1.f / 3.f, 1.f / 3.f), v - u, u), p1b);
+  b = sweep_combine<COMB>(p1b, eb, u, v, db.f);
 }
 
 template <int R>
 constexpr int pair_halo() { return (3 * R + 1) / 2 * 2; }  // 3R rounded up to even
 
-template <int R, bool XFIRST>
+template <int R, bool XFIRST, int COMB = kCombCec>
 __global__ __launch_bounds__(kThreads) void k_sweep_xyp(const float* __restrict__ phi,
                                                         const float* __restrict__ ux,
                                                         const float* __restrict__ uy,
@@ -1163,7 +1160,7 @@ __global__ __launch_bounds__(kThreads) void k_sweep_xyp(const float* __restrict_
       const float cxa = opaque(nu[0][i]) * lamx, cxb = opaque(nu[1][i]) * lamx;
       {
         float a = opaque(np[0][i]), b = opaque(np[1][i]);
-        if (XFIRST) xsweep_pair<R>(a, b, cxa, cxb, over);
+        if (XFIRST) xsweep_pair<R, COMB>(a, b, cxa, cxb, over);
         pr[0][i] = a;
         pr[1][i] = b;
       }
@@ -1201,10 +1198,9 @@ __global__ __launch_bounds__(kThreads) void k_sweep_xyp(const float* __restrict_
           const DepN d = depart_n<R>(cr[v][j3], over);
           float ea, eb;
           ring_pair<R, K, j3>(er[v], d, ea, eb);
-          const float w = fmaf(d.f, 1.f / 3.f, 1.f / 3.f);
-          o[v] = fmaf(0.5f, fmaf(w, eb - ea, ea), p1[v][j3]);
+          o[v] = sweep_combine<COMB>(p1[v][j3], er[v][j3], ea, eb, d.f);
         }
-        if (!XFIRST) xsweep_pair<R>(o[0], o[1], cxa, cxb, over);
+        if (!XFIRST) xsweep_pair<R, COMB>(o[0], o[1], cxa, cxb, over);
         if (lane_out) st2_row(out, vx, zoff + unsigned(srow) * rowb, o[0], o[1]);
       }
       srow = srow + 1 == ny ? 0 : srow + 1;
@@ -1253,7 +1249,7 @@ hipError_t launch_ec_r(int R, const Geo& g, const float* phi, const float* u, fl
   return hipErrorInvalidValue;
 }
 
-template <int R>
+template <int R, int COMB = kCombCec>
 hipError_t launch_sweep_t(int d, const Geo& g, const float* phi, const float* ud, float* out,
                           int* flag, hipStream_t st, bool march) {
   if (d != 0 && march && offsets32_ok(g)) {
@@ -1272,12 +1268,12 @@ hipError_t launch_sweep_t(int d, const Geo& g, const float* phi, const float* ud
     dim3 grid((g.nx + cols - 1) / cols, (other + 3) / 4, (L + chunk - 1) / chunk);
     if constexpr (R <= 2) {
       if (two) {
-        hipLaunchKernelGGL((k_sweep_m<R, 2>), grid, dim3(kThreads), 0, st, phi, ud, out, g.nx, L, S4,
+        hipLaunchKernelGGL((k_sweep_m<R, 2, COMB>), grid, dim3(kThreads), 0, st, phi, ud, out, g.nx, L, S4,
                            So4, other, chunk, g.lam[d], flag);
         return hipGetLastError();
       }
     }
-    hipLaunchKernelGGL((k_sweep_m<R, 1>), grid, dim3(kThreads), 0, st, phi, ud, out, g.nx, L, S4,
+    hipLaunchKernelGGL((k_sweep_m<R, 1, COMB>), grid, dim3(kThreads), 0, st, phi, ud, out, g.nx, L, S4,
                        So4, other, chunk, g.lam[d], flag);
     return hipGetLastError();
   }
@@ -1285,13 +1281,13 @@ hipError_t launch_sweep_t(int d, const Geo& g, const float* phi, const float* ud
     const int nrows = g.ny * g.nz;
     const int nwin = (g.nx + 64 - 6 * R - 1) / (64 - 6 * R);
     const long long waves = (long long)nrows * ((nwin + 3) / 4);
-    hipLaunchKernelGGL(k_sweep_xw<R>, dim3(unsigned((waves + 3) / 4)), dim3(kThreads), 0, st, phi, ud,
+    hipLaunchKernelGGL((k_sweep_xw<R, COMB>), dim3(unsigned((waves + 3) / 4)), dim3(kThreads), 0, st, phi, ud,
                        out, g.nx, nrows, nwin, g.lam[0], flag);
     return hipGetLastError();
   }
   if (d == 0) {
     dim3 grid((g.nx + 255) / 256, (g.ny + 3) / 4, g.nz);
-    hipLaunchKernelGGL(k_sweep_x<R>, grid, dim3(kThreads), 0, st, phi, ud, out, g.nx, g.ny,
+    hipLaunchKernelGGL((k_sweep_x<R, COMB>), grid, dim3(kThreads), 0, st, phi, ud, out, g.nx, g.ny,
                        g.lam[0], flag);
   } else {
     const int L = d == 1 ? g.ny : g.nz;
@@ -1299,7 +1295,7 @@ hipError_t launch_sweep_t(int d, const Geo& g, const float* phi, const float* ud
     const int other = d == 1 ? g.nz : g.ny;
     const int64_t So = d == 1 ? (int64_t)g.nx * g.ny : (int64_t)g.nx;
     dim3 grid((g.nx + 63) / 64, (L + 31) / 32, other);
-    hipLaunchKernelGGL(k_sweep_s<R>, grid, dim3(kThreads), 0, st, phi, ud, out, g.nx, L, S, So,
+    hipLaunchKernelGGL((k_sweep_s<R, COMB>), grid, dim3(kThreads), 0, st, phi, ud, out, g.nx, L, S, So,
                        g.lam[d], flag);
   }
   return hipGetLastError();
@@ -1365,7 +1361,7 @@ hipError_t launch_ec(int ndim, int scheme, int R, const Geo& g, const float* phi
   return hipErrorInvalidValue;
 }
 
-template <int R>
+template <int R, int COMB>
 hipError_t launch_sweep_xy_t(bool xfirst, const Geo& g, const float* phi, const float* u,
                              float* out, int* flag, hipStream_t st) {
   constexpr int USE = 64 - 6 * R;
@@ -1378,10 +1374,10 @@ hipError_t launch_sweep_xy_t(bool xfirst, const Geo& g, const float* phi, const 
   const long long waves = per * ((g.ny + chunk - 1) / chunk);
   const dim3 grid(unsigned((waves + 3) / 4));
   if (xfirst)
-    hipLaunchKernelGGL((k_sweep_xym<R, true>), grid, dim3(kThreads), 0, st, phi, u, u + n, out, g.nx,
+    hipLaunchKernelGGL((k_sweep_xym<R, true, COMB>), grid, dim3(kThreads), 0, st, phi, u, u + n, out, g.nx,
                        g.ny, g.nz, nwin, chunk, g.lam[0], g.lam[1], flag);
   else
-    hipLaunchKernelGGL((k_sweep_xym<R, false>), grid, dim3(kThreads), 0, st, phi, u, u + n, out,
+    hipLaunchKernelGGL((k_sweep_xym<R, false, COMB>), grid, dim3(kThreads), 0, st, phi, u, u + n, out,
                        g.nx, g.ny, g.nz, nwin, chunk, g.lam[0], g.lam[1], flag);
   return hipGetLastError();
 }
@@ -1395,7 +1391,7 @@ hipError_t launch_sweep_xy_t(bool xfirst, const Geo& g, const float* phi, const 
 #define SLA_XYP_WAVES 8192
 #endif
 
-template <int R>
+template <int R, int COMB>
 hipError_t launch_sweep_xyp_t(bool xfirst, const Geo& g, const float* phi, const float* u,
                               float* out, int* flag, hipStream_t st) {
   constexpr int USE = 128 - 2 * pair_halo<R>();  // most outputs of a window
@@ -1412,29 +1408,43 @@ hipError_t launch_sweep_xyp_t(bool xfirst, const Geo& g, const float* phi, const
   const long long waves = per * ((g.ny + chunk - 1) / chunk);
   const dim3 grid(unsigned((waves + 3) / 4));
   if (xfirst)
-    hipLaunchKernelGGL((k_sweep_xyp<R, true>), grid, dim3(kThreads), 0, st, phi, u, u + n, out, g.nx,
+    hipLaunchKernelGGL((k_sweep_xyp<R, true, COMB>), grid, dim3(kThreads), 0, st, phi, u, u + n, out, g.nx,
                        g.ny, g.nz, nwin, usew, chunk, g.lam[0], g.lam[1], flag);
   else
-    hipLaunchKernelGGL((k_sweep_xyp<R, false>), grid, dim3(kThreads), 0, st, phi, u, u + n, out,
+    hipLaunchKernelGGL((k_sweep_xyp<R, false, COMB>), grid, dim3(kThreads), 0, st, phi, u, u + n, out,
                        g.nx, g.ny, g.nz, nwin, usew, chunk, g.lam[0], g.lam[1], flag);
   return hipGetLastError();
 }
 
-hipError_t launch_cec_sweep_xy(int R, bool xfirst, const Geo& g, const float* phi, const float* u,
-                               float* out, int* flag, hipStream_t st, bool pairs) {
+namespace {
+template <int COMB>
+hipError_t launch_sweep_xy_c(int R, bool xfirst, const Geo& g, const float* phi, const float* u,
+                             float* out, int* flag, hipStream_t st, bool pairs) {
   if (!offsets32_ok(g)) return hipErrorInvalidValue;
   if (pairs) {
     if (g.nx % 2 != 0) return hipErrorInvalidValue;
     switch (R) {
-      case 1: return launch_sweep_xyp_t<1>(xfirst, g, phi, u, out, flag, st);
-      case 2: return launch_sweep_xyp_t<2>(xfirst, g, phi, u, out, flag, st);
-      case 3: return launch_sweep_xyp_t<3>(xfirst, g, phi, u, out, flag, st);
+      case 1: return launch_sweep_xyp_t<1, COMB>(xfirst, g, phi, u, out, flag, st);
+      case 2: return launch_sweep_xyp_t<2, COMB>(xfirst, g, phi, u, out, flag, st);
+      case 3: return launch_sweep_xyp_t<3, COMB>(xfirst, g, phi, u, out, flag, st);
     }
     return hipErrorInvalidValue;
   }
   switch (R) {  // one node per lane: reach 3 and more run one sweep per axis (see the caller)
-    case 1: return launch_sweep_xy_t<1>(xfirst, g, phi, u, out, flag, st);
-    case 2: return launch_sweep_xy_t<2>(xfirst, g, phi, u, out, flag, st);
+    case 1: return launch_sweep_xy_t<1, COMB>(xfirst, g, phi, u, out, flag, st);
+    case 2: return launch_sweep_xy_t<2, COMB>(xfirst, g, phi, u, out, flag, st);
+  }
+  return hipErrorInvalidValue;
+}
+}  // namespace
+
+hipError_t launch_cec_sweep_xy(int R, bool xfirst, const Geo& g, const float* phi, const float* u,
+                               float* out, int* flag, hipStream_t st, bool pairs, int scheme) {
+  switch (scheme) {
+    case CEC: return launch_sweep_xy_c<kCombCec>(R, xfirst, g, phi, u, out, flag, st, pairs);
+    case FEC: return launch_sweep_xy_c<kCombFec>(R, xfirst, g, phi, u, out, flag, st, pairs);
+    case BEC: return launch_sweep_xy_c<kCombBec>(R, xfirst, g, phi, u, out, flag, st, pairs);
+    case CEC_LITERAL: return launch_sweep_xy_c<kCombCecLit>(R, xfirst, g, phi, u, out, flag, st, pairs);
   }
   return hipErrorInvalidValue;
 }
@@ -1471,11 +1481,25 @@ hipError_t launch_split_r(int d, int R, const Geo& g, const float* phi, const fl
 }
 }  // namespace
 
+namespace {
+template <int COMB>
+hipError_t launch_sweep_c(int d, int R, const Geo& g, const float* phi, const float* ud, float* out,
+                          int* flag, hipStream_t st, bool march) {
+  switch (R) {
+    case 1: return launch_sweep_t<1, COMB>(d, g, phi, ud, out, flag, st, march);
+    case 2: return launch_sweep_t<2, COMB>(d, g, phi, ud, out, flag, st, march);
+    case 3: return launch_sweep_t<3, COMB>(d, g, phi, ud, out, flag, st, march);
+    case 4: return launch_sweep_t<4, COMB>(d, g, phi, ud, out, flag, st, march);
+  }
+  return hipErrorInvalidValue;
+}
+}  // namespace
+
 hipError_t launch_ec_sweep(int scheme, int d, int R, const Geo& g, const float* phi,
-                           const float* ud, float* out, int* flag, hipStream_t st) {
-  if (scheme == FEC) return launch_split_r<kCombFec>(d, R, g, phi, ud, out, flag, st);
-  if (scheme == BEC) return launch_split_r<kCombBec>(d, R, g, phi, ud, out, flag, st);
-  if (scheme == CEC_LITERAL) return launch_split_r<kCombCecLit>(d, R, g, phi, ud, out, flag, st);
+                           const float* ud, float* out, int* flag, hipStream_t st, bool march) {
+  if (scheme == FEC) return launch_sweep_c<kCombFec>(d, R, g, phi, ud, out, flag, st, march);
+  if (scheme == BEC) return launch_sweep_c<kCombBec>(d, R, g, phi, ud, out, flag, st, march);
+  if (scheme == CEC_LITERAL) return launch_sweep_c<kCombCecLit>(d, R, g, phi, ud, out, flag, st, march);
   return hipErrorInvalidValue;
 }
 
@@ -1486,13 +1510,7 @@ hipError_t launch_cec_sweep_mid(int d, int R, const Geo& g, const float* phi, co
 
 hipError_t launch_cec_sweep(int d, int R, const Geo& g, const float* phi, const float* ud,
                             float* out, int* flag, hipStream_t st, bool march) {
-  switch (R) {
-    case 1: return launch_sweep_t<1>(d, g, phi, ud, out, flag, st, march);
-    case 2: return launch_sweep_t<2>(d, g, phi, ud, out, flag, st, march);
-    case 3: return launch_sweep_t<3>(d, g, phi, ud, out, flag, st, march);
-    case 4: return launch_sweep_t<4>(d, g, phi, ud, out, flag, st, march);
-  }
-  return hipErrorInvalidValue;
+  return launch_sweep_c<kCombCec>(d, R, g, phi, ud, out, flag, st, march);
 }
 
 }  // namespace sla

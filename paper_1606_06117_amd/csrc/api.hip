@@ -831,21 +831,46 @@ int advect_steps(sla_ctx* ctx, const sla_grid* grid, float* phi, const float* u,
       }
       case SLA_FEC_SPLIT:
       case SLA_BEC_SPLIT:
-      case SLA_CEC_LITERAL:
+      case SLA_CEC_LITERAL: {
         // one 1D FEC, BEC or literal-weight sweep per axis, x,y,z on even
-        // steps, z,y,x on odd
+        // steps, z,y,x on odd, by the kernels of the third order's sweeps
+        // (x and y in one kernel where SLA_CEC runs them so)
+        const int one = scheme == SLA_FEC_SPLIT ? sla::FEC
+                        : scheme == SLA_BEC_SPLIT ? sla::BEC
+                                                  : sla::CEC_LITERAL;
+        const int rxy = reach[0] > reach[1] ? reach[0] : reach[1];
+        const bool pairs = xy_pairs(ctx, geo, rxy);
+        if (ndim >= 2 && (pairs || (ctx->sweep_kernel >= 2 && rxy <= 2)) &&
+            sla::offsets32_ok(geo)) {
+          const bool even = m % 2 == 0;
+          for (int part = 0; part < 2 && e == hipSuccess; ++part) {
+            const bool xy = (part == 0) == even;
+            if (xy) {
+              e = run(ctx, SLA_K_SWEEP_XY, [&] {
+                return sla::launch_cec_sweep_xy(rxy, even, geo, cur, u, nxt, ctx->flag, ctx->stream,
+                                                pairs, one);
+              });
+            } else {
+              if (ndim < 3) continue;
+              e = run(ctx, SLA_K_SWEEP_Z, [&] {
+                return sla::launch_ec_sweep(one, 2, reach[2], geo, cur, u + 2 * n, nxt, ctx->flag,
+                                            ctx->stream, true);
+              });
+            }
+            std::swap(cur, nxt);
+          }
+          break;
+        }
         for (int j = 0; j < ndim && e == hipSuccess; ++j) {
           const int d = (m % 2 == 0) ? j : ndim - 1 - j;
-          const int one = scheme == SLA_FEC_SPLIT ? sla::FEC
-                          : scheme == SLA_BEC_SPLIT ? sla::BEC
-                                                    : sla::CEC_LITERAL;
           e = run(ctx, SLA_K_SWEEP_X + d, [&] {
             return sla::launch_ec_sweep(one, d, reach[d], geo, cur, u + size_t(d) * n, nxt,
-                                        ctx->flag, ctx->stream);
+                                        ctx->flag, ctx->stream, ctx->sweep_kernel != 0);
           });
           std::swap(cur, nxt);
         }
         break;
+      }
       case SLA_CEC_STRANG: {
         // half steps: lambda = fl32(dt/2/dx) = fl32(dt/dx)/2 exactly, so
         // every half-step Courant number is half the whole step's; their

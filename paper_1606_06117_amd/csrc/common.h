@@ -58,9 +58,10 @@ hipError_t launch_ec_gather(int ndim, int mode, const Geo& g, const float* a, co
                             const float* u, float* out, int* flag, hipStream_t st);
 // One FEC (scheme FEC), BEC (scheme BEC) or literal large-CFL third-order
 // (scheme CEC_LITERAL) sweep along axis d: the one-dimensional scheme
-// applied along one axis (tile kernels, reach 1-4).
+// applied along one axis, reach 1-4, by the kernels of launch_cec_sweep
+// (march: window and marching sweeps; otherwise LDS tiles).
 hipError_t launch_ec_sweep(int scheme, int d, int R, const Geo& g, const float* phi,
-                           const float* ud, float* out, int* flag, hipStream_t st);
+                           const float* ud, float* out, int* flag, hipStream_t st, bool march);
 // One third-order sweep along axis d with a midpoint backtrace: the calls of
 // L_U depart from x - c(x - c/2), the call of L_{-U} from x + c(x + c/2)
 // (tile kernels, reach 1-4).
@@ -69,12 +70,13 @@ hipError_t launch_cec_sweep_mid(int d, int R, const Geo& g, const float* phi, co
 hipError_t launch_cec_sweep(int d, int R, const Geo& g, const float* phi,
                             const float* u_d, float* out, int* flag, hipStream_t st,
                             bool march = true);
-// The x and y sweeps of a third-order step in one kernel: x then y if
-// xfirst, else y then x; u holds the x and y planes.  Same results as the
-// two sweeps.  pairs: two nodes per lane, even nx, reach R <= 3 on both
-// axes; otherwise one node per lane, R <= 2.  Needs offsets32_ok(g).
+// The x and y sweeps of a split step in one kernel: x then y if xfirst,
+// else y then x; u holds the x and y planes.  scheme: the third order (CEC),
+// FEC, BEC or CEC_LITERAL along each axis.  Same results as the two sweeps.
+// pairs: two nodes per lane, even nx, reach R <= 3 on both axes; otherwise
+// one node per lane, R <= 2.  Needs offsets32_ok(g).
 hipError_t launch_cec_sweep_xy(int R, bool xfirst, const Geo& g, const float* phi, const float* u,
-                               float* out, int* flag, hipStream_t st, bool pairs);
+                               float* out, int* flag, hipStream_t st, bool pairs, int scheme = CEC);
 
 // Fused three-axis third-order step (reach 1 only): x,y,z order if even,
 // z,y,x otherwise.  variant: 1 register segments, 2 streaming (direct

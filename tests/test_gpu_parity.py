@@ -466,6 +466,46 @@ def test_marching_sweeps_match_tiles(ctx, shape, cfl, steps):
     assert np.array_equal(pairs, tiles)
 
 
+@pytest.mark.parametrize("scheme", [oracle.FEC_SPLIT, oracle.BEC_SPLIT, oracle.CEC_LITERAL])
+@pytest.mark.parametrize("shape,cfl", [
+    ((40, 96, 24), 0.9),    # reach 1
+    ((12, 33, 70), 1.8),    # reach 2, ragged
+    ((12, 33, 69), 1.8),    # odd nx
+    ((12, 33, 70), 2.5),    # reach 3: x and y in the two-node kernel
+    ((8, 9, 70), 3.5),      # reach 4: one sweep per axis
+    ((1, 50, 66), 1.5),     # 2D
+])
+def test_split_schemes_sweep_kernels_agree(ctx, scheme, shape, cfl):
+    """FEC, BEC and the literal-weight third order split per axis run on the
+    third order's sweep kernels (only the last stage of a sweep differs): the
+    default (x and y in one kernel with two nodes per lane where nx is even),
+    one node per lane, one kernel per axis, and the LDS tiles give the same
+    bits.  Two steps from an odd step, so both sweep orders run."""
+    from paper_1606_06117_amd import native
+    if shape[0] == 1:
+        shp = shape[1:]
+        phi = W.random_gaussians(shp, 5, seed=43).astype(np.float32)
+        u = W.cellular_velocity_2d(shp)
+    else:
+        shp = shape
+        phi = W.random_gaussians(shp, 5, seed=43).astype(np.float32)
+        u = W.abc_velocity(shp)
+    dx = tuple(2 * np.pi / n for n in reversed(shp))
+    dt = cfl * min(dx) / float(np.max(np.abs(u)))
+    outs = []
+    for kern in (3, 2, 1, 0):
+        ctx.set_option(native.OPT_SWEEP_KERNEL, kern)
+        try:
+            outs.append(gpu_advect(ctx, phi, u, dx, dt, scheme, 2, step0=1))
+        finally:
+            ctx.set_option(native.OPT_SWEEP_KERNEL, 3)
+    for o in outs[1:]:  # the literal weights are NaN where |c| is whole (c = 0 at some nodes)
+        assert np.array_equal(outs[0], o, equal_nan=True)
+    if scheme != oracle.CEC_LITERAL:  # the literal weights amplify rounding near whole |c|
+        ref = oracle_advect(phi, u, dx, dt, scheme, 2, step0=1)
+        assert rel_l2(outs[0], ref) < 1e-5
+
+
 def test_fused_1024_matches_sweeps_and_last_cell(ctx):
     """2^30 cells, the largest grid the fused kernels take, at CFL 0.9 (the
     fused path, default implementation): two steps agree bitwise with the
