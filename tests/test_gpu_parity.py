@@ -329,6 +329,37 @@ def test_abc_512_cfl09_cec_boxes(ctx):
     torch.cuda.empty_cache()
 
 
+@pytest.mark.parametrize("cfl", [1.5, 2.0])
+def test_abc_512_reach23_sweeps(ctx, cfl):
+    """The benchmark's 512^3 workload at CFL 1.5 and 2.0 (reach 2 and 3), in
+    the launch shapes the benchmark times: the x+y kernel with two nodes per
+    lane (five windows of 104 outputs per row, 128-row chunks) and the
+    two-column z march.  Two steps from an odd step, so both orders run.
+    The whole grid agrees bitwise with one kernel per axis (one node per
+    lane, SLA_OPT_SWEEP_KERNEL 1), and four 24^3 boxes match the oracle."""
+    import torch
+    from paper_1606_06117_amd import native
+    shape = (512, 512, 512)
+    phi = W.random_gaussians(shape, 8, seed=2000).astype(np.float32)
+    u = W.abc_velocity(shape)
+    dx = tuple(2 * np.pi / n for n in reversed(shape))
+    dt = cfl * dx[0] / 2
+    steps = 2
+    got = gpu_advect(ctx, phi, u, dx, dt, oracle.CEC, steps, step0=1, courant_max=cfl)
+    ctx.set_option(native.OPT_SWEEP_KERNEL, 1)
+    try:
+        per_axis = gpu_advect(ctx, phi, u, dx, dt, oracle.CEC, steps, step0=1, courant_max=cfl)
+    finally:
+        ctx.set_option(native.OPT_SWEEP_KERNEL, 3)
+    assert np.array_equal(got, per_axis)
+    del per_axis
+    l2, linf = box_parity(got, phi, u, dx, dt, oracle.CEC, steps, steps * 3 * (int(cfl) + 1),
+                          (24, 24, 24), np.random.default_rng(5), 4, step0=1)
+    print(f"512^3 cfl={cfl} boxes relL2={l2:.3e} Linf={linf:.3e}")
+    assert l2 <= TOL * steps and linf <= TOL * steps
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("variant,launch", [(1, 0), (2, 0), (4, 0), (5, 0), (6, 0), (7, 0), (7, 16),
                                             (8, 0), (8, -16), (8, 1),
                                             (9, -16), (10, 0), (11, -16), (12, 0), (13, 1),
