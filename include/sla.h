@@ -228,8 +228,9 @@ typedef enum {
    * of these for each parity and grid size as measured from 256^3 to
    * 1024^3 (14 from 2^24 cells on with an even nx). */
   SLA_OPT_CEC3D_KERNEL = 1,
-  /* How the sweeps of a third-order step that is not fused run (same FP32
-   * operations, same results): 3 (default) the x and y sweeps in one kernel
+  /* How the sweeps of a third-order step that is not fused, and of the
+   * split schemes (SLA_CEC_STRANG, SLA_FEC_SPLIT, SLA_BEC_SPLIT,
+   * SLA_CEC_LITERAL), run (same FP32 operations, same results): 3 (default) the x and y sweeps in one kernel
    * (x then y on even steps, y then x on odd ones) with two nodes per lane
    * (128-node x windows marching along y) when nx is even and their reach
    * is at most 3, z by column walks, else as 2; 2 the x and y sweeps in
