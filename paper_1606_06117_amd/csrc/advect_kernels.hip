@@ -672,9 +672,8 @@ __device__ __forceinline__ DepN dep_fwd(float c, float f, float n) { return DepN
 __device__ __forceinline__ DepN dep_rev(float c, float f, float n) { return DepN{f, n, c <= 0.f}; }
 
 // A value passed through an empty asm statement: the compiler cannot move
-// an operation on it to where v was produced (the ring marches use it on
-// prefetched values: see k_sweep_m).  Elsewhere it kept selects between
-// elements of one register array from becoming a dynamically indexed array.
+// an operation on it to where v was produced.  The ring marches pass their
+// prefetched values through it where they are used (see k_sweep_m).
 __device__ __forceinline__ float opaque(float v) {
   asm("" : "+v"(v));
   return v;
