@@ -145,7 +145,7 @@ def cpu_scheme_parity(ctx, size, cfl, steps, workers):
     from paper_1606_06117_amd import native
     from paper_1606_06117_amd import workloads as W
     shape = (size,) * 3
-    phi0 = W.random_gaussians(shape, 8, seed=2000).astype(np.float32)
+    phi0 = W.random_gaussians_torch(shape, 8, 2000, "cuda:0").cpu().numpy()  # random_gaussians' values
     u = W.abc_velocity(shape)
     dx = (2 * math.pi / size,) * 3
     dt = W.abc_dt(shape, cfl)
@@ -212,7 +212,7 @@ def learned_probe(size: int, reps: int, warmup: int) -> int:
     from paper_1606_06117_amd import workloads as W
     shape = (size,) * 3
     dev = torch.device("cuda:0")
-    phi = torch.from_numpy(W.random_gaussians(shape, 8, seed=2000).astype(np.float32)).to(dev)
+    phi = W.random_gaussians_torch(shape, 8, 2000, dev)
     u = W.abc_velocity_torch(shape, dev)
     dx = (2 * math.pi / size,) * 3
     dt = W.abc_dt(shape, 0.9)
@@ -367,7 +367,7 @@ def cfl_section(ctx, size, cfls, steps, scheme=None, name="third order"):
     from paper_1606_06117_amd import workloads as W
     shape = (size,) * 3
     dev = torch.device("cuda:0")
-    phi = torch.from_numpy(W.random_gaussians(shape, 8, seed=2000).astype(np.float32)).to(dev)
+    phi = W.random_gaussians_torch(shape, 8, 2000, dev)
     u = W.abc_velocity_torch(shape, dev)
     dx = (2 * math.pi / size,) * 3
     rows = []
@@ -393,7 +393,7 @@ def schemes_section(ctx, size, cfl, steps):
     from paper_1606_06117_amd import workloads as W
     shape = (size,) * 3
     dev = torch.device("cuda:0")
-    phi = torch.from_numpy(W.random_gaussians(shape, 8, seed=2000).astype(np.float32)).to(dev)
+    phi = W.random_gaussians_torch(shape, 8, 2000, dev)
     u = W.abc_velocity_torch(shape, dev)
     dx = (2 * math.pi / size,) * 3
     rows = []
@@ -420,7 +420,7 @@ def ec_section(ctx, size, cfl, steps):
     from paper_1606_06117_amd import workloads as W
     shape = (size,) * 3
     dev = torch.device("cuda:0")
-    phi0 = torch.from_numpy(W.random_gaussians(shape, 8, seed=2000).astype(np.float32)).to(dev)
+    phi0 = W.random_gaussians_torch(shape, 8, 2000, dev)
     u = W.abc_velocity_torch(shape, dev)
     dx = (2 * math.pi / size,) * 3
     dt = W.abc_dt(shape, cfl)
@@ -455,7 +455,7 @@ def norms_section(ctx, size, reps):
     from paper_1606_06117_amd import workloads as W
     shape = (size,) * 3
     dev = torch.device("cuda:0")
-    a = torch.from_numpy(W.random_gaussians(shape, 8, seed=2000).astype(np.float32)).to(dev)
+    a = W.random_gaussians_torch(shape, 8, 2000, dev)
     b = a * 1.0001
     ctx.norms(a, b)
     torch.cuda.synchronize()
@@ -621,7 +621,7 @@ def main(argv=None):
     N = args.size
     shape = (N, N, N)
     print(f"[bench] building inputs {N}^3 ...", file=sys.stderr, flush=True)
-    phi0 = W.random_gaussians(shape, 8, seed=2000).astype(np.float32)
+    phi0 = W.random_gaussians_torch(shape, 8, 2000, "cuda:0").cpu().numpy()  # random_gaussians' values
     u = W.abc_velocity(shape)
     dx = (2 * math.pi / N,) * 3
     dt = W.abc_dt(shape, args.cfl)

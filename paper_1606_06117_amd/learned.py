@@ -89,7 +89,7 @@ def generate_pairs(ctx, shape, fields, steps_per_field, cells_per_snapshot, cfl,
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for seed in fields:
-        phi = torch.from_numpy(W.random_gaussians(shape, 8, seed=seed).astype(np.float32)).cuda()
+        phi = W.random_gaussians_torch(shape, 8, seed, "cuda")
         for m in range(steps_per_field):
             a = modulation(m, period)
             phi1 = phi.clone()
@@ -179,7 +179,7 @@ def evaluate(ctx, model, shape, seed, periods, cfl, period=PERIOD):
     dx = (2 * math.pi / N,) * 3
     dt = W.abc_dt(shape, cfl)
     u = torch.from_numpy(W.abc_velocity(shape)).cuda()
-    phi0 = torch.from_numpy(W.random_gaussians(shape, 8, seed=seed).astype(np.float32)).cuda()
+    phi0 = W.random_gaussians_torch(shape, 8, seed, "cuda")
     runs = {"cec": phi0.clone(), "learned": phi0.clone(), "cir": phi0.clone()}
     times = {k: 0.0 for k in runs}
     per_step = []
@@ -230,7 +230,7 @@ def error_at_cfl(ctx, shape, seed, cfl, steps_per_period, periods, learned_model
     c = cfl * PERIOD / steps_per_period
     dt = W.abc_dt(shape, c)
     u = torch.from_numpy(W.abc_velocity(shape)).cuda()
-    phi0 = torch.from_numpy(W.random_gaussians(shape, 8, seed=seed).astype(np.float32)).cuda()
+    phi0 = W.random_gaussians_torch(shape, 8, seed, "cuda")
     phi = phi0.clone()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -261,7 +261,7 @@ def error_at_resolution(ctx, n, ref_n, seed, cfl, periods, period=PERIOD):
     dt = W.abc_dt((ref_n,) * 3, cfl)
     c = cfl * n / ref_n  # the Courant number on this grid
     u = torch.from_numpy(W.abc_velocity(shape)).cuda()
-    phi0 = torch.from_numpy(W.random_gaussians(shape, 8, seed=seed).astype(np.float32)).cuda()
+    phi0 = W.random_gaussians_torch(shape, 8, seed, "cuda")
     phi = phi0.clone()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
