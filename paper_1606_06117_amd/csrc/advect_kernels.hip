@@ -1256,16 +1256,16 @@ hipError_t launch_sweep_t(int d, const Geo& g, const float* phi, const float* ud
     const int other = d == 1 ? g.nz : g.ny;
     const unsigned S4 = 4u * unsigned(d == 1 ? g.nx : g.nx * g.ny);
     const unsigned So4 = 4u * unsigned(d == 1 ? g.nx * g.ny : g.nx);
-    // two columns per lane with an even nx up to reach 2 (more rings would
-    // cost occupancy); enough waves to fill the chip (about 8 per CU),
-    // chunks of >= 16R nodes
-    const bool two = g.nx % 2 == 0 && R <= 2;
+    // two columns per lane with an even nx up to reach 3 (at reach 4 the
+    // rings would cost occupancy); enough waves to fill the chip (about 8
+    // per CU), chunks of >= 16R nodes
+    const bool two = g.nx % 2 == 0 && R <= 3;
     const int cols = two ? 128 : 64;
     const long long waves = (long long)((g.nx + cols - 1) / cols) * other;
     const int want = int(std::min<long long>((2048 + waves - 1) / waves, std::max(1, L / (16 * R))));
     const int chunk = (L + want - 1) / want;
     dim3 grid((g.nx + cols - 1) / cols, (other + 3) / 4, (L + chunk - 1) / chunk);
-    if constexpr (R <= 2) {
+    if constexpr (R <= 3) {
       if (two) {
         hipLaunchKernelGGL((k_sweep_m<R, 2, COMB>), grid, dim3(kThreads), 0, st, phi, ud, out, g.nx, L, S4,
                            So4, other, chunk, g.lam[d], flag);
