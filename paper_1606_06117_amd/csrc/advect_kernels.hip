@@ -722,19 +722,26 @@ __global__ __launch_bounds__(kThreads) void k_sweep_m(const float* __restrict__ 
     return m < 0 ? m + L : m;
   };
   const int m0 = l0 - 3 * R, m1 = l1 + 3 * R;  // steps m0 .. m1 - 1
+  // loads run PD steps ahead: K, or K/2 for two columns at reach 3 (20
+  // registers fewer, as in k_sweep_xyp)
+  constexpr int PD = (R == 3 && V == 2) ? K / 2 : K;
+  static_assert(K % PD == 0, "prefetch slots are ring indices mod PD");
   float pr[V][K], p1[V][K], er[V][K], cr[V][K];  // rings, per column
   float fr[V][K], nr[V][K];  // departure fraction and distance of each ring slot
-  float np[V][K], nc[V][K];  // loads of the next K steps
+  float np[V][PD], nc[V][PD];  // loads of the next PD steps
   int lrow = wrapped(m0);    // wrapped axis position of the next load
 #pragma unroll
-  for (int i = 0; i < K; ++i) {
+  for (int i = 0; i < K; ++i)
+#pragma unroll
+    for (int v = 0; v < V; ++v) pr[v][i] = p1[v][i] = er[v][i] = cr[v][i] = fr[v][i] = nr[v][i] = 0.f;
+#pragma unroll
+  for (int i = 0; i < PD; ++i) {
     const unsigned ro_i = unsigned(lrow) * S4;
     float a[V], c[V];
     ld_rowv<V>(rp, voff, ro_i, a);
     ld_rowv<V>(ru, voff, ro_i, c);
 #pragma unroll
     for (int v = 0; v < V; ++v) {
-      pr[v][i] = p1[v][i] = er[v][i] = cr[v][i] = fr[v][i] = nr[v][i] = 0.f;
       np[v][i] = a[v];
       nc[v][i] = c[v];
     }
@@ -749,13 +756,14 @@ __global__ __launch_bounds__(kThreads) void k_sweep_m(const float* __restrict__ 
     static_for<K>([&](auto ic) {
       constexpr int i = decltype(ic)::value;
       const int m = mb + i;
+      constexpr int q = i % PD;  // prefetch slot of this step
 #pragma unroll
       for (int v = 0; v < V; ++v) {
         // the loaded values pass through opaque() where they are used: the
         // compiler would otherwise move these products into the previous
         // iteration, right after the loads, and wait for them there
-        pr[v][i] = opaque(np[v][i]);
-        cr[v][i] = opaque(nc[v][i]) * lam;
+        pr[v][i] = opaque(np[v][q]);
+        cr[v][i] = opaque(nc[v][q]) * lam;
         depart_fn<R>(cr[v][i], fr[v][i], nr[v][i], over);
       }
       {  // unconditional, and every iteration runs all K steps (past m1 the
@@ -767,8 +775,8 @@ __global__ __launch_bounds__(kThreads) void k_sweep_m(const float* __restrict__ 
         ld_rowv<V>(ru, voff, rn, c);
 #pragma unroll
         for (int v = 0; v < V; ++v) {
-          np[v][i] = a[v];
-          nc[v][i] = c[v];
+          np[v][q] = a[v];
+          nc[v][q] = c[v];
         }
       }
       lrow = lrow + 1 == L ? 0 : lrow + 1;
@@ -1133,14 +1141,20 @@ __global__ __launch_bounds__(kThreads) void k_sweep_xyp(const float* __restrict_
     return m < 0 ? m + ny : m;
   };
   const int m0 = l0 - 3 * R, m1 = l1 + 3 * R;  // steps m0 .. m1 - 1
+  // loads run PD steps ahead: K, or K/2 at reach 3 (60 registers fewer,
+  // still thousands of cycles ahead at that kernel's occupancy)
+  constexpr int PD = R == 3 ? K / 2 : K;
+  static_assert(K % PD == 0, "prefetch slots are ring indices mod PD");
   float pr[2][K], p1[2][K], er[2][K], cr[2][K];  // rings, per node of the pair
-  float np[2][K], nc[2][K], nu[2][K];            // loads of the next K steps (nu: x velocity)
+  float np[2][PD], nc[2][PD], nu[2][PD];         // loads of the next PD steps (nu: x velocity)
   int lrow = wrapped(m0);                         // row of the next phi / y-velocity load
   int xrow = XFIRST ? lrow : wrapped(m0 - 3 * R); // row of the next x-velocity load
 #pragma unroll
-  for (int i = 0; i < K; ++i) {
+  for (int i = 0; i < K; ++i)
 #pragma unroll
     for (int v = 0; v < 2; ++v) pr[v][i] = p1[v][i] = er[v][i] = cr[v][i] = 0.f;
+#pragma unroll
+  for (int i = 0; i < PD; ++i) {
     const unsigned ro = zoff + unsigned(lrow) * rowb;
     ld2_row(phi, vx, ro, np[0][i], np[1][i]);
     ld2_row(uy, vx, ro, nc[0][i], nc[1][i]);
@@ -1156,20 +1170,21 @@ __global__ __launch_bounds__(kThreads) void k_sweep_xyp(const float* __restrict_
       constexpr int i = decltype(ic)::value;
       const int m = mb + i;
       // x Courant numbers of row m (XFIRST) or of row m - 3R
-      const float cxa = opaque(nu[0][i]) * lamx, cxb = opaque(nu[1][i]) * lamx;
+      constexpr int q = i % PD;  // prefetch slot of this step
+      const float cxa = opaque(nu[0][q]) * lamx, cxb = opaque(nu[1][q]) * lamx;
       {
-        float a = opaque(np[0][i]), b = opaque(np[1][i]);
+        float a = opaque(np[0][q]), b = opaque(np[1][q]);
         if (XFIRST) xsweep_pair<R, COMB>(a, b, cxa, cxb, over);
         pr[0][i] = a;
         pr[1][i] = b;
       }
 #pragma unroll
-      for (int v = 0; v < 2; ++v) cr[v][i] = opaque(nc[v][i]) * lamy;
+      for (int v = 0; v < 2; ++v) cr[v][i] = opaque(nc[v][q]) * lamy;
       {  // unconditional, all K steps, as in k_sweep_m
         const unsigned rn = zoff + unsigned(lrow) * rowb;
-        ld2_row(phi, vx, rn, np[0][i], np[1][i]);
-        ld2_row(uy, vx, rn, nc[0][i], nc[1][i]);
-        ld2_row(ux, vx, zoff + unsigned(xrow) * rowb, nu[0][i], nu[1][i]);
+        ld2_row(phi, vx, rn, np[0][q], np[1][q]);
+        ld2_row(uy, vx, rn, nc[0][q], nc[1][q]);
+        ld2_row(ux, vx, zoff + unsigned(xrow) * rowb, nu[0][q], nu[1][q]);
       }
       lrow = lrow + 1 == ny ? 0 : lrow + 1;
       xrow = xrow + 1 == ny ? 0 : xrow + 1;
