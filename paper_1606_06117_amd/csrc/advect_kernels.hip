@@ -820,9 +820,10 @@ __global__ __launch_bounds__(kThreads) void k_sweep_m(const float* __restrict__ 
 // consecutive windows of its row together.  A window
 // produces the 64 - 6R outputs x0 .. x0 + 63 - 6R; the anchor and far
 // values of each call are read from the lanes at the departure offsets
-// (__shfl, a cross-lane read): Phi1 is valid on lanes R .. 63 - R, e on
-// 2R .. 63 - 2R, the output on 3R .. 63 - 3R.  No LDS memory, no barriers.
-// The arithmetic per node is that of k_sweep_x.
+// (xsweep_lanes: DPP shifts at reach 1 and 2, __shfl beyond): Phi1 is valid
+// on lanes R .. 63 - R, e on 2R .. 63 - 2R, the output on 3R .. 63 - 3R.
+// No LDS memory, no barriers.  The arithmetic per node is that of k_sweep_x
+// (COMB: the scheme applied along the axis, as there).
 // ---------------------------------------------------------------------------
 // Value of the lane below (lane - 1) and above (lane + 1): DPP wave shifts,
 // one vector move each; lanes 0 and 63 receive 0.
@@ -938,8 +939,9 @@ __global__ __launch_bounds__(kThreads) void k_sweep_xw(const float* __restrict__
 }
 
 // ---------------------------------------------------------------------------
-// Fused x and y sweeps, any reach R: the first two sweeps of an x,y,z step
-// (XFIRST: x then y) or the last two of a z,y,x step (y then x).  A wave
+// Fused x and y sweeps, reach 1 or 2 (odd nx; even nx takes k_sweep_xyp):
+// the first two sweeps of an x,y,z step (XFIRST: x then y) or the last two
+// of a z,y,x step (y then x), COMB the scheme along each axis.  A wave
 // takes one 64-lane x window of one z plane, x0 - 3R .. x0 + 60 - 3R
 // (wrapped, one node per lane; lanes 3R .. 63 - 3R are its 64 - 6R
 // outputs), and marches along y through a chunk of rows with the y sweep's
