@@ -679,27 +679,25 @@ __device__ __forceinline__ float opaque(float v) {
   return v;
 }
 
-// Anchor and far values of a call at ring index BASE: the candidates
-// ring[BASE -+ k], k = 0 .. R, chosen by distance n, then by direction.
+// Anchor and far values of a call at ring index BASE: the anchor at
+// distance n from the node, the far value at n + 1, both on the side the
+// departure lies (pos: lower indices).  The side is chosen first for each
+// distance (R selects), then the distance (2(R - 1) selects): 3R - 2 in
+// all, against 4R - 2 choosing the distance first.
 template <int R, int K, int BASE>
 __device__ __forceinline__ void ring_pair(const float (&ring)[K], const DepN& d, float& a, float& b) {
-  const float c0 = ring[pmod(BASE, K)];
-  float an_l = c0, an_r = c0;
-  float fa_l = ring[pmod(BASE - 1, K)], fa_r = ring[pmod(BASE + 1, K)];
-  float pl = fa_l, pr = fa_r;  // candidates at distance k
+  float v[R + 1];  // v[k]: the candidate at distance k on the departure's side
+  v[0] = ring[pmod(BASE, K)];
+#pragma unroll
+  for (int k = 1; k <= R; ++k) v[k] = d.pos ? ring[pmod(BASE - k, K)] : ring[pmod(BASE + k, K)];
+  a = v[0];
+  b = v[1];
 #pragma unroll
   for (int k = 1; k < R; ++k) {
-    const float nl = ring[pmod(BASE - k - 1, K)], nr = ring[pmod(BASE + k + 1, K)];
     const bool hit = d.n == float(k);
-    an_l = hit ? pl : an_l;
-    an_r = hit ? pr : an_r;
-    fa_l = hit ? nl : fa_l;
-    fa_r = hit ? nr : fa_r;
-    pl = nl;
-    pr = nr;
+    a = hit ? v[k] : a;
+    b = hit ? v[k + 1] : b;
   }
-  a = d.pos ? an_l : an_r;
-  b = d.pos ? fa_l : fa_r;
 }
 
 template <int R, int V, int COMB = kCombCec>
@@ -841,23 +839,18 @@ __device__ __forceinline__ float lane_above(float v) {
 template <int R>
 __device__ __forceinline__ void view_pair(const float (&lo)[R + 1], const float (&hi)[R + 1],
                                           const DepN& d, float& a, float& b) {
-  const float c0 = lo[0];
-  float an_l = c0, an_r = c0;
-  float fa_l = lo[1], fa_r = hi[1];
-  float pl = fa_l, pr = fa_r;
+  float v[R + 1];
+  v[0] = lo[0];
+#pragma unroll
+  for (int k = 1; k <= R; ++k) v[k] = d.pos ? lo[k] : hi[k];
+  a = v[0];
+  b = v[1];
 #pragma unroll
   for (int k = 1; k < R; ++k) {
-    const float nl = lo[k + 1], nr = hi[k + 1];
     const bool hit = d.n == float(k);
-    an_l = hit ? pl : an_l;
-    an_r = hit ? pr : an_r;
-    fa_l = hit ? nl : fa_l;
-    fa_r = hit ? nr : fa_r;
-    pl = nl;
-    pr = nr;
+    a = hit ? v[k] : a;
+    b = hit ? v[k + 1] : b;
   }
-  a = d.pos ? an_l : an_r;
-  b = d.pos ? fa_l : fa_r;
 }
 template <int R>
 __device__ __forceinline__ void lane_views(float v, float (&lo)[R + 1], float (&hi)[R + 1]) {
