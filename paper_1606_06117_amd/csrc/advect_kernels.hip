@@ -50,6 +50,22 @@ __device__ __forceinline__ Dep depart(float c, int* flag) {
   d.f = f;
   return d;
 }
+// The same decomposition and clamp with the overflow or-ed into `over`, for
+// kernels that store the flag once instead of a conditional store per call.
+template <int R>
+__device__ __forceinline__ Dep depart_o(float c, bool& over) {
+  const float mag = fabsf(c);
+  const float nf = floorf(mag);
+  const float f = mag - nf;
+  over |= nf > float(R - 1);  // false for NaN, which propagates
+  const int n = int(fminf(nf, float(R - 1)));
+  const bool pos = c >= 0.f;  // -0.0 counts as positive
+  Dep d;
+  d.oa = pos ? -n : n;
+  d.ob = pos ? -(n + 1) : (n + 1);
+  d.f = f;
+  return d;
+}
 
 __device__ __forceinline__ float lerp(float p, float q, float f) { return fmaf(f, q - p, p); }
 
@@ -119,21 +135,22 @@ __global__ __launch_bounds__(kThreads) void k_gather(const float* __restrict__ a
     if (NDIM == 3) cz[j] = uz[idx[j]];
   }
   float v[CPT][8];
+  bool over = false;  // an overflow, stored once below
 #pragma unroll
   for (int j = 0; j < CPT; ++j) {
     const int y = min(blockIdx.y * (4 * CPT) + 4 * j + threadIdx.y, g.ny - 1);
-    dx[j] = depart<R>(sgn * (cx[j] * g.lam[0]), flag);
+    dx[j] = depart_o<R>(sgn * (cx[j] * g.lam[0]), over);
     const int xa = wrap1(x + dx[j].oa, g.nx), xb = wrap1(x + dx[j].ob, g.nx);
     if (NDIM == 1) {
       v[j][0] = a[xa];
       v[j][1] = a[xb];
       continue;
     }
-    dy[j] = depart<R>(sgn * (cy[j] * g.lam[1]), flag);
+    dy[j] = depart_o<R>(sgn * (cy[j] * g.lam[1]), over);
     const int ya = wrap1(y + dy[j].oa, g.ny) * g.nx, yb = wrap1(y + dy[j].ob, g.ny) * g.nx;
     int za = z * plane, zb = za;
     if (NDIM == 3) {
-      dz[j] = depart<R>(sgn * (cz[j] * g.lam[2]), flag);
+      dz[j] = depart_o<R>(sgn * (cz[j] * g.lam[2]), over);
       za = wrap1(z + dz[j].oa, g.nz) * plane;
       zb = wrap1(z + dz[j].ob, g.nz) * plane;
     }
@@ -168,6 +185,7 @@ __global__ __launch_bounds__(kThreads) void k_gather(const float* __restrict__ a
     }
     if (ok[j]) out[idx[j]] = r;
   }
+  if (over) *flag = 1;
 }
 
 // ---------------------------------------------------------------------------
